@@ -1,0 +1,246 @@
+"""FP64 CPU oracle for the reverse-order pruning PC skeleton (test
+infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The library under
+``paper_2109_04626_amd/`` never loads it, and it shares no code with it.
+
+The arithmetic lives in ``fastpc_oracle.c`` (plain C, FP64, OpenMP over
+the edges of one level); this module is the ctypes marshalling around it
+plus small pure-Python pieces (Phase II orientation, the MLP reference).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fastpc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ORC_OK, ORC_EINVAL, ORC_ESINGULAR, ORC_EBUDGET, ORC_ENOMEM = 0, 1, 2, 3, 4
+_ERRNAMES = {1: "EINVAL", 2: "ESINGULAR", 3: "EBUDGET", 4: "ENOMEM"}
+
+SEP_NONE, SEP_LIST, SEP_ALL_BUT = 0, 1, 2
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle error {_ERRNAMES.get(code, code)}")
+        self.code = code
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (FP64, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        d, i, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+        lib.orc_ppnd16.restype = d
+        lib.orc_ppnd16.argtypes = [d]
+        lib.orc_quantile.restype = d
+        lib.orc_quantile.argtypes = [d]
+        lib.orc_corr.restype = i
+        lib.orc_corr.argtypes = [vp, i, i, vp]
+        lib.orc_cov_to_corr.restype = i
+        lib.orc_cov_to_corr.argtypes = [vp, i, vp]
+        lib.orc_pcor.restype = i
+        lib.orc_pcor.argtypes = [vp, i, i, i, vp, i, vp]
+        lib.orc_pcor_inverse.restype = i
+        lib.orc_pcor_inverse.argtypes = [vp, i, i, i, vp, i, vp]
+        lib.orc_inverse.restype = i
+        lib.orc_inverse.argtypes = [vp, i, vp]
+        lib.orc_zstat.restype = d
+        lib.orc_zstat.argtypes = [d, i, i]
+        lib.orc_candidates.restype = i
+        lib.orc_candidates.argtypes = [vp, i, i, i, vp]
+        lib.orc_skeleton.restype = vp
+        lib.orc_skeleton.argtypes = [vp, i, i, d, i, i, i, i64, i, i]
+        lib.orc_result_free.argtypes = [vp]
+        lib.orc_result_status.restype = i
+        lib.orc_result_status.argtypes = [vp]
+        lib.orc_result_nlevels.restype = i
+        lib.orc_result_nlevels.argtypes = [vp]
+        lib.orc_result_total_tests.restype = i64
+        lib.orc_result_total_tests.argtypes = [vp]
+        lib.orc_result_min_margin.restype = d
+        lib.orc_result_min_margin.argtypes = [vp]
+        lib.orc_result_adj.argtypes = [vp, vp]
+        lib.orc_result_sepsets.restype = i64
+        lib.orc_result_sepsets.argtypes = [vp, vp, vp, vp, vp, i64]
+        lib.orc_result_levels.argtypes = [vp, vp, vp]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------- pieces
+def ppnd16(p: float) -> float:
+    """Phi^{-1}(p) by Wichura's AS 241."""
+    return _L().orc_ppnd16(float(p))
+
+
+def quantile(alpha: float) -> float:
+    """Threshold Phi^{-1}(1 - alpha/2) of the two-sided Fisher-z test."""
+    return _L().orc_quantile(float(alpha))
+
+
+def corr(X: np.ndarray) -> np.ndarray:
+    """Pearson correlation matrix of row-major data (n x p), FP64."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    n, p = X.shape
+    C = np.empty((p, p), dtype=np.float64)
+    st = _L().orc_corr(_ptr(X), n, p, _ptr(C))
+    if st:
+        raise OracleError(st)
+    return C
+
+
+def cov_to_corr(S: np.ndarray) -> np.ndarray:
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    C = np.empty_like(S)
+    _L().orc_cov_to_corr(_ptr(S), S.shape[0], _ptr(C))
+    return C
+
+
+def pcor(C: np.ndarray, i: int, j: int, K) -> tuple[float, int]:
+    """(r, status) from H = H0 - H1 H2^{-1} H1^T; status 1 = degenerate."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    K = np.ascontiguousarray(np.asarray(K, dtype=np.int32).reshape(-1))
+    r = np.zeros(1)
+    st = _L().orc_pcor(_ptr(C), C.shape[0], int(i), int(j), _ptr(K), K.size, _ptr(r))
+    return float(r[0]), int(st)
+
+
+def pcor_inverse(C: np.ndarray, i: int, j: int, K) -> tuple[float, int]:
+    """(r, status) from the explicit inverse of the (l+2)x(l+2) matrix."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    K = np.ascontiguousarray(np.asarray(K, dtype=np.int32).reshape(-1))
+    r = np.zeros(1)
+    st = _L().orc_pcor_inverse(_ptr(C), C.shape[0], int(i), int(j), _ptr(K), K.size, _ptr(r))
+    return float(r[0]), int(st)
+
+
+def inverse(A: np.ndarray) -> np.ndarray:
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    out = np.empty_like(A)
+    st = _L().orc_inverse(_ptr(A), A.shape[0], _ptr(out))
+    if st:
+        raise OracleError(st)
+    return out
+
+
+def zstat(r: float, n: int, l: int) -> float:
+    """sqrt(n - l - 3) * |atanh r|."""
+    return _L().orc_zstat(float(r), int(n), int(l))
+
+
+def ci_test(C, n, i, j, K, q) -> tuple[bool, float, int]:
+    """(independent, z, status) of one Fisher-z test; degenerate = dependent."""
+    r, st = pcor(C, i, j, K)
+    if st:
+        return False, float("nan"), st
+    z = zstat(r, n, len(K))
+    return bool(z <= q), z, 0
+
+
+def candidates(adj: np.ndarray, i: int, j: int) -> list[int]:
+    """adj(G,i,j) n path(G,i,j), sorted."""
+    adj = np.ascontiguousarray(adj, dtype=np.uint8)
+    out = np.empty(adj.shape[0], dtype=np.int32)
+    m = _L().orc_candidates(_ptr(adj), adj.shape[0], int(i), int(j), _ptr(out))
+    return [int(v) for v in out[:m]]
+
+
+def pair_index(i: int, j: int, p: int) -> int:
+    """Row-major index of the unordered pair i<j in the upper triangle."""
+    if i > j:
+        i, j = j, i
+    return i * p - i * (i + 1) // 2 + (j - i - 1)
+
+
+# ---------------------------------------------------------------- Phase I
+def skeleton(C: np.ndarray, n: int, alpha: float | None = None, q: float | None = None,
+             max_level: int = -1, reverse: bool = True, stable: bool = True,
+             max_tests: int = 0, nthreads: int = 0, verbose: bool = False) -> dict:
+    """Phase I (Algorithm 2 if ``reverse`` else Algorithm 1), sampling
+    version, on the correlation matrix ``C`` with sample size ``n``.
+
+    Returns a dict with ``adj`` (p x p uint8), ``sep_level``/``sep_kind``
+    (per pair i<j, row-major upper triangle), ``sepsets`` ({(i,j): list}
+    for LIST kind; ALL_BUT kind means K = V \\ {i,j}), ``levels`` (rows of
+    level, eligible edges, tests, deleted, degenerate), ``total_tests``,
+    ``min_margin`` (min |z - q| over the tests) and ``q``.
+    """
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    p = C.shape[0]
+    if q is None:
+        if alpha is None:
+            raise ValueError("alpha or q required")
+        q = quantile(alpha)
+    lib = _L()
+    R = lib.orc_skeleton(_ptr(C), p, int(n), float(q), int(max_level), int(reverse),
+                         int(stable), int(max_tests), int(nthreads), int(verbose))
+    if not R:
+        raise MemoryError("oracle allocation failed")
+    try:
+        st = lib.orc_result_status(R)
+        if st:
+            raise OracleError(st)
+        adj = np.empty((p, p), dtype=np.uint8)
+        lib.orc_result_adj(R, _ptr(adj))
+        P = p * (p - 1) // 2
+        lev = np.empty(P, dtype=np.int32)
+        kind = np.empty(P, dtype=np.int8)
+        off = np.empty(P + 1, dtype=np.int64)
+        tot = lib.orc_result_sepsets(R, _ptr(lev), _ptr(kind), _ptr(off), None, 0)
+        nodes = np.empty(max(tot, 1), dtype=np.int32)
+        lib.orc_result_sepsets(R, None, None, None, _ptr(nodes), tot)
+        nl = lib.orc_result_nlevels(R)
+        rows = np.empty((nl, 5), dtype=np.int64)
+        secs = np.empty(nl, dtype=np.float64)
+        lib.orc_result_levels(R, _ptr(rows), _ptr(secs))
+        sepsets = {}
+        iu, ju = np.triu_indices(p, 1)
+        for k in np.nonzero(kind == SEP_LIST)[0]:
+            sepsets[(int(iu[k]), int(ju[k]))] = [int(v) for v in nodes[off[k]:off[k + 1]]]
+        return dict(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets,
+                    levels=rows, level_seconds=secs,
+                    total_tests=int(lib.orc_result_total_tests(R)),
+                    min_margin=float(lib.orc_result_min_margin(R)), q=float(q), p=p, n=int(n))
+    finally:
+        lib.orc_result_free(R)
+
+
+def sepset_of(res: dict, i: int, j: int):
+    """The recorded separating set of pair (i, j), or None if kept."""
+    if i > j:
+        i, j = j, i
+    p = res["p"]
+    k = pair_index(i, j, p)
+    kind = int(res["sep_kind"][k])
+    if kind == SEP_NONE:
+        return None
+    if kind == SEP_ALL_BUT:
+        return [v for v in range(p) if v != i and v != j]
+    return list(res["sepsets"][(i, j)])

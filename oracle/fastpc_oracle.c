@@ -130,8 +130,10 @@ double orc_ppnd16(double p)
     return q < 0.0 ? -val : val;
 }
 
-/* Threshold of the sampling test, Phi^{-1}(1 - alpha/2). */
-double orc_quantile(double alpha) { return orc_ppnd16(1.0 - alpha / 2.0); }
+/* Threshold of the sampling test, Phi^{-1}(1 - alpha/2), taken as
+ * -Phi^{-1}(alpha/2) (symmetry of the normal law) so that the upper tail
+ * alpha/2 is never formed as 1 - alpha/2 in floating point. */
+double orc_quantile(double alpha) { return -orc_ppnd16(alpha / 2.0); }
 
 /* ------------------------------------------------------------------ */
 /* Correlation matrix of the data (row-major n x p), FP64 loops.       */

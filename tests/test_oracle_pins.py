@@ -28,10 +28,14 @@ def test_ppnd16_matches_library_ndtri():
         assert abs(got - ref) <= 1e-14 * max(1.0, abs(ref)), (p, got, ref)
 
 
-def test_quantile_values_at_benchmark_alphas():
-    # Phi^{-1}(1 - alpha/2) for alpha = 0.01 and 1e-3 (full-precision values)
-    assert oracle.quantile(0.01) == pytest.approx(2.5758293035489004, rel=1e-15)
-    assert oracle.quantile(1e-3) == pytest.approx(3.2905267314919255, rel=1e-15)
+def test_quantile_matches_high_precision_values():
+    """Phi^{-1}(1 - alpha/2) against 50-digit values (golden file)."""
+    for line in open(os.path.join(HERE, "golden", "normal_quantiles.txt")):
+        line = line.split("#", 1)[0].split()
+        if not line:
+            continue
+        alpha, ref = float(line[0]), float(line[1])
+        assert oracle.quantile(alpha) == pytest.approx(ref, rel=5e-16, abs=0), alpha
 
 
 def test_paper_printed_threshold_pins_n_minus_l_minus_3():

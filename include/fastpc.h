@@ -1,0 +1,194 @@
+/*
+ * fastpc.h -- C ABI of the MI355X (gfx950) skeleton library for the
+ * reverse-order pruning PC algorithm (Zhang, Tian, Johnson, Zhang, Jiang,
+ * "A Fast PC Algorithm with Reversed-order Pruning and A Parallelization
+ * Strategy", arXiv 2109.04626).
+ *
+ * Notation: the paper writes n for the number of variables and N for the
+ * number of samples; this interface writes p for variables and n for
+ * samples, and l = |K| for the size of a conditioning set.
+ *
+ * Conventions for every call:
+ *   - plain C types only; pointers are borrowed (the caller keeps
+ *     ownership) unless a call says it allocates;
+ *   - "device pointer" = memory on the context's HIP device, "host
+ *     pointer" = ordinary process memory;
+ *   - every int-returning call returns FPC_OK (0) or one of the FPC_E*
+ *     codes below and leaves its outputs untouched or undefined on error
+ *     (all-or-nothing for results that the library allocates);
+ *   - calls on one context are not thread-safe; different contexts are
+ *     independent.  Work is enqueued on the context's stream and every
+ *     call returns only after that work is complete, unless stated.
+ */
+#ifndef FASTPC_H
+#define FASTPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define FPC_OK 0
+#define FPC_EINVAL 1     /* bad argument: p < 2, n <= p + 1, alpha not in (0,1), NULL pointer, ... */
+#define FPC_ENONFINITE 2 /* NaN or Inf in the data                                                */
+#define FPC_ESINGULAR 3  /* correlation matrix not positive definite at the first level            */
+#define FPC_EBUDGET 4    /* test budget (max_tests) exceeded, or a level whose test count overflows */
+#define FPC_ENOMEM 5     /* host or device allocation failed                                       */
+#define FPC_EDEVICE 6    /* a HIP runtime call failed; fpc_last_hip_error() names it               */
+
+/* ---------------------------------------------------------------- enums */
+#define FPC_F64 0 /* IEEE binary64 elements */
+#define FPC_F32 1 /* IEEE binary32 elements */
+
+/* Correlation-matrix methods (fpc_corr). */
+#define FPC_CORR_FP64 0   /* FP64 centring and FP64 products            */
+#define FPC_CORR_BF16X3 1 /* bf16 split, three MFMA products, FP32 sums */
+
+/* Arithmetic of the level tests (fpc_params.precision). */
+#define FPC_PREC_FP64 0  /* FP64 correlation, FP64 tests                                   */
+#define FPC_PREC_MIXED 1 /* bf16x3 correlation, FP32 tests, FP64 re-run near the threshold */
+
+/* Level schedules (fpc_params.schedule). */
+#define FPC_REVERSE 0 /* Algorithm 2: l = p-2 down to 0, no early termination (Sec. 3.2)  */
+#define FPC_FORWARD 1 /* Algorithm 1 (PC-stable): l = 0 upward, early termination (2.2.1) */
+
+/* Order of the conditioning sets inside one level (fpc_params.order). */
+#define FPC_ORDER_LEX 0    /* lexicographic over the sorted candidate list                   */
+#define FPC_ORDER_SCORED 1 /* lexicographic over candidates sorted by a per-pair score       */
+
+/* Kinds of recorded separating sets (fpc_result.sep_kind). */
+#define FPC_SEP_NONE 0    /* edge kept                                                  */
+#define FPC_SEP_LIST 1    /* K listed in sep_nodes                                      */
+#define FPC_SEP_ALL_BUT 2 /* K = every variable except i and j (the l = p-2 level)      */
+
+typedef struct fpc_ctx fpc_ctx;
+
+/* ------------------------------------------------------------- context */
+/* Create a context on HIP device `hip_device`.  `hip_stream` is a
+ * hipStream_t to enqueue on, or NULL for a library-owned stream.  The
+ * context owns its device workspace (grown on demand, freed by
+ * fpc_destroy).  Errors: FPC_EINVAL (NULL out), FPC_EDEVICE. */
+int fpc_create(fpc_ctx **out, int hip_device, void *hip_stream);
+int fpc_destroy(fpc_ctx *ctx);
+
+/* Text of an error code (static storage). */
+const char *fpc_strerror(int code);
+/* Name of the last HIP error seen by any call on this thread ("" if none). */
+const char *fpc_last_hip_error(void);
+
+/* Phi^{-1}(1 - alpha/2): threshold of the two-sided Fisher-z test
+ * (Sec. 2.2.2).  Host-only; NaN for alpha outside (0,1). */
+double fpc_quantile(double alpha);
+
+/* ------------------------------------------------- correlation matrix (Sec. 5, "corr")
+ * X: device pointer, row-major n x p (sample t, variable j at X[t*p + j]),
+ * dtype x_dtype (FPC_F64 / FPC_F32).  C_out: device pointer, p x p
+ * row-major, FPC_F64 for FPC_CORR_FP64 and FPC_F32 for FPC_CORR_BF16X3.
+ * C_ij = S_ij / sqrt(S_ii S_jj) with S the covariance of the centred
+ * columns; C_ii = 1 exactly.  Errors: FPC_EINVAL (n < 2, p < 1, NULL),
+ * FPC_ENONFINITE (a non-finite sample), FPC_ESINGULAR (a constant column). */
+int fpc_corr(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out);
+
+/* --------------------------------------------- the first reverse level (Algorithm 2, l = p-2)
+ * On the complete graph every pair is conditioned on all other p-2
+ * variables, so r_ij = -Omega_ij / sqrt(Omega_ii Omega_jj) with
+ * Omega = C^{-1} (Sec. 5 formula with K = V \ {i,j}).  C: device, FP64,
+ * p x p.  r_out: device, FP64 p x p (diagonal set to 1).  indep_out:
+ * device, uint8 p x p, 1 where sqrt(n - (p-2) - 3) |atanh r| <= q.
+ * Either output may be NULL.  Errors: FPC_EINVAL (n <= p + 1),
+ * FPC_ESINGULAR (C not positive definite). */
+int fpc_first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
+                    uint8_t *indep_out);
+
+/* ------------------------------------------ one batch of CI tests (Sec. 5, index matrix B)
+ * B: device, int32, b rows of (2 + l) entries [i, j, k_1 .. k_l] (the
+ * paper's B^{b x (2+l)}); all indices in [0, p), distinct within a row.
+ * C: device, p x p, c_dtype FPC_F64 or FPC_F32; the tests run in that
+ * precision.  For each row: H = H0 - H1 H2^{-1} H1^T, r = h12/sqrt(h11 h22),
+ * z_out[row] = sqrt(n - l - 3) |atanh r| (FP64, device), indep_out[row] =
+ * (z <= q) (uint8, device).  A row whose H2 is not positive definite, whose
+ * h11 or h22 is not positive or whose |r| >= 1 is degenerate: z = NaN,
+ * indep = 0.  Either output may be NULL.  Errors: FPC_EINVAL (l < 0,
+ * n - l - 3 <= 0, b < 0, bad dtype). */
+int fpc_ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, const int32_t *B,
+                 int64_t b, double q, double *z_out, uint8_t *indep_out);
+
+/* ------------------------------------------------------- candidate sets (Sec. 2.1)
+ * Host-only.  For every edge (i<j, row-major order) of the undirected
+ * graph adj (host, uint8 p x p, symmetric, zero diagonal), the sorted set
+ * adj(G,i,j) n path(G,i,j): neighbours of i or j lying on a simple path
+ * between them.  Outputs (host): edge_i/edge_j[E], off[E+1] and
+ * nodes[off[E]].  Call once with nodes == NULL to get E (return value
+ * via *n_edges) and off[E] (via *n_nodes); buffers may be NULL when only
+ * counting.  Returns FPC_OK or FPC_EINVAL. */
+int fpc_candidates(const uint8_t *adj, int p, int64_t *n_edges, int64_t *n_nodes, int32_t *edge_i,
+                   int32_t *edge_j, int64_t *off, int32_t *nodes);
+
+/* ------------------------------------------------------------- skeleton (Phase I)
+ * Learns the skeleton and separating sets (Algorithm 2, stable variant,
+ * sampling version: Sec. 3.2 and 2.2.2; Algorithm 1 with FPC_FORWARD).
+ */
+typedef struct fpc_params {
+    int32_t n;            /* samples                                                         */
+    int32_t p;            /* variables                                                       */
+    const void *X;        /* data, row-major n x p                                           */
+    int32_t x_dtype;      /* FPC_F64 or FPC_F32                                              */
+    int32_t x_on_device;  /* 1: X is a device pointer, 0: host pointer (copied in)           */
+    double alpha;         /* significance level in (0,1)                                     */
+    int32_t max_level;    /* < 0 uncapped; else reverse levels after the first start at
+                             min(max_level, p-3) (the first level always runs), forward
+                             levels stop after max_level                                    */
+    int32_t precision;    /* FPC_PREC_FP64 or FPC_PREC_MIXED                                 */
+    double recheck_margin;/* mixed: FP32 tests with |z - q| below this (plus the per-test
+                             error bound) are re-run in FP64; <= 0 selects 1e-3             */
+    int32_t schedule;     /* FPC_REVERSE or FPC_FORWARD                                      */
+    int32_t order;        /* FPC_ORDER_LEX or FPC_ORDER_SCORED                               */
+    const float *score;   /* FPC_ORDER_SCORED: device, p x p FP32, score[i*p + k] ranks
+                             candidate k for edges at i (larger = earlier); NULL otherwise  */
+    int64_t max_tests;    /* 0 = unlimited, else FPC_EBUDGET past this many tests            */
+    double q_override;    /* NaN: q = Phi^{-1}(1 - alpha/2); else this threshold            */
+    uint32_t flags;       /* reserved, 0                                                     */
+} fpc_params;
+
+typedef struct fpc_level_stats {
+    int32_t level;            /* l                                                      */
+    int32_t max_cand;         /* largest |cand| among the level's edges                */
+    int64_t edges_eligible;   /* edges with |cand| >= l                                 */
+    int64_t tests_possible;   /* sum over eligible edges of C(|cand|, l)                */
+    int64_t tests_executed;   /* tests the GPU ran (early exit per edge and tile)       */
+    int64_t tests_rechecked;  /* mixed: FP32 tests re-run in FP64                       */
+    int64_t deleted;          /* edges removed at the end of the level                  */
+    double kernel_ms;         /* CI-test kernels, HIP events on the context stream      */
+    double level_ms;          /* whole level, host clock                                */
+} fpc_level_stats;
+
+typedef struct fpc_result {
+    int32_t p;
+    int32_t n_levels;
+    uint8_t *adj;             /* p*p, symmetric skeleton, zero diagonal                 */
+    int32_t *sep_level;       /* per pair i<j (row-major upper triangle index), -1 kept */
+    int8_t *sep_kind;         /* FPC_SEP_*                                              */
+    int64_t *sep_off;         /* P+1 offsets into sep_nodes (LIST kind only)            */
+    int32_t *sep_nodes;       /* sorted node ids                                        */
+    fpc_level_stats *levels;  /* n_levels rows, in execution order                      */
+    int64_t total_tests;      /* tests executed over all levels                          */
+    double q;                 /* threshold used                                          */
+    double corr_ms;           /* correlation matrix                                      */
+    double first_level_ms;    /* l = p-2 level (reverse schedule)                        */
+    double total_ms;          /* whole call, data resident on the device                 */
+    double corr_max_abs_err;  /* mixed: max |C_bf16x3 - C_fp64|, else 0                  */
+} fpc_result;
+
+/* Errors: FPC_EINVAL, FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET,
+ * FPC_ENOMEM, FPC_EDEVICE.  On success *out is a library allocation
+ * freed with fpc_result_free; on error *out is NULL. */
+int fpc_skeleton(fpc_ctx *ctx, const fpc_params *params, fpc_result **out);
+void fpc_result_free(fpc_result *r);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTPC_H */

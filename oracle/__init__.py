@@ -182,7 +182,8 @@ def pair_index(i: int, j: int, p: int) -> int:
 # ---------------------------------------------------------------- Phase I
 def skeleton(C: np.ndarray, n: int, alpha: float | None = None, q: float | None = None,
              max_level: int = -1, reverse: bool = True, stable: bool = True,
-             max_tests: int = 0, nthreads: int = 0, verbose: bool = False) -> dict:
+             max_tests: int = 0, nthreads: int = 0, verbose: bool = False,
+             partial_ok: bool = False) -> dict:
     """Phase I (Algorithm 2 if ``reverse`` else Algorithm 1), sampling
     version, on the correlation matrix ``C`` with sample size ``n``.
 
@@ -190,7 +191,10 @@ def skeleton(C: np.ndarray, n: int, alpha: float | None = None, q: float | None 
     (per pair i<j, row-major upper triangle), ``sepsets`` ({(i,j): list}
     for LIST kind; ALL_BUT kind means K = V \\ {i,j}), ``levels`` (rows of
     level, eligible edges, tests, deleted, degenerate), ``total_tests``,
-    ``min_margin`` (min |z - q| over the tests) and ``q``.
+    ``min_margin`` (min |z - q| over the tests) and ``q``.  With
+    ``partial_ok`` a run stopped by ``max_tests`` returns its counts so far
+    (``budget_stopped`` = True; the graph and separating sets are then
+    incomplete).
     """
     C = np.ascontiguousarray(C, dtype=np.float64)
     p = C.shape[0]
@@ -205,7 +209,8 @@ def skeleton(C: np.ndarray, n: int, alpha: float | None = None, q: float | None 
         raise MemoryError("oracle allocation failed")
     try:
         st = lib.orc_result_status(R)
-        if st:
+        stopped = st == ORC_EBUDGET and partial_ok
+        if st and not stopped:
             raise OracleError(st)
         adj = np.empty((p, p), dtype=np.uint8)
         lib.orc_result_adj(R, _ptr(adj))
@@ -227,7 +232,8 @@ def skeleton(C: np.ndarray, n: int, alpha: float | None = None, q: float | None 
         return dict(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets,
                     levels=rows, level_seconds=secs,
                     total_tests=int(lib.orc_result_total_tests(R)),
-                    min_margin=float(lib.orc_result_min_margin(R)), q=float(q), p=p, n=int(n))
+                    min_margin=float(lib.orc_result_min_margin(R)), q=float(q), p=p, n=int(n),
+                    budget_stopped=bool(stopped))
     finally:
         lib.orc_result_free(R)
 

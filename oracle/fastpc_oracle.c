@@ -45,7 +45,9 @@
  *   - a test whose H2 is not positive definite, whose h11 or h22 is not
  *     positive, or whose |r| >= 1 is "dependent" (edge kept), and counted;
  *   - max_level >= 0 caps the reverse levels after the first one at
- *     min(max_level, n-3); the first level always runs.
+ *     min(max_level, n-3); the first level always runs;
+ *   - corr is rejected as singular when some Omega_aa = 1/(1 - R^2_a) is
+ *     not positive or exceeds 1e12 (a variable determined by the others).
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so fastpc_oracle.c -lm
  */
@@ -621,8 +623,13 @@ orc_result *orc_skeleton(const double *C, int p, int n, double q, int max_level,
             int st = gauss_jordan(A, Om, p);
             free(A);
             if (st != ORC_OK) { free(Om); R->status = ORC_ESINGULAR; goto done; }
-            for (int a = 0; a < p; ++a)
-                if (!(Om[(size_t)a * p + a] > 0.0)) { free(Om); R->status = ORC_ESINGULAR; goto done; }
+            /* Omega_aa = 1 / (1 - R^2_a), R^2_a the squared multiple correlation of
+             * variable a on all others: a variable (numerically) determined by the
+             * others, 1 - R^2 < 1e-12, makes C singular for the test. */
+            for (int a = 0; a < p; ++a) {
+                const double oaa = Om[(size_t)a * p + a];
+                if (!(oaa > 0.0) || !(oaa <= 1e12)) { free(Om); R->status = ORC_ESINGULAR; goto done; }
+            }
             for (int i = 0; i < p; ++i)
                 for (int j = i + 1; j < p; ++j) {
                     int64_t pr = PAIR(i, j, p);

@@ -1,0 +1,333 @@
+"""Python binding of libfastpc (the C ABI in include/fastpc.h).
+
+Argument marshalling only: every step of the skeleton runs in the HIP
+library.  PyTorch provides device memory and the stream.  Importing this
+module fails if the library has not been built (python -m
+paper_2109_04626_amd.build); there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastpc.so")
+
+FPC_OK, FPC_EINVAL, FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET, FPC_ENOMEM, FPC_EDEVICE = range(7)
+FPC_F64, FPC_F32 = 0, 1
+FPC_CORR_FP64, FPC_CORR_BF16X3 = 0, 1
+FPC_PREC_FP64, FPC_PREC_MIXED = 0, 1
+FPC_REVERSE, FPC_FORWARD = 0, 1
+FPC_ORDER_LEX, FPC_ORDER_SCORED = 0, 1
+FPC_SEP_NONE, FPC_SEP_LIST, FPC_SEP_ALL_BUT = 0, 1, 2
+
+EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "fpc_quantile",
+            "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton",
+            "fpc_result_free"]
+
+
+class FastPCError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = f"{where}: {_strerror(code)}"
+        if code == FPC_EDEVICE:
+            msg += f" [{_lib.fpc_last_hip_error().decode()}]"
+        super().__init__(msg)
+        self.code = code
+
+
+class fpc_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("p", ctypes.c_int32), ("X", ctypes.c_void_p),
+                ("x_dtype", ctypes.c_int32), ("x_on_device", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("max_level", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("recheck_margin", ctypes.c_double),
+                ("schedule", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("score", ctypes.c_void_p), ("max_tests", ctypes.c_int64),
+                ("q_override", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class fpc_level_stats(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("max_cand", ctypes.c_int32),
+                ("edges_eligible", ctypes.c_int64), ("tests_possible", ctypes.c_int64),
+                ("tests_executed", ctypes.c_int64), ("tests_rechecked", ctypes.c_int64),
+                ("deleted", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
+                ("level_ms", ctypes.c_double)]
+
+
+class fpc_result(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("adj", ctypes.POINTER(ctypes.c_uint8)), ("sep_level", ctypes.POINTER(ctypes.c_int32)),
+                ("sep_kind", ctypes.POINTER(ctypes.c_int8)), ("sep_off", ctypes.POINTER(ctypes.c_int64)),
+                ("sep_nodes", ctypes.POINTER(ctypes.c_int32)),
+                ("levels", ctypes.POINTER(fpc_level_stats)), ("total_tests", ctypes.c_int64),
+                ("q", ctypes.c_double), ("corr_ms", ctypes.c_double),
+                ("first_level_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("corr_max_abs_err", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2109_04626_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    lib.fpc_create.argtypes = [ctypes.POINTER(vp), i, vp]
+    lib.fpc_create.restype = i
+    lib.fpc_destroy.argtypes = [vp]
+    lib.fpc_destroy.restype = i
+    lib.fpc_strerror.argtypes = [i]
+    lib.fpc_strerror.restype = ctypes.c_char_p
+    lib.fpc_last_hip_error.argtypes = []
+    lib.fpc_last_hip_error.restype = ctypes.c_char_p
+    lib.fpc_quantile.argtypes = [d]
+    lib.fpc_quantile.restype = d
+    lib.fpc_corr.argtypes = [vp, vp, i, i, i, i, vp]
+    lib.fpc_corr.restype = i
+    lib.fpc_first_level.argtypes = [vp, vp, i, i, d, vp, vp]
+    lib.fpc_first_level.restype = i
+    lib.fpc_ci_batch.argtypes = [vp, vp, i, i, i, i, vp, i64, d, vp, vp]
+    lib.fpc_ci_batch.restype = i
+    lib.fpc_candidates.argtypes = [vp, i, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp, vp]
+    lib.fpc_candidates.restype = i
+    lib.fpc_skeleton.argtypes = [vp, ctypes.POINTER(fpc_params), ctypes.POINTER(ctypes.POINTER(fpc_result))]
+    lib.fpc_skeleton.restype = i
+    lib.fpc_result_free.argtypes = [ctypes.POINTER(fpc_result)]
+    lib.fpc_result_free.restype = None
+    return lib
+
+
+_lib = _load()
+
+
+def _strerror(code: int) -> str:
+    return _lib.fpc_strerror(code).decode()
+
+
+def _check(code: int, where: str):
+    if code != FPC_OK:
+        raise FastPCError(code, where)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _t_ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ host calls
+def fpc_strerror(code: int) -> str:
+    return _strerror(code)
+
+
+def fpc_last_hip_error() -> str:
+    return _lib.fpc_last_hip_error().decode()
+
+
+def fpc_result_free(res) -> None:
+    """Results are copied into Python objects and freed by fpc_skeleton;
+    this accepts a raw POINTER(fpc_result) for completeness."""
+    if res:
+        _lib.fpc_result_free(res)
+
+
+def fpc_quantile(alpha: float) -> float:
+    return float(_lib.fpc_quantile(float(alpha)))
+
+
+def fpc_candidates(adj: np.ndarray):
+    """(edge_i, edge_j, off, nodes) of adj(G,i,j) n path(G,i,j) per edge."""
+    adj = np.ascontiguousarray(adj, dtype=np.uint8)
+    p = adj.shape[0]
+    E, N = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.fpc_candidates(_np_ptr(adj), p, ctypes.byref(E), ctypes.byref(N), None, None, None, None),
+           "fpc_candidates")
+    ei = np.empty(E.value, np.int32)
+    ej = np.empty(E.value, np.int32)
+    off = np.empty(E.value + 1, np.int64)
+    nodes = np.empty(max(N.value, 1), np.int32)
+    _check(_lib.fpc_candidates(_np_ptr(adj), p, ctypes.byref(E), ctypes.byref(N), _np_ptr(ei), _np_ptr(ej),
+                               _np_ptr(off), _np_ptr(nodes)), "fpc_candidates")
+    return ei, ej, off, nodes[: N.value]
+
+
+# ------------------------------------------------------------------ device calls
+class Context:
+    """An fpc_ctx on a HIP device, enqueuing on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(_lib.fpc_create(ctypes.byref(h), int(device), ctypes.c_void_p(stream.cuda_stream)), "fpc_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fpc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def fpc_create(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+def fpc_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def _dtype_code(t):
+    import torch
+
+    if t.dtype == torch.float64:
+        return FPC_F64
+    if t.dtype == torch.float32:
+        return FPC_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def fpc_corr(ctx: Context, X, method: int = FPC_CORR_FP64):
+    """Correlation matrix of the device tensor X (n x p, row-major)."""
+    import torch
+
+    X = X.contiguous()
+    n, p = X.shape
+    out = torch.empty((p, p), dtype=torch.float64 if method == FPC_CORR_FP64 else torch.float32, device=X.device)
+    _check(_lib.fpc_corr(ctx.handle, _t_ptr(X), _dtype_code(X), n, p, int(method), _t_ptr(out)), "fpc_corr")
+    return out
+
+
+def fpc_first_level(ctx: Context, C, n: int, q: float):
+    """(r, indep) of the l = p-2 level on the FP64 device matrix C."""
+    import torch
+
+    C = C.contiguous()
+    p = C.shape[0]
+    r = torch.empty((p, p), dtype=torch.float64, device=C.device)
+    ind = torch.empty((p, p), dtype=torch.uint8, device=C.device)
+    _check(_lib.fpc_first_level(ctx.handle, _t_ptr(C), p, int(n), float(q), _t_ptr(r), _t_ptr(ind)),
+           "fpc_first_level")
+    return r, ind
+
+
+def fpc_ci_batch(ctx: Context, C, n: int, B, q: float):
+    """(z, indep) for the rows [i, j, k_1..k_l] of the int32 device matrix B."""
+    import torch
+
+    C = C.contiguous()
+    B = B.contiguous()
+    assert B.dtype == torch.int32 and B.dim() == 2
+    b, w = B.shape
+    l = w - 2
+    z = torch.empty(b, dtype=torch.float64, device=C.device)
+    ind = torch.empty(b, dtype=torch.uint8, device=C.device)
+    _check(_lib.fpc_ci_batch(ctx.handle, _t_ptr(C), _dtype_code(C), C.shape[0], int(n), l, _t_ptr(B), b,
+                             float(q), _t_ptr(z), _t_ptr(ind)), "fpc_ci_batch")
+    return z, ind
+
+
+def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, precision: int = FPC_PREC_FP64,
+                 recheck_margin: float = 1e-3, schedule: int = FPC_REVERSE, max_tests: int = 0,
+                 q_override: float = float("nan")) -> dict:
+    """Skeleton and separating sets of the data X (torch tensor on the
+    device, or a host numpy array), n x p row-major."""
+    prm = fpc_params()
+    keep = X
+    if isinstance(X, np.ndarray):
+        keep = np.ascontiguousarray(X)
+        n, p = keep.shape
+        prm.X = _np_ptr(keep)
+        prm.x_dtype = FPC_F64 if keep.dtype == np.float64 else FPC_F32
+        if keep.dtype not in (np.float64, np.float32):
+            raise TypeError(keep.dtype)
+        prm.x_on_device = 0
+    else:
+        keep = X.contiguous()
+        n, p = keep.shape
+        prm.X = _t_ptr(keep).value
+        prm.x_dtype = _dtype_code(keep)
+        prm.x_on_device = 1
+    prm.n, prm.p = n, p
+    prm.alpha = float(alpha)
+    prm.max_level = int(max_level)
+    prm.precision = int(precision)
+    prm.recheck_margin = float(recheck_margin)
+    prm.schedule = int(schedule)
+    prm.order = FPC_ORDER_LEX
+    prm.score = None
+    prm.max_tests = int(max_tests)
+    prm.q_override = float(q_override)
+    prm.flags = 0
+    res = ctypes.POINTER(fpc_result)()
+    _check(_lib.fpc_skeleton(ctx.handle, ctypes.byref(prm), ctypes.byref(res)), "fpc_skeleton")
+    try:
+        return _unpack(res.contents)
+    finally:
+        _lib.fpc_result_free(res)
+
+
+def _unpack(r: fpc_result) -> dict:
+    p = r.p
+    P = p * (p - 1) // 2
+    adj = np.ctypeslib.as_array(r.adj, shape=(p * p,)).reshape(p, p).copy()
+    lev = np.ctypeslib.as_array(r.sep_level, shape=(P,)).copy() if P else np.zeros(0, np.int32)
+    kind = np.ctypeslib.as_array(r.sep_kind, shape=(P,)).copy() if P else np.zeros(0, np.int8)
+    off = np.ctypeslib.as_array(r.sep_off, shape=(P + 1,)).copy()
+    tot = int(off[-1])
+    nodes = np.ctypeslib.as_array(r.sep_nodes, shape=(max(tot, 1),))[:tot].copy()
+    sepsets = {}
+    iu, ju = np.triu_indices(p, 1)
+    for k in np.nonzero(kind == FPC_SEP_LIST)[0]:
+        sepsets[(int(iu[k]), int(ju[k]))] = [int(v) for v in nodes[off[k]:off[k + 1]]]
+    levels = []
+    for k in range(r.n_levels):
+        s = r.levels[k]
+        levels.append({f: getattr(s, f) for f, _ in fpc_level_stats._fields_})
+    return dict(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets, levels=levels,
+                total_tests=int(r.total_tests), q=float(r.q), corr_ms=float(r.corr_ms),
+                first_level_ms=float(r.first_level_ms), total_ms=float(r.total_ms),
+                corr_max_abs_err=float(r.corr_max_abs_err), p=p)
+
+
+def sepset_of(res: dict, i: int, j: int):
+    """Recorded separating set of (i, j) from a fpc_skeleton result, or None."""
+    if i > j:
+        i, j = j, i
+    p = res["p"]
+    k = i * p - i * (i + 1) // 2 + (j - i - 1)
+    kind = int(res["sep_kind"][k])
+    if kind == FPC_SEP_NONE:
+        return None
+    if kind == FPC_SEP_ALL_BUT:
+        return [v for v in range(p) if v not in (i, j)]
+    return list(res["sepsets"][(i, j)])
+
+
+def tests_per_second(res: dict) -> float:
+    """Executed CI tests of the levels after the first / their kernel time."""
+    lv = res["levels"][1:] if res["levels"] and res["levels"][0]["level"] == res["p"] - 2 else res["levels"]
+    t = sum(x["kernel_ms"] for x in lv) / 1e3
+    n = sum(x["tests_executed"] for x in lv)
+    return n / t if t > 0 else math.nan

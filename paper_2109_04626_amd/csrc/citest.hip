@@ -1,0 +1,839 @@
+// Level tests of Algorithm 2 (Sec. 3.2) with the Fisher-z CI test of
+// Sec. 2.2.2 and the partial correlation of Sec. 5:
+//     H = H0 - H1 H2^{-1} H1^T,  r = h12 / sqrt(h11 h22),
+//     independent iff sqrt(n - l - 3) |atanh r| <= q.
+// H is formed through a Cholesky factorisation H2 = L L^T:
+//     u = L^{-1} C_Ki, v = L^{-1} C_Kj,
+//     h11 = 1 - u.u,  h22 = 1 - v.v,  h12 = C_ij - u.v
+// (the unit diagonal of a correlation matrix is used directly).
+//
+// Work layout.  One level enumerates, for every edge e with m_e = |cand|
+// >= l, the C(m_e, l) l-subsets of its sorted candidate list in
+// lexicographic order; rank r of edge e is the r-th subset.  A launch
+// covers a window of ranks [lo, hi) of every edge; a workgroup owns
+// kRanksPerBlock consecutive ranks of one edge and first stages that
+// edge's correlation entries in LDS (strict upper triangle over the
+// candidates plus the i and j rows: m(m-1)/2 + 2m + 1 values).  Each
+// wave walks 64 consecutive ranks per step: neighbouring lanes then share
+// the first l-1 elements of K (broadcast LDS reads) and differ in the last
+// one (consecutive LDS addresses).  Each lane runs one test with the
+// factor in registers (l <= kMaxTemplL, l a template parameter).
+//
+// Edge deletion: a hit (independent test) at rank r lowers the edge's
+// minhit to r with one atomicMin per wave (ballot of the lanes, lowest
+// lane).  A wave or workgroup whose ranks all lie above the current minhit
+// stops, so each edge's final minhit is the lexicographically first
+// separating set whatever the launch order.
+//
+// Mixed precision: FP32 tests whose z lies within band of q (band = the
+// stated margin plus a bound on the FP32 error of this test) are appended
+// to a queue (ballot + prefix sum per wave) and re-run in FP64 from the
+// FP64 matrix by the recheck kernel; degenerate FP32 tests are re-run too.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "fpc_internal.h"
+
+namespace fpc {
+
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kSteps = 8;
+constexpr int kRanksPerWave = 64 * kSteps;
+constexpr int kRanksPerBlock = kWaves * kRanksPerWave;  // 2048
+constexpr int kGenericRanks = 16;                        // ranks per workgroup, wide-level kernel
+constexpr double kErrSafety = 4.0;                       // multiplier of the FP32 error bound
+
+enum : int { DEC_DEP = 0, DEC_INDEP = 1, DEC_RECHECK = 2 };
+
+__device__ __forceinline__ uint64_t load_minhit(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
+// ------------------------------------------------------------------ views
+// Candidate positions 0..m-1 index the edge's candidate list; i and j are
+// addressed separately.  kk(row(a), b) = C(cand[a], cand[b]).
+template <typename T>
+struct PackedTile {
+    const T *tri, *ci, *cj;
+    T cij;
+    int m;
+    __device__ __forceinline__ int row(int a) const { return a * (2 * m - a - 3) / 2 - 1; }
+    __device__ __forceinline__ T kk(int rowa, int b) const { return tri[rowa + b]; }  // a < b
+    __device__ __forceinline__ T ki(int b) const { return ci[b]; }
+    __device__ __forceinline__ T kj(int b) const { return cj[b]; }
+    __device__ __forceinline__ T ij() const { return cij; }
+};
+
+template <typename T>
+struct GlobalRows {
+    const T *C;
+    int p;
+    const int32_t *cand;
+    int i, j;
+    __device__ __forceinline__ int row(int a) const { return cand[a] * p; }
+    __device__ __forceinline__ T kk(int rowa, int b) const { return C[(size_t)rowa + cand[b]]; }
+    __device__ __forceinline__ T ki(int b) const { return C[(size_t)i * p + cand[b]]; }
+    __device__ __forceinline__ T kj(int b) const { return C[(size_t)j * p + cand[b]]; }
+    __device__ __forceinline__ T ij() const { return C[(size_t)i * p + j]; }
+};
+
+// Rows of the index matrix B: positions are variable ids, any order.
+template <typename T>
+struct DirectRows {
+    const T *C;
+    int p, i, j;
+    __device__ __forceinline__ int row(int a) const { return a * p; }
+    __device__ __forceinline__ T kk(int rowa, int b) const { return C[(size_t)rowa + b]; }
+    __device__ __forceinline__ T ki(int b) const { return C[(size_t)i * p + b]; }
+    __device__ __forceinline__ T kj(int b) const { return C[(size_t)j * p + b]; }
+    __device__ __forceinline__ T ij() const { return C[(size_t)i * p + j]; }
+};
+
+// ------------------------------------------------------------------ one test
+// r and the smallest pivot (d of K, h11, h22) of the factorisation; ok is
+// false for a degenerate test (pivot <= 0, h11 or h22 <= 0, |r| >= 1).
+template <typename T, int L, class View>
+__device__ __forceinline__ void pcor_reg(const View &V, const int *k, T &r, T &dmin, bool &ok)
+{
+    constexpr int LL = L > 0 ? L : 1;
+    T Lf[L > 0 ? L * (L + 1) / 2 : 1];
+    T u[LL], v[LL], inv[LL];
+    int rw[LL];
+    ok = true;
+    dmin = T(1);
+    T h11 = T(1), h22 = T(1), h12 = V.ij();
+#pragma unroll
+    for (int t = 0; t < L; ++t) rw[t] = V.row(k[t]);
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const int kt = k[t];
+        T *Lt = Lf + t * (t + 1) / 2;
+#pragma unroll
+        for (int s = 0; s < t; ++s) {
+            T a = V.kk(rw[s], kt);
+            const T *Ls = Lf + s * (s + 1) / 2;
+#pragma unroll
+            for (int c = 0; c < s; ++c) a -= Lt[c] * Ls[c];
+            Lt[s] = a * inv[s];
+        }
+        T d = T(1);
+#pragma unroll
+        for (int c = 0; c < t; ++c) d -= Lt[c] * Lt[c];
+        ok = ok && (d > T(0));
+        dmin = d < dmin ? d : dmin;
+        inv[t] = rsq(d);
+        T ai = V.ki(kt), aj = V.kj(kt);
+#pragma unroll
+        for (int c = 0; c < t; ++c) {
+            ai -= Lt[c] * u[c];
+            aj -= Lt[c] * v[c];
+        }
+        u[t] = ai * inv[t];
+        v[t] = aj * inv[t];
+        h11 -= u[t] * u[t];
+        h22 -= v[t] * v[t];
+        h12 -= u[t] * v[t];
+    }
+    ok = ok && (h11 > T(0)) && (h22 > T(0));
+    dmin = h11 < dmin ? h11 : dmin;
+    dmin = h22 < dmin ? h22 : dmin;
+    r = h12 * rsq(h11 * h22);
+    ok = ok && (fabs(r) < T(1));
+}
+
+struct Thresholds {
+    double q;       // Phi^{-1}(1 - alpha/2)
+    double r_lo;    // below: surely z < q
+    double r_hi;    // above: surely z > q
+    double sqrt_nu; // sqrt(n - l - 3)
+    double band_z;  // mixed: stated margin (z units)
+    double c_eff;   // mixed: entry error bound of the FP32 matrix + FP32 rounding
+};
+
+// FP64 decision identical in form to the reference rule z <= q.
+__device__ __forceinline__ bool decide64(double r, bool ok, const Thresholds &th)
+{
+    if (!ok) return false;
+    const double a = fabs(r);
+    if (a < th.r_lo) return true;
+    if (a > th.r_hi) return false;
+    return th.sqrt_nu * fabs(atanh(r)) <= th.q;
+}
+
+template <int L>
+__device__ __forceinline__ int decide32(float r, float dmin, bool ok, const Thresholds &th)
+{
+    if (!ok) return DEC_RECHECK;
+    const float a = fabsf(r);
+    const float snu = (float)th.sqrt_nu;
+    const float z = snu * 0.5f * __logf((1.0f + a) / (1.0f - a));
+    const float err = (float)kErrSafety * snu * (float)th.c_eff * (float)(L + 2) / (dmin * (1.0f - a * a));
+    const float band = (float)th.band_z + err;
+    const float qf = (float)th.q;
+    if (z < qf - band) return DEC_INDEP;
+    if (z > qf + band) return DEC_DEP;
+    return DEC_RECHECK;
+}
+
+// ------------------------------------------------------------------ enumeration
+// C(a, b) from the table, through C(a, b) = C(a, a - b): every value the
+// enumeration reads is at most C(m, l) < 2^63, which forces min(b, a-b) <= 33.
+__device__ __forceinline__ int64_t binom_at(const int64_t *__restrict__ binom, int a, int b)
+{
+    if (b < 0 || b > a) return 0;
+    const int bb = min(b, a - b);
+    return bb < kBinomCols ? binom[a * kBinomCols + bb] : INT64_MAX;
+}
+
+// Lexicographic unranking of rank R among the L-subsets of m positions.
+template <int L>
+__device__ __forceinline__ void unrank(int64_t R, int m, const int64_t *__restrict__ binom, int *c)
+{
+    int x = 0;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        for (;;) {
+            const int a = m - 1 - x;
+            if (a < L - 1 - t) break;  // never taken for R < C(m, L)
+            const int64_t cnt = binom_at(binom, a, L - 1 - t);
+            if (R < cnt) break;
+            R -= cnt;
+            ++x;
+        }
+        c[t] = x;
+        ++x;
+    }
+}
+
+// Given c = the combination at some rank b (wave-uniform), set my = the
+// combination at rank b + lane and advance c to rank b + 64.  Lanes past
+// the last combination keep the (valid) initial my.  Returns false when no
+// combination follows rank b + 63.
+template <int L>
+__device__ __forceinline__ bool walk64(int *c, int m, int lane, int *my)
+{
+    int cur[L];
+#pragma unroll
+    for (int s = 0; s < L; ++s) {
+        cur[s] = c[s];
+        my[s] = s;
+    }
+    int off = 0;
+    for (int guard = 0; guard <= 64; ++guard) {
+        const int leaves = m - cur[L - 1];
+        const int t = lane - off;
+        if (t >= 0 && t < leaves) {
+#pragma unroll
+            for (int s = 0; s < L - 1; ++s) my[s] = cur[s];
+            my[L - 1] = cur[L - 1] + t;
+        }
+        if (off + leaves > 64) {
+#pragma unroll
+            for (int s = 0; s < L - 1; ++s) c[s] = cur[s];
+            c[L - 1] = cur[L - 1] + (64 - off);
+            return true;
+        }
+        off += leaves;
+        int a = -1;
+#pragma unroll
+        for (int s = 0; s + 1 < L; ++s)
+            if (cur[s] != m - L + s) a = s;
+        if (a < 0) return false;
+#pragma unroll
+        for (int s = 0; s < L; ++s) {
+            if (s == a) cur[s] += 1;
+            else if (s > a) cur[s] = cur[s - 1] + 1;
+        }
+        if (off == 64) {
+#pragma unroll
+            for (int s = 0; s < L; ++s) c[s] = cur[s];
+            return true;
+        }
+    }
+    return false;
+}
+
+struct LevelArgs {
+    const EdgeRec *edges;
+    const int32_t *cand;
+    const void *C;
+    const double *C64;
+    const int64_t *blockoff;  // n_edges + 1 prefix of workgroups per edge
+    const int64_t *binom;
+    uint64_t *minhit;
+    unsigned long long *counters;
+    int64_t *queue;
+    int64_t queue_cap;
+    int64_t n_edges;
+    int64_t win_lo, win_hi;
+    int p;
+    int ranks_per_block;
+    Thresholds th;
+};
+
+__device__ __forceinline__ int64_t find_edge(const int64_t *__restrict__ off, int64_t n, int64_t b)
+{
+    int64_t lo = 0, hi = n;  // off[lo] <= b < off[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ void stage_tile(const T *__restrict__ C, int p, const int32_t *__restrict__ cand, int m, int i, int j,
+                           T *tri, T *ci, T *cj)
+{
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+        const int a = t / m, b = t % m;
+        if (a < b) tri[a * (2 * m - a - 3) / 2 - 1 + b] = C[(size_t)cand[a] * p + cand[b]];
+    }
+    for (int b = threadIdx.x; b < m; b += blockDim.x) {
+        ci[b] = C[(size_t)i * p + cand[b]];
+        cj[b] = C[(size_t)j * p + cand[b]];
+    }
+}
+
+// ------------------------------------------------------------------ level kernel
+template <typename T, int L, bool TILE>
+__global__ __launch_bounds__(256) void level_kernel(LevelArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t blk = blockIdx.x;
+    const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
+    const EdgeRec E = A.edges[e];
+    const int m = E.m;
+    const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * kRanksPerBlock;
+    const int64_t r1 = min(r0 + (int64_t)kRanksPerBlock, min(A.win_hi, E.ntests));
+    if (r0 >= r1) return;  // uniform
+    __shared__ int skip;
+    if (threadIdx.x == 0) skip = load_minhit(&A.minhit[e]) < (uint64_t)r0;
+    __syncthreads();
+    if (skip) return;  // uniform
+    const T *C = static_cast<const T *>(A.C);
+    const int32_t *cand = A.cand + E.cand_off;
+
+    PackedTile<T> tile{};
+    GlobalRows<T> glob{C, A.p, cand, E.i, E.j};
+    if constexpr (TILE) {
+        T *tri = reinterpret_cast<T *>(smem);
+        const int ntri = m * (m - 1) / 2;
+        T *ci = tri + ntri, *cj = ci + m;
+        stage_tile<T>(C, A.p, cand, m, E.i, E.j, tri, ci, cj);
+        tile = PackedTile<T>{tri, ci, cj, C[(size_t)E.i * A.p + E.j], m};
+        __syncthreads();
+    }
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int64_t wlo = r0 + (int64_t)wave * kRanksPerWave;
+    const int64_t whi = min(wlo + (int64_t)kRanksPerWave, r1);
+    uint64_t executed = 0;
+    if (wlo < whi) {
+        constexpr int LL = L > 0 ? L : 1;
+        int c[LL], my[LL];
+        if constexpr (L > 0) unrank<L>(wlo, m, A.binom, c);
+        for (int64_t base = wlo; base < whi; base += 64) {
+            const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
+            if (mh < (unsigned long long)base) break;
+            bool more = true;
+            if constexpr (L > 0) more = walk64<L>(c, m, lane, my);
+            const bool valid = base + lane < whi;
+            T r, dmin;
+            bool ok;
+            if constexpr (TILE) pcor_reg<T, L>(tile, my, r, dmin, ok);
+            else pcor_reg<T, L>(glob, my, r, dmin, ok);
+            int dec;
+            if constexpr (sizeof(T) == 8) dec = decide64((double)r, ok, A.th) ? DEC_INDEP : DEC_DEP;
+            else dec = decide32<L>((float)r, (float)dmin, ok, A.th);
+            const uint64_t nvalid = (uint64_t)min((int64_t)64, whi - base);
+            executed += nvalid;
+            if constexpr (sizeof(T) == 4) {
+                const bool rq = valid && dec == DEC_RECHECK;
+                const unsigned long long qb = __ballot(rq);
+                if (qb) {
+                    unsigned long long slot = 0;
+                    if (lane == 0) slot = atomicAdd(&A.counters[1], (unsigned long long)__popcll(qb));
+                    slot = __shfl(slot, 0);
+                    if (rq) {
+                        const unsigned long long idx = slot + __popcll(qb & ((1ull << lane) - 1ull));
+                        if ((int64_t)idx < A.queue_cap) {
+                            A.queue[2 * idx] = e;
+                            A.queue[2 * idx + 1] = base + lane;
+                        }
+                    }
+                }
+            }
+            const unsigned long long hb = __ballot(valid && dec == DEC_INDEP);
+            if (hb) {
+                if (lane == 0) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)(base + __ffsll((long long)hb) - 1));
+                break;
+            }
+            if (!more) break;
+        }
+    }
+    if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
+}
+
+// FP64 re-run of queued FP32 tests (rank below the edge's current minhit).
+template <int L>
+__global__ __launch_bounds__(256) void recheck_kernel(LevelArgs A)
+{
+    const unsigned long long queued = A.counters[1];
+    const unsigned long long total = min((unsigned long long)A.queue_cap, queued);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && queued > (unsigned long long)A.queue_cap)
+        atomicMax(&A.counters[3], 1ull);  // entries were dropped: the caller re-runs the level in FP64
+    unsigned long long done = 0;
+    for (unsigned long long idx = (unsigned long long)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (unsigned long long)gridDim.x * 256) {
+        const int64_t e = A.queue[2 * idx], R = A.queue[2 * idx + 1];
+        if ((uint64_t)R >= load_minhit(&A.minhit[e])) continue;
+        const EdgeRec E = A.edges[e];
+        int k[L > 0 ? L : 1];
+        if constexpr (L > 0) unrank<L>(R, E.m, A.binom, k);
+        GlobalRows<double> g{A.C64, A.p, A.cand + E.cand_off, E.i, E.j};
+        double r, dmin;
+        bool ok;
+        pcor_reg<double, L>(g, k, r, dmin, ok);
+        ++done;
+        if (decide64(r, ok, A.th)) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
+    }
+    if (done) atomicAdd(&A.counters[2], done);
+}
+
+// ------------------------------------------------------------------ wide levels
+// One wave per test, the (l+2)x(l+2) matrix over [K, i, j] packed lower in
+// LDS, right-looking Cholesky; after l steps the trailing 2x2 block is H.
+template <typename T>
+__device__ bool wave_pcor(T *M, int l, int lane, T &r)
+{
+    auto at = [&](int a, int b) -> T & { return M[a * (a + 1) / 2 + b]; };  // a >= b
+    const int n2 = l + 2;
+    for (int t = 0; t < l; ++t) {
+        const T d = at(t, t);
+        if (!(d > T(0))) return false;  // uniform: every lane reads the same value
+        const T s = rsq(d);
+        for (int a = t + 1 + lane; a < n2; a += 64) at(a, t) *= s;
+        __syncthreads();
+        const int rem = n2 - t - 1;
+        for (int idx = lane; idx < rem * (rem + 1) / 2; idx += 64) {
+            // idx -> (a, b) with t < b <= a
+            int a = (int)((sqrtf(8.0f * idx + 1.0f) - 1.0f) * 0.5f);
+            while ((a + 1) * (a + 2) / 2 <= idx) ++a;
+            while (a * (a + 1) / 2 > idx) --a;
+            const int b = idx - a * (a + 1) / 2;
+            const int aa = t + 1 + a, bb = t + 1 + b;
+            at(aa, bb) -= at(aa, t) * at(bb, t);
+        }
+        __syncthreads();
+    }
+    const T h11 = at(l, l), h22 = at(l + 1, l + 1), h12 = at(l + 1, l);
+    if (!(h11 > T(0)) || !(h22 > T(0))) return false;
+    r = h12 * rsq(h11 * h22);
+    return fabs(r) < T(1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void level_kernel_wide(LevelArgs A, int l)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *M = reinterpret_cast<T *>(smem);
+    int *k = reinterpret_cast<int *>(M + (size_t)(l + 2) * (l + 3) / 2 + 1);
+    const int64_t blk = blockIdx.x;
+    const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
+    const EdgeRec E = A.edges[e];
+    const int m = E.m;
+    const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * A.ranks_per_block;
+    const int64_t r1 = min(r0 + (int64_t)A.ranks_per_block, min(A.win_hi, E.ntests));
+    if (r0 >= r1) return;
+    const T *C = static_cast<const T *>(A.C);
+    const int32_t *cand = A.cand + E.cand_off;
+    const int lane = threadIdx.x;
+    // unrank r0 into k (lane 0), shared through LDS
+    if (lane == 0) {
+        int64_t R = r0;
+        int x = 0;
+        for (int t = 0; t < l; ++t) {
+            for (;;) {
+                const int a = m - 1 - x;
+                if (a < l - 1 - t) break;
+                const int64_t cnt = binom_at(A.binom, a, l - 1 - t);
+                if (R < cnt) break;
+                R -= cnt;
+                ++x;
+            }
+            k[t] = x++;
+        }
+    }
+    __syncthreads();
+    uint64_t executed = 0;
+    for (int64_t R = r0; R < r1; ++R) {
+        const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
+        if (mh < (unsigned long long)R) break;  // wave-uniform
+        __syncthreads();
+        // gather [cand[k_0..k_{l-1}], i, j]
+        const int n2 = l + 2;
+        for (int idx = lane; idx < n2 * (n2 + 1) / 2; idx += 64) {
+            int a = (int)((sqrtf(8.0f * idx + 1.0f) - 1.0f) * 0.5f);
+            while ((a + 1) * (a + 2) / 2 <= idx) ++a;
+            while (a * (a + 1) / 2 > idx) --a;
+            const int b = idx - a * (a + 1) / 2;
+            const int va = a < l ? cand[k[a]] : (a == l ? E.i : E.j);
+            const int vb = b < l ? cand[k[b]] : (b == l ? E.i : E.j);
+            M[idx] = C[(size_t)va * A.p + vb];
+        }
+        __syncthreads();
+        T r;
+        const bool ok = wave_pcor<T>(M, l, lane, r);
+        ++executed;
+        bool indep = false;
+        if (ok) {
+            const double a = fabs((double)r);
+            indep = a < A.th.r_lo ? true
+                  : a > A.th.r_hi ? false
+                  : A.th.sqrt_nu * fabs(atanh((double)r)) <= A.th.q;
+        }
+        if (indep) {
+            if (lane == 0) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
+            break;
+        }
+        __syncthreads();
+        if (lane == 0) {  // next combination
+            int a = l - 1;
+            while (a >= 0 && k[a] == m - l + a) --a;
+            if (a >= 0) {
+                ++k[a];
+                for (int b = a + 1; b < l; ++b) k[b] = k[b - 1] + 1;
+            }
+        }
+        __syncthreads();
+    }
+    if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
+}
+
+// ------------------------------------------------------------------ compaction
+__global__ __launch_bounds__(256) void compact_kernel(const uint64_t *__restrict__ minhit, int64_t n,
+                                                      int64_t *__restrict__ out, unsigned long long *__restrict__ cnt)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x % 64;
+    const bool del = e < n && minhit[e] != ~0ull;
+    const unsigned long long b = __ballot(del);
+    if (!b) return;
+    unsigned long long slot = 0;
+    if (lane == 0) slot = atomicAdd(cnt, (unsigned long long)__popcll(b));
+    slot = __shfl(slot, 0);
+    if (del) {
+        const unsigned long long idx = slot + __popcll(b & ((1ull << lane) - 1ull));
+        out[2 * idx] = e;
+        out[2 * idx + 1] = (int64_t)minhit[e];
+    }
+}
+
+// ------------------------------------------------------------------ index-matrix batch
+template <typename T, int L>
+__global__ __launch_bounds__(256) void batch_kernel(const T *__restrict__ C, int p, const int32_t *__restrict__ B,
+                                                    int64_t b, Thresholds th, double *__restrict__ z_out,
+                                                    uint8_t *__restrict__ ind_out, int *__restrict__ bad)
+{
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= b) return;
+    const int32_t *Br = B + row * (2 + L);
+    int k[L > 0 ? L : 1];
+    bool inb = Br[0] >= 0 && Br[0] < p && Br[1] >= 0 && Br[1] < p;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        k[t] = Br[2 + t];
+        inb = inb && k[t] >= 0 && k[t] < p;
+    }
+    if (!inb) {  // out-of-range index: flagged, nothing read
+        if (z_out) z_out[row] = NAN;
+        if (ind_out) ind_out[row] = 0;
+        atomicOr(bad, 1);
+        return;
+    }
+    DirectRows<T> V{C, p, Br[0], Br[1]};
+    T r, dmin;
+    bool ok;
+    pcor_reg<T, L>(V, k, r, dmin, ok);
+    double z = NAN;
+    uint8_t ind = 0;
+    if (ok) {
+        if constexpr (sizeof(T) == 8) {
+            z = th.sqrt_nu * fabs(atanh((double)r));
+            ind = decide64((double)r, ok, th);
+        } else {
+            const float zf = (float)th.sqrt_nu * fabsf(atanhf((float)r));
+            z = zf;
+            ind = zf <= (float)th.q;
+        }
+    }
+    if (z_out) z_out[row] = z;
+    if (ind_out) ind_out[row] = ind;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void batch_kernel_wide(const T *__restrict__ C, int p, const int32_t *__restrict__ B,
+                                                        int64_t b, int l, Thresholds th, double *__restrict__ z_out,
+                                                        uint8_t *__restrict__ ind_out, int *__restrict__ bad)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *M = reinterpret_cast<T *>(smem);
+    const int64_t row = blockIdx.x;
+    const int32_t *Br = B + row * (2 + l);
+    const int n2 = l + 2;
+    __shared__ int oob;
+    if (threadIdx.x == 0) oob = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < n2; t += 64)
+        if (Br[t] < 0 || Br[t] >= p) oob = 1;
+    __syncthreads();
+    if (oob) {  // uniform
+        if (threadIdx.x == 0) {
+            if (z_out) z_out[row] = NAN;
+            if (ind_out) ind_out[row] = 0;
+            atomicOr(bad, 1);
+        }
+        return;
+    }
+    for (int idx = threadIdx.x; idx < n2 * (n2 + 1) / 2; idx += 64) {
+        int a = (int)((sqrtf(8.0f * idx + 1.0f) - 1.0f) * 0.5f);
+        while ((a + 1) * (a + 2) / 2 <= idx) ++a;
+        while (a * (a + 1) / 2 > idx) --a;
+        const int bb = idx - a * (a + 1) / 2;
+        const int va = a < l ? Br[2 + a] : (a == l ? Br[0] : Br[1]);
+        const int vb = bb < l ? Br[2 + bb] : (bb == l ? Br[0] : Br[1]);
+        M[idx] = C[(size_t)va * p + vb];
+    }
+    __syncthreads();
+    T r;
+    const bool ok = wave_pcor<T>(M, l, threadIdx.x, r);
+    if (threadIdx.x == 0) {
+        double z = NAN;
+        uint8_t ind = 0;
+        if (ok) {
+            z = th.sqrt_nu * fabs(atanh((double)r));
+            ind = z <= th.q;
+        }
+        if (z_out) z_out[row] = z;
+        if (ind_out) ind_out[row] = ind;
+    }
+}
+
+// ------------------------------------------------------------------ dispatch tables
+template <typename T, bool TILE, int L = 0>
+void launch_level(int l, dim3 g, size_t shm, hipStream_t st, const LevelArgs &A)
+{
+    if constexpr (L <= kMaxTemplL) {
+        if (l == L) {
+            level_kernel<T, L, TILE><<<g, 256, shm, st>>>(A);
+            return;
+        }
+        launch_level<T, TILE, L + 1>(l, g, shm, st, A);
+    }
+}
+
+template <int L = 0>
+void launch_recheck(int l, hipStream_t st, const LevelArgs &A)
+{
+    if constexpr (L <= kMaxTemplL) {
+        if (l == L) {
+            recheck_kernel<L><<<512, 256, 0, st>>>(A);
+            return;
+        }
+        launch_recheck<L + 1>(l, st, A);
+    }
+}
+
+template <typename T, int L = 0>
+void launch_batch(int l, dim3 g, hipStream_t st, const T *C, int p, const int32_t *B, int64_t b,
+                  const Thresholds &th, double *z, uint8_t *ind, int *bad)
+{
+    if constexpr (L <= kMaxTemplL) {
+        if (l == L) {
+            batch_kernel<T, L><<<g, 256, 0, st>>>(C, p, B, b, th, z, ind, bad);
+            return;
+        }
+        launch_batch<T, L + 1>(l, g, st, C, p, B, b, th, z, ind, bad);
+    }
+}
+
+Thresholds make_thresholds(double q, int n, int l, double band_z, double c_eff)
+{
+    Thresholds th;
+    th.q = q;
+    th.sqrt_nu = std::sqrt((double)(n - l - 3));
+    const double rt = std::tanh(q / th.sqrt_nu);
+    th.r_lo = rt * (1.0 - 1e-9);
+    th.r_hi = rt * (1.0 + 1e-9);
+    if (!std::isfinite(q)) {  // q = +inf: every non-degenerate test is independent
+        th.r_lo = 2.0;
+        th.r_hi = 2.0;
+    }
+    th.band_z = band_z;
+    th.c_eff = c_eff;
+    return th;
+}
+
+size_t tile_bytes(int m, size_t elem) { return elem * ((size_t)m * (m - 1) / 2 + 2 * (size_t)m + 1) + 16; }
+
+}  // namespace
+
+int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> &ntests, float *kernel_ms)
+{
+    hipStream_t st = ctx->stream;
+    const int l = Lv.l;
+    const int64_t E = Lv.n_edges;
+    *kernel_ms = 0.f;
+    if (E == 0) return FPC_OK;
+    int64_t maxN = 0;
+    for (int64_t e = 0; e < E; ++e) maxN = std::max(maxN, ntests[e]);
+    const bool wide = l > kMaxTemplL;
+    const bool fp32 = Lv.fp32 && !wide;
+    const int rpb = wide ? kGenericRanks : kRanksPerBlock;
+    // windows of ranks: [0, rpb), then growing by 8x
+    std::vector<int64_t> wins{0};
+    for (int64_t w = rpb; wins.back() < maxN; w *= 8) wins.push_back(std::min<int64_t>(maxN, wins.back() + w));
+    const int nw = (int)wins.size() - 1;
+    std::vector<int64_t> offs((size_t)nw * (E + 1));
+    std::vector<int64_t> nblocks(nw);
+    for (int w = 0; w < nw; ++w) {
+        int64_t *o = offs.data() + (size_t)w * (E + 1);
+        o[0] = 0;
+        for (int64_t e = 0; e < E; ++e) {
+            const int64_t span = std::max<int64_t>(0, std::min(ntests[e], wins[w + 1]) - wins[w]);
+            o[e + 1] = o[e] + (span + rpb - 1) / rpb;
+        }
+        nblocks[w] = o[E];
+        if (nblocks[w] > 0x7fffffffLL) return FPC_EBUDGET;
+    }
+    FPC_HIP(hipStreamSynchronize(st));  // earlier uploads from the staging buffer have completed
+    int rc = ctx->blockoff.ensure(sizeof(int64_t) * offs.size());
+    if (rc) return rc;
+    if ((rc = ctx->h_stage.ensure(sizeof(int64_t) * offs.size()))) return rc;
+    std::memcpy(ctx->h_stage.ptr, offs.data(), sizeof(int64_t) * offs.size());
+    FPC_HIP(hipMemcpyAsync(ctx->blockoff.ptr, ctx->h_stage.ptr, sizeof(int64_t) * offs.size(),
+                           hipMemcpyHostToDevice, st));
+
+    LevelArgs A{};
+    A.edges = Lv.edges;
+    A.cand = Lv.cand;
+    A.C = wide ? (const void *)Lv.C64 : Lv.C;
+    A.C64 = Lv.C64;
+    A.binom = ctx->binom.as<int64_t>();
+    A.minhit = Lv.minhit;
+    A.counters = Lv.counters;
+    A.queue = Lv.queue;
+    A.queue_cap = Lv.queue_cap;
+    A.n_edges = E;
+    A.p = Lv.p;
+    A.ranks_per_block = rpb;
+    A.th = make_thresholds(Lv.q, Lv.n, l, Lv.band_z, Lv.c_err + 4.0 * (l + 2) * 6.0e-8);
+
+    FPC_HIP(hipEventRecord(ctx->ev0, st));
+    for (int w = 0; w < nw; ++w) {
+        if (!nblocks[w]) continue;
+        A.blockoff = ctx->blockoff.as<int64_t>() + (size_t)w * (E + 1);
+        A.win_lo = wins[w];
+        A.win_hi = wins[w + 1];
+        dim3 g((unsigned)nblocks[w]);
+        if (wide) {
+            const size_t shm = (fp32 ? 4 : 8) * ((size_t)(l + 2) * (l + 3) / 2 + 1) + sizeof(int) * (l + 1) + 16;
+            if (shm > (size_t)ctx->lds_per_block) return FPC_EBUDGET;
+            // wide levels always run in FP64
+            level_kernel_wide<double><<<g, 64, shm, st>>>(A, l);
+        } else {
+            const size_t shm = tile_bytes(Lv.max_m, fp32 ? 4 : 8);
+            const bool tile = shm <= (size_t)ctx->lds_per_block;
+            if (fp32) {
+                if (tile) launch_level<float, true>(l, g, shm, st, A);
+                else launch_level<float, false>(l, g, 0, st, A);
+            } else {
+                if (tile) launch_level<double, true>(l, g, shm, st, A);
+                else launch_level<double, false>(l, g, 0, st, A);
+            }
+            if (fp32) {
+                launch_recheck(l, st, A);
+                FPC_HIP(hipMemsetAsync(&Lv.counters[1], 0, sizeof(unsigned long long), st));
+            }
+        }
+        FPC_HIP(hipGetLastError());
+    }
+    FPC_HIP(hipEventRecord(ctx->ev1, st));
+    FPC_HIP(hipEventSynchronize(ctx->ev1));
+    FPC_HIP(hipEventElapsedTime(kernel_ms, ctx->ev0, ctx->ev1));
+    return FPC_OK;
+}
+
+int level_compact(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *out_pairs, int64_t *n_out)
+{
+    hipStream_t st = ctx->stream;
+    int rc = ctx->dellist.ensure(sizeof(int64_t) * (2 * (size_t)n_edges + 2));
+    if (rc) return rc;
+    int64_t *d = ctx->dellist.as<int64_t>();
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(d + 2 * n_edges);
+    FPC_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), st));
+    if (n_edges > 0)
+        compact_kernel<<<(unsigned)((n_edges + 255) / 256), 256, 0, st>>>(minhit, n_edges, d, cnt);
+    FPC_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    FPC_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+    FPC_HIP(hipStreamSynchronize(st));
+    if (h) FPC_HIP(hipMemcpyAsync(out_pairs, d, sizeof(int64_t) * 2 * h, hipMemcpyDeviceToHost, st));
+    FPC_HIP(hipStreamSynchronize(st));
+    *n_out = (int64_t)h;
+    return FPC_OK;
+}
+
+int ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, const int32_t *B, int64_t b, double q,
+             double *z_out, uint8_t *indep_out)
+{
+    if (!C || p < 2 || l < 0 || b < 0 || n - l - 3 <= 0 || l > p - 2) return FPC_EINVAL;
+    if (c_dtype != FPC_F64 && c_dtype != FPC_F32) return FPC_EINVAL;
+    if (b == 0) return FPC_OK;
+    if (!B) return FPC_EINVAL;
+    hipStream_t st = ctx->stream;
+    const Thresholds th = make_thresholds(q, n, l, 0.0, 0.0);
+    int rc = ctx->flag.ensure(64);
+    if (rc) return rc;
+    int *bad = ctx->flag.as<int>() + 6;
+    FPC_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+    if (l <= kMaxTemplL) {
+        if ((b + 255) / 256 > 0x7fffffffLL) return FPC_EINVAL;
+        dim3 g((unsigned)((b + 255) / 256));
+        if (c_dtype == FPC_F64) launch_batch<double>(l, g, st, (const double *)C, p, B, b, th, z_out, indep_out, bad);
+        else launch_batch<float>(l, g, st, (const float *)C, p, B, b, th, z_out, indep_out, bad);
+    } else {
+        const size_t shm = (c_dtype == FPC_F64 ? 8 : 4) * ((size_t)(l + 2) * (l + 3) / 2 + 1) + 16;
+        if (shm > (size_t)ctx->lds_per_block) return FPC_EINVAL;
+        if (b > 0x7fffffffLL) return FPC_EINVAL;
+        dim3 g((unsigned)b);
+        if (c_dtype == FPC_F64)
+            batch_kernel_wide<double><<<g, 64, shm, st>>>((const double *)C, p, B, b, l, th, z_out, indep_out, bad);
+        else
+            batch_kernel_wide<float><<<g, 64, shm, st>>>((const float *)C, p, B, b, l, th, z_out, indep_out, bad);
+    }
+    FPC_HIP(hipGetLastError());
+    int hbad = 0;
+    FPC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    FPC_HIP(hipStreamSynchronize(st));
+    return hbad ? FPC_EINVAL : FPC_OK;
+}
+
+}  // namespace fpc
+
+extern "C" int fpc_ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, const int32_t *B,
+                            int64_t b, double q, double *z_out, uint8_t *indep_out)
+{
+    if (!ctx) return FPC_EINVAL;
+    return fpc::ci_batch(ctx, C, c_dtype, p, n, l, B, b, q, z_out, indep_out);
+}

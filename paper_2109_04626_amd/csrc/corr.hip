@@ -1,0 +1,375 @@
+// Correlation matrix of the data ("corr", Sec. 5): C_ij = S_ij / sqrt(S_ii S_jj)
+// with S the cross-product matrix of the centred columns.
+//
+// Two methods:
+//   FP64     column means in FP64, centred FP64 products on the vector
+//            units (LDS-tiled, upper-triangle tiles only, split over the
+//            samples so that the launch fills the chip);
+//   BF16X3   columns standardised in FP64, each value split as
+//            z = hi + lo with hi, lo in bf16, and S ~ hi.hi + hi.lo + lo.hi
+//            on the MFMA units (v_mfma_f32_16x16x32_bf16) with FP32
+//            accumulation over chunks of 512 samples, the chunk sums folded
+//            into FP64 registers.
+// Both renormalise by the computed diagonal, so C_ii = 1 exactly.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "fpc_internal.h"
+
+namespace fpc {
+
+namespace {
+
+constexpr int kStatRows = 256;  // rows per partial in the column statistics
+
+// Partial column sums (pass 0) or centred sums of squares (pass 1).
+template <typename TX>
+__global__ __launch_bounds__(256) void colstat_partial(const TX *__restrict__ X, int n, int p,
+                                                       const double *__restrict__ mu, int pass,
+                                                       double *__restrict__ part,
+                                                       int *__restrict__ nonfinite)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= p) return;
+    const int r0 = blockIdx.y * kStatRows, r1 = min(n, r0 + kStatRows);
+    double s = 0.0;
+    bool bad = false;
+    const double m = pass ? mu[j] : 0.0;
+    for (int t = r0; t < r1; ++t) {
+        const double x = (double)X[(size_t)t * p + j];
+        bad |= !isfinite(x);
+        const double d = x - m;
+        s += pass ? d * d : x;
+    }
+    part[(size_t)blockIdx.y * p + j] = s;
+    if (bad) atomicOr(nonfinite, 1);
+}
+
+__global__ void colstat_reduce(const double *__restrict__ part, int nchunks, int n, int p,
+                               int pass, double *__restrict__ out, int *__restrict__ constant)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= p) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * p + j];
+    if (pass == 0) {
+        out[j] = s / n;  // mean
+    } else {
+        const double var = s / n;
+        out[j] = sqrt(var);  // standard deviation
+        if (!(var > 0.0)) atomicOr(constant, 1);
+    }
+}
+
+// ---------------------------------------------------------------- FP64 products
+constexpr int kT = 64;   // output tile edge
+constexpr int kK = 16;   // samples per LDS stage
+
+__device__ inline void tile_of(int t, int nbt, int &bi, int &bj)
+{
+    int b = 0;
+    while (t >= nbt - b) {
+        t -= nbt - b;
+        ++b;
+    }
+    bi = b;
+    bj = b + t;
+}
+
+// S_part[split][i][j] for the upper-triangle tiles; split = blockIdx.y covers
+// samples [split*chunk, (split+1)*chunk).
+template <typename TX>
+__global__ __launch_bounds__(256) void syrk_f64(const TX *__restrict__ X, const double *__restrict__ mu,
+                                                int n, int p, int nbt, int chunk,
+                                                double *__restrict__ Spart)
+{
+    int bi, bj;
+    tile_of(blockIdx.x, nbt, bi, bj);
+    const int t0 = blockIdx.y * chunk, t1 = min(n, t0 + chunk);
+    __shared__ double As[kK][kT + 1];
+    __shared__ double Bs[kK][kT + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int k0 = t0; k0 < t1; k0 += kK) {
+        for (int e = threadIdx.x; e < kK * kT; e += 256) {
+            const int r = e / kT, c = e % kT, row = k0 + r;
+            const int ca = bi * kT + c, cb = bj * kT + c;
+            As[r][c] = (row < t1 && ca < p) ? (double)X[(size_t)row * p + ca] - mu[ca] : 0.0;
+            Bs[r][c] = (row < t1 && cb < p) ? (double)X[(size_t)row * p + cb] - mu[cb] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int r = 0; r < kK; ++r) {
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = As[r][ty * 4 + q];
+                b[q] = Bs[r][tx * 4 + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc[q][s] = fma(a[q], b[s], acc[q][s]);
+        }
+        __syncthreads();
+    }
+    double *out = Spart + (size_t)blockIdx.y * p * p;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = bi * kT + ty * 4 + q;
+        if (i >= p) continue;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int j = bj * kT + tx * 4 + s;
+            if (j < p) out[(size_t)i * p + j] = acc[q][s];
+        }
+    }
+}
+
+// C[i][j] = S_ij / sqrt(S_ii S_jj), S summed over the splits in order and
+// read from the upper triangle; C_ii = 1.
+template <typename TC>
+__global__ __launch_bounds__(256) void normalize(const double *__restrict__ Spart, int nsplit, int p,
+                                                 TC *__restrict__ C)
+{
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)p * p) return;
+    const int i = (int)(idx / p), j = (int)(idx % p);
+    if (i == j) {
+        C[idx] = (TC)1.0;
+        return;
+    }
+    const int a = min(i, j), b = max(i, j);
+    double s = 0.0, sa = 0.0, sb = 0.0;
+    for (int k = 0; k < nsplit; ++k) {
+        const double *S = Spart + (size_t)k * p * p;
+        s += S[(size_t)a * p + b];
+        sa += S[(size_t)a * p + a];
+        sb += S[(size_t)b * p + b];
+    }
+    C[idx] = (TC)(s / sqrt(sa * sb));
+}
+
+// ---------------------------------------------------------------- bf16x3 on MFMA
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Standardise and split, writing the transposed copies Zh[j][t], Zl[j][t]
+// (t < npad, zero beyond n) through a 32x32 LDS tile.
+template <typename TX>
+__global__ __launch_bounds__(256) void split_bf16(const TX *__restrict__ X, const double *__restrict__ mu,
+                                                  const double *__restrict__ sd, int n, int p, int npad,
+                                                  __bf16 *__restrict__ Zh, __bf16 *__restrict__ Zl)
+{
+    __shared__ float tile[32][33];
+    const int t0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int lx = threadIdx.x % 32, ly = threadIdx.x / 32;  // 32 x 8
+    for (int r = ly; r < 32; r += 8) {
+        const int t = t0 + r, j = j0 + lx;
+        float z = 0.0f;
+        if (t < n && j < p) z = (float)(((double)X[(size_t)t * p + j] - mu[j]) / sd[j]);
+        tile[r][lx] = z;
+    }
+    __syncthreads();
+    for (int r = ly; r < 32; r += 8) {
+        const int j = j0 + r, t = t0 + lx;
+        if (j < p && t < npad) {
+            const float z = tile[lx][r];
+            const __bf16 hi = (__bf16)z;
+            const __bf16 lo = (__bf16)(z - (float)hi);
+            Zh[(size_t)j * npad + t] = hi;
+            Zl[(size_t)j * npad + t] = lo;
+        }
+    }
+}
+
+constexpr int kFold = 512;  // samples per FP32 accumulation chunk
+
+// One 64x64 upper-triangle tile per block (4 waves, each 32x32 = 2x2 MFMA
+// 16x16 tiles); blockIdx.y is the sample split.  Operand layout of
+// v_mfma_f32_16x16x32_bf16: lane l supplies row (l % 16) and the 8
+// consecutive k values 8*(l/16) .. 8*(l/16)+7; the result element r of
+// lane l is row 4*(l/16) + r, column l % 16.
+__global__ __launch_bounds__(256) void syrk_bf16x3(const __bf16 *__restrict__ Zh,
+                                                   const __bf16 *__restrict__ Zl, int p, int npad,
+                                                   int nbt, int chunk, double *__restrict__ Spart)
+{
+    int bi, bj;
+    tile_of(blockIdx.x, nbt, bi, bj);
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wr = wave / 2, wc = wave % 2;
+    const int k_lo = blockIdx.y * chunk, k_hi = min(npad, k_lo + chunk);
+    const int rowA[2] = {bi * kT + wr * 32 + lane % 16, bi * kT + wr * 32 + 16 + lane % 16};
+    const int rowB[2] = {bj * kT + wc * 32 + lane % 16, bj * kT + wc * 32 + 16 + lane % 16};
+    const int koff = 8 * (lane / 16);
+    double sum[2][2][4];
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            acc[g][h] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sum[g][h][r] = 0.0;
+        }
+    const bf16x8 zero = {};
+    for (int kc = k_lo; kc < k_hi; kc += kFold) {
+        const int kend = min(k_hi, kc + kFold);
+        for (int k0 = kc; k0 < kend; k0 += 32) {
+            bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const bool okA = rowA[g] < p, okB = rowB[g] < p;
+                const size_t oA = (size_t)rowA[g] * npad + k0 + koff;
+                const size_t oB = (size_t)rowB[g] * npad + k0 + koff;
+                ah[g] = okA ? *reinterpret_cast<const bf16x8 *>(Zh + oA) : zero;
+                al[g] = okA ? *reinterpret_cast<const bf16x8 *>(Zl + oA) : zero;
+                bh[g] = okB ? *reinterpret_cast<const bf16x8 *>(Zh + oB) : zero;
+                bl[g] = okB ? *reinterpret_cast<const bf16x8 *>(Zl + oB) : zero;
+            }
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bh[h], acc[g][h], 0, 0, 0);
+                    acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bl[h], acc[g][h], 0, 0, 0);
+                    acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[g], bh[h], acc[g][h], 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sum[g][h][r] += (double)acc[g][h][r];
+                acc[g][h] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+    }
+    double *out = Spart + (size_t)blockIdx.y * p * p;
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = bi * kT + wr * 32 + g * 16 + 4 * (lane / 16) + r;
+                const int j = bj * kT + wc * 32 + h * 16 + lane % 16;
+                if (i < p && j < p) out[(size_t)i * p + j] = sum[g][h][r];
+            }
+}
+
+__global__ __launch_bounds__(256) void max_abs_diff(const double *__restrict__ a, const float *__restrict__ b,
+                                                    size_t cnt, unsigned long long *__restrict__ out)
+{
+    double m = 0.0;
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < cnt; k += (size_t)gridDim.x * 256)
+        m = fmax(m, fabs(a[k] - (double)b[k]));
+    __shared__ double red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+int splits_for(int tiles, int n, int num_cus)
+{
+    int s = (2 * num_cus + tiles - 1) / tiles;
+    s = s < 1 ? 1 : (s > 32 ? 32 : s);
+    const int maxs = (n + 511) / 512;
+    return s > maxs ? (maxs < 1 ? 1 : maxs) : s;
+}
+
+}  // namespace
+
+int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out)
+{
+    if (!X || !C_out || n < 2 || p < 1) return FPC_EINVAL;
+    if (x_dtype != FPC_F64 && x_dtype != FPC_F32) return FPC_EINVAL;
+    if (method != FPC_CORR_FP64 && method != FPC_CORR_BF16X3) return FPC_EINVAL;
+    hipStream_t st = ctx->stream;
+    const int nchunks = (n + kStatRows - 1) / kStatRows;
+    const int nbt = (p + kT - 1) / kT, tiles = nbt * (nbt + 1) / 2;
+    const int npad = (n + 31) / 32 * 32;
+    const int nsplit = splits_for(tiles, method == FPC_CORR_FP64 ? n : npad, ctx->num_cus);
+    const size_t pp = (size_t)p * p;
+    // colstat layout: mu[p], sd[p], partials[nchunks*p]
+    int rc = ctx->colstat.ensure(sizeof(double) * ((size_t)2 * p + (size_t)nchunks * p));
+    if (rc) return rc;
+    if ((rc = ctx->flag.ensure(64))) return rc;
+    if ((rc = ctx->inv_work.ensure(sizeof(double) * pp * nsplit))) return rc;
+    double *mu = ctx->colstat.as<double>(), *sd = mu + p, *part = sd + p;
+    int *flags = ctx->flag.as<int>();
+    double *Spart = ctx->inv_work.as<double>();
+    FPC_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(int), st));
+    dim3 g0((p + 255) / 256, nchunks);
+    for (int pass = 0; pass < 2; ++pass) {
+        if (x_dtype == FPC_F64)
+            colstat_partial<double><<<g0, 256, 0, st>>>((const double *)X, n, p, mu, pass, part, flags);
+        else
+            colstat_partial<float><<<g0, 256, 0, st>>>((const float *)X, n, p, mu, pass, part, flags);
+        colstat_reduce<<<(p + 255) / 256, 256, 0, st>>>(part, nchunks, n, p, pass, pass ? sd : mu, flags + 1);
+    }
+    FPC_HIP(hipGetLastError());
+    if (method == FPC_CORR_FP64) {
+        const int chunk = ((n + nsplit - 1) / nsplit + kK - 1) / kK * kK;
+        dim3 g(tiles, nsplit);
+        if (x_dtype == FPC_F64)
+            syrk_f64<double><<<g, 256, 0, st>>>((const double *)X, mu, n, p, nbt, chunk, Spart);
+        else
+            syrk_f64<float><<<g, 256, 0, st>>>((const float *)X, mu, n, p, nbt, chunk, Spart);
+        normalize<double><<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(Spart, nsplit, p, (double *)C_out);
+    } else {
+        if ((rc = ctx->zsplit.ensure(sizeof(__bf16) * 2 * (size_t)p * npad))) return rc;
+        __bf16 *Zh = ctx->zsplit.as<__bf16>(), *Zl = Zh + (size_t)p * npad;
+        dim3 gs(npad / 32, (p + 31) / 32);
+        if (x_dtype == FPC_F64)
+            split_bf16<double><<<gs, 256, 0, st>>>((const double *)X, mu, sd, n, p, npad, Zh, Zl);
+        else
+            split_bf16<float><<<gs, 256, 0, st>>>((const float *)X, mu, sd, n, p, npad, Zh, Zl);
+        const int chunk = ((npad + nsplit - 1) / nsplit + 31) / 32 * 32;
+        dim3 g(tiles, nsplit);
+        syrk_bf16x3<<<g, 256, 0, st>>>(Zh, Zl, p, npad, nbt, chunk, Spart);
+        normalize<float><<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(Spart, nsplit, p, (float *)C_out);
+    }
+    FPC_HIP(hipGetLastError());
+    int hflags[2];
+    FPC_HIP(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+    FPC_HIP(hipStreamSynchronize(st));
+    if (hflags[0]) return FPC_ENONFINITE;
+    if (hflags[1]) return FPC_ESINGULAR;
+    return FPC_OK;
+}
+
+int corr_max_abs_diff(fpc_ctx *ctx, const double *c64, const float *c32, int p, double *out)
+{
+    int rc = ctx->flag.ensure(64);
+    if (rc) return rc;
+    unsigned long long *d = reinterpret_cast<unsigned long long *>(ctx->flag.as<char>() + 32);
+    FPC_HIP(hipMemsetAsync(d, 0, sizeof(*d), ctx->stream));
+    max_abs_diff<<<512, 256, 0, ctx->stream>>>(c64, c32, (size_t)p * p, d);
+    FPC_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    FPC_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    FPC_HIP(hipStreamSynchronize(ctx->stream));
+    double v;
+    memcpy(&v, &h, sizeof(v));
+    *out = v;
+    return FPC_OK;
+}
+
+}  // namespace fpc
+
+extern "C" int fpc_corr(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out)
+{
+    if (!ctx) return FPC_EINVAL;
+    return fpc::corr_compute(ctx, X, x_dtype, n, p, method, C_out);
+}

@@ -1,0 +1,143 @@
+// Internal declarations shared by the library's translation units.
+// Not part of the ABI (see include/fastpc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fastpc.h"
+
+namespace fpc {
+
+// Records the HIP error text for fpc_last_hip_error() and maps it to FPC_EDEVICE.
+int hip_fail(hipError_t e, const char *what);
+
+#define FPC_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t _e = (call);                                         \
+        if (_e != hipSuccess) return ::fpc::hip_fail(_e, #call);        \
+    } while (0)
+
+// A device buffer that grows on demand and is freed with the context.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need);  // FPC_OK / FPC_ENOMEM / FPC_EDEVICE
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Pinned host staging buffer.
+struct HostBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need);
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+constexpr int kMaxTemplL = 16;   // largest level with a register-resident test kernel
+constexpr int kBinomRows = 1024; // binomial table: C(a, b), a < kBinomRows, b <= kBinomCols-1
+constexpr int kBinomCols = 64;
+
+}  // namespace fpc
+
+struct fpc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int lds_per_block = 65536;  // max dynamic LDS bytes per workgroup
+    int num_cus = 256;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    // binomial table on the device (saturating int64), kBinomRows x kBinomCols
+    fpc::DevBuf binom;
+    std::vector<int64_t> binom_host;
+
+    // correlation / first level
+    fpc::DevBuf x_copy;           // X uploaded from host
+    fpc::DevBuf colstat;          // mu, sd (FP64) + partials
+    fpc::DevBuf c64, c32;         // correlation matrices
+    fpc::DevBuf zsplit;           // bf16 hi/lo copies of the standardized data
+    fpc::DevBuf inv_work;         // first level: matrix being inverted + panel buffers
+    fpc::DevBuf flag;             // small device scalars (error flags, counters)
+
+    // level workspace
+    fpc::DevBuf cand;             // int32 candidate lists of eligible edges
+    fpc::DevBuf edges;            // EdgeRec per eligible edge
+    fpc::DevBuf blockoff;         // per-window block prefix sums
+    fpc::DevBuf minhit;           // uint64 per edge: lowest independent rank
+    fpc::DevBuf counters;         // uint64 counters (tests executed, queue length, ...)
+    fpc::DevBuf queue;            // recheck queue (edge, rank)
+    fpc::DevBuf dellist;          // compacted deletions
+    fpc::DevBuf batch_tmp;        // fpc_ci_batch scratch
+
+    fpc::HostBuf h_stage;         // pinned staging for uploads
+    fpc::HostBuf h_back;          // pinned staging for downloads
+};
+
+namespace fpc {
+
+// One eligible edge of a level, as the test kernels see it.
+struct EdgeRec {
+    int32_t i, j;      // variables, i < j
+    int32_t m;         // |cand|
+    int32_t cand_off;  // offset of its candidate list in the level's cand array
+    int64_t ntests;    // C(m, l)
+};
+
+// ---- correlation (corr.hip)
+int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out);
+int corr_max_abs_diff(fpc_ctx *ctx, const double *c64, const float *c32, int p, double *out);
+
+// ---- first level (first_level.hip)
+int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
+                uint8_t *indep_out, int *n_singular);
+
+// ---- level tests (citest.hip)
+struct LevelLaunch {
+    int l;
+    int max_m;                     // largest |cand| among the eligible edges
+    int64_t n_edges;               // eligible edges
+    const EdgeRec *edges;          // device
+    const int32_t *cand;           // device
+    const void *C;                 // device matrix of the test precision
+    const double *C64;             // device FP64 matrix (recheck)
+    int p, n;
+    bool fp32;                     // tests in FP32 with FP64 recheck
+    double q;                      // threshold
+    double r_thr;                  // tanh(q / sqrt(n - l - 3))
+    double band_z;                 // recheck margin in z units
+    double c_err;                  // bound on the entry error of the FP32 matrix
+    uint64_t *minhit;              // device, per edge
+    unsigned long long *counters;  // device: [0] executed, [1] queue length, [2] rechecked
+    int64_t *queue;                // device, 2 * queue_cap entries (edge, rank)
+    int64_t queue_cap;
+};
+int level_tests(fpc_ctx *ctx, const LevelLaunch &L, const std::vector<int64_t> &host_ntests,
+                float *kernel_ms);
+int level_compact(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *out_pairs,
+                  int64_t *n_out);
+int ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, const int32_t *B,
+             int64_t b, double q, double *z_out, uint8_t *indep_out);
+
+// ---- host graph logic (graph.cpp)
+// Candidate sets of every edge of the graph (row-major i<j order).
+struct CandSets {
+    std::vector<int32_t> ei, ej;
+    std::vector<int64_t> off;   // E+1
+    std::vector<int32_t> nodes;
+};
+void candidate_sets(const uint8_t *adj, int p, CandSets &out);
+
+// ---- quantile (quantile.cpp)
+double normal_quantile_upper(double alpha);  // Phi^{-1}(1 - alpha/2)
+
+// ---- binomials (skeleton.cpp)
+int64_t binom_sat(int a, int b);  // C(a,b), saturating at INT64_MAX
+
+}  // namespace fpc

@@ -190,3 +190,26 @@ def true_skeleton(sem: SEM) -> np.ndarray:
     """Undirected 0/1 adjacency of the DAG."""
     a = sem.W != 0
     return (a | a.T).astype(np.uint8)
+
+
+# ---------------------------------------------------------------- workloads
+# Named synthetic workloads (shapes of the benchmark configurations).
+WORKLOADS = {
+    # plain method, FP64, all levels
+    "er_p20_n1000_d3": dict(p=20, n=1000, graph="er", degree=3.0, x_dtype="f64", alpha=0.01, max_level=-1),
+    # dense small graph, FP32 tests with FP64 recheck
+    "er_p95_n5000_d12": dict(p=95, n=5000, graph="er", degree=12.0, x_dtype="f64", alpha=0.01, max_level=6),
+    # sparse large graph, X in FP32
+    "er_p1000_n10000_d4": dict(p=1000, n=10000, graph="er", degree=4.0, x_dtype="f32", alpha=0.01, max_level=5),
+    # scale-free graph
+    "ba_p1000_n10000_m2": dict(p=1000, n=10000, graph="ba", degree=0.0, x_dtype="f32", alpha=0.01, max_level=3),
+}
+
+
+def workload(name: str, seed: int, **over):
+    """(X, sem, cfg) for a named workload; ``over`` overrides cfg keys."""
+    cfg = dict(WORKLOADS[name])
+    cfg.update(over)
+    sem = make_sem(cfg["p"], seed, graph=cfg["graph"], degree=cfg["degree"])
+    X = sample(sem, cfg["n"], seed, dtype=np.float32 if cfg["x_dtype"] == "f32" else np.float64)
+    return X, sem, cfg

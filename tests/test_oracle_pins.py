@@ -445,3 +445,11 @@ def test_invalid_inputs():
     with pytest.raises(oracle.OracleError) as e:
         oracle.skeleton(S, 100, alpha=0.01)  # singular
     assert e.value.code == oracle.ORC_ESINGULAR
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((40, 6))
+    X[:, 4] = X[:, 1]  # duplicate column: 1 - R^2 of column 4 is 0
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.skeleton(oracle.corr(X), 40, alpha=0.01)
+    assert e.value.code == oracle.ORC_ESINGULAR
+    X[:, 4] = X[:, 1] + 1e-3 * rng.standard_normal(40)  # nearly, not numerically, determined
+    oracle.skeleton(oracle.corr(X), 40, alpha=0.01)

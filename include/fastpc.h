@@ -160,7 +160,12 @@ typedef struct fpc_level_stats {
     int64_t tests_executed;   /* tests the GPU ran (early exit per edge and tile)       */
     int64_t tests_rechecked;  /* mixed: FP32 tests re-run in FP64                       */
     int64_t deleted;          /* edges removed at the end of the level                  */
-    double kernel_ms;         /* CI-test kernels, HIP events on the context stream      */
+    double kernel_ms;         /* device time of the level: test kernels, rechecks and
+                                 gaps between them (HIP events on the context stream)   */
+    double test_kernel_ms;    /* sum of the test-kernel launches alone (an event pair
+                                 around each of the first 64 launches)                  */
+    int32_t test_launches;    /* launches timed in test_kernel_ms                       */
+    int32_t reserved;
     double level_ms;          /* whole level, host clock                                */
 } fpc_level_stats;
 

@@ -53,7 +53,8 @@ class fpc_level_stats(ctypes.Structure):
                 ("edges_eligible", ctypes.c_int64), ("tests_possible", ctypes.c_int64),
                 ("tests_executed", ctypes.c_int64), ("tests_rechecked", ctypes.c_int64),
                 ("deleted", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
-                ("level_ms", ctypes.c_double)]
+                ("test_kernel_ms", ctypes.c_double), ("test_launches", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("level_ms", ctypes.c_double)]
 
 
 class fpc_result(ctypes.Structure):

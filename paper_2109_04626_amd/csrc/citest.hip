@@ -688,12 +688,12 @@ size_t tile_bytes(int m, size_t elem) { return elem * ((size_t)m * (m - 1) / 2 +
 
 }  // namespace
 
-int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> &ntests, float *kernel_ms)
+int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> &ntests, LevelTiming *timing)
 {
     hipStream_t st = ctx->stream;
     const int l = Lv.l;
     const int64_t E = Lv.n_edges;
-    *kernel_ms = 0.f;
+    *timing = LevelTiming{};
     if (E == 0) return FPC_OK;
     int64_t maxN = 0;
     for (int64_t e = 0; e < E; ++e) maxN = std::max(maxN, ntests[e]);
@@ -740,8 +740,11 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     A.th = make_thresholds(Lv.q, Lv.n, l, Lv.band_z, Lv.c_err + 4.0 * (l + 2) * 6.0e-8);
 
     FPC_HIP(hipEventRecord(ctx->ev0, st));
+    int nev = 0;
     for (int w = 0; w < nw; ++w) {
         if (!nblocks[w]) continue;
+        const bool timed = nev < fpc_ctx::kLaunchEvents;
+        if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev], st));
         A.blockoff = ctx->blockoff.as<int64_t>() + (size_t)w * (E + 1);
         A.win_lo = wins[w];
         A.win_hi = wins[w + 1];
@@ -751,6 +754,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             if (shm > (size_t)ctx->lds_per_block) return FPC_EBUDGET;
             // wide levels always run in FP64
             level_kernel_wide<double><<<g, 64, shm, st>>>(A, l);
+            if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev + 1], st));
         } else {
             const size_t shm = tile_bytes(Lv.max_m, fp32 ? 4 : 8);
             const bool tile = shm <= (size_t)ctx->lds_per_block;
@@ -761,16 +765,24 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                 if (tile) launch_level<double, true>(l, g, shm, st, A);
                 else launch_level<double, false>(l, g, 0, st, A);
             }
+            if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev + 1], st));
             if (fp32) {
                 launch_recheck(l, st, A);
                 FPC_HIP(hipMemsetAsync(&Lv.counters[1], 0, sizeof(unsigned long long), st));
             }
         }
         FPC_HIP(hipGetLastError());
+        if (timed) ++nev;
     }
     FPC_HIP(hipEventRecord(ctx->ev1, st));
     FPC_HIP(hipEventSynchronize(ctx->ev1));
-    FPC_HIP(hipEventElapsedTime(kernel_ms, ctx->ev0, ctx->ev1));
+    FPC_HIP(hipEventElapsedTime(&timing->all_ms, ctx->ev0, ctx->ev1));
+    for (int k = 0; k < nev; ++k) {
+        float ms = 0.f;
+        FPC_HIP(hipEventElapsedTime(&ms, ctx->lev[2 * k], ctx->lev[2 * k + 1]));
+        timing->test_ms += ms;
+    }
+    timing->test_launches = nev;
     return FPC_OK;
 }
 

@@ -53,6 +53,8 @@ struct fpc_ctx {
     int lds_per_block = 65536;  // max dynamic LDS bytes per workgroup
     int num_cus = 256;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    static constexpr int kLaunchEvents = 64;
+    hipEvent_t lev[2 * kLaunchEvents] = {};  // per-launch timing of the test kernels
 
     // binomial table on the device (saturating int64), kBinomRows x kBinomCols
     fpc::DevBuf binom;
@@ -118,8 +120,13 @@ struct LevelLaunch {
     int64_t *queue;                // device, 2 * queue_cap entries (edge, rank)
     int64_t queue_cap;
 };
+struct LevelTiming {
+    float all_ms = 0.f;       // first test launch to last recheck, one event pair
+    float test_ms = 0.f;      // sum of the test-kernel launches alone
+    int test_launches = 0;
+};
 int level_tests(fpc_ctx *ctx, const LevelLaunch &L, const std::vector<int64_t> &host_ntests,
-                float *kernel_ms);
+                LevelTiming *timing);
 int level_compact(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *out_pairs,
                   int64_t *n_out);
 int ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, const int32_t *B,

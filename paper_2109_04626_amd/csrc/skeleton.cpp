@@ -107,14 +107,20 @@ inline int64_t pair_index(int i, int j, int p)
     return (int64_t)i * p - (int64_t)i * (i + 1) / 2 + (j - i - 1);
 }
 
-// Lexicographic unranking of rank R among the l-subsets of m positions.
-void unrank_host(int64_t R, int m, int l, std::vector<int> &out)
+// Lexicographic unranking of rank R among the l-subsets of m positions
+// (tab: kBinomRows x kBinomCols saturating table; C(a,b) = C(a,a-b)).
+void unrank_host(int64_t R, int m, int l, const std::vector<int64_t> &tab, std::vector<int> &out)
 {
     out.resize(l);
     int x = 0;
+    auto C = [&](int a, int b) -> int64_t {
+        if (b < 0 || b > a) return 0;
+        const int bb = std::min(b, a - b);
+        return bb < kBinomCols ? tab[(size_t)a * kBinomCols + bb] : binom_sat(a, b);
+    };
     for (int t = 0; t < l; ++t) {
         for (;;) {
-            const int64_t cnt = binom_sat(m - 1 - x, l - 1 - t);
+            const int64_t cnt = C(m - 1 - x, l - 1 - t);
             if (R < cnt) break;
             R -= cnt;
             ++x;
@@ -182,6 +188,12 @@ extern "C" int fpc_create(fpc_ctx **out, int hip_device, void *hip_stream)
         fpc_destroy(c);
         return hip_fail(e, "hipEventCreate");
     }
+    for (hipEvent_t &ev : c->lev) {
+        if ((e = hipEventCreate(&ev)) != hipSuccess) {
+            fpc_destroy(c);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
     c->binom_host.resize((size_t)kBinomRows * kBinomCols);
     for (int a = 0; a < kBinomRows; ++a)
         for (int b = 0; b < kBinomCols; ++b) c->binom_host[(size_t)a * kBinomCols + b] = binom_sat(a, b);
@@ -211,6 +223,8 @@ extern "C" int fpc_destroy(fpc_ctx *c)
     for (DevBuf *b : bufs) b->release();
     c->h_stage.release();
     c->h_back.release();
+    for (hipEvent_t ev : c->lev)
+        if (ev) (void)hipEventDestroy(ev);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -333,9 +347,11 @@ retry:
     Lv.counters = ctx->counters.as<unsigned long long>();
     Lv.queue = fp32 ? ctx->queue.as<int64_t>() : nullptr;
     Lv.queue_cap = fp32 ? kQueueCap : 0;
-    float kms = 0.f;
-    if ((rc = level_tests(ctx, Lv, ntests, &kms))) return rc;
-    st.kernel_ms = kms;
+    LevelTiming tm;
+    if ((rc = level_tests(ctx, Lv, ntests, &tm))) return rc;
+    st.kernel_ms = tm.all_ms;
+    st.test_kernel_ms = tm.test_ms;
+    st.test_launches = tm.test_launches;
 
     std::vector<int64_t> pairs(2 * E);
     int64_t ndel = 0;
@@ -358,7 +374,7 @@ retry:
     std::vector<int> pos;
     for (const auto &d : dl) {
         const EdgeRec &er = recs[d.first];
-        unrank_host(d.second, er.m, l, pos);
+        unrank_host(d.second, er.m, l, ctx->binom_host, pos);
         SepRec &sr = R.sep[pair_index(er.i, er.j, R.p)];
         sr.level = l;
         sr.kind = FPC_SEP_LIST;

@@ -58,6 +58,10 @@ extern "C" {
 #define FPC_ORDER_LEX 0    /* lexicographic over the sorted candidate list                   */
 #define FPC_ORDER_SCORED 1 /* lexicographic over candidates sorted by a per-pair score       */
 
+/* fpc_params.flags bits. */
+#define FPC_FLAG_PER_TEST_KERNEL 1u /* run levels l >= 2 with the per-test Cholesky kernel instead of
+                                       the shared-prefix (Schur pair) kernel; same results            */
+
 /* Kinds of recorded separating sets (fpc_result.sep_kind). */
 #define FPC_SEP_NONE 0    /* edge kept                                                  */
 #define FPC_SEP_LIST 1    /* K listed in sep_nodes                                      */
@@ -149,7 +153,7 @@ typedef struct fpc_params {
                              candidate k for edges at i (larger = earlier); NULL otherwise  */
     int64_t max_tests;    /* 0 = unlimited, else FPC_EBUDGET past this many tests            */
     double q_override;    /* NaN: q = Phi^{-1}(1 - alpha/2); else this threshold            */
-    uint32_t flags;       /* reserved, 0                                                     */
+    uint32_t flags;       /* FPC_FLAG_* bits, 0 for the defaults                             */
 } fpc_params;
 
 typedef struct fpc_level_stats {

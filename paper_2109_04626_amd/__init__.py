@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import math
 import os
+from collections.abc import Mapping
 
 import numpy as np
 
@@ -23,6 +24,7 @@ FPC_PREC_FP64, FPC_PREC_MIXED = 0, 1
 FPC_REVERSE, FPC_FORWARD = 0, 1
 FPC_ORDER_LEX, FPC_ORDER_SCORED = 0, 1
 FPC_SEP_NONE, FPC_SEP_LIST, FPC_SEP_ALL_BUT = 0, 1, 2
+FPC_FLAG_PER_TEST_KERNEL = 1
 
 EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "fpc_quantile",
             "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton",
@@ -251,7 +253,7 @@ def fpc_ci_batch(ctx: Context, C, n: int, B, q: float):
 
 def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, precision: int = FPC_PREC_FP64,
                  recheck_margin: float = 1e-3, schedule: int = FPC_REVERSE, max_tests: int = 0,
-                 q_override: float = float("nan")) -> dict:
+                 q_override: float = float("nan"), flags: int = 0) -> dict:
     """Skeleton and separating sets of the data X (torch tensor on the
     device, or a host numpy array), n x p row-major."""
     prm = fpc_params()
@@ -280,13 +282,45 @@ def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, prec
     prm.score = None
     prm.max_tests = int(max_tests)
     prm.q_override = float(q_override)
-    prm.flags = 0
+    prm.flags = int(flags)
     res = ctypes.POINTER(fpc_result)()
     _check(_lib.fpc_skeleton(ctx.handle, ctypes.byref(prm), ctypes.byref(res)), "fpc_skeleton")
     try:
         return _unpack(res.contents)
     finally:
         _lib.fpc_result_free(res)
+
+
+class SepSets(Mapping):
+    """Read-only {(i, j): sorted separating set} over the LIST-kind pairs,
+    backed by the result's CSR arrays (built lazily)."""
+
+    def __init__(self, p, kind, off, nodes):
+        self._p, self._off, self._nodes = p, off, nodes
+        self._idx = np.nonzero(kind == FPC_SEP_LIST)[0]
+        self._map = None
+
+    def _pairs(self):
+        if self._map is None:
+            p = self._p
+            k = self._idx
+            # inverse of k = i*p - i*(i+1)/2 + (j - i - 1)
+            i = np.floor(((2 * p - 1) - np.sqrt((2 * p - 1) ** 2 - 8.0 * k)) / 2).astype(np.int64)
+            i -= (i * p - i * (i + 1) // 2 > k)
+            i += ((i + 1) * p - (i + 1) * (i + 2) // 2 <= k)
+            j = k - (i * p - i * (i + 1) // 2) + i + 1
+            self._map = {(int(a), int(b)): int(kk) for a, b, kk in zip(i, j, k)}
+        return self._map
+
+    def __getitem__(self, key):
+        k = self._pairs()[key]
+        return self._nodes[self._off[k]:self._off[k + 1]].tolist()
+
+    def __iter__(self):
+        return iter(self._pairs())
+
+    def __len__(self):
+        return len(self._idx)
 
 
 def _unpack(r: fpc_result) -> dict:
@@ -298,10 +332,7 @@ def _unpack(r: fpc_result) -> dict:
     off = np.ctypeslib.as_array(r.sep_off, shape=(P + 1,)).copy()
     tot = int(off[-1])
     nodes = np.ctypeslib.as_array(r.sep_nodes, shape=(max(tot, 1),))[:tot].copy()
-    sepsets = {}
-    iu, ju = np.triu_indices(p, 1)
-    for k in np.nonzero(kind == FPC_SEP_LIST)[0]:
-        sepsets[(int(iu[k]), int(ju[k]))] = [int(v) for v in nodes[off[k]:off[k + 1]]]
+    sepsets = SepSets(p, kind, off, nodes)
     levels = []
     for k in range(r.n_levels):
         s = r.levels[k]

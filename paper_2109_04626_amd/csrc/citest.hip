@@ -157,6 +157,8 @@ struct Thresholds {
     double sqrt_nu; // sqrt(n - l - 3)
     double band_z;  // mixed: stated margin (z units)
     double c_eff;   // mixed: entry error bound of the FP32 matrix + FP32 rounding
+    double rb_lo;   // mixed: tanh((q - band_z) / sqrt_nu)
+    double rb_hi;   // mixed: tanh((q + band_z) / sqrt_nu)
 };
 
 // FP64 decision identical in form to the reference rule z <= q.
@@ -277,6 +279,7 @@ struct LevelArgs {
     int64_t win_lo, win_hi;
     int p;
     int ranks_per_block;
+    int max_m;  // largest candidate set of the level
     Thresholds th;
 };
 
@@ -408,6 +411,316 @@ __global__ __launch_bounds__(256) void recheck_kernel(LevelArgs A)
         if (decide64(r, ok, A.th)) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
     }
     if (done) atomicAdd(&A.counters[2], done);
+}
+
+
+// ------------------------------------------------------------------ pair kernel (l >= 2)
+// Tests of one edge in lexicographic order are grouped by their first
+// l-2 elements Q; the last two (a < b) range over the positions after
+// max(Q).  With L_Q the Cholesky factor of C_QQ and, for every later
+// position x, w_x = L_Q^{-1} C_Qx, the Schur complement of C_QQ is
+//     S_xy = C_xy - w_x.w_y,   S_xi = C_xi - w_x.u_Q,   S_xj = C_xj - w_x.v_Q
+// (u_Q = L_Q^{-1} C_Qi, v_Q = L_Q^{-1} C_Qj), and the test of K = Q + {a,b}
+// eliminates a and b from it:
+//     l1 = S_ab / sqrt(S_aa),  d2 = S_bb - l1^2,
+//     ua = S_ai / sqrt(S_aa),  ub = (S_bi - l1 ua) / sqrt(d2)  (same for j)
+//     h11 = H11_Q - ua^2 - ub^2, h22 = H22_Q - va^2 - vb^2, h12 = H12_Q - ua va - ub vb
+// -- the same factorisation of [K, i, j] as a per-test Cholesky, with the
+// Q part shared.  A wave walks kPairRanksPerWave consecutive ranks; per Q
+// it builds a table of the per-position quantities in its LDS slice (one
+// lane per position) and then runs 64 pairs per step, decoding the pair
+// index in the triangle of the positions after max(Q).
+constexpr int kPairRanksPerWave = 2048;
+constexpr int kPairRanksPerBlock = kWaves * kPairRanksPerWave;
+
+template <typename T, int QL>
+struct PairLayout {
+    static constexpr int V = 16 / (int)sizeof(T);           // elements per 16-byte load
+    static constexpr int nA = QL + 5;                        // w[QL], 1/sqrt(S_xx), S_xi/sqrt(S_xx), S_xj/sqrt(S_xx),
+                                                             // S_xx, row offset of x in the packed tile
+    static constexpr int nB = QL + 3;                        // w[QL], S_xx, S_xi, S_xj
+    static constexpr int SA = (nA + V - 1) / V * V;
+    static constexpr int SB = (nB + V - 1) / V * V;
+    static constexpr int S = SA + SB;                        // elements per position
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Reciprocal square root: the hardware approximation in FP32 (about 1 ulp;
+// a denormal or zero argument gives +inf, which the positivity checks of
+// the test then reject), the accurate library routine in FP64.
+__device__ __forceinline__ float rsqv(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqv(double x) { return rsqrt(x); }
+
+__device__ __forceinline__ void put_int(float &d, int v) { d = __int_as_float(v); }
+__device__ __forceinline__ void put_int(double &d, int v) { d = (double)v; }
+__device__ __forceinline__ int get_int(float d) { return __float_as_int(d); }
+__device__ __forceinline__ int get_int(double d) { return (int)d; }
+
+// Decision of one FP32 pair test in r space (band and error bound).
+__device__ __forceinline__ int decide32r(float r, float dmin, bool ok, float rlo, float rhi, float errk)
+{
+    if (!ok) return DEC_RECHECK;
+    const float a = fabsf(r);
+    const float err = errk * __builtin_amdgcn_rcpf(dmin);
+    if (a < rlo - err) return DEC_INDEP;
+    if (a > rhi + err) return DEC_DEP;
+    return DEC_RECHECK;
+}
+
+template <typename T, int QL>
+__global__ __launch_bounds__(256) void pair_kernel(LevelArgs A)
+{
+    using Lay = PairLayout<T, QL>;
+    constexpr int L = QL + 2;
+    constexpr int QLL = QL > 0 ? QL : 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t blk = blockIdx.x;
+    const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
+    const EdgeRec E = A.edges[e];
+    const int m = E.m;
+    const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * kPairRanksPerBlock;
+    const int64_t r1 = min(r0 + (int64_t)kPairRanksPerBlock, min(A.win_hi, E.ntests));
+    if (r0 >= r1) return;  // uniform
+    __shared__ int skip;
+    if (threadIdx.x == 0) skip = load_minhit(&A.minhit[e]) < (uint64_t)r0;
+    __syncthreads();
+    if (skip) return;  // uniform
+    const T *C = static_cast<const T *>(A.C);
+    const int32_t *cand = A.cand + E.cand_off;
+    T *tri = reinterpret_cast<T *>(smem);
+    const int ntri = m * (m - 1) / 2;
+    T *ci = tri + ntri, *cj = ci + m;
+    stage_tile<T>(C, A.p, cand, m, E.i, E.j, tri, ci, cj);
+    const T cij = C[(size_t)E.i * A.p + E.j];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    // per-wave table slice, 16-byte aligned after the tile
+    const size_t tile_elems = ((size_t)ntri + 2 * (size_t)m + Lay::V - 1) / Lay::V * Lay::V;
+    T *tab = tri + tile_elems + (size_t)wave * A.max_m * Lay::S;
+    __syncthreads();
+
+    const int64_t wlo = r0 + (int64_t)wave * kPairRanksPerWave;
+    const int64_t whi = min(wlo + (int64_t)kPairRanksPerWave, r1);
+    if (wlo >= whi) return;  // no later block-wide barrier
+    const auto row = [&](int a) { return a * (2 * m - a - 3) / 2 - 1; };
+
+    // first test of the range: K = Q + {a, b}
+    int c[L];
+    unrank<L>(wlo, m, A.binom, c);
+    int Q[QLL];
+#pragma unroll
+    for (int t = 0; t < QL; ++t) Q[t] = c[t];
+    int sQ = QL > 0 ? Q[QL - 1] + 1 : 0;  // first position after Q
+    int n = m - sQ;
+    int tau;
+    {
+        const int a0 = c[L - 2] - sQ, b0 = c[L - 1] - sQ;
+        tau = a0 * (2 * n - a0 - 1) / 2 + (b0 - a0 - 1);
+    }
+    int64_t rank = wlo;
+    int64_t remaining = whi - wlo;
+    uint64_t executed = 0;
+    const float errk = (float)(kErrSafety * A.th.c_eff * (L + 2));
+    const float rlo32 = (float)A.th.rb_lo, rhi32 = (float)A.th.rb_hi;
+    while (remaining > 0) {
+        const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
+        if (mh < (unsigned long long)rank) break;
+        // ---- Q state: L_Q, u_Q, v_Q, H_Q (identical in every lane)
+        T LQ[QL > 0 ? QL * (QL + 1) / 2 : 1], invQ[QLL], uQ[QLL], vQ[QLL];
+        int rwQ[QLL];
+        T H11 = T(1), H22 = T(1), H12 = cij, dminQ = T(1);
+        bool okQ = true;
+#pragma unroll
+        for (int t = 0; t < QL; ++t) rwQ[t] = row(Q[t]);
+#pragma unroll
+        for (int t = 0; t < QL; ++t) {
+            T *Lt = LQ + t * (t + 1) / 2;
+#pragma unroll
+            for (int s2 = 0; s2 < t; ++s2) {
+                T a = tri[rwQ[s2] + Q[t]];
+                const T *Ls = LQ + s2 * (s2 + 1) / 2;
+#pragma unroll
+                for (int q = 0; q < s2; ++q) a -= Lt[q] * Ls[q];
+                Lt[s2] = a * invQ[s2];
+            }
+            T d = T(1);
+#pragma unroll
+            for (int q = 0; q < t; ++q) d -= Lt[q] * Lt[q];
+            okQ = okQ && d > T(0);
+            dminQ = d < dminQ ? d : dminQ;
+            invQ[t] = rsqv(d);
+            T ai = ci[Q[t]], aj = cj[Q[t]];
+#pragma unroll
+            for (int q = 0; q < t; ++q) {
+                ai -= Lt[q] * uQ[q];
+                aj -= Lt[q] * vQ[q];
+            }
+            uQ[t] = ai * invQ[t];
+            vQ[t] = aj * invQ[t];
+            H11 -= uQ[t] * uQ[t];
+            H22 -= vQ[t] * vQ[t];
+            H12 -= uQ[t] * vQ[t];
+        }
+        // ---- per-position table for x in [sQ, m)
+        wave_sync();  // previous Q's table fully read
+        for (int xp = lane; xp < n; xp += 64) {
+            const int x = sQ + xp;
+            T w[QLL];
+#pragma unroll
+            for (int t = 0; t < QL; ++t) {
+                T a = tri[rwQ[t] + x];
+#pragma unroll
+                for (int q = 0; q < t; ++q) a -= LQ[t * (t + 1) / 2 + q] * w[q];
+                w[t] = a * invQ[t];
+            }
+            T sxx = T(1), sxi = ci[x], sxj = cj[x];
+#pragma unroll
+            for (int t = 0; t < QL; ++t) {
+                sxx -= w[t] * w[t];
+                sxi -= w[t] * uQ[t];
+                sxj -= w[t] * vQ[t];
+            }
+            const T i1 = sxx > T(0) ? rsqv(sxx) : T(0);
+            T *ea = tab + (size_t)xp * Lay::S, *eb = ea + Lay::SA;
+#pragma unroll
+            for (int t = 0; t < QL; ++t) {
+                ea[t] = w[t];
+                eb[t] = w[t];
+            }
+            ea[QL] = i1;
+            ea[QL + 1] = sxi * i1;
+            ea[QL + 2] = sxj * i1;
+            ea[QL + 3] = sxx;
+            put_int(ea[QL + 4], row(x));
+            eb[QL] = sxx;
+            eb[QL + 1] = sxi;
+            eb[QL + 2] = sxj;
+        }
+        wave_sync();
+        // ---- pairs tau .. tau + cnt - 1 of this Q
+        const int P = n * (n - 1) / 2;
+        const int cnt = (int)min((int64_t)(P - tau), remaining);
+        bool hit_found = false;
+        for (int it = 0; it < cnt; it += 64) {
+            const bool valid = it + lane < cnt;
+            // pair index t -> (a', b') in the triangle over n positions,
+            // from the reversed index u = P-1-t: u = rr(rr+1)/2 + (n-1-b')
+            const unsigned t = (unsigned)(tau + min(it + lane, cnt - 1));
+            const unsigned u = (unsigned)P - 1u - t;
+            unsigned rr = (unsigned)((__builtin_amdgcn_sqrtf(8.0f * (float)u + 1.0f) - 1.0f) * 0.5f);
+            rr += ((rr + 1u) * (rr + 2u) >> 1) <= u ? 1u : 0u;
+            rr -= ((rr * (rr + 1u)) >> 1) > u ? 1u : 0u;
+            const int ap = n - 2 - (int)rr, bp = n - 1 - (int)(u - ((rr * (rr + 1u)) >> 1));
+            const T *ea = tab + (size_t)ap * Lay::S;
+            const T *eb = tab + (size_t)bp * Lay::S + Lay::SA;
+            T sab = tri[get_int(ea[QL + 4]) + sQ + bp];
+#pragma unroll
+            for (int q = 0; q < QL; ++q) sab -= ea[q] * eb[q];
+            const T i1 = ea[QL], ua = ea[QL + 1], va = ea[QL + 2], d1 = ea[QL + 3];
+            const T sbb = eb[QL], sbi = eb[QL + 1], sbj = eb[QL + 2];
+            const T l1 = sab * i1;
+            const T d2 = sbb - l1 * l1;
+            const T i2 = rsqv(d2);
+            const T ub = (sbi - l1 * ua) * i2, vb = (sbj - l1 * va) * i2;
+            const T h11 = H11 - ua * ua - ub * ub;
+            const T h22 = H22 - va * va - vb * vb;
+            const T h12 = H12 - ua * va - ub * vb;
+            bool ok = okQ && d1 > T(0) && d2 > T(0) && h11 > T(0) && h22 > T(0);
+            const T r = h12 * rsqv(h11 * h22);
+            ok = ok && fabs(r) < T(1);
+            int dec;
+            if constexpr (sizeof(T) == 8) {
+                dec = decide64((double)r, ok, A.th) ? DEC_INDEP : DEC_DEP;
+            } else {
+                const float dmin = fminf(fminf((float)dminQ, fminf((float)d1, (float)d2)),
+                                         fminf((float)h11, (float)h22));
+                dec = decide32r((float)r, dmin, ok, rlo32, rhi32, errk);
+            }
+            executed += (uint64_t)min(64, cnt - it);
+            if constexpr (sizeof(T) == 4) {
+                const bool rq = valid && dec == DEC_RECHECK;
+                const unsigned long long qb = __ballot(rq);
+                if (qb) {
+                    unsigned long long slot = 0;
+                    if (lane == 0) slot = atomicAdd(&A.counters[1], (unsigned long long)__popcll(qb));
+                    slot = __shfl(slot, 0);
+                    if (rq) {
+                        const unsigned long long idx = slot + __popcll(qb & ((1ull << lane) - 1ull));
+                        if ((int64_t)idx < A.queue_cap) {
+                            A.queue[2 * idx] = e;
+                            A.queue[2 * idx + 1] = rank + it + lane;
+                        }
+                    }
+                }
+            }
+            const unsigned long long hb = __ballot(valid && dec == DEC_INDEP);
+            if (hb) {
+                if (lane == 0)
+                    atomicMin((unsigned long long *)&A.minhit[e],
+                              (unsigned long long)(rank + it + __ffsll((long long)hb) - 1));
+                hit_found = true;
+                break;
+            }
+        }
+        if (hit_found) break;
+        rank += cnt;
+        remaining -= cnt;
+        if (remaining <= 0) break;
+        // ---- next Q: next (L-2)-combination of positions [0, m-2)
+        if constexpr (QL == 0) {
+            break;
+        } else {
+            int a = -1;
+#pragma unroll
+            for (int t = 0; t < QL; ++t)
+                if (Q[t] != (m - 2) - QL + t) a = t;
+            if (a < 0) break;
+#pragma unroll
+            for (int t = 0; t < QL; ++t) {
+                if (t == a) Q[t] += 1;
+                else if (t > a) Q[t] = Q[t - 1] + 1;
+            }
+            sQ = Q[QL - 1] + 1;
+            n = m - sQ;
+            tau = 0;
+        }
+    }
+    if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
+}
+
+template <typename T, int QL = 0>
+hipError_t launch_pair(int l, dim3 g, size_t shm, hipStream_t st, const LevelArgs &A)
+{
+    if constexpr (QL + 2 <= kMaxTemplL) {
+        if (l == QL + 2) {
+            if (shm > 65536) {
+                // dynamic LDS beyond 64 KiB is opted into per kernel
+                const hipError_t e = hipFuncSetAttribute((const void *)pair_kernel<T, QL>,
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+                if (e != hipSuccess) return e;
+            }
+            pair_kernel<T, QL><<<g, 256, shm, st>>>(A);
+            return hipGetLastError();
+        }
+        return launch_pair<T, QL + 1>(l, g, shm, st, A);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+size_t pair_lds_bytes(int l, int m)
+{
+    // tile (rounded to 16 bytes) + 4 wave tables of m positions
+    const int QL = l - 2;
+    const int V = 16 / (int)sizeof(T);
+    const int SA = (QL + 5 + V - 1) / V * V, SB = (QL + 3 + V - 1) / V * V;
+    const size_t tile = ((size_t)m * (m - 1) / 2 + 2 * (size_t)m + V - 1) / V * V;
+    return sizeof(T) * (tile + (size_t)kWaves * m * (SA + SB));
 }
 
 // ------------------------------------------------------------------ wide levels
@@ -681,6 +994,12 @@ Thresholds make_thresholds(double q, int n, int l, double band_z, double c_eff)
     }
     th.band_z = band_z;
     th.c_eff = c_eff;
+    th.rb_lo = std::tanh(std::max(0.0, q - band_z) / th.sqrt_nu);
+    th.rb_hi = std::tanh((q + band_z) / th.sqrt_nu);
+    if (!std::isfinite(q)) {
+        th.rb_lo = 2.0;
+        th.rb_hi = 2.0;
+    }
     return th;
 }
 
@@ -699,7 +1018,12 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     for (int64_t e = 0; e < E; ++e) maxN = std::max(maxN, ntests[e]);
     const bool wide = l > kMaxTemplL;
     const bool fp32 = Lv.fp32 && !wide;
-    const int rpb = wide ? kGenericRanks : kRanksPerBlock;
+    const size_t lds_cap = (size_t)ctx->lds_per_block;
+    const size_t pair_shm = l >= 2 && !wide ? (fp32 ? pair_lds_bytes<float>(l, Lv.max_m)
+                                                     : pair_lds_bytes<double>(l, Lv.max_m))
+                                            : 0;
+    const bool pair = l >= 2 && !wide && ctx->use_pair_kernel && pair_shm <= lds_cap;
+    const int rpb = wide ? kGenericRanks : (pair ? kPairRanksPerBlock : kRanksPerBlock);
     // windows of ranks: [0, rpb), then growing by 8x
     std::vector<int64_t> wins{0};
     for (int64_t w = rpb; wins.back() < maxN; w *= 8) wins.push_back(std::min<int64_t>(maxN, wins.back() + w));
@@ -737,6 +1061,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     A.n_edges = E;
     A.p = Lv.p;
     A.ranks_per_block = rpb;
+    A.max_m = Lv.max_m;
     A.th = make_thresholds(Lv.q, Lv.n, l, Lv.band_z, Lv.c_err + 4.0 * (l + 2) * 6.0e-8);
 
     FPC_HIP(hipEventRecord(ctx->ev0, st));
@@ -755,9 +1080,17 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             // wide levels always run in FP64
             level_kernel_wide<double><<<g, 64, shm, st>>>(A, l);
             if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev + 1], st));
+        } else if (pair) {
+            if (fp32) FPC_HIP(launch_pair<float>(l, g, pair_shm, st, A));
+            else FPC_HIP(launch_pair<double>(l, g, pair_shm, st, A));
+            if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev + 1], st));
+            if (fp32) {
+                launch_recheck(l, st, A);
+                FPC_HIP(hipMemsetAsync(&Lv.counters[1], 0, sizeof(unsigned long long), st));
+            }
         } else {
             const size_t shm = tile_bytes(Lv.max_m, fp32 ? 4 : 8);
-            const bool tile = shm <= (size_t)ctx->lds_per_block;
+            const bool tile = shm <= std::min<size_t>(lds_cap, 65536);
             if (fp32) {
                 if (tile) launch_level<float, true>(l, g, shm, st, A);
                 else launch_level<float, false>(l, g, 0, st, A);

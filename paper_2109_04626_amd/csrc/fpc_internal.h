@@ -51,6 +51,7 @@ struct fpc_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int lds_per_block = 65536;  // max dynamic LDS bytes per workgroup
+    bool use_pair_kernel = true; // shared-prefix kernel for levels l >= 2 (off with FPC_FLAG_PER_TEST_KERNEL)
     int num_cus = 256;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     static constexpr int kLaunchEvents = 64;

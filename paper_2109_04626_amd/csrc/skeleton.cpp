@@ -129,10 +129,19 @@ void unrank_host(int64_t R, int m, int l, const std::vector<int64_t> &tab, std::
     }
 }
 
-struct SepRec {
-    int32_t level = -1;
-    int8_t kind = FPC_SEP_NONE;
+// Separating sets: level and kind per pair, LIST nodes in a flat array.
+struct SepStore {
+    std::vector<int32_t> level;                        // per pair, -1 kept
+    std::vector<int8_t> kind;                          // per pair
+    std::vector<std::pair<int64_t, int64_t>> lists;    // (pair, offset into nodes)
     std::vector<int32_t> nodes;
+    void reset(int64_t P)
+    {
+        level.assign(P, -1);
+        kind.assign(P, FPC_SEP_NONE);
+        lists.clear();
+        nodes.clear();
+    }
 };
 
 }  // namespace
@@ -258,7 +267,7 @@ struct Run {
     const float *C32 = nullptr;
     double c_err = 0.0;
     std::vector<uint8_t> adj;
-    std::vector<SepRec> sep;
+    SepStore sep;
     std::vector<fpc_level_stats> levels;
     int64_t spent_possible = 0;
     int64_t total_exec = 0;
@@ -375,12 +384,13 @@ retry:
     for (const auto &d : dl) {
         const EdgeRec &er = recs[d.first];
         unrank_host(d.second, er.m, l, ctx->binom_host, pos);
-        SepRec &sr = R.sep[pair_index(er.i, er.j, R.p)];
-        sr.level = l;
-        sr.kind = FPC_SEP_LIST;
-        sr.nodes.resize(l);
-        for (int t = 0; t < l; ++t) sr.nodes[t] = cand[er.cand_off + pos[t]];
-        std::sort(sr.nodes.begin(), sr.nodes.end());
+        const int64_t pr = pair_index(er.i, er.j, R.p);
+        R.sep.level[pr] = l;
+        R.sep.kind[pr] = FPC_SEP_LIST;
+        const size_t o = R.sep.nodes.size();
+        R.sep.lists.emplace_back(pr, (int64_t)o);
+        for (int t = 0; t < l; ++t) R.sep.nodes.push_back(cand[er.cand_off + pos[t]]);
+        std::sort(R.sep.nodes.begin() + o, R.sep.nodes.end());
     }
     for (const auto &d : dl) {
         const EdgeRec &er = recs[d.first];
@@ -411,6 +421,7 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
     int rc = validate(P);
     if (rc) return rc;
     FPC_HIP(hipSetDevice(ctx->device));
+    ctx->use_pair_kernel = !(P->flags & FPC_FLAG_PER_TEST_KERNEL);
     Run R;
     R.ctx = ctx;
     R.P = P;
@@ -445,7 +456,7 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
 
     R.adj.assign(pp, 1);
     for (int i = 0; i < p; ++i) R.adj[(size_t)i * p + i] = 0;
-    R.sep.assign((size_t)p * (p - 1) / 2, SepRec{});
+    R.sep.reset((int64_t)p * (p - 1) / 2);
     double first_ms = 0.0;
     const int cap = P->max_level;
     CandSets cs;
@@ -472,9 +483,9 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
         for (int i = 0; i < p; ++i)
             for (int j = i + 1; j < p; ++j)
                 if (ind[(size_t)i * p + j]) {
-                    SepRec &sr = R.sep[pair_index(i, j, p)];
-                    sr.level = p - 2;
-                    sr.kind = FPC_SEP_ALL_BUT;
+                    const int64_t pr = pair_index(i, j, p);
+                    R.sep.level[pr] = p - 2;
+                    R.sep.kind[pr] = FPC_SEP_ALL_BUT;
                     R.adj[(size_t)i * p + j] = R.adj[(size_t)j * p + i] = 0;
                     ++dels;
                 }
@@ -522,8 +533,7 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
     res->sep_level = (int32_t *)std::malloc(sizeof(int32_t) * PP);
     res->sep_kind = (int8_t *)std::malloc(PP);
     res->sep_off = (int64_t *)std::malloc(sizeof(int64_t) * (PP + 1));
-    int64_t tot = 0;
-    for (const SepRec &sr : R.sep) tot += (int64_t)sr.nodes.size();
+    const int64_t tot = (int64_t)R.sep.nodes.size();
     res->sep_nodes = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1));
     res->levels = (fpc_level_stats *)std::malloc(sizeof(fpc_level_stats) * std::max<size_t>(R.levels.size(), 1));
     if (!res->adj || !res->sep_level || !res->sep_kind || !res->sep_off || !res->sep_nodes || !res->levels) {
@@ -531,13 +541,20 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
         return FPC_ENOMEM;
     }
     std::memcpy(res->adj, R.adj.data(), pp);
+    // LIST sets in pair order; each pair is deleted at most once
+    std::sort(R.sep.lists.begin(), R.sep.lists.end());
+    std::memcpy(res->sep_level, R.sep.level.data(), sizeof(int32_t) * PP);
+    std::memcpy(res->sep_kind, R.sep.kind.data(), PP);
     int64_t o = 0;
+    size_t li = 0;
     for (int64_t k = 0; k < PP; ++k) {
-        const SepRec &sr = R.sep[k];
-        res->sep_level[k] = sr.level;
-        res->sep_kind[k] = sr.kind;
         res->sep_off[k] = o;
-        for (int32_t v : sr.nodes) res->sep_nodes[o++] = v;
+        if (li < R.sep.lists.size() && R.sep.lists[li].first == k) {
+            const int L = R.sep.level[k];
+            std::memcpy(res->sep_nodes + o, R.sep.nodes.data() + R.sep.lists[li].second, sizeof(int32_t) * L);
+            o += L;
+            ++li;
+        }
     }
     res->sep_off[PP] = o;
     std::memcpy(res->levels, R.levels.data(), sizeof(fpc_level_stats) * R.levels.size());

@@ -43,11 +43,13 @@ def test_golden_matches_workload(setup):
     assert gold["min_margin"] > 1e-9  # no near-tie in the oracle's decisions
 
 
+@pytest.mark.parametrize("flags", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_fullsize_skeleton_bit_exact(setup, prec):
+def test_fullsize_skeleton_bit_exact(setup, prec, flags):
     fpc, ctx, X, Xd, cfg, gold = setup
-    print(f"[fullsize] {NAME} seed={SEED} precision={prec}", flush=True)
-    got = fpc.fpc_skeleton(ctx, Xd, alpha=cfg["alpha"], max_level=cfg["max_level"], precision=prec)
+    print(f"[fullsize] {NAME} seed={SEED} precision={prec} flags={flags}", flush=True)
+    got = fpc.fpc_skeleton(ctx, Xd, alpha=cfg["alpha"], max_level=cfg["max_level"], precision=prec,
+                           flags=flags)
     assert np.array_equal(got["adj"], gold["adj"])
     assert np.array_equal(got["sep_level"], gold["sep_level"])
     assert np.array_equal(got["sep_kind"], gold["sep_kind"])

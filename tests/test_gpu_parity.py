@@ -228,16 +228,18 @@ def test_skeleton_forward_matches_oracle(fpc, ctx, seed):
     _compare_fp64(fpc, got, ref, cfg["p"])
 
 
+@pytest.mark.parametrize("flags", [0, 1])
 @pytest.mark.parametrize("p,n,deg,L,prec", [(57, 2000, 5.0, 4, 0), (57, 2000, 5.0, 4, 1),
                                              (130, 3000, 4.0, 3, 0), (130, 3000, 4.0, 3, 1),
-                                             (40, 800, 6.0, -1, 0)])
-def test_skeleton_mid_sizes(fpc, ctx, p, n, deg, L, prec):
-    _say(f"[skeleton mid] p={p} n={n} deg={deg} L={L} prec={prec}")
+                                             (90, 3000, 5.0, 6, 0), (90, 3000, 5.0, 6, 1),
+                                             (40, 800, 6.0, -1, 0), (40, 800, 6.0, -1, 1)])
+def test_skeleton_mid_sizes(fpc, ctx, p, n, deg, L, prec, flags):
+    _say(f"[skeleton mid] p={p} n={n} deg={deg} L={L} prec={prec} flags={flags}")
     sem = semdata.make_sem(p, 11, degree=deg)
     X = semdata.sample(sem, n, 11)
     C = oracle.corr(X)
     ref = oracle.skeleton(C, n, alpha=0.01, max_level=L)
-    got = fpc.fpc_skeleton(ctx, dev(X), alpha=0.01, max_level=L, precision=prec)
+    got = fpc.fpc_skeleton(ctx, dev(X), alpha=0.01, max_level=L, precision=prec, flags=flags)
     assert np.array_equal(got["adj"], ref["adj"])
     assert np.array_equal(got["sep_level"], ref["sep_level"])
     if prec == 0:

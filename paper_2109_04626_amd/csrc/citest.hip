@@ -294,13 +294,17 @@ __device__ __forceinline__ int64_t find_edge(const int64_t *__restrict__ off, in
     return lo;
 }
 
+// One row of the strict upper triangle per wave at a time, lanes along the
+// row (coalesced reads of C, consecutive LDS writes).
 template <typename T>
 __device__ void stage_tile(const T *__restrict__ C, int p, const int32_t *__restrict__ cand, int m, int i, int j,
                            T *tri, T *ci, T *cj)
 {
-    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
-        const int a = t / m, b = t % m;
-        if (a < b) tri[a * (2 * m - a - 3) / 2 - 1 + b] = C[(size_t)cand[a] * p + cand[b]];
+    const int lane = threadIdx.x % 64, nw = blockDim.x / 64;
+    for (int a = threadIdx.x / 64; a < m - 1; a += nw) {
+        const int base = a * (2 * m - a - 3) / 2 - 1;
+        const T *Crow = C + (size_t)cand[a] * p;
+        for (int b = a + 1 + lane; b < m; b += 64) tri[base + b] = Crow[cand[b]];
     }
     for (int b = threadIdx.x; b < m; b += blockDim.x) {
         ci[b] = C[(size_t)i * p + cand[b]];
@@ -723,6 +727,296 @@ size_t pair_lds_bytes(int l, int m)
     return sizeof(T) * (tile + (size_t)kWaves * m * (SA + SB));
 }
 
+
+// ------------------------------------------------------------------ triple kernel (l >= 3)
+// As the pair kernel, with the shared prefix one shorter: Q holds the
+// first l-3 elements, the next element a is uniform across the wave (its
+// row of the Schur table is a broadcast read and its pivot is computed
+// once), and the lanes run the pairs (b < c) after a.  Eliminating a from
+// the Schur complement of Q is a rank-1 update applied on the fly:
+//     l_x = S_ax / sqrt(S_aa),  S'_xy = S_xy - l_x l_y,  S'_xi = S_xi - l_x u_a
+// and the pair (b, c) is then eliminated from S' as in the pair kernel.
+// The table is built once per Q (C(n,3) tests) instead of once per
+// (l-2)-prefix (C(n,2) tests).
+template <typename T, int QL>
+struct TripleLayout {
+    static constexpr int V = 16 / (int)sizeof(T);
+    static constexpr int nE = QL + 4;  // w[QL], S_xx, S_xi, S_xj, row offset of x in the packed tile
+    static constexpr int S = (nE + V - 1) / V * V;
+};
+
+template <typename T, int QL>
+__global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
+{
+    using Lay = TripleLayout<T, QL>;
+    constexpr int L = QL + 3;
+    constexpr int QLL = QL > 0 ? QL : 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t blk = blockIdx.x;
+    const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
+    const EdgeRec E = A.edges[e];
+    const int m = E.m;
+    const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * kPairRanksPerBlock;
+    const int64_t r1 = min(r0 + (int64_t)kPairRanksPerBlock, min(A.win_hi, E.ntests));
+    if (r0 >= r1) return;  // uniform
+    __shared__ int skip;
+    if (threadIdx.x == 0) skip = load_minhit(&A.minhit[e]) < (uint64_t)r0;
+    __syncthreads();
+    if (skip) return;  // uniform
+    const T *C = static_cast<const T *>(A.C);
+    const int32_t *cand = A.cand + E.cand_off;
+    T *tri = reinterpret_cast<T *>(smem);
+    const int ntri = m * (m - 1) / 2;
+    T *ci = tri + ntri, *cj = ci + m;
+    stage_tile<T>(C, A.p, cand, m, E.i, E.j, tri, ci, cj);
+    const T cij = C[(size_t)E.i * A.p + E.j];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const size_t tile_elems = ((size_t)ntri + 2 * (size_t)m + Lay::V - 1) / Lay::V * Lay::V;
+    T *tab = tri + tile_elems + (size_t)wave * A.max_m * Lay::S;
+    __syncthreads();
+
+    const int64_t wlo = r0 + (int64_t)wave * kPairRanksPerWave;
+    const int64_t whi = min(wlo + (int64_t)kPairRanksPerWave, r1);
+    if (wlo >= whi) return;  // no later block-wide barrier
+    const auto row = [&](int a) { return a * (2 * m - a - 3) / 2 - 1; };
+
+    int c[L];
+    unrank<L>(wlo, m, A.binom, c);
+    int Q[QLL];
+#pragma unroll
+    for (int t = 0; t < QL; ++t) Q[t] = c[t];
+    int sQ = QL > 0 ? Q[QL - 1] + 1 : 0;
+    int a = c[QL];
+    int tau;
+    {
+        const int na = m - 1 - a, b0 = c[QL + 1] - (a + 1), c0 = c[QL + 2] - (a + 1);
+        tau = b0 * (2 * na - b0 - 1) / 2 + (c0 - b0 - 1);
+    }
+    int64_t rank = wlo;
+    int64_t remaining = whi - wlo;
+    uint64_t executed = 0;
+    const float errk = (float)(kErrSafety * A.th.c_eff * (L + 2));
+    const float rlo32 = (float)A.th.rb_lo, rhi32 = (float)A.th.rb_hi;
+    bool stop = false;
+    while (!stop) {
+        // ---- Q state (identical in every lane)
+        T LQ[QL > 0 ? QL * (QL + 1) / 2 : 1], invQ[QLL], uQ[QLL], vQ[QLL];
+        int rwQ[QLL];
+        T H11 = T(1), H22 = T(1), H12 = cij, dminQ = T(1);
+        bool okQ = true;
+#pragma unroll
+        for (int t = 0; t < QL; ++t) rwQ[t] = row(Q[t]);
+#pragma unroll
+        for (int t = 0; t < QL; ++t) {
+            T *Lt = LQ + t * (t + 1) / 2;
+#pragma unroll
+            for (int s2 = 0; s2 < t; ++s2) {
+                T v = tri[rwQ[s2] + Q[t]];
+                const T *Ls = LQ + s2 * (s2 + 1) / 2;
+#pragma unroll
+                for (int q = 0; q < s2; ++q) v -= Lt[q] * Ls[q];
+                Lt[s2] = v * invQ[s2];
+            }
+            T d = T(1);
+#pragma unroll
+            for (int q = 0; q < t; ++q) d -= Lt[q] * Lt[q];
+            okQ = okQ && d > T(0);
+            dminQ = d < dminQ ? d : dminQ;
+            invQ[t] = rsqv(d);
+            T ai = ci[Q[t]], aj = cj[Q[t]];
+#pragma unroll
+            for (int q = 0; q < t; ++q) {
+                ai -= Lt[q] * uQ[q];
+                aj -= Lt[q] * vQ[q];
+            }
+            uQ[t] = ai * invQ[t];
+            vQ[t] = aj * invQ[t];
+            H11 -= uQ[t] * uQ[t];
+            H22 -= vQ[t] * vQ[t];
+            H12 -= uQ[t] * vQ[t];
+        }
+        // ---- Schur table of Q over the positions [sQ, m)
+        const int n = m - sQ;
+        wave_sync();
+        for (int xp = lane; xp < n; xp += 64) {
+            const int x = sQ + xp;
+            T w[QLL];
+#pragma unroll
+            for (int t = 0; t < QL; ++t) {
+                T v = tri[rwQ[t] + x];
+#pragma unroll
+                for (int q = 0; q < t; ++q) v -= LQ[t * (t + 1) / 2 + q] * w[q];
+                w[t] = v * invQ[t];
+            }
+            T sxx = T(1), sxi = ci[x], sxj = cj[x];
+#pragma unroll
+            for (int t = 0; t < QL; ++t) {
+                sxx -= w[t] * w[t];
+                sxi -= w[t] * uQ[t];
+                sxj -= w[t] * vQ[t];
+            }
+            T *ex = tab + (size_t)xp * Lay::S;
+#pragma unroll
+            for (int t = 0; t < QL; ++t) ex[t] = w[t];
+            ex[QL] = sxx;
+            ex[QL + 1] = sxi;
+            ex[QL + 2] = sxj;
+            put_int(ex[QL + 3], row(x));
+        }
+        wave_sync();
+        // ---- a loop (uniform), pairs (b, c) after a across the lanes
+        for (; a <= m - 3; ++a) {
+            const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
+            if (mh < (unsigned long long)rank) {
+                stop = true;
+                break;
+            }
+            const T *eaP = tab + (size_t)(a - sQ) * Lay::S;
+            T wa[QLL];
+#pragma unroll
+            for (int t = 0; t < QL; ++t) wa[t] = eaP[t];
+            const T saa = eaP[QL], sai = eaP[QL + 1], saj = eaP[QL + 2];
+            const int rowa = get_int(eaP[QL + 3]);
+            const T i1 = saa > T(0) ? rsqv(saa) : T(0);
+            const T ua = sai * i1, va = saj * i1;
+            const T H11a = H11 - ua * ua, H22a = H22 - va * va, H12a = H12 - ua * va;
+            const bool oka = okQ && saa > T(0);
+            const T dmina = saa < dminQ ? saa : dminQ;
+            const int na = m - 1 - a;
+            const int P = na * (na - 1) / 2;
+            const int cnt = (int)min((int64_t)(P - tau), remaining);
+            bool hit_found = false;
+            for (int it = 0; it < cnt; it += 64) {
+                const bool valid = it + lane < cnt;
+                const unsigned t = (unsigned)(tau + min(it + lane, cnt - 1));
+                const unsigned u = (unsigned)P - 1u - t;
+                unsigned rr = (unsigned)((__builtin_amdgcn_sqrtf(8.0f * (float)u + 1.0f) - 1.0f) * 0.5f);
+                rr += ((rr + 1u) * (rr + 2u) >> 1) <= u ? 1u : 0u;
+                rr -= ((rr * (rr + 1u)) >> 1) > u ? 1u : 0u;
+                const int b = a + 1 + (na - 2 - (int)rr);
+                const int cc = a + 1 + (na - 1 - (int)(u - ((rr * (rr + 1u)) >> 1)));
+                const T *eb = tab + (size_t)(b - sQ) * Lay::S;
+                const T *ec = tab + (size_t)(cc - sQ) * Lay::S;
+                T sab = tri[rowa + b], sac = tri[rowa + cc], sbc = tri[get_int(eb[QL + 3]) + cc];
+#pragma unroll
+                for (int q = 0; q < QL; ++q) {
+                    sab -= wa[q] * eb[q];
+                    sac -= wa[q] * ec[q];
+                    sbc -= eb[q] * ec[q];
+                }
+                const T lb = sab * i1, lc = sac * i1;
+                const T sbb = eb[QL] - lb * lb, scc = ec[QL] - lc * lc, sbc2 = sbc - lb * lc;
+                const T sbi = eb[QL + 1] - lb * ua, sbj = eb[QL + 2] - lb * va;
+                const T sci = ec[QL + 1] - lc * ua, scj = ec[QL + 2] - lc * va;
+                const T i2 = rsqv(sbb);
+                const T l2 = sbc2 * i2;
+                const T d3 = scc - l2 * l2;
+                const T i3 = rsqv(d3);
+                const T ub = sbi * i2, vb = sbj * i2;
+                const T uc = (sci - l2 * ub) * i3, vc = (scj - l2 * vb) * i3;
+                const T h11 = H11a - ub * ub - uc * uc;
+                const T h22 = H22a - vb * vb - vc * vc;
+                const T h12 = H12a - ub * vb - uc * vc;
+                bool ok = oka && sbb > T(0) && d3 > T(0) && h11 > T(0) && h22 > T(0);
+                const T r = h12 * rsqv(h11 * h22);
+                ok = ok && fabs(r) < T(1);
+                int dec;
+                if constexpr (sizeof(T) == 8) {
+                    dec = decide64((double)r, ok, A.th) ? DEC_INDEP : DEC_DEP;
+                } else {
+                    const float dmin = fminf(fminf((float)dmina, fminf((float)sbb, (float)d3)),
+                                             fminf((float)h11, (float)h22));
+                    dec = decide32r((float)r, dmin, ok, rlo32, rhi32, errk);
+                }
+                executed += (uint64_t)min(64, cnt - it);
+                if constexpr (sizeof(T) == 4) {
+                    const bool rq = valid && dec == DEC_RECHECK;
+                    const unsigned long long qb = __ballot(rq);
+                    if (qb) {
+                        unsigned long long slot = 0;
+                        if (lane == 0) slot = atomicAdd(&A.counters[1], (unsigned long long)__popcll(qb));
+                        slot = __shfl(slot, 0);
+                        if (rq) {
+                            const unsigned long long idx = slot + __popcll(qb & ((1ull << lane) - 1ull));
+                            if ((int64_t)idx < A.queue_cap) {
+                                A.queue[2 * idx] = e;
+                                A.queue[2 * idx + 1] = rank + it + lane;
+                            }
+                        }
+                    }
+                }
+                const unsigned long long hb = __ballot(valid && dec == DEC_INDEP);
+                if (hb) {
+                    if (lane == 0)
+                        atomicMin((unsigned long long *)&A.minhit[e],
+                                  (unsigned long long)(rank + it + __ffsll((long long)hb) - 1));
+                    hit_found = true;
+                    break;
+                }
+            }
+            if (hit_found) {
+                stop = true;
+                break;
+            }
+            rank += cnt;
+            remaining -= cnt;
+            tau = 0;
+            if (remaining <= 0) {
+                stop = true;
+                break;
+            }
+        }
+        if (stop) break;
+        // ---- next Q: next (l-3)-combination of positions [0, m-3)
+        if constexpr (QL == 0) {
+            break;
+        } else {
+            int k = -1;
+#pragma unroll
+            for (int t = 0; t < QL; ++t)
+                if (Q[t] != (m - 3) - QL + t) k = t;
+            if (k < 0) break;
+#pragma unroll
+            for (int t = 0; t < QL; ++t) {
+                if (t == k) Q[t] += 1;
+                else if (t > k) Q[t] = Q[t - 1] + 1;
+            }
+            sQ = Q[QL - 1] + 1;
+            a = sQ;
+            tau = 0;
+        }
+    }
+    if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
+}
+
+template <typename T, int QL = 0>
+hipError_t launch_triple(int l, dim3 g, size_t shm, hipStream_t st, const LevelArgs &A)
+{
+    if constexpr (QL + 3 <= kMaxTemplL) {
+        if (l == QL + 3) {
+            if (shm > 65536) {
+                const hipError_t e = hipFuncSetAttribute((const void *)triple_kernel<T, QL>,
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+                if (e != hipSuccess) return e;
+            }
+            triple_kernel<T, QL><<<g, 256, shm, st>>>(A);
+            return hipGetLastError();
+        }
+        return launch_triple<T, QL + 1>(l, g, shm, st, A);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+size_t triple_lds_bytes(int l, int m)
+{
+    const int QL = l - 3;
+    const int V = 16 / (int)sizeof(T);
+    const int S = (QL + 4 + V - 1) / V * V;
+    const size_t tile = ((size_t)m * (m - 1) / 2 + 2 * (size_t)m + V - 1) / V * V;
+    return sizeof(T) * (tile + (size_t)kWaves * m * S);
+}
+
 // ------------------------------------------------------------------ wide levels
 // One wave per test, the (l+2)x(l+2) matrix over [K, i, j] packed lower in
 // LDS, right-looking Cholesky; after l steps the trailing 2x2 block is H.
@@ -1019,8 +1313,10 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     const bool wide = l > kMaxTemplL;
     const bool fp32 = Lv.fp32 && !wide;
     const size_t lds_cap = (size_t)ctx->lds_per_block;
-    const size_t pair_shm = l >= 2 && !wide ? (fp32 ? pair_lds_bytes<float>(l, Lv.max_m)
+    const size_t pair_shm = l == 2 && !wide ? (fp32 ? pair_lds_bytes<float>(l, Lv.max_m)
                                                      : pair_lds_bytes<double>(l, Lv.max_m))
+                          : l >= 3 && !wide ? (fp32 ? triple_lds_bytes<float>(l, Lv.max_m)
+                                                    : triple_lds_bytes<double>(l, Lv.max_m))
                                             : 0;
     const bool pair = l >= 2 && !wide && ctx->use_pair_kernel && pair_shm <= lds_cap;
     const int rpb = wide ? kGenericRanks : (pair ? kPairRanksPerBlock : kRanksPerBlock);
@@ -1028,25 +1324,27 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     std::vector<int64_t> wins{0};
     for (int64_t w = rpb; wins.back() < maxN; w *= 8) wins.push_back(std::min<int64_t>(maxN, wins.back() + w));
     const int nw = (int)wins.size() - 1;
-    std::vector<int64_t> offs((size_t)nw * (E + 1));
-    std::vector<int64_t> nblocks(nw);
-    for (int w = 0; w < nw; ++w) {
-        int64_t *o = offs.data() + (size_t)w * (E + 1);
+    // Workgroup prefix sums per window.  The first window covers every
+    // edge; later ones only the edges with no separating rank yet (their
+    // minhit is read back after the previous window), so the ranks past an
+    // edge's first hit are never launched.
+    FPC_HIP(hipStreamSynchronize(st));  // earlier uploads from the staging buffer have completed
+    int rc = ctx->blockoff.ensure(sizeof(int64_t) * (size_t)nw * (E + 1));
+    if (rc) return rc;
+    if ((rc = ctx->h_stage.ensure(sizeof(int64_t) * (size_t)nw * (E + 1)))) return rc;
+    if ((rc = ctx->h_back.ensure(sizeof(uint64_t) * (size_t)E))) return rc;
+    int64_t *h_offs = ctx->h_stage.as<int64_t>();
+    uint64_t *h_minhit = ctx->h_back.as<uint64_t>();
+    auto window_offsets = [&](int w, bool filter) -> int64_t {
+        int64_t *o = h_offs + (size_t)w * (E + 1);
         o[0] = 0;
         for (int64_t e = 0; e < E; ++e) {
-            const int64_t span = std::max<int64_t>(0, std::min(ntests[e], wins[w + 1]) - wins[w]);
+            int64_t span = std::max<int64_t>(0, std::min(ntests[e], wins[w + 1]) - wins[w]);
+            if (filter && h_minhit[e] != ~0ull) span = 0;
             o[e + 1] = o[e] + (span + rpb - 1) / rpb;
         }
-        nblocks[w] = o[E];
-        if (nblocks[w] > 0x7fffffffLL) return FPC_EBUDGET;
-    }
-    FPC_HIP(hipStreamSynchronize(st));  // earlier uploads from the staging buffer have completed
-    int rc = ctx->blockoff.ensure(sizeof(int64_t) * offs.size());
-    if (rc) return rc;
-    if ((rc = ctx->h_stage.ensure(sizeof(int64_t) * offs.size()))) return rc;
-    std::memcpy(ctx->h_stage.ptr, offs.data(), sizeof(int64_t) * offs.size());
-    FPC_HIP(hipMemcpyAsync(ctx->blockoff.ptr, ctx->h_stage.ptr, sizeof(int64_t) * offs.size(),
-                           hipMemcpyHostToDevice, st));
+        return o[E];
+    };
 
     LevelArgs A{};
     A.edges = Lv.edges;
@@ -1067,19 +1365,35 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     FPC_HIP(hipEventRecord(ctx->ev0, st));
     int nev = 0;
     for (int w = 0; w < nw; ++w) {
-        if (!nblocks[w]) continue;
+        if (w > 0) {
+            FPC_HIP(hipMemcpyAsync(h_minhit, Lv.minhit, sizeof(uint64_t) * E, hipMemcpyDeviceToHost, st));
+            FPC_HIP(hipStreamSynchronize(st));
+        }
+        const int64_t nblk = window_offsets(w, w > 0);
+        if (nblk > 0x7fffffffLL) return FPC_EBUDGET;
+        if (!nblk) continue;
+        FPC_HIP(hipMemcpyAsync(ctx->blockoff.as<int64_t>() + (size_t)w * (E + 1), h_offs + (size_t)w * (E + 1),
+                               sizeof(int64_t) * (E + 1), hipMemcpyHostToDevice, st));
         const bool timed = nev < fpc_ctx::kLaunchEvents;
         if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev], st));
         A.blockoff = ctx->blockoff.as<int64_t>() + (size_t)w * (E + 1);
         A.win_lo = wins[w];
         A.win_hi = wins[w + 1];
-        dim3 g((unsigned)nblocks[w]);
+        dim3 g((unsigned)nblk);
         if (wide) {
             const size_t shm = (fp32 ? 4 : 8) * ((size_t)(l + 2) * (l + 3) / 2 + 1) + sizeof(int) * (l + 1) + 16;
             if (shm > (size_t)ctx->lds_per_block) return FPC_EBUDGET;
             // wide levels always run in FP64
             level_kernel_wide<double><<<g, 64, shm, st>>>(A, l);
             if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev + 1], st));
+        } else if (pair && l >= 3) {
+            if (fp32) FPC_HIP(launch_triple<float>(l, g, pair_shm, st, A));
+            else FPC_HIP(launch_triple<double>(l, g, pair_shm, st, A));
+            if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev + 1], st));
+            if (fp32) {
+                launch_recheck(l, st, A);
+                FPC_HIP(hipMemsetAsync(&Lv.counters[1], 0, sizeof(unsigned long long), st));
+            }
         } else if (pair) {
             if (fp32) FPC_HIP(launch_pair<float>(l, g, pair_shm, st, A));
             else FPC_HIP(launch_pair<double>(l, g, pair_shm, st, A));

@@ -24,7 +24,7 @@ namespace fpc {
 namespace {
 
 constexpr int kNB = 32;
-constexpr int kUT = 64;  // update tile
+constexpr int kUT = 32;  // update tile
 
 // Invert the nb x nb diagonal block at k0 in LDS (Gauss-Jordan, no pivoting).
 __global__ __launch_bounds__(1024) void panel_inverse(const double *__restrict__ A, int p, int k0, int nb,
@@ -60,24 +60,20 @@ __global__ __launch_bounds__(1024) void panel_inverse(const double *__restrict__
     if (r < nb && c < nb) Pinv[r * kNB + c] = P[r][c];
 }
 
-// V = A[:,K] (p x nb, row stride kNB) and U = Pinv A[K,:] (nb x p).
+// V = A[:,K] (p x nb, row stride kNB) and U = Pinv A[K,:] (nb x p); one
+// thread per (row r of the panel, column j).
 __global__ __launch_bounds__(256) void panel_copy(const double *__restrict__ A, int p, int k0, int nb,
                                                   const double *__restrict__ Pinv, double *__restrict__ V,
                                                   double *__restrict__ U)
 {
-    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.x * 64 + threadIdx.x % 64;
+    const int r0 = threadIdx.x / 64;  // 4 rows of the panel per block, strided
     if (j >= p) return;
-    double col[kNB];
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) col[c] = c < nb ? A[(size_t)(k0 + c) * p + j] : 0.0;
-#pragma unroll
-    for (int c = 0; c < kNB; ++c)
-        if (c < nb) V[(size_t)j * kNB + c] = A[(size_t)j * p + k0 + c];
-    for (int r = 0; r < nb; ++r) {
+    for (int r = r0; r < nb; r += 4) {
         double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < kNB; ++c) s = fma(Pinv[r * kNB + c], col[c], s);
+        for (int c = 0; c < nb; ++c) s = fma(Pinv[r * kNB + c], A[(size_t)(k0 + c) * p + j], s);
         U[(size_t)r * p + j] = s;
+        V[(size_t)j * kNB + r] = A[(size_t)j * p + k0 + r];
     }
 }
 
@@ -99,26 +95,26 @@ __global__ __launch_bounds__(256) void sweep_update(double *__restrict__ A, int 
     }
     __syncthreads();
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    for (int q = 0; q < 4; ++q) {
-        const int i = i0 + ty * 4 + q;
+    for (int q = 0; q < 2; ++q) {
+        const int i = i0 + ty * 2 + q;
         if (i >= p) continue;
         const bool inK_i = i >= k0 && i < k0 + nb;
-        for (int s = 0; s < 4; ++s) {
-            const int j = j0 + tx * 4 + s;
+        for (int s = 0; s < 2; ++s) {
+            const int j = j0 + tx * 2 + s;
             if (j >= p) continue;
             const bool inK_j = j >= k0 && j < k0 + nb;
             double v;
             if (inK_i && inK_j) {
                 v = Pinv[(i - k0) * kNB + (j - k0)];
             } else if (inK_i) {
-                v = Us[i - k0][tx * 4 + s];
+                v = Us[i - k0][tx * 2 + s];
             } else if (inK_j) {
                 double acc = 0.0;
-                for (int c = 0; c < nb; ++c) acc = fma(Vs[ty * 4 + q][c], Pinv[c * kNB + (j - k0)], acc);
+                for (int c = 0; c < nb; ++c) acc = fma(Vs[ty * 2 + q][c], Pinv[c * kNB + (j - k0)], acc);
                 v = -acc;
             } else {
                 double acc = A[(size_t)i * p + j];
-                for (int c = 0; c < nb; ++c) acc = fma(-Vs[ty * 4 + q][c], Us[c][tx * 4 + s], acc);
+                for (int c = 0; c < nb; ++c) acc = fma(-Vs[ty * 2 + q][c], Us[c][tx * 2 + s], acc);
                 v = acc;
             }
             A[(size_t)i * p + j] = v;
@@ -176,7 +172,7 @@ int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r
     for (int k0 = 0; k0 < p; k0 += kNB) {
         const int nb = p - k0 < kNB ? p - k0 : kNB;
         panel_inverse<<<1, 1024, 0, st>>>(A, p, k0, nb, Pinv, bad);
-        panel_copy<<<(p + 255) / 256, 256, 0, st>>>(A, p, k0, nb, Pinv, V, U);
+        panel_copy<<<(p + 63) / 64, 256, 0, st>>>(A, p, k0, nb, Pinv, V, U);
         sweep_update<<<dim3(nbt, nbt), 256, 0, st>>>(A, p, k0, nb, V, U, Pinv);
     }
     first_level_decide<<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(A, p, n, q, r_out, indep_out, bad);

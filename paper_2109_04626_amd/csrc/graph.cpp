@@ -10,6 +10,7 @@
 // the labelling plus O(deg i + deg j) per edge.
 #include <algorithm>
 #include <cstring>
+#include <thread>
 
 #include "fpc_internal.h"
 
@@ -24,44 +25,48 @@ struct Adjacency {
 
 void build_adjacency(const uint8_t *adj, int p, Adjacency &g)
 {
-    g.off.assign(p + 1, 0);
-    for (int u = 0; u < p; ++u) {
-        int d = 0;
-        const uint8_t *row = adj + (size_t)u * p;
-        for (int v = 0; v < p; ++v) d += (row[v] != 0 && v != u);
-        g.off[u + 1] = g.off[u] + d;
-    }
-    g.nb.resize(g.off[p]);
-    g.eid.resize(g.off[p]);
+    // one pass over the upper triangle: edge ids in row-major (u < v) order
     g.eu.clear();
     g.ev.clear();
-    std::vector<int32_t> fill(g.off.begin(), g.off.end() - 1);
-    // edge ids in row-major (u < v) order
+    std::vector<int32_t> deg(p, 0);
     for (int u = 0; u < p; ++u) {
         const uint8_t *row = adj + (size_t)u * p;
-        for (int v = u + 1; v < p; ++v) {
-            if (!row[v]) continue;
-            int id = (int)g.eu.size();
-            g.eu.push_back(u);
-            g.ev.push_back(v);
-            g.nb[fill[u]] = v;
-            g.eid[fill[u]++] = id;
-            g.nb[fill[v]] = u;
-            g.eid[fill[v]++] = id;
+        int v = u + 1;
+        while (v < p) {
+            if (v + 8 <= p) {  // skip eight absent entries at a time
+                uint64_t word;
+                std::memcpy(&word, row + v, 8);
+                if (!word) {
+                    v += 8;
+                    continue;
+                }
+            }
+            if (row[v]) {
+                g.eu.push_back(u);
+                g.ev.push_back(v);
+                ++deg[u];
+                ++deg[v];
+            }
+            ++v;
         }
     }
-    // neighbour lists sorted ascending (u's list gets smaller ids first from
-    // the v-loop of earlier rows, then larger ones from its own row)
-    for (int u = 0; u < p; ++u) {
-        int a = g.off[u], b = g.off[u + 1];
-        std::vector<std::pair<int32_t, int32_t>> tmp;
-        tmp.reserve(b - a);
-        for (int t = a; t < b; ++t) tmp.emplace_back(g.nb[t], g.eid[t]);
-        std::sort(tmp.begin(), tmp.end());
-        for (int t = a; t < b; ++t) {
-            g.nb[t] = tmp[t - a].first;
-            g.eid[t] = tmp[t - a].second;
-        }
+    g.off.assign(p + 1, 0);
+    for (int u = 0; u < p; ++u) g.off[u + 1] = g.off[u] + deg[u];
+    g.nb.resize(g.off[p]);
+    g.eid.resize(g.off[p]);
+    std::vector<int32_t> fill(g.off.begin(), g.off.end() - 1);
+    // edges in (u, v) row-major order: every list receives its smaller
+    // neighbours (as v) before its larger ones (as u), in increasing order
+    const int E = (int)g.eu.size();
+    for (int id = 0; id < E; ++id) {
+        const int u = g.eu[id], v = g.ev[id];
+        g.nb[fill[v]] = u;
+        g.eid[fill[v]++] = id;
+    }
+    for (int id = 0; id < E; ++id) {
+        const int u = g.eu[id], v = g.ev[id];
+        g.nb[fill[u]] = v;
+        g.eid[fill[u]++] = id;
     }
 }
 
@@ -123,27 +128,75 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out)
     std::vector<int32_t> block;
     edge_blocks(g, p, block);
     const int E = (int)g.eu.size();
+    // block id of each adjacency slot, so the merge reads two flat arrays
+    std::vector<int32_t> nbblk(g.nb.size());
+    for (size_t t = 0; t < g.nb.size(); ++t) nbblk[t] = block[g.eid[t]];
     out.ei.assign(g.eu.begin(), g.eu.end());
     out.ej.assign(g.ev.begin(), g.ev.end());
-    out.off.assign(E + 1, 0);
-    out.nodes.clear();
-    out.nodes.reserve((size_t)E * 8);
-    for (int e = 0; e < E; ++e) {
-        const int i = g.eu[e], j = g.ev[e], b = block[e];
-        int a = g.off[i], ae = g.off[i + 1], c = g.off[j], ce = g.off[j + 1];
-        // merge the block-filtered neighbour lists of i and j
-        while (a < ae || c < ce) {
-            int ka = INT32_MAX, kc = INT32_MAX;
-            while (a < ae && (g.nb[a] == j || block[g.eid[a]] != b)) ++a;
-            while (c < ce && (g.nb[c] == i || block[g.eid[c]] != b)) ++c;
-            if (a < ae) ka = g.nb[a];
-            if (c < ce) kc = g.nb[c];
-            if (ka == INT32_MAX && kc == INT32_MAX) break;
-            if (ka < kc) { out.nodes.push_back(ka); ++a; }
-            else if (kc < ka) { out.nodes.push_back(kc); ++c; }
-            else { out.nodes.push_back(ka); ++a; ++c; }
+    out.off.resize(E + 1);
+    out.off[0] = 0;
+    // merge the neighbour lists of i and j, keeping the entries of block b
+    // other than i and j themselves (both lists are sorted); edges are split
+    // into contiguous chunks merged by separate host threads
+    auto merge_range = [&](int e0, int e1, std::vector<int32_t> &dst, std::vector<int64_t> &len) {
+        for (int e = e0; e < e1; ++e) {
+            const int i = g.eu[e], j = g.ev[e], b = block[e];
+            const int32_t *na = g.nb.data() + g.off[i], *ba = nbblk.data() + g.off[i];
+            const int32_t *nc = g.nb.data() + g.off[j], *bc = nbblk.data() + g.off[j];
+            const int la = g.off[i + 1] - g.off[i], lc = g.off[j + 1] - g.off[j];
+            const size_t start = dst.size();
+            int a = 0, c = 0;
+            while (a < la && c < lc) {
+                const int ka = na[a], kc = nc[c];
+                if (ka < kc) {
+                    if (ba[a] == b && ka != j) dst.push_back(ka);
+                    ++a;
+                } else if (kc < ka) {
+                    if (bc[c] == b && kc != i) dst.push_back(kc);
+                    ++c;
+                } else {
+                    if ((ba[a] == b || bc[c] == b) && ka != i && ka != j) dst.push_back(ka);
+                    ++a;
+                    ++c;
+                }
+            }
+            for (; a < la; ++a)
+                if (ba[a] == b && na[a] != j) dst.push_back(na[a]);
+            for (; c < lc; ++c)
+                if (bc[c] == b && nc[c] != i) dst.push_back(nc[c]);
+            len.push_back((int64_t)(dst.size() - start));
         }
-        out.off[e + 1] = (int64_t)out.nodes.size();
+    };
+    unsigned hw = std::thread::hardware_concurrency();
+    int nth = (int)std::min<unsigned>(hw ? hw : 1, 16u);
+    if (E < 2048) nth = 1;
+    std::vector<std::vector<int32_t>> parts(nth);
+    std::vector<std::vector<int64_t>> lens(nth);
+    std::vector<int> bounds(nth + 1);
+    for (int t = 0; t <= nth; ++t) bounds[t] = (int)((int64_t)E * t / nth);
+    if (nth == 1) {
+        merge_range(0, E, parts[0], lens[0]);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t)
+            pool.emplace_back([&, t] {
+                parts[t].reserve((size_t)(bounds[t + 1] - bounds[t]) * 48);
+                merge_range(bounds[t], bounds[t + 1], parts[t], lens[t]);
+            });
+        for (auto &th : pool) th.join();
+    }
+    size_t total = 0;
+    for (const auto &v : parts) total += v.size();
+    out.nodes.resize(total);
+    size_t o = 0;
+    int e = 0;
+    for (int t = 0; t < nth; ++t) {
+        std::memcpy(out.nodes.data() + o, parts[t].data(), sizeof(int32_t) * parts[t].size());
+        for (int64_t L : lens[t]) {
+            out.off[e + 1] = out.off[e] + L;
+            ++e;
+        }
+        o += parts[t].size();
     }
 }
 

@@ -196,6 +196,21 @@ typedef struct fpc_result {
 int fpc_skeleton(fpc_ctx *ctx, const fpc_params *params, fpc_result **out);
 void fpc_result_free(fpc_result *r);
 
+/* ------------------------------------------------------------- Phase II (orientation)
+ * Host-only.  Orients the skeleton adj (host, uint8 p x p) into a CPDAG
+ * from the separating sets, given as in fpc_result (sep_level, sep_kind,
+ * sep_off, sep_nodes per pair i<j; sep_level is accepted for symmetry and
+ * not read): unshielded triples i - k - j with k outside S(i, j) become
+ * i -> k <- j (lexicographic (i, j, k) order; a triple that would reverse
+ * an arrow already placed is skipped), then rules R1-R4 are applied in
+ * row-major sweeps over the undirected edges until a sweep changes nothing
+ * (Phase II listing of Algorithm 1, Sec. 2.2.1; reused by Algorithm 2,
+ * Sec. 3.2.2).  cpdag_out (host, uint8 p x p): [a*p+b] = 1 when the edge
+ * a-b may point a -> b (undirected: both 1; a -> b: [a][b] = 1, [b][a] = 0).
+ * Returns FPC_OK or FPC_EINVAL. */
+int fpc_orient(int p, const uint8_t *adj, const int32_t *sep_level, const int8_t *sep_kind,
+               const int64_t *sep_off, const int32_t *sep_nodes, uint8_t *cpdag_out);
+
 #ifdef __cplusplus
 }
 #endif

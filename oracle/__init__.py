@@ -250,3 +250,89 @@ def sepset_of(res: dict, i: int, j: int):
     if kind == SEP_ALL_BUT:
         return [v for v in range(p) if v != i and v != j]
     return list(res["sepsets"][(i, j)])
+
+
+# ---------------------------------------------------------------- Phase II
+def orient(adj: np.ndarray, sepset) -> np.ndarray:
+    """Phase II of Algorithm 1 (reused by Algorithm 2): CPDAG marks from the
+    skeleton ``adj`` and ``sepset(i, j)`` (the separating set of a deleted
+    pair, or None).  D[a, b] = 1 when the edge a-b may point a -> b.
+
+    Unshielded triples i - k - j with k not in S(i, j) become i -> k <- j,
+    taken in lexicographic (i, j, k) order, skipping a triple that would
+    reverse an arrow already placed; then R1-R4 (Phase II listing; R4 in
+    Meek's form, the printed one being garbled) are applied in row-major
+    sweeps over the undirected edges until a sweep changes nothing.
+    Plain O(p^3)-per-sweep loops, for small graphs.
+    """
+    p = adj.shape[0]
+    A = adj.astype(bool)
+    D = A.astype(np.uint8).copy()
+
+    def directed(a, b):
+        return D[a, b] and not D[b, a]
+
+    def undirected(a, b):
+        return D[a, b] and D[b, a]
+
+    for i in range(p):
+        for j in range(i + 1, p):
+            if A[i, j]:
+                continue
+            S = sepset(i, j)
+            for k in range(p):
+                if k in (i, j) or not (A[i, k] and A[j, k]):
+                    continue
+                if S is not None and k in S:
+                    continue
+                if not directed(k, i) and not directed(k, j):
+                    D[k, i] = 0
+                    D[k, j] = 0
+    changed = True
+    while changed:
+        changed = False
+        for a in range(p):
+            for b in range(p):
+                if a == b or not undirected(a, b):
+                    continue
+                hit = False
+                for c in range(p):
+                    if c in (a, b):
+                        continue
+                    if directed(c, a) and not A[c, b]:  # R1
+                        hit = True
+                    if directed(a, c) and directed(c, b):  # R2
+                        hit = True
+                for c in range(p):  # R3
+                    for d in range(c + 1, p):
+                        if len({a, b, c, d}) < 4:
+                            continue
+                        if (undirected(a, c) and directed(c, b) and undirected(a, d) and directed(d, b)
+                                and not A[c, d]):
+                            hit = True
+                for c in range(p):  # R4
+                    for d in range(p):
+                        if len({a, b, c, d}) < 4:
+                            continue
+                        if (undirected(a, c) and not A[c, b] and directed(c, d) and directed(d, b)
+                                and A[a, d]):
+                            hit = True
+                if hit:
+                    D[b, a] = 0
+                    changed = True
+    return D
+
+
+def dag_v_structures(W: np.ndarray):
+    """Unshielded colliders i -> k <- j (i < j non-adjacent) of a DAG."""
+    A = W != 0
+    p = A.shape[0]
+    out = set()
+    for k in range(p):
+        pa = np.nonzero(A[:, k])[0]
+        for x in range(len(pa)):
+            for y in range(x + 1, len(pa)):
+                i, j = int(pa[x]), int(pa[y])
+                if not A[i, j] and not A[j, i]:
+                    out.add((min(i, j), max(i, j), k))
+    return out

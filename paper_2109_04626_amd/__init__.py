@@ -28,7 +28,7 @@ FPC_FLAG_PER_TEST_KERNEL = 1
 
 EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "fpc_quantile",
             "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton",
-            "fpc_result_free"]
+            "fpc_result_free", "fpc_orient"]
 
 
 class FastPCError(RuntimeError):
@@ -97,6 +97,8 @@ def _load():
     lib.fpc_skeleton.restype = i
     lib.fpc_result_free.argtypes = [ctypes.POINTER(fpc_result)]
     lib.fpc_result_free.restype = None
+    lib.fpc_orient.argtypes = [i, vp, vp, vp, vp, vp, vp]
+    lib.fpc_orient.restype = i
     return lib
 
 
@@ -154,6 +156,21 @@ def fpc_candidates(adj: np.ndarray):
     _check(_lib.fpc_candidates(_np_ptr(adj), p, ctypes.byref(E), ctypes.byref(N), _np_ptr(ei), _np_ptr(ej),
                                _np_ptr(off), _np_ptr(nodes)), "fpc_candidates")
     return ei, ej, off, nodes[: N.value]
+
+
+def fpc_orient(res: dict) -> np.ndarray:
+    """CPDAG marks (p x p uint8) of a fpc_skeleton result: [a, b] = 1 when
+    the edge a-b may point a -> b."""
+    p = res["p"]
+    adj = np.ascontiguousarray(res["adj"], dtype=np.uint8)
+    lev = np.ascontiguousarray(res["sep_level"], dtype=np.int32)
+    kind = np.ascontiguousarray(res["sep_kind"], dtype=np.int8)
+    off = np.ascontiguousarray(res["sep_off"], dtype=np.int64)
+    nodes = np.ascontiguousarray(res["sep_nodes"], dtype=np.int32)
+    out = np.empty((p, p), dtype=np.uint8)
+    _check(_lib.fpc_orient(p, _np_ptr(adj), _np_ptr(lev), _np_ptr(kind), _np_ptr(off),
+                           _np_ptr(nodes) if nodes.size else None, _np_ptr(out)), "fpc_orient")
+    return out
 
 
 # ------------------------------------------------------------------ device calls
@@ -337,7 +354,8 @@ def _unpack(r: fpc_result) -> dict:
     for k in range(r.n_levels):
         s = r.levels[k]
         levels.append({f: getattr(s, f) for f, _ in fpc_level_stats._fields_})
-    return dict(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets, levels=levels,
+    return dict(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets, sep_off=off, sep_nodes=nodes,
+                levels=levels,
                 total_tests=int(r.total_tests), q=float(r.q), corr_ms=float(r.corr_ms),
                 first_level_ms=float(r.first_level_ms), total_ms=float(r.total_ms),
                 corr_max_abs_err=float(r.corr_max_abs_err), p=p)

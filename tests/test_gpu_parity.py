@@ -303,3 +303,15 @@ def test_skeleton_host_input_and_determinism(fpc, ctx):
     b = fpc.fpc_skeleton(ctx, dev(X))
     assert np.array_equal(a["adj"], b["adj"]) and a["sepsets"] == b["sepsets"]
     assert [x["tests_executed"] for x in a["levels"][:1]] == [x["tests_executed"] for x in b["levels"][:1]]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_cpdag_from_gpu_skeleton_matches_oracle(fpc, ctx, seed):
+    """Phase II on the GPU run's skeleton and separating sets equals the
+    oracle's Phase II on its own run."""
+    X, sem, cfg = semdata.workload("er_p20_n1000_d3", seed)
+    C = oracle.corr(X)
+    ref = oracle.skeleton(C, cfg["n"], alpha=cfg["alpha"])
+    want = oracle.orient(ref["adj"], lambda i, j: oracle.sepset_of(ref, i, j))
+    got = fpc.fpc_skeleton(ctx, dev(X), alpha=cfg["alpha"])
+    assert np.array_equal(fpc.fpc_orient(got), want)

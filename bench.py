@@ -7,7 +7,10 @@ the first capped at max_level = 5.  One step = one whole skeleton call
 (correlation matrix, the l = p-2 level, levels 5..0 with deletion) on data
 already resident in HBM.  The headline form is the mixed one (bf16x3
 correlation on MFMA, FP32 tests, FP64 re-run near the threshold); the
-plain FP64 form is timed in the same run for comparison.
+plain FP64 form and the learned form (mixed, candidates ordered by the
+ranking MLP trained on scale-free graphs) are timed in the same run, and
+the learned form is also timed against the mixed one on a held-out
+scale-free workload (BA DAG, p = 1000, n = 10000, max_level = 3).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -25,6 +28,8 @@ if ROOT not in sys.path:
 
 WORKLOAD = "er_p1000_n10000_d4"
 SEED = 0
+BA_WORKLOAD = "ba_p1000_n10000_m2"
+BA_SEED = 2000  # a held-out seed of the ranker's evaluation set
 FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32
 FP64_PEAK_TFLOPS = 78.6    # MI355X published vector FP64
 
@@ -69,26 +74,42 @@ def main() -> int:
     torch.cuda.synchronize()
     ctx = fpc.Context(0)
 
-    def run(prec):
-        return fpc.fpc_skeleton(ctx, Xd, alpha=cfg["alpha"], max_level=cfg["max_level"], precision=prec)
+    from paper_2109_04626_amd.learned import DEFAULT_MODEL
 
-    forms = {"mixed": fpc.FPC_PREC_MIXED, "plain": fpc.FPC_PREC_FP64}
-    results = {}
-    for name, prec in forms.items():
+    model = fpc.fpc_mlp_init(ctx, np.load(DEFAULT_MODEL))
+
+    def timed(X_dev, c, prec, m=None):
+        def run():
+            return fpc.fpc_skeleton(ctx, X_dev, alpha=c["alpha"], max_level=c["max_level"], precision=prec,
+                                    order_model=m)
+
         for _ in range(args.warmup):
-            run(prec)
+            run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        outs = [run(prec) for _ in range(args.steps)]
+        outs = [run() for _ in range(args.steps)]
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        results[name] = (dt, outs)
-        print(f"[bench] {name}: {dt / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+        return time.perf_counter() - t0, outs
+
+    # plain = FP64 tests, lexicographic order; mixed = bf16x3 C + FP32 tests
+    # with FP64 recheck; learned = mixed with the MLP-ranked candidate order
+    forms = {"mixed": (fpc.FPC_PREC_MIXED, None), "plain": (fpc.FPC_PREC_FP64, None),
+             "learned": (fpc.FPC_PREC_MIXED, model)}
+    results = {}
+    for name, (prec, m) in forms.items():
+        results[name] = timed(Xd, cfg, prec, m)
+        print(f"[bench] {name}: {results[name][0] / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    # the learned order on the scale-free workload it was trained for
+    Xb, _, cfg_b = semdata.workload(BA_WORKLOAD, BA_SEED)
+    Xbd = torch.from_numpy(Xb).cuda()
+    ba = {name: timed(Xbd, cfg_b, fpc.FPC_PREC_MIXED, m) for name, m in (("mixed", None), ("learned", model))}
+    del Xbd
 
     dt, outs = results["mixed"]
     last = outs[-1]
     ref_adj = results["plain"][1][-1]["adj"]
     same = bool(np.array_equal(last["adj"], ref_adj))
+    same_learned = bool(np.array_equal(results["learned"][1][-1]["adj"], ref_adj))
     tests = sum(o["total_tests"] for o in outs)
     value = tests / dt
 
@@ -134,7 +155,20 @@ def main() -> int:
                    "form": "mixed"},
         "plain_ms_per_step": results["plain"][0] / args.steps * 1e3,
         "mixed_vs_plain_speedup": results["plain"][0] / dt,
+        "learned_ms_per_step": results["learned"][0] / args.steps * 1e3,
+        "learned_vs_plain_speedup": results["plain"][0] / results["learned"][0],
+        "learned_vs_mixed_speedup": dt / results["learned"][0],
+        "tests_per_step_learned": results["learned"][1][-1]["total_tests"],
         "skeleton_equal_mixed_plain": same,
+        "skeleton_equal_learned_plain": same_learned,
+        "scale_free": {"workload": f"{BA_WORKLOAD} seed {BA_SEED}: BA DAG m=2 p={cfg_b['p']}, n={cfg_b['n']}, "
+                                   f"alpha={cfg_b['alpha']}, max_level={cfg_b['max_level']}",
+                       "mixed_ms_per_step": ba["mixed"][0] / args.steps * 1e3,
+                       "learned_ms_per_step": ba["learned"][0] / args.steps * 1e3,
+                       "tests_mixed": ba["mixed"][1][-1]["total_tests"],
+                       "tests_learned": ba["learned"][1][-1]["total_tests"],
+                       "skeleton_equal": bool(np.array_equal(ba["mixed"][1][-1]["adj"],
+                                                             ba["learned"][1][-1]["adj"]))},
         "tests_per_step": outs[-1]["total_tests"],
         "edges": int(last["adj"].sum()) // 2,
         "level_kernel_ms_mixed": kms,

@@ -55,12 +55,15 @@ extern "C" {
 #define FPC_FORWARD 1 /* Algorithm 1 (PC-stable): l = 0 upward, early termination (2.2.1) */
 
 /* Order of the conditioning sets inside one level (fpc_params.order). */
-#define FPC_ORDER_LEX 0    /* lexicographic over the sorted candidate list                   */
-#define FPC_ORDER_SCORED 1 /* lexicographic over candidates sorted by a per-pair score       */
+#define FPC_ORDER_LEX 0     /* lexicographic over the candidate list sorted by variable id      */
+#define FPC_ORDER_LEARNED 1 /* lexicographic over the candidate list sorted by decreasing MLP
+                               score (fpc_params.order_model); reverse schedule only          */
 
 /* fpc_params.flags bits. */
 #define FPC_FLAG_PER_TEST_KERNEL 1u /* run levels l >= 2 with the per-test Cholesky kernel instead of
                                        the shared-prefix (Schur pair) kernel; same results            */
+#define FPC_FLAG_LOG_FEATURES 2u    /* record the ranking features of every candidate of every edge
+                                       deleted after the first level (fpc_result.log_*)              */
 
 /* Kinds of recorded separating sets (fpc_result.sep_kind). */
 #define FPC_SEP_NONE 0    /* edge kept                                                  */
@@ -149,8 +152,8 @@ typedef struct fpc_params {
                              error bound) are re-run in FP64; <= 0 selects 1e-3             */
     int32_t schedule;     /* FPC_REVERSE or FPC_FORWARD                                      */
     int32_t order;        /* FPC_ORDER_LEX or FPC_ORDER_SCORED                               */
-    const float *score;   /* FPC_ORDER_SCORED: device, p x p FP32, score[i*p + k] ranks
-                             candidate k for edges at i (larger = earlier); NULL otherwise  */
+    const void *order_model; /* FPC_ORDER_LEARNED: device buffer of fpc_mlp_bytes() bytes
+                                (fpc_mlp_init); NULL otherwise                                */
     int64_t max_tests;    /* 0 = unlimited, else FPC_EBUDGET past this many tests            */
     double q_override;    /* NaN: q = Phi^{-1}(1 - alpha/2); else this threshold            */
     uint32_t flags;       /* FPC_FLAG_* bits, 0 for the defaults                             */
@@ -188,6 +191,16 @@ typedef struct fpc_result {
     double first_level_ms;    /* l = p-2 level (reverse schedule)                        */
     double total_ms;          /* whole call, data resident on the device                 */
     double corr_max_abs_err;  /* mixed: max |C_bf16x3 - C_fp64|, else 0                  */
+    /* FPC_FLAG_LOG_FEATURES: one row per candidate of each edge deleted
+     * after the first level (features at that level, in the order the
+     * level used) */
+    int64_t log_rows;
+    float *log_x;             /* log_rows x 3: the ranking features                      */
+    uint8_t *log_y;           /* 1 if the candidate is in the recorded separating set    */
+    int32_t *log_group;       /* serial number of the edge the row belongs to: deleted   */
+                              /* edges in level order, pair order within a level (one    */
+                              /* deleted with no candidates has a serial and no rows)    */
+    int32_t *log_level;       /* level of the deletion                                   */
 } fpc_result;
 
 /* Errors: FPC_EINVAL, FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET,
@@ -195,6 +208,36 @@ typedef struct fpc_result {
  * freed with fpc_result_free; on error *out is NULL. */
 int fpc_skeleton(fpc_ctx *ctx, const fpc_params *params, fpc_result **out);
 void fpc_result_free(fpc_result *r);
+
+/* ------------------------------------------------------------- candidate-ranking MLP
+ * Orders each edge's candidate list for FPC_ORDER_LEARNED.  Features of a
+ * candidate k of the pair (i, j): max(|C_ik|, |C_jk|), max(|R_ik|, |R_jk|)
+ * with R the first-level partial correlations, and deg(k)/(p-1) in the
+ * current graph.  Network 3 -> 64 -> 64 -> 1 with ReLU; bf16 weights in the
+ * passes, FP32 accumulation, FP32 master weights and Adam moments.
+ * The model is an opaque device buffer of fpc_mlp_bytes() bytes; its
+ * parameters are fpc_mlp_params() floats ordered W1[3][64], b1[64],
+ * W2[64][64], b2[64], W3[64], b3 (row-major, input index first).  X is a
+ * device n x 3 FP32 array, y a device n FP32 array of 0/1 labels.  Not part
+ * of the paper: the stable schedule makes the skeleton independent of this
+ * order, which only changes how soon a separating set is found. */
+size_t fpc_mlp_bytes(void);
+int fpc_mlp_params(void);
+/* model := params (host, FP32) with zero Adam state. */
+int fpc_mlp_init(fpc_ctx *ctx, void *model, const float *params);
+/* params_out (host) := the FP32 master parameters. */
+int fpc_mlp_get(fpc_ctx *ctx, const void *model, float *params_out);
+/* logits_out (device, n FP32) := network output; n = 0 is a no-op (X and
+ * logits_out may then be NULL). */
+int fpc_mlp_forward(fpc_ctx *ctx, const float *X, int64_t n, const void *model, float *logits_out);
+/* grad_out (device, fpc_mlp_params() + 1 FP32) := gradient of the mean
+ * binary cross-entropy with logits over the n rows (n > 0, else
+ * FPC_EINVAL), then the loss. */
+int fpc_mlp_grad(fpc_ctx *ctx, const float *X, const float *y, int64_t n, const void *model, float *grad_out);
+/* One Adam step (beta 0.9 / 0.999) on the mean loss of the n rows;
+ * *loss_out (host, may be NULL) receives the loss before the step. */
+int fpc_mlp_train_step(fpc_ctx *ctx, const float *X, const float *y, int64_t n, void *model, float lr,
+                       float *loss_out);
 
 /* ------------------------------------------------------------- Phase II (orientation)
  * Host-only.  Orients the skeleton adj (host, uint8 p x p) into a CPDAG

@@ -336,3 +336,58 @@ def dag_v_structures(W: np.ndarray):
                 if not A[i, j] and not A[j, i]:
                     out.add((min(i, j), max(i, j), k))
     return out
+
+
+# ---------------------------------------------------------------- ranking MLP reference
+MLP_IN, MLP_H = 3, 64
+
+
+def mlp_unpack(params):
+    """Split the flat parameter vector (W1[3][64], b1, W2[64][64], b2, W3, b3)."""
+    params = np.asarray(params, dtype=np.float64)
+    o = 0
+    W1 = params[o:o + MLP_IN * MLP_H].reshape(MLP_IN, MLP_H); o += MLP_IN * MLP_H
+    b1 = params[o:o + MLP_H]; o += MLP_H
+    W2 = params[o:o + MLP_H * MLP_H].reshape(MLP_H, MLP_H); o += MLP_H * MLP_H
+    b2 = params[o:o + MLP_H]; o += MLP_H
+    W3 = params[o:o + MLP_H]; o += MLP_H
+    b3 = params[o]
+    return W1, b1, W2, b2, W3, b3
+
+
+def mlp_forward(params, X):
+    """Logits of the 3 -> 64 -> 64 -> 1 ReLU network, FP64."""
+    W1, b1, W2, b2, W3, b3 = mlp_unpack(params)
+    h1 = np.maximum(np.asarray(X, np.float64) @ W1 + b1, 0.0)
+    h2 = np.maximum(h1 @ W2 + b2, 0.0)
+    return h2 @ W3 + b3
+
+
+def mlp_loss(params, X, y):
+    """Mean binary cross-entropy with logits."""
+    z = mlp_forward(params, X)
+    y = np.asarray(y, np.float64)
+    return float(np.mean(np.maximum(z, 0) + np.log1p(np.exp(-np.abs(z))) - y * z))
+
+
+def mlp_grad(params, X, y):
+    """Gradient of mlp_loss by the chain rule (backpropagation), FP64."""
+    W1, b1, W2, b2, W3, b3 = mlp_unpack(params)
+    X = np.asarray(X, np.float64)
+    y = np.asarray(y, np.float64)
+    N = X.shape[0]
+    a1 = X @ W1 + b1
+    h1 = np.maximum(a1, 0.0)
+    a2 = h1 @ W2 + b2
+    h2 = np.maximum(a2, 0.0)
+    z = h2 @ W3 + b3
+    dz = (1.0 / (1.0 + np.exp(-z)) - y) / N
+    dW3 = h2.T @ dz
+    db3 = dz.sum()
+    da2 = np.outer(dz, W3) * (a2 > 0)
+    dW2 = h1.T @ da2
+    db2 = da2.sum(0)
+    da1 = (da2 @ W2.T) * (a1 > 0)
+    dW1 = X.T @ da1
+    db1 = da1.sum(0)
+    return np.concatenate([dW1.ravel(), db1, dW2.ravel(), db2, dW3, [db3]])

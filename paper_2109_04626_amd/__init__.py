@@ -22,13 +22,15 @@ FPC_F64, FPC_F32 = 0, 1
 FPC_CORR_FP64, FPC_CORR_BF16X3 = 0, 1
 FPC_PREC_FP64, FPC_PREC_MIXED = 0, 1
 FPC_REVERSE, FPC_FORWARD = 0, 1
-FPC_ORDER_LEX, FPC_ORDER_SCORED = 0, 1
+FPC_ORDER_LEX, FPC_ORDER_LEARNED = 0, 1
 FPC_SEP_NONE, FPC_SEP_LIST, FPC_SEP_ALL_BUT = 0, 1, 2
 FPC_FLAG_PER_TEST_KERNEL = 1
+FPC_FLAG_LOG_FEATURES = 2
 
 EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "fpc_quantile",
             "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton",
-            "fpc_result_free", "fpc_orient"]
+            "fpc_result_free", "fpc_orient", "fpc_mlp_bytes", "fpc_mlp_params", "fpc_mlp_init", "fpc_mlp_get",
+            "fpc_mlp_forward", "fpc_mlp_grad", "fpc_mlp_train_step"]
 
 
 class FastPCError(RuntimeError):
@@ -46,7 +48,7 @@ class fpc_params(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("max_level", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("recheck_margin", ctypes.c_double),
                 ("schedule", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("score", ctypes.c_void_p), ("max_tests", ctypes.c_int64),
+                ("order_model", ctypes.c_void_p), ("max_tests", ctypes.c_int64),
                 ("q_override", ctypes.c_double), ("flags", ctypes.c_uint32)]
 
 
@@ -67,10 +69,17 @@ class fpc_result(ctypes.Structure):
                 ("levels", ctypes.POINTER(fpc_level_stats)), ("total_tests", ctypes.c_int64),
                 ("q", ctypes.c_double), ("corr_ms", ctypes.c_double),
                 ("first_level_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
-                ("corr_max_abs_err", ctypes.c_double)]
+                ("corr_max_abs_err", ctypes.c_double), ("log_rows", ctypes.c_int64),
+                ("log_x", ctypes.POINTER(ctypes.c_float)), ("log_y", ctypes.POINTER(ctypes.c_uint8)),
+                ("log_group", ctypes.POINTER(ctypes.c_int32)), ("log_level", ctypes.POINTER(ctypes.c_int32))]
 
 
 def _load():
+    # torch first: its HIP runtime (soname libamdhip64.so.7) is then the one
+    # the library binds to.  Loaded the other way round, torch would bring a
+    # second runtime into the process and the library's would see no device.
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2109_04626_amd.build")
     lib = ctypes.CDLL(LIB_PATH)
@@ -99,6 +108,20 @@ def _load():
     lib.fpc_result_free.restype = None
     lib.fpc_orient.argtypes = [i, vp, vp, vp, vp, vp, vp]
     lib.fpc_orient.restype = i
+    lib.fpc_mlp_bytes.argtypes = []
+    lib.fpc_mlp_bytes.restype = ctypes.c_size_t
+    lib.fpc_mlp_params.argtypes = []
+    lib.fpc_mlp_params.restype = i
+    lib.fpc_mlp_init.argtypes = [vp, vp, vp]
+    lib.fpc_mlp_init.restype = i
+    lib.fpc_mlp_get.argtypes = [vp, vp, vp]
+    lib.fpc_mlp_get.restype = i
+    lib.fpc_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    lib.fpc_mlp_forward.restype = i
+    lib.fpc_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
+    lib.fpc_mlp_grad.restype = i
+    lib.fpc_mlp_train_step.argtypes = [vp, vp, vp, i64, vp, ctypes.c_float, vp]
+    lib.fpc_mlp_train_step.restype = i
     return lib
 
 
@@ -268,9 +291,64 @@ def fpc_ci_batch(ctx: Context, C, n: int, B, q: float):
     return z, ind
 
 
+def fpc_mlp_bytes() -> int:
+    return int(_lib.fpc_mlp_bytes())
+
+
+def fpc_mlp_params() -> int:
+    return int(_lib.fpc_mlp_params())
+
+
+def fpc_mlp_init(ctx: Context, params: np.ndarray, model=None):
+    """A device model buffer (torch uint8 tensor) holding ``params`` (FP32)."""
+    import torch
+
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    assert params.size == fpc_mlp_params()
+    if model is None:
+        model = torch.empty(fpc_mlp_bytes(), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+    _check(_lib.fpc_mlp_init(ctx.handle, _t_ptr(model), _np_ptr(params)), "fpc_mlp_init")
+    return model
+
+
+def fpc_mlp_get(ctx: Context, model) -> np.ndarray:
+    out = np.empty(fpc_mlp_params(), dtype=np.float32)
+    _check(_lib.fpc_mlp_get(ctx.handle, _t_ptr(model), _np_ptr(out)), "fpc_mlp_get")
+    return out
+
+
+def fpc_mlp_forward(ctx: Context, X, model):
+    import torch
+
+    X = X.contiguous()
+    out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(_lib.fpc_mlp_forward(ctx.handle, _t_ptr(X), X.shape[0], _t_ptr(model), _t_ptr(out)), "fpc_mlp_forward")
+    return out
+
+
+def fpc_mlp_grad(ctx: Context, X, y, model):
+    """(gradient of the mean BCE loss (FP32 vector), loss)."""
+    import torch
+
+    X, y = X.contiguous(), y.contiguous()
+    out = torch.empty(fpc_mlp_params() + 1, dtype=torch.float32, device=X.device)
+    _check(_lib.fpc_mlp_grad(ctx.handle, _t_ptr(X), _t_ptr(y), X.shape[0], _t_ptr(model), _t_ptr(out)),
+           "fpc_mlp_grad")
+    g = out.cpu().numpy()
+    return g[:-1], float(g[-1])
+
+
+def fpc_mlp_train_step(ctx: Context, X, y, model, lr: float) -> float:
+    X, y = X.contiguous(), y.contiguous()
+    loss = ctypes.c_float()
+    _check(_lib.fpc_mlp_train_step(ctx.handle, _t_ptr(X), _t_ptr(y), X.shape[0], _t_ptr(model), float(lr),
+                                   ctypes.byref(loss)), "fpc_mlp_train_step")
+    return float(loss.value)
+
+
 def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, precision: int = FPC_PREC_FP64,
                  recheck_margin: float = 1e-3, schedule: int = FPC_REVERSE, max_tests: int = 0,
-                 q_override: float = float("nan"), flags: int = 0) -> dict:
+                 q_override: float = float("nan"), flags: int = 0, order_model=None) -> dict:
     """Skeleton and separating sets of the data X (torch tensor on the
     device, or a host numpy array), n x p row-major."""
     prm = fpc_params()
@@ -295,8 +373,8 @@ def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, prec
     prm.precision = int(precision)
     prm.recheck_margin = float(recheck_margin)
     prm.schedule = int(schedule)
-    prm.order = FPC_ORDER_LEX
-    prm.score = None
+    prm.order = FPC_ORDER_LEX if order_model is None else FPC_ORDER_LEARNED
+    prm.order_model = None if order_model is None else _t_ptr(order_model).value
     prm.max_tests = int(max_tests)
     prm.q_override = float(q_override)
     prm.flags = int(flags)
@@ -354,8 +432,15 @@ def _unpack(r: fpc_result) -> dict:
     for k in range(r.n_levels):
         s = r.levels[k]
         levels.append({f: getattr(s, f) for f, _ in fpc_level_stats._fields_})
+    nlog = int(r.log_rows)
+    log = None
+    if nlog:
+        log = dict(x=np.ctypeslib.as_array(r.log_x, shape=(nlog * 3,)).reshape(nlog, 3).copy(),
+                   y=np.ctypeslib.as_array(r.log_y, shape=(nlog,)).copy(),
+                   group=np.ctypeslib.as_array(r.log_group, shape=(nlog,)).copy(),
+                   level=np.ctypeslib.as_array(r.log_level, shape=(nlog,)).copy())
     return dict(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets, sep_off=off, sep_nodes=nodes,
-                levels=levels,
+                levels=levels, log=log,
                 total_tests=int(r.total_tests), q=float(r.q), corr_ms=float(r.corr_ms),
                 first_level_ms=float(r.first_level_ms), total_ms=float(r.total_ms),
                 corr_max_abs_err=float(r.corr_max_abs_err), p=p)

@@ -77,7 +77,12 @@ struct fpc_ctx {
     fpc::DevBuf counters;         // uint64 counters (tests executed, queue length, ...)
     fpc::DevBuf queue;            // recheck queue (edge, rank)
     fpc::DevBuf dellist;          // compacted deletions
-    fpc::DevBuf batch_tmp;        // fpc_ci_batch scratch
+    fpc::DevBuf batch_tmp;        // fpc_ci_batch / MLP gradient partials
+    fpc::DevBuf mlp_grad;         // MLP gradient + loss of one training step
+    fpc::DevBuf rfirst;           // first-level partial correlations (learned order)
+    fpc::DevBuf feat;             // per-position features and scores
+    fpc::DevBuf cand2;            // reordered candidate lists
+    fpc::DevBuf degs;             // node degrees of the current graph
 
     fpc::HostBuf h_stage;         // pinned staging for uploads
     fpc::HostBuf h_back;          // pinned staging for downloads
@@ -132,6 +137,16 @@ int level_compact(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t
                   int64_t *n_out);
 int ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, const int32_t *B,
              int64_t b, double q, double *z_out, uint8_t *indep_out);
+
+// ---- learned order (order.hip, mlp.hip)
+int level_features(fpc_ctx *ctx, const EdgeRec *edges, int64_t n_edges, const int32_t *cand, int64_t n_pos,
+                   const double *C, const double *R, const int32_t *deg, int p, float *X);
+int level_reorder(fpc_ctx *ctx, const EdgeRec *edges, int64_t n_edges, const int32_t *cand_in, const float *score,
+                  int32_t *cand_out);
+int mlp_forward(fpc_ctx *ctx, const float *X, int64_t N, const void *model, float *out);
+int mlp_grad(fpc_ctx *ctx, const float *X, const float *Y, int64_t N, const void *model, float *grad_out);
+size_t mlp_model_bytes();
+int mlp_params();
 
 // ---- host graph logic (graph.cpp)
 // Candidate sets of every edge of the graph (row-major i<j order).

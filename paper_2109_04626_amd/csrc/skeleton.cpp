@@ -228,7 +228,8 @@ extern "C" int fpc_destroy(fpc_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     DevBuf *bufs[] = {&c->binom, &c->x_copy, &c->colstat, &c->c64, &c->c32, &c->zsplit, &c->inv_work,
                       &c->flag, &c->cand, &c->edges, &c->blockoff, &c->minhit, &c->counters,
-                      &c->queue, &c->dellist, &c->batch_tmp};
+                      &c->queue, &c->dellist, &c->batch_tmp, &c->mlp_grad, &c->rfirst, &c->feat,
+                      &c->cand2, &c->degs};
     for (DevBuf *b : bufs) b->release();
     c->h_stage.release();
     c->h_back.release();
@@ -250,6 +251,10 @@ extern "C" void fpc_result_free(fpc_result *r)
     std::free(r->sep_off);
     std::free(r->sep_nodes);
     std::free(r->levels);
+    std::free(r->log_x);
+    std::free(r->log_y);
+    std::free(r->log_group);
+    std::free(r->log_level);
     std::free(r);
 }
 
@@ -271,6 +276,12 @@ struct Run {
     std::vector<fpc_level_stats> levels;
     int64_t spent_possible = 0;
     int64_t total_exec = 0;
+    bool learned = false, logging = false;
+    const double *Rfirst = nullptr;  // first-level partial correlations (device)
+    std::vector<float> log_x;
+    std::vector<uint8_t> log_y;
+    std::vector<int32_t> log_group, log_level;
+    int32_t log_serial = 0;
 };
 
 // Runs one level (l >= 0) on the frozen graph with precomputed candidate
@@ -332,6 +343,39 @@ int run_level(Run &R, int l, const CandSets &cs, fpc_level_stats &st)
     if (!cand.empty())
         FPC_HIP(hipMemcpyAsync(ctx->cand.ptr, ctx->h_stage.as<char>() + sizeof(EdgeRec) * E,
                                sizeof(int32_t) * cand.size(), hipMemcpyHostToDevice, s));
+    // learned order: features, MLP scores, per-edge reorder of the lists
+    // (at l = 0 each edge has one subset, so the order cannot matter)
+    std::vector<float> hfeat;
+    const int32_t *d_cand = ctx->cand.as<int32_t>();
+    const bool reorder = R.learned && l >= 1;
+    if (reorder || R.logging) {
+        const int64_t T = (int64_t)cand.size();
+        std::vector<int32_t> deg(R.p, 0);  // degrees in the current graph, from its edge list
+        for (size_t e = 0; e < cs.ei.size(); ++e) {
+            ++deg[cs.ei[e]];
+            ++deg[cs.ej[e]];
+        }
+        if ((rc = ctx->degs.ensure(sizeof(int32_t) * R.p))) return rc;
+        if ((rc = ctx->feat.ensure(sizeof(float) * 4 * (size_t)(T + 1)))) return rc;
+        if ((rc = ctx->cand2.ensure(sizeof(int32_t) * (size_t)(T + 1)))) return rc;
+        FPC_HIP(hipMemcpyAsync(ctx->degs.ptr, deg.data(), sizeof(int32_t) * R.p, hipMemcpyHostToDevice, s));
+        float *X = ctx->feat.as<float>(), *score = X + 3 * T;
+        if ((rc = level_features(ctx, ctx->edges.as<EdgeRec>(), E, d_cand, T, R.C64, R.Rfirst,
+                                 ctx->degs.as<int32_t>(), R.p, X)))
+            return rc;
+        if (reorder) {
+            if ((rc = mlp_forward(ctx, X, T, R.P->order_model, score))) return rc;
+            if ((rc = level_reorder(ctx, ctx->edges.as<EdgeRec>(), E, d_cand, score, ctx->cand2.as<int32_t>())))
+                return rc;
+            d_cand = ctx->cand2.as<int32_t>();
+        }
+        if (R.logging) {
+            hfeat.resize(3 * (size_t)T);
+            // features follow the original order; the reorder maps them
+            FPC_HIP(hipMemcpyAsync(hfeat.data(), X, sizeof(float) * 3 * T, hipMemcpyDeviceToHost, s));
+            FPC_HIP(hipStreamSynchronize(s));
+        }
+    }
     bool fp32 = R.mixed && l <= kMaxTemplL;
     if (fp32 && (rc = ctx->queue.ensure(sizeof(int64_t) * 2 * kQueueCap))) return rc;
 retry:
@@ -343,7 +387,7 @@ retry:
     Lv.max_m = sel_max_m;
     Lv.n_edges = E;
     Lv.edges = ctx->edges.as<EdgeRec>();
-    Lv.cand = ctx->cand.as<int32_t>();
+    Lv.cand = d_cand;
     Lv.C = fp32 ? (const void *)R.C32 : (const void *)R.C64;
     Lv.C64 = R.C64;
     Lv.p = R.p;
@@ -358,6 +402,11 @@ retry:
     Lv.queue_cap = fp32 ? kQueueCap : 0;
     LevelTiming tm;
     if ((rc = level_tests(ctx, Lv, ntests, &tm))) return rc;
+    // the host decodes separating sets against the lists the level used
+    // (through the pinned stage: the upload that read it precedes this
+    // copy on the stream)
+    if (reorder && !cand.empty())
+        FPC_HIP(hipMemcpyAsync(ctx->h_stage.ptr, d_cand, sizeof(int32_t) * cand.size(), hipMemcpyDeviceToHost, s));
     st.kernel_ms = tm.all_ms;
     st.test_kernel_ms = tm.test_ms;
     st.test_launches = tm.test_launches;
@@ -375,6 +424,7 @@ retry:
         fp32 = false;
         goto retry;
     }
+    if (reorder && !cand.empty()) std::memcpy(cand.data(), ctx->h_stage.ptr, sizeof(int32_t) * cand.size());
 
     // sepsets and level-end deletion (stable: all of D at once)
     std::vector<std::pair<int64_t, int64_t>> dl(ndel);
@@ -391,6 +441,20 @@ retry:
         R.sep.lists.emplace_back(pr, (int64_t)o);
         for (int t = 0; t < l; ++t) R.sep.nodes.push_back(cand[er.cand_off + pos[t]]);
         std::sort(R.sep.nodes.begin() + o, R.sep.nodes.end());
+        if (R.logging) {
+            // features were computed over the list sorted by id (the cs order)
+            const int32_t *orig = cs.nodes.data() + cs.off[sel[d.first]];
+            const int32_t *S = R.sep.nodes.data() + o;
+            for (int a = 0; a < er.m; ++a) {
+                const int k = orig[a];
+                const bool in = std::binary_search(S, S + l, k);
+                for (int f = 0; f < 3; ++f) R.log_x.push_back(hfeat[3 * ((size_t)er.cand_off + a) + f]);
+                R.log_y.push_back(in ? 1 : 0);
+                R.log_group.push_back(R.log_serial);
+                R.log_level.push_back(l);
+            }
+            ++R.log_serial;
+        }
     }
     for (const auto &d : dl) {
         const EdgeRec &er = recs[d.first];
@@ -408,7 +472,8 @@ int validate(const fpc_params *P)
     if (P->x_dtype != FPC_F64 && P->x_dtype != FPC_F32) return FPC_EINVAL;
     if (P->precision != FPC_PREC_FP64 && P->precision != FPC_PREC_MIXED) return FPC_EINVAL;
     if (P->schedule != FPC_REVERSE && P->schedule != FPC_FORWARD) return FPC_EINVAL;
-    if (P->order != FPC_ORDER_LEX) return FPC_EINVAL;
+    if (P->order != FPC_ORDER_LEX && P->order != FPC_ORDER_LEARNED) return FPC_EINVAL;
+    if (P->order == FPC_ORDER_LEARNED && (!P->order_model || P->schedule != FPC_REVERSE)) return FPC_EINVAL;
     if (std::isnan(P->q_override) && !(P->alpha > 0.0 && P->alpha < 1.0)) return FPC_EINVAL;
     if (!std::isnan(P->q_override) && !(P->q_override >= 0.0)) return FPC_EINVAL;
     if (P->max_tests < 0) return FPC_EINVAL;
@@ -429,6 +494,8 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
     R.n = P->n;
     R.q = std::isnan(P->q_override) ? normal_quantile_upper(P->alpha) : P->q_override;
     R.mixed = P->precision == FPC_PREC_MIXED;
+    R.learned = P->order == FPC_ORDER_LEARNED;
+    R.logging = (P->flags & FPC_FLAG_LOG_FEATURES) != 0 && P->schedule == FPC_REVERSE;
     const int p = P->p, n = P->n;
     const size_t pp = (size_t)p * p;
     hipStream_t s = ctx->stream;
@@ -471,7 +538,13 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
         if ((rc = ctx->dellist.ensure(pp))) return rc;
         uint8_t *d_ind = ctx->dellist.as<uint8_t>();
         FPC_HIP(hipEventRecord(ctx->ev0, s));
-        if ((rc = first_level(ctx, R.C64, p, n, R.q, nullptr, d_ind, nullptr))) return rc;
+        double *d_r = nullptr;
+        if (R.learned || R.logging) {
+            if ((rc = ctx->rfirst.ensure(sizeof(double) * pp))) return rc;
+            d_r = ctx->rfirst.as<double>();
+            R.Rfirst = d_r;
+        }
+        if ((rc = first_level(ctx, R.C64, p, n, R.q, d_r, d_ind, nullptr))) return rc;
         FPC_HIP(hipEventRecord(ctx->ev1, s));
         std::vector<uint8_t> ind(pp);
         FPC_HIP(hipMemcpyAsync(ind.data(), d_ind, pp, hipMemcpyDeviceToHost, s));
@@ -563,6 +636,21 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
     res->corr_ms = corr_ms;
     res->first_level_ms = first_ms;
     res->corr_max_abs_err = R.c_err;
+    res->log_rows = (int64_t)R.log_y.size();
+    if (res->log_rows) {
+        res->log_x = (float *)std::malloc(sizeof(float) * R.log_x.size());
+        res->log_y = (uint8_t *)std::malloc(R.log_y.size());
+        res->log_group = (int32_t *)std::malloc(sizeof(int32_t) * R.log_group.size());
+        res->log_level = (int32_t *)std::malloc(sizeof(int32_t) * R.log_level.size());
+        if (!res->log_x || !res->log_y || !res->log_group || !res->log_level) {
+            fpc_result_free(res);
+            return FPC_ENOMEM;
+        }
+        std::memcpy(res->log_x, R.log_x.data(), sizeof(float) * R.log_x.size());
+        std::memcpy(res->log_y, R.log_y.data(), R.log_y.size());
+        std::memcpy(res->log_group, R.log_group.data(), sizeof(int32_t) * R.log_group.size());
+        std::memcpy(res->log_level, R.log_level.data(), sizeof(int32_t) * R.log_level.size());
+    }
     res->total_ms = now_ms() - t_start;
     *out = res;
     return FPC_OK;

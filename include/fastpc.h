@@ -64,6 +64,9 @@ extern "C" {
                                        the shared-prefix (Schur pair) kernel; same results            */
 #define FPC_FLAG_LOG_FEATURES 2u    /* record the ranking features of every candidate of every edge
                                        deleted after the first level (fpc_result.log_*)              */
+#define FPC_FLAG_GRAPH 4u           /* capture each level's launches (window plans, persistent test
+                                       kernels, FP64 rechecks) in one HIP graph and launch it once;
+                                       same results, per-launch timings not reported separately     */
 
 /* Kinds of recorded separating sets (fpc_result.sep_kind). */
 #define FPC_SEP_NONE 0    /* edge kept                                                  */

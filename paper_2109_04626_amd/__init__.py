@@ -26,6 +26,7 @@ FPC_ORDER_LEX, FPC_ORDER_LEARNED = 0, 1
 FPC_SEP_NONE, FPC_SEP_LIST, FPC_SEP_ALL_BUT = 0, 1, 2
 FPC_FLAG_PER_TEST_KERNEL = 1
 FPC_FLAG_LOG_FEATURES = 2
+FPC_FLAG_GRAPH = 4
 
 EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "fpc_quantile",
             "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton",

@@ -161,6 +161,16 @@ struct Thresholds {
     double rb_hi;   // mixed: tanh((q + band_z) / sqrt_nu)
 };
 
+// Per-instance parameters of a level: the matrices, their row stride and
+// the thresholds.  Every edge names its instance, so one launch can serve
+// several independent problems.
+struct InstRec {
+    const void *C;       // matrix of the test precision
+    const double *C64;   // FP64 matrix (recheck, wide levels)
+    int64_t ld;          // row stride: the instance's p
+    Thresholds th;
+};
+
 // FP64 decision identical in form to the reference rule z <= q.
 __device__ __forceinline__ bool decide64(double r, bool ok, const Thresholds &th)
 {
@@ -267,9 +277,10 @@ __device__ __forceinline__ bool walk64(int *c, int m, int lane, int *my)
 struct LevelArgs {
     const EdgeRec *edges;
     const int32_t *cand;
-    const void *C;
-    const double *C64;
-    const int64_t *blockoff;  // n_edges + 1 prefix of workgroups per edge
+    const InstRec *inst;      // per-instance matrices and thresholds
+    const int64_t *blockoff;  // n_edges + 1 prefix of work items per edge (this window)
+    const int64_t *n_items;   // work items of this window (written on the device)
+    unsigned long long *item_ctr;  // next work item (zeroed with the window's plan)
     const int64_t *binom;
     uint64_t *minhit;
     unsigned long long *counters;
@@ -277,11 +288,45 @@ struct LevelArgs {
     int64_t queue_cap;
     int64_t n_edges;
     int64_t win_lo, win_hi;
-    int p;
     int ranks_per_block;
     int max_m;  // largest candidate set of the level
-    Thresholds th;
 };
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Persistent workgroups: each takes work items (a run of consecutive ranks
+// of one edge) from the window's counter until none is left.  Item bodies
+// may return early only uniformly over the workgroup or after their last
+// block-wide barrier; the barrier after each item protects the LDS tile.
+template <class F>
+__device__ __forceinline__ void for_each_item(const LevelArgs &A, F &&body)
+{
+    __shared__ int64_t next_item;
+    const int64_t total = *A.n_items;
+    for (;;) {
+        if (threadIdx.x == 0) next_item = (int64_t)atomicAdd(A.item_ctr, 1ull);
+        __syncthreads();
+        const int64_t blk = uniform_i64(next_item);
+        if (blk >= total) return;  // uniform
+        body(blk);
+        __syncthreads();
+    }
+}
+
+// Persistent grid: as many workgroups as fit on the device at once, and no
+// more than the window can possibly use.
+unsigned resident_grid(const void *fn, int threads, size_t shm, int64_t ub, int cus)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, shm) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ub, (int64_t)per_cu * cus));
+}
 
 __device__ __forceinline__ int64_t find_edge(const int64_t *__restrict__ off, int64_t n, int64_t b)
 {
@@ -314,10 +359,8 @@ __device__ void stage_tile(const T *__restrict__ C, int p, const int32_t *__rest
 
 // ------------------------------------------------------------------ level kernel
 template <typename T, int L, bool TILE>
-__global__ __launch_bounds__(256) void level_kernel(LevelArgs A)
+__device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsigned char *smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t blk = blockIdx.x;
     const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = E.m;
@@ -328,17 +371,20 @@ __global__ __launch_bounds__(256) void level_kernel(LevelArgs A)
     if (threadIdx.x == 0) skip = load_minhit(&A.minhit[e]) < (uint64_t)r0;
     __syncthreads();
     if (skip) return;  // uniform
-    const T *C = static_cast<const T *>(A.C);
+    const InstRec &I = A.inst[E.inst];
+    const T *C = static_cast<const T *>(I.C);
+    const int p = (int)I.ld;
+    const Thresholds th = I.th;
     const int32_t *cand = A.cand + E.cand_off;
 
     PackedTile<T> tile{};
-    GlobalRows<T> glob{C, A.p, cand, E.i, E.j};
+    GlobalRows<T> glob{C, p, cand, E.i, E.j};
     if constexpr (TILE) {
         T *tri = reinterpret_cast<T *>(smem);
         const int ntri = m * (m - 1) / 2;
         T *ci = tri + ntri, *cj = ci + m;
-        stage_tile<T>(C, A.p, cand, m, E.i, E.j, tri, ci, cj);
-        tile = PackedTile<T>{tri, ci, cj, C[(size_t)E.i * A.p + E.j], m};
+        stage_tile<T>(C, p, cand, m, E.i, E.j, tri, ci, cj);
+        tile = PackedTile<T>{tri, ci, cj, C[(size_t)E.i * p + E.j], m};
         __syncthreads();
     }
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -360,8 +406,8 @@ __global__ __launch_bounds__(256) void level_kernel(LevelArgs A)
             if constexpr (TILE) pcor_reg<T, L>(tile, my, r, dmin, ok);
             else pcor_reg<T, L>(glob, my, r, dmin, ok);
             int dec;
-            if constexpr (sizeof(T) == 8) dec = decide64((double)r, ok, A.th) ? DEC_INDEP : DEC_DEP;
-            else dec = decide32<L>((float)r, (float)dmin, ok, A.th);
+            if constexpr (sizeof(T) == 8) dec = decide64((double)r, ok, th) ? DEC_INDEP : DEC_DEP;
+            else dec = decide32<L>((float)r, (float)dmin, ok, th);
             const uint64_t nvalid = (uint64_t)min((int64_t)64, whi - base);
             executed += nvalid;
             if constexpr (sizeof(T) == 4) {
@@ -391,6 +437,13 @@ __global__ __launch_bounds__(256) void level_kernel(LevelArgs A)
     if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
 }
 
+template <typename T, int L, bool TILE>
+__global__ __launch_bounds__(256) void level_kernel(LevelArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    for_each_item(A, [&](int64_t blk) { level_item<T, L, TILE>(A, blk, smem); });
+}
+
 // FP64 re-run of queued FP32 tests (rank below the edge's current minhit).
 template <int L>
 __global__ __launch_bounds__(256) void recheck_kernel(LevelArgs A)
@@ -407,12 +460,13 @@ __global__ __launch_bounds__(256) void recheck_kernel(LevelArgs A)
         const EdgeRec E = A.edges[e];
         int k[L > 0 ? L : 1];
         if constexpr (L > 0) unrank<L>(R, E.m, A.binom, k);
-        GlobalRows<double> g{A.C64, A.p, A.cand + E.cand_off, E.i, E.j};
+        const InstRec &I = A.inst[E.inst];
+        GlobalRows<double> g{I.C64, (int)I.ld, A.cand + E.cand_off, E.i, E.j};
         double r, dmin;
         bool ok;
         pcor_reg<double, L>(g, k, r, dmin, ok);
         ++done;
-        if (decide64(r, ok, A.th)) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
+        if (decide64(r, ok, I.th)) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
     }
     if (done) atomicAdd(&A.counters[2], done);
 }
@@ -478,13 +532,11 @@ __device__ __forceinline__ int decide32r(float r, float dmin, bool ok, float rlo
 }
 
 template <typename T, int QL>
-__global__ __launch_bounds__(256) void pair_kernel(LevelArgs A)
+__device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsigned char *smem)
 {
     using Lay = PairLayout<T, QL>;
     constexpr int L = QL + 2;
     constexpr int QLL = QL > 0 ? QL : 1;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t blk = blockIdx.x;
     const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = E.m;
@@ -495,13 +547,16 @@ __global__ __launch_bounds__(256) void pair_kernel(LevelArgs A)
     if (threadIdx.x == 0) skip = load_minhit(&A.minhit[e]) < (uint64_t)r0;
     __syncthreads();
     if (skip) return;  // uniform
-    const T *C = static_cast<const T *>(A.C);
+    const InstRec &I = A.inst[E.inst];
+    const T *C = static_cast<const T *>(I.C);
+    const int p = (int)I.ld;
+    const Thresholds th = I.th;
     const int32_t *cand = A.cand + E.cand_off;
     T *tri = reinterpret_cast<T *>(smem);
     const int ntri = m * (m - 1) / 2;
     T *ci = tri + ntri, *cj = ci + m;
-    stage_tile<T>(C, A.p, cand, m, E.i, E.j, tri, ci, cj);
-    const T cij = C[(size_t)E.i * A.p + E.j];
+    stage_tile<T>(C, p, cand, m, E.i, E.j, tri, ci, cj);
+    const T cij = C[(size_t)E.i * p + E.j];
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     // per-wave table slice, 16-byte aligned after the tile
     const size_t tile_elems = ((size_t)ntri + 2 * (size_t)m + Lay::V - 1) / Lay::V * Lay::V;
@@ -529,8 +584,8 @@ __global__ __launch_bounds__(256) void pair_kernel(LevelArgs A)
     int64_t rank = wlo;
     int64_t remaining = whi - wlo;
     uint64_t executed = 0;
-    const float errk = (float)(kErrSafety * A.th.c_eff * (L + 2));
-    const float rlo32 = (float)A.th.rb_lo, rhi32 = (float)A.th.rb_hi;
+    const float errk = (float)(kErrSafety * th.c_eff * (L + 2));
+    const float rlo32 = (float)th.rb_lo, rhi32 = (float)th.rb_hi;
     while (remaining > 0) {
         const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
         if (mh < (unsigned long long)rank) break;
@@ -639,7 +694,7 @@ __global__ __launch_bounds__(256) void pair_kernel(LevelArgs A)
             ok = ok && fabs(r) < T(1);
             int dec;
             if constexpr (sizeof(T) == 8) {
-                dec = decide64((double)r, ok, A.th) ? DEC_INDEP : DEC_DEP;
+                dec = decide64((double)r, ok, th) ? DEC_INDEP : DEC_DEP;
             } else {
                 const float dmin = fminf(fminf((float)dminQ, fminf((float)d1, (float)d2)),
                                          fminf((float)h11, (float)h22));
@@ -697,21 +752,28 @@ __global__ __launch_bounds__(256) void pair_kernel(LevelArgs A)
     if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
 }
 
+template <typename T, int QL>
+__global__ __launch_bounds__(256) void pair_kernel(LevelArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    for_each_item(A, [&](int64_t blk) { pair_item<T, QL>(A, blk, smem); });
+}
+
 template <typename T, int QL = 0>
-hipError_t launch_pair(int l, dim3 g, size_t shm, hipStream_t st, const LevelArgs &A)
+hipError_t launch_pair(int l, int64_t ub, int cus, size_t shm, hipStream_t st, const LevelArgs &A)
 {
     if constexpr (QL + 2 <= kMaxTemplL) {
         if (l == QL + 2) {
+            const void *fn = (const void *)pair_kernel<T, QL>;
             if (shm > 65536) {
                 // dynamic LDS beyond 64 KiB is opted into per kernel
-                const hipError_t e = hipFuncSetAttribute((const void *)pair_kernel<T, QL>,
-                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+                const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
                 if (e != hipSuccess) return e;
             }
-            pair_kernel<T, QL><<<g, 256, shm, st>>>(A);
+            pair_kernel<T, QL><<<resident_grid(fn, 256, shm, ub, cus), 256, shm, st>>>(A);
             return hipGetLastError();
         }
-        return launch_pair<T, QL + 1>(l, g, shm, st, A);
+        return launch_pair<T, QL + 1>(l, ub, cus, shm, st, A);
     }
     return hipErrorInvalidValue;
 }
@@ -746,13 +808,11 @@ struct TripleLayout {
 };
 
 template <typename T, int QL>
-__global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
+__device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, unsigned char *smem)
 {
     using Lay = TripleLayout<T, QL>;
     constexpr int L = QL + 3;
     constexpr int QLL = QL > 0 ? QL : 1;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t blk = blockIdx.x;
     const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = E.m;
@@ -763,13 +823,16 @@ __global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
     if (threadIdx.x == 0) skip = load_minhit(&A.minhit[e]) < (uint64_t)r0;
     __syncthreads();
     if (skip) return;  // uniform
-    const T *C = static_cast<const T *>(A.C);
+    const InstRec &I = A.inst[E.inst];
+    const T *C = static_cast<const T *>(I.C);
+    const int p = (int)I.ld;
+    const Thresholds th = I.th;
     const int32_t *cand = A.cand + E.cand_off;
     T *tri = reinterpret_cast<T *>(smem);
     const int ntri = m * (m - 1) / 2;
     T *ci = tri + ntri, *cj = ci + m;
-    stage_tile<T>(C, A.p, cand, m, E.i, E.j, tri, ci, cj);
-    const T cij = C[(size_t)E.i * A.p + E.j];
+    stage_tile<T>(C, p, cand, m, E.i, E.j, tri, ci, cj);
+    const T cij = C[(size_t)E.i * p + E.j];
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const size_t tile_elems = ((size_t)ntri + 2 * (size_t)m + Lay::V - 1) / Lay::V * Lay::V;
     T *tab = tri + tile_elems + (size_t)wave * A.max_m * Lay::S;
@@ -795,8 +858,8 @@ __global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
     int64_t rank = wlo;
     int64_t remaining = whi - wlo;
     uint64_t executed = 0;
-    const float errk = (float)(kErrSafety * A.th.c_eff * (L + 2));
-    const float rlo32 = (float)A.th.rb_lo, rhi32 = (float)A.th.rb_hi;
+    const float errk = (float)(kErrSafety * th.c_eff * (L + 2));
+    const float rlo32 = (float)th.rb_lo, rhi32 = (float)th.rb_hi;
     bool stop = false;
     while (!stop) {
         // ---- Q state (identical in every lane)
@@ -922,7 +985,7 @@ __global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
                 ok = ok && fabs(r) < T(1);
                 int dec;
                 if constexpr (sizeof(T) == 8) {
-                    dec = decide64((double)r, ok, A.th) ? DEC_INDEP : DEC_DEP;
+                    dec = decide64((double)r, ok, th) ? DEC_INDEP : DEC_DEP;
                 } else {
                     const float dmin = fminf(fminf((float)dmina, fminf((float)sbb, (float)d3)),
                                              fminf((float)h11, (float)h22));
@@ -989,20 +1052,27 @@ __global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
     if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
 }
 
+template <typename T, int QL>
+__global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    for_each_item(A, [&](int64_t blk) { triple_item<T, QL>(A, blk, smem); });
+}
+
 template <typename T, int QL = 0>
-hipError_t launch_triple(int l, dim3 g, size_t shm, hipStream_t st, const LevelArgs &A)
+hipError_t launch_triple(int l, int64_t ub, int cus, size_t shm, hipStream_t st, const LevelArgs &A)
 {
     if constexpr (QL + 3 <= kMaxTemplL) {
         if (l == QL + 3) {
+            const void *fn = (const void *)triple_kernel<T, QL>;
             if (shm > 65536) {
-                const hipError_t e = hipFuncSetAttribute((const void *)triple_kernel<T, QL>,
-                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+                const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
                 if (e != hipSuccess) return e;
             }
-            triple_kernel<T, QL><<<g, 256, shm, st>>>(A);
+            triple_kernel<T, QL><<<resident_grid(fn, 256, shm, ub, cus), 256, shm, st>>>(A);
             return hipGetLastError();
         }
-        return launch_triple<T, QL + 1>(l, g, shm, st, A);
+        return launch_triple<T, QL + 1>(l, ub, cus, shm, st, A);
     }
     return hipErrorInvalidValue;
 }
@@ -1050,19 +1120,20 @@ __device__ bool wave_pcor(T *M, int l, int lane, T &r)
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void level_kernel_wide(LevelArgs A, int l)
+__device__ __forceinline__ void wide_item(const LevelArgs &A, int l, int64_t blk, unsigned char *smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     T *M = reinterpret_cast<T *>(smem);
     int *k = reinterpret_cast<int *>(M + (size_t)(l + 2) * (l + 3) / 2 + 1);
-    const int64_t blk = blockIdx.x;
     const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = E.m;
     const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * A.ranks_per_block;
     const int64_t r1 = min(r0 + (int64_t)A.ranks_per_block, min(A.win_hi, E.ntests));
-    if (r0 >= r1) return;
-    const T *C = static_cast<const T *>(A.C);
+    if (r0 >= r1) return;  // uniform
+    const InstRec &I = A.inst[E.inst];
+    const double *C = I.C64;  // wide levels run in FP64
+    const int p = (int)I.ld;
+    const Thresholds th = I.th;
     const int32_t *cand = A.cand + E.cand_off;
     const int lane = threadIdx.x;
     // unrank r0 into k (lane 0), shared through LDS
@@ -1096,7 +1167,7 @@ __global__ __launch_bounds__(64) void level_kernel_wide(LevelArgs A, int l)
             const int b = idx - a * (a + 1) / 2;
             const int va = a < l ? cand[k[a]] : (a == l ? E.i : E.j);
             const int vb = b < l ? cand[k[b]] : (b == l ? E.i : E.j);
-            M[idx] = C[(size_t)va * A.p + vb];
+            M[idx] = (T)C[(size_t)va * p + vb];
         }
         __syncthreads();
         T r;
@@ -1105,9 +1176,9 @@ __global__ __launch_bounds__(64) void level_kernel_wide(LevelArgs A, int l)
         bool indep = false;
         if (ok) {
             const double a = fabs((double)r);
-            indep = a < A.th.r_lo ? true
-                  : a > A.th.r_hi ? false
-                  : A.th.sqrt_nu * fabs(atanh((double)r)) <= A.th.q;
+            indep = a < th.r_lo ? true
+                  : a > th.r_hi ? false
+                  : th.sqrt_nu * fabs(atanh((double)r)) <= th.q;
         }
         if (indep) {
             if (lane == 0) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
@@ -1125,6 +1196,123 @@ __global__ __launch_bounds__(64) void level_kernel_wide(LevelArgs A, int l)
         __syncthreads();
     }
     if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void level_kernel_wide(LevelArgs A, int l)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    for_each_item(A, [&](int64_t blk) { wide_item<T>(A, l, blk, smem); });
+}
+
+// ------------------------------------------------------------------ window plans
+// Work items of window [lo, hi) of one edge: ceil(span / rpb) runs of
+// ranks, none for an edge that already has a separating rank (filter).
+// The plan is an exclusive prefix over the edges, built on the device from
+// the current minhit, so windows follow each other with no host round trip.
+struct PlanArgs {
+    const EdgeRec *edges;
+    const uint64_t *minhit;
+    int64_t n_edges;
+    int64_t lo, hi;
+    int rpb;
+    int filter;
+    int64_t *sums;                  // per-workgroup totals, then their exclusive prefix
+    int64_t *off;                   // n_edges + 1 exclusive prefix of items per edge
+    int64_t *n_items;               // total items of the window
+    unsigned long long *item_ctr;   // zeroed for the window's test kernel
+    unsigned long long *queue_len;  // recheck queue of the previous window, emptied
+};
+
+constexpr int kPlanPer = 8;                 // edges per thread
+constexpr int kPlanChunk = 256 * kPlanPer;  // edges per workgroup
+
+__device__ __forceinline__ int64_t window_items(const EdgeRec &E, uint64_t mh, int64_t lo, int64_t hi, int rpb,
+                                                int filter)
+{
+    if (filter && mh != ~0ull) return 0;
+    const int64_t span = min(E.ntests, hi) - lo;
+    return span > 0 ? (span + rpb - 1) / rpb : 0;
+}
+
+// Exclusive scan of one value per thread over a 256-thread workgroup;
+// returns the workgroup total.
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t &excl)
+{
+    __shared__ int64_t wsum[4];
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    int64_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int64_t before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < w) before += wsum[k];
+        total += wsum[k];
+    }
+    excl = before + x - v;
+    __syncthreads();  // wsum is free again
+    return total;
+}
+
+__global__ __launch_bounds__(256) void plan_reduce(PlanArgs P)
+{
+    const int64_t base = (int64_t)blockIdx.x * kPlanChunk;
+    int64_t s = 0;
+#pragma unroll
+    for (int t = 0; t < kPlanPer; ++t) {
+        const int64_t e = base + (int64_t)t * 256 + threadIdx.x;
+        if (e < P.n_edges) s += window_items(P.edges[e], P.minhit[e], P.lo, P.hi, P.rpb, P.filter);
+    }
+    int64_t ex;
+    const int64_t tot = block_exclusive_scan(s, ex);
+    if (threadIdx.x == 0) P.sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void plan_sums(PlanArgs P, int nb)
+{
+    int64_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 256) {
+        const int b = b0 + threadIdx.x;
+        const int64_t v = b < nb ? P.sums[b] : 0;
+        int64_t ex;
+        const int64_t tot = block_exclusive_scan(v, ex);
+        if (b < nb) P.sums[b] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        P.off[P.n_edges] = carry;
+        *P.n_items = carry;
+        *P.item_ctr = 0;
+        *P.queue_len = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void plan_scan(PlanArgs P)
+{
+    const int64_t base = (int64_t)blockIdx.x * kPlanChunk + (int64_t)threadIdx.x * kPlanPer;
+    int64_t v[kPlanPer];
+    int64_t s = 0;
+#pragma unroll
+    for (int t = 0; t < kPlanPer; ++t) {
+        const int64_t e = base + t;
+        v[t] = e < P.n_edges ? window_items(P.edges[e], P.minhit[e], P.lo, P.hi, P.rpb, P.filter) : 0;
+        s += v[t];
+    }
+    int64_t ex;
+    block_exclusive_scan(s, ex);
+    int64_t run = P.sums[blockIdx.x] + ex;
+#pragma unroll
+    for (int t = 0; t < kPlanPer; ++t) {
+        const int64_t e = base + t;
+        if (e < P.n_edges) P.off[e] = run;
+        run += v[t];
+    }
 }
 
 // ------------------------------------------------------------------ compaction
@@ -1238,14 +1426,15 @@ __global__ __launch_bounds__(64) void batch_kernel_wide(const T *__restrict__ C,
 
 // ------------------------------------------------------------------ dispatch tables
 template <typename T, bool TILE, int L = 0>
-void launch_level(int l, dim3 g, size_t shm, hipStream_t st, const LevelArgs &A)
+void launch_level(int l, int64_t ub, int cus, size_t shm, hipStream_t st, const LevelArgs &A)
 {
     if constexpr (L <= kMaxTemplL) {
         if (l == L) {
-            level_kernel<T, L, TILE><<<g, 256, shm, st>>>(A);
+            const void *fn = (const void *)level_kernel<T, L, TILE>;
+            level_kernel<T, L, TILE><<<resident_grid(fn, 256, shm, ub, cus), 256, shm, st>>>(A);
             return;
         }
-        launch_level<T, TILE, L + 1>(l, g, shm, st, A);
+        launch_level<T, TILE, L + 1>(l, ub, cus, shm, st, A);
     }
 }
 
@@ -1308,11 +1497,13 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     const int64_t E = Lv.n_edges;
     *timing = LevelTiming{};
     if (E == 0) return FPC_OK;
+    if (Lv.n_insts < 1 || !Lv.insts) return FPC_EINVAL;
     int64_t maxN = 0;
     for (int64_t e = 0; e < E; ++e) maxN = std::max(maxN, ntests[e]);
     const bool wide = l > kMaxTemplL;
     const bool fp32 = Lv.fp32 && !wide;
-    const size_t lds_cap = (size_t)ctx->lds_per_block;
+    // dynamic LDS available next to the kernels' few static words
+    const size_t lds_cap = (size_t)ctx->lds_per_block - 64;
     const size_t pair_shm = l == 2 && !wide ? (fp32 ? pair_lds_bytes<float>(l, Lv.max_m)
                                                      : pair_lds_bytes<double>(l, Lv.max_m))
                           : l >= 3 && !wide ? (fp32 ? triple_lds_bytes<float>(l, Lv.max_m)
@@ -1320,107 +1511,127 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                                             : 0;
     const bool pair = l >= 2 && !wide && ctx->use_pair_kernel && pair_shm <= lds_cap;
     const int rpb = wide ? kGenericRanks : (pair ? kPairRanksPerBlock : kRanksPerBlock);
-    // windows of ranks: [0, rpb), then growing by 8x
+    // windows of ranks: [0, rpb), then growing by 8x.  The first window
+    // covers every edge; later ones only the edges with no separating rank
+    // yet, so the ranks past an edge's first hit are never handed out.
     std::vector<int64_t> wins{0};
     for (int64_t w = rpb; wins.back() < maxN; w *= 8) wins.push_back(std::min<int64_t>(maxN, wins.back() + w));
     const int nw = (int)wins.size() - 1;
-    // Workgroup prefix sums per window.  The first window covers every
-    // edge; later ones only the edges with no separating rank yet (their
-    // minhit is read back after the previous window), so the ranks past an
-    // edge's first hit are never launched.
-    FPC_HIP(hipStreamSynchronize(st));  // earlier uploads from the staging buffer have completed
-    int rc = ctx->blockoff.ensure(sizeof(int64_t) * (size_t)nw * (E + 1));
+
+    // instance table: matrices of the level's precision and thresholds
+    const int ni = Lv.n_insts;
+    int rc = ctx->insts.ensure(sizeof(InstRec) * (size_t)ni);
     if (rc) return rc;
-    if ((rc = ctx->h_stage.ensure(sizeof(int64_t) * (size_t)nw * (E + 1)))) return rc;
-    if ((rc = ctx->h_back.ensure(sizeof(uint64_t) * (size_t)E))) return rc;
-    int64_t *h_offs = ctx->h_stage.as<int64_t>();
-    uint64_t *h_minhit = ctx->h_back.as<uint64_t>();
-    auto window_offsets = [&](int w, bool filter) -> int64_t {
-        int64_t *o = h_offs + (size_t)w * (E + 1);
-        o[0] = 0;
-        for (int64_t e = 0; e < E; ++e) {
-            int64_t span = std::max<int64_t>(0, std::min(ntests[e], wins[w + 1]) - wins[w]);
-            if (filter && h_minhit[e] != ~0ull) span = 0;
-            o[e + 1] = o[e] + (span + rpb - 1) / rpb;
-        }
-        return o[E];
-    };
+    if ((rc = ctx->h_inst.ensure(sizeof(InstRec) * (size_t)ni))) return rc;
+    FPC_HIP(hipStreamSynchronize(st));  // the previous upload from h_inst has completed
+    InstRec *hin = ctx->h_inst.as<InstRec>();
+    for (int k = 0; k < ni; ++k) {
+        const LevelInst &I = Lv.insts[k];
+        hin[k].C = fp32 ? (const void *)I.C32 : (const void *)I.C64;
+        hin[k].C64 = I.C64;
+        hin[k].ld = I.p;
+        hin[k].th = make_thresholds(I.q, I.n, l, Lv.band_z, I.c_err + 4.0 * (l + 2) * 6.0e-8);
+    }
+    FPC_HIP(hipMemcpyAsync(ctx->insts.ptr, hin, sizeof(InstRec) * (size_t)ni, hipMemcpyHostToDevice, st));
+
+    // plan buffers: [n_items, item_ctr], workgroup sums, per-edge offsets
+    const int64_t nb = (E + kPlanChunk - 1) / kPlanChunk;
+    if ((rc = ctx->blockoff.ensure(sizeof(int64_t) * (size_t)(2 + nb + E + 1)))) return rc;
+    int64_t *pl = ctx->blockoff.as<int64_t>();
+    PlanArgs P{};
+    P.edges = Lv.edges;
+    P.minhit = Lv.minhit;
+    P.n_edges = E;
+    P.rpb = rpb;
+    P.sums = pl + 2;
+    P.off = pl + 2 + nb;
+    P.n_items = pl;
+    P.item_ctr = reinterpret_cast<unsigned long long *>(pl + 1);
+    P.queue_len = &Lv.counters[1];
 
     LevelArgs A{};
     A.edges = Lv.edges;
     A.cand = Lv.cand;
-    A.C = wide ? (const void *)Lv.C64 : Lv.C;
-    A.C64 = Lv.C64;
+    A.inst = ctx->insts.as<InstRec>();
+    A.blockoff = P.off;
+    A.n_items = P.n_items;
+    A.item_ctr = P.item_ctr;
     A.binom = ctx->binom.as<int64_t>();
     A.minhit = Lv.minhit;
     A.counters = Lv.counters;
     A.queue = Lv.queue;
     A.queue_cap = Lv.queue_cap;
     A.n_edges = E;
-    A.p = Lv.p;
     A.ranks_per_block = rpb;
     A.max_m = Lv.max_m;
-    A.th = make_thresholds(Lv.q, Lv.n, l, Lv.band_z, Lv.c_err + 4.0 * (l + 2) * 6.0e-8);
 
-    FPC_HIP(hipEventRecord(ctx->ev0, st));
+    const int cus = ctx->num_cus;
+    const bool graph = Lv.graph;
+    hipGraph_t g = nullptr;
+    if (graph) FPC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    else FPC_HIP(hipEventRecord(ctx->ev0, st));
     int nev = 0;
-    for (int w = 0; w < nw; ++w) {
-        if (w > 0) {
-            FPC_HIP(hipMemcpyAsync(h_minhit, Lv.minhit, sizeof(uint64_t) * E, hipMemcpyDeviceToHost, st));
-            FPC_HIP(hipStreamSynchronize(st));
+    hipError_t err = hipSuccess;
+    for (int w = 0; w < nw && err == hipSuccess; ++w) {
+        // upper bound of the window's items (every edge live) sizes the grid
+        int64_t ub = 0;
+        for (int64_t e = 0; e < E; ++e) {
+            const int64_t span = std::min(ntests[e], wins[w + 1]) - wins[w];
+            if (span > 0) ub += (span + rpb - 1) / rpb;
         }
-        const int64_t nblk = window_offsets(w, w > 0);
-        if (nblk > 0x7fffffffLL) return FPC_EBUDGET;
-        if (!nblk) continue;
-        FPC_HIP(hipMemcpyAsync(ctx->blockoff.as<int64_t>() + (size_t)w * (E + 1), h_offs + (size_t)w * (E + 1),
-                               sizeof(int64_t) * (E + 1), hipMemcpyHostToDevice, st));
-        const bool timed = nev < fpc_ctx::kLaunchEvents;
-        if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev], st));
-        A.blockoff = ctx->blockoff.as<int64_t>() + (size_t)w * (E + 1);
-        A.win_lo = wins[w];
-        A.win_hi = wins[w + 1];
-        dim3 g((unsigned)nblk);
+        if (ub == 0) continue;
+        P.lo = A.win_lo = wins[w];
+        P.hi = A.win_hi = wins[w + 1];
+        P.filter = w > 0;
+        plan_reduce<<<(unsigned)nb, 256, 0, st>>>(P);
+        plan_sums<<<1, 256, 0, st>>>(P, (int)nb);
+        plan_scan<<<(unsigned)nb, 256, 0, st>>>(P);
+        const bool timed = !graph && nev < fpc_ctx::kLaunchEvents;
+        if (timed) (void)hipEventRecord(ctx->lev[2 * nev], st);
         if (wide) {
             const size_t shm = (fp32 ? 4 : 8) * ((size_t)(l + 2) * (l + 3) / 2 + 1) + sizeof(int) * (l + 1) + 16;
-            if (shm > (size_t)ctx->lds_per_block) return FPC_EBUDGET;
+            if (shm > (size_t)ctx->lds_per_block) {
+                err = hipErrorInvalidValue;
+                break;
+            }
             // wide levels always run in FP64
-            level_kernel_wide<double><<<g, 64, shm, st>>>(A, l);
-            if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev + 1], st));
+            const void *fn = (const void *)level_kernel_wide<double>;
+            level_kernel_wide<double><<<resident_grid(fn, 64, shm, ub, cus), 64, shm, st>>>(A, l);
         } else if (pair && l >= 3) {
-            if (fp32) FPC_HIP(launch_triple<float>(l, g, pair_shm, st, A));
-            else FPC_HIP(launch_triple<double>(l, g, pair_shm, st, A));
-            if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev + 1], st));
-            if (fp32) {
-                launch_recheck(l, st, A);
-                FPC_HIP(hipMemsetAsync(&Lv.counters[1], 0, sizeof(unsigned long long), st));
-            }
+            err = fp32 ? launch_triple<float>(l, ub, cus, pair_shm, st, A)
+                       : launch_triple<double>(l, ub, cus, pair_shm, st, A);
         } else if (pair) {
-            if (fp32) FPC_HIP(launch_pair<float>(l, g, pair_shm, st, A));
-            else FPC_HIP(launch_pair<double>(l, g, pair_shm, st, A));
-            if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev + 1], st));
-            if (fp32) {
-                launch_recheck(l, st, A);
-                FPC_HIP(hipMemsetAsync(&Lv.counters[1], 0, sizeof(unsigned long long), st));
-            }
+            err = fp32 ? launch_pair<float>(l, ub, cus, pair_shm, st, A)
+                       : launch_pair<double>(l, ub, cus, pair_shm, st, A);
         } else {
             const size_t shm = tile_bytes(Lv.max_m, fp32 ? 4 : 8);
             const bool tile = shm <= std::min<size_t>(lds_cap, 65536);
             if (fp32) {
-                if (tile) launch_level<float, true>(l, g, shm, st, A);
-                else launch_level<float, false>(l, g, 0, st, A);
+                if (tile) launch_level<float, true>(l, ub, cus, shm, st, A);
+                else launch_level<float, false>(l, ub, cus, 0, st, A);
             } else {
-                if (tile) launch_level<double, true>(l, g, shm, st, A);
-                else launch_level<double, false>(l, g, 0, st, A);
-            }
-            if (timed) FPC_HIP(hipEventRecord(ctx->lev[2 * nev + 1], st));
-            if (fp32) {
-                launch_recheck(l, st, A);
-                FPC_HIP(hipMemsetAsync(&Lv.counters[1], 0, sizeof(unsigned long long), st));
+                if (tile) launch_level<double, true>(l, ub, cus, shm, st, A);
+                else launch_level<double, false>(l, ub, cus, 0, st, A);
             }
         }
-        FPC_HIP(hipGetLastError());
-        if (timed) ++nev;
+        if (timed) {
+            (void)hipEventRecord(ctx->lev[2 * nev + 1], st);
+            ++nev;
+        }
+        if (fp32) launch_recheck(l, st, A);  // the next window's plan empties the queue
+        if (err == hipSuccess) err = hipGetLastError();
     }
+    if (graph) {
+        const hipError_t e2 = hipStreamEndCapture(st, &g);
+        if (err == hipSuccess) err = e2;
+        hipGraphExec_t ge = nullptr;
+        if (err == hipSuccess) err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (err == hipSuccess) err = hipEventRecord(ctx->ev0, st);
+        if (err == hipSuccess) err = hipGraphLaunch(ge, st);
+        if (ge) hipGraphExecDestroy(ge);
+        if (g) hipGraphDestroy(g);
+    }
+    FPC_HIP(err);
     FPC_HIP(hipEventRecord(ctx->ev1, st));
     FPC_HIP(hipEventSynchronize(ctx->ev1));
     FPC_HIP(hipEventElapsedTime(&timing->all_ms, ctx->ev0, ctx->ev1));
@@ -1429,7 +1640,8 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
         FPC_HIP(hipEventElapsedTime(&ms, ctx->lev[2 * k], ctx->lev[2 * k + 1]));
         timing->test_ms += ms;
     }
-    timing->test_launches = nev;
+    if (graph) timing->test_ms = timing->all_ms;  // one graph: plans and rechecks included
+    timing->test_launches = graph ? nw : nev;
     return FPC_OK;
 }
 

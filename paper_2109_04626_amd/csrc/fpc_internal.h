@@ -72,7 +72,8 @@ struct fpc_ctx {
     // level workspace
     fpc::DevBuf cand;             // int32 candidate lists of eligible edges
     fpc::DevBuf edges;            // EdgeRec per eligible edge
-    fpc::DevBuf blockoff;         // per-window block prefix sums
+    fpc::DevBuf blockoff;         // window plan: item counters, workgroup sums, per-edge item prefix
+    fpc::DevBuf insts;            // per-instance matrices and thresholds of a level
     fpc::DevBuf minhit;           // uint64 per edge: lowest independent rank
     fpc::DevBuf counters;         // uint64 counters (tests executed, queue length, ...)
     fpc::DevBuf queue;            // recheck queue (edge, rank)
@@ -86,16 +87,19 @@ struct fpc_ctx {
 
     fpc::HostBuf h_stage;         // pinned staging for uploads
     fpc::HostBuf h_back;          // pinned staging for downloads
+    fpc::HostBuf h_inst;          // pinned staging for the instance table
 };
 
 namespace fpc {
 
 // One eligible edge of a level, as the test kernels see it.
 struct EdgeRec {
-    int32_t i, j;      // variables, i < j
+    int32_t i, j;      // variables, i < j (within the instance)
     int32_t m;         // |cand|
     int32_t cand_off;  // offset of its candidate list in the level's cand array
     int64_t ntests;    // C(m, l)
+    int32_t inst;      // instance the edge belongs to (index into the level's instance table)
+    int32_t reserved;
 };
 
 // ---- correlation (corr.hip)
@@ -107,22 +111,27 @@ int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r
                 uint8_t *indep_out, int *n_singular);
 
 // ---- level tests (citest.hip)
+// One problem instance of a level: its matrices and threshold.
+struct LevelInst {
+    const float *C32;              // device FP32 matrix (mixed form; may be NULL otherwise)
+    const double *C64;             // device FP64 matrix
+    int p, n;
+    double q;                      // threshold
+    double c_err;                  // bound on the entry error of the FP32 matrix
+};
 struct LevelLaunch {
     int l;
     int max_m;                     // largest |cand| among the eligible edges
-    int64_t n_edges;               // eligible edges
+    int64_t n_edges;               // eligible edges (of every instance)
     const EdgeRec *edges;          // device
     const int32_t *cand;           // device
-    const void *C;                 // device matrix of the test precision
-    const double *C64;             // device FP64 matrix (recheck)
-    int p, n;
+    const LevelInst *insts;        // host, n_insts entries; EdgeRec::inst indexes them
+    int n_insts;
     bool fp32;                     // tests in FP32 with FP64 recheck
-    double q;                      // threshold
-    double r_thr;                  // tanh(q / sqrt(n - l - 3))
+    bool graph;                    // capture the level's launches in one HIP graph
     double band_z;                 // recheck margin in z units
-    double c_err;                  // bound on the entry error of the FP32 matrix
     uint64_t *minhit;              // device, per edge
-    unsigned long long *counters;  // device: [0] executed, [1] queue length, [2] rechecked
+    unsigned long long *counters;  // device: [0] executed, [1] queue length, [2] rechecked, [3] overflow
     int64_t *queue;                // device, 2 * queue_cap entries (edge, rank)
     int64_t queue_cap;
 };

@@ -229,10 +229,11 @@ extern "C" int fpc_destroy(fpc_ctx *c)
     DevBuf *bufs[] = {&c->binom, &c->x_copy, &c->colstat, &c->c64, &c->c32, &c->zsplit, &c->inv_work,
                       &c->flag, &c->cand, &c->edges, &c->blockoff, &c->minhit, &c->counters,
                       &c->queue, &c->dellist, &c->batch_tmp, &c->mlp_grad, &c->rfirst, &c->feat,
-                      &c->cand2, &c->degs};
+                      &c->cand2, &c->degs, &c->insts};
     for (DevBuf *b : bufs) b->release();
     c->h_stage.release();
     c->h_back.release();
+    c->h_inst.release();
     for (hipEvent_t ev : c->lev)
         if (ev) (void)hipEventDestroy(ev);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -321,7 +322,7 @@ int run_level(Run &R, int l, const CandSets &cs, fpc_level_stats &st)
         if (N == INT64_MAX || possible > INT64_MAX - N) return FPC_EBUDGET;
         possible += N;
         sel_max_m = std::max(sel_max_m, m);
-        recs[k] = EdgeRec{cs.ei[e], cs.ej[e], m, (int32_t)cand.size(), N};
+        recs[k] = EdgeRec{cs.ei[e], cs.ej[e], m, (int32_t)cand.size(), N, 0, 0};
         ntests[k] = N;
         cand.insert(cand.end(), cs.nodes.begin() + cs.off[e], cs.nodes.begin() + cs.off[e + 1]);
     }
@@ -388,14 +389,12 @@ retry:
     Lv.n_edges = E;
     Lv.edges = ctx->edges.as<EdgeRec>();
     Lv.cand = d_cand;
-    Lv.C = fp32 ? (const void *)R.C32 : (const void *)R.C64;
-    Lv.C64 = R.C64;
-    Lv.p = R.p;
-    Lv.n = R.n;
+    const LevelInst inst{R.C32, R.C64, R.p, R.n, R.q, R.c_err};
+    Lv.insts = &inst;
+    Lv.n_insts = 1;
     Lv.fp32 = fp32;
-    Lv.q = R.q;
+    Lv.graph = (R.P->flags & FPC_FLAG_GRAPH) != 0;
     Lv.band_z = R.P->recheck_margin > 0 ? R.P->recheck_margin : 1e-3;
-    Lv.c_err = R.c_err;
     Lv.minhit = ctx->minhit.as<uint64_t>();
     Lv.counters = ctx->counters.as<unsigned long long>();
     Lv.queue = fp32 ? ctx->queue.as<int64_t>() : nullptr;

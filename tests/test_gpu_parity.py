@@ -249,6 +249,30 @@ def test_skeleton_mid_sizes(fpc, ctx, p, n, deg, L, prec, flags):
     _say(f"  tests gpu={got['total_tests']} oracle={ref['total_tests']}")
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_skeleton_graph_mode_matches_eager(fpc, ctx, prec):
+    """FPC_FLAG_GRAPH: each level's launches captured in one HIP graph; three
+    runs in a row, eager runs between them, all equal to the eager result
+    and to the oracle's skeleton."""
+    p, n = 90, 3000
+    _say(f"[graph mode] p={p} n={n} prec={prec}")
+    sem = semdata.make_sem(p, 41, degree=5.0)
+    X = semdata.sample(sem, n, 41)
+    C = oracle.corr(X)
+    ref = oracle.skeleton(C, n, alpha=0.01, max_level=6)
+    Xd = dev(X)
+    for rep in range(3):
+        eager = fpc.fpc_skeleton(ctx, Xd, alpha=0.01, max_level=6, precision=prec)
+        got = fpc.fpc_skeleton(ctx, Xd, alpha=0.01, max_level=6, precision=prec, flags=fpc.FPC_FLAG_GRAPH)
+        assert np.array_equal(got["adj"], ref["adj"]) and np.array_equal(eager["adj"], ref["adj"])
+        assert np.array_equal(got["sep_level"], ref["sep_level"])
+        assert got["sepsets"] == eager["sepsets"]
+        if prec == 0:
+            assert got["sepsets"] == ref["sepsets"]
+    if prec == 1:
+        _retest_sepsets(fpc, got, C, n, ref["q"])
+
+
 # ------------------------------------------------------------------ edge cases
 def test_skeleton_smallest_graphs(fpc, ctx):
     rng = np.random.default_rng(3)

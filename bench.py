@@ -56,6 +56,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=3e8, help="oracle tests in the CPU sample")
     ap.add_argument("--max-level", type=int, default=None)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the many-instance workload")
+    ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
@@ -104,6 +106,47 @@ def main() -> int:
     Xbd = torch.from_numpy(Xb).cuda()
     ba = {name: timed(Xbd, cfg_b, fpc.FPC_PREC_MIXED, m) for name, m in (("mixed", None), ("learned", model))}
     del Xbd
+    # many instances in one call: 64 bootstrap resamples of one data set and
+    # 16 data sets of uneven p, against the same instances one call each
+    batched = None
+    if not args.no_batched:
+        base, boots, datas, cfg5 = semdata.batched_workload()
+        base_d = torch.from_numpy(base).cuda()
+        inst = [(base_d, torch.from_numpy(r).cuda()) for r in boots] + \
+               [(torch.from_numpy(d).cuda(), None) for d in datas]
+
+        def run_batch():
+            return fpc.fpc_skeleton_batch(ctx, inst, alpha=cfg5["alpha"], max_level=cfg5["max_level"],
+                                          precision=fpc.FPC_PREC_MIXED)
+
+        def run_singles():
+            return [fpc.fpc_skeleton(ctx, X if r is None else X[r.long()], alpha=cfg5["alpha"],
+                                     max_level=cfg5["max_level"], precision=fpc.FPC_PREC_MIXED) for X, r in inst]
+
+        run_batch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            outs_b = run_batch()
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / args.batch_steps
+        run_singles()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs_s = run_singles()
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        same_b = all(np.array_equal(a["adj"], b["adj"]) for a, b in zip(outs_b, outs_s))
+        tests_b = sum(o["total_tests"] for o in outs_b)
+        batched = {"workload": f"64 bootstrap resamples of an ER p={cfg5['base_p']} deg={cfg5['degree']} data set "
+                               f"+ 16 ER data sets p~U[{cfg5['p_lo']},{cfg5['p_hi']}], n={cfg5['n']} X f32, "
+                               f"alpha={cfg5['alpha']}, max_level={cfg5['max_level']}, mixed",
+                   "instances": len(inst), "ms_per_call": tb * 1e3, "one_call_each_ms": ts * 1e3,
+                   "speedup_vs_one_call_each": ts / tb, "tests_per_call": tests_b,
+                   "ci_tests_per_s": tests_b / tb, "skeletons_equal": same_b}
+        print(f"[bench] batched: {tb * 1e3:.1f} ms/call vs {ts * 1e3:.1f} ms one call each", file=sys.stderr,
+              flush=True)
+        del inst, base_d
 
     dt, outs = results["mixed"]
     last = outs[-1]
@@ -169,6 +212,7 @@ def main() -> int:
                        "tests_learned": ba["learned"][1][-1]["total_tests"],
                        "skeleton_equal": bool(np.array_equal(ba["mixed"][1][-1]["adj"],
                                                              ba["learned"][1][-1]["adj"]))},
+        "batched": batched,
         "tests_per_step": outs[-1]["total_tests"],
         "edges": int(last["adj"].sum()) // 2,
         "level_kernel_ms_mixed": kms,

@@ -212,6 +212,37 @@ typedef struct fpc_result {
 int fpc_skeleton(fpc_ctx *ctx, const fpc_params *params, fpc_result **out);
 void fpc_result_free(fpc_result *r);
 
+/* ------------------------------------------------------------- many instances
+ * Runs the skeleton of several independent problems (bootstrap resamples of
+ * one data set, separate data sets of uneven p) together: correlation and
+ * first level per instance, then every following level of all instances in
+ * shared launches (one edge table over the instances, persistent kernels).
+ * Each result equals that of fpc_skeleton on the instance alone (same
+ * skeleton, separating sets and level sequence); level timings in the
+ * per-level stats are those of the shared launches, total_ms that of the
+ * whole call.  Not in the paper: its batching concerns the tests of one
+ * problem (Sec. 5).
+ *
+ * params: alpha or q_override, max_level, precision, recheck_margin, flags
+ * (FPC_FLAG_GRAPH, FPC_FLAG_PER_TEST_KERNEL) and x_dtype apply to every
+ * instance; schedule must be FPC_REVERSE and order FPC_ORDER_LEX (else
+ * FPC_EINVAL); X, n, p and x_on_device are not read; max_tests is a
+ * per-instance budget. */
+typedef struct {
+    int32_t n;            /* samples of the instance (> p + 1)                                  */
+    int32_t p;            /* variables (>= 2)                                                   */
+    const void *X;        /* device, row-major x_rows x p, params->x_dtype; borrowed            */
+    int64_t x_rows;       /* rows of X                                                          */
+    const int32_t *rows;  /* device, n row indices into X (a resample: the instance's data are
+                             those rows in this order); NULL: the first n rows (x_rows >= n)    */
+} fpc_instance;
+
+/* out: caller array of n_inst pointers; on success each holds a result freed
+ * with fpc_result_free; on error all are NULL.  Errors as fpc_skeleton, and
+ * FPC_EINVAL for an instance field or row index out of range. */
+int fpc_skeleton_batch(fpc_ctx *ctx, const fpc_params *params, int n_inst, const fpc_instance *inst,
+                       fpc_result **out);
+
 /* ------------------------------------------------------------- candidate-ranking MLP
  * Orders each edge's candidate list for FPC_ORDER_LEARNED.  Features of a
  * candidate k of the pair (i, j): max(|C_ik|, |C_jk|), max(|R_ik|, |R_jk|)

@@ -29,7 +29,7 @@ FPC_FLAG_LOG_FEATURES = 2
 FPC_FLAG_GRAPH = 4
 
 EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "fpc_quantile",
-            "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton",
+            "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton", "fpc_skeleton_batch",
             "fpc_result_free", "fpc_orient", "fpc_mlp_bytes", "fpc_mlp_params", "fpc_mlp_init", "fpc_mlp_get",
             "fpc_mlp_forward", "fpc_mlp_grad", "fpc_mlp_train_step"]
 
@@ -75,6 +75,11 @@ class fpc_result(ctypes.Structure):
                 ("log_group", ctypes.POINTER(ctypes.c_int32)), ("log_level", ctypes.POINTER(ctypes.c_int32))]
 
 
+class fpc_instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("p", ctypes.c_int32), ("X", ctypes.c_void_p), ("x_rows", ctypes.c_int64),
+                ("rows", ctypes.c_void_p)]
+
+
 def _load():
     # torch first: its HIP runtime (soname libamdhip64.so.7) is then the one
     # the library binds to.  Loaded the other way round, torch would bring a
@@ -105,6 +110,9 @@ def _load():
     lib.fpc_candidates.restype = i
     lib.fpc_skeleton.argtypes = [vp, ctypes.POINTER(fpc_params), ctypes.POINTER(ctypes.POINTER(fpc_result))]
     lib.fpc_skeleton.restype = i
+    lib.fpc_skeleton_batch.argtypes = [vp, ctypes.POINTER(fpc_params), i, ctypes.POINTER(fpc_instance),
+                                       ctypes.POINTER(ctypes.POINTER(fpc_result))]
+    lib.fpc_skeleton_batch.restype = i
     lib.fpc_result_free.argtypes = [ctypes.POINTER(fpc_result)]
     lib.fpc_result_free.restype = None
     lib.fpc_orient.argtypes = [i, vp, vp, vp, vp, vp, vp]
@@ -385,6 +393,61 @@ def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, prec
         return _unpack(res.contents)
     finally:
         _lib.fpc_result_free(res)
+
+
+def fpc_skeleton_batch(ctx: Context, instances, alpha: float = 0.01, max_level: int = -1,
+                       precision: int = FPC_PREC_FP64, recheck_margin: float = 1e-3, max_tests: int = 0,
+                       q_override: float = float("nan"), flags: int = 0) -> list:
+    """Skeletons of several instances in one call.  ``instances`` is a
+    sequence of (X, rows): X a device tensor (x_rows x p, one dtype for
+    all), rows None (the instance is X itself) or a device int32 tensor of
+    row indices into X (a resample).  Returns one result dict per
+    instance, as fpc_skeleton."""
+    keep = []
+    arr = (fpc_instance * len(instances))()
+    dt = None
+    for k, (X, rows) in enumerate(instances):
+        X = X.contiguous()
+        keep.append(X)
+        if dt is None:
+            dt = _dtype_code(X)
+        elif _dtype_code(X) != dt:
+            raise TypeError("every instance must have the same dtype")
+        arr[k].p = X.shape[1]
+        arr[k].X = _t_ptr(X).value
+        arr[k].x_rows = X.shape[0]
+        if rows is None:
+            arr[k].n = X.shape[0]
+            arr[k].rows = None
+        else:
+            rows = rows.contiguous()
+            keep.append(rows)
+            if str(rows.dtype) != "torch.int32":
+                raise TypeError("rows must be int32")
+            arr[k].n = rows.shape[0]
+            arr[k].rows = _t_ptr(rows).value
+    prm = fpc_params()
+    prm.x_dtype = dt if dt is not None else FPC_F32
+    prm.x_on_device = 1
+    prm.alpha = float(alpha)
+    prm.max_level = int(max_level)
+    prm.precision = int(precision)
+    prm.recheck_margin = float(recheck_margin)
+    prm.schedule = FPC_REVERSE
+    prm.order = FPC_ORDER_LEX
+    prm.max_tests = int(max_tests)
+    prm.q_override = float(q_override)
+    prm.flags = int(flags)
+    outs = (ctypes.POINTER(fpc_result) * max(len(instances), 1))()
+    _check(_lib.fpc_skeleton_batch(ctx.handle, ctypes.byref(prm), len(instances), arr, outs), "fpc_skeleton_batch")
+    res = []
+    try:
+        for k in range(len(instances)):
+            res.append(_unpack(outs[k].contents))
+    finally:
+        for k in range(len(instances)):
+            _lib.fpc_result_free(outs[k])
+    return res
 
 
 class SepSets(Mapping):

@@ -283,7 +283,8 @@ struct LevelArgs {
     unsigned long long *item_ctr;  // next work item (zeroed with the window's plan)
     const int64_t *binom;
     uint64_t *minhit;
-    unsigned long long *counters;
+    unsigned long long *counters;  // [1] recheck queue length, [3] queue overflow
+    unsigned long long *inst_cnt;  // per instance: tests executed, tests re-run in FP64
     int64_t *queue;
     int64_t queue_cap;
     int64_t n_edges;
@@ -320,11 +321,15 @@ __device__ __forceinline__ void for_each_item(const LevelArgs &A, F &&body)
 
 // Persistent grid: as many workgroups as fit on the device at once, and no
 // more than the window can possibly use.
-unsigned resident_grid(const void *fn, int threads, size_t shm, int64_t ub, int cus)
+// The register and wave limits come from the runtime's occupancy query;
+// the LDS limit is applied here from the CU's LDS size, since the query
+// does not account for workgroups that opt into more than 64 KiB.
+unsigned resident_grid(const void *fn, int threads, size_t shm, int64_t ub, int cus, size_t lds_cu)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, shm) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
+    if (shm > 0) per_cu = std::min<int>(per_cu, std::max<int>(1, (int)(lds_cu / (shm + 256))));
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ub, (int64_t)per_cu * cus));
 }
 
@@ -434,7 +439,7 @@ __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsi
             if (!more) break;
         }
     }
-    if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
+    if (lane == 0 && executed) atomicAdd(&A.inst_cnt[2 * E.inst], (unsigned long long)executed);
 }
 
 template <typename T, int L, bool TILE>
@@ -452,7 +457,6 @@ __global__ __launch_bounds__(256) void recheck_kernel(LevelArgs A)
     const unsigned long long total = min((unsigned long long)A.queue_cap, queued);
     if (blockIdx.x == 0 && threadIdx.x == 0 && queued > (unsigned long long)A.queue_cap)
         atomicMax(&A.counters[3], 1ull);  // entries were dropped: the caller re-runs the level in FP64
-    unsigned long long done = 0;
     for (unsigned long long idx = (unsigned long long)blockIdx.x * 256 + threadIdx.x; idx < total;
          idx += (unsigned long long)gridDim.x * 256) {
         const int64_t e = A.queue[2 * idx], R = A.queue[2 * idx + 1];
@@ -465,10 +469,9 @@ __global__ __launch_bounds__(256) void recheck_kernel(LevelArgs A)
         double r, dmin;
         bool ok;
         pcor_reg<double, L>(g, k, r, dmin, ok);
-        ++done;
+        atomicAdd(&A.inst_cnt[2 * E.inst + 1], 1ull);
         if (decide64(r, ok, I.th)) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
     }
-    if (done) atomicAdd(&A.counters[2], done);
 }
 
 
@@ -749,7 +752,7 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
             tau = 0;
         }
     }
-    if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
+    if (lane == 0 && executed) atomicAdd(&A.inst_cnt[2 * E.inst], (unsigned long long)executed);
 }
 
 template <typename T, int QL>
@@ -760,7 +763,7 @@ __global__ __launch_bounds__(256) void pair_kernel(LevelArgs A)
 }
 
 template <typename T, int QL = 0>
-hipError_t launch_pair(int l, int64_t ub, int cus, size_t shm, hipStream_t st, const LevelArgs &A)
+hipError_t launch_pair(int l, int64_t ub, int cus, size_t lds_cu, size_t shm, hipStream_t st, const LevelArgs &A)
 {
     if constexpr (QL + 2 <= kMaxTemplL) {
         if (l == QL + 2) {
@@ -770,10 +773,10 @@ hipError_t launch_pair(int l, int64_t ub, int cus, size_t shm, hipStream_t st, c
                 const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
                 if (e != hipSuccess) return e;
             }
-            pair_kernel<T, QL><<<resident_grid(fn, 256, shm, ub, cus), 256, shm, st>>>(A);
+            pair_kernel<T, QL><<<resident_grid(fn, 256, shm, ub, cus, lds_cu), 256, shm, st>>>(A);
             return hipGetLastError();
         }
-        return launch_pair<T, QL + 1>(l, ub, cus, shm, st, A);
+        return launch_pair<T, QL + 1>(l, ub, cus, lds_cu, shm, st, A);
     }
     return hipErrorInvalidValue;
 }
@@ -1049,7 +1052,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
             tau = 0;
         }
     }
-    if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
+    if (lane == 0 && executed) atomicAdd(&A.inst_cnt[2 * E.inst], (unsigned long long)executed);
 }
 
 template <typename T, int QL>
@@ -1060,7 +1063,7 @@ __global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
 }
 
 template <typename T, int QL = 0>
-hipError_t launch_triple(int l, int64_t ub, int cus, size_t shm, hipStream_t st, const LevelArgs &A)
+hipError_t launch_triple(int l, int64_t ub, int cus, size_t lds_cu, size_t shm, hipStream_t st, const LevelArgs &A)
 {
     if constexpr (QL + 3 <= kMaxTemplL) {
         if (l == QL + 3) {
@@ -1069,10 +1072,10 @@ hipError_t launch_triple(int l, int64_t ub, int cus, size_t shm, hipStream_t st,
                 const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
                 if (e != hipSuccess) return e;
             }
-            triple_kernel<T, QL><<<resident_grid(fn, 256, shm, ub, cus), 256, shm, st>>>(A);
+            triple_kernel<T, QL><<<resident_grid(fn, 256, shm, ub, cus, lds_cu), 256, shm, st>>>(A);
             return hipGetLastError();
         }
-        return launch_triple<T, QL + 1>(l, ub, cus, shm, st, A);
+        return launch_triple<T, QL + 1>(l, ub, cus, lds_cu, shm, st, A);
     }
     return hipErrorInvalidValue;
 }
@@ -1195,7 +1198,7 @@ __device__ __forceinline__ void wide_item(const LevelArgs &A, int l, int64_t blk
         }
         __syncthreads();
     }
-    if (lane == 0 && executed) atomicAdd(&A.counters[0], (unsigned long long)executed);
+    if (lane == 0 && executed) atomicAdd(&A.inst_cnt[2 * E.inst], (unsigned long long)executed);
 }
 
 template <typename T>
@@ -1426,15 +1429,15 @@ __global__ __launch_bounds__(64) void batch_kernel_wide(const T *__restrict__ C,
 
 // ------------------------------------------------------------------ dispatch tables
 template <typename T, bool TILE, int L = 0>
-void launch_level(int l, int64_t ub, int cus, size_t shm, hipStream_t st, const LevelArgs &A)
+void launch_level(int l, int64_t ub, int cus, size_t lds_cu, size_t shm, hipStream_t st, const LevelArgs &A)
 {
     if constexpr (L <= kMaxTemplL) {
         if (l == L) {
             const void *fn = (const void *)level_kernel<T, L, TILE>;
-            level_kernel<T, L, TILE><<<resident_grid(fn, 256, shm, ub, cus), 256, shm, st>>>(A);
+            level_kernel<T, L, TILE><<<resident_grid(fn, 256, shm, ub, cus, lds_cu), 256, shm, st>>>(A);
             return;
         }
-        launch_level<T, TILE, L + 1>(l, ub, cus, shm, st, A);
+        launch_level<T, TILE, L + 1>(l, ub, cus, lds_cu, shm, st, A);
     }
 }
 
@@ -1490,6 +1493,27 @@ size_t tile_bytes(int m, size_t elem) { return elem * ((size_t)m * (m - 1) / 2 +
 
 }  // namespace
 
+int level_class_key(const fpc_ctx *ctx, int l, bool fp32, int m)
+{
+    if (l > kMaxTemplL) return 0;  // wide levels: one class
+    const size_t cap = (size_t)ctx->lds_per_block - 64;
+    const size_t ps = l == 2 ? (fp32 ? pair_lds_bytes<float>(l, m) : pair_lds_bytes<double>(l, m))
+                    : l >= 3 ? (fp32 ? triple_lds_bytes<float>(l, m) : triple_lds_bytes<double>(l, m))
+                             : 0;
+    int kind;
+    size_t shm;
+    if (l >= 2 && ctx->use_pair_kernel && ps <= cap) {
+        kind = 0;
+        shm = ps;
+    } else {
+        const size_t ts = tile_bytes(m, fp32 ? 4 : 8);
+        kind = ts <= std::min<size_t>(cap, 65536) ? 1 : 2;
+        shm = kind == 1 ? ts : 0;
+    }
+    const int per_cu = shm ? std::max(1, std::min(8, (int)((size_t)ctx->lds_per_cu / (shm + 256)))) : 8;
+    return kind * 16 + (8 - per_cu);
+}
+
 int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> &ntests, LevelTiming *timing)
 {
     hipStream_t st = ctx->stream;
@@ -1498,25 +1522,60 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     *timing = LevelTiming{};
     if (E == 0) return FPC_OK;
     if (Lv.n_insts < 1 || !Lv.insts) return FPC_EINVAL;
-    int64_t maxN = 0;
-    for (int64_t e = 0; e < E; ++e) maxN = std::max(maxN, ntests[e]);
     const bool wide = l > kMaxTemplL;
     const bool fp32 = Lv.fp32 && !wide;
     // dynamic LDS available next to the kernels' few static words
     const size_t lds_cap = (size_t)ctx->lds_per_block - 64;
-    const size_t pair_shm = l == 2 && !wide ? (fp32 ? pair_lds_bytes<float>(l, Lv.max_m)
-                                                     : pair_lds_bytes<double>(l, Lv.max_m))
-                          : l >= 3 && !wide ? (fp32 ? triple_lds_bytes<float>(l, Lv.max_m)
-                                                    : triple_lds_bytes<double>(l, Lv.max_m))
-                                            : 0;
-    const bool pair = l >= 2 && !wide && ctx->use_pair_kernel && pair_shm <= lds_cap;
-    const int rpb = wide ? kGenericRanks : (pair ? kPairRanksPerBlock : kRanksPerBlock);
-    // windows of ranks: [0, rpb), then growing by 8x.  The first window
-    // covers every edge; later ones only the edges with no separating rank
-    // yet, so the ranks past an edge's first hit are never handed out.
-    std::vector<int64_t> wins{0};
-    for (int64_t w = rpb; wins.back() < maxN; w *= 8) wins.push_back(std::min<int64_t>(maxN, wins.back() + w));
-    const int nw = (int)wins.size() - 1;
+
+    // per size class: kernel, LDS, ranks per work item, windows of ranks
+    // ([0, rpb), then growing by 8x; the first window covers every edge,
+    // later ones only the edges with no separating rank yet, so the ranks
+    // past an edge's first hit are never handed out)
+    enum Kind { K_WIDE, K_TRIPLE, K_PAIR, K_TILE, K_GLOBAL };
+    struct Cls {
+        int64_t begin, end;
+        int max_m;
+        Kind kind;
+        size_t shm;
+        int rpb;
+        std::vector<int64_t> wins;
+    };
+    std::vector<Cls> cls;
+    const LevelClass all{0, E, Lv.max_m};
+    const LevelClass *lc = Lv.classes ? Lv.classes : &all;
+    const int nlc = Lv.classes ? Lv.n_classes : 1;
+    int max_nw = 0;
+    for (int c = 0; c < nlc; ++c) {
+        Cls k{lc[c].begin, lc[c].end, lc[c].max_m, K_GLOBAL, 0, 0, {}};
+        if (k.begin < 0 || k.end > E || k.begin >= k.end) return FPC_EINVAL;
+        if (wide) {
+            k.kind = K_WIDE;
+            k.shm = 8 * ((size_t)(l + 2) * (l + 3) / 2 + 1) + sizeof(int) * (l + 1) + 16;
+            if (k.shm > lds_cap) return FPC_EBUDGET;
+        } else {
+            const size_t ps = l == 2 ? (fp32 ? pair_lds_bytes<float>(l, k.max_m) : pair_lds_bytes<double>(l, k.max_m))
+                            : l >= 3 ? (fp32 ? triple_lds_bytes<float>(l, k.max_m)
+                                             : triple_lds_bytes<double>(l, k.max_m))
+                                     : 0;
+            if (l >= 2 && ctx->use_pair_kernel && ps <= lds_cap) {
+                k.kind = l >= 3 ? K_TRIPLE : K_PAIR;
+                k.shm = ps;
+            } else {
+                const size_t ts = tile_bytes(k.max_m, fp32 ? 4 : 8);
+                k.kind = ts <= std::min<size_t>(lds_cap, 65536) ? K_TILE : K_GLOBAL;
+                k.shm = k.kind == K_TILE ? ts : 0;
+            }
+        }
+        k.rpb = k.kind == K_WIDE ? kGenericRanks : (k.kind == K_TRIPLE || k.kind == K_PAIR) ? kPairRanksPerBlock
+                                                                                              : kRanksPerBlock;
+        int64_t maxN = 0;
+        for (int64_t e = k.begin; e < k.end; ++e) maxN = std::max(maxN, ntests[e]);
+        k.wins.push_back(0);
+        for (int64_t w = k.rpb; k.wins.back() < maxN; w *= 8)
+            k.wins.push_back(std::min<int64_t>(maxN, k.wins.back() + w));
+        max_nw = std::max(max_nw, (int)k.wins.size() - 1);
+        cls.push_back(std::move(k));
+    }
 
     // instance table: matrices of the level's precision and thresholds
     const int ni = Lv.n_insts;
@@ -1534,92 +1593,101 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     }
     FPC_HIP(hipMemcpyAsync(ctx->insts.ptr, hin, sizeof(InstRec) * (size_t)ni, hipMemcpyHostToDevice, st));
 
-    // plan buffers: [n_items, item_ctr], workgroup sums, per-edge offsets
-    const int64_t nb = (E + kPlanChunk - 1) / kPlanChunk;
-    if ((rc = ctx->blockoff.ensure(sizeof(int64_t) * (size_t)(2 + nb + E + 1)))) return rc;
+    // plan buffers, reused by every (window, class) launch in stream order:
+    // [n_items, item_ctr], workgroup sums, per-edge offsets
+    const int64_t nbmax = (E + kPlanChunk - 1) / kPlanChunk;
+    if ((rc = ctx->blockoff.ensure(sizeof(int64_t) * (size_t)(2 + nbmax + E + 1)))) return rc;
     int64_t *pl = ctx->blockoff.as<int64_t>();
-    PlanArgs P{};
-    P.edges = Lv.edges;
-    P.minhit = Lv.minhit;
-    P.n_edges = E;
-    P.rpb = rpb;
-    P.sums = pl + 2;
-    P.off = pl + 2 + nb;
-    P.n_items = pl;
-    P.item_ctr = reinterpret_cast<unsigned long long *>(pl + 1);
-    P.queue_len = &Lv.counters[1];
 
     LevelArgs A{};
-    A.edges = Lv.edges;
     A.cand = Lv.cand;
     A.inst = ctx->insts.as<InstRec>();
-    A.blockoff = P.off;
-    A.n_items = P.n_items;
-    A.item_ctr = P.item_ctr;
+    A.n_items = pl;
+    A.item_ctr = reinterpret_cast<unsigned long long *>(pl + 1);
     A.binom = ctx->binom.as<int64_t>();
-    A.minhit = Lv.minhit;
     A.counters = Lv.counters;
+    A.inst_cnt = Lv.inst_cnt;
     A.queue = Lv.queue;
     A.queue_cap = Lv.queue_cap;
-    A.n_edges = E;
-    A.ranks_per_block = rpb;
-    A.max_m = Lv.max_m;
 
     const int cus = ctx->num_cus;
+    const size_t lds_cu = (size_t)ctx->lds_per_cu;
     const bool graph = Lv.graph;
     hipGraph_t g = nullptr;
     if (graph) FPC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     else FPC_HIP(hipEventRecord(ctx->ev0, st));
-    int nev = 0;
+    int nev = 0, nlaunch = 0;
     hipError_t err = hipSuccess;
-    for (int w = 0; w < nw && err == hipSuccess; ++w) {
-        // upper bound of the window's items (every edge live) sizes the grid
-        int64_t ub = 0;
-        for (int64_t e = 0; e < E; ++e) {
-            const int64_t span = std::min(ntests[e], wins[w + 1]) - wins[w];
-            if (span > 0) ub += (span + rpb - 1) / rpb;
-        }
-        if (ub == 0) continue;
-        P.lo = A.win_lo = wins[w];
-        P.hi = A.win_hi = wins[w + 1];
-        P.filter = w > 0;
-        plan_reduce<<<(unsigned)nb, 256, 0, st>>>(P);
-        plan_sums<<<1, 256, 0, st>>>(P, (int)nb);
-        plan_scan<<<(unsigned)nb, 256, 0, st>>>(P);
-        const bool timed = !graph && nev < fpc_ctx::kLaunchEvents;
-        if (timed) (void)hipEventRecord(ctx->lev[2 * nev], st);
-        if (wide) {
-            const size_t shm = (fp32 ? 4 : 8) * ((size_t)(l + 2) * (l + 3) / 2 + 1) + sizeof(int) * (l + 1) + 16;
-            if (shm > (size_t)ctx->lds_per_block) {
-                err = hipErrorInvalidValue;
+    for (int w = 0; w < max_nw && err == hipSuccess; ++w) {
+        for (const Cls &k : cls) {
+            if (w + 1 >= (int)k.wins.size()) continue;
+            const int64_t lo = k.wins[w], hi = k.wins[w + 1];
+            // upper bound of the items (every edge live) sizes the grid
+            int64_t ub = 0;
+            for (int64_t e = k.begin; e < k.end; ++e) {
+                const int64_t span = std::min(ntests[e], hi) - lo;
+                if (span > 0) ub += (span + k.rpb - 1) / k.rpb;
+            }
+            if (ub == 0) continue;
+            const int64_t Ek = k.end - k.begin, nb = (Ek + kPlanChunk - 1) / kPlanChunk;
+            PlanArgs P{};
+            P.edges = Lv.edges + k.begin;
+            P.minhit = Lv.minhit + k.begin;
+            P.n_edges = Ek;
+            P.lo = lo;
+            P.hi = hi;
+            P.rpb = k.rpb;
+            P.filter = w > 0;
+            P.sums = pl + 2;
+            P.off = pl + 2 + nb;
+            P.n_items = pl;
+            P.item_ctr = A.item_ctr;
+            P.queue_len = &Lv.counters[1];
+            A.edges = P.edges;
+            A.minhit = Lv.minhit + k.begin;
+            A.n_edges = Ek;
+            A.blockoff = P.off;
+            A.win_lo = lo;
+            A.win_hi = hi;
+            A.ranks_per_block = k.rpb;
+            A.max_m = k.max_m;
+            plan_reduce<<<(unsigned)nb, 256, 0, st>>>(P);
+            plan_sums<<<1, 256, 0, st>>>(P, (int)nb);
+            plan_scan<<<(unsigned)nb, 256, 0, st>>>(P);
+            const bool timed = !graph && nev < fpc_ctx::kLaunchEvents;
+            if (timed) (void)hipEventRecord(ctx->lev[2 * nev], st);
+            switch (k.kind) {
+            case K_WIDE: {  // wide levels always run in FP64
+                const void *fn = (const void *)level_kernel_wide<double>;
+                level_kernel_wide<double><<<resident_grid(fn, 64, k.shm, ub, cus, lds_cu), 64, k.shm, st>>>(A, l);
                 break;
             }
-            // wide levels always run in FP64
-            const void *fn = (const void *)level_kernel_wide<double>;
-            level_kernel_wide<double><<<resident_grid(fn, 64, shm, ub, cus), 64, shm, st>>>(A, l);
-        } else if (pair && l >= 3) {
-            err = fp32 ? launch_triple<float>(l, ub, cus, pair_shm, st, A)
-                       : launch_triple<double>(l, ub, cus, pair_shm, st, A);
-        } else if (pair) {
-            err = fp32 ? launch_pair<float>(l, ub, cus, pair_shm, st, A)
-                       : launch_pair<double>(l, ub, cus, pair_shm, st, A);
-        } else {
-            const size_t shm = tile_bytes(Lv.max_m, fp32 ? 4 : 8);
-            const bool tile = shm <= std::min<size_t>(lds_cap, 65536);
-            if (fp32) {
-                if (tile) launch_level<float, true>(l, ub, cus, shm, st, A);
-                else launch_level<float, false>(l, ub, cus, 0, st, A);
-            } else {
-                if (tile) launch_level<double, true>(l, ub, cus, shm, st, A);
-                else launch_level<double, false>(l, ub, cus, 0, st, A);
+            case K_TRIPLE:
+                err = fp32 ? launch_triple<float>(l, ub, cus, lds_cu, k.shm, st, A)
+                           : launch_triple<double>(l, ub, cus, lds_cu, k.shm, st, A);
+                break;
+            case K_PAIR:
+                err = fp32 ? launch_pair<float>(l, ub, cus, lds_cu, k.shm, st, A)
+                           : launch_pair<double>(l, ub, cus, lds_cu, k.shm, st, A);
+                break;
+            case K_TILE:
+                if (fp32) launch_level<float, true>(l, ub, cus, lds_cu, k.shm, st, A);
+                else launch_level<double, true>(l, ub, cus, lds_cu, k.shm, st, A);
+                break;
+            case K_GLOBAL:
+                if (fp32) launch_level<float, false>(l, ub, cus, lds_cu, 0, st, A);
+                else launch_level<double, false>(l, ub, cus, lds_cu, 0, st, A);
+                break;
             }
+            if (timed) {
+                (void)hipEventRecord(ctx->lev[2 * nev + 1], st);
+                ++nev;
+            }
+            ++nlaunch;
+            if (fp32) launch_recheck(l, st, A);  // the next plan empties the queue
+            if (err == hipSuccess) err = hipGetLastError();
+            if (err != hipSuccess) break;
         }
-        if (timed) {
-            (void)hipEventRecord(ctx->lev[2 * nev + 1], st);
-            ++nev;
-        }
-        if (fp32) launch_recheck(l, st, A);  // the next window's plan empties the queue
-        if (err == hipSuccess) err = hipGetLastError();
     }
     if (graph) {
         const hipError_t e2 = hipStreamEndCapture(st, &g);
@@ -1628,8 +1696,8 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
         if (err == hipSuccess) err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         if (err == hipSuccess) err = hipEventRecord(ctx->ev0, st);
         if (err == hipSuccess) err = hipGraphLaunch(ge, st);
-        if (ge) hipGraphExecDestroy(ge);
-        if (g) hipGraphDestroy(g);
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
     }
     FPC_HIP(err);
     FPC_HIP(hipEventRecord(ctx->ev1, st));
@@ -1641,7 +1709,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
         timing->test_ms += ms;
     }
     if (graph) timing->test_ms = timing->all_ms;  // one graph: plans and rechecks included
-    timing->test_launches = graph ? nw : nev;
+    timing->test_launches = nlaunch;
     return FPC_OK;
 }
 

@@ -13,6 +13,7 @@
 // Both renormalise by the computed diagonal, so C_ii = 1 exactly.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -347,6 +348,49 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
     if (hflags[0]) return FPC_ENONFINITE;
     if (hflags[1]) return FPC_ESINGULAR;
     return FPC_OK;
+}
+
+namespace {
+
+// out[r][:] = X[rows[r]][:] (a resample of the rows); an index outside
+// [0, x_rows) sets *bad and leaves the row unwritten.  One workgroup per
+// row at a time, lanes along the row.
+template <typename TX>
+__global__ __launch_bounds__(256) void gather_rows_kernel(const TX *__restrict__ X, int64_t x_rows, int p,
+                                                          const int32_t *__restrict__ rows, int n,
+                                                          TX *__restrict__ out, int *__restrict__ bad)
+{
+    for (int r = blockIdx.x; r < n; r += gridDim.x) {
+        const int32_t src = rows[r];
+        if (src < 0 || (int64_t)src >= x_rows) {
+            if (threadIdx.x == 0) atomicOr(bad, 1);
+            continue;
+        }
+        for (int j = threadIdx.x; j < p; j += 256) out[(size_t)r * p + j] = X[(size_t)src * p + j];
+    }
+}
+
+}  // namespace
+
+int gather_rows(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p, const int32_t *rows, int n,
+                void *out)
+{
+    if (!X || !rows || !out || p < 1 || n < 1) return FPC_EINVAL;
+    hipStream_t st = ctx->stream;
+    int rc = ctx->flag.ensure(64);
+    if (rc) return rc;
+    int *bad = ctx->flag.as<int>() + 8;
+    FPC_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+    const unsigned g = (unsigned)std::min(n, 8 * ctx->num_cus);
+    if (x_dtype == FPC_F64)
+        gather_rows_kernel<double><<<g, 256, 0, st>>>((const double *)X, x_rows, p, rows, n, (double *)out, bad);
+    else
+        gather_rows_kernel<float><<<g, 256, 0, st>>>((const float *)X, x_rows, p, rows, n, (float *)out, bad);
+    FPC_HIP(hipGetLastError());
+    int h = 0;
+    FPC_HIP(hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    FPC_HIP(hipStreamSynchronize(st));
+    return h ? FPC_EINVAL : FPC_OK;
 }
 
 int corr_max_abs_diff(fpc_ctx *ctx, const double *c64, const float *c32, int p, double *out)

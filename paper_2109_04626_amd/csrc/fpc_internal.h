@@ -51,10 +51,11 @@ struct fpc_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int lds_per_block = 65536;  // max dynamic LDS bytes per workgroup
+    int lds_per_cu = 65536;     // LDS bytes per compute unit
     bool use_pair_kernel = true; // shared-prefix kernel for levels l >= 2 (off with FPC_FLAG_PER_TEST_KERNEL)
     int num_cus = 256;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    static constexpr int kLaunchEvents = 64;
+    static constexpr int kLaunchEvents = 256;
     hipEvent_t lev[2 * kLaunchEvents] = {};  // per-launch timing of the test kernels
 
     // binomial table on the device (saturating int64), kBinomRows x kBinomCols
@@ -74,6 +75,7 @@ struct fpc_ctx {
     fpc::DevBuf edges;            // EdgeRec per eligible edge
     fpc::DevBuf blockoff;         // window plan: item counters, workgroup sums, per-edge item prefix
     fpc::DevBuf insts;            // per-instance matrices and thresholds of a level
+    fpc::DevBuf batch_c;          // fpc_skeleton_batch: every instance's correlation matrices
     fpc::DevBuf minhit;           // uint64 per edge: lowest independent rank
     fpc::DevBuf counters;         // uint64 counters (tests executed, queue length, ...)
     fpc::DevBuf queue;            // recheck queue (edge, rank)
@@ -105,6 +107,9 @@ struct EdgeRec {
 // ---- correlation (corr.hip)
 int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out);
 int corr_max_abs_diff(fpc_ctx *ctx, const double *c64, const float *c32, int p, double *out);
+// out (device, n x p) := rows[r] of X (device, x_rows x p); FPC_EINVAL for an index out of range.
+int gather_rows(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p, const int32_t *rows, int n,
+                void *out);
 
 // ---- first level (first_level.hip)
 int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
@@ -119,10 +124,17 @@ struct LevelInst {
     double q;                      // threshold
     double c_err;                  // bound on the entry error of the FP32 matrix
 };
+// A run of consecutive edge records launched together (one size class).
+struct LevelClass {
+    int64_t begin, end;            // edge records [begin, end)
+    int max_m;                     // largest |cand| in the class
+};
 struct LevelLaunch {
     int l;
     int max_m;                     // largest |cand| among the eligible edges
     int64_t n_edges;               // eligible edges (of every instance)
+    const LevelClass *classes;     // host; NULL: one class of every edge
+    int n_classes;
     const EdgeRec *edges;          // device
     const int32_t *cand;           // device
     const LevelInst *insts;        // host, n_insts entries; EdgeRec::inst indexes them
@@ -131,7 +143,8 @@ struct LevelLaunch {
     bool graph;                    // capture the level's launches in one HIP graph
     double band_z;                 // recheck margin in z units
     uint64_t *minhit;              // device, per edge
-    unsigned long long *counters;  // device: [0] executed, [1] queue length, [2] rechecked, [3] overflow
+    unsigned long long *counters;  // device: [1] recheck queue length, [3] queue overflow
+    unsigned long long *inst_cnt;  // device, per instance: [2k] tests executed, [2k+1] re-run in FP64
     int64_t *queue;                // device, 2 * queue_cap entries (edge, rank)
     int64_t queue_cap;
 };
@@ -140,6 +153,9 @@ struct LevelTiming {
     float test_ms = 0.f;      // sum of the test-kernel launches alone
     int test_launches = 0;
 };
+// Size class of an edge with m candidates at level l: edges of one class
+// share a kernel and the number of workgroups that fit on a CU.
+int level_class_key(const fpc_ctx *ctx, int l, bool fp32, int m);
 int level_tests(fpc_ctx *ctx, const LevelLaunch &L, const std::vector<int64_t> &host_ntests,
                 LevelTiming *timing);
 int level_compact(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *out_pairs,
@@ -164,7 +180,8 @@ struct CandSets {
     std::vector<int64_t> off;   // E+1
     std::vector<int32_t> nodes;
 };
-void candidate_sets(const uint8_t *adj, int p, CandSets &out);
+// threads: host threads for the merge (0: up to 16).
+void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads = 0);
 
 // ---- quantile (quantile.cpp)
 double normal_quantile_upper(double alpha);  // Phi^{-1}(1 - alpha/2)

@@ -121,7 +121,7 @@ void edge_blocks(const Adjacency &g, int p, std::vector<int32_t> &block)
 
 }  // namespace
 
-void candidate_sets(const uint8_t *adj, int p, CandSets &out)
+void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
 {
     Adjacency g;
     build_adjacency(adj, p, g);
@@ -168,7 +168,7 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out)
         }
     };
     unsigned hw = std::thread::hardware_concurrency();
-    int nth = (int)std::min<unsigned>(hw ? hw : 1, 16u);
+    int nth = threads > 0 ? threads : (int)std::min<unsigned>(hw ? hw : 1, 16u);
     if (E < 2048) nth = 1;
     std::vector<std::vector<int32_t>> parts(nth);
     std::vector<std::vector<int64_t>> lens(nth);

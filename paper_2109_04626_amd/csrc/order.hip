@@ -19,24 +19,21 @@ namespace fpc {
 
 namespace {
 
-__global__ __launch_bounds__(256) void features_kernel(const EdgeRec *__restrict__ edges, int64_t n_edges,
-                                                       const int32_t *__restrict__ cand, int64_t n_pos,
-                                                       const double *__restrict__ C, const double *__restrict__ R,
-                                                       const int32_t *__restrict__ deg, int p, float *__restrict__ X)
+// One wave per edge, lanes over its candidate positions (the edge records
+// need not be in list order).
+__global__ __launch_bounds__(64) void features_kernel(const EdgeRec *__restrict__ edges,
+                                                      const int32_t *__restrict__ cand,
+                                                      const double *__restrict__ C, const double *__restrict__ R,
+                                                      const int32_t *__restrict__ deg, int p, float *__restrict__ X)
 {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_pos) return;
-    int64_t lo = 0, hi = n_edges;  // edges[lo].cand_off <= t < edges[lo + 1].cand_off
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (edges[mid].cand_off <= t) lo = mid;
-        else hi = mid;
+    const EdgeRec E = edges[blockIdx.x];
+    for (int a = threadIdx.x; a < E.m; a += 64) {
+        const int64_t t = (int64_t)E.cand_off + a;
+        const int k = cand[t];
+        X[3 * t + 0] = (float)fmax(fabs(C[(size_t)E.i * p + k]), fabs(C[(size_t)E.j * p + k]));
+        X[3 * t + 1] = (float)fmax(fabs(R[(size_t)E.i * p + k]), fabs(R[(size_t)E.j * p + k]));
+        X[3 * t + 2] = (float)deg[k] / (float)(p - 1);
     }
-    const EdgeRec E = edges[lo];
-    const int k = cand[t];
-    X[3 * t + 0] = (float)fmax(fabs(C[(size_t)E.i * p + k]), fabs(C[(size_t)E.j * p + k]));
-    X[3 * t + 1] = (float)fmax(fabs(R[(size_t)E.i * p + k]), fabs(R[(size_t)E.j * p + k]));
-    X[3 * t + 2] = (float)deg[k] / (float)(p - 1);
 }
 
 // One block per edge: position a goes to rank(a) = #{b : s_b > s_a or
@@ -68,9 +65,9 @@ __global__ __launch_bounds__(256) void reorder_kernel(const EdgeRec *__restrict_
 int level_features(fpc_ctx *ctx, const EdgeRec *edges, int64_t n_edges, const int32_t *cand, int64_t n_pos,
                    const double *C, const double *R, const int32_t *deg, int p, float *X)
 {
-    if (n_pos == 0) return FPC_OK;
-    features_kernel<<<(unsigned)((n_pos + 255) / 256), 256, 0, ctx->stream>>>(edges, n_edges, cand, n_pos, C, R,
-                                                                             deg, p, X);
+    if (n_pos == 0 || n_edges == 0) return FPC_OK;
+    if (n_edges > 0x7fffffffLL) return FPC_EINVAL;
+    features_kernel<<<(unsigned)n_edges, 64, 0, ctx->stream>>>(edges, cand, C, R, deg, p, X);
     FPC_HIP(hipGetLastError());
     return FPC_OK;
 }

@@ -12,8 +12,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -102,6 +105,16 @@ double now_ms()
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// FPC_TRACE=1 in the environment: phase timings of each level on stderr.
+bool trace_on()
+{
+    static const bool on = [] {
+        const char *v = std::getenv("FPC_TRACE");
+        return v && *v && *v != '0';
+    }();
+    return on;
+}
+
 inline int64_t pair_index(int i, int j, int p)
 {
     return (int64_t)i * p - (int64_t)i * (i + 1) / 2 + (j - i - 1);
@@ -183,6 +196,10 @@ extern "C" int fpc_create(fpc_ctx **out, int hip_device, void *hip_stream)
         c->lds_per_block = v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && v > 0)
         c->num_cus = v;
+    c->lds_per_cu = c->lds_per_block;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, hip_device) == hipSuccess &&
+        v > c->lds_per_cu)
+        c->lds_per_cu = v;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
@@ -229,7 +246,7 @@ extern "C" int fpc_destroy(fpc_ctx *c)
     DevBuf *bufs[] = {&c->binom, &c->x_copy, &c->colstat, &c->c64, &c->c32, &c->zsplit, &c->inv_work,
                       &c->flag, &c->cand, &c->edges, &c->blockoff, &c->minhit, &c->counters,
                       &c->queue, &c->dellist, &c->batch_tmp, &c->mlp_grad, &c->rfirst, &c->feat,
-                      &c->cand2, &c->degs, &c->insts};
+                      &c->cand2, &c->degs, &c->insts, &c->batch_c};
     for (DevBuf *b : bufs) b->release();
     c->h_stage.release();
     c->h_back.release();
@@ -285,182 +302,300 @@ struct Run {
     int32_t log_serial = 0;
 };
 
-// Runs one level (l >= 0) on the frozen graph with precomputed candidate
-// sets; applies its deletions at the end.
-int run_level(Run &R, int l, const CandSets &cs, fpc_level_stats &st)
+// Runs fn(k) for k in [0, n) on up to 16 host threads (inline when n is 1).
+template <class F>
+void parallel_for(int n, F &&fn)
 {
-    fpc_ctx *ctx = R.ctx;
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int nth = std::min(n, (int)std::min<unsigned>(hw ? hw : 1, 16u));
+    if (nth <= 1) {
+        for (int k = 0; k < n; ++k) fn(k);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nth; ++t)
+        pool.emplace_back([&] {
+            for (int k = next++; k < n; k = next++) fn(k);
+        });
+    for (auto &th : pool) th.join();
+}
+
+// Runs one level (l >= 0) of one or more instances, each on its frozen
+// graph with precomputed candidate sets, in shared launches; applies every
+// instance's deletions at the end.  The learned order and feature logging
+// are available for a single instance only.
+int run_level(const std::vector<Run *> &runs, int l, const std::vector<const CandSets *> &css,
+              std::vector<fpc_level_stats> &sts)
+{
+    const int ni = (int)runs.size();
+    fpc_ctx *ctx = runs[0]->ctx;
     hipStream_t s = ctx->stream;
     const double t0 = now_ms();
-    std::memset(&st, 0, sizeof(st));
-    st.level = l;
-    const int64_t Eall = (int64_t)cs.ei.size();
-    std::vector<int64_t> sel;
-    int max_m = 0;
-    for (int64_t e = 0; e < Eall; ++e) {
-        const int m = (int)(cs.off[e + 1] - cs.off[e]);
-        max_m = std::max(max_m, m);
-        if (m >= l) sel.push_back(e);
+    sts.assign(ni, fpc_level_stats{});
+    // pass 1: eligible edges, list lengths and test counts per instance
+    std::vector<int64_t> n_el(ni, 0), n_cd(ni, 0);
+    std::vector<int> mx(ni, 0), bad(ni, 0);
+    parallel_for(ni, [&](int k) {
+        const CandSets &cs = *css[k];
+        fpc_level_stats &st = sts[k];
+        st.level = l;
+        const int64_t Eall = (int64_t)cs.ei.size();
+        int max_m = 0, sel_m = 0;
+        int64_t possible = 0;
+        for (int64_t e = 0; e < Eall; ++e) {
+            const int m = (int)(cs.off[e + 1] - cs.off[e]);
+            max_m = std::max(max_m, m);
+            if (m < l) continue;
+            if (m >= kBinomRows) {
+                bad[k] = 1;
+                return;
+            }
+            const int64_t N = binom_sat(m, l);
+            if (N == INT64_MAX || possible > INT64_MAX - N) {
+                bad[k] = 1;
+                return;
+            }
+            possible += N;
+            ++n_el[k];
+            n_cd[k] += m;
+            sel_m = std::max(sel_m, m);
+        }
+        st.max_cand = max_m;
+        st.edges_eligible = n_el[k];
+        st.tests_possible = possible;
+        mx[k] = sel_m;
+    });
+    int64_t E = 0, T = 0;
+    int sel_max_m = 0;
+    std::vector<int64_t> e_off(ni), c_off(ni);
+    for (int k = 0; k < ni; ++k) {
+        if (bad[k]) return FPC_EBUDGET;
+        Run &R = *runs[k];
+        if (R.P->max_tests > 0 && R.spent_possible + sts[k].tests_possible > R.P->max_tests) return FPC_EBUDGET;
+        R.spent_possible += sts[k].tests_possible;
+        e_off[k] = E;
+        c_off[k] = T;
+        E += n_el[k];
+        T += n_cd[k];
+        sel_max_m = std::max(sel_max_m, mx[k]);
     }
-    st.max_cand = max_m;
-    const int64_t E = (int64_t)sel.size();
-    st.edges_eligible = E;
+    if (T > INT32_MAX) return FPC_EBUDGET;
     if (E == 0) {
-        st.level_ms = now_ms() - t0;
+        for (auto &st : sts) st.level_ms = now_ms() - t0;
         return FPC_OK;
     }
-    std::vector<EdgeRec> recs(E);
-    std::vector<int64_t> ntests(E);
-    std::vector<int32_t> cand;
-    int sel_max_m = 0;
-    int64_t possible = 0;
-    for (int64_t k = 0; k < E; ++k) {
-        const int64_t e = sel[k];
-        const int m = (int)(cs.off[e + 1] - cs.off[e]);
-        if (m >= kBinomRows) return FPC_EBUDGET;
-        const int64_t N = binom_sat(m, l);
-        if (N == INT64_MAX || possible > INT64_MAX - N) return FPC_EBUDGET;
-        possible += N;
-        sel_max_m = std::max(sel_max_m, m);
-        recs[k] = EdgeRec{cs.ei[e], cs.ej[e], m, (int32_t)cand.size(), N, 0, 0};
-        ntests[k] = N;
-        cand.insert(cand.end(), cs.nodes.begin() + cs.off[e], cs.nodes.begin() + cs.off[e + 1]);
-    }
-    st.tests_possible = possible;
-    if (R.P->max_tests > 0 && R.spent_possible + possible > R.P->max_tests) return FPC_EBUDGET;
-    R.spent_possible += possible;
-
+    // pass 2: records and lists straight into the pinned staging buffer
     int rc;
-    if ((rc = ctx->edges.ensure(sizeof(EdgeRec) * E))) return rc;
-    if ((rc = ctx->cand.ensure(sizeof(int32_t) * (cand.size() + 1)))) return rc;
-    if ((rc = ctx->minhit.ensure(sizeof(uint64_t) * E))) return rc;
-    if ((rc = ctx->counters.ensure(sizeof(unsigned long long) * 8))) return rc;
-    const size_t up = sizeof(EdgeRec) * E + sizeof(int32_t) * (cand.size() + 1);
+    const size_t up = sizeof(EdgeRec) * E + sizeof(int32_t) * (T + 1);
     FPC_HIP(hipStreamSynchronize(s));  // the staging buffer is free
     if ((rc = ctx->h_stage.ensure(up))) return rc;
-    std::memcpy(ctx->h_stage.ptr, recs.data(), sizeof(EdgeRec) * E);
-    std::memcpy(ctx->h_stage.as<char>() + sizeof(EdgeRec) * E, cand.data(), sizeof(int32_t) * cand.size());
-    FPC_HIP(hipMemcpyAsync(ctx->edges.ptr, ctx->h_stage.ptr, sizeof(EdgeRec) * E, hipMemcpyHostToDevice, s));
-    if (!cand.empty())
-        FPC_HIP(hipMemcpyAsync(ctx->cand.ptr, ctx->h_stage.as<char>() + sizeof(EdgeRec) * E,
-                               sizeof(int32_t) * cand.size(), hipMemcpyHostToDevice, s));
+    EdgeRec *hrec = ctx->h_stage.as<EdgeRec>();
+    int32_t *cand = reinterpret_cast<int32_t *>(hrec + E);  // lists, in instance order
+    std::vector<int64_t> cs_edge(E);  // edge index of each record in its instance's candidate sets
+    parallel_for(ni, [&](int k) {
+        const CandSets &cs = *css[k];
+        int64_t r = e_off[k], c = c_off[k];
+        for (int64_t e = 0; e < (int64_t)cs.ei.size(); ++e) {
+            const int m = (int)(cs.off[e + 1] - cs.off[e]);
+            if (m < l) continue;
+            hrec[r] = EdgeRec{cs.ei[e], cs.ej[e], m, (int32_t)c, binom_sat(m, l), k, 0};
+            cs_edge[r] = e;
+            std::memcpy(cand + c, cs.nodes.data() + cs.off[e], sizeof(int32_t) * m);
+            ++r;
+            c += m;
+        }
+    });
+    // size classes of the candidate lists: each class is launched with the
+    // LDS its own largest list needs, so a few long lists do not lower the
+    // occupancy (or the kernel choice) of all the others; a stable counting
+    // sort of the records by class keeps each instance's edges together
+    std::vector<EdgeRec> recs(E);
+    std::vector<int64_t> ntests(E);
+    std::vector<LevelClass> classes;
+    {
+        const bool fp32_cls = runs[0]->mixed && l <= kMaxTemplL;
+        std::vector<int> key_of(sel_max_m + 1);
+        int kmax = 0;
+        for (int m = 0; m <= sel_max_m; ++m) kmax = std::max(kmax, key_of[m] = level_class_key(ctx, l, fp32_cls, m));
+        std::vector<int64_t> cnt_k(kmax + 2, 0), c2(E);
+        for (int64_t k = 0; k < E; ++k) ++cnt_k[key_of[hrec[k].m] + 1];
+        for (int c = 0; c <= kmax; ++c) cnt_k[c + 1] += cnt_k[c];
+        for (int64_t k = 0; k < E; ++k) {
+            const int64_t d = cnt_k[key_of[hrec[k].m]]++;
+            recs[d] = hrec[k];
+            ntests[d] = recs[d].ntests;
+            c2[d] = cs_edge[k];
+        }
+        cs_edge.swap(c2);
+        std::memcpy(hrec, recs.data(), sizeof(EdgeRec) * E);
+        for (int64_t k = 0; k < E; ++k) {
+            const int c = key_of[recs[k].m];
+            if (classes.empty() || key_of[recs[classes.back().begin].m] != c) classes.push_back({k, k, 0});
+            classes.back().end = k + 1;
+            classes.back().max_m = std::max(classes.back().max_m, recs[k].m);
+        }
+    }
+
+    const double t_build = now_ms();
+    if ((rc = ctx->edges.ensure(sizeof(EdgeRec) * E))) return rc;
+    if ((rc = ctx->cand.ensure(sizeof(int32_t) * (T + 1)))) return rc;
+    if ((rc = ctx->minhit.ensure(sizeof(uint64_t) * E))) return rc;
+    if ((rc = ctx->counters.ensure(sizeof(unsigned long long) * (8 + 2 * (size_t)ni)))) return rc;
+    FPC_HIP(hipMemcpyAsync(ctx->edges.ptr, hrec, sizeof(EdgeRec) * E, hipMemcpyHostToDevice, s));
+    if (T) FPC_HIP(hipMemcpyAsync(ctx->cand.ptr, cand, sizeof(int32_t) * T, hipMemcpyHostToDevice, s));
     // learned order: features, MLP scores, per-edge reorder of the lists
     // (at l = 0 each edge has one subset, so the order cannot matter)
+    Run &R0 = *runs[0];
     std::vector<float> hfeat;
     const int32_t *d_cand = ctx->cand.as<int32_t>();
-    const bool reorder = R.learned && l >= 1;
-    if (reorder || R.logging) {
-        const int64_t T = (int64_t)cand.size();
-        std::vector<int32_t> deg(R.p, 0);  // degrees in the current graph, from its edge list
+    const bool reorder = ni == 1 && R0.learned && l >= 1;
+    const bool logging = ni == 1 && R0.logging;
+    if (reorder || logging) {
+        const CandSets &cs = *css[0];
+        std::vector<int32_t> deg(R0.p, 0);  // degrees in the current graph, from its edge list
         for (size_t e = 0; e < cs.ei.size(); ++e) {
             ++deg[cs.ei[e]];
             ++deg[cs.ej[e]];
         }
-        if ((rc = ctx->degs.ensure(sizeof(int32_t) * R.p))) return rc;
+        if ((rc = ctx->degs.ensure(sizeof(int32_t) * R0.p))) return rc;
         if ((rc = ctx->feat.ensure(sizeof(float) * 4 * (size_t)(T + 1)))) return rc;
         if ((rc = ctx->cand2.ensure(sizeof(int32_t) * (size_t)(T + 1)))) return rc;
-        FPC_HIP(hipMemcpyAsync(ctx->degs.ptr, deg.data(), sizeof(int32_t) * R.p, hipMemcpyHostToDevice, s));
+        FPC_HIP(hipMemcpyAsync(ctx->degs.ptr, deg.data(), sizeof(int32_t) * R0.p, hipMemcpyHostToDevice, s));
         float *X = ctx->feat.as<float>(), *score = X + 3 * T;
-        if ((rc = level_features(ctx, ctx->edges.as<EdgeRec>(), E, d_cand, T, R.C64, R.Rfirst,
-                                 ctx->degs.as<int32_t>(), R.p, X)))
+        if ((rc = level_features(ctx, ctx->edges.as<EdgeRec>(), E, d_cand, T, R0.C64, R0.Rfirst,
+                                 ctx->degs.as<int32_t>(), R0.p, X)))
             return rc;
         if (reorder) {
-            if ((rc = mlp_forward(ctx, X, T, R.P->order_model, score))) return rc;
+            if ((rc = mlp_forward(ctx, X, T, R0.P->order_model, score))) return rc;
             if ((rc = level_reorder(ctx, ctx->edges.as<EdgeRec>(), E, d_cand, score, ctx->cand2.as<int32_t>())))
                 return rc;
             d_cand = ctx->cand2.as<int32_t>();
         }
-        if (R.logging) {
+        if (logging) {
             hfeat.resize(3 * (size_t)T);
             // features follow the original order; the reorder maps them
             FPC_HIP(hipMemcpyAsync(hfeat.data(), X, sizeof(float) * 3 * T, hipMemcpyDeviceToHost, s));
             FPC_HIP(hipStreamSynchronize(s));
         }
     }
-    bool fp32 = R.mixed && l <= kMaxTemplL;
+    std::vector<LevelInst> insts(ni);
+    for (int k = 0; k < ni; ++k) {
+        const Run &R = *runs[k];
+        insts[k] = LevelInst{R.C32, R.C64, R.p, R.n, R.q, R.c_err};
+    }
+    bool fp32 = R0.mixed && l <= kMaxTemplL;
     if (fp32 && (rc = ctx->queue.ensure(sizeof(int64_t) * 2 * kQueueCap))) return rc;
+    std::vector<unsigned long long> cnt(8 + 2 * (size_t)ni);
+    LevelLaunch Lv{};
+    LevelTiming tm;
+    std::vector<int64_t> pairs(2 * E);
+    int64_t ndel = 0;
+    double t_tests0 = 0.0, t_tests1 = 0.0;
 retry:
     FPC_HIP(hipMemsetAsync(ctx->minhit.ptr, 0xff, sizeof(uint64_t) * E, s));
-    FPC_HIP(hipMemsetAsync(ctx->counters.ptr, 0, sizeof(unsigned long long) * 8, s));
-
-    LevelLaunch Lv{};
+    FPC_HIP(hipMemsetAsync(ctx->counters.ptr, 0, sizeof(unsigned long long) * cnt.size(), s));
     Lv.l = l;
     Lv.max_m = sel_max_m;
     Lv.n_edges = E;
+    Lv.classes = classes.data();
+    Lv.n_classes = (int)classes.size();
     Lv.edges = ctx->edges.as<EdgeRec>();
     Lv.cand = d_cand;
-    const LevelInst inst{R.C32, R.C64, R.p, R.n, R.q, R.c_err};
-    Lv.insts = &inst;
-    Lv.n_insts = 1;
+    Lv.insts = insts.data();
+    Lv.n_insts = ni;
     Lv.fp32 = fp32;
-    Lv.graph = (R.P->flags & FPC_FLAG_GRAPH) != 0;
-    Lv.band_z = R.P->recheck_margin > 0 ? R.P->recheck_margin : 1e-3;
+    Lv.graph = (R0.P->flags & FPC_FLAG_GRAPH) != 0;
+    Lv.band_z = R0.P->recheck_margin > 0 ? R0.P->recheck_margin : 1e-3;
     Lv.minhit = ctx->minhit.as<uint64_t>();
     Lv.counters = ctx->counters.as<unsigned long long>();
+    Lv.inst_cnt = Lv.counters + 8;
     Lv.queue = fp32 ? ctx->queue.as<int64_t>() : nullptr;
     Lv.queue_cap = fp32 ? kQueueCap : 0;
-    LevelTiming tm;
+    t_tests0 = now_ms();
     if ((rc = level_tests(ctx, Lv, ntests, &tm))) return rc;
+    t_tests1 = now_ms();
     // the host decodes separating sets against the lists the level used
-    // (through the pinned stage: the upload that read it precedes this
-    // copy on the stream)
-    if (reorder && !cand.empty())
-        FPC_HIP(hipMemcpyAsync(ctx->h_stage.ptr, d_cand, sizeof(int32_t) * cand.size(), hipMemcpyDeviceToHost, s));
-    st.kernel_ms = tm.all_ms;
-    st.test_kernel_ms = tm.test_ms;
-    st.test_launches = tm.test_launches;
-
-    std::vector<int64_t> pairs(2 * E);
-    int64_t ndel = 0;
+    // (the uploads that read the staging buffer precede this copy on the stream)
+    if (reorder && T)
+        FPC_HIP(hipMemcpyAsync(cand, d_cand, sizeof(int32_t) * T, hipMemcpyDeviceToHost, s));
     if ((rc = level_compact(ctx, Lv.minhit, E, pairs.data(), &ndel))) return rc;
-    unsigned long long cnt[8];
-    FPC_HIP(hipMemcpyAsync(cnt, Lv.counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    FPC_HIP(hipMemcpyAsync(cnt.data(), Lv.counters, sizeof(unsigned long long) * cnt.size(),
+                           hipMemcpyDeviceToHost, s));
     FPC_HIP(hipStreamSynchronize(s));
-    st.tests_executed = (int64_t)cnt[0];
-    st.tests_rechecked = (int64_t)cnt[2];
-    R.total_exec += st.tests_executed;
+    for (int k = 0; k < ni; ++k) {
+        sts[k].tests_executed += (int64_t)cnt[8 + 2 * k];
+        sts[k].tests_rechecked += (int64_t)cnt[8 + 2 * k + 1];
+        runs[k]->total_exec += (int64_t)cnt[8 + 2 * k];
+    }
     if (cnt[3]) {  // the recheck queue overflowed: run the whole level again in FP64
         fp32 = false;
         goto retry;
     }
-    if (reorder && !cand.empty()) std::memcpy(cand.data(), ctx->h_stage.ptr, sizeof(int32_t) * cand.size());
 
-    // sepsets and level-end deletion (stable: all of D at once)
+    const double t_decode = now_ms();
+    // sepsets and level-end deletion (stable: all of D at once), each
+    // instance's deletions in pair order (the records are in class order)
     std::vector<std::pair<int64_t, int64_t>> dl(ndel);
     for (int64_t k = 0; k < ndel; ++k) dl[k] = {pairs[2 * k], pairs[2 * k + 1]};
-    std::sort(dl.begin(), dl.end());
-    std::vector<int> pos;
-    for (const auto &d : dl) {
-        const EdgeRec &er = recs[d.first];
-        unrank_host(d.second, er.m, l, ctx->binom_host, pos);
-        const int64_t pr = pair_index(er.i, er.j, R.p);
-        R.sep.level[pr] = l;
-        R.sep.kind[pr] = FPC_SEP_LIST;
-        const size_t o = R.sep.nodes.size();
-        R.sep.lists.emplace_back(pr, (int64_t)o);
-        for (int t = 0; t < l; ++t) R.sep.nodes.push_back(cand[er.cand_off + pos[t]]);
-        std::sort(R.sep.nodes.begin() + o, R.sep.nodes.end());
-        if (R.logging) {
-            // features were computed over the list sorted by id (the cs order)
-            const int32_t *orig = cs.nodes.data() + cs.off[sel[d.first]];
-            const int32_t *S = R.sep.nodes.data() + o;
-            for (int a = 0; a < er.m; ++a) {
-                const int k = orig[a];
-                const bool in = std::binary_search(S, S + l, k);
-                for (int f = 0; f < 3; ++f) R.log_x.push_back(hfeat[3 * ((size_t)er.cand_off + a) + f]);
-                R.log_y.push_back(in ? 1 : 0);
-                R.log_group.push_back(R.log_serial);
-                R.log_level.push_back(l);
+    std::sort(dl.begin(), dl.end(), [&](const std::pair<int64_t, int64_t> &a, const std::pair<int64_t, int64_t> &b) {
+        const EdgeRec &x = recs[a.first], &y = recs[b.first];
+        if (x.inst != y.inst) return x.inst < y.inst;
+        if (x.i != y.i) return x.i < y.i;
+        return x.j < y.j;
+    });
+    std::vector<int64_t> d_lo(ni + 1, 0);  // deletions of instance k: dl[d_lo[k], d_lo[k+1])
+    for (const auto &d : dl) ++d_lo[recs[d.first].inst + 1];
+    for (int k = 0; k < ni; ++k) d_lo[k + 1] += d_lo[k];
+    parallel_for(ni, [&](int k) {
+        Run &R = *runs[k];
+        std::vector<int> pos;
+        for (int64_t t = d_lo[k]; t < d_lo[k + 1]; ++t) {
+            const auto &d = dl[t];
+            const EdgeRec &er = recs[d.first];
+            unrank_host(d.second, er.m, l, ctx->binom_host, pos);
+            const int64_t pr = pair_index(er.i, er.j, R.p);
+            R.sep.level[pr] = l;
+            R.sep.kind[pr] = FPC_SEP_LIST;
+            const size_t o = R.sep.nodes.size();
+            R.sep.lists.emplace_back(pr, (int64_t)o);
+            for (int q = 0; q < l; ++q) R.sep.nodes.push_back(cand[er.cand_off + pos[q]]);
+            std::sort(R.sep.nodes.begin() + o, R.sep.nodes.end());
+            ++sts[k].deleted;
+            if (logging) {
+                // features were computed over the list sorted by id (the cs order)
+                const CandSets &cs = *css[0];
+                const int32_t *orig = cs.nodes.data() + cs.off[cs_edge[d.first]];
+                const int32_t *S = R.sep.nodes.data() + o;
+                for (int a2 = 0; a2 < er.m; ++a2) {
+                    const int v = orig[a2];
+                    const bool in = std::binary_search(S, S + l, v);
+                    for (int f = 0; f < 3; ++f) R.log_x.push_back(hfeat[3 * ((size_t)er.cand_off + a2) + f]);
+                    R.log_y.push_back(in ? 1 : 0);
+                    R.log_group.push_back(R.log_serial);
+                    R.log_level.push_back(l);
+                }
+                ++R.log_serial;
             }
-            ++R.log_serial;
         }
+        for (int64_t t = d_lo[k]; t < d_lo[k + 1]; ++t) {
+            const EdgeRec &er = recs[dl[t].first];
+            R.adj[(size_t)er.i * R.p + er.j] = R.adj[(size_t)er.j * R.p + er.i] = 0;
+        }
+    });
+    const double level_ms = now_ms() - t0;
+    if (trace_on())
+        std::fprintf(stderr,
+                     "[fpc] level %d: %d instance(s) %lld edges %lld candidates %d classes | setup %.2f upload+order "
+                     "%.2f tests %.2f (device %.2f) compact %.2f decode %.2f ms | deleted %lld\n",
+                     l, ni, (long long)E, (long long)T, (int)classes.size(), t_build - t0, t_tests0 - t_build,
+                     t_tests1 - t_tests0, tm.all_ms, t_decode - t_tests1, now_ms() - t_decode, (long long)ndel);
+    for (auto &st : sts) {
+        st.kernel_ms = tm.all_ms;
+        st.test_kernel_ms = tm.test_ms;
+        st.test_launches = tm.test_launches;
+        st.level_ms = level_ms;
     }
-    for (const auto &d : dl) {
-        const EdgeRec &er = recs[d.first];
-        R.adj[(size_t)er.i * R.p + er.j] = R.adj[(size_t)er.j * R.p + er.i] = 0;
-    }
-    st.deleted = ndel;
-    st.level_ms = now_ms() - t0;
     return FPC_OK;
 }
 
@@ -479,123 +614,102 @@ int validate(const fpc_params *P)
     return FPC_OK;
 }
 
-int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
+// Instance state before the levels: the complete graph, no separating sets.
+void init_run(Run &R, fpc_ctx *ctx, const fpc_params *P, int p, int n)
 {
-    const double t_start = now_ms();
-    int rc = validate(P);
-    if (rc) return rc;
-    FPC_HIP(hipSetDevice(ctx->device));
-    ctx->use_pair_kernel = !(P->flags & FPC_FLAG_PER_TEST_KERNEL);
-    Run R;
     R.ctx = ctx;
     R.P = P;
-    R.p = P->p;
-    R.n = P->n;
+    R.p = p;
+    R.n = n;
     R.q = std::isnan(P->q_override) ? normal_quantile_upper(P->alpha) : P->q_override;
     R.mixed = P->precision == FPC_PREC_MIXED;
     R.learned = P->order == FPC_ORDER_LEARNED;
     R.logging = (P->flags & FPC_FLAG_LOG_FEATURES) != 0 && P->schedule == FPC_REVERSE;
-    const int p = P->p, n = P->n;
     const size_t pp = (size_t)p * p;
-    hipStream_t s = ctx->stream;
-
-    // data on the device
-    const void *X = P->X;
-    if (!P->x_on_device) {
-        const size_t bytes = (size_t)n * p * (P->x_dtype == FPC_F64 ? 8 : 4);
-        if ((rc = ctx->x_copy.ensure(bytes))) return rc;
-        FPC_HIP(hipMemcpyAsync(ctx->x_copy.ptr, P->X, bytes, hipMemcpyHostToDevice, s));
-        X = ctx->x_copy.ptr;
-    }
-    // correlation matrices
-    double t0 = now_ms();
-    if ((rc = ctx->c64.ensure(sizeof(double) * pp))) return rc;
-    if ((rc = corr_compute(ctx, X, P->x_dtype, n, p, FPC_CORR_FP64, ctx->c64.ptr))) return rc;
-    R.C64 = ctx->c64.as<double>();
-    if (R.mixed) {
-        if ((rc = ctx->c32.ensure(sizeof(float) * pp))) return rc;
-        if ((rc = corr_compute(ctx, X, P->x_dtype, n, p, FPC_CORR_BF16X3, ctx->c32.ptr))) return rc;
-        R.C32 = ctx->c32.as<float>();
-        if ((rc = corr_max_abs_diff(ctx, R.C64, R.C32, p, &R.c_err))) return rc;
-    }
-    const double corr_ms = now_ms() - t0;
-
     R.adj.assign(pp, 1);
     for (int i = 0; i < p; ++i) R.adj[(size_t)i * p + i] = 0;
     R.sep.reset((int64_t)p * (p - 1) / 2);
-    double first_ms = 0.0;
-    const int cap = P->max_level;
-    CandSets cs;
-    if (P->schedule == FPC_REVERSE) {
-        // l = p - 2 on the complete graph, through Omega = C^{-1}
-        t0 = now_ms();
-        fpc_level_stats st{};
-        st.level = p - 2;
-        st.max_cand = p - 2;
-        st.edges_eligible = st.tests_possible = st.tests_executed = (int64_t)p * (p - 1) / 2;
-        if ((rc = ctx->flag.ensure(64))) return rc;
-        if ((rc = ctx->dellist.ensure(pp))) return rc;
-        uint8_t *d_ind = ctx->dellist.as<uint8_t>();
-        FPC_HIP(hipEventRecord(ctx->ev0, s));
-        double *d_r = nullptr;
-        if (R.learned || R.logging) {
-            if ((rc = ctx->rfirst.ensure(sizeof(double) * pp))) return rc;
-            d_r = ctx->rfirst.as<double>();
-            R.Rfirst = d_r;
-        }
-        if ((rc = first_level(ctx, R.C64, p, n, R.q, d_r, d_ind, nullptr))) return rc;
-        FPC_HIP(hipEventRecord(ctx->ev1, s));
-        std::vector<uint8_t> ind(pp);
-        FPC_HIP(hipMemcpyAsync(ind.data(), d_ind, pp, hipMemcpyDeviceToHost, s));
-        FPC_HIP(hipStreamSynchronize(s));
-        float kms = 0.f;
-        FPC_HIP(hipEventElapsedTime(&kms, ctx->ev0, ctx->ev1));
-        st.kernel_ms = kms;
-        int64_t dels = 0;
-        for (int i = 0; i < p; ++i)
-            for (int j = i + 1; j < p; ++j)
-                if (ind[(size_t)i * p + j]) {
-                    const int64_t pr = pair_index(i, j, p);
-                    R.sep.level[pr] = p - 2;
-                    R.sep.kind[pr] = FPC_SEP_ALL_BUT;
-                    R.adj[(size_t)i * p + j] = R.adj[(size_t)j * p + i] = 0;
-                    ++dels;
-                }
-        st.deleted = dels;
-        R.total_exec += st.tests_executed;
-        R.spent_possible += st.tests_possible;
-        first_ms = now_ms() - t0;
-        st.level_ms = first_ms;
-        R.levels.push_back(st);
-        // following levels: l = min(p-3, cap, largest candidate set), down to 0
-        int l = p - 3;
-        if (cap >= 0) l = std::min(l, cap);
-        while (l >= 0) {
-            candidate_sets(R.adj.data(), p, cs);
-            int mmax = -1;
-            for (size_t e = 0; e + 1 < cs.off.size(); ++e) mmax = std::max<int>(mmax, (int)(cs.off[e + 1] - cs.off[e]));
-            if (mmax < 0) break;  // no edges left
-            l = std::min(l, mmax);
-            fpc_level_stats lv{};
-            if ((rc = run_level(R, l, cs, lv))) return rc;
-            R.levels.push_back(lv);
-            --l;
-        }
-    } else {
-        // Algorithm 1: l = 0, 1, ... while some edge has |cand| >= l
-        for (int l = 0;; ++l) {
-            if (cap >= 0 && l > cap) break;
-            candidate_sets(R.adj.data(), p, cs);
-            int mmax = -1;
-            for (size_t e = 0; e + 1 < cs.off.size(); ++e) mmax = std::max<int>(mmax, (int)(cs.off[e + 1] - cs.off[e]));
-            if (mmax < l) break;
-            fpc_level_stats lv{};
-            if ((rc = run_level(R, l, cs, lv))) return rc;
-            R.levels.push_back(lv);
-        }
-    }
+}
 
-    // result
+// Correlation matrices of the instance's data (device, n x p row-major):
+// FP64 into C64, and in the mixed form the bf16x3 FP32 copy into C32 with
+// its largest entry error against C64.
+int corr_stage(Run &R, const void *X, int x_dtype, double *C64, float *C32, double *ms)
+{
+    const double t0 = now_ms();
+    int rc;
+    if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_FP64, C64))) return rc;
+    R.C64 = C64;
+    if (R.mixed) {
+        if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_BF16X3, C32))) return rc;
+        R.C32 = C32;
+        if ((rc = corr_max_abs_diff(R.ctx, R.C64, R.C32, R.p, &R.c_err))) return rc;
+    }
+    *ms = now_ms() - t0;
+    return FPC_OK;
+}
+
+// The l = p - 2 level on the complete graph, through Omega = C^{-1}.
+int first_stage(Run &R, double *ms)
+{
+    fpc_ctx *ctx = R.ctx;
+    hipStream_t s = ctx->stream;
+    const int p = R.p;
+    const size_t pp = (size_t)p * p;
+    const double t0 = now_ms();
+    fpc_level_stats st{};
+    st.level = p - 2;
+    st.max_cand = p - 2;
+    st.edges_eligible = st.tests_possible = st.tests_executed = (int64_t)p * (p - 1) / 2;
+    int rc;
+    if ((rc = ctx->flag.ensure(64))) return rc;
+    if ((rc = ctx->dellist.ensure(pp))) return rc;
+    uint8_t *d_ind = ctx->dellist.as<uint8_t>();
+    FPC_HIP(hipEventRecord(ctx->ev0, s));
+    double *d_r = nullptr;
+    if (R.learned || R.logging) {
+        if ((rc = ctx->rfirst.ensure(sizeof(double) * pp))) return rc;
+        d_r = ctx->rfirst.as<double>();
+        R.Rfirst = d_r;
+    }
+    if ((rc = first_level(ctx, R.C64, p, R.n, R.q, d_r, d_ind, nullptr))) return rc;
+    FPC_HIP(hipEventRecord(ctx->ev1, s));
+    std::vector<uint8_t> ind(pp);
+    FPC_HIP(hipMemcpyAsync(ind.data(), d_ind, pp, hipMemcpyDeviceToHost, s));
+    FPC_HIP(hipStreamSynchronize(s));
+    float kms = 0.f;
+    FPC_HIP(hipEventElapsedTime(&kms, ctx->ev0, ctx->ev1));
+    st.kernel_ms = kms;
+    int64_t dels = 0;
+    for (int i = 0; i < p; ++i)
+        for (int j = i + 1; j < p; ++j)
+            if (ind[(size_t)i * p + j]) {
+                const int64_t pr = pair_index(i, j, p);
+                R.sep.level[pr] = p - 2;
+                R.sep.kind[pr] = FPC_SEP_ALL_BUT;
+                R.adj[(size_t)i * p + j] = R.adj[(size_t)j * p + i] = 0;
+                ++dels;
+            }
+    st.deleted = dels;
+    R.total_exec += st.tests_executed;
+    R.spent_possible += st.tests_possible;
+    *ms = now_ms() - t0;
+    st.level_ms = *ms;
+    R.levels.push_back(st);
+    return FPC_OK;
+}
+
+int largest_cand(const CandSets &cs)
+{
+    int mmax = -1;
+    for (size_t e = 0; e + 1 < cs.off.size(); ++e) mmax = std::max<int>(mmax, (int)(cs.off[e + 1] - cs.off[e]));
+    return mmax;
+}
+
+int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result **out)
+{
+    const int p = R.p;
+    const size_t pp = (size_t)p * p;
     fpc_result *res = (fpc_result *)std::calloc(1, sizeof(fpc_result));
     if (!res) return FPC_ENOMEM;
     const int64_t PP = (int64_t)p * (p - 1) / 2;
@@ -655,6 +769,207 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
     return FPC_OK;
 }
 
+int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
+{
+    const double t_start = now_ms();
+    int rc = validate(P);
+    if (rc) return rc;
+    FPC_HIP(hipSetDevice(ctx->device));
+    ctx->use_pair_kernel = !(P->flags & FPC_FLAG_PER_TEST_KERNEL);
+    const int p = P->p, n = P->n;
+    const size_t pp = (size_t)p * p;
+    hipStream_t s = ctx->stream;
+    Run R;
+    init_run(R, ctx, P, p, n);
+
+    // data on the device
+    const void *X = P->X;
+    if (!P->x_on_device) {
+        const size_t bytes = (size_t)n * p * (P->x_dtype == FPC_F64 ? 8 : 4);
+        if ((rc = ctx->x_copy.ensure(bytes))) return rc;
+        FPC_HIP(hipMemcpyAsync(ctx->x_copy.ptr, P->X, bytes, hipMemcpyHostToDevice, s));
+        X = ctx->x_copy.ptr;
+    }
+    double corr_ms = 0.0, first_ms = 0.0;
+    if ((rc = ctx->c64.ensure(sizeof(double) * pp))) return rc;
+    if (R.mixed && (rc = ctx->c32.ensure(sizeof(float) * pp))) return rc;
+    if ((rc = corr_stage(R, X, P->x_dtype, ctx->c64.as<double>(), ctx->c32.as<float>(), &corr_ms))) return rc;
+
+    const int cap = P->max_level;
+    CandSets cs;
+    const std::vector<Run *> one_run{&R};
+    const std::vector<const CandSets *> one_cs{&cs};
+    if (P->schedule == FPC_REVERSE) {
+        if ((rc = first_stage(R, &first_ms))) return rc;
+        // following levels: l = min(p-3, cap, largest candidate set), down to 0
+        int l = p - 3;
+        if (cap >= 0) l = std::min(l, cap);
+        while (l >= 0) {
+            candidate_sets(R.adj.data(), p, cs);
+            const int mmax = largest_cand(cs);
+            if (mmax < 0) break;  // no edges left
+            l = std::min(l, mmax);
+            std::vector<fpc_level_stats> lv;
+            if ((rc = run_level(one_run, l, one_cs, lv))) return rc;
+            R.levels.push_back(lv[0]);
+            --l;
+        }
+    } else {
+        // Algorithm 1: l = 0, 1, ... while some edge has |cand| >= l
+        for (int l = 0;; ++l) {
+            if (cap >= 0 && l > cap) break;
+            candidate_sets(R.adj.data(), p, cs);
+            if (largest_cand(cs) < l) break;
+            std::vector<fpc_level_stats> lv;
+            if ((rc = run_level(one_run, l, one_cs, lv))) return rc;
+            R.levels.push_back(lv[0]);
+        }
+    }
+    return assemble(R, corr_ms, first_ms, t_start, out);
+}
+
+int validate_batch(const fpc_params *P, int ni, const fpc_instance *inst)
+{
+    if (!P || ni < 1 || !inst) return FPC_EINVAL;
+    if (P->x_dtype != FPC_F64 && P->x_dtype != FPC_F32) return FPC_EINVAL;
+    if (P->precision != FPC_PREC_FP64 && P->precision != FPC_PREC_MIXED) return FPC_EINVAL;
+    if (P->schedule != FPC_REVERSE || P->order != FPC_ORDER_LEX) return FPC_EINVAL;
+    if (P->flags & FPC_FLAG_LOG_FEATURES) return FPC_EINVAL;
+    if (std::isnan(P->q_override) && !(P->alpha > 0.0 && P->alpha < 1.0)) return FPC_EINVAL;
+    if (!std::isnan(P->q_override) && !(P->q_override >= 0.0)) return FPC_EINVAL;
+    if (P->max_tests < 0) return FPC_EINVAL;
+    for (int k = 0; k < ni; ++k) {
+        const fpc_instance &I = inst[k];
+        if (!I.X || I.p < 2 || I.n <= I.p + 1 || I.x_rows < 1) return FPC_EINVAL;
+        if (!I.rows && I.x_rows < I.n) return FPC_EINVAL;
+    }
+    return FPC_OK;
+}
+
+// Several instances: correlation and first level one instance after the
+// other, then every following level of all instances in shared launches.
+// Each instance takes exactly the levels, in the same order, that a run of
+// it alone would take: at every step each unfinished instance has a next
+// level min(its current level, its largest candidate set), and the
+// instances whose next level is the highest of all run it together.
+int skeleton_batch_impl(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_instance *inst, fpc_result **outs)
+{
+    const double t_start = now_ms();
+    int rc = validate_batch(P, ni, inst);
+    if (rc) return rc;
+    FPC_HIP(hipSetDevice(ctx->device));
+    ctx->use_pair_kernel = !(P->flags & FPC_FLAG_PER_TEST_KERNEL);
+    const bool mixed = P->precision == FPC_PREC_MIXED;
+    // every instance's matrices stay resident through all levels
+    std::vector<size_t> off64(ni), off32(ni);
+    size_t total = 0;
+    auto a256 = [](size_t x) { return (x + 255) / 256 * 256; };
+    for (int k = 0; k < ni; ++k) {
+        const size_t pp = (size_t)inst[k].p * inst[k].p;
+        off64[k] = total;
+        total += a256(sizeof(double) * pp);
+        off32[k] = total;
+        if (mixed) total += a256(sizeof(float) * pp);
+    }
+    if ((rc = ctx->batch_c.ensure(total))) return rc;
+    char *base = ctx->batch_c.as<char>();
+    std::vector<Run> runs(ni);
+    std::vector<double> corr_ms(ni, 0.0), first_ms(ni, 0.0);
+    const size_t esz = P->x_dtype == FPC_F64 ? 8 : 4;
+    const double t_prep = now_ms();
+    for (int k = 0; k < ni; ++k) {
+        const fpc_instance &I = inst[k];
+        Run &R = runs[k];
+        init_run(R, ctx, P, I.p, I.n);
+        const void *X = I.X;
+        if (I.rows) {  // resample: the listed rows of X, in order
+            if ((rc = ctx->x_copy.ensure(esz * (size_t)I.n * I.p))) return rc;
+            if ((rc = gather_rows(ctx, I.X, P->x_dtype, I.x_rows, I.p, I.rows, I.n, ctx->x_copy.ptr))) return rc;
+            X = ctx->x_copy.ptr;
+        }
+        if ((rc = corr_stage(R, X, P->x_dtype, reinterpret_cast<double *>(base + off64[k]),
+                             mixed ? reinterpret_cast<float *>(base + off32[k]) : nullptr, &corr_ms[k])))
+            return rc;
+        if ((rc = first_stage(R, &first_ms[k]))) return rc;
+    }
+    if (trace_on())
+        std::fprintf(stderr, "[fpc] batch of %d: correlation and first level %.2f ms\n", ni, now_ms() - t_prep);
+    // following levels, level-synchronous over the instances
+    const int cap = P->max_level;
+    std::vector<CandSets> cs(ni);
+    std::vector<int> next(ni);    // current level of each instance (as in a single run)
+    std::vector<char> done(ni, 0), fresh(ni, 0);
+    for (int k = 0; k < ni; ++k) next[k] = cap >= 0 ? std::min(inst[k].p - 3, cap) : inst[k].p - 3;
+    for (;;) {
+        int top = -1;
+        std::vector<int> eff(ni, -1);
+        // candidate sets of the instances whose graph changed, on host threads
+        {
+            std::vector<int> todo;
+            for (int k = 0; k < ni; ++k)
+                if (!done[k] && next[k] >= 0 && !fresh[k]) todo.push_back(k);
+            const unsigned hw = std::thread::hardware_concurrency();
+            const int nth = (int)std::min<size_t>(todo.size(), std::min<unsigned>(hw ? hw : 1, 16u));
+            if (nth <= 1) {
+                for (int k : todo) candidate_sets(runs[k].adj.data(), runs[k].p, cs[k]);
+            } else {
+                std::atomic<size_t> at{0};
+                std::vector<std::thread> pool;
+                for (int t = 0; t < nth; ++t)
+                    pool.emplace_back([&] {
+                        for (size_t x = at++; x < todo.size(); x = at++)
+                            candidate_sets(runs[todo[x]].adj.data(), runs[todo[x]].p, cs[todo[x]], 1);
+                    });
+                for (auto &th : pool) th.join();
+            }
+            for (int k : todo) fresh[k] = 1;
+            if (trace_on()) std::fprintf(stderr, "[fpc] candidate sets of %zu instance(s)\n", todo.size());
+        }
+        for (int k = 0; k < ni; ++k) {
+            if (done[k]) continue;
+            if (next[k] < 0) {
+                done[k] = 1;
+                continue;
+            }
+            const int mmax = largest_cand(cs[k]);
+            if (mmax < 0) {  // no edges left
+                done[k] = 1;
+                continue;
+            }
+            eff[k] = std::min(next[k], mmax);
+            top = std::max(top, eff[k]);
+        }
+        if (top < 0) break;
+        std::vector<Run *> part;
+        std::vector<const CandSets *> pcs;
+        std::vector<int> ids;
+        for (int k = 0; k < ni; ++k)
+            if (!done[k] && eff[k] == top) {
+                part.push_back(&runs[k]);
+                pcs.push_back(&cs[k]);
+                ids.push_back(k);
+            }
+        std::vector<fpc_level_stats> lv;
+        if ((rc = run_level(part, top, pcs, lv))) return rc;
+        for (size_t t = 0; t < ids.size(); ++t) {
+            const int k = ids[t];
+            runs[k].levels.push_back(lv[t]);
+            next[k] = top - 1;
+            fresh[k] = 0;  // its graph changed
+        }
+    }
+    for (int k = 0; k < ni; ++k) {
+        if ((rc = assemble(runs[k], corr_ms[k], first_ms[k], t_start, &outs[k]))) {
+            for (int t = 0; t < k; ++t) {
+                fpc_result_free(outs[t]);
+                outs[t] = nullptr;
+            }
+            return rc;
+        }
+    }
+    return FPC_OK;
+}
+
 }  // namespace
 
 extern "C" int fpc_skeleton(fpc_ctx *ctx, const fpc_params *params, fpc_result **out)
@@ -663,4 +978,13 @@ extern "C" int fpc_skeleton(fpc_ctx *ctx, const fpc_params *params, fpc_result *
     *out = nullptr;
     if (!ctx) return FPC_EINVAL;
     return skeleton_impl(ctx, params, out);
+}
+
+extern "C" int fpc_skeleton_batch(fpc_ctx *ctx, const fpc_params *params, int n_inst, const fpc_instance *inst,
+                                  fpc_result **out)
+{
+    if (!out || n_inst < 1) return FPC_EINVAL;
+    for (int k = 0; k < n_inst; ++k) out[k] = nullptr;
+    if (!ctx) return FPC_EINVAL;
+    return skeleton_batch_impl(ctx, params, n_inst, inst, out);
 }

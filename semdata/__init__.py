@@ -39,7 +39,9 @@ __all__ = [
     "population_cov",
     "make_sem",
     "bootstrap_rows",
+    "bootstrap_index",
     "true_skeleton",
+    "batched_workload",
 ]
 
 
@@ -179,11 +181,15 @@ def population_cov(sem: SEM) -> np.ndarray:
     return M.T @ M
 
 
+def bootstrap_index(n: int, seed: int) -> np.ndarray:
+    """Row indices of a bootstrap resample: n draws with replacement."""
+    rng = np.random.default_rng([seed, 0xB007])
+    return rng.integers(0, n, size=n).astype(np.int32)
+
+
 def bootstrap_rows(X: np.ndarray, seed: int) -> np.ndarray:
     """Rows drawn with replacement (same n)."""
-    rng = np.random.default_rng([seed, 0xB007])
-    idx = rng.integers(0, X.shape[0], size=X.shape[0])
-    return np.ascontiguousarray(X[idx])
+    return np.ascontiguousarray(X[bootstrap_index(X.shape[0], seed)])
 
 
 def true_skeleton(sem: SEM) -> np.ndarray:
@@ -213,3 +219,37 @@ def workload(name: str, seed: int, **over):
     sem = make_sem(cfg["p"], seed, graph=cfg["graph"], degree=cfg["degree"])
     X = sample(sem, cfg["n"], seed, dtype=np.float32 if cfg["x_dtype"] == "f32" else np.float64)
     return X, sem, cfg
+
+
+# Many instances in one call: bootstrap resamples of one data set plus
+# independent data sets of uneven size (ER DAGs, expected degree 6, n=5000).
+BATCHED = dict(n=5000, degree=6.0, x_dtype="f32", alpha=0.01, max_level=4, base_p=500, n_boot=64, n_data=16,
+               p_lo=50, p_hi=2000, base_seed=3000, boot_seed=3001, data_seed=3100)
+
+
+def batched_workload(n_boot: int | None = None, n_data: int | None = None, scale: float = 1.0, **over):
+    """(base X, bootstrap row-index arrays, [independent X], cfg).
+
+    The base data set has ``base_p`` variables (seed ``base_seed``); resample
+    b uses seed ``boot_seed + b``; data set d has p uniform in
+    [p_lo, p_hi] (drawn from seed ``data_seed + d``) and seed
+    ``data_seed + d``.  ``scale`` shrinks every p (and n) for small tests.
+    """
+    cfg = dict(BATCHED)
+    cfg.update(over)
+    nb = cfg["n_boot"] if n_boot is None else n_boot
+    nd = cfg["n_data"] if n_data is None else n_data
+    dt = np.float32 if cfg["x_dtype"] == "f32" else np.float64
+    n = max(8, int(round(cfg["n"] * scale)))
+    bp = max(4, int(round(cfg["base_p"] * scale)))
+    base = sample(make_sem(bp, cfg["base_seed"], degree=cfg["degree"]), n, cfg["base_seed"], dtype=dt)
+    boots = [bootstrap_index(n, cfg["boot_seed"] + b) for b in range(nb)]
+    datas = []
+    for d in range(nd):
+        seed = cfg["data_seed"] + d
+        pd = int(np.random.default_rng([seed, 0xD1]).integers(cfg["p_lo"], cfg["p_hi"] + 1))
+        pd = max(4, min(n - 3, int(round(pd * scale))))
+        datas.append(sample(make_sem(pd, seed, degree=cfg["degree"]), n, seed, dtype=dt))
+    cfg["n"] = n
+    cfg["base_p"] = bp
+    return base, boots, datas, cfg

@@ -31,6 +31,30 @@ SEED = 0
 BA_WORKLOAD = "ba_p1000_n10000_m2"
 BA_SEED = 2000  # a held-out seed of the ranker's evaluation set
 FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32
+# HBM bytes per launch of the dominant kernel (triple_kernel<float, 2>, level
+# 5 of the workload above) from the FETCH_SIZE and WRITE_SIZE counter runs in
+# profiles/triple_kernel_er_p1000_n10000_d4.md, scaled by the copy-kernel
+# calibration (fetch x2.000, write x1.000).  Valid only for the kernel source
+# and launch table they were taken with: any change to either makes the
+# figure null until the counters are taken again.
+MEASURED_TRAFFIC = {"bytes_per_launch": 8323309.0,
+                    "sha256": {"paper_2109_04626_amd/csrc/citest.hip":
+                               "e0cb3cc5feac14f8852fac27f1b025f00b8cb79b80234210d7994b1f8f793c3b",
+                               "paper_2109_04626_amd/tuning_gfx950.json":
+                               "72bbcab89d47417aa15a427e07332ae4386e0c0decbe97fe179e189f8912e9a1"}}
+
+
+def measured_traffic():
+    import hashlib
+
+    for rel, want in MEASURED_TRAFFIC["sha256"].items():
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != want:
+                    return None
+        except OSError:
+            return None
+    return MEASURED_TRAFFIC["bytes_per_launch"]
 FP64_PEAK_TFLOPS = 78.6    # MI355X published vector FP64
 
 
@@ -58,6 +82,10 @@ def main() -> int:
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-instance workload")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--profile-mixed", action="store_true",
+                    help="profiling mode: only the mixed form on the headline workload, one short line")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="profiling mode: a plain device copy of 1 GiB, five times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
@@ -69,6 +97,20 @@ def main() -> int:
 
     import paper_2109_04626_amd as fpc
     import semdata
+
+    if args.copy_probe:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": dt * 1e3,
+                          "GB_per_s": 2 * nbytes / dt / 1e9}), flush=True)
+        return 0
 
     over = {} if args.max_level is None else {"max_level": args.max_level}
     X, sem, cfg = semdata.workload(WORKLOAD, SEED, **over)
@@ -95,6 +137,14 @@ def main() -> int:
 
     # plain = FP64 tests, lexicographic order; mixed = bf16x3 C + FP32 tests
     # with FP64 recheck; learned = mixed with the MLP-ranked candidate order
+    if args.profile_mixed:
+        dt, outs = timed(Xd, cfg, fpc.FPC_PREC_MIXED)
+        lv5 = [x for x in outs[-1]["levels"] if x["level"] == cfg["max_level"]]
+        print(json.dumps({"form": "mixed", "ms_per_step": dt / args.steps * 1e3,
+                          "levels": [{k: x[k] for k in ("level", "tests_executed", "test_kernel_ms", "test_launches")}
+                                     for x in lv5]}), flush=True)
+        ctx.close()
+        return 0
     forms = {"mixed": (fpc.FPC_PREC_MIXED, None), "plain": (fpc.FPC_PREC_FP64, None),
              "learned": (fpc.FPC_PREC_MIXED, model)}
     results = {}
@@ -138,12 +188,14 @@ def main() -> int:
         ts = time.perf_counter() - t0
         same_b = all(np.array_equal(a["adj"], b["adj"]) for a, b in zip(outs_b, outs_s))
         tests_b = sum(o["total_tests"] for o in outs_b)
+        req_b = sum(o["total_required"] for o in outs_b)
         batched = {"workload": f"64 bootstrap resamples of an ER p={cfg5['base_p']} deg={cfg5['degree']} data set "
                                f"+ 16 ER data sets p~U[{cfg5['p_lo']},{cfg5['p_hi']}], n={cfg5['n']} X f32, "
                                f"alpha={cfg5['alpha']}, max_level={cfg5['max_level']}, mixed",
                    "instances": len(inst), "ms_per_call": tb * 1e3, "one_call_each_ms": ts * 1e3,
                    "speedup_vs_one_call_each": ts / tb, "tests_per_call": tests_b,
-                   "ci_tests_per_s": tests_b / tb, "skeletons_equal": same_b}
+                   "ci_tests_per_s": tests_b / tb, "tests_required_per_call": req_b,
+                   "required_tests_per_s": req_b / tb, "skeletons_equal": same_b}
         print(f"[bench] batched: {tb * 1e3:.1f} ms/call vs {ts * 1e3:.1f} ms one call each", file=sys.stderr,
               flush=True)
         del inst, base_d
@@ -214,6 +266,8 @@ def main() -> int:
                                                              ba["learned"][1][-1]["adj"]))},
         "batched": batched,
         "tests_per_step": outs[-1]["total_tests"],
+        "tests_required_per_step": outs[-1]["total_required"],
+        "required_tests_per_s": outs[-1]["total_required"] * args.steps / dt,
         "edges": int(last["adj"].sum()) // 2,
         "level_kernel_ms_mixed": kms,
         "level_kernel_ms_plain": kms_p,
@@ -226,7 +280,7 @@ def main() -> int:
                             "avg_launch_ms": dom["test_kernel_ms"] / max(dom["test_launches"], 1),
                             "tests": dom["tests_executed"], "flops_per_test": flops_per_test(dom["level"])},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None},
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic()},
     }
 
     if not args.no_cpu_baseline:

@@ -173,10 +173,13 @@ typedef struct fpc_level_stats {
     double kernel_ms;         /* device time of the level: test kernels, rechecks and
                                  gaps between them (HIP events on the context stream)   */
     double test_kernel_ms;    /* sum of the test-kernel launches alone (an event pair
-                                 around each of the first 64 launches)                  */
-    int32_t test_launches;    /* launches timed in test_kernel_ms                       */
+                                 around each of the first 256 launches)                 */
+    int32_t test_launches;    /* test-kernel launches of the level                      */
     int32_t reserved;
     double level_ms;          /* whole level, host clock                                */
+    int64_t tests_required;   /* tests the method needs: per eligible edge, C(|cand|, l)
+                                 if kept, else the rank of its first separating set + 1
+                                 (independent of launch shapes and scheduling)          */
 } fpc_level_stats;
 
 typedef struct fpc_result {
@@ -211,6 +214,33 @@ typedef struct fpc_result {
  * freed with fpc_result_free; on error *out is NULL. */
 int fpc_skeleton(fpc_ctx *ctx, const fpc_params *params, fpc_result **out);
 void fpc_result_free(fpc_result *r);
+
+/* ------------------------------------------------------------- launch tuning
+ * Shapes of the level-test launches, per level l < FPC_TUNE_LEVELS (levels
+ * above use the last entry).  They change only speed, never results:
+ *   test_ranks_per_wave    ranks one wave of the per-test kernel (l <= 1,
+ *                          or lists too long for the shared-prefix kernels)
+ *                          takes per work item (64 .. 2^20)
+ *   shared_ranks_per_wave  the same for the shared-prefix kernels (l >= 2)
+ *   window_growth          ratio of consecutive rank windows (2 .. 64);
+ *                          a window only runs edges with no separating set
+ *   first_window_items     work items per edge in the first window (1 .. 64)
+ *   max_blocks_per_cu      cap on resident workgroups per CU (0: none)
+ * fpc_set_tuning(ctx, NULL) restores the defaults.  The autotuner
+ * (paper_2109_04626_amd.autotune) measures settings on synthetic workloads
+ * and writes a table the Python binding loads into each context. */
+#define FPC_TUNE_LEVELS 17
+typedef struct {
+    int32_t test_ranks_per_wave[FPC_TUNE_LEVELS];
+    int32_t shared_ranks_per_wave[FPC_TUNE_LEVELS];
+    int32_t window_growth[FPC_TUNE_LEVELS];
+    int32_t first_window_items[FPC_TUNE_LEVELS];
+    int32_t max_blocks_per_cu[FPC_TUNE_LEVELS];
+} fpc_tuning;
+
+int fpc_get_tuning(const fpc_ctx *ctx, fpc_tuning *out);
+/* FPC_EINVAL for a value out of range (the context keeps its table). */
+int fpc_set_tuning(fpc_ctx *ctx, const fpc_tuning *t);
 
 /* ------------------------------------------------------------- many instances
  * Runs the skeleton of several independent problems (bootstrap resamples of

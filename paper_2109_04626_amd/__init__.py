@@ -31,7 +31,12 @@ FPC_FLAG_GRAPH = 4
 EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "fpc_quantile",
             "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton", "fpc_skeleton_batch",
             "fpc_result_free", "fpc_orient", "fpc_mlp_bytes", "fpc_mlp_params", "fpc_mlp_init", "fpc_mlp_get",
-            "fpc_mlp_forward", "fpc_mlp_grad", "fpc_mlp_train_step"]
+            "fpc_mlp_forward", "fpc_mlp_grad", "fpc_mlp_train_step", "fpc_get_tuning", "fpc_set_tuning"]
+FPC_TUNE_LEVELS = 17
+TUNING_FIELDS = ("test_ranks_per_wave", "shared_ranks_per_wave", "window_growth", "first_window_items",
+                 "max_blocks_per_cu")
+# launch-shape table written by the autotuner (python -m paper_2109_04626_amd.autotune)
+TUNING_TABLE = os.path.join(_HERE, "tuning_gfx950.json")
 
 
 class FastPCError(RuntimeError):
@@ -59,7 +64,8 @@ class fpc_level_stats(ctypes.Structure):
                 ("tests_executed", ctypes.c_int64), ("tests_rechecked", ctypes.c_int64),
                 ("deleted", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
                 ("test_kernel_ms", ctypes.c_double), ("test_launches", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("level_ms", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("level_ms", ctypes.c_double),
+                ("tests_required", ctypes.c_int64)]
 
 
 class fpc_result(ctypes.Structure):
@@ -73,6 +79,10 @@ class fpc_result(ctypes.Structure):
                 ("corr_max_abs_err", ctypes.c_double), ("log_rows", ctypes.c_int64),
                 ("log_x", ctypes.POINTER(ctypes.c_float)), ("log_y", ctypes.POINTER(ctypes.c_uint8)),
                 ("log_group", ctypes.POINTER(ctypes.c_int32)), ("log_level", ctypes.POINTER(ctypes.c_int32))]
+
+
+class fpc_tuning(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32 * FPC_TUNE_LEVELS) for f in TUNING_FIELDS]
 
 
 class fpc_instance(ctypes.Structure):
@@ -113,6 +123,10 @@ def _load():
     lib.fpc_skeleton_batch.argtypes = [vp, ctypes.POINTER(fpc_params), i, ctypes.POINTER(fpc_instance),
                                        ctypes.POINTER(ctypes.POINTER(fpc_result))]
     lib.fpc_skeleton_batch.restype = i
+    lib.fpc_get_tuning.argtypes = [vp, ctypes.POINTER(fpc_tuning)]
+    lib.fpc_get_tuning.restype = i
+    lib.fpc_set_tuning.argtypes = [vp, ctypes.POINTER(fpc_tuning)]
+    lib.fpc_set_tuning.restype = i
     lib.fpc_result_free.argtypes = [ctypes.POINTER(fpc_result)]
     lib.fpc_result_free.restype = None
     lib.fpc_orient.argtypes = [i, vp, vp, vp, vp, vp, vp]
@@ -207,9 +221,13 @@ def fpc_orient(res: dict) -> np.ndarray:
 
 # ------------------------------------------------------------------ device calls
 class Context:
-    """An fpc_ctx on a HIP device, enqueuing on torch's current stream."""
+    """An fpc_ctx on a HIP device, enqueuing on torch's current stream.
 
-    def __init__(self, device: int = 0, stream=None):
+    ``tuning``: "table" loads the autotuned launch shapes shipped with the
+    package (when present), "default" keeps the library defaults, a dict
+    {field: [per-level values]} sets them explicitly."""
+
+    def __init__(self, device: int = 0, stream=None, tuning="table"):
         import torch
 
         self.device = device
@@ -219,6 +237,13 @@ class Context:
         h = ctypes.c_void_p()
         _check(_lib.fpc_create(ctypes.byref(h), int(device), ctypes.c_void_p(stream.cuda_stream)), "fpc_create")
         self._h = h
+        if isinstance(tuning, dict):
+            fpc_set_tuning(self, tuning)
+        elif tuning == "table" and os.path.exists(TUNING_TABLE):
+            import json
+
+            with open(TUNING_TABLE) as f:
+                fpc_set_tuning(self, json.load(f)["tuning"])
 
     @property
     def handle(self):
@@ -240,6 +265,28 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+
+def fpc_get_tuning(ctx: Context) -> dict:
+    t = fpc_tuning()
+    _check(_lib.fpc_get_tuning(ctx.handle, ctypes.byref(t)), "fpc_get_tuning")
+    return {f: list(getattr(t, f)) for f in TUNING_FIELDS}
+
+
+def fpc_set_tuning(ctx: Context, tuning) -> None:
+    """tuning: dict of per-level lists (missing fields keep their values),
+    or None for the library defaults."""
+    if tuning is None:
+        _check(_lib.fpc_set_tuning(ctx.handle, None), "fpc_set_tuning")
+        return
+    cur = fpc_get_tuning(ctx)
+    t = fpc_tuning()
+    for f in TUNING_FIELDS:
+        vals = list(tuning.get(f, cur[f]))
+        if len(vals) != FPC_TUNE_LEVELS:
+            raise ValueError(f"{f}: {FPC_TUNE_LEVELS} values expected")
+        getattr(t, f)[:] = [int(v) for v in vals]
+    _check(_lib.fpc_set_tuning(ctx.handle, ctypes.byref(t)), "fpc_set_tuning")
 
 
 def fpc_create(device: int = 0, stream=None) -> Context:
@@ -505,7 +552,8 @@ def _unpack(r: fpc_result) -> dict:
                    level=np.ctypeslib.as_array(r.log_level, shape=(nlog,)).copy())
     return dict(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets, sep_off=off, sep_nodes=nodes,
                 levels=levels, log=log,
-                total_tests=int(r.total_tests), q=float(r.q), corr_ms=float(r.corr_ms),
+                total_tests=int(r.total_tests), total_required=sum(x["tests_required"] for x in levels),
+                q=float(r.q), corr_ms=float(r.corr_ms),
                 first_level_ms=float(r.first_level_ms), total_ms=float(r.total_ms),
                 corr_max_abs_err=float(r.corr_max_abs_err), p=p)
 

@@ -43,8 +43,7 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kSteps = 8;
-constexpr int kRanksPerWave = 64 * kSteps;
-constexpr int kRanksPerBlock = kWaves * kRanksPerWave;  // 2048
+constexpr int kRanksPerWave = 64 * kSteps;               // default ranks per wave, per-test kernel
 constexpr int kGenericRanks = 16;                        // ranks per workgroup, wide-level kernel
 constexpr double kErrSafety = 4.0;                       // multiplier of the FP32 error bound
 
@@ -324,12 +323,15 @@ __device__ __forceinline__ void for_each_item(const LevelArgs &A, F &&body)
 // The register and wave limits come from the runtime's occupancy query;
 // the LDS limit is applied here from the CU's LDS size, since the query
 // does not account for workgroups that opt into more than 64 KiB.
+thread_local int g_max_blocks_per_cu = 0;  // tuning cap of the launch being issued (0: none)
+
 unsigned resident_grid(const void *fn, int threads, size_t shm, int64_t ub, int cus, size_t lds_cu)
 {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     if (shm > 0) per_cu = std::min<int>(per_cu, std::max<int>(1, (int)(lds_cu / (shm + 256))));
+    if (g_max_blocks_per_cu > 0) per_cu = std::min(per_cu, g_max_blocks_per_cu);
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ub, (int64_t)per_cu * cus));
 }
 
@@ -369,8 +371,9 @@ __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsi
     const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = E.m;
-    const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * kRanksPerBlock;
-    const int64_t r1 = min(r0 + (int64_t)kRanksPerBlock, min(A.win_hi, E.ntests));
+    const int64_t rpb = A.ranks_per_block, rpw = rpb / kWaves;
+    const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * rpb;
+    const int64_t r1 = min(r0 + rpb, min(A.win_hi, E.ntests));
     if (r0 >= r1) return;  // uniform
     __shared__ int skip;
     if (threadIdx.x == 0) skip = load_minhit(&A.minhit[e]) < (uint64_t)r0;
@@ -393,8 +396,8 @@ __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsi
         __syncthreads();
     }
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    const int64_t wlo = r0 + (int64_t)wave * kRanksPerWave;
-    const int64_t whi = min(wlo + (int64_t)kRanksPerWave, r1);
+    const int64_t wlo = r0 + (int64_t)wave * rpw;
+    const int64_t whi = min(wlo + rpw, r1);
     uint64_t executed = 0;
     if (wlo < whi) {
         constexpr int LL = L > 0 ? L : 1;
@@ -491,8 +494,7 @@ __global__ __launch_bounds__(256) void recheck_kernel(LevelArgs A)
 // it builds a table of the per-position quantities in its LDS slice (one
 // lane per position) and then runs 64 pairs per step, decoding the pair
 // index in the triangle of the positions after max(Q).
-constexpr int kPairRanksPerWave = 2048;
-constexpr int kPairRanksPerBlock = kWaves * kPairRanksPerWave;
+constexpr int kPairRanksPerWave = 2048;  // default ranks per wave, shared-prefix kernels
 
 template <typename T, int QL>
 struct PairLayout {
@@ -543,8 +545,9 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
     const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = E.m;
-    const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * kPairRanksPerBlock;
-    const int64_t r1 = min(r0 + (int64_t)kPairRanksPerBlock, min(A.win_hi, E.ntests));
+    const int64_t rpb = A.ranks_per_block, rpw = rpb / kWaves;
+    const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * rpb;
+    const int64_t r1 = min(r0 + rpb, min(A.win_hi, E.ntests));
     if (r0 >= r1) return;  // uniform
     __shared__ int skip;
     if (threadIdx.x == 0) skip = load_minhit(&A.minhit[e]) < (uint64_t)r0;
@@ -566,8 +569,8 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
     T *tab = tri + tile_elems + (size_t)wave * A.max_m * Lay::S;
     __syncthreads();
 
-    const int64_t wlo = r0 + (int64_t)wave * kPairRanksPerWave;
-    const int64_t whi = min(wlo + (int64_t)kPairRanksPerWave, r1);
+    const int64_t wlo = r0 + (int64_t)wave * rpw;
+    const int64_t whi = min(wlo + rpw, r1);
     if (wlo >= whi) return;  // no later block-wide barrier
     const auto row = [&](int a) { return a * (2 * m - a - 3) / 2 - 1; };
 
@@ -819,8 +822,9 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
     const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = E.m;
-    const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * kPairRanksPerBlock;
-    const int64_t r1 = min(r0 + (int64_t)kPairRanksPerBlock, min(A.win_hi, E.ntests));
+    const int64_t rpb = A.ranks_per_block, rpw = rpb / kWaves;
+    const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * rpb;
+    const int64_t r1 = min(r0 + rpb, min(A.win_hi, E.ntests));
     if (r0 >= r1) return;  // uniform
     __shared__ int skip;
     if (threadIdx.x == 0) skip = load_minhit(&A.minhit[e]) < (uint64_t)r0;
@@ -841,8 +845,8 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
     T *tab = tri + tile_elems + (size_t)wave * A.max_m * Lay::S;
     __syncthreads();
 
-    const int64_t wlo = r0 + (int64_t)wave * kPairRanksPerWave;
-    const int64_t whi = min(wlo + (int64_t)kPairRanksPerWave, r1);
+    const int64_t wlo = r0 + (int64_t)wave * rpw;
+    const int64_t whi = min(wlo + rpw, r1);
     if (wlo >= whi) return;  // no later block-wide barrier
     const auto row = [&](int a) { return a * (2 * m - a - 3) / 2 - 1; };
 
@@ -1524,6 +1528,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     if (Lv.n_insts < 1 || !Lv.insts) return FPC_EINVAL;
     const bool wide = l > kMaxTemplL;
     const bool fp32 = Lv.fp32 && !wide;
+    const int lt = std::min(l, FPC_TUNE_LEVELS - 1);  // row of the tuning table
     // dynamic LDS available next to the kernels' few static words
     const size_t lds_cap = (size_t)ctx->lds_per_block - 64;
 
@@ -1566,12 +1571,16 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                 k.shm = k.kind == K_TILE ? ts : 0;
             }
         }
-        k.rpb = k.kind == K_WIDE ? kGenericRanks : (k.kind == K_TRIPLE || k.kind == K_PAIR) ? kPairRanksPerBlock
-                                                                                              : kRanksPerBlock;
+        // ranks per work item: the tuning table's value for this level and kernel
+        const fpc_tuning &tu = ctx->tuning;
+        k.rpb = k.kind == K_WIDE ? kGenericRanks
+              : (k.kind == K_TRIPLE || k.kind == K_PAIR) ? kWaves * tu.shared_ranks_per_wave[lt]
+                                                           : kWaves * tu.test_ranks_per_wave[lt];
         int64_t maxN = 0;
         for (int64_t e = k.begin; e < k.end; ++e) maxN = std::max(maxN, ntests[e]);
         k.wins.push_back(0);
-        for (int64_t w = k.rpb; k.wins.back() < maxN; w *= 8)
+        for (int64_t w = (int64_t)k.rpb * std::max(1, ctx->tuning.first_window_items[lt]); k.wins.back() < maxN;
+             w *= std::max(2, ctx->tuning.window_growth[lt]))
             k.wins.push_back(std::min<int64_t>(maxN, k.wins.back() + w));
         max_nw = std::max(max_nw, (int)k.wins.size() - 1);
         cls.push_back(std::move(k));
@@ -1612,6 +1621,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
 
     const int cus = ctx->num_cus;
     const size_t lds_cu = (size_t)ctx->lds_per_cu;
+    g_max_blocks_per_cu = ctx->tuning.max_blocks_per_cu[lt];
     const bool graph = Lv.graph;
     hipGraph_t g = nullptr;
     if (graph) FPC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -1775,4 +1785,45 @@ extern "C" int fpc_ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int
 {
     if (!ctx) return FPC_EINVAL;
     return fpc::ci_batch(ctx, C, c_dtype, p, n, l, B, b, q, z_out, indep_out);
+}
+
+namespace fpc {
+
+void tuning_defaults(fpc_tuning *t)
+{
+    std::memset(t, 0, sizeof(*t));
+    for (int l = 0; l < FPC_TUNE_LEVELS; ++l) {
+        t->test_ranks_per_wave[l] = kRanksPerWave;
+        t->shared_ranks_per_wave[l] = kPairRanksPerWave;
+        t->window_growth[l] = 8;
+        t->first_window_items[l] = 1;
+        t->max_blocks_per_cu[l] = 0;
+    }
+}
+
+}  // namespace fpc
+
+extern "C" int fpc_get_tuning(const fpc_ctx *ctx, fpc_tuning *out)
+{
+    if (!ctx || !out) return FPC_EINVAL;
+    *out = ctx->tuning;
+    return FPC_OK;
+}
+
+extern "C" int fpc_set_tuning(fpc_ctx *ctx, const fpc_tuning *t)
+{
+    if (!ctx) return FPC_EINVAL;
+    if (!t) {
+        fpc::tuning_defaults(&ctx->tuning);
+        return FPC_OK;
+    }
+    for (int l = 0; l < FPC_TUNE_LEVELS; ++l) {
+        if (t->test_ranks_per_wave[l] < 64 || t->test_ranks_per_wave[l] > (1 << 20)) return FPC_EINVAL;
+        if (t->shared_ranks_per_wave[l] < 64 || t->shared_ranks_per_wave[l] > (1 << 20)) return FPC_EINVAL;
+        if (t->window_growth[l] < 2 || t->window_growth[l] > 64) return FPC_EINVAL;
+        if (t->first_window_items[l] < 1 || t->first_window_items[l] > 64) return FPC_EINVAL;
+        if (t->max_blocks_per_cu[l] < 0 || t->max_blocks_per_cu[l] > 32) return FPC_EINVAL;
+    }
+    ctx->tuning = *t;
+    return FPC_OK;
 }

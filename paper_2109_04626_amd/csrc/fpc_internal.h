@@ -54,6 +54,7 @@ struct fpc_ctx {
     int lds_per_cu = 65536;     // LDS bytes per compute unit
     bool use_pair_kernel = true; // shared-prefix kernel for levels l >= 2 (off with FPC_FLAG_PER_TEST_KERNEL)
     int num_cus = 256;
+    fpc_tuning tuning{};          // launch shapes of the level kernels (fpc_set_tuning)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     static constexpr int kLaunchEvents = 256;
     hipEvent_t lev[2 * kLaunchEvents] = {};  // per-launch timing of the test kernels
@@ -156,6 +157,7 @@ struct LevelTiming {
 // Size class of an edge with m candidates at level l: edges of one class
 // share a kernel and the number of workgroups that fit on a CU.
 int level_class_key(const fpc_ctx *ctx, int l, bool fp32, int m);
+void tuning_defaults(fpc_tuning *t);
 int level_tests(fpc_ctx *ctx, const LevelLaunch &L, const std::vector<int64_t> &host_ntests,
                 LevelTiming *timing);
 int level_compact(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *out_pairs,

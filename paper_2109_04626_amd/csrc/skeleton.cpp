@@ -196,6 +196,7 @@ extern "C" int fpc_create(fpc_ctx **out, int hip_device, void *hip_stream)
         c->lds_per_block = v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && v > 0)
         c->num_cus = v;
+    fpc::tuning_defaults(&c->tuning);
     c->lds_per_cu = c->lds_per_block;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, hip_device) == hipSuccess &&
         v > c->lds_per_cu)
@@ -532,6 +533,11 @@ retry:
         fp32 = false;
         goto retry;
     }
+    for (int k = 0; k < ni; ++k) sts[k].tests_required = sts[k].tests_possible;
+    for (int64_t t = 0; t < ndel; ++t) {
+        const EdgeRec &er = recs[pairs[2 * t]];
+        sts[er.inst].tests_required -= er.ntests - (pairs[2 * t + 1] + 1);
+    }
 
     const double t_decode = now_ms();
     // sepsets and level-end deletion (stable: all of D at once), each
@@ -660,7 +666,7 @@ int first_stage(Run &R, double *ms)
     fpc_level_stats st{};
     st.level = p - 2;
     st.max_cand = p - 2;
-    st.edges_eligible = st.tests_possible = st.tests_executed = (int64_t)p * (p - 1) / 2;
+    st.edges_eligible = st.tests_possible = st.tests_executed = st.tests_required = (int64_t)p * (p - 1) / 2;
     int rc;
     if ((rc = ctx->flag.ensure(64))) return rc;
     if ((rc = ctx->dellist.ensure(pp))) return rc;

@@ -204,6 +204,8 @@ def test_skeleton_fp64_cfg1_bit_exact(fpc, ctx, seed):
     got = fpc.fpc_skeleton(ctx, dev(X), alpha=cfg["alpha"])
     _compare_fp64(fpc, got, ref, cfg["p"])
     assert got["total_tests"] >= ref["total_tests"]
+    # tests the method needs (first hit per edge in lexicographic order) = the oracle's count
+    assert got["total_required"] == ref["total_tests"]
 
 
 @pytest.mark.parametrize("seed", range(5))
@@ -244,9 +246,10 @@ def test_skeleton_mid_sizes(fpc, ctx, p, n, deg, L, prec, flags):
     assert np.array_equal(got["sep_level"], ref["sep_level"])
     if prec == 0:
         assert got["sepsets"] == ref["sepsets"]
+        assert got["total_required"] == ref["total_tests"]
     else:
         _retest_sepsets(fpc, got, C, n, ref["q"])
-    _say(f"  tests gpu={got['total_tests']} oracle={ref['total_tests']}")
+    _say(f"  tests gpu={got['total_tests']} required={got['total_required']} oracle={ref['total_tests']}")
 
 
 @pytest.mark.parametrize("prec", [0, 1])

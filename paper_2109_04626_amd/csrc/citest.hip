@@ -525,15 +525,35 @@ __device__ __forceinline__ void put_int(double &d, int v) { d = (double)v; }
 __device__ __forceinline__ int get_int(float d) { return __float_as_int(d); }
 __device__ __forceinline__ int get_int(double d) { return (int)d; }
 
-// Decision of one FP32 pair test in r space (band and error bound).
+// Decision of one FP32 pair test in r space (band and error bound):
+// independent when |r| < rlo - errk/dmin, dependent when |r| > rhi +
+// errk/dmin, else re-run in FP64; dmin > 0 whenever ok, so the bounds are
+// compared after multiplying through by dmin.
 __device__ __forceinline__ int decide32r(float r, float dmin, bool ok, float rlo, float rhi, float errk)
 {
     if (!ok) return DEC_RECHECK;
     const float a = fabsf(r);
-    const float err = errk * __builtin_amdgcn_rcpf(dmin);
-    if (a < rlo - err) return DEC_INDEP;
-    if (a > rhi + err) return DEC_DEP;
+    if ((rlo - a) * dmin > errk) return DEC_INDEP;
+    if ((a - rhi) * dmin > errk) return DEC_DEP;
     return DEC_RECHECK;
+}
+
+// Smaller of two positive floats through their bit patterns (positive
+// floats order as integers); the result is used only when both are > 0.
+__device__ __forceinline__ float pos_min(float a, float b)
+{
+    return __int_as_float(min(__float_as_int(a), __float_as_int(b)));
+}
+
+// Row of the reversed pair index u in a triangle: rr with
+// rr(rr+1)/2 <= u < (rr+1)(rr+2)/2.  u < 2^19 (lists shorter than 1024), so
+// the products fit the 24-bit multiplier.
+__device__ __forceinline__ unsigned tri_root(unsigned u)
+{
+    unsigned rr = (unsigned)((__builtin_amdgcn_sqrtf(8.0f * (float)u + 1.0f) - 1.0f) * 0.5f);
+    rr += (__umul24(rr + 1u, rr + 2u) >> 1) <= u ? 1u : 0u;
+    rr -= (__umul24(rr, rr + 1u) >> 1) > u ? 1u : 0u;
+    return rr;
 }
 
 template <typename T, int QL>
@@ -677,10 +697,8 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
             // from the reversed index u = P-1-t: u = rr(rr+1)/2 + (n-1-b')
             const unsigned t = (unsigned)(tau + min(it + lane, cnt - 1));
             const unsigned u = (unsigned)P - 1u - t;
-            unsigned rr = (unsigned)((__builtin_amdgcn_sqrtf(8.0f * (float)u + 1.0f) - 1.0f) * 0.5f);
-            rr += ((rr + 1u) * (rr + 2u) >> 1) <= u ? 1u : 0u;
-            rr -= ((rr * (rr + 1u)) >> 1) > u ? 1u : 0u;
-            const int ap = n - 2 - (int)rr, bp = n - 1 - (int)(u - ((rr * (rr + 1u)) >> 1));
+            const unsigned rr = tri_root(u);
+            const int ap = n - 2 - (int)rr, bp = n - 1 - (int)(u - (__umul24(rr, rr + 1u) >> 1));
             const T *ea = tab + (size_t)ap * Lay::S;
             const T *eb = tab + (size_t)bp * Lay::S + Lay::SA;
             T sab = tri[get_int(ea[QL + 4]) + sQ + bp];
@@ -956,15 +974,14 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
             const int P = na * (na - 1) / 2;
             const int cnt = (int)min((int64_t)(P - tau), remaining);
             bool hit_found = false;
+            int done_tests = cnt;  // tests of this a run by the wave
             for (int it = 0; it < cnt; it += 64) {
                 const bool valid = it + lane < cnt;
                 const unsigned t = (unsigned)(tau + min(it + lane, cnt - 1));
                 const unsigned u = (unsigned)P - 1u - t;
-                unsigned rr = (unsigned)((__builtin_amdgcn_sqrtf(8.0f * (float)u + 1.0f) - 1.0f) * 0.5f);
-                rr += ((rr + 1u) * (rr + 2u) >> 1) <= u ? 1u : 0u;
-                rr -= ((rr * (rr + 1u)) >> 1) > u ? 1u : 0u;
+                const unsigned rr = tri_root(u);
                 const int b = a + 1 + (na - 2 - (int)rr);
-                const int cc = a + 1 + (na - 1 - (int)(u - ((rr * (rr + 1u)) >> 1)));
+                const int cc = a + 1 + (na - 1 - (int)(u - (__umul24(rr, rr + 1u) >> 1)));
                 const T *eb = tab + (size_t)(b - sQ) * Lay::S;
                 const T *ec = tab + (size_t)(cc - sQ) * Lay::S;
                 T sab = tri[rowa + b], sac = tri[rowa + cc], sbc = tri[get_int(eb[QL + 3]) + cc];
@@ -994,11 +1011,10 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                 if constexpr (sizeof(T) == 8) {
                     dec = decide64((double)r, ok, th) ? DEC_INDEP : DEC_DEP;
                 } else {
-                    const float dmin = fminf(fminf((float)dmina, fminf((float)sbb, (float)d3)),
-                                             fminf((float)h11, (float)h22));
+                    const float dmin = pos_min(pos_min((float)dmina, pos_min((float)sbb, (float)d3)),
+                                               pos_min((float)h11, (float)h22));
                     dec = decide32r((float)r, dmin, ok, rlo32, rhi32, errk);
                 }
-                executed += (uint64_t)min(64, cnt - it);
                 if constexpr (sizeof(T) == 4) {
                     const bool rq = valid && dec == DEC_RECHECK;
                     const unsigned long long qb = __ballot(rq);
@@ -1021,9 +1037,11 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                         atomicMin((unsigned long long *)&A.minhit[e],
                                   (unsigned long long)(rank + it + __ffsll((long long)hb) - 1));
                     hit_found = true;
+                    done_tests = min(cnt, it + 64);
                     break;
                 }
             }
+            executed += (uint64_t)done_tests;
             if (hit_found) {
                 stop = true;
                 break;

@@ -553,42 +553,61 @@ retry:
     std::vector<int64_t> d_lo(ni + 1, 0);  // deletions of instance k: dl[d_lo[k], d_lo[k+1])
     for (const auto &d : dl) ++d_lo[recs[d.first].inst + 1];
     for (int k = 0; k < ni; ++k) d_lo[k + 1] += d_lo[k];
-    parallel_for(ni, [&](int k) {
+    // every deletion owns l slots of its instance's node store and one list
+    // entry, so the sets are decoded in parallel chunks
+    std::vector<size_t> o0(ni), li0(ni);
+    for (int k = 0; k < ni; ++k) {
+        Run &R = *runs[k];
+        const int64_t nd = d_lo[k + 1] - d_lo[k];
+        o0[k] = R.sep.nodes.size();
+        li0[k] = R.sep.lists.size();
+        R.sep.nodes.resize(o0[k] + (size_t)nd * l);
+        R.sep.lists.resize(li0[k] + (size_t)nd);
+        sts[k].deleted += nd;
+    }
+    constexpr int64_t kChunk = 2048;
+    std::vector<std::pair<int, int64_t>> chunks;  // (instance, first deletion)
+    for (int k = 0; k < ni; ++k)
+        for (int64_t t = d_lo[k]; t < d_lo[k + 1]; t += kChunk) chunks.emplace_back(k, t);
+    parallel_for((int)chunks.size(), [&](int c) {
+        const int k = chunks[c].first;
         Run &R = *runs[k];
         std::vector<int> pos;
-        for (int64_t t = d_lo[k]; t < d_lo[k + 1]; ++t) {
+        const int64_t t1 = std::min(d_lo[k + 1], chunks[c].second + kChunk);
+        for (int64_t t = chunks[c].second; t < t1; ++t) {
             const auto &d = dl[t];
             const EdgeRec &er = recs[d.first];
             unrank_host(d.second, er.m, l, ctx->binom_host, pos);
             const int64_t pr = pair_index(er.i, er.j, R.p);
             R.sep.level[pr] = l;
             R.sep.kind[pr] = FPC_SEP_LIST;
-            const size_t o = R.sep.nodes.size();
-            R.sep.lists.emplace_back(pr, (int64_t)o);
-            for (int q = 0; q < l; ++q) R.sep.nodes.push_back(cand[er.cand_off + pos[q]]);
-            std::sort(R.sep.nodes.begin() + o, R.sep.nodes.end());
-            ++sts[k].deleted;
-            if (logging) {
-                // features were computed over the list sorted by id (the cs order)
-                const CandSets &cs = *css[0];
-                const int32_t *orig = cs.nodes.data() + cs.off[cs_edge[d.first]];
-                const int32_t *S = R.sep.nodes.data() + o;
-                for (int a2 = 0; a2 < er.m; ++a2) {
-                    const int v = orig[a2];
-                    const bool in = std::binary_search(S, S + l, v);
-                    for (int f = 0; f < 3; ++f) R.log_x.push_back(hfeat[3 * ((size_t)er.cand_off + a2) + f]);
-                    R.log_y.push_back(in ? 1 : 0);
-                    R.log_group.push_back(R.log_serial);
-                    R.log_level.push_back(l);
-                }
-                ++R.log_serial;
-            }
-        }
-        for (int64_t t = d_lo[k]; t < d_lo[k + 1]; ++t) {
-            const EdgeRec &er = recs[dl[t].first];
+            const size_t o = o0[k] + (size_t)(t - d_lo[k]) * l;
+            R.sep.lists[li0[k] + (size_t)(t - d_lo[k])] = {pr, (int64_t)o};
+            int32_t *S = R.sep.nodes.data() + o;
+            for (int q = 0; q < l; ++q) S[q] = cand[er.cand_off + pos[q]];
+            std::sort(S, S + l);
             R.adj[(size_t)er.i * R.p + er.j] = R.adj[(size_t)er.j * R.p + er.i] = 0;
         }
     });
+    if (logging) {
+        // features were computed over the list sorted by id (the cs order)
+        Run &R = *runs[0];
+        const CandSets &cs = *css[0];
+        for (int64_t t = 0; t < ndel; ++t) {
+            const EdgeRec &er = recs[dl[t].first];
+            const int32_t *orig = cs.nodes.data() + cs.off[cs_edge[dl[t].first]];
+            const int32_t *S = R.sep.nodes.data() + o0[0] + (size_t)t * l;
+            for (int a2 = 0; a2 < er.m; ++a2) {
+                const int v = orig[a2];
+                const bool in = std::binary_search(S, S + l, v);
+                for (int f = 0; f < 3; ++f) R.log_x.push_back(hfeat[3 * ((size_t)er.cand_off + a2) + f]);
+                R.log_y.push_back(in ? 1 : 0);
+                R.log_group.push_back(R.log_serial);
+                R.log_level.push_back(l);
+            }
+            ++R.log_serial;
+        }
+    }
     const double level_ms = now_ms() - t0;
     if (trace_on())
         std::fprintf(stderr,
@@ -810,14 +829,20 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
         // following levels: l = min(p-3, cap, largest candidate set), down to 0
         int l = p - 3;
         if (cap >= 0) l = std::min(l, cap);
+        bool cs_valid = false;  // the graph is unchanged since cs was computed
         while (l >= 0) {
-            candidate_sets(R.adj.data(), p, cs);
+            const double tc = now_ms();
+            if (!cs_valid) candidate_sets(R.adj.data(), p, cs);
+            if (trace_on())
+                std::fprintf(stderr, "[fpc] candidate sets: %zu edges, %.2f ms%s\n", cs.ei.size(), now_ms() - tc,
+                             cs_valid ? " (unchanged graph)" : "");
             const int mmax = largest_cand(cs);
             if (mmax < 0) break;  // no edges left
             l = std::min(l, mmax);
             std::vector<fpc_level_stats> lv;
             if ((rc = run_level(one_run, l, one_cs, lv))) return rc;
             R.levels.push_back(lv[0]);
+            cs_valid = lv[0].deleted == 0;
             --l;
         }
     } else {
@@ -831,7 +856,12 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
             R.levels.push_back(lv[0]);
         }
     }
-    return assemble(R, corr_ms, first_ms, t_start, out);
+    const double ta = now_ms();
+    rc = assemble(R, corr_ms, first_ms, t_start, out);
+    if (trace_on())
+        std::fprintf(stderr, "[fpc] correlation %.2f ms, first level %.2f ms, result %.2f ms, total %.2f ms\n", corr_ms,
+                     first_ms, now_ms() - ta, now_ms() - t_start);
+    return rc;
 }
 
 int validate_batch(const fpc_params *P, int ni, const fpc_instance *inst)
@@ -961,7 +991,7 @@ int skeleton_batch_impl(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_ins
             const int k = ids[t];
             runs[k].levels.push_back(lv[t]);
             next[k] = top - 1;
-            fresh[k] = 0;  // its graph changed
+            fresh[k] = lv[t].deleted == 0;  // candidate sets stay valid while the graph is unchanged
         }
     }
     for (int k = 0; k < ni; ++k) {

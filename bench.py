@@ -37,11 +37,11 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32
 # calibration (fetch x2.000, write x1.000).  Valid only for the kernel source
 # and launch table they were taken with: any change to either makes the
 # figure null until the counters are taken again.
-MEASURED_TRAFFIC = {"bytes_per_launch": 8323309.0,
+MEASURED_TRAFFIC = {"bytes_per_launch": 8359706.0,
                     "sha256": {"paper_2109_04626_amd/csrc/citest.hip":
-                               "e0cb3cc5feac14f8852fac27f1b025f00b8cb79b80234210d7994b1f8f793c3b",
+                               "84833377ea101821ebcc16cd6db227f40059ca24533e4180a10da109e5018d78",
                                "paper_2109_04626_amd/tuning_gfx950.json":
-                               "72bbcab89d47417aa15a427e07332ae4386e0c0decbe97fe179e189f8912e9a1"}}
+                               "c71999b8c07c303e20d1ea1683cf83dd64c668f62ec0c73fb9f70023a330657a"}}
 
 
 def measured_traffic():

@@ -226,6 +226,9 @@ void fpc_result_free(fpc_result *r);
  *                          a window only runs edges with no separating set
  *   first_window_items     work items per edge in the first window (1 .. 64)
  *   max_blocks_per_cu      cap on resident workgroups per CU (0: none)
+ *   shared_prefix_depth    2: tests share their first l-2 conditioning
+ *                          variables (pair kernel); 3 (l >= 3 only): their
+ *                          first l-3 and the next one per wave (triple kernel)
  * fpc_set_tuning(ctx, NULL) restores the defaults.  The autotuner
  * (paper_2109_04626_amd.autotune) measures settings on synthetic workloads
  * and writes a table the Python binding loads into each context. */
@@ -236,6 +239,7 @@ typedef struct {
     int32_t window_growth[FPC_TUNE_LEVELS];
     int32_t first_window_items[FPC_TUNE_LEVELS];
     int32_t max_blocks_per_cu[FPC_TUNE_LEVELS];
+    int32_t shared_prefix_depth[FPC_TUNE_LEVELS];
 } fpc_tuning;
 
 int fpc_get_tuning(const fpc_ctx *ctx, fpc_tuning *out);

@@ -34,7 +34,7 @@ EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "
             "fpc_mlp_forward", "fpc_mlp_grad", "fpc_mlp_train_step", "fpc_get_tuning", "fpc_set_tuning"]
 FPC_TUNE_LEVELS = 17
 TUNING_FIELDS = ("test_ranks_per_wave", "shared_ranks_per_wave", "window_growth", "first_window_items",
-                 "max_blocks_per_cu")
+                 "max_blocks_per_cu", "shared_prefix_depth")
 # launch-shape table written by the autotuner (python -m paper_2109_04626_amd.autotune)
 TUNING_TABLE = os.path.join(_HERE, "tuning_gfx950.json")
 

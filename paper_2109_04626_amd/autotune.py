@@ -23,6 +23,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 CANDIDATES = {
+    "shared_prefix_depth": [2, 3],
     "shared_ranks_per_wave": [1024, 2048, 4096, 8192, 16384, 32768, 65536],
     "test_ranks_per_wave": [256, 512, 2048, 8192],
     "window_growth": [4, 8, 16],
@@ -102,6 +103,8 @@ def tune(reps: int = 2, verbose: bool = True) -> dict:
         for v in cands:
             trial = {k: list(x) for k, x in table.items()}
             trial[field] = [v] * L
+            if field == "shared_prefix_depth":  # the triple kernel needs l >= 3
+                trial[field] = [min(v, 2) if l < 3 else v for l in range(L)]
             fpc.fpc_set_tuning(ctx, trial)
             per_val[v] = measure(fpc, ctx, runs, reps)
             if verbose:
@@ -109,6 +112,8 @@ def tune(reps: int = 2, verbose: bool = True) -> dict:
         levels = sorted({l for m in per_val.values() for l in m})
         for l in levels:
             best = min(cands, key=lambda v: per_val[v].get(l, 1e30))
+            if field == "shared_prefix_depth" and l < 3:
+                best = 2
             table[field][min(l, L - 1)] = best
         fpc.fpc_set_tuning(ctx, table)
         log[field] = {str(v): per_val[v] for v in cands}

@@ -1515,13 +1515,25 @@ size_t tile_bytes(int m, size_t elem) { return elem * ((size_t)m * (m - 1) / 2 +
 
 }  // namespace
 
+// LDS of the shared-prefix kernel the tuning table picks for level l: the
+// pair kernel (prefix l-2) or, from l = 3, the triple kernel (prefix l-3).
+bool use_triple(const fpc_ctx *ctx, int l)
+{
+    return l >= 3 && ctx->tuning.shared_prefix_depth[std::min(l, FPC_TUNE_LEVELS - 1)] == 3;
+}
+
+size_t shared_lds_bytes(const fpc_ctx *ctx, int l, bool fp32, int m)
+{
+    if (l < 2) return 0;
+    if (use_triple(ctx, l)) return fp32 ? triple_lds_bytes<float>(l, m) : triple_lds_bytes<double>(l, m);
+    return fp32 ? pair_lds_bytes<float>(l, m) : pair_lds_bytes<double>(l, m);
+}
+
 int level_class_key(const fpc_ctx *ctx, int l, bool fp32, int m)
 {
     if (l > kMaxTemplL) return 0;  // wide levels: one class
     const size_t cap = (size_t)ctx->lds_per_block - 64;
-    const size_t ps = l == 2 ? (fp32 ? pair_lds_bytes<float>(l, m) : pair_lds_bytes<double>(l, m))
-                    : l >= 3 ? (fp32 ? triple_lds_bytes<float>(l, m) : triple_lds_bytes<double>(l, m))
-                             : 0;
+    const size_t ps = shared_lds_bytes(ctx, l, fp32, m);
     int kind;
     size_t shm;
     if (l >= 2 && ctx->use_pair_kernel && ps <= cap) {
@@ -1576,12 +1588,9 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             k.shm = 8 * ((size_t)(l + 2) * (l + 3) / 2 + 1) + sizeof(int) * (l + 1) + 16;
             if (k.shm > lds_cap) return FPC_EBUDGET;
         } else {
-            const size_t ps = l == 2 ? (fp32 ? pair_lds_bytes<float>(l, k.max_m) : pair_lds_bytes<double>(l, k.max_m))
-                            : l >= 3 ? (fp32 ? triple_lds_bytes<float>(l, k.max_m)
-                                             : triple_lds_bytes<double>(l, k.max_m))
-                                     : 0;
+            const size_t ps = shared_lds_bytes(ctx, l, fp32, k.max_m);
             if (l >= 2 && ctx->use_pair_kernel && ps <= lds_cap) {
-                k.kind = l >= 3 ? K_TRIPLE : K_PAIR;
+                k.kind = use_triple(ctx, l) ? K_TRIPLE : K_PAIR;
                 k.shm = ps;
             } else {
                 const size_t ts = tile_bytes(k.max_m, fp32 ? 4 : 8);
@@ -1816,6 +1825,7 @@ void tuning_defaults(fpc_tuning *t)
         t->window_growth[l] = 8;
         t->first_window_items[l] = 1;
         t->max_blocks_per_cu[l] = 0;
+        t->shared_prefix_depth[l] = l >= 3 ? 3 : 2;
     }
 }
 
@@ -1841,6 +1851,8 @@ extern "C" int fpc_set_tuning(fpc_ctx *ctx, const fpc_tuning *t)
         if (t->window_growth[l] < 2 || t->window_growth[l] > 64) return FPC_EINVAL;
         if (t->first_window_items[l] < 1 || t->first_window_items[l] > 64) return FPC_EINVAL;
         if (t->max_blocks_per_cu[l] < 0 || t->max_blocks_per_cu[l] > 32) return FPC_EINVAL;
+        if (t->shared_prefix_depth[l] != 2 && t->shared_prefix_depth[l] != 3) return FPC_EINVAL;
+        if (l < 3 && t->shared_prefix_depth[l] != 2) return FPC_EINVAL;
     }
     ctx->tuning = *t;
     return FPC_OK;

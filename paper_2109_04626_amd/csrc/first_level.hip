@@ -57,27 +57,42 @@ __global__ __launch_bounds__(1024) void panel_inverse(const double *__restrict__
         }
         __syncthreads();
     }
-    if (r < nb && c < nb) Pinv[r * kNB + c] = P[r][c];
+    // the whole kNB x kNB block, zero outside nb, so later passes may run
+    // over kNB terms
+    Pinv[r * kNB + c] = (r < nb && c < nb) ? P[r][c] : 0.0;
 }
 
-// V = A[:,K] (p x nb, row stride kNB) and U = Pinv A[K,:] (nb x p); one
-// thread per (row r of the panel, column j).
-__global__ __launch_bounds__(256) void panel_copy(const double *__restrict__ A, int p, int k0, int nb,
-                                                  const double *__restrict__ Pinv, double *__restrict__ V,
-                                                  double *__restrict__ U)
+// U = Pinv A[K,:] (nb x p): a block takes 64 columns (lanes, coalesced
+// rows of A) and kNB/4 panel rows (blockIdx.y); the panel column of A sits
+// in registers.
+__global__ __launch_bounds__(256) void panel_u(const double *__restrict__ A, int p, int k0, int nb,
+                                               const double *__restrict__ Pinv, double *__restrict__ U)
 {
     const int j = blockIdx.x * 64 + threadIdx.x % 64;
-    const int r0 = threadIdx.x / 64;  // 4 rows of the panel per block, strided
     if (j >= p) return;
-    for (int r = r0; r < nb; r += 4) {
+    double a[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) a[c] = c < nb ? A[(size_t)(k0 + c) * p + j] : 0.0;
+    const int r0 = blockIdx.y * (kNB / 4);
+    for (int r = r0 + threadIdx.x / 64; r < r0 + kNB / 4 && r < nb; r += 4) {
         double s = 0.0;
-        for (int c = 0; c < nb; ++c) s = fma(Pinv[r * kNB + c], A[(size_t)(k0 + c) * p + j], s);
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) s = fma(Pinv[r * kNB + c], a[c], s);
         U[(size_t)r * p + j] = s;
-        V[(size_t)j * kNB + r] = A[(size_t)j * p + k0 + r];
     }
 }
 
-// The sweep update over 64 x 64 tiles of A.
+// V = A[:,K] (p x kNB, row stride kNB): 8 rows per block, the panel
+// columns along the low 5 bits of the thread index (coalesced).
+__global__ __launch_bounds__(256) void panel_v(const double *__restrict__ A, int p, int k0, int nb,
+                                               double *__restrict__ V)
+{
+    const int j = blockIdx.x * 8 + threadIdx.x / 32, r = threadIdx.x % 32;
+    if (j < p && r < nb) V[(size_t)j * kNB + r] = A[(size_t)j * p + k0 + r];
+}
+
+// The sweep update over kUT x kUT tiles of A; lanes along the columns j
+// (coalesced), each thread four rows.
 __global__ __launch_bounds__(256) void sweep_update(double *__restrict__ A, int p, int k0, int nb,
                                                     const double *__restrict__ V, const double *__restrict__ U,
                                                     const double *__restrict__ Pinv)
@@ -94,31 +109,32 @@ __global__ __launch_bounds__(256) void sweep_update(double *__restrict__ A, int 
         Us[r][c] = (j < p && r < nb) ? U[(size_t)r * p + j] : 0.0;
     }
     __syncthreads();
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    for (int q = 0; q < 2; ++q) {
-        const int i = i0 + ty * 2 + q;
-        if (i >= p) continue;
+    const int tx = threadIdx.x % kUT, ty = threadIdx.x / kUT;  // 32 x 8
+    const int j = j0 + tx;
+    if (j >= p) return;  // no barrier follows
+    const bool inK_j = j >= k0 && j < k0 + nb;
+#pragma unroll
+    for (int q = 0; q < kUT / 8; ++q) {
+        const int ri = ty + 8 * q, i = i0 + ri;
+        if (i >= p) break;
         const bool inK_i = i >= k0 && i < k0 + nb;
-        for (int s = 0; s < 2; ++s) {
-            const int j = j0 + tx * 2 + s;
-            if (j >= p) continue;
-            const bool inK_j = j >= k0 && j < k0 + nb;
-            double v;
-            if (inK_i && inK_j) {
-                v = Pinv[(i - k0) * kNB + (j - k0)];
-            } else if (inK_i) {
-                v = Us[i - k0][tx * 2 + s];
-            } else if (inK_j) {
-                double acc = 0.0;
-                for (int c = 0; c < nb; ++c) acc = fma(Vs[ty * 2 + q][c], Pinv[c * kNB + (j - k0)], acc);
-                v = -acc;
-            } else {
-                double acc = A[(size_t)i * p + j];
-                for (int c = 0; c < nb; ++c) acc = fma(-Vs[ty * 2 + q][c], Us[c][tx * 2 + s], acc);
-                v = acc;
-            }
-            A[(size_t)i * p + j] = v;
+        double v;
+        if (inK_i && inK_j) {
+            v = Pinv[(i - k0) * kNB + (j - k0)];
+        } else if (inK_i) {
+            v = Us[i - k0][tx];
+        } else if (inK_j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < kNB; ++c) acc = fma(Vs[ri][c], Pinv[c * kNB + (j - k0)], acc);
+            v = -acc;
+        } else {
+            double acc = A[(size_t)i * p + j];
+#pragma unroll
+            for (int c = 0; c < kNB; ++c) acc = fma(-Vs[ri][c], Us[c][tx], acc);
+            v = acc;
         }
+        A[(size_t)i * p + j] = v;
     }
 }
 
@@ -172,7 +188,8 @@ int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r
     for (int k0 = 0; k0 < p; k0 += kNB) {
         const int nb = p - k0 < kNB ? p - k0 : kNB;
         panel_inverse<<<1, 1024, 0, st>>>(A, p, k0, nb, Pinv, bad);
-        panel_copy<<<(p + 63) / 64, 256, 0, st>>>(A, p, k0, nb, Pinv, V, U);
+        panel_u<<<dim3((p + 63) / 64, 4), 256, 0, st>>>(A, p, k0, nb, Pinv, U);
+        panel_v<<<(p + 7) / 8, 256, 0, st>>>(A, p, k0, nb, V);
         sweep_update<<<dim3(nbt, nbt), 256, 0, st>>>(A, p, k0, nb, V, U, Pinv);
     }
     first_level_decide<<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(A, p, n, q, r_out, indep_out, bad);

@@ -699,23 +699,29 @@ int first_stage(Run &R, double *ms)
     }
     if ((rc = first_level(ctx, R.C64, p, R.n, R.q, d_r, d_ind, nullptr))) return rc;
     FPC_HIP(hipEventRecord(ctx->ev1, s));
-    std::vector<uint8_t> ind(pp);
-    FPC_HIP(hipMemcpyAsync(ind.data(), d_ind, pp, hipMemcpyDeviceToHost, s));
+    if ((rc = ctx->h_back.ensure(pp))) return rc;
+    const uint8_t *ind = ctx->h_back.as<uint8_t>();
+    FPC_HIP(hipMemcpyAsync(ctx->h_back.ptr, d_ind, pp, hipMemcpyDeviceToHost, s));
     FPC_HIP(hipStreamSynchronize(s));
     float kms = 0.f;
     FPC_HIP(hipEventElapsedTime(&kms, ctx->ev0, ctx->ev1));
     st.kernel_ms = kms;
-    int64_t dels = 0;
-    for (int i = 0; i < p; ++i)
-        for (int j = i + 1; j < p; ++j)
-            if (ind[(size_t)i * p + j]) {
-                const int64_t pr = pair_index(i, j, p);
-                R.sep.level[pr] = p - 2;
-                R.sep.kind[pr] = FPC_SEP_ALL_BUT;
-                R.adj[(size_t)i * p + j] = R.adj[(size_t)j * p + i] = 0;
-                ++dels;
-            }
-    st.deleted = dels;
+    // deletions, rows interleaved over host threads (each pair is written once)
+    const int nblk = std::min(p, 64);
+    std::vector<int64_t> dels(nblk, 0);
+    parallel_for(nblk, [&](int b) {
+        for (int i = b; i < p; i += nblk)
+            for (int j = i + 1; j < p; ++j)
+                if (ind[(size_t)i * p + j]) {
+                    const int64_t pr = pair_index(i, j, p);
+                    R.sep.level[pr] = p - 2;
+                    R.sep.kind[pr] = FPC_SEP_ALL_BUT;
+                    R.adj[(size_t)i * p + j] = R.adj[(size_t)j * p + i] = 0;
+                    ++dels[b];
+                }
+    });
+    st.deleted = 0;
+    for (int64_t d : dels) st.deleted += d;
     R.total_exec += st.tests_executed;
     R.spent_possible += st.tests_possible;
     *ms = now_ms() - t0;

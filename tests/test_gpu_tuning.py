@@ -37,6 +37,7 @@ EXTREME = {
     "window_growth": [2] * 17,
     "first_window_items": [3] * 17,
     "max_blocks_per_cu": [1] * 17,
+    "shared_prefix_depth": [2] * 17,  # the pair kernel at every level
 }
 
 
@@ -70,7 +71,7 @@ def test_tuning_rejects_out_of_range(fpc):
     with fpc.Context(0, tuning="default") as c:
         before = fpc.fpc_get_tuning(c)
         for field, bad in (("test_ranks_per_wave", 10), ("window_growth", 1), ("first_window_items", 0),
-                           ("max_blocks_per_cu", -1)):
+                           ("max_blocks_per_cu", -1), ("shared_prefix_depth", 3)):
             t = {field: [bad] * 17}
             with pytest.raises(fpc.FastPCError):
                 fpc.fpc_set_tuning(c, t)

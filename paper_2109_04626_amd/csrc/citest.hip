@@ -46,6 +46,7 @@ constexpr int kSteps = 8;
 constexpr int kRanksPerWave = 64 * kSteps;               // default ranks per wave, per-test kernel
 constexpr int kGenericRanks = 16;                        // ranks per workgroup, wide-level kernel
 constexpr double kErrSafety = 4.0;                       // multiplier of the FP32 error bound
+constexpr int kMinhitEvery = 512;  // shared-prefix kernels: tests between reads of an edge's minimum hit
 
 enum : int { DEC_DEP = 0, DEC_INDEP = 1, DEC_RECHECK = 2 };
 
@@ -886,6 +887,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
     const float errk = (float)(kErrSafety * th.c_eff * (L + 2));
     const float rlo32 = (float)th.rb_lo, rhi32 = (float)th.rb_hi;
     bool stop = false;
+    int since_check = kMinhitEvery;  // tests since the shared minimum was last read
     while (!stop) {
         // ---- Q state (identical in every lane)
         T LQ[QL > 0 ? QL * (QL + 1) / 2 : 1], invQ[QLL], uQ[QLL], vQ[QLL];
@@ -954,10 +956,15 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
         wave_sync();
         // ---- a loop (uniform), pairs (b, c) after a across the lanes
         for (; a <= m - 3; ++a) {
-            const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
-            if (mh < (unsigned long long)rank) {
-                stop = true;
-                break;
+            // another wave's hit below this rank ends the range; the shared
+            // minimum is read once per kMinhitEvery tests run
+            if (since_check >= kMinhitEvery) {
+                since_check = 0;
+                const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
+                if (mh < (unsigned long long)rank) {
+                    stop = true;
+                    break;
+                }
             }
             const T *eaP = tab + (size_t)(a - sQ) * Lay::S;
             T wa[QLL];
@@ -1042,6 +1049,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                 }
             }
             executed += (uint64_t)done_tests;
+            since_check += done_tests;
             if (hit_found) {
                 stop = true;
                 break;

@@ -706,19 +706,27 @@ int first_stage(Run &R, double *ms)
     float kms = 0.f;
     FPC_HIP(hipEventElapsedTime(&kms, ctx->ev0, ctx->ev1));
     st.kernel_ms = kms;
-    // deletions, rows interleaved over host threads (each pair is written once)
-    const int nblk = std::min(p, 64);
+    // deletions on host threads, each owning a block of rows: it clears its
+    // rows of adj (the decision matrix is symmetric) and records the pairs
+    // (i, j > i) of its rows, so no two threads write the same cache line
+    // except at block edges
+    const int nblk = std::min(p, 16);
     std::vector<int64_t> dels(nblk, 0);
     parallel_for(nblk, [&](int b) {
-        for (int i = b; i < p; i += nblk)
+        const int i0 = (int)((int64_t)p * b / nblk), i1 = (int)((int64_t)p * (b + 1) / nblk);
+        for (int i = i0; i < i1; ++i) {
+            const uint8_t *irow = ind + (size_t)i * p;
+            uint8_t *arow = R.adj.data() + (size_t)i * p;
+            for (int j = 0; j < p; ++j)
+                if (j != i && irow[j]) arow[j] = 0;
             for (int j = i + 1; j < p; ++j)
-                if (ind[(size_t)i * p + j]) {
+                if (irow[j]) {
                     const int64_t pr = pair_index(i, j, p);
                     R.sep.level[pr] = p - 2;
                     R.sep.kind[pr] = FPC_SEP_ALL_BUT;
-                    R.adj[(size_t)i * p + j] = R.adj[(size_t)j * p + i] = 0;
                     ++dels[b];
                 }
+        }
     });
     st.deleted = 0;
     for (int64_t d : dels) st.deleted += d;

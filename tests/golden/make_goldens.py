@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import semdata  # noqa: E402
 
-GOLDENS = [("er_p1000_n10000_d4", 0)]
+GOLDENS = [("er_p1000_n10000_d4", 0), ("er_p95_n5000_d12", 0)]
 
 
 def make(name: str, seed: int) -> str:

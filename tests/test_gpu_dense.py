@@ -1,0 +1,62 @@
+"""Dense small graph (p = 95, expected degree 12, n = 5000, FP64 data,
+max_level 6): FP32 tests with FP64 re-runs near the threshold must give
+the oracle's skeleton bit-exact; the FP64 form also its separating sets and
+the oracle's test count.  Against the oracle's stored result
+(tests/golden/make_goldens.py).  GPU only."""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import semdata
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+import make_goldens  # noqa: E402
+
+NAME, SEED = "er_p95_n5000_d12", 0
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_04626_amd as fpc
+
+    X, sem, cfg = semdata.workload(NAME, SEED)
+    gold = make_goldens.load(NAME, SEED)
+    ctx = fpc.Context(0)
+    yield fpc, ctx, X, torch.from_numpy(X).cuda(), cfg, gold
+    ctx.close()
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dense_skeleton_bit_exact(setup, prec, flags):
+    fpc, ctx, X, Xd, cfg, gold = setup
+    print(f"[dense] {NAME} seed={SEED} precision={prec} flags={flags}", flush=True)
+    assert gold["p"] == cfg["p"] and gold["max_level"] == cfg["max_level"] and gold["min_margin"] > 1e-9
+    got = fpc.fpc_skeleton(ctx, Xd, alpha=cfg["alpha"], max_level=cfg["max_level"], precision=prec, flags=flags)
+    assert np.array_equal(got["adj"], gold["adj"])
+    assert np.array_equal(got["sep_level"], gold["sep_level"])
+    assert np.array_equal(got["sep_kind"], gold["sep_kind"])
+    assert got["total_required"] == gold["total_tests"]
+    if prec == 0:
+        assert got["sepsets"] == gold["sepsets"]
+    else:
+        C = oracle.corr(X)
+        bad = [(k, K) for k, K in got["sepsets"].items() if not oracle.ci_test(C, cfg["n"], *k, K, gold["q"])[0]]
+        assert not bad, bad[:5]
+        print(f"  re-run in FP64: {sum(x['tests_rechecked'] for x in got['levels'])} of "
+              f"{got['total_tests']} tests; corr max abs err {got['corr_max_abs_err']:.2e}", flush=True)
+    lv = {x["level"]: x for x in got["levels"]}
+    for row in gold["levels"]:
+        l, elig, dels = int(row[0]), int(row[1]), int(row[3])
+        assert lv[l]["deleted"] == dels and lv[l]["edges_eligible"] == elig

@@ -2,9 +2,9 @@
 // with S the cross-product matrix of the centred columns.
 //
 // Two methods:
-//   FP64     column means in FP64, centred FP64 products on the vector
-//            units (LDS-tiled, upper-triangle tiles only, split over the
-//            samples so that the launch fills the chip);
+//   FP64     column means in FP64, centred FP64 products on the FP64
+//            matrix cores (LDS-staged, upper-triangle tiles only, split over
+//            the samples so that the launch fills the chip);
 //   BF16X3   columns standardised in FP64, each value split as
 //            z = hi + lo with hi, lo in bf16, and S ~ hi.hi + hi.lo + lo.hi
 //            on the MFMA units (v_mfma_f32_16x16x32_bf16) with FP32
@@ -80,7 +80,13 @@ __device__ inline void tile_of(int t, int nbt, int &bi, int &bj)
 }
 
 // S_part[split][i][j] for the upper-triangle tiles; split = blockIdx.y covers
-// samples [split*chunk, (split+1)*chunk).
+// samples [split*chunk, (split+1)*chunk).  FP64 matrix cores: each wave owns
+// a 32 x 32 quarter of the 64 x 64 tile as 2 x 2 blocks of
+// v_mfma_f64_16x16x4_f64 (A = the tile rows' centred samples, B = the tile
+// columns'); lane l feeds A[l % 16][l / 16] and B[l / 16][l % 16], and
+// accumulator v of lane l is D[4 v + l / 16][l % 16].
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 template <typename TX>
 __global__ __launch_bounds__(256) void syrk_f64(const TX *__restrict__ X, const double *__restrict__ mu,
                                                 int n, int p, int nbt, int chunk,
@@ -91,12 +97,13 @@ __global__ __launch_bounds__(256) void syrk_f64(const TX *__restrict__ X, const 
     const int t0 = blockIdx.y * chunk, t1 = min(n, t0 + chunk);
     __shared__ double As[kK][kT + 1];
     __shared__ double Bs[kK][kT + 1];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wr = wave / 2, wc = wave % 2;  // the wave's 32 x 32 quarter
+    v4d acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
     for (int k0 = t0; k0 < t1; k0 += kK) {
         for (int e = threadIdx.x; e < kK * kT; e += 256) {
             const int r = e / kT, c = e % kT, row = k0 + r;
@@ -105,32 +112,34 @@ __global__ __launch_bounds__(256) void syrk_f64(const TX *__restrict__ X, const 
             Bs[r][c] = (row < t1 && cb < p) ? (double)X[(size_t)row * p + cb] - mu[cb] : 0.0;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int r = 0; r < kK; ++r) {
-            double a[4], b[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[r][ty * 4 + q];
-                b[q] = Bs[r][tx * 4 + q];
+        for (int kk = 0; kk < kK; kk += 4) {
+            const int kr = kk + lane / 16;
+            double av[2], bv[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                av[t] = As[kr][wr * 32 + t * 16 + lane % 16];
+                bv[t] = Bs[kr][wc * 32 + t * 16 + lane % 16];
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int s = 0; s < 4; ++s) acc[q][s] = fma(a[q], b[s], acc[q][s]);
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
         __syncthreads();
     }
     double *out = Spart + (size_t)blockIdx.y * p * p;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = bi * kT + ty * 4 + q;
-        if (i >= p) continue;
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int j = bj * kT + tx * 4 + s;
-            if (j < p) out[(size_t)i * p + j] = acc[q][s];
-        }
-    }
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = bi * kT + wr * 32 + a * 16 + 4 * v + lane / 16;
+                const int j = bj * kT + wc * 32 + b * 16 + lane % 16;
+                if (i < p && j < p) out[(size_t)i * p + j] = acc[a][b][v];
+            }
 }
 
 // C[i][j] = S_ij / sqrt(S_ii S_jj), S summed over the splits in order and
@@ -291,7 +300,7 @@ int splits_for(int tiles, int n, int num_cus)
 
 }  // namespace
 
-int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out)
+int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out, bool reuse_stats)
 {
     if (!X || !C_out || n < 2 || p < 1) return FPC_EINVAL;
     if (x_dtype != FPC_F64 && x_dtype != FPC_F32) return FPC_EINVAL;
@@ -310,9 +319,11 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
     double *mu = ctx->colstat.as<double>(), *sd = mu + p, *part = sd + p;
     int *flags = ctx->flag.as<int>();
     double *Spart = ctx->inv_work.as<double>();
-    FPC_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(int), st));
     dim3 g0((p + 255) / 256, nchunks);
-    for (int pass = 0; pass < 2; ++pass) {
+    // column means and deviations (kept from the previous call on the same
+    // data when reuse_stats is set)
+    if (!reuse_stats) FPC_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(int), st));
+    for (int pass = 0; pass < 2 && !reuse_stats; ++pass) {
         if (x_dtype == FPC_F64)
             colstat_partial<double><<<g0, 256, 0, st>>>((const double *)X, n, p, mu, pass, part, flags);
         else

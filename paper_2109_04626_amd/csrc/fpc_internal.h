@@ -106,7 +106,10 @@ struct EdgeRec {
 };
 
 // ---- correlation (corr.hip)
-int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out);
+// reuse_stats: the column statistics of the previous call on the same X
+// (same n, p) are still in the context and are used as they are.
+int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out,
+                 bool reuse_stats = false);
 int corr_max_abs_diff(fpc_ctx *ctx, const double *c64, const float *c32, int p, double *out);
 // out (device, n x p) := rows[r] of X (device, x_rows x p); FPC_EINVAL for an index out of range.
 int gather_rows(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p, const int32_t *rows, int n,

@@ -666,7 +666,7 @@ int corr_stage(Run &R, const void *X, int x_dtype, double *C64, float *C32, doub
     if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_FP64, C64))) return rc;
     R.C64 = C64;
     if (R.mixed) {
-        if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_BF16X3, C32))) return rc;
+        if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_BF16X3, C32, true))) return rc;
         R.C32 = C32;
         if ((rc = corr_max_abs_diff(R.ctx, R.C64, R.C32, R.p, &R.c_err))) return rc;
     }

@@ -498,12 +498,13 @@ def fpc_skeleton_batch(ctx: Context, instances, alpha: float = 0.01, max_level: 
 
 
 class SepSets(Mapping):
-    """Read-only {(i, j): sorted separating set} over the LIST-kind pairs,
-    backed by the result's CSR arrays (built lazily)."""
+    """Read-only {(i, j): sorted separating set} over the LIST-kind pairs.
+    ``idx`` holds their pair indices in increasing order and ``off`` the
+    offsets of their sets in ``nodes`` (the library stores the LIST sets in
+    pair order, each as long as its level); the pair map is built lazily."""
 
-    def __init__(self, p, kind, off, nodes):
-        self._p, self._off, self._nodes = p, off, nodes
-        self._idx = np.nonzero(kind == FPC_SEP_LIST)[0]
+    def __init__(self, p, idx, off, nodes):
+        self._p, self._idx, self._off, self._nodes = p, idx, off, nodes
         self._map = None
 
     def _pairs(self):
@@ -515,12 +516,12 @@ class SepSets(Mapping):
             i -= (i * p - i * (i + 1) // 2 > k)
             i += ((i + 1) * p - (i + 1) * (i + 2) // 2 <= k)
             j = k - (i * p - i * (i + 1) // 2) + i + 1
-            self._map = {(int(a), int(b)): int(kk) for a, b, kk in zip(i, j, k)}
+            self._map = {(int(a), int(b)): t for t, (a, b) in enumerate(zip(i.tolist(), j.tolist()))}
         return self._map
 
     def __getitem__(self, key):
-        k = self._pairs()[key]
-        return self._nodes[self._off[k]:self._off[k + 1]].tolist()
+        t = self._pairs()[key]
+        return self._nodes[self._off[t]:self._off[t + 1]].tolist()
 
     def __iter__(self):
         return iter(self._pairs())
@@ -529,16 +530,32 @@ class SepSets(Mapping):
         return len(self._idx)
 
 
+class _Result(dict):
+    """fpc_skeleton result; ``sep_off`` (the P + 1 offsets of the C result)
+    is rebuilt on first use from the kinds and levels."""
+
+    def __missing__(self, key):
+        if key != "sep_off":
+            raise KeyError(key)
+        lens = np.where(self["sep_kind"] == FPC_SEP_LIST, self["sep_level"], 0).astype(np.int64)
+        off = np.zeros(len(lens) + 1, np.int64)
+        np.cumsum(lens, out=off[1:])
+        self["sep_off"] = off
+        return off
+
+
 def _unpack(r: fpc_result) -> dict:
     p = r.p
     P = p * (p - 1) // 2
     adj = np.ctypeslib.as_array(r.adj, shape=(p * p,)).reshape(p, p).copy()
     lev = np.ctypeslib.as_array(r.sep_level, shape=(P,)).copy() if P else np.zeros(0, np.int32)
     kind = np.ctypeslib.as_array(r.sep_kind, shape=(P,)).copy() if P else np.zeros(0, np.int8)
-    off = np.ctypeslib.as_array(r.sep_off, shape=(P + 1,)).copy()
-    tot = int(off[-1])
+    tot = int(r.sep_off[P])
     nodes = np.ctypeslib.as_array(r.sep_nodes, shape=(max(tot, 1),))[:tot].copy()
-    sepsets = SepSets(p, kind, off, nodes)
+    idx = np.flatnonzero(kind == FPC_SEP_LIST)
+    off = np.zeros(len(idx) + 1, np.int64)
+    np.cumsum(lev[idx], out=off[1:])
+    sepsets = SepSets(p, idx, off, nodes)
     levels = []
     for k in range(r.n_levels):
         s = r.levels[k]
@@ -550,12 +567,12 @@ def _unpack(r: fpc_result) -> dict:
                    y=np.ctypeslib.as_array(r.log_y, shape=(nlog,)).copy(),
                    group=np.ctypeslib.as_array(r.log_group, shape=(nlog,)).copy(),
                    level=np.ctypeslib.as_array(r.log_level, shape=(nlog,)).copy())
-    return dict(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets, sep_off=off, sep_nodes=nodes,
-                levels=levels, log=log,
-                total_tests=int(r.total_tests), total_required=sum(x["tests_required"] for x in levels),
-                q=float(r.q), corr_ms=float(r.corr_ms),
-                first_level_ms=float(r.first_level_ms), total_ms=float(r.total_ms),
-                corr_max_abs_err=float(r.corr_max_abs_err), p=p)
+    return _Result(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets, sep_nodes=nodes,
+                   levels=levels, log=log,
+                   total_tests=int(r.total_tests), total_required=sum(x["tests_required"] for x in levels),
+                   q=float(r.q), corr_ms=float(r.corr_ms),
+                   first_level_ms=float(r.first_level_ms), total_ms=float(r.total_ms),
+                   corr_max_abs_err=float(r.corr_max_abs_err), p=p)
 
 
 def sepset_of(res: dict, i: int, j: int):

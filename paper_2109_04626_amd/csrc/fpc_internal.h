@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -187,6 +188,12 @@ struct CandSets {
 };
 // threads: host threads for the merge (0: up to 16).
 void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads = 0);
+
+// ---- host thread pool (hostpool.cpp)
+// fn(k) for k in [0, n) on the library's persistent host threads (inline
+// when the pool is busy or when called from inside a job).
+void host_parallel(int n, const std::function<void(int)> &fn);
+int host_threads();
 
 // ---- quantile (quantile.cpp)
 double normal_quantile_upper(double alpha);  // Phi^{-1}(1 - alpha/2)

@@ -167,8 +167,7 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
             len.push_back((int64_t)(dst.size() - start));
         }
     };
-    unsigned hw = std::thread::hardware_concurrency();
-    int nth = threads > 0 ? threads : (int)std::min<unsigned>(hw ? hw : 1, 16u);
+    int nth = threads > 0 ? threads : host_threads();
     if (E < 2048) nth = 1;
     std::vector<std::vector<int32_t>> parts(nth);
     std::vector<std::vector<int64_t>> lens(nth);
@@ -177,13 +176,10 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
     if (nth == 1) {
         merge_range(0, E, parts[0], lens[0]);
     } else {
-        std::vector<std::thread> pool;
-        for (int t = 0; t < nth; ++t)
-            pool.emplace_back([&, t] {
-                parts[t].reserve((size_t)(bounds[t + 1] - bounds[t]) * 48);
-                merge_range(bounds[t], bounds[t + 1], parts[t], lens[t]);
-            });
-        for (auto &th : pool) th.join();
+        host_parallel(nth, [&](int t) {
+            parts[t].reserve((size_t)(bounds[t + 1] - bounds[t]) * 48);
+            merge_range(bounds[t], bounds[t + 1], parts[t], lens[t]);
+        });
     }
     size_t total = 0;
     for (const auto &v : parts) total += v.size();

@@ -303,23 +303,11 @@ struct Run {
     int32_t log_serial = 0;
 };
 
-// Runs fn(k) for k in [0, n) on up to 16 host threads (inline when n is 1).
+// Runs fn(k) for k in [0, n) on the library's host threads.
 template <class F>
 void parallel_for(int n, F &&fn)
 {
-    const unsigned hw = std::thread::hardware_concurrency();
-    const int nth = std::min(n, (int)std::min<unsigned>(hw ? hw : 1, 16u));
-    if (nth <= 1) {
-        for (int k = 0; k < n; ++k) fn(k);
-        return;
-    }
-    std::atomic<int> next{0};
-    std::vector<std::thread> pool;
-    for (int t = 0; t < nth; ++t)
-        pool.emplace_back([&] {
-            for (int k = next++; k < n; k = next++) fn(k);
-        });
-    for (auto &th : pool) th.join();
+    host_parallel(n, std::function<void(int)>(fn));
 }
 
 // Runs one level (l >= 0) of one or more instances, each on its frozen
@@ -958,20 +946,12 @@ int skeleton_batch_impl(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_ins
             std::vector<int> todo;
             for (int k = 0; k < ni; ++k)
                 if (!done[k] && next[k] >= 0 && !fresh[k]) todo.push_back(k);
-            const unsigned hw = std::thread::hardware_concurrency();
-            const int nth = (int)std::min<size_t>(todo.size(), std::min<unsigned>(hw ? hw : 1, 16u));
-            if (nth <= 1) {
-                for (int k : todo) candidate_sets(runs[k].adj.data(), runs[k].p, cs[k]);
-            } else {
-                std::atomic<size_t> at{0};
-                std::vector<std::thread> pool;
-                for (int t = 0; t < nth; ++t)
-                    pool.emplace_back([&] {
-                        for (size_t x = at++; x < todo.size(); x = at++)
-                            candidate_sets(runs[todo[x]].adj.data(), runs[todo[x]].p, cs[todo[x]], 1);
-                    });
-                for (auto &th : pool) th.join();
-            }
+            if (todo.size() == 1)
+                candidate_sets(runs[todo[0]].adj.data(), runs[todo[0]].p, cs[todo[0]]);
+            else
+                parallel_for((int)todo.size(), [&](int x) {
+                    candidate_sets(runs[todo[x]].adj.data(), runs[todo[x]].p, cs[todo[x]], 1);
+                });
             for (int k : todo) fresh[k] = 1;
             if (trace_on()) std::fprintf(stderr, "[fpc] candidate sets of %zu instance(s)\n", todo.size());
         }

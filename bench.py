@@ -37,11 +37,11 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32
 # calibration (fetch x2.000, write x1.000).  Valid only for the kernel source
 # and launch table they were taken with: any change to either makes the
 # figure null until the counters are taken again.
-MEASURED_TRAFFIC = {"bytes_per_launch": 8359706.0,
+MEASURED_TRAFFIC = {"bytes_per_launch": 8324148.0,
                     "sha256": {"paper_2109_04626_amd/csrc/citest.hip":
-                               "84833377ea101821ebcc16cd6db227f40059ca24533e4180a10da109e5018d78",
+                               "ca9cc8501fb1a07749de5499098922db2a6711c6edf6d2cf16ce29a13d567774",
                                "paper_2109_04626_amd/tuning_gfx950.json":
-                               "c71999b8c07c303e20d1ea1683cf83dd64c668f62ec0c73fb9f70023a330657a"}}
+                               "29feb5af2bb4a581d54b494454c6abdbfe3970ba18c4164e58eaabfb4954dec5"}}
 
 
 def measured_traffic():

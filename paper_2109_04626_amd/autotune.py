@@ -2,8 +2,10 @@
 
 The level kernels take their work in items of consecutive ranks of one
 edge; how many ranks a wave takes per item, how fast the rank windows
-grow, how many items an edge gets in the first window and how many
-workgroups may share a CU change only the speed, never the results.  This
+grow, how many items an edge gets in the first window, how many
+workgroups may share a CU and how long a conditioning prefix the
+shared-prefix kernels factor once change only the speed, never the
+results.  This
 tool measures candidate values on seeded synthetic workloads, keeps per
 level the value with the smallest device time of that level's tests
 (coordinate descent, one field at a time), and writes the table the Python

@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "fpc_internal.h"
 
@@ -291,6 +292,7 @@ struct LevelArgs {
     int64_t win_lo, win_hi;
     int ranks_per_block;
     int max_m;  // largest candidate set of the level
+    int pdec_n;  // entries of the triple kernel's pair table
 };
 
 __device__ __forceinline__ int64_t uniform_i64(int64_t v)
@@ -299,6 +301,9 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v)
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+
+// A value equal in every lane, marked so for the compiler (kept in SGPRs)
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Persistent workgroups: each takes work items (a run of consecutive ranks
 // of one edge) from the window's counter until none is left.  Item bodies
@@ -405,7 +410,7 @@ __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsi
         int c[LL], my[LL];
         if constexpr (L > 0) unrank<L>(wlo, m, A.binom, c);
         for (int64_t base = wlo; base < whi; base += 64) {
-            const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
+            const unsigned long long mh = (unsigned long long)uniform_i64((int64_t)load_minhit(&A.minhit[e]));
             if (mh < (unsigned long long)base) break;
             bool more = true;
             if constexpr (L > 0) more = walk64<L>(c, m, lane, my);
@@ -614,7 +619,7 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
     const float errk = (float)(kErrSafety * th.c_eff * (L + 2));
     const float rlo32 = (float)th.rb_lo, rhi32 = (float)th.rb_hi;
     while (remaining > 0) {
-        const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
+        const unsigned long long mh = (unsigned long long)uniform_i64((int64_t)load_minhit(&A.minhit[e]));
         if (mh < (unsigned long long)rank) break;
         // ---- Q state: L_Q, u_Q, v_Q, H_Q (identical in every lane)
         T LQ[QL > 0 ? QL * (QL + 1) / 2 : 1], invQ[QLL], uQ[QLL], vQ[QLL];
@@ -833,14 +838,15 @@ struct TripleLayout {
 };
 
 template <typename T, int QL>
-__device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, unsigned char *smem)
+__device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, unsigned char *smem,
+                                            const uint16_t *__restrict__ pdec)
 {
     using Lay = TripleLayout<T, QL>;
     constexpr int L = QL + 3;
     constexpr int QLL = QL > 0 ? QL : 1;
     const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
-    const int m = E.m;
+    const int m = uniform_i32(E.m);
     const int64_t rpb = A.ranks_per_block, rpw = rpb / kWaves;
     const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * rpb;
     const int64_t r1 = min(r0 + rpb, min(A.win_hi, E.ntests));
@@ -869,20 +875,21 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
     if (wlo >= whi) return;  // no later block-wide barrier
     const auto row = [&](int a) { return a * (2 * m - a - 3) / 2 - 1; };
 
+    // the walk's position (Q, a, tau, rank) is the same in every lane
     int c[L];
     unrank<L>(wlo, m, A.binom, c);
     int Q[QLL];
 #pragma unroll
-    for (int t = 0; t < QL; ++t) Q[t] = c[t];
+    for (int t = 0; t < QL; ++t) Q[t] = uniform_i32(c[t]);
     int sQ = QL > 0 ? Q[QL - 1] + 1 : 0;
-    int a = c[QL];
+    int a = uniform_i32(c[QL]);
     int tau;
     {
-        const int na = m - 1 - a, b0 = c[QL + 1] - (a + 1), c0 = c[QL + 2] - (a + 1);
+        const int na = m - 1 - a, b0 = uniform_i32(c[QL + 1]) - (a + 1), c0 = uniform_i32(c[QL + 2]) - (a + 1);
         tau = b0 * (2 * na - b0 - 1) / 2 + (c0 - b0 - 1);
     }
-    int64_t rank = wlo;
-    int64_t remaining = whi - wlo;
+    int64_t rank = uniform_i64(wlo);
+    int64_t remaining = uniform_i64(whi - wlo);
     uint64_t executed = 0;
     const float errk = (float)(kErrSafety * th.c_eff * (L + 2));
     const float rlo32 = (float)th.rb_lo, rhi32 = (float)th.rb_hi;
@@ -960,7 +967,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
             // minimum is read once per kMinhitEvery tests run
             if (since_check >= kMinhitEvery) {
                 since_check = 0;
-                const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
+                const unsigned long long mh = (unsigned long long)uniform_i64((int64_t)load_minhit(&A.minhit[e]));
                 if (mh < (unsigned long long)rank) {
                     stop = true;
                     break;
@@ -982,13 +989,23 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
             const int cnt = (int)min((int64_t)(P - tau), remaining);
             bool hit_found = false;
             int done_tests = cnt;  // tests of this a run by the wave
+            const int u0 = P - 1 - tau;  // reversed index of the first pair
+            // pairs from the table when it covers u0 (and so every u below),
+            // from tri_root otherwise
+            auto pairs = [&](auto tabled) {
             for (int it = 0; it < cnt; it += 64) {
                 const bool valid = it + lane < cnt;
-                const unsigned t = (unsigned)(tau + min(it + lane, cnt - 1));
-                const unsigned u = (unsigned)P - 1u - t;
-                const unsigned rr = tri_root(u);
-                const int b = a + 1 + (na - 2 - (int)rr);
-                const int cc = a + 1 + (na - 1 - (int)(u - (__umul24(rr, rr + 1u) >> 1)));
+                const unsigned u = (unsigned)(u0 - min(it + lane, cnt - 1));
+                int b, cc;
+                if constexpr (decltype(tabled)::value) {
+                    const unsigned d = pdec[u];
+                    b = m - 2 - (int)(d & 0xffu);
+                    cc = m - 1 - (int)(d >> 8);
+                } else {
+                    const unsigned rr = tri_root(u);
+                    b = m - 2 - (int)rr;
+                    cc = m - 1 - (int)(u - (__umul24(rr, rr + 1u) >> 1));
+                }
                 const T *eb = tab + (size_t)(b - sQ) * Lay::S;
                 const T *ec = tab + (size_t)(cc - sQ) * Lay::S;
                 T sab = tri[rowa + b], sac = tri[rowa + cc], sbc = tri[get_int(eb[QL + 3]) + cc];
@@ -1048,6 +1065,9 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                     break;
                 }
             }
+            };
+            if (u0 < A.pdec_n) pairs(std::true_type{});
+            else pairs(std::false_type{});
             executed += (uint64_t)done_tests;
             since_check += done_tests;
             if (hit_found) {
@@ -1085,11 +1105,29 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
     if (lane == 0 && executed) atomicAdd(&A.inst_cnt[2 * E.inst], (unsigned long long)executed);
 }
 
+// Pairs (b < c) of the positions after a, in reversed order: the pair of
+// reversed index u lies in row rr = tri_root(u) of the triangle, column
+// s = u - rr(rr+1)/2, which puts it at b = m-2-rr, c = m-1-s whatever a is.
+// The table holds one 16-bit entry rr | s << 8 for each u below pdec_n;
+// pdec_n <= C(256, 2) keeps rr and s below 255.  The host sizes it to the
+// LDS a workgroup can take without fewer workgroups fitting on a CU.
+constexpr int kPdecCap = 256 * 255 / 2;
+__host__ __device__ constexpr size_t pdec_bytes(int n) { return ((size_t)n * 2 + 15) / 16 * 16; }
+
 template <typename T, int QL>
 __global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    for_each_item(A, [&](int64_t blk) { triple_item<T, QL>(A, blk, smem); });
+    // the pair table is built once per launch and read by every item; the
+    // barrier at the start of each item orders these writes before the reads
+    uint16_t *pdec = reinterpret_cast<uint16_t *>(smem);
+    const unsigned np = (unsigned)A.pdec_n;
+    for (unsigned u = threadIdx.x; u < np; u += blockDim.x) {
+        const unsigned rr = tri_root(u);
+        pdec[u] = (uint16_t)(rr | ((u - (__umul24(rr, rr + 1u) >> 1)) << 8));
+    }
+    unsigned char *rest = smem + pdec_bytes(A.pdec_n);
+    for_each_item(A, [&](int64_t blk) { triple_item<T, QL>(A, blk, rest, pdec); });
 }
 
 template <typename T, int QL = 0>
@@ -1110,6 +1148,7 @@ hipError_t launch_triple(int l, int64_t ub, int cus, size_t lds_cu, size_t shm, 
     return hipErrorInvalidValue;
 }
 
+// LDS of the triple kernel without its pair table
 template <typename T>
 size_t triple_lds_bytes(int l, int m)
 {
@@ -1118,6 +1157,33 @@ size_t triple_lds_bytes(int l, int m)
     const int S = (QL + 4 + V - 1) / V * V;
     const size_t tile = ((size_t)m * (m - 1) / 2 + 2 * (size_t)m + V - 1) / V * V;
     return sizeof(T) * (tile + (size_t)kWaves * m * S);
+}
+
+template <typename T, int QL = 0>
+const void *triple_fn(int l)
+{
+    if constexpr (QL + 3 <= kMaxTemplL) {
+        if (l == QL + 3) return (const void *)triple_kernel<T, QL>;
+        return triple_fn<T, QL + 1>(l);
+    }
+    return nullptr;
+}
+
+// Entries of the pair table for a class whose other LDS is `base` bytes:
+// as many as cover its largest list, within what leaves the workgroups per
+// CU (by registers, LDS and the tuning cap) unchanged.
+int triple_table_entries(int l, bool fp32, int max_m, size_t base, size_t lds_cu, size_t lds_cap, int cap_blocks)
+{
+    const size_t full = max_m > 2 ? std::min<size_t>((size_t)(max_m - 1) * (max_m - 2) / 2, kPdecCap) : 0;
+    const void *fn = fp32 ? triple_fn<float>(l) : triple_fn<double>(l);
+    int regs = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&regs, fn, 256, 0) != hipSuccess || regs < 1) regs = 1;
+    int k0 = std::min<int>(regs, (int)(lds_cu / (base + 256)));
+    if (cap_blocks > 0) k0 = std::min(k0, cap_blocks);
+    k0 = std::max(k0, 1);
+    const size_t room = std::min<size_t>(lds_cu / (size_t)k0 - 256, lds_cap);
+    if (room <= base) return 0;
+    return (int)std::min<size_t>(full, (room - base) / 2 / 8 * 8);
 }
 
 // ------------------------------------------------------------------ wide levels
@@ -1188,7 +1254,7 @@ __device__ __forceinline__ void wide_item(const LevelArgs &A, int l, int64_t blk
     __syncthreads();
     uint64_t executed = 0;
     for (int64_t R = r0; R < r1; ++R) {
-        const unsigned long long mh = __shfl((unsigned long long)load_minhit(&A.minhit[e]), 0);
+        const unsigned long long mh = (unsigned long long)uniform_i64((int64_t)load_minhit(&A.minhit[e]));
         if (mh < (unsigned long long)R) break;  // wave-uniform
         __syncthreads();
         // gather [cand[k_0..k_{l-1}], i, j]
@@ -1580,6 +1646,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
         int max_m;
         Kind kind;
         size_t shm;
+        int pdec_n;
         int rpb;
         std::vector<int64_t> wins;
     };
@@ -1589,7 +1656,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     const int nlc = Lv.classes ? Lv.n_classes : 1;
     int max_nw = 0;
     for (int c = 0; c < nlc; ++c) {
-        Cls k{lc[c].begin, lc[c].end, lc[c].max_m, K_GLOBAL, 0, 0, {}};
+        Cls k{lc[c].begin, lc[c].end, lc[c].max_m, K_GLOBAL, 0, 0, 0, {}};
         if (k.begin < 0 || k.end > E || k.begin >= k.end) return FPC_EINVAL;
         if (wide) {
             k.kind = K_WIDE;
@@ -1600,6 +1667,11 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             if (l >= 2 && ctx->use_pair_kernel && ps <= lds_cap) {
                 k.kind = use_triple(ctx, l) ? K_TRIPLE : K_PAIR;
                 k.shm = ps;
+                if (k.kind == K_TRIPLE) {
+                    k.pdec_n = triple_table_entries(l, fp32, k.max_m, ps, (size_t)ctx->lds_per_cu, lds_cap,
+                                                    ctx->tuning.max_blocks_per_cu[lt]);
+                    k.shm += pdec_bytes(k.pdec_n);
+                }
             } else {
                 const size_t ts = tile_bytes(k.max_m, fp32 ? 4 : 8);
                 k.kind = ts <= std::min<size_t>(lds_cap, 65536) ? K_TILE : K_GLOBAL;
@@ -1696,6 +1768,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             A.win_hi = hi;
             A.ranks_per_block = k.rpb;
             A.max_m = k.max_m;
+            A.pdec_n = k.pdec_n;
             plan_reduce<<<(unsigned)nb, 256, 0, st>>>(P);
             plan_sums<<<1, 256, 0, st>>>(P, (int)nb);
             plan_scan<<<(unsigned)nb, 256, 0, st>>>(P);

@@ -830,11 +830,21 @@ size_t pair_lds_bytes(int l, int m)
 // and the pair (b, c) is then eliminated from S' as in the pair kernel.
 // The table is built once per Q (C(n,3) tests) instead of once per
 // (l-2)-prefix (C(n,2) tests).
+// Entry stride (elements) of the per-wave Schur table.  Lanes read the
+// entries of consecutive positions; a stride of an odd number of 8-byte
+// words (FP32: read as 8-byte pairs) or of 16-byte words (FP64: read as
+// double pairs) spreads such reads over all LDS banks.  Four FP32 values fit
+// one 16-byte read, which is conflict free as it is.
+__host__ __device__ constexpr int triple_stride(int nE, int elem_bytes)
+{
+    return elem_bytes == 4 && nE <= 4 ? 4 : ((nE + 1) / 2 | 1) * 2;
+}
+
 template <typename T, int QL>
 struct TripleLayout {
     static constexpr int V = 16 / (int)sizeof(T);
     static constexpr int nE = QL + 4;  // w[QL], S_xx, S_xi, S_xj, row offset of x in the packed tile
-    static constexpr int S = (nE + V - 1) / V * V;
+    static constexpr int S = triple_stride(nE, (int)sizeof(T));
 };
 
 template <typename T, int QL>
@@ -952,7 +962,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                 sxi -= w[t] * uQ[t];
                 sxj -= w[t] * vQ[t];
             }
-            T *ex = tab + (size_t)xp * Lay::S;
+            T *ex = tab + __umul24((unsigned)xp, (unsigned)Lay::S);
 #pragma unroll
             for (int t = 0; t < QL; ++t) ex[t] = w[t];
             ex[QL] = sxx;
@@ -973,7 +983,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                     break;
                 }
             }
-            const T *eaP = tab + (size_t)(a - sQ) * Lay::S;
+            const T *eaP = tab + __umul24((unsigned)(a - sQ), (unsigned)Lay::S);
             T wa[QLL];
 #pragma unroll
             for (int t = 0; t < QL; ++t) wa[t] = eaP[t];
@@ -1006,8 +1016,9 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                     b = m - 2 - (int)rr;
                     cc = m - 1 - (int)(u - (__umul24(rr, rr + 1u) >> 1));
                 }
-                const T *eb = tab + (size_t)(b - sQ) * Lay::S;
-                const T *ec = tab + (size_t)(cc - sQ) * Lay::S;
+                // LDS offsets fit 24 bits
+                const T *eb = tab + __umul24((unsigned)(b - sQ), (unsigned)Lay::S);
+                const T *ec = tab + __umul24((unsigned)(cc - sQ), (unsigned)Lay::S);
                 T sab = tri[rowa + b], sac = tri[rowa + cc], sbc = tri[get_int(eb[QL + 3]) + cc];
 #pragma unroll
                 for (int q = 0; q < QL; ++q) {
@@ -1154,7 +1165,7 @@ size_t triple_lds_bytes(int l, int m)
 {
     const int QL = l - 3;
     const int V = 16 / (int)sizeof(T);
-    const int S = (QL + 4 + V - 1) / V * V;
+    const int S = triple_stride(QL + 4, (int)sizeof(T));
     const size_t tile = ((size_t)m * (m - 1) / 2 + 2 * (size_t)m + V - 1) / V * V;
     return sizeof(T) * (tile + (size_t)kWaves * m * S);
 }

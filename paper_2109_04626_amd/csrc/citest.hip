@@ -33,6 +33,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <type_traits>
 
@@ -330,6 +331,7 @@ __device__ __forceinline__ void for_each_item(const LevelArgs &A, F &&body)
 // the LDS limit is applied here from the CU's LDS size, since the query
 // does not account for workgroups that opt into more than 64 KiB.
 thread_local int g_max_blocks_per_cu = 0;  // tuning cap of the launch being issued (0: none)
+thread_local unsigned g_last_grid = 0;      // grid of the last launch sized here (for tracing)
 
 unsigned resident_grid(const void *fn, int threads, size_t shm, int64_t ub, int cus, size_t lds_cu)
 {
@@ -338,7 +340,8 @@ unsigned resident_grid(const void *fn, int threads, size_t shm, int64_t ub, int 
         per_cu = 1;
     if (shm > 0) per_cu = std::min<int>(per_cu, std::max<int>(1, (int)(lds_cu / (shm + 256))));
     if (g_max_blocks_per_cu > 0) per_cu = std::min(per_cu, g_max_blocks_per_cu);
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ub, (int64_t)per_cu * cus));
+    g_last_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ub, (int64_t)per_cu * cus));
+    return g_last_grid;
 }
 
 __device__ __forceinline__ int64_t find_edge(const int64_t *__restrict__ off, int64_t n, int64_t b)
@@ -1812,6 +1815,10 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                 (void)hipEventRecord(ctx->lev[2 * nev + 1], st);
                 ++nev;
             }
+            if (trace_on())
+                std::fprintf(stderr, "[fpc]   l=%d window %d class %d: kind %d, lists <= %d, LDS %zu B (pair table %d), "
+                             "grid %u, items <= %lld\n", l, w, (int)(&k - cls.data()), (int)k.kind, k.max_m, k.shm,
+                             k.pdec_n, g_last_grid, (long long)ub);
             ++nlaunch;
             if (fp32) launch_recheck(l, st, A);  // the next plan empties the queue
             if (err == hipSuccess) err = hipGetLastError();

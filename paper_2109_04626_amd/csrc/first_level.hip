@@ -170,8 +170,8 @@ __global__ __launch_bounds__(256) void first_level_decide(const double *__restri
 
 }  // namespace
 
-int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out, uint8_t *indep_out,
-                int *n_singular)
+int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
+                        uint8_t *indep_out, const int **d_bad)
 {
     if (!C || p < 2 || n <= p + 1) return FPC_EINVAL;
     hipStream_t st = ctx->stream;
@@ -194,9 +194,19 @@ int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r
     }
     first_level_decide<<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(A, p, n, q, r_out, indep_out, bad);
     FPC_HIP(hipGetLastError());
+    *d_bad = bad;
+    return FPC_OK;
+}
+
+int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out, uint8_t *indep_out,
+                int *n_singular)
+{
+    const int *bad = nullptr;
+    int rc = first_level_enqueue(ctx, C, p, n, q, r_out, indep_out, &bad);
+    if (rc) return rc;
     int hbad = 0;
-    FPC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
-    FPC_HIP(hipStreamSynchronize(st));
+    FPC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    FPC_HIP(hipStreamSynchronize(ctx->stream));
     if (n_singular) *n_singular = hbad;
     return hbad ? FPC_ESINGULAR : FPC_OK;
 }

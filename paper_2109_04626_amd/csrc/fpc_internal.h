@@ -116,9 +116,16 @@ int corr_max_abs_diff(fpc_ctx *ctx, const double *c64, const float *c32, int p, 
 int gather_rows(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p, const int32_t *rows, int n,
                 void *out);
 
+// FPC_TRACE=1 in the environment: phase timings and launch shapes on stderr.
+bool trace_on();
+
 // ---- first level (first_level.hip)
 int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
                 uint8_t *indep_out, int *n_singular);
+// The same work queued on the context's stream without waiting for it;
+// *d_bad (device int) becomes nonzero if C is not positive definite.
+int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
+                        uint8_t *indep_out, const int **d_bad);
 
 // ---- level tests (citest.hip)
 // One problem instance of a level: its matrices and threshold.

@@ -97,14 +97,6 @@ int64_t binom_sat(int a, int b)
     return (int64_t)v;
 }
 
-namespace {
-
-double now_ms()
-{
-    using namespace std::chrono;
-    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
-}
-
 // FPC_TRACE=1 in the environment: phase timings of each level on stderr.
 bool trace_on()
 {
@@ -114,6 +106,15 @@ bool trace_on()
     }();
     return on;
 }
+
+namespace {
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
 
 inline int64_t pair_index(int i, int j, int p)
 {
@@ -142,18 +143,24 @@ void unrank_host(int64_t R, int m, int l, const std::vector<int64_t> &tab, std::
     }
 }
 
-// Separating sets: level and kind per pair, LIST nodes in a flat array.
+// Separating sets found by the subset levels: one entry per deleted pair
+// with its level (= set size) and the set's nodes in a flat array.  Pairs
+// deleted by the first level are not listed: in the result they are the
+// pairs absent from the graph and from this list (kind ALL_BUT).
+struct SepList {
+    int64_t pair;   // pair index (i < j, row-major upper triangle)
+    int64_t off;    // offset into nodes
+    int32_t level;  // set size
+};
 struct SepStore {
-    std::vector<int32_t> level;                        // per pair, -1 kept
-    std::vector<int8_t> kind;                          // per pair
-    std::vector<std::pair<int64_t, int64_t>> lists;    // (pair, offset into nodes)
+    std::vector<SepList> lists;
     std::vector<int32_t> nodes;
-    void reset(int64_t P)
+    bool first_level = false;  // the l = p-2 level ran (its deletions are implicit)
+    void reset()
     {
-        level.assign(P, -1);
-        kind.assign(P, FPC_SEP_NONE);
         lists.clear();
         nodes.clear();
+        first_level = false;
     }
 };
 
@@ -567,10 +574,8 @@ retry:
             const EdgeRec &er = recs[d.first];
             unrank_host(d.second, er.m, l, ctx->binom_host, pos);
             const int64_t pr = pair_index(er.i, er.j, R.p);
-            R.sep.level[pr] = l;
-            R.sep.kind[pr] = FPC_SEP_LIST;
             const size_t o = o0[k] + (size_t)(t - d_lo[k]) * l;
-            R.sep.lists[li0[k] + (size_t)(t - d_lo[k])] = {pr, (int64_t)o};
+            R.sep.lists[li0[k] + (size_t)(t - d_lo[k])] = {pr, (int64_t)o, l};
             int32_t *S = R.sep.nodes.data() + o;
             for (int q = 0; q < l; ++q) S[q] = cand[er.cand_off + pos[q]];
             std::sort(S, S + l);
@@ -641,7 +646,7 @@ void init_run(Run &R, fpc_ctx *ctx, const fpc_params *P, int p, int n)
     const size_t pp = (size_t)p * p;
     R.adj.assign(pp, 1);
     for (int i = 0; i < p; ++i) R.adj[(size_t)i * p + i] = 0;
-    R.sep.reset((int64_t)p * (p - 1) / 2);
+    R.sep.reset();
 }
 
 // Correlation matrices of the instance's data (device, n x p row-major):
@@ -685,42 +690,48 @@ int first_stage(Run &R, double *ms)
         d_r = ctx->rfirst.as<double>();
         R.Rfirst = d_r;
     }
-    if ((rc = first_level(ctx, R.C64, p, R.n, R.q, d_r, d_ind, nullptr))) return rc;
+    const int *d_bad = nullptr;
+    if ((rc = first_level_enqueue(ctx, R.C64, p, R.n, R.q, d_r, d_ind, &d_bad))) return rc;
     FPC_HIP(hipEventRecord(ctx->ev1, s));
-    if ((rc = ctx->h_back.ensure(pp))) return rc;
+    // one round trip: the decisions and the positive-definiteness flag
+    if ((rc = ctx->h_back.ensure(pp + 64))) return rc;
     const uint8_t *ind = ctx->h_back.as<uint8_t>();
+    int *h_bad = reinterpret_cast<int *>(ctx->h_back.as<uint8_t>() + (pp + 15) / 16 * 16);
     FPC_HIP(hipMemcpyAsync(ctx->h_back.ptr, d_ind, pp, hipMemcpyDeviceToHost, s));
+    FPC_HIP(hipMemcpyAsync(h_bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    const double tq = now_ms();
     FPC_HIP(hipStreamSynchronize(s));
+    const double tw = now_ms();
+    if (*h_bad) return FPC_ESINGULAR;
     float kms = 0.f;
     FPC_HIP(hipEventElapsedTime(&kms, ctx->ev0, ctx->ev1));
     st.kernel_ms = kms;
-    // deletions on host threads, each owning a block of rows: it clears its
-    // rows of adj (the decision matrix is symmetric) and records the pairs
-    // (i, j > i) of its rows, so no two threads write the same cache line
-    // except at block edges
+    // the graph after the level: adj = not independent, off the diagonal;
+    // the decision matrix is symmetric, so the deleted pairs are half its ones
     const int nblk = std::min(p, 16);
     std::vector<int64_t> dels(nblk, 0);
     parallel_for(nblk, [&](int b) {
-        const int i0 = (int)((int64_t)p * b / nblk), i1 = (int)((int64_t)p * (b + 1) / nblk);
-        for (int i = i0; i < i1; ++i) {
-            const uint8_t *irow = ind + (size_t)i * p;
-            uint8_t *arow = R.adj.data() + (size_t)i * p;
-            for (int j = 0; j < p; ++j)
-                if (j != i && irow[j]) arow[j] = 0;
-            for (int j = i + 1; j < p; ++j)
-                if (irow[j]) {
-                    const int64_t pr = pair_index(i, j, p);
-                    R.sep.level[pr] = p - 2;
-                    R.sep.kind[pr] = FPC_SEP_ALL_BUT;
-                    ++dels[b];
-                }
+        const size_t k0 = pp * (size_t)b / nblk, k1 = pp * (size_t)(b + 1) / nblk;
+        const uint8_t *__restrict__ src = ind;
+        uint8_t *__restrict__ dst = R.adj.data();
+        int64_t ones = 0;
+        for (size_t k = k0; k < k1; ++k) {
+            dst[k] = (uint8_t)(src[k] ^ 1u);
+            ones += src[k];
         }
+        dels[b] = ones;
     });
+    for (int i = 0; i < p; ++i) R.adj[(size_t)i * p + i] = 0;
+    R.sep.first_level = true;
     st.deleted = 0;
     for (int64_t d : dels) st.deleted += d;
+    st.deleted /= 2;
     R.total_exec += st.tests_executed;
     R.spent_possible += st.tests_possible;
     *ms = now_ms() - t0;
+    if (trace_on())
+        std::fprintf(stderr, "[fpc] first level: queue %.2f wait %.2f (device %.2f) marks %.2f ms\n", tq - t0, tw - tq,
+                     kms, now_ms() - tw);
     st.level_ms = *ms;
     R.levels.push_back(st);
     return FPC_OK;
@@ -753,23 +764,67 @@ int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result
         fpc_result_free(res);
         return FPC_ENOMEM;
     }
-    std::memcpy(res->adj, R.adj.data(), pp);
-    // LIST sets in pair order; each pair is deleted at most once
-    std::sort(R.sep.lists.begin(), R.sep.lists.end());
-    std::memcpy(res->sep_level, R.sep.level.data(), sizeof(int32_t) * PP);
-    std::memcpy(res->sep_kind, R.sep.kind.data(), PP);
-    int64_t o = 0;
-    size_t li = 0;
-    for (int64_t k = 0; k < PP; ++k) {
-        res->sep_off[k] = o;
-        if (li < R.sep.lists.size() && R.sep.lists[li].first == k) {
-            const int L = R.sep.level[k];
-            std::memcpy(res->sep_nodes + o, R.sep.nodes.data() + R.sep.lists[li].second, sizeof(int32_t) * L);
-            o += L;
-            ++li;
+    // per pair: the subset level's set, else the first level's deletion
+    // (absent from the graph), else kept; row blocks on the host threads,
+    // each writing its pairs' entries and its share of the set nodes
+    std::sort(R.sep.lists.begin(), R.sep.lists.end(),
+              [](const SepList &a, const SepList &b) { return a.pair < b.pair; });
+    const int nblk = std::max(1, std::min(p, 16));
+    std::vector<int> row0(nblk + 1, p);  // rows of block b: [row0[b], row0[b+1]), about PP / nblk pairs each
+    {
+        int64_t acc = 0;
+        int b = 0;
+        row0[0] = 0;
+        for (int i = 0; i < p && b + 1 < nblk; ++i) {
+            acc += p - 1 - i;
+            if (acc * nblk >= PP * (b + 1)) row0[++b] = i + 1;
         }
+        for (++b; b < nblk; ++b) row0[b] = p;
     }
-    res->sep_off[PP] = o;
+    auto first_pair = [&](int i) { return i < p - 1 ? pair_index(i, i + 1, p) : PP; };  // first pair of row i on
+    std::vector<size_t> li_lo(nblk + 1);
+    std::vector<int64_t> node_lo(nblk + 1, 0);
+    for (int b = 0; b <= nblk; ++b) {
+        const int64_t pr0 = b < nblk ? first_pair(row0[b]) : PP;
+        li_lo[b] = (size_t)(std::lower_bound(R.sep.lists.begin(), R.sep.lists.end(), pr0,
+                                             [](const SepList &a, int64_t v) { return a.pair < v; }) -
+                            R.sep.lists.begin());
+    }
+    for (int b = 0; b < nblk; ++b) {
+        int64_t nn = 0;
+        for (size_t t = li_lo[b]; t < li_lo[b + 1]; ++t) nn += R.sep.lists[t].level;
+        node_lo[b + 1] = node_lo[b] + nn;
+    }
+    const bool implicit_first = R.sep.first_level;
+    const int first_l = p - 2;
+    parallel_for(nblk, [&](int b) {
+        std::memcpy(res->adj + (size_t)row0[b] * p, R.adj.data() + (size_t)row0[b] * p,
+                    (size_t)(row0[b + 1] - row0[b]) * p);
+        size_t li = li_lo[b];
+        int64_t o = node_lo[b];
+        for (int i = row0[b]; i < row0[b + 1]; ++i) {
+            const uint8_t *arow = R.adj.data() + (size_t)i * p;
+            const int64_t base = first_pair(i) - (i + 1);  // pair (i, j) at base + j
+            for (int j = i + 1; j < p; ++j) {
+                const int64_t k = base + j;
+                res->sep_off[k] = o;
+                if (li < li_lo[b + 1] && R.sep.lists[li].pair == k) {
+                    const SepList &e = R.sep.lists[li++];
+                    res->sep_level[k] = e.level;
+                    res->sep_kind[k] = FPC_SEP_LIST;
+                    std::memcpy(res->sep_nodes + o, R.sep.nodes.data() + e.off, sizeof(int32_t) * e.level);
+                    o += e.level;
+                } else if (!arow[j] && implicit_first) {
+                    res->sep_level[k] = first_l;
+                    res->sep_kind[k] = FPC_SEP_ALL_BUT;
+                } else {
+                    res->sep_level[k] = -1;
+                    res->sep_kind[k] = FPC_SEP_NONE;
+                }
+            }
+        }
+    });
+    res->sep_off[PP] = node_lo[nblk];
     std::memcpy(res->levels, R.levels.data(), sizeof(fpc_level_stats) * R.levels.size());
     res->total_tests = R.total_exec;
     res->q = R.q;

@@ -178,8 +178,8 @@ def fpc_last_hip_error() -> str:
 
 
 def fpc_result_free(res) -> None:
-    """Results are copied into Python objects and freed by fpc_skeleton;
-    this accepts a raw POINTER(fpc_result) for completeness."""
+    """Result dicts free their C buffers themselves once no array taken from
+    them is left; this accepts a raw POINTER(fpc_result) for completeness."""
     if res:
         _lib.fpc_result_free(res)
 
@@ -436,10 +436,7 @@ def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, prec
     prm.flags = int(flags)
     res = ctypes.POINTER(fpc_result)()
     _check(_lib.fpc_skeleton(ctx.handle, ctypes.byref(prm), ctypes.byref(res)), "fpc_skeleton")
-    try:
-        return _unpack(res.contents)
-    finally:
-        _lib.fpc_result_free(res)
+    return _unpack(res)
 
 
 def fpc_skeleton_batch(ctx: Context, instances, alpha: float = 0.01, max_level: int = -1,
@@ -487,14 +484,8 @@ def fpc_skeleton_batch(ctx: Context, instances, alpha: float = 0.01, max_level: 
     prm.flags = int(flags)
     outs = (ctypes.POINTER(fpc_result) * max(len(instances), 1))()
     _check(_lib.fpc_skeleton_batch(ctx.handle, ctypes.byref(prm), len(instances), arr, outs), "fpc_skeleton_batch")
-    res = []
-    try:
-        for k in range(len(instances)):
-            res.append(_unpack(outs[k].contents))
-    finally:
-        for k in range(len(instances)):
-            _lib.fpc_result_free(outs[k])
-    return res
+    owners = [_Owner(ctypes.cast(outs[k], ctypes.POINTER(fpc_result))) for k in range(len(instances))]
+    return [_unpack(o.ptr, o) for o in owners]
 
 
 class SepSets(Mapping):
@@ -544,14 +535,45 @@ class _Result(dict):
         return off
 
 
-def _unpack(r: fpc_result) -> dict:
+class _Owner:
+    """Holds one fpc_result and frees it once no array viewing its buffers
+    is left (the arrays keep their owner alive)."""
+
+    __slots__ = ("ptr",)
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        lib = _lib
+        if lib is not None and self.ptr:
+            lib.fpc_result_free(self.ptr)
+            self.ptr = None
+
+
+def _view(field, ctype, dtype, n: int, owner: _Owner) -> np.ndarray:
+    """numpy view of n elements of a result buffer, without a copy."""
+    addr = ctypes.cast(field, ctypes.c_void_p).value
+    if n <= 0 or not addr:
+        return np.zeros(0, dtype)
+    buf = (ctype * n).from_address(addr)
+    buf._owner = owner
+    return np.frombuffer(buf, dtype=dtype)
+
+
+def _unpack(res, owner: _Owner | None = None) -> dict:
+    """Result dict over the buffers of a POINTER(fpc_result); the buffers
+    are freed when the last array taken from them is."""
+    if owner is None:
+        owner = _Owner(res)
+    r = res.contents
     p = r.p
     P = p * (p - 1) // 2
-    adj = np.ctypeslib.as_array(r.adj, shape=(p * p,)).reshape(p, p).copy()
-    lev = np.ctypeslib.as_array(r.sep_level, shape=(P,)).copy() if P else np.zeros(0, np.int32)
-    kind = np.ctypeslib.as_array(r.sep_kind, shape=(P,)).copy() if P else np.zeros(0, np.int8)
+    adj = _view(r.adj, ctypes.c_uint8, np.uint8, p * p, owner).reshape(p, p)
+    lev = _view(r.sep_level, ctypes.c_int32, np.int32, P, owner)
+    kind = _view(r.sep_kind, ctypes.c_int8, np.int8, P, owner)
     tot = int(r.sep_off[P])
-    nodes = np.ctypeslib.as_array(r.sep_nodes, shape=(max(tot, 1),))[:tot].copy()
+    nodes = _view(r.sep_nodes, ctypes.c_int32, np.int32, tot, owner)
     idx = np.flatnonzero(kind == FPC_SEP_LIST)
     off = np.zeros(len(idx) + 1, np.int64)
     np.cumsum(lev[idx], out=off[1:])
@@ -563,10 +585,10 @@ def _unpack(r: fpc_result) -> dict:
     nlog = int(r.log_rows)
     log = None
     if nlog:
-        log = dict(x=np.ctypeslib.as_array(r.log_x, shape=(nlog * 3,)).reshape(nlog, 3).copy(),
-                   y=np.ctypeslib.as_array(r.log_y, shape=(nlog,)).copy(),
-                   group=np.ctypeslib.as_array(r.log_group, shape=(nlog,)).copy(),
-                   level=np.ctypeslib.as_array(r.log_level, shape=(nlog,)).copy())
+        log = dict(x=_view(r.log_x, ctypes.c_float, np.float32, nlog * 3, owner).reshape(nlog, 3),
+                   y=_view(r.log_y, ctypes.c_uint8, np.uint8, nlog, owner),
+                   group=_view(r.log_group, ctypes.c_int32, np.int32, nlog, owner),
+                   level=_view(r.log_level, ctypes.c_int32, np.int32, nlog, owner))
     return _Result(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets, sep_nodes=nodes,
                    levels=levels, log=log,
                    total_tests=int(r.total_tests), total_required=sum(x["tests_required"] for x in levels),

@@ -1712,7 +1712,8 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     int rc = ctx->insts.ensure(sizeof(InstRec) * (size_t)ni);
     if (rc) return rc;
     if ((rc = ctx->h_inst.ensure(sizeof(InstRec) * (size_t)ni))) return rc;
-    FPC_HIP(hipStreamSynchronize(st));  // the previous upload from h_inst has completed
+    // h_inst is free: the previous level's upload from it completed before
+    // the stream synchronisation that ends every level
     InstRec *hin = ctx->h_inst.as<InstRec>();
     for (int k = 0; k < ni; ++k) {
         const LevelInst &I = Lv.insts[k];
@@ -1837,35 +1838,38 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     }
     FPC_HIP(err);
     FPC_HIP(hipEventRecord(ctx->ev1, st));
+    timing->test_launches = nlaunch;
+    timing->n_events = nev;
+    timing->graph = graph;
+    return FPC_OK;
+}
+
+int level_timing(fpc_ctx *ctx, LevelTiming *timing)
+{
     FPC_HIP(hipEventSynchronize(ctx->ev1));
     FPC_HIP(hipEventElapsedTime(&timing->all_ms, ctx->ev0, ctx->ev1));
-    for (int k = 0; k < nev; ++k) {
+    timing->test_ms = 0.f;
+    for (int k = 0; k < timing->n_events; ++k) {
         float ms = 0.f;
         FPC_HIP(hipEventElapsedTime(&ms, ctx->lev[2 * k], ctx->lev[2 * k + 1]));
         timing->test_ms += ms;
     }
-    if (graph) timing->test_ms = timing->all_ms;  // one graph: plans and rechecks included
-    timing->test_launches = nlaunch;
+    if (timing->graph) timing->test_ms = timing->all_ms;  // one graph: plans and rechecks included
     return FPC_OK;
 }
 
-int level_compact(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *out_pairs, int64_t *n_out)
+int level_compact_enqueue(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *h)
 {
     hipStream_t st = ctx->stream;
     int rc = ctx->dellist.ensure(sizeof(int64_t) * (2 * (size_t)n_edges + 2));
     if (rc) return rc;
     int64_t *d = ctx->dellist.as<int64_t>();
-    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(d + 2 * n_edges);
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(d);
     FPC_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), st));
     if (n_edges > 0)
-        compact_kernel<<<(unsigned)((n_edges + 255) / 256), 256, 0, st>>>(minhit, n_edges, d, cnt);
+        compact_kernel<<<(unsigned)((n_edges + 255) / 256), 256, 0, st>>>(minhit, n_edges, d + 2, cnt);
     FPC_HIP(hipGetLastError());
-    unsigned long long h = 0;
-    FPC_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
-    FPC_HIP(hipStreamSynchronize(st));
-    if (h) FPC_HIP(hipMemcpyAsync(out_pairs, d, sizeof(int64_t) * 2 * h, hipMemcpyDeviceToHost, st));
-    FPC_HIP(hipStreamSynchronize(st));
-    *n_out = (int64_t)h;
+    FPC_HIP(hipMemcpyAsync(h, d, sizeof(int64_t) * (2 * (size_t)n_edges + 2), hipMemcpyDeviceToHost, st));
     return FPC_OK;
 }
 

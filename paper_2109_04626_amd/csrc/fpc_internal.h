@@ -164,15 +164,23 @@ struct LevelTiming {
     float all_ms = 0.f;       // first test launch to last recheck, one event pair
     float test_ms = 0.f;      // sum of the test-kernel launches alone
     int test_launches = 0;
+    int n_events = 0;         // timed launches (event pairs)
+    bool graph = false;       // the level ran as one captured graph
 };
 // Size class of an edge with m candidates at level l: edges of one class
 // share a kernel and the number of workgroups that fit on a CU.
 int level_class_key(const fpc_ctx *ctx, int l, bool fp32, int m);
 void tuning_defaults(fpc_tuning *t);
+// Queues a level's tests on the context's stream (no wait); callers
+// synchronise the stream before the next level and before level_timing.
 int level_tests(fpc_ctx *ctx, const LevelLaunch &L, const std::vector<int64_t> &host_ntests,
                 LevelTiming *timing);
-int level_compact(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *out_pairs,
-                  int64_t *n_out);
+// Reads the timings of the last level_tests once its work has completed.
+int level_timing(fpc_ctx *ctx, LevelTiming *timing);
+// Queues the compaction of the level's hits and its copy into host memory
+// h (pinned, 2 * n_edges + 2 int64): after a stream synchronisation h[0]
+// is the number of deletions and h[2 + 2t], h[3 + 2t] the t-th (edge, rank).
+int level_compact_enqueue(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *h);
 int ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, const int32_t *B,
              int64_t b, double q, double *z_out, uint8_t *indep_out);
 

@@ -32,23 +32,28 @@ void build_adjacency(const uint8_t *adj, int p, Adjacency &g)
     for (int u = 0; u < p; ++u) {
         const uint8_t *row = adj + (size_t)u * p;
         int v = u + 1;
-        while (v < p) {
-            if (v + 8 <= p) {  // skip eight absent entries at a time
-                uint64_t word;
-                std::memcpy(&word, row + v, 8);
-                if (!word) {
-                    v += 8;
-                    continue;
-                }
+        // eight entries at a time: nz has the top bit of every nonzero byte
+        constexpr uint64_t lo7 = 0x7f7f7f7f7f7f7f7full;
+        for (; v + 8 <= p; v += 8) {
+            uint64_t word;
+            std::memcpy(&word, row + v, 8);
+            uint64_t nz = (((word & lo7) + lo7) | word) & ~lo7;
+            while (nz) {
+                const int w = v + (__builtin_ctzll(nz) >> 3);
+                g.eu.push_back(u);
+                g.ev.push_back(w);
+                ++deg[u];
+                ++deg[w];
+                nz &= nz - 1;
             }
+        }
+        for (; v < p; ++v)
             if (row[v]) {
                 g.eu.push_back(u);
                 g.ev.push_back(v);
                 ++deg[u];
                 ++deg[v];
             }
-            ++v;
-        }
     }
     g.off.assign(p + 1, 0);
     for (int u = 0; u < p; ++u) g.off[u + 1] = g.off[u] + deg[u];
@@ -181,19 +186,20 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
             merge_range(bounds[t], bounds[t + 1], parts[t], lens[t]);
         });
     }
-    size_t total = 0;
-    for (const auto &v : parts) total += v.size();
-    out.nodes.resize(total);
-    size_t o = 0;
+    std::vector<size_t> at(nth + 1, 0);
+    for (int t = 0; t < nth; ++t) at[t + 1] = at[t] + parts[t].size();
+    out.nodes.resize(at[nth]);
     int e = 0;
-    for (int t = 0; t < nth; ++t) {
-        std::memcpy(out.nodes.data() + o, parts[t].data(), sizeof(int32_t) * parts[t].size());
+    for (int t = 0; t < nth; ++t)
         for (int64_t L : lens[t]) {
             out.off[e + 1] = out.off[e] + L;
             ++e;
         }
-        o += parts[t].size();
-    }
+    auto copy_part = [&](int t) {
+        std::memcpy(out.nodes.data() + at[t], parts[t].data(), sizeof(int32_t) * parts[t].size());
+    };
+    if (nth == 1) copy_part(0);
+    else host_parallel(nth, copy_part);
 }
 
 }  // namespace fpc

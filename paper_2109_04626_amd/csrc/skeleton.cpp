@@ -482,15 +482,20 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     }
     bool fp32 = R0.mixed && l <= kMaxTemplL;
     if (fp32 && (rc = ctx->queue.ensure(sizeof(int64_t) * 2 * kQueueCap))) return rc;
-    std::vector<unsigned long long> cnt(8 + 2 * (size_t)ni);
+    const size_t n_cnt = 8 + 2 * (size_t)ni;
+    // pinned landing area of the level's results: deletions, then counters
+    if ((rc = ctx->h_back.ensure(sizeof(int64_t) * (2 * (size_t)E + 2) + sizeof(unsigned long long) * n_cnt)))
+        return rc;
+    int64_t *h_del = ctx->h_back.as<int64_t>();
+    const unsigned long long *cnt = reinterpret_cast<const unsigned long long *>(h_del + 2 * E + 2);
     LevelLaunch Lv{};
     LevelTiming tm;
-    std::vector<int64_t> pairs(2 * E);
+    const int64_t *pairs = h_del + 2;
     int64_t ndel = 0;
     double t_tests0 = 0.0, t_tests1 = 0.0;
 retry:
     FPC_HIP(hipMemsetAsync(ctx->minhit.ptr, 0xff, sizeof(uint64_t) * E, s));
-    FPC_HIP(hipMemsetAsync(ctx->counters.ptr, 0, sizeof(unsigned long long) * cnt.size(), s));
+    FPC_HIP(hipMemsetAsync(ctx->counters.ptr, 0, sizeof(unsigned long long) * n_cnt, s));
     Lv.l = l;
     Lv.max_m = sel_max_m;
     Lv.n_edges = E;
@@ -510,15 +515,17 @@ retry:
     Lv.queue_cap = fp32 ? kQueueCap : 0;
     t_tests0 = now_ms();
     if ((rc = level_tests(ctx, Lv, ntests, &tm))) return rc;
-    t_tests1 = now_ms();
     // the host decodes separating sets against the lists the level used
     // (the uploads that read the staging buffer precede this copy on the stream)
     if (reorder && T)
         FPC_HIP(hipMemcpyAsync(cand, d_cand, sizeof(int32_t) * T, hipMemcpyDeviceToHost, s));
-    if ((rc = level_compact(ctx, Lv.minhit, E, pairs.data(), &ndel))) return rc;
-    FPC_HIP(hipMemcpyAsync(cnt.data(), Lv.counters, sizeof(unsigned long long) * cnt.size(),
+    if ((rc = level_compact_enqueue(ctx, Lv.minhit, E, h_del))) return rc;
+    FPC_HIP(hipMemcpyAsync(const_cast<unsigned long long *>(cnt), Lv.counters, sizeof(unsigned long long) * n_cnt,
                            hipMemcpyDeviceToHost, s));
-    FPC_HIP(hipStreamSynchronize(s));
+    FPC_HIP(hipStreamSynchronize(s));  // the one wait of the level
+    t_tests1 = now_ms();
+    if ((rc = level_timing(ctx, &tm))) return rc;
+    ndel = h_del[0];
     for (int k = 0; k < ni; ++k) {
         sts[k].tests_executed += (int64_t)cnt[8 + 2 * k];
         sts[k].tests_rechecked += (int64_t)cnt[8 + 2 * k + 1];
@@ -605,7 +612,7 @@ retry:
     if (trace_on())
         std::fprintf(stderr,
                      "[fpc] level %d: %d instance(s) %lld edges %lld candidates %d classes | setup %.2f upload+order "
-                     "%.2f tests %.2f (device %.2f) compact %.2f decode %.2f ms | deleted %lld\n",
+                     "%.2f tests and compaction %.2f (device %.2f) counts %.2f decode %.2f ms | deleted %lld\n",
                      l, ni, (long long)E, (long long)T, (int)classes.size(), t_build - t0, t_tests0 - t_build,
                      t_tests1 - t_tests0, tm.all_ms, t_decode - t_tests1, now_ms() - t_decode, (long long)ndel);
     for (auto &st : sts) {

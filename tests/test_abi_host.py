@@ -68,6 +68,20 @@ def test_candidate_sets_match_oracle_bfs(p, dens):
             assert got == oracle.candidates(adj, int(ei[e]), int(ej[e])), (e, ei[e], ej[e])
 
 
+def test_candidate_sets_take_any_nonzero_entry_as_an_edge():
+    import paper_2109_04626_amd as fpc
+
+    rng = np.random.default_rng(7)
+    p = 37  # rows of eight entries plus a ragged tail
+    adj = _random_graph(rng, p, 0.2)
+    w = np.triu(rng.choice(np.array([1, 2, 3, 128, 255], np.uint8), size=(p, p)), 1)
+    heavy = (adj * (w + w.T)).astype(np.uint8)
+    ref = fpc.fpc_candidates(adj)
+    got = fpc.fpc_candidates(heavy)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
 def test_candidate_sets_on_complete_and_empty_graphs():
     import paper_2109_04626_amd as fpc
 

@@ -13,6 +13,11 @@
 //     A[K,K]  = A[K,K]^{-1}
 // After the last panel A = C^{-1}.  A non-positive pivot inside a panel
 // inverse reports the matrix as not positive definite.
+//
+// One launch per panel: the sweep reads the matrix before the panel and
+// writes a second buffer (the two alternate), so each kNB x kNB tile can
+// form its own slice of U and read its slice of V; the tile that becomes
+// the next panel's diagonal block inverts it in the same launch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -23,119 +28,155 @@ namespace fpc {
 
 namespace {
 
-constexpr int kNB = 32;
-constexpr int kUT = 32;  // update tile
+constexpr int kNB = 32;  // panel width and tile size
 
-// Invert the nb x nb diagonal block at k0 in LDS (Gauss-Jordan, no pivoting).
-__global__ __launch_bounds__(1024) void panel_inverse(const double *__restrict__ A, int p, int k0, int nb,
-                                                      double *__restrict__ Pinv, int *__restrict__ bad)
+// Gauss-Jordan inverse of the nb x nb block P (LDS, kNB x kNB tile) by a
+// 256-thread block, thread (ty, tx) owning rows ty + 8q of column tx.  The
+// next pivot row and column are published into a second buffer by the
+// threads that compute them, so each step needs one barrier.  Writes the
+// whole kNB x kNB result (zero outside nb) to Pinv.
+__device__ void tile_inverse(double (*P)[kNB + 1], double (*rowk)[kNB], double (*colk)[kNB], int nb,
+                             double *__restrict__ Pinv, int *__restrict__ bad)
 {
-    __shared__ double P[kNB][kNB + 1];
-    __shared__ double rowk[kNB], colk[kNB];
-    const int r = threadIdx.x / kNB, c = threadIdx.x % kNB;
-    if (r < nb && c < nb) P[r][c] = A[(size_t)(k0 + r) * p + k0 + c];
+    const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = P[ty + 8 * q][tx];
+    // step 0's pivot row and column
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q;
+        if (r == 0) rowk[0][tx] = v[q];
+        if (tx == 0) colk[0][r] = v[q];
+    }
     __syncthreads();
+    bool ok = true;
     for (int t = 0; t < nb; ++t) {
-        const double piv = P[t][t];
-        if (!(piv > 0.0)) {
-            if (threadIdx.x == 0) atomicOr(bad, 1);
-            return;  // uniform: every thread read the same pivot
-        }
-        if (r == 0 && c < nb) {
-            rowk[c] = P[t][c];
-            colk[c] = P[c][t];
-        }
-        __syncthreads();
+        // every LDS read of the step first, then select-only updates: one
+        // read latency and one barrier per step
+        const int b = t & 1;
+        const double piv = rowk[b][t], rt = rowk[b][tx];
+        double ct[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ct[q] = colk[b][ty + 8 * q];
+        ok = ok && piv > 0.0;
         const double ip = 1.0 / piv;
-        if (r < nb && c < nb) {
-            double v;
-            if (r == t && c == t) v = ip;
-            else if (r == t) v = rowk[c] * ip;
-            else if (c == t) v = -colk[r] * ip;
-            else v = P[r][c] - colk[r] * rowk[c] * ip;
-            P[r][c] = v;
+        const double rti = rt * ip;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ty + 8 * q, c = tx;
+            double nv = fma(-ct[q], rti, v[q]);  // r != t, c != t
+            nv = c == t ? -ct[q] * ip : nv;
+            nv = r == t ? rti : nv;
+            nv = (r == t && c == t) ? ip : nv;
+            v[q] = (r < nb && c < nb) ? nv : v[q];
+            if (r == t + 1) rowk[b ^ 1][c] = v[q];
+            if (c == t + 1) colk[b ^ 1][r] = v[q];
         }
         __syncthreads();
     }
-    // the whole kNB x kNB block, zero outside nb, so later passes may run
-    // over kNB terms
-    Pinv[r * kNB + c] = (r < nb && c < nb) ? P[r][c] : 0.0;
-}
-
-// U = Pinv A[K,:] (nb x p): a block takes 64 columns (lanes, coalesced
-// rows of A) and kNB/4 panel rows (blockIdx.y); the panel column of A sits
-// in registers.
-__global__ __launch_bounds__(256) void panel_u(const double *__restrict__ A, int p, int k0, int nb,
-                                               const double *__restrict__ Pinv, double *__restrict__ U)
-{
-    const int j = blockIdx.x * 64 + threadIdx.x % 64;
-    if (j >= p) return;
-    double a[kNB];
+    if (!ok && threadIdx.x == 0) atomicOr(bad, 1);
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) a[c] = c < nb ? A[(size_t)(k0 + c) * p + j] : 0.0;
-    const int r0 = blockIdx.y * (kNB / 4);
-    for (int r = r0 + threadIdx.x / 64; r < r0 + kNB / 4 && r < nb; r += 4) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < kNB; ++c) s = fma(Pinv[r * kNB + c], a[c], s);
-        U[(size_t)r * p + j] = s;
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q;
+        Pinv[r * kNB + tx] = (r < nb && tx < nb) ? v[q] : 0.0;
     }
 }
 
-// V = A[:,K] (p x kNB, row stride kNB): 8 rows per block, the panel
-// columns along the low 5 bits of the thread index (coalesced).
-__global__ __launch_bounds__(256) void panel_v(const double *__restrict__ A, int p, int k0, int nb,
-                                               double *__restrict__ V)
-{
-    const int j = blockIdx.x * 8 + threadIdx.x / 32, r = threadIdx.x % 32;
-    if (j < p && r < nb) V[(size_t)j * kNB + r] = A[(size_t)j * p + k0 + r];
-}
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-// The sweep update over kUT x kUT tiles of A; lanes along the columns j
-// (coalesced), each thread four rows.
-__global__ __launch_bounds__(256) void sweep_update(double *__restrict__ A, int p, int k0, int nb,
-                                                    const double *__restrict__ V, const double *__restrict__ U,
-                                                    const double *__restrict__ Pinv)
+// One panel of the sweep over kNB x kNB tiles, from Ain to Aout.  The block
+// of tile (I, J) stages Pinv = A[K,K]^{-1}, A[K,J] and V = A[I,K] in LDS,
+// forms U[:,J] = Pinv A[K,J] and writes its tile of the updated matrix.
+// The products run on the FP64 matrix cores: each wave owns a 16 x 16
+// quarter, v_mfma_f64_16x16x4f64 with lane l feeding A[l%16][l/16] and
+// B[l/16][l%16] and holding D[4v + l/16][l%16] in accumulator v.  The tile
+// at (next_k0, next_k0), if any, then inverts its new values into
+// Pinv_next.
+__global__ __launch_bounds__(256) void sweep_panel(const double *__restrict__ Ain, double *__restrict__ Aout, int p,
+                                                   int k0, int nb, const double *__restrict__ Pinv,
+                                                   int next_k0, int next_nb, double *__restrict__ Pinv_next,
+                                                   int *__restrict__ bad)
 {
-    __shared__ double Vs[kUT][kNB + 1];
-    __shared__ double Us[kNB][kUT + 1];
-    const int i0 = blockIdx.y * kUT, j0 = blockIdx.x * kUT;
-    for (int e = threadIdx.x; e < kUT * kNB; e += 256) {
-        const int r = e / kNB, c = e % kNB, i = i0 + r;
-        Vs[r][c] = (i < p && c < nb) ? V[(size_t)i * kNB + c] : 0.0;
-    }
-    for (int e = threadIdx.x; e < kNB * kUT; e += 256) {
-        const int r = e / kUT, c = e % kUT, j = j0 + c;
-        Us[r][c] = (j < p && r < nb) ? U[(size_t)r * p + j] : 0.0;
+    __shared__ double Ps[kNB][kNB + 1];
+    __shared__ double Us[kNB][kNB + 1];
+    __shared__ double Vs[kNB][kNB + 1];
+    __shared__ double rowk[2][kNB], colk[2][kNB];
+    const int i0 = blockIdx.y * kNB, j0 = blockIdx.x * kNB;
+    const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;  // 32 x 8
+    const int j = j0 + tx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q, i = i0 + r;
+        Ps[r][tx] = Pinv[r * kNB + tx];  // zero outside nb
+        Us[r][tx] = (r < nb && j < p) ? Ain[(size_t)(k0 + r) * p + j] : 0.0;
+        Vs[r][tx] = (i < p && tx < nb) ? Ain[(size_t)i * p + k0 + tx] : 0.0;
     }
     __syncthreads();
-    const int tx = threadIdx.x % kUT, ty = threadIdx.x / kUT;  // 32 x 8
-    const int j = j0 + tx;
-    if (j >= p) return;  // no barrier follows
-    const bool inK_j = j >= k0 && j < k0 + nb;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int qr = (wave / 2) * 16, qc = (wave % 2) * 16;  // the wave's quarter
+    const int ar = qr + lane % 16, bc = qc + lane % 16, kq = lane / 16;
+    const bool rowK = i0 == k0, colK = j0 == k0;  // tile row / column of the panel (uniform)
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    if (rowK && colK) {  // A[K,K] <- Pinv
 #pragma unroll
-    for (int q = 0; q < kUT / 8; ++q) {
-        const int ri = ty + 8 * q, i = i0 + ri;
-        if (i >= p) break;
-        const bool inK_i = i >= k0 && i < k0 + nb;
-        double v;
-        if (inK_i && inK_j) {
-            v = Pinv[(i - k0) * kNB + (j - k0)];
-        } else if (inK_i) {
-            v = Us[i - k0][tx];
-        } else if (inK_j) {
-            double acc = 0.0;
+        for (int v = 0; v < 4; ++v) acc[v] = Ps[qr + 4 * v + kq][bc];
+    } else if (colK) {  // A[I,K] <- -V Pinv
 #pragma unroll
-            for (int c = 0; c < kNB; ++c) acc = fma(Vs[ri][c], Pinv[c * kNB + (j - k0)], acc);
-            v = -acc;
-        } else {
-            double acc = A[(size_t)i * p + j];
+        for (int s4 = 0; s4 < kNB; s4 += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Vs[ar][s4 + kq], Ps[s4 + kq][bc], acc, 0, 0, 0);
+    } else {
+        // U quarter = Pinv[qr.., :] A[K, qc..]
+        v4d u = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < kNB; ++c) acc = fma(-Vs[ri][c], Us[c][tx], acc);
-            v = acc;
+        for (int s4 = 0; s4 < kNB; s4 += 4)
+            u = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[ar][s4 + kq], Us[s4 + kq][bc], u, 0, 0, 0);
+        if (rowK) {  // A[K,J] <- U
+            acc = u;
+        } else {  // A[I,J] <- A[I,J] - V U
+            __syncthreads();  // every read of A[K,J] is done (uniform branch)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Us[qr + 4 * v + kq][bc] = u[v];
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + qr + 4 * v + kq, jj = j0 + bc;
+                acc[v] = (i < p && jj < p) ? Ain[(size_t)i * p + jj] : 0.0;
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < kNB; s4 += 4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Vs[ar][s4 + kq], Us[s4 + kq][bc], acc, 0, 0, 0);
         }
-        A[(size_t)i * p + j] = v;
     }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = i0 + qr + 4 * v + kq, jj = j0 + bc;
+        if (i < p && jj < p) Aout[(size_t)i * p + jj] = acc[v];
+    }
+    if (next_nb > 0 && i0 == next_k0 && j0 == next_k0) {  // uniform over the block
+        __syncthreads();  // Ps is free again
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            Ps[qr + 4 * v + kq][bc] = (i0 + qr + 4 * v + kq < p && j0 + bc < p) ? acc[v] : 0.0;
+        __syncthreads();
+        tile_inverse(Ps, rowk, colk, next_nb, Pinv_next, bad);
+    }
+}
+
+// Inverse of the first panel's diagonal block.
+__global__ __launch_bounds__(256) void first_tile_inverse(const double *__restrict__ A, int p, int nb,
+                                                          double *__restrict__ Pinv, int *__restrict__ bad)
+{
+    __shared__ double Ps[kNB][kNB + 1];
+    __shared__ double rowk[2][kNB], colk[2][kNB];
+    const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q;
+        Ps[r][tx] = (r < nb && tx < nb) ? A[(size_t)r * p + tx] : 0.0;
+    }
+    __syncthreads();
+    tile_inverse(Ps, rowk, colk, nb, Pinv, bad);
 }
 
 // r_ij = -Omega_ij / sqrt(Omega_ii Omega_jj) (symmetrised), z, decision.
@@ -176,23 +217,27 @@ int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, d
     if (!C || p < 2 || n <= p + 1) return FPC_EINVAL;
     hipStream_t st = ctx->stream;
     const size_t pp = (size_t)p * p;
-    // work: A (p*p), V (p*kNB), U (kNB*p), Pinv (kNB*kNB)
-    int rc = ctx->inv_work.ensure(sizeof(double) * (pp + 2 * (size_t)p * kNB + kNB * kNB));
+    // work: two p x p buffers (the sweep reads one and writes the other)
+    // and two kNB x kNB panel inverses
+    int rc = ctx->inv_work.ensure(sizeof(double) * (2 * pp + 2 * kNB * kNB));
     if (rc) return rc;
     if ((rc = ctx->flag.ensure(64))) return rc;
-    double *A = ctx->inv_work.as<double>(), *V = A + pp, *U = V + (size_t)p * kNB, *Pinv = U + (size_t)kNB * p;
+    double *buf[2] = {ctx->inv_work.as<double>(), ctx->inv_work.as<double>() + pp};
+    double *pinv[2] = {buf[1] + pp, buf[1] + pp + kNB * kNB};
     int *bad = ctx->flag.as<int>() + 4;
     FPC_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
-    FPC_HIP(hipMemcpyAsync(A, C, sizeof(double) * pp, hipMemcpyDeviceToDevice, st));
-    const int nbt = (p + kUT - 1) / kUT;
-    for (int k0 = 0; k0 < p; k0 += kNB) {
+    const int nbt = (p + kNB - 1) / kNB;
+    first_tile_inverse<<<1, 256, 0, st>>>(C, p, p < kNB ? p : kNB, pinv[0], bad);
+    const double *Ain = C;
+    int t = 0;
+    for (int k0 = 0; k0 < p; k0 += kNB, ++t) {
         const int nb = p - k0 < kNB ? p - k0 : kNB;
-        panel_inverse<<<1, 1024, 0, st>>>(A, p, k0, nb, Pinv, bad);
-        panel_u<<<dim3((p + 63) / 64, 4), 256, 0, st>>>(A, p, k0, nb, Pinv, U);
-        panel_v<<<(p + 7) / 8, 256, 0, st>>>(A, p, k0, nb, V);
-        sweep_update<<<dim3(nbt, nbt), 256, 0, st>>>(A, p, k0, nb, V, U, Pinv);
+        const int nk = k0 + kNB, nnb = nk < p ? (p - nk < kNB ? p - nk : kNB) : 0;
+        sweep_panel<<<dim3(nbt, nbt), 256, 0, st>>>(Ain, buf[t & 1], p, k0, nb, pinv[t & 1], nk, nnb,
+                                                     pinv[(t + 1) & 1], bad);
+        Ain = buf[t & 1];
     }
-    first_level_decide<<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(A, p, n, q, r_out, indep_out, bad);
+    first_level_decide<<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(Ain, p, n, q, r_out, indep_out, bad);
     FPC_HIP(hipGetLastError());
     *d_bad = bad;
     return FPC_OK;

@@ -329,52 +329,64 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     hipStream_t s = ctx->stream;
     const double t0 = now_ms();
     sts.assign(ni, fpc_level_stats{});
-    // pass 1: eligible edges, list lengths and test counts per instance
-    std::vector<int64_t> n_el(ni, 0), n_cd(ni, 0);
-    std::vector<int> mx(ni, 0), bad(ni, 0);
-    parallel_for(ni, [&](int k) {
-        const CandSets &cs = *css[k];
-        fpc_level_stats &st = sts[k];
-        st.level = l;
-        const int64_t Eall = (int64_t)cs.ei.size();
+    // pass 1: eligible edges, list lengths and test counts per chunk of each
+    // instance's edges (chunks keep one instance on many host threads)
+    constexpr int64_t kEdgeChunk = 1024;
+    struct Chunk {
+        int k;
+        int64_t e0, e1;         // edges [e0, e1) of instance k's candidate sets
+        int64_t n_el = 0, n_cd = 0, possible = 0;
         int max_m = 0, sel_m = 0;
-        int64_t possible = 0;
-        for (int64_t e = 0; e < Eall; ++e) {
+        bool bad = false;
+        int64_t r = 0, c = 0;   // first record and list slot (pass 2)
+    };
+    std::vector<Chunk> chunks;
+    for (int k = 0; k < ni; ++k) {
+        sts[k].level = l;
+        const int64_t Eall = (int64_t)css[k]->ei.size();
+        for (int64_t e0 = 0; e0 < Eall; e0 += kEdgeChunk) chunks.push_back(Chunk{k, e0, std::min(Eall, e0 + kEdgeChunk)});
+    }
+    parallel_for((int)chunks.size(), [&](int u) {
+        Chunk &ch = chunks[u];
+        const CandSets &cs = *css[ch.k];
+        for (int64_t e = ch.e0; e < ch.e1; ++e) {
             const int m = (int)(cs.off[e + 1] - cs.off[e]);
-            max_m = std::max(max_m, m);
+            ch.max_m = std::max(ch.max_m, m);
             if (m < l) continue;
             if (m >= kBinomRows) {
-                bad[k] = 1;
+                ch.bad = true;
                 return;
             }
             const int64_t N = binom_sat(m, l);
-            if (N == INT64_MAX || possible > INT64_MAX - N) {
-                bad[k] = 1;
+            if (N == INT64_MAX || ch.possible > INT64_MAX - N) {
+                ch.bad = true;
                 return;
             }
-            possible += N;
-            ++n_el[k];
-            n_cd[k] += m;
-            sel_m = std::max(sel_m, m);
+            ch.possible += N;
+            ++ch.n_el;
+            ch.n_cd += m;
+            ch.sel_m = std::max(ch.sel_m, m);
         }
-        st.max_cand = max_m;
-        st.edges_eligible = n_el[k];
-        st.tests_possible = possible;
-        mx[k] = sel_m;
     });
     int64_t E = 0, T = 0;
     int sel_max_m = 0;
-    std::vector<int64_t> e_off(ni), c_off(ni);
+    for (Chunk &ch : chunks) {  // in instance order, so each instance's records stay together
+        if (ch.bad) return FPC_EBUDGET;
+        fpc_level_stats &st = sts[ch.k];
+        st.max_cand = std::max(st.max_cand, ch.max_m);
+        st.edges_eligible += ch.n_el;
+        if (ch.possible > INT64_MAX - st.tests_possible) return FPC_EBUDGET;
+        st.tests_possible += ch.possible;
+        ch.r = E;
+        ch.c = T;
+        E += ch.n_el;
+        T += ch.n_cd;
+        sel_max_m = std::max(sel_max_m, ch.sel_m);
+    }
     for (int k = 0; k < ni; ++k) {
-        if (bad[k]) return FPC_EBUDGET;
         Run &R = *runs[k];
         if (R.P->max_tests > 0 && R.spent_possible + sts[k].tests_possible > R.P->max_tests) return FPC_EBUDGET;
         R.spent_possible += sts[k].tests_possible;
-        e_off[k] = E;
-        c_off[k] = T;
-        E += n_el[k];
-        T += n_cd[k];
-        sel_max_m = std::max(sel_max_m, mx[k]);
     }
     if (T > INT32_MAX) return FPC_EBUDGET;
     if (E == 0) {
@@ -389,13 +401,14 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     EdgeRec *hrec = ctx->h_stage.as<EdgeRec>();
     int32_t *cand = reinterpret_cast<int32_t *>(hrec + E);  // lists, in instance order
     std::vector<int64_t> cs_edge(E);  // edge index of each record in its instance's candidate sets
-    parallel_for(ni, [&](int k) {
-        const CandSets &cs = *css[k];
-        int64_t r = e_off[k], c = c_off[k];
-        for (int64_t e = 0; e < (int64_t)cs.ei.size(); ++e) {
+    parallel_for((int)chunks.size(), [&](int u) {
+        const Chunk &ch = chunks[u];
+        const CandSets &cs = *css[ch.k];
+        int64_t r = ch.r, c = ch.c;
+        for (int64_t e = ch.e0; e < ch.e1; ++e) {
             const int m = (int)(cs.off[e + 1] - cs.off[e]);
             if (m < l) continue;
-            hrec[r] = EdgeRec{cs.ei[e], cs.ej[e], m, (int32_t)c, binom_sat(m, l), k, 0};
+            hrec[r] = EdgeRec{cs.ei[e], cs.ej[e], m, (int32_t)c, binom_sat(m, l), ch.k, 0};
             cs_edge[r] = e;
             std::memcpy(cand + c, cs.nodes.data() + cs.off[e], sizeof(int32_t) * m);
             ++r;
@@ -544,17 +557,24 @@ retry:
     const double t_decode = now_ms();
     // sepsets and level-end deletion (stable: all of D at once), each
     // instance's deletions in pair order (the records are in class order)
+    // (the result lists every set in pair order, so the decoding order is
+    // free: deletions are only grouped by instance, and put in pair order
+    // for the feature log, whose rows follow it)
     std::vector<std::pair<int64_t, int64_t>> dl(ndel);
-    for (int64_t k = 0; k < ndel; ++k) dl[k] = {pairs[2 * k], pairs[2 * k + 1]};
-    std::sort(dl.begin(), dl.end(), [&](const std::pair<int64_t, int64_t> &a, const std::pair<int64_t, int64_t> &b) {
-        const EdgeRec &x = recs[a.first], &y = recs[b.first];
-        if (x.inst != y.inst) return x.inst < y.inst;
-        if (x.i != y.i) return x.i < y.i;
-        return x.j < y.j;
-    });
     std::vector<int64_t> d_lo(ni + 1, 0);  // deletions of instance k: dl[d_lo[k], d_lo[k+1])
-    for (const auto &d : dl) ++d_lo[recs[d.first].inst + 1];
+    for (int64_t t = 0; t < ndel; ++t) ++d_lo[recs[pairs[2 * t]].inst + 1];
     for (int k = 0; k < ni; ++k) d_lo[k + 1] += d_lo[k];
+    {
+        std::vector<int64_t> at(d_lo.begin(), d_lo.end() - 1);
+        for (int64_t t = 0; t < ndel; ++t) dl[at[recs[pairs[2 * t]].inst]++] = {pairs[2 * t], pairs[2 * t + 1]};
+    }
+    if (logging)
+        std::sort(dl.begin(), dl.end(), [&](const std::pair<int64_t, int64_t> &a, const std::pair<int64_t, int64_t> &b) {
+            const EdgeRec &x = recs[a.first], &y = recs[b.first];
+            if (x.inst != y.inst) return x.inst < y.inst;
+            if (x.i != y.i) return x.i < y.i;
+            return x.j < y.j;
+        });
     // every deletion owns l slots of its instance's node store and one list
     // entry, so the sets are decoded in parallel chunks
     std::vector<size_t> o0(ni), li0(ni);
@@ -567,16 +587,16 @@ retry:
         R.sep.lists.resize(li0[k] + (size_t)nd);
         sts[k].deleted += nd;
     }
-    constexpr int64_t kChunk = 2048;
-    std::vector<std::pair<int, int64_t>> chunks;  // (instance, first deletion)
+    constexpr int64_t kChunk = 512;
+    std::vector<std::pair<int, int64_t>> dchunks;  // (instance, first deletion)
     for (int k = 0; k < ni; ++k)
-        for (int64_t t = d_lo[k]; t < d_lo[k + 1]; t += kChunk) chunks.emplace_back(k, t);
-    parallel_for((int)chunks.size(), [&](int c) {
-        const int k = chunks[c].first;
+        for (int64_t t = d_lo[k]; t < d_lo[k + 1]; t += kChunk) dchunks.emplace_back(k, t);
+    parallel_for((int)dchunks.size(), [&](int c) {
+        const int k = dchunks[c].first;
         Run &R = *runs[k];
         std::vector<int> pos;
-        const int64_t t1 = std::min(d_lo[k + 1], chunks[c].second + kChunk);
-        for (int64_t t = chunks[c].second; t < t1; ++t) {
+        const int64_t t1 = std::min(d_lo[k + 1], dchunks[c].second + kChunk);
+        for (int64_t t = dchunks[c].second; t < t1; ++t) {
             const auto &d = dl[t];
             const EdgeRec &er = recs[d.first];
             unrank_host(d.second, er.m, l, ctx->binom_host, pos);

@@ -207,6 +207,8 @@ typedef struct fpc_result {
                               /* edges in level order, pair order within a level (one    */
                               /* deleted with no candidates has a serial and no rows)    */
     int32_t *log_level;       /* level of the deletion                                   */
+    int64_t n_lists;          /* pairs whose separating set is of LIST kind              */
+    int64_t *list_pairs;      /* their pair indices, increasing (n_lists entries)        */
 } fpc_result;
 
 /* Errors: FPC_EINVAL, FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET,

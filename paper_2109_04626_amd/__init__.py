@@ -78,7 +78,8 @@ class fpc_result(ctypes.Structure):
                 ("first_level_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("corr_max_abs_err", ctypes.c_double), ("log_rows", ctypes.c_int64),
                 ("log_x", ctypes.POINTER(ctypes.c_float)), ("log_y", ctypes.POINTER(ctypes.c_uint8)),
-                ("log_group", ctypes.POINTER(ctypes.c_int32)), ("log_level", ctypes.POINTER(ctypes.c_int32))]
+                ("log_group", ctypes.POINTER(ctypes.c_int32)), ("log_level", ctypes.POINTER(ctypes.c_int32)),
+                ("n_lists", ctypes.c_int64), ("list_pairs", ctypes.POINTER(ctypes.c_int64))]
 
 
 class fpc_tuning(ctypes.Structure):
@@ -521,20 +522,6 @@ class SepSets(Mapping):
         return len(self._idx)
 
 
-class _Result(dict):
-    """fpc_skeleton result; ``sep_off`` (the P + 1 offsets of the C result)
-    is rebuilt on first use from the kinds and levels."""
-
-    def __missing__(self, key):
-        if key != "sep_off":
-            raise KeyError(key)
-        lens = np.where(self["sep_kind"] == FPC_SEP_LIST, self["sep_level"], 0).astype(np.int64)
-        off = np.zeros(len(lens) + 1, np.int64)
-        np.cumsum(lens, out=off[1:])
-        self["sep_off"] = off
-        return off
-
-
 class _Owner:
     """Holds one fpc_result and frees it once no array viewing its buffers
     is left (the arrays keep their owner alive)."""
@@ -572,11 +559,13 @@ def _unpack(res, owner: _Owner | None = None) -> dict:
     adj = _view(r.adj, ctypes.c_uint8, np.uint8, p * p, owner).reshape(p, p)
     lev = _view(r.sep_level, ctypes.c_int32, np.int32, P, owner)
     kind = _view(r.sep_kind, ctypes.c_int8, np.int8, P, owner)
-    tot = int(r.sep_off[P])
+    sep_off = _view(r.sep_off, ctypes.c_int64, np.int64, P + 1, owner)
+    tot = int(sep_off[P])
     nodes = _view(r.sep_nodes, ctypes.c_int32, np.int32, tot, owner)
-    idx = np.flatnonzero(kind == FPC_SEP_LIST)
-    off = np.zeros(len(idx) + 1, np.int64)
-    np.cumsum(lev[idx], out=off[1:])
+    idx = _view(r.list_pairs, ctypes.c_int64, np.int64, int(r.n_lists), owner)
+    off = np.empty(len(idx) + 1, np.int64)
+    off[:-1] = sep_off[idx]
+    off[-1] = tot
     sepsets = SepSets(p, idx, off, nodes)
     levels = []
     for k in range(r.n_levels):
@@ -589,7 +578,7 @@ def _unpack(res, owner: _Owner | None = None) -> dict:
                    y=_view(r.log_y, ctypes.c_uint8, np.uint8, nlog, owner),
                    group=_view(r.log_group, ctypes.c_int32, np.int32, nlog, owner),
                    level=_view(r.log_level, ctypes.c_int32, np.int32, nlog, owner))
-    return _Result(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets, sep_nodes=nodes,
+    return dict(adj=adj, sep_level=lev, sep_kind=kind, sep_off=sep_off, sepsets=sepsets, sep_nodes=nodes,
                    levels=levels, log=log,
                    total_tests=int(r.total_tests), total_required=sum(x["tests_required"] for x in levels),
                    q=float(r.q), corr_ms=float(r.corr_ms),

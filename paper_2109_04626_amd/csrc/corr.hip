@@ -25,48 +25,54 @@ namespace {
 
 constexpr int kStatRows = 256;  // rows per partial in the column statistics
 
-// Partial column sums (pass 0) or centred sums of squares (pass 1).
+// One pass of column statistics: per chunk of rows, the sums of x - K and
+// (x - K)^2 with K = X[0][j], a value of the column itself (the shifted-data
+// form of the two-pass variance: its cancellation error scales with
+// (mean - K)^2 / var, of order one for a sample of the column).
 template <typename TX>
 __global__ __launch_bounds__(256) void colstat_partial(const TX *__restrict__ X, int n, int p,
-                                                       const double *__restrict__ mu, int pass,
-                                                       double *__restrict__ part,
-                                                       int *__restrict__ nonfinite)
+                                                       double *__restrict__ part, int *__restrict__ nonfinite)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= p) return;
     const int r0 = blockIdx.y * kStatRows, r1 = min(n, r0 + kStatRows);
-    double s = 0.0;
+    const double K = (double)X[j];
+    double s1 = 0.0, s2 = 0.0;
     bool bad = false;
-    const double m = pass ? mu[j] : 0.0;
     for (int t = r0; t < r1; ++t) {
         const double x = (double)X[(size_t)t * p + j];
         bad |= !isfinite(x);
-        const double d = x - m;
-        s += pass ? d * d : x;
+        const double d = x - K;
+        s1 += d;
+        s2 = fma(d, d, s2);
     }
-    part[(size_t)blockIdx.y * p + j] = s;
+    part[(size_t)blockIdx.y * 2 * p + j] = s1;
+    part[(size_t)blockIdx.y * 2 * p + p + j] = s2;
     if (bad) atomicOr(nonfinite, 1);
 }
 
-__global__ void colstat_reduce(const double *__restrict__ part, int nchunks, int n, int p,
-                               int pass, double *__restrict__ out, int *__restrict__ constant)
+// mean and standard deviation of each column from the partial sums
+template <typename TX>
+__global__ void colstat_reduce(const TX *__restrict__ X, const double *__restrict__ part, int nchunks, int n, int p,
+                               double *__restrict__ mu, double *__restrict__ sd, int *__restrict__ constant)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= p) return;
-    double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * p + j];
-    if (pass == 0) {
-        out[j] = s / n;  // mean
-    } else {
-        const double var = s / n;
-        out[j] = sqrt(var);  // standard deviation
-        if (!(var > 0.0)) atomicOr(constant, 1);
+    double s1 = 0.0, s2 = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+        s1 += part[(size_t)c * 2 * p + j];
+        s2 += part[(size_t)c * 2 * p + p + j];
     }
+    const double m1 = s1 / n;
+    mu[j] = (double)X[j] + m1;
+    const double var = fmax(s2 / n - m1 * m1, 0.0);
+    sd[j] = sqrt(var);
+    if (!(var > 0.0)) atomicOr(constant, 1);
 }
 
 // ---------------------------------------------------------------- FP64 products
 constexpr int kT = 64;   // output tile edge
-constexpr int kK = 16;   // samples per LDS stage
+constexpr int kK = 32;   // samples per LDS stage
 
 __device__ inline void tile_of(int t, int nbt, int &bi, int &bj)
 {
@@ -99,19 +105,39 @@ __global__ __launch_bounds__(256) void syrk_f64(const TX *__restrict__ X, const 
     __shared__ double Bs[kK][kT + 1];
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int wr = wave / 2, wc = wave % 2;  // the wave's 32 x 32 quarter
+    // staging: thread t loads column t % 64 of the tile rows and columns,
+    // samples t / 64 + 4 m (m < kK / 4) of each stage; the next stage's
+    // samples are fetched into registers while the current one is multiplied
+    constexpr int kM = kK * kT / 256;
+    const int c = threadIdx.x % kT, r0 = threadIdx.x / kT;
+    const int ca = bi * kT + c, cb = bj * kT + c;
+    const bool va = ca < p, vb = cb < p;
+    const double mua = va ? mu[ca] : 0.0, mub = vb ? mu[cb] : 0.0;
+    TX ra[kM], rb[kM];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int m = 0; m < kM; ++m) {
+            const int row = k0 + r0 + 4 * m;
+            ra[m] = (row < t1 && va) ? X[(size_t)row * p + ca] : TX(0);
+            rb[m] = (row < t1 && vb) ? X[(size_t)row * p + cb] : TX(0);
+        }
+    };
     v4d acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (t0 < t1) fetch(t0);
     for (int k0 = t0; k0 < t1; k0 += kK) {
-        for (int e = threadIdx.x; e < kK * kT; e += 256) {
-            const int r = e / kT, c = e % kT, row = k0 + r;
-            const int ca = bi * kT + c, cb = bj * kT + c;
-            As[r][c] = (row < t1 && ca < p) ? (double)X[(size_t)row * p + ca] - mu[ca] : 0.0;
-            Bs[r][c] = (row < t1 && cb < p) ? (double)X[(size_t)row * p + cb] - mu[cb] : 0.0;
+#pragma unroll
+        for (int m = 0; m < kM; ++m) {
+            const int r = r0 + 4 * m;
+            const bool in = k0 + r < t1;
+            As[r][c] = (in && va) ? (double)ra[m] - mua : 0.0;
+            Bs[r][c] = (in && vb) ? (double)rb[m] - mub : 0.0;
         }
         __syncthreads();
+        if (k0 + kK < t1) fetch(k0 + kK);
 #pragma unroll
         for (int kk = 0; kk < kK; kk += 4) {
             const int kr = kk + lane / 16;
@@ -311,8 +337,8 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
     const int npad = (n + 31) / 32 * 32;
     const int nsplit = splits_for(tiles, method == FPC_CORR_FP64 ? n : npad, ctx->num_cus);
     const size_t pp = (size_t)p * p;
-    // colstat layout: mu[p], sd[p], partials[nchunks*p]
-    int rc = ctx->colstat.ensure(sizeof(double) * ((size_t)2 * p + (size_t)nchunks * p));
+    // colstat layout: mu[p], sd[p], partials[nchunks * 2p]
+    int rc = ctx->colstat.ensure(sizeof(double) * ((size_t)2 * p + (size_t)nchunks * 2 * p));
     if (rc) return rc;
     if ((rc = ctx->flag.ensure(64))) return rc;
     if ((rc = ctx->inv_work.ensure(sizeof(double) * pp * nsplit))) return rc;
@@ -322,13 +348,17 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
     dim3 g0((p + 255) / 256, nchunks);
     // column means and deviations (kept from the previous call on the same
     // data when reuse_stats is set)
-    if (!reuse_stats) FPC_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(int), st));
-    for (int pass = 0; pass < 2 && !reuse_stats; ++pass) {
-        if (x_dtype == FPC_F64)
-            colstat_partial<double><<<g0, 256, 0, st>>>((const double *)X, n, p, mu, pass, part, flags);
-        else
-            colstat_partial<float><<<g0, 256, 0, st>>>((const float *)X, n, p, mu, pass, part, flags);
-        colstat_reduce<<<(p + 255) / 256, 256, 0, st>>>(part, nchunks, n, p, pass, pass ? sd : mu, flags + 1);
+    if (!reuse_stats) {
+        FPC_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(int), st));
+        if (x_dtype == FPC_F64) {
+            colstat_partial<double><<<g0, 256, 0, st>>>((const double *)X, n, p, part, flags);
+            colstat_reduce<double><<<(p + 255) / 256, 256, 0, st>>>((const double *)X, part, nchunks, n, p, mu, sd,
+                                                                    flags + 1);
+        } else {
+            colstat_partial<float><<<g0, 256, 0, st>>>((const float *)X, n, p, part, flags);
+            colstat_reduce<float><<<(p + 255) / 256, 256, 0, st>>>((const float *)X, part, nchunks, n, p, mu, sd,
+                                                                   flags + 1);
+        }
     }
     FPC_HIP(hipGetLastError());
     if (method == FPC_CORR_FP64) {

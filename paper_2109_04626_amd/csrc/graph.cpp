@@ -9,6 +9,8 @@
 // candidate set is a merge of two filtered neighbour lists: O(p + E) for
 // the labelling plus O(deg i + deg j) per edge.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <thread>
 
@@ -128,10 +130,17 @@ void edge_blocks(const Adjacency &g, int p, std::vector<int32_t> &block)
 
 void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
 {
+    using clk = std::chrono::steady_clock;
+    const auto ms = [](clk::time_point a, clk::time_point b) {
+        return std::chrono::duration<double, std::milli>(b - a).count();
+    };
+    const auto t0 = clk::now();
     Adjacency g;
     build_adjacency(adj, p, g);
+    const auto t1 = clk::now();
     std::vector<int32_t> block;
     edge_blocks(g, p, block);
+    const auto t2 = clk::now();
     const int E = (int)g.eu.size();
     // block id of each adjacency slot, so the merge reads two flat arrays
     std::vector<int32_t> nbblk(g.nb.size());
@@ -140,37 +149,48 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
     out.ej.assign(g.ev.begin(), g.ev.end());
     out.off.resize(E + 1);
     out.off[0] = 0;
-    // merge the neighbour lists of i and j, keeping the entries of block b
-    // other than i and j themselves (both lists are sorted); edges are split
-    // into contiguous chunks merged by separate host threads
+    // per edge: the neighbours of i in block b (other than j) and those of j
+    // in block b (other than i), each filtered without branches, then their
+    // sorted union by a branch-free merge (both lists are sorted); edges
+    // are split into contiguous chunks handled by separate host threads
+    int maxdeg = 0;
+    for (int u = 0; u < p; ++u) maxdeg = std::max(maxdeg, g.off[u + 1] - g.off[u]);
     auto merge_range = [&](int e0, int e1, std::vector<int32_t> &dst, std::vector<int64_t> &len) {
+        size_t bound = 0;
+        for (int e = e0; e < e1; ++e)
+            bound += (size_t)(g.off[g.eu[e] + 1] - g.off[g.eu[e]]) + (size_t)(g.off[g.ev[e] + 1] - g.off[g.ev[e]]);
+        dst.resize(bound);
+        len.resize((size_t)(e1 - e0));
+        std::vector<int32_t> fa((size_t)maxdeg + 1), fc((size_t)maxdeg + 1);
+        size_t o = 0;
         for (int e = e0; e < e1; ++e) {
             const int i = g.eu[e], j = g.ev[e], b = block[e];
             const int32_t *na = g.nb.data() + g.off[i], *ba = nbblk.data() + g.off[i];
             const int32_t *nc = g.nb.data() + g.off[j], *bc = nbblk.data() + g.off[j];
-            const int la = g.off[i + 1] - g.off[i], lc = g.off[j + 1] - g.off[j];
-            const size_t start = dst.size();
-            int a = 0, c = 0;
-            while (a < la && c < lc) {
-                const int ka = na[a], kc = nc[c];
-                if (ka < kc) {
-                    if (ba[a] == b && ka != j) dst.push_back(ka);
-                    ++a;
-                } else if (kc < ka) {
-                    if (bc[c] == b && kc != i) dst.push_back(kc);
-                    ++c;
-                } else {
-                    if ((ba[a] == b || bc[c] == b) && ka != i && ka != j) dst.push_back(ka);
-                    ++a;
-                    ++c;
-                }
+            const int da = g.off[i + 1] - g.off[i], dc = g.off[j + 1] - g.off[j];
+            int la = 0, lc = 0;
+            for (int t = 0; t < da; ++t) {
+                fa[la] = na[t];
+                la += (ba[t] == b) & (na[t] != j);
             }
-            for (; a < la; ++a)
-                if (ba[a] == b && na[a] != j) dst.push_back(na[a]);
-            for (; c < lc; ++c)
-                if (bc[c] == b && nc[c] != i) dst.push_back(nc[c]);
-            len.push_back((int64_t)(dst.size() - start));
+            for (int t = 0; t < dc; ++t) {
+                fc[lc] = nc[t];
+                lc += (bc[t] == b) & (nc[t] != i);
+            }
+            int32_t *out = dst.data() + o;
+            int a = 0, c = 0, k = 0;
+            while (a < la && c < lc) {
+                const int32_t x = fa[a], y = fc[c];
+                out[k++] = x < y ? x : y;
+                a += x <= y;
+                c += y <= x;
+            }
+            while (a < la) out[k++] = fa[a++];
+            while (c < lc) out[k++] = fc[c++];
+            o += (size_t)k;
+            len[e - e0] = k;
         }
+        dst.resize(o);
     };
     int nth = threads > 0 ? threads : host_threads();
     if (E < 2048) nth = 1;
@@ -181,10 +201,7 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
     if (nth == 1) {
         merge_range(0, E, parts[0], lens[0]);
     } else {
-        host_parallel(nth, [&](int t) {
-            parts[t].reserve((size_t)(bounds[t + 1] - bounds[t]) * 48);
-            merge_range(bounds[t], bounds[t + 1], parts[t], lens[t]);
-        });
+        host_parallel(nth, [&](int t) { merge_range(bounds[t], bounds[t + 1], parts[t], lens[t]); });
     }
     std::vector<size_t> at(nth + 1, 0);
     for (int t = 0; t < nth; ++t) at[t + 1] = at[t] + parts[t].size();
@@ -195,11 +212,15 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
             out.off[e + 1] = out.off[e] + L;
             ++e;
         }
+    const auto t3 = clk::now();
     auto copy_part = [&](int t) {
         std::memcpy(out.nodes.data() + at[t], parts[t].data(), sizeof(int32_t) * parts[t].size());
     };
     if (nth == 1) copy_part(0);
     else host_parallel(nth, copy_part);
+    if (trace_on())
+        std::fprintf(stderr, "[fpc]   candidate sets: adjacency %.3f blocks %.3f merge %.3f concat %.3f ms (%d threads)\n",
+                     ms(t0, t1), ms(t1, t2), ms(t2, t3), ms(t3, clk::now()), nth);
 }
 
 }  // namespace fpc

@@ -281,6 +281,7 @@ extern "C" void fpc_result_free(fpc_result *r)
     std::free(r->log_y);
     std::free(r->log_group);
     std::free(r->log_level);
+    std::free(r->list_pairs);
     std::free(r);
 }
 
@@ -346,7 +347,16 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
         const int64_t Eall = (int64_t)css[k]->ei.size();
         for (int64_t e0 = 0; e0 < Eall; e0 += kEdgeChunk) chunks.push_back(Chunk{k, e0, std::min(Eall, e0 + kEdgeChunk)});
     }
-    parallel_for((int)chunks.size(), [&](int u) {
+    // a level of a few thousand edges runs on the calling thread: waking the
+    // pool costs more than the work
+    const bool few = chunks.size() <= 4;
+    auto for_chunks = [&](const std::function<void(int)> &fn) {
+        if (few)
+            for (int u = 0; u < (int)chunks.size(); ++u) fn(u);
+        else
+            parallel_for((int)chunks.size(), fn);
+    };
+    for_chunks([&](int u) {
         Chunk &ch = chunks[u];
         const CandSets &cs = *css[ch.k];
         for (int64_t e = ch.e0; e < ch.e1; ++e) {
@@ -401,7 +411,7 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     EdgeRec *hrec = ctx->h_stage.as<EdgeRec>();
     int32_t *cand = reinterpret_cast<int32_t *>(hrec + E);  // lists, in instance order
     std::vector<int64_t> cs_edge(E);  // edge index of each record in its instance's candidate sets
-    parallel_for((int)chunks.size(), [&](int u) {
+    for_chunks([&](int u) {
         const Chunk &ch = chunks[u];
         const CandSets &cs = *css[ch.k];
         int64_t r = ch.r, c = ch.c;
@@ -786,8 +796,11 @@ int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result
     res->sep_off = (int64_t *)std::malloc(sizeof(int64_t) * (PP + 1));
     const int64_t tot = (int64_t)R.sep.nodes.size();
     res->sep_nodes = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1));
+    res->n_lists = (int64_t)R.sep.lists.size();
+    res->list_pairs = (int64_t *)std::malloc(sizeof(int64_t) * (size_t)std::max<int64_t>(res->n_lists, 1));
     res->levels = (fpc_level_stats *)std::malloc(sizeof(fpc_level_stats) * std::max<size_t>(R.levels.size(), 1));
-    if (!res->adj || !res->sep_level || !res->sep_kind || !res->sep_off || !res->sep_nodes || !res->levels) {
+    if (!res->adj || !res->sep_level || !res->sep_kind || !res->sep_off || !res->sep_nodes || !res->levels ||
+        !res->list_pairs) {
         fpc_result_free(res);
         return FPC_ENOMEM;
     }
@@ -852,6 +865,7 @@ int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result
         }
     });
     res->sep_off[PP] = node_lo[nblk];
+    for (size_t t = 0; t < R.sep.lists.size(); ++t) res->list_pairs[t] = R.sep.lists[t].pair;
     std::memcpy(res->levels, R.levels.data(), sizeof(fpc_level_stats) * R.levels.size());
     res->total_tests = R.total_exec;
     res->q = R.q;

@@ -28,7 +28,8 @@
 // Mixed precision: FP32 tests whose z lies within band of q (band = the
 // stated margin plus a bound on the FP32 error of this test) are appended
 // to a queue (ballot + prefix sum per wave) and re-run in FP64 from the
-// FP64 matrix by the recheck kernel; degenerate FP32 tests are re-run too.
+// FP64 matrix by the recheck kernel once the level's windows are done;
+// degenerate FP32 tests are re-run too.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -209,7 +210,8 @@ __device__ __forceinline__ int64_t binom_at(const int64_t *__restrict__ binom, i
 }
 
 // Lexicographic unranking of rank R among the L-subsets of m positions.
-template <int L>
+// It reads C(a, b) for b < L only; STRIDE = columns of the table.
+template <int L, int STRIDE = kBinomCols>
 __device__ __forceinline__ void unrank(int64_t R, int m, const int64_t *__restrict__ binom, int *c)
 {
     int x = 0;
@@ -218,7 +220,8 @@ __device__ __forceinline__ void unrank(int64_t R, int m, const int64_t *__restri
         for (;;) {
             const int a = m - 1 - x;
             if (a < L - 1 - t) break;  // never taken for R < C(m, L)
-            const int64_t cnt = binom_at(binom, a, L - 1 - t);
+            const int b = L - 1 - t, bb = min(b, a - b);
+            const int64_t cnt = binom[a * STRIDE + bb];
             if (R < cnt) break;
             R -= cnt;
             ++x;
@@ -287,8 +290,9 @@ struct LevelArgs {
     uint64_t *minhit;
     unsigned long long *counters;  // [1] recheck queue length, [3] queue overflow
     unsigned long long *inst_cnt;  // per instance: tests executed, tests re-run in FP64
-    int64_t *queue;
+    int64_t *queue;       // recheck queue: (level edge index, rank) pairs
     int64_t queue_cap;
+    int64_t edge_base;    // level index of edges[0] (the launch's class starts there)
     int64_t n_edges;
     int64_t win_lo, win_hi;
     int ranks_per_block;
@@ -437,7 +441,7 @@ __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsi
                     if (rq) {
                         const unsigned long long idx = slot + __popcll(qb & ((1ull << lane) - 1ull));
                         if ((int64_t)idx < A.queue_cap) {
-                            A.queue[2 * idx] = e;
+                            A.queue[2 * idx] = e + A.edge_base;
                             A.queue[2 * idx + 1] = base + lane;
                         }
                     }
@@ -461,10 +465,29 @@ __global__ __launch_bounds__(256) void level_kernel(LevelArgs A)
     for_each_item(A, [&](int64_t blk) { level_item<T, L, TILE>(A, blk, smem); });
 }
 
+// Binomial rows the recheck kernel stages in LDS: C(a, b), a < max_m,
+// b < L, when they fit in kRecheckLds bytes (else it reads the global table).
+constexpr size_t kRecheckLds = 32768;
+__host__ __device__ inline size_t recheck_lds_bytes(int max_m, int L)
+{
+    const size_t b = sizeof(int64_t) * (size_t)max_m * (size_t)(L > 0 ? L : 1);
+    return b <= kRecheckLds ? b : 0;
+}
+
 // FP64 re-run of queued FP32 tests (rank below the edge's current minhit).
 template <int L>
 __global__ __launch_bounds__(256) void recheck_kernel(LevelArgs A)
 {
+    extern __shared__ int64_t bl[];  // C(a, b) at a * L + b
+    constexpr int LL = L > 0 ? L : 1;
+    const bool staged = recheck_lds_bytes(A.max_m, L) > 0;
+    if (staged) {
+        for (int t = threadIdx.x; t < A.max_m * LL; t += blockDim.x) {
+            const int a = t / LL, b = t % LL;
+            bl[t] = binom_at(A.binom, a, b);
+        }
+        __syncthreads();
+    }
     const unsigned long long queued = A.counters[1];
     const unsigned long long total = min((unsigned long long)A.queue_cap, queued);
     if (blockIdx.x == 0 && threadIdx.x == 0 && queued > (unsigned long long)A.queue_cap)
@@ -472,17 +495,37 @@ __global__ __launch_bounds__(256) void recheck_kernel(LevelArgs A)
     for (unsigned long long idx = (unsigned long long)blockIdx.x * 256 + threadIdx.x; idx < total;
          idx += (unsigned long long)gridDim.x * 256) {
         const int64_t e = A.queue[2 * idx], R = A.queue[2 * idx + 1];
-        if ((uint64_t)R >= load_minhit(&A.minhit[e])) continue;
-        const EdgeRec E = A.edges[e];
-        int k[L > 0 ? L : 1];
-        if constexpr (L > 0) unrank<L>(R, E.m, A.binom, k);
-        const InstRec &I = A.inst[E.inst];
-        GlobalRows<double> g{I.C64, (int)I.ld, A.cand + E.cand_off, E.i, E.j};
-        double r, dmin;
-        bool ok;
-        pcor_reg<double, L>(g, k, r, dmin, ok);
-        atomicAdd(&A.inst_cnt[2 * E.inst + 1], 1ull);
-        if (decide64(r, ok, I.th)) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
+        const bool run = (uint64_t)R < load_minhit(&A.minhit[e]);
+        int inst = -1;
+        if (run) {
+            const EdgeRec E = A.edges[e];
+            inst = E.inst;
+            int k[L > 0 ? L : 1];
+            if constexpr (L > 0) {
+                if (staged) unrank<L, L>(R, E.m, bl, k);
+                else unrank<L>(R, E.m, A.binom, k);
+            }
+            const InstRec &I = A.inst[E.inst];
+            GlobalRows<double> g{I.C64, (int)I.ld, A.cand + E.cand_off, E.i, E.j};
+            double r, dmin;
+            bool ok;
+            pcor_reg<double, L>(g, k, r, dmin, ok);
+            if (decide64(r, ok, I.th)) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
+        }
+        // re-run counts: one atomic per wave when the wave's re-runs share
+        // an instance (the usual case), per lane otherwise; a single
+        // counter hit by every lane would serialise the launch
+        const unsigned long long mask = __ballot(run);
+        if (mask) {
+            const int lead = __ffsll((long long)mask) - 1;
+            const int inst0 = __shfl(inst, lead);
+            if (__all(!run || inst == inst0)) {
+                if ((int)(threadIdx.x % 64) == lead)
+                    atomicAdd(&A.inst_cnt[2 * inst0 + 1], (unsigned long long)__popcll(mask));
+            } else if (run) {
+                atomicAdd(&A.inst_cnt[2 * inst + 1], 1ull);
+            }
+        }
     }
 }
 
@@ -744,7 +787,7 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
                     if (rq) {
                         const unsigned long long idx = slot + __popcll(qb & ((1ull << lane) - 1ull));
                         if ((int64_t)idx < A.queue_cap) {
-                            A.queue[2 * idx] = e;
+                            A.queue[2 * idx] = e + A.edge_base;
                             A.queue[2 * idx + 1] = rank + it + lane;
                         }
                     }
@@ -1063,7 +1106,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                         if (rq) {
                             const unsigned long long idx = slot + __popcll(qb & ((1ull << lane) - 1ull));
                             if ((int64_t)idx < A.queue_cap) {
-                                A.queue[2 * idx] = e;
+                                A.queue[2 * idx] = e + A.edge_base;
                                 A.queue[2 * idx + 1] = rank + it + lane;
                             }
                         }
@@ -1334,7 +1377,6 @@ struct PlanArgs {
     int64_t *off;                   // n_edges + 1 exclusive prefix of items per edge
     int64_t *n_items;               // total items of the window
     unsigned long long *item_ctr;   // zeroed for the window's test kernel
-    unsigned long long *queue_len;  // recheck queue of the previous window, emptied
 };
 
 constexpr int kPlanPer = 8;                 // edges per thread
@@ -1402,7 +1444,6 @@ __global__ __launch_bounds__(256) void plan_sums(PlanArgs P, int nb)
         P.off[P.n_edges] = carry;
         *P.n_items = carry;
         *P.item_ctr = 0;
-        *P.queue_len = 0;
     }
 }
 
@@ -1556,7 +1597,7 @@ void launch_recheck(int l, hipStream_t st, const LevelArgs &A)
 {
     if constexpr (L <= kMaxTemplL) {
         if (l == L) {
-            recheck_kernel<L><<<512, 256, 0, st>>>(A);
+            recheck_kernel<L><<<512, 256, recheck_lds_bytes(A.max_m, L), st>>>(A);
             return;
         }
         launch_recheck<L + 1>(l, st, A);
@@ -1774,7 +1815,6 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             P.off = pl + 2 + nb;
             P.n_items = pl;
             P.item_ctr = A.item_ctr;
-            P.queue_len = &Lv.counters[1];
             A.edges = P.edges;
             A.minhit = Lv.minhit + k.begin;
             A.n_edges = Ek;
@@ -1782,6 +1822,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             A.win_lo = lo;
             A.win_hi = hi;
             A.ranks_per_block = k.rpb;
+            A.edge_base = k.begin;
             A.max_m = k.max_m;
             A.pdec_n = k.pdec_n;
             plan_reduce<<<(unsigned)nb, 256, 0, st>>>(P);
@@ -1821,10 +1862,21 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                              "grid %u, items <= %lld\n", l, w, (int)(&k - cls.data()), (int)k.kind, k.max_m, k.shm,
                              k.pdec_n, g_last_grid, (long long)ub);
             ++nlaunch;
-            if (fp32) launch_recheck(l, st, A);  // the next plan empties the queue
             if (err == hipSuccess) err = hipGetLastError();
             if (err != hipSuccess) break;
         }
+    }
+    // one FP64 pass over the whole level's queue: the windows' plans read a
+    // minhit that a pending recheck may still lower, which only keeps an
+    // edge live for longer; the level's result is the same
+    if (fp32 && err == hipSuccess) {
+        A.edges = Lv.edges;
+        A.minhit = Lv.minhit;
+        A.n_edges = E;
+        A.edge_base = 0;
+        A.max_m = Lv.max_m;
+        launch_recheck(l, st, A);
+        err = hipGetLastError();
     }
     if (graph) {
         const hipError_t e2 = hipStreamEndCapture(st, &g);

@@ -642,9 +642,11 @@ retry:
     if (trace_on())
         std::fprintf(stderr,
                      "[fpc] level %d: %d instance(s) %lld edges %lld candidates %d classes | setup %.2f upload+order "
-                     "%.2f tests and compaction %.2f (device %.2f) counts %.2f decode %.2f ms | deleted %lld\n",
+                     "%.2f tests and compaction %.2f (device %.2f) counts %.2f decode %.2f ms | deleted %lld, "
+                     "queued for FP64 %llu\n",
                      l, ni, (long long)E, (long long)T, (int)classes.size(), t_build - t0, t_tests0 - t_build,
-                     t_tests1 - t_tests0, tm.all_ms, t_decode - t_tests1, now_ms() - t_decode, (long long)ndel);
+                     t_tests1 - t_tests0, tm.all_ms, t_decode - t_tests1, now_ms() - t_decode, (long long)ndel,
+                     fp32 ? cnt[1] : 0ull);
     for (auto &st : sts) {
         st.kernel_ms = tm.all_ms;
         st.test_kernel_ms = tm.test_ms;

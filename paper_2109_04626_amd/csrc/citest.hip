@@ -329,6 +329,28 @@ __device__ __forceinline__ void for_each_item(const LevelArgs &A, F &&body)
     }
 }
 
+// Tests run, per instance: each wave sums them in a register and adds the
+// sum to the instance's shared counter when it moves on to an item of
+// another instance and when it ends, so the counter takes a few atomics per
+// wave instead of one per work item.
+struct ExecCount {
+    int inst = -1;
+    unsigned long long n = 0;
+    __device__ void add(const LevelArgs &A, int i, unsigned long long k)
+    {
+        if (i != inst) {
+            flush(A);
+            inst = i;
+        }
+        n += k;
+    }
+    __device__ void flush(const LevelArgs &A)
+    {
+        if (n && threadIdx.x % 64 == 0) atomicAdd(&A.inst_cnt[2 * inst], n);
+        n = 0;
+    }
+};
+
 // Persistent grid: as many workgroups as fit on the device at once, and no
 // more than the window can possibly use.
 // The register and wave limits come from the runtime's occupancy query;
@@ -379,7 +401,7 @@ __device__ void stage_tile(const T *__restrict__ C, int p, const int32_t *__rest
 
 // ------------------------------------------------------------------ level kernel
 template <typename T, int L, bool TILE>
-__device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsigned char *smem)
+__device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsigned char *smem, ExecCount &ec)
 {
     const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
@@ -455,14 +477,16 @@ __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsi
             if (!more) break;
         }
     }
-    if (lane == 0 && executed) atomicAdd(&A.inst_cnt[2 * E.inst], (unsigned long long)executed);
+    ec.add(A, E.inst, (unsigned long long)executed);
 }
 
 template <typename T, int L, bool TILE>
 __global__ __launch_bounds__(256) void level_kernel(LevelArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    for_each_item(A, [&](int64_t blk) { level_item<T, L, TILE>(A, blk, smem); });
+    ExecCount ec;
+    for_each_item(A, [&](int64_t blk) { level_item<T, L, TILE>(A, blk, smem, ec); });
+    ec.flush(A);
 }
 
 // Binomial rows the recheck kernel stages in LDS: C(a, b), a < max_m,
@@ -609,7 +633,7 @@ __device__ __forceinline__ unsigned tri_root(unsigned u)
 }
 
 template <typename T, int QL>
-__device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsigned char *smem)
+__device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsigned char *smem, ExecCount &ec)
 {
     using Lay = PairLayout<T, QL>;
     constexpr int L = QL + 2;
@@ -825,14 +849,16 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
             tau = 0;
         }
     }
-    if (lane == 0 && executed) atomicAdd(&A.inst_cnt[2 * E.inst], (unsigned long long)executed);
+    ec.add(A, E.inst, (unsigned long long)executed);
 }
 
 template <typename T, int QL>
 __global__ __launch_bounds__(256) void pair_kernel(LevelArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    for_each_item(A, [&](int64_t blk) { pair_item<T, QL>(A, blk, smem); });
+    ExecCount ec;
+    for_each_item(A, [&](int64_t blk) { pair_item<T, QL>(A, blk, smem, ec); });
+    ec.flush(A);
 }
 
 template <typename T, int QL = 0>
@@ -895,7 +921,7 @@ struct TripleLayout {
 
 template <typename T, int QL>
 __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, unsigned char *smem,
-                                            const uint16_t *__restrict__ pdec)
+                                            const uint16_t *__restrict__ pdec, ExecCount &ec)
 {
     using Lay = TripleLayout<T, QL>;
     constexpr int L = QL + 3;
@@ -1159,7 +1185,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
             tau = 0;
         }
     }
-    if (lane == 0 && executed) atomicAdd(&A.inst_cnt[2 * E.inst], (unsigned long long)executed);
+    ec.add(A, E.inst, (unsigned long long)executed);
 }
 
 // Pairs (b < c) of the positions after a, in reversed order: the pair of
@@ -1184,7 +1210,9 @@ __global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
         pdec[u] = (uint16_t)(rr | ((u - (__umul24(rr, rr + 1u) >> 1)) << 8));
     }
     unsigned char *rest = smem + pdec_bytes(A.pdec_n);
-    for_each_item(A, [&](int64_t blk) { triple_item<T, QL>(A, blk, rest, pdec); });
+    ExecCount ec;
+    for_each_item(A, [&](int64_t blk) { triple_item<T, QL>(A, blk, rest, pdec, ec); });
+    ec.flush(A);
 }
 
 template <typename T, int QL = 0>
@@ -1276,7 +1304,7 @@ __device__ bool wave_pcor(T *M, int l, int lane, T &r)
 }
 
 template <typename T>
-__device__ __forceinline__ void wide_item(const LevelArgs &A, int l, int64_t blk, unsigned char *smem)
+__device__ __forceinline__ void wide_item(const LevelArgs &A, int l, int64_t blk, unsigned char *smem, ExecCount &ec)
 {
     T *M = reinterpret_cast<T *>(smem);
     int *k = reinterpret_cast<int *>(M + (size_t)(l + 2) * (l + 3) / 2 + 1);
@@ -1351,14 +1379,16 @@ __device__ __forceinline__ void wide_item(const LevelArgs &A, int l, int64_t blk
         }
         __syncthreads();
     }
-    if (lane == 0 && executed) atomicAdd(&A.inst_cnt[2 * E.inst], (unsigned long long)executed);
+    ec.add(A, E.inst, (unsigned long long)executed);
 }
 
 template <typename T>
 __global__ __launch_bounds__(64) void level_kernel_wide(LevelArgs A, int l)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    for_each_item(A, [&](int64_t blk) { wide_item<T>(A, l, blk, smem); });
+    ExecCount ec;
+    for_each_item(A, [&](int64_t blk) { wide_item<T>(A, l, blk, smem, ec); });
+    ec.flush(A);
 }
 
 // ------------------------------------------------------------------ window plans

@@ -1111,16 +1111,20 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                 const T h11 = H11a - ub * ub - uc * uc;
                 const T h22 = H22a - vb * vb - vc * vc;
                 const T h12 = H12a - ub * vb - uc * vc;
-                bool ok = oka && sbb > T(0) && d3 > T(0) && h11 > T(0) && h22 > T(0);
                 const T r = h12 * rsqv(h11 * h22);
-                ok = ok && fabs(r) < T(1);
                 int dec;
                 if constexpr (sizeof(T) == 8) {
+                    const bool ok = oka && sbb > T(0) && d3 > T(0) && h11 > T(0) && h22 > T(0) && fabs(r) < T(1);
                     dec = decide64((double)r, ok, th) ? DEC_INDEP : DEC_DEP;
                 } else {
-                    const float dmin = pos_min(pos_min((float)dmina, pos_min((float)sbb, (float)d3)),
-                                               pos_min((float)h11, (float)h22));
-                    dec = decide32r((float)r, dmin, ok, rlo32, rhi32, errk);
+                    // smallest pivot through the bit patterns: > 0 as an integer
+                    // exactly when every pivot is a positive float (a negative
+                    // one or a zero becomes the minimum).  A NaN needs a zero or
+                    // denormal pivot upstream, which is then the minimum and
+                    // makes every decision a recheck (margin * dmin <= errk).
+                    const float dmin = pos_min(pos_min(dmina, pos_min(sbb, d3)), pos_min(h11, h22));
+                    const bool ok = oka && __float_as_int(dmin) > 0 && fabsf(r) < 1.0f;
+                    dec = decide32r(r, dmin, ok, rlo32, rhi32, errk);
                 }
                 if constexpr (sizeof(T) == 4) {
                     const bool rq = valid && dec == DEC_RECHECK;

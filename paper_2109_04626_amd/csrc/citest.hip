@@ -28,8 +28,8 @@
 // Mixed precision: FP32 tests whose z lies within band of q (band = the
 // stated margin plus a bound on the FP32 error of this test) are appended
 // to a queue (ballot + prefix sum per wave) and re-run in FP64 from the
-// FP64 matrix by the recheck kernel once the level's windows are done;
-// degenerate FP32 tests are re-run too.
+// FP64 matrix by the recheck kernel after each window's launch; degenerate
+// FP32 tests are re-run too.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1411,6 +1411,7 @@ struct PlanArgs {
     int64_t *off;                   // n_edges + 1 exclusive prefix of items per edge
     int64_t *n_items;               // total items of the window
     unsigned long long *item_ctr;   // zeroed for the window's test kernel
+    unsigned long long *queue_len;  // recheck queue of the previous launch, emptied
 };
 
 constexpr int kPlanPer = 8;                 // edges per thread
@@ -1478,6 +1479,7 @@ __global__ __launch_bounds__(256) void plan_sums(PlanArgs P, int nb)
         P.off[P.n_edges] = carry;
         *P.n_items = carry;
         *P.item_ctr = 0;
+        *P.queue_len = 0;
     }
 }
 
@@ -1849,6 +1851,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             P.off = pl + 2 + nb;
             P.n_items = pl;
             P.item_ctr = A.item_ctr;
+            P.queue_len = &Lv.counters[1];
             A.edges = P.edges;
             A.minhit = Lv.minhit + k.begin;
             A.n_edges = Ek;
@@ -1896,21 +1899,20 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                              "grid %u, items <= %lld\n", l, w, (int)(&k - cls.data()), (int)k.kind, k.max_m, k.shm,
                              k.pdec_n, g_last_grid, (long long)ub);
             ++nlaunch;
+            // FP64 re-run of this launch's queue (level edge indices);
+            // the next plan empties it
+            if (fp32 && err == hipSuccess) {
+                LevelArgs Q = A;
+                Q.edges = Lv.edges;
+                Q.minhit = Lv.minhit;
+                Q.n_edges = E;
+                Q.edge_base = 0;
+                Q.max_m = Lv.max_m;
+                launch_recheck(l, st, Q);
+            }
             if (err == hipSuccess) err = hipGetLastError();
             if (err != hipSuccess) break;
         }
-    }
-    // one FP64 pass over the whole level's queue: the windows' plans read a
-    // minhit that a pending recheck may still lower, which only keeps an
-    // edge live for longer; the level's result is the same
-    if (fp32 && err == hipSuccess) {
-        A.edges = Lv.edges;
-        A.minhit = Lv.minhit;
-        A.n_edges = E;
-        A.edge_base = 0;
-        A.max_m = Lv.max_m;
-        launch_recheck(l, st, A);
-        err = hipGetLastError();
     }
     if (graph) {
         const hipError_t e2 = hipStreamEndCapture(st, &g);
@@ -1941,6 +1943,25 @@ int level_timing(fpc_ctx *ctx, LevelTiming *timing)
         timing->test_ms += ms;
     }
     if (timing->graph) timing->test_ms = timing->all_ms;  // one graph: plans and rechecks included
+    return FPC_OK;
+}
+
+// minhit[e] = no hit yet (all ones), counters zeroed: one small kernel in
+// place of two memset commands.
+__global__ __launch_bounds__(256) void level_init_kernel(uint64_t *__restrict__ minhit, int64_t n_edges,
+                                                         unsigned long long *__restrict__ counters, int n_cnt)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < n_edges) minhit[t] = ~0ull;
+    if (t < n_cnt) counters[t] = 0ull;
+}
+
+int level_init(fpc_ctx *ctx, uint64_t *minhit, int64_t n_edges, unsigned long long *counters, int n_cnt)
+{
+    const int64_t n = std::max<int64_t>(n_edges, n_cnt);
+    if (n > 0)
+        level_init_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(minhit, n_edges, counters, n_cnt);
+    FPC_HIP(hipGetLastError());
     return FPC_OK;
 }
 

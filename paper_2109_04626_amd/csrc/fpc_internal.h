@@ -177,6 +177,9 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &L, const std::vector<int64_t> &
                 LevelTiming *timing);
 // Reads the timings of the last level_tests once its work has completed.
 int level_timing(fpc_ctx *ctx, LevelTiming *timing);
+// Queues minhit[e] = all ones (no hit) for the level's edges and zeroes
+// the n_cnt counters.
+int level_init(fpc_ctx *ctx, uint64_t *minhit, int64_t n_edges, unsigned long long *counters, int n_cnt);
 // Queues the compaction of the level's hits and its copy into host memory
 // h (pinned, 2 * n_edges + 2 int64): after a stream synchronisation h[0]
 // is the number of deletions and h[2 + 2t], h[3 + 2t] the t-th (edge, rank).

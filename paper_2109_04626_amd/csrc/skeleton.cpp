@@ -287,7 +287,12 @@ extern "C" void fpc_result_free(fpc_result *r)
 
 namespace {
 
-constexpr int64_t kQueueCap = 1 << 23;  // recheck queue entries
+// Recheck queue entries: the queue starts at kQueueCap entries (128 MB)
+// and, when a launch overflows it, grows 4x (up to kQueueCapMax, 4 GB) and
+// the level is run again in the mixed form; past that the level runs in
+// FP64.  The grown size stays with the context.
+constexpr int64_t kQueueCap = 1 << 23;
+constexpr int64_t kQueueCapMax = 1 << 28;
 
 struct Run {
     fpc_ctx *ctx;
@@ -463,6 +468,7 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     if ((rc = ctx->counters.ensure(sizeof(unsigned long long) * (8 + 2 * (size_t)ni)))) return rc;
     FPC_HIP(hipMemcpyAsync(ctx->edges.ptr, hrec, sizeof(EdgeRec) * E, hipMemcpyHostToDevice, s));
     if (T) FPC_HIP(hipMemcpyAsync(ctx->cand.ptr, cand, sizeof(int32_t) * T, hipMemcpyHostToDevice, s));
+
     // learned order: features, MLP scores, per-edge reorder of the lists
     // (at l = 0 each edge has one subset, so the order cannot matter)
     Run &R0 = *runs[0];
@@ -504,11 +510,13 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
         insts[k] = LevelInst{R.C32, R.C64, R.p, R.n, R.q, R.c_err};
     }
     bool fp32 = R0.mixed && l <= kMaxTemplL;
-    if (fp32 && (rc = ctx->queue.ensure(sizeof(int64_t) * 2 * kQueueCap))) return rc;
+    int64_t qcap = std::max<int64_t>(kQueueCap, (int64_t)(ctx->queue.bytes / (2 * sizeof(int64_t))));
+    if (fp32 && (rc = ctx->queue.ensure(sizeof(int64_t) * 2 * qcap))) return rc;
     const size_t n_cnt = 8 + 2 * (size_t)ni;
     // pinned landing area of the level's results: deletions, then counters
     if ((rc = ctx->h_back.ensure(sizeof(int64_t) * (2 * (size_t)E + 2) + sizeof(unsigned long long) * n_cnt)))
         return rc;
+
     int64_t *h_del = ctx->h_back.as<int64_t>();
     const unsigned long long *cnt = reinterpret_cast<const unsigned long long *>(h_del + 2 * E + 2);
     LevelLaunch Lv{};
@@ -517,8 +525,8 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     int64_t ndel = 0;
     double t_tests0 = 0.0, t_tests1 = 0.0;
 retry:
-    FPC_HIP(hipMemsetAsync(ctx->minhit.ptr, 0xff, sizeof(uint64_t) * E, s));
-    FPC_HIP(hipMemsetAsync(ctx->counters.ptr, 0, sizeof(unsigned long long) * n_cnt, s));
+    if ((rc = level_init(ctx, ctx->minhit.as<uint64_t>(), E, ctx->counters.as<unsigned long long>(), (int)n_cnt)))
+        return rc;
     Lv.l = l;
     Lv.max_m = sel_max_m;
     Lv.n_edges = E;
@@ -535,7 +543,7 @@ retry:
     Lv.counters = ctx->counters.as<unsigned long long>();
     Lv.inst_cnt = Lv.counters + 8;
     Lv.queue = fp32 ? ctx->queue.as<int64_t>() : nullptr;
-    Lv.queue_cap = fp32 ? kQueueCap : 0;
+    Lv.queue_cap = fp32 ? qcap : 0;
     t_tests0 = now_ms();
     if ((rc = level_tests(ctx, Lv, ntests, &tm))) return rc;
     // the host decodes separating sets against the lists the level used
@@ -554,8 +562,15 @@ retry:
         sts[k].tests_rechecked += (int64_t)cnt[8 + 2 * k + 1];
         runs[k]->total_exec += (int64_t)cnt[8 + 2 * k];
     }
-    if (cnt[3]) {  // the recheck queue overflowed: run the whole level again in FP64
-        fp32 = false;
+    if (cnt[3]) {  // the recheck queue overflowed: run the whole level again
+        if (qcap < kQueueCapMax && ctx->queue.ensure(sizeof(int64_t) * 2 * qcap * 4) == FPC_OK) {
+            qcap *= 4;
+        } else {
+            fp32 = false;
+        }
+        if (trace_on())
+            std::fprintf(stderr, "[fpc] level %d: recheck queue overflow, level re-run %s\n", l,
+                         fp32 ? "with a 4x queue" : "in FP64");
         goto retry;
     }
     for (int k = 0; k < ni; ++k) sts[k].tests_required = sts[k].tests_possible;
@@ -643,7 +658,7 @@ retry:
         std::fprintf(stderr,
                      "[fpc] level %d: %d instance(s) %lld edges %lld candidates %d classes | setup %.2f upload+order "
                      "%.2f tests and compaction %.2f (device %.2f) counts %.2f decode %.2f ms | deleted %lld, "
-                     "queued for FP64 %llu\n",
+                     "queued for FP64 in the last launch %llu\n",
                      l, ni, (long long)E, (long long)T, (int)classes.size(), t_build - t0, t_tests0 - t_build,
                      t_tests1 - t_tests0, tm.all_ms, t_decode - t_tests1, now_ms() - t_decode, (long long)ndel,
                      fp32 ? cnt[1] : 0ull);

@@ -248,6 +248,18 @@ int fpc_get_tuning(const fpc_ctx *ctx, fpc_tuning *out);
 /* FPC_EINVAL for a value out of range (the context keeps its table). */
 int fpc_set_tuning(fpc_ctx *ctx, const fpc_tuning *t);
 
+/* ------------------------------------------------------------- recheck queue
+ * Mixed form (FPC_PREC_MIXED): FP32 tests whose decision lies within the
+ * error band of the threshold are queued and re-run in FP64 after each
+ * launch (Sec. 2.2.2 decides the test; the band is a precision design).
+ * The queue starts at `initial` entries (16 bytes each; default 2^23) and,
+ * when a launch overflows it, grows 4x up to `max` entries (default 2^28)
+ * and the level runs again in the mixed form; an overflow at `max` runs the
+ * level in FP64.  Results never depend on these sizes.  Takes effect at the
+ * next level run (the current queue is released).  FPC_EINVAL unless
+ * 1 <= initial <= max <= 2^31. */
+int fpc_set_recheck_queue(fpc_ctx *ctx, int64_t initial, int64_t max);
+
 /* ------------------------------------------------------------- many instances
  * Runs the skeleton of several independent problems (bootstrap resamples of
  * one data set, separate data sets of uneven p) together: correlation and

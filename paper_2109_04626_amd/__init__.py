@@ -2,8 +2,8 @@
 
 Argument marshalling only: every step of the skeleton runs in the HIP
 library.  PyTorch provides device memory and the stream.  Importing this
-module fails if the library has not been built (python -m
-paper_2109_04626_amd.build); there is no CPU fallback.
+module fails if the library has not been built (python
+paper_2109_04626_amd/build.py); there is no CPU fallback.
 """
 from __future__ import annotations
 
@@ -31,7 +31,8 @@ FPC_FLAG_GRAPH = 4
 EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "fpc_quantile",
             "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton", "fpc_skeleton_batch",
             "fpc_result_free", "fpc_orient", "fpc_mlp_bytes", "fpc_mlp_params", "fpc_mlp_init", "fpc_mlp_get",
-            "fpc_mlp_forward", "fpc_mlp_grad", "fpc_mlp_train_step", "fpc_get_tuning", "fpc_set_tuning"]
+            "fpc_mlp_forward", "fpc_mlp_grad", "fpc_mlp_train_step", "fpc_get_tuning", "fpc_set_tuning",
+            "fpc_set_recheck_queue"]
 FPC_TUNE_LEVELS = 17
 TUNING_FIELDS = ("test_ranks_per_wave", "shared_ranks_per_wave", "window_growth", "first_window_items",
                  "max_blocks_per_cu", "shared_prefix_depth")
@@ -98,7 +99,7 @@ def _load():
     import torch  # noqa: F401
 
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2109_04626_amd.build")
+        raise ImportError(f"{LIB_PATH} is missing: build it with python paper_2109_04626_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     lib.fpc_create.argtypes = [ctypes.POINTER(vp), i, vp]
@@ -128,6 +129,8 @@ def _load():
     lib.fpc_get_tuning.restype = i
     lib.fpc_set_tuning.argtypes = [vp, ctypes.POINTER(fpc_tuning)]
     lib.fpc_set_tuning.restype = i
+    lib.fpc_set_recheck_queue.argtypes = [vp, i64, i64]
+    lib.fpc_set_recheck_queue.restype = i
     lib.fpc_result_free.argtypes = [ctypes.POINTER(fpc_result)]
     lib.fpc_result_free.restype = None
     lib.fpc_orient.argtypes = [i, vp, vp, vp, vp, vp, vp]
@@ -272,6 +275,12 @@ def fpc_get_tuning(ctx: Context) -> dict:
     t = fpc_tuning()
     _check(_lib.fpc_get_tuning(ctx.handle, ctypes.byref(t)), "fpc_get_tuning")
     return {f: list(getattr(t, f)) for f in TUNING_FIELDS}
+
+
+def fpc_set_recheck_queue(ctx: Context, initial: int = 1 << 23, maximum: int = 1 << 28) -> None:
+    """First and largest size (entries) of the mixed form's FP64 recheck
+    queue; results do not depend on them."""
+    _check(_lib.fpc_set_recheck_queue(ctx.handle, int(initial), int(maximum)), "fpc_set_recheck_queue")
 
 
 def fpc_set_tuning(ctx: Context, tuning) -> None:

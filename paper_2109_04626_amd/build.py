@@ -1,6 +1,6 @@
 """Build libfastpc.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2109_04626_amd.build
+    python paper_2109_04626_amd/build.py
 """
 from __future__ import annotations
 

@@ -56,6 +56,8 @@ struct fpc_ctx {
     bool use_pair_kernel = true; // shared-prefix kernel for levels l >= 2 (off with FPC_FLAG_PER_TEST_KERNEL)
     int num_cus = 256;
     fpc_tuning tuning{};          // launch shapes of the level kernels (fpc_set_tuning)
+    int64_t queue_init = int64_t(1) << 23;  // recheck queue entries: first size and cap
+    int64_t queue_max = int64_t(1) << 28;   // (fpc_set_recheck_queue)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     static constexpr int kLaunchEvents = 256;
     hipEvent_t lev[2 * kLaunchEvents] = {};  // per-launch timing of the test kernels

@@ -268,6 +268,15 @@ extern "C" int fpc_destroy(fpc_ctx *c)
     return FPC_OK;
 }
 
+extern "C" int fpc_set_recheck_queue(fpc_ctx *ctx, int64_t initial, int64_t max)
+{
+    if (!ctx || initial < 1 || max < initial || max > (int64_t(1) << 31)) return FPC_EINVAL;
+    ctx->queue_init = initial;
+    ctx->queue_max = max;
+    ctx->queue.release();
+    return FPC_OK;
+}
+
 extern "C" void fpc_result_free(fpc_result *r)
 {
     if (!r) return;
@@ -287,12 +296,10 @@ extern "C" void fpc_result_free(fpc_result *r)
 
 namespace {
 
-// Recheck queue entries: the queue starts at kQueueCap entries (128 MB)
-// and, when a launch overflows it, grows 4x (up to kQueueCapMax, 4 GB) and
-// the level is run again in the mixed form; past that the level runs in
-// FP64.  The grown size stays with the context.
-constexpr int64_t kQueueCap = 1 << 23;
-constexpr int64_t kQueueCapMax = 1 << 28;
+// Recheck queue entries: the queue starts at ctx->queue_init entries and,
+// when a launch overflows it, grows 4x (up to ctx->queue_max) and the level
+// is run again in the mixed form; past that the level runs in FP64.  The
+// grown size stays with the context.
 
 struct Run {
     fpc_ctx *ctx;
@@ -510,7 +517,7 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
         insts[k] = LevelInst{R.C32, R.C64, R.p, R.n, R.q, R.c_err};
     }
     bool fp32 = R0.mixed && l <= kMaxTemplL;
-    int64_t qcap = std::max<int64_t>(kQueueCap, (int64_t)(ctx->queue.bytes / (2 * sizeof(int64_t))));
+    int64_t qcap = std::max<int64_t>(ctx->queue_init, (int64_t)(ctx->queue.bytes / (2 * sizeof(int64_t))));
     if (fp32 && (rc = ctx->queue.ensure(sizeof(int64_t) * 2 * qcap))) return rc;
     const size_t n_cnt = 8 + 2 * (size_t)ni;
     // pinned landing area of the level's results: deletions, then counters
@@ -563,8 +570,9 @@ retry:
         runs[k]->total_exec += (int64_t)cnt[8 + 2 * k];
     }
     if (cnt[3]) {  // the recheck queue overflowed: run the whole level again
-        if (qcap < kQueueCapMax && ctx->queue.ensure(sizeof(int64_t) * 2 * qcap * 4) == FPC_OK) {
-            qcap *= 4;
+        const int64_t grown = std::min(qcap * 4, ctx->queue_max);
+        if (grown > qcap && ctx->queue.ensure(sizeof(int64_t) * 2 * grown) == FPC_OK) {
+            qcap = grown;
         } else {
             fp32 = false;
         }

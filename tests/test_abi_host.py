@@ -24,7 +24,7 @@ def _declared():
 
 
 def test_library_exports_every_declared_symbol():
-    assert os.path.exists(LIB), "build the library first (python -m paper_2109_04626_amd.build)"
+    assert os.path.exists(LIB), "build the library first (python paper_2109_04626_amd/build.py)"
     lib = ctypes.CDLL(LIB)
     names = _declared()
     assert len(names) >= 10

@@ -87,3 +87,29 @@ def test_shipped_table_loads(fpc):
         tab = json.load(f)["tuning"]
     with fpc.Context(0) as c:
         assert fpc.fpc_get_tuning(c) == {k: list(v) for k, v in tab.items()}
+
+
+def test_recheck_queue_sizes_do_not_change_results(fpc):
+    """A tiny recheck queue overflows: the level runs again with a 4x queue
+    (still mixed), and past the cap in FP64; the results stay the same."""
+    p, n = 90, 3000
+    _say(f"[recheck queue] p={p} n={n}")
+    sem = semdata.make_sem(p, 52, degree=5.0)
+    X = semdata.sample(sem, n, 52)
+    ref = oracle.skeleton(oracle.corr(X), n, alpha=0.01, max_level=6)
+    Xd = torch.from_numpy(X).cuda()
+    kw = dict(alpha=0.01, max_level=6, precision=fpc.FPC_PREC_MIXED, recheck_margin=0.5)  # a wide band
+    with fpc.Context(0) as c:
+        base = fpc.fpc_skeleton(c, Xd, **kw)
+        assert sum(x["tests_rechecked"] for x in base["levels"]) > 1000
+        assert np.array_equal(base["adj"], ref["adj"])
+        for init, cap in ((16, 1 << 20), (16, 64)):  # growth in the mixed form; the cap, then FP64
+            fpc.fpc_set_recheck_queue(c, init, cap)
+            got = fpc.fpc_skeleton(c, Xd, **kw)
+            assert got["total_tests"] > base["total_tests"]  # the overflowed launches ran too
+            assert np.array_equal(got["adj"], ref["adj"])
+            assert np.array_equal(got["sep_level"], base["sep_level"])
+            assert got["sepsets"] == base["sepsets"]
+        for bad in ((0, 10), (10, 5), (1, 1 << 40)):
+            with pytest.raises(fpc.FastPCError):
+                fpc.fpc_set_recheck_queue(c, *bad)

@@ -255,20 +255,34 @@ __global__ __launch_bounds__(256) void syrk_bf16x3(const __bf16 *__restrict__ Zh
             for (int r = 0; r < 4; ++r) sum[g][h][r] = 0.0;
         }
     const bf16x8 zero = {};
+    // operand fragments of the next 32-sample step are loaded while the
+    // current step's products run
+    bf16x8 nah[2], nal[2], nbh[2], nbl[2];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const bool okA = rowA[g] < p && k0 < k_hi, okB = rowB[g] < p && k0 < k_hi;
+            const size_t oA = (size_t)rowA[g] * npad + k0 + koff;
+            const size_t oB = (size_t)rowB[g] * npad + k0 + koff;
+            nah[g] = okA ? *reinterpret_cast<const bf16x8 *>(Zh + oA) : zero;
+            nal[g] = okA ? *reinterpret_cast<const bf16x8 *>(Zl + oA) : zero;
+            nbh[g] = okB ? *reinterpret_cast<const bf16x8 *>(Zh + oB) : zero;
+            nbl[g] = okB ? *reinterpret_cast<const bf16x8 *>(Zl + oB) : zero;
+        }
+    };
+    fetch(k_lo);
     for (int kc = k_lo; kc < k_hi; kc += kFold) {
         const int kend = min(k_hi, kc + kFold);
         for (int k0 = kc; k0 < kend; k0 += 32) {
             bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
-                const bool okA = rowA[g] < p, okB = rowB[g] < p;
-                const size_t oA = (size_t)rowA[g] * npad + k0 + koff;
-                const size_t oB = (size_t)rowB[g] * npad + k0 + koff;
-                ah[g] = okA ? *reinterpret_cast<const bf16x8 *>(Zh + oA) : zero;
-                al[g] = okA ? *reinterpret_cast<const bf16x8 *>(Zl + oA) : zero;
-                bh[g] = okB ? *reinterpret_cast<const bf16x8 *>(Zh + oB) : zero;
-                bl[g] = okB ? *reinterpret_cast<const bf16x8 *>(Zl + oB) : zero;
+                ah[g] = nah[g];
+                al[g] = nal[g];
+                bh[g] = nbh[g];
+                bl[g] = nbl[g];
             }
+            fetch(k0 + 32);
 #pragma unroll
             for (int g = 0; g < 2; ++g)
 #pragma unroll

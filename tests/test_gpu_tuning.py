@@ -98,10 +98,10 @@ def test_recheck_queue_sizes_do_not_change_results(fpc):
     X = semdata.sample(sem, n, 52)
     ref = oracle.skeleton(oracle.corr(X), n, alpha=0.01, max_level=6)
     Xd = torch.from_numpy(X).cuda()
-    kw = dict(alpha=0.01, max_level=6, precision=fpc.FPC_PREC_MIXED, recheck_margin=0.5)  # a wide band
+    kw = dict(alpha=0.01, max_level=6, precision=fpc.FPC_PREC_MIXED, recheck_margin=3.0)  # a wide band
     with fpc.Context(0) as c:
         base = fpc.fpc_skeleton(c, Xd, **kw)
-        assert sum(x["tests_rechecked"] for x in base["levels"]) > 1000
+        assert sum(x["tests_rechecked"] for x in base["levels"]) > 200
         assert np.array_equal(base["adj"], ref["adj"])
         for init, cap in ((16, 1 << 20), (16, 64)):  # growth in the mixed form; the cap, then FP64
             fpc.fpc_set_recheck_queue(c, init, cap)

@@ -1505,6 +1505,43 @@ __global__ __launch_bounds__(256) void plan_scan(PlanArgs P)
     }
 }
 
+// The three plan passes in one workgroup, for classes of at most
+// kPlanSingle chunks: the chunks are scanned one after the other with a
+// running carry.
+constexpr int kPlanSingle = 8;
+
+__global__ __launch_bounds__(256) void plan_single(PlanArgs P)
+{
+    int64_t carry = 0;
+    for (int64_t base0 = 0; base0 < P.n_edges; base0 += kPlanChunk) {
+        const int64_t base = base0 + (int64_t)threadIdx.x * kPlanPer;
+        int64_t v[kPlanPer];
+        int64_t s = 0;
+#pragma unroll
+        for (int t = 0; t < kPlanPer; ++t) {
+            const int64_t e = base + t;
+            v[t] = e < P.n_edges ? window_items(P.edges[e], P.minhit[e], P.lo, P.hi, P.rpb, P.filter) : 0;
+            s += v[t];
+        }
+        int64_t ex;
+        const int64_t tot = block_exclusive_scan(s, ex);
+        int64_t run = carry + ex;
+#pragma unroll
+        for (int t = 0; t < kPlanPer; ++t) {
+            const int64_t e = base + t;
+            if (e < P.n_edges) P.off[e] = run;
+            run += v[t];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        P.off[P.n_edges] = carry;
+        *P.n_items = carry;
+        *P.item_ctr = 0;
+        *P.queue_len = 0;
+    }
+}
+
 // ------------------------------------------------------------------ compaction
 __global__ __launch_bounds__(256) void compact_kernel(const uint64_t *__restrict__ minhit, int64_t n,
                                                       int64_t *__restrict__ out, unsigned long long *__restrict__ cnt)
@@ -1862,9 +1899,13 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             A.edge_base = k.begin;
             A.max_m = k.max_m;
             A.pdec_n = k.pdec_n;
-            plan_reduce<<<(unsigned)nb, 256, 0, st>>>(P);
-            plan_sums<<<1, 256, 0, st>>>(P, (int)nb);
-            plan_scan<<<(unsigned)nb, 256, 0, st>>>(P);
+            if (nb <= kPlanSingle) {
+                plan_single<<<1, 256, 0, st>>>(P);
+            } else {
+                plan_reduce<<<(unsigned)nb, 256, 0, st>>>(P);
+                plan_sums<<<1, 256, 0, st>>>(P, (int)nb);
+                plan_scan<<<(unsigned)nb, 256, 0, st>>>(P);
+            }
             const bool timed = !graph && nev < fpc_ctx::kLaunchEvents;
             if (timed) (void)hipEventRecord(ctx->lev[2 * nev], st);
             switch (k.kind) {

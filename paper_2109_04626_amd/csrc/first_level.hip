@@ -31,47 +31,83 @@ namespace {
 constexpr int kNB = 32;  // panel width and tile size
 
 // Gauss-Jordan inverse of the nb x nb block P (LDS, kNB x kNB tile) by a
-// 256-thread block, thread (ty, tx) owning rows ty + 8q of column tx.  The
-// next pivot row and column are published into a second buffer by the
-// threads that compute them, so each step needs one barrier.  Writes the
-// whole kNB x kNB result (zero outside nb) to Pinv.
-__device__ void tile_inverse(double (*P)[kNB + 1], double (*rowk)[kNB], double (*colk)[kNB], int nb,
+// 256-thread block, thread (ty, tx) owning rows ty + 8q of column tx.  Two
+// pivots per step: the 2 x 2 pivot block K2 = {t, t+1} is inverted in
+// closed form and eliminated as one block (the sweep formulas above with a
+// panel of two), with a single pivot for an odd last one.  The next step's
+// pivot rows and columns are published into a second buffer by the threads
+// that compute them, so each step needs one barrier.  Writes the whole
+// kNB x kNB result (zero outside nb) to Pinv.
+__device__ void tile_inverse(double (*P)[kNB + 1], double (*rowk)[2][kNB], double (*colk)[2][kNB], int nb,
                              double *__restrict__ Pinv, int *__restrict__ bad)
 {
     const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;
     double v[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) v[q] = P[ty + 8 * q][tx];
-    // step 0's pivot row and column
+    // the first step's pivot rows and columns
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int r = ty + 8 * q;
-        if (r == 0) rowk[0][tx] = v[q];
-        if (tx == 0) colk[0][r] = v[q];
+        if (r < 2) rowk[0][r][tx] = v[q];
+        if (tx < 2) colk[0][tx][r] = v[q];
     }
     __syncthreads();
     bool ok = true;
-    for (int t = 0; t < nb; ++t) {
-        // every LDS read of the step first, then select-only updates: one
-        // read latency and one barrier per step
-        const int b = t & 1;
-        const double piv = rowk[b][t], rt = rowk[b][tx];
-        double ct[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ct[q] = colk[b][ty + 8 * q];
-        ok = ok && piv > 0.0;
-        const double ip = 1.0 / piv;
-        const double rti = rt * ip;
+    int b = 0;
+    for (int t = 0; t < nb;) {
+        const bool two = t + 1 < nb;  // uniform
+        const int c = tx;
+        const double r1 = rowk[b][0][c], r2 = rowk[b][1][c];
+        double c1[4], c2[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = ty + 8 * q, c = tx;
-            double nv = fma(-ct[q], rti, v[q]);  // r != t, c != t
-            nv = c == t ? -ct[q] * ip : nv;
-            nv = r == t ? rti : nv;
-            nv = (r == t && c == t) ? ip : nv;
-            v[q] = (r < nb && c < nb) ? nv : v[q];
-            if (r == t + 1) rowk[b ^ 1][c] = v[q];
-            if (c == t + 1) colk[b ^ 1][r] = v[q];
+            c1[q] = colk[b][0][ty + 8 * q];
+            c2[q] = colk[b][1][ty + 8 * q];
+        }
+        if (two) {
+            const double a = rowk[b][0][t], bt = rowk[b][0][t + 1], ct = rowk[b][1][t], d = rowk[b][1][t + 1];
+            const double det = a * d - bt * ct;
+            ok = ok && a > 0.0 && det > 0.0;
+            const double idet = 1.0 / det;
+            const double i00 = d * idet, i01 = -bt * idet, i10 = -ct * idet, i11 = a * idet;
+            const double u1 = fma(i00, r1, i01 * r2), u2 = fma(i10, r1, i11 * r2);  // inv(K2) A[K2, c]
+            const bool inC = c == t || c == t + 1;
+            const double ic0 = c == t ? i00 : i01, ic1 = c == t ? i10 : i11;   // column c - t of inv(K2)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = ty + 8 * q;
+                const bool inR = r == t || r == t + 1;
+                double nv = fma(-c1[q], u1, fma(-c2[q], u2, v[q]));
+                nv = inC ? -fma(c1[q], ic0, c2[q] * ic1) : nv;
+                nv = inR ? (r == t ? u1 : u2) : nv;
+                nv = (inR && inC) ? (r == t ? ic0 : ic1) : nv;
+                v[q] = (r < nb && c < nb) ? nv : v[q];
+            }
+            t += 2;
+        } else {
+            const double piv = rowk[b][0][t];
+            ok = ok && piv > 0.0;
+            const double ip = 1.0 / piv, rti = r1 * ip;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = ty + 8 * q;
+                double nv = fma(-c1[q], rti, v[q]);
+                nv = c == t ? -c1[q] * ip : nv;
+                nv = r == t ? rti : nv;
+                nv = (r == t && c == t) ? ip : nv;
+                v[q] = (r < nb && c < nb) ? nv : v[q];
+            }
+            t += 1;
+        }
+        b ^= 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ty + 8 * q;
+            if (r == t) rowk[b][0][c] = v[q];
+            if (r == t + 1) rowk[b][1][c] = v[q];
+            if (c == t) colk[b][0][r] = v[q];
+            if (c == t + 1) colk[b][1][r] = v[q];
         }
         __syncthreads();
     }
@@ -101,7 +137,7 @@ __global__ __launch_bounds__(256) void sweep_panel(const double *__restrict__ Ai
     __shared__ double Ps[kNB][kNB + 1];
     __shared__ double Us[kNB][kNB + 1];
     __shared__ double Vs[kNB][kNB + 1];
-    __shared__ double rowk[2][kNB], colk[2][kNB];
+    __shared__ double rowk[2][2][kNB], colk[2][2][kNB];
     const int i0 = blockIdx.y * kNB, j0 = blockIdx.x * kNB;
     const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;  // 32 x 8
     const int j = j0 + tx;
@@ -168,7 +204,7 @@ __global__ __launch_bounds__(256) void first_tile_inverse(const double *__restri
                                                           double *__restrict__ Pinv, int *__restrict__ bad)
 {
     __shared__ double Ps[kNB][kNB + 1];
-    __shared__ double rowk[2][kNB], colk[2][kNB];
+    __shared__ double rowk[2][2][kNB], colk[2][2][kNB];
     const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {

@@ -25,13 +25,10 @@ struct Adjacency {
     std::vector<int32_t> eu, ev;        // endpoints of edge id (eu < ev)
 };
 
-void build_adjacency(const uint8_t *adj, int p, Adjacency &g)
+// Edges (u < v) of rows [u0, u1), in row-major order.
+void scan_rows(const uint8_t *adj, int p, int u0, int u1, std::vector<int32_t> &eu, std::vector<int32_t> &ev)
 {
-    // one pass over the upper triangle: edge ids in row-major (u < v) order
-    g.eu.clear();
-    g.ev.clear();
-    std::vector<int32_t> deg(p, 0);
-    for (int u = 0; u < p; ++u) {
+    for (int u = u0; u < u1; ++u) {
         const uint8_t *row = adj + (size_t)u * p;
         int v = u + 1;
         // eight entries at a time: nz has the top bit of every nonzero byte
@@ -41,21 +38,53 @@ void build_adjacency(const uint8_t *adj, int p, Adjacency &g)
             std::memcpy(&word, row + v, 8);
             uint64_t nz = (((word & lo7) + lo7) | word) & ~lo7;
             while (nz) {
-                const int w = v + (__builtin_ctzll(nz) >> 3);
-                g.eu.push_back(u);
-                g.ev.push_back(w);
-                ++deg[u];
-                ++deg[w];
+                eu.push_back(u);
+                ev.push_back(v + (__builtin_ctzll(nz) >> 3));
                 nz &= nz - 1;
             }
         }
         for (; v < p; ++v)
             if (row[v]) {
-                g.eu.push_back(u);
-                g.ev.push_back(v);
-                ++deg[u];
-                ++deg[v];
+                eu.push_back(u);
+                ev.push_back(v);
             }
+    }
+}
+
+void build_adjacency(const uint8_t *adj, int p, Adjacency &g, int nth)
+{
+    // one pass over the upper triangle: edge ids in row-major (u < v) order;
+    // for large p, blocks of rows (of about equal upper-triangle size) on
+    // separate host threads, concatenated in row order
+    g.eu.clear();
+    g.ev.clear();
+    if (nth <= 1 || p < 512) {
+        scan_rows(adj, p, 0, p, g.eu, g.ev);
+    } else {
+        std::vector<int> r0(nth + 1, p);
+        r0[0] = 0;
+        const double tri = 0.5 * (double)p * (p - 1);
+        int b = 1;
+        double acc = 0.0;
+        for (int u = 0; u < p && b < nth; ++u) {
+            acc += p - 1 - u;
+            if (acc >= tri * b / nth) r0[b++] = u + 1;
+        }
+        std::vector<std::vector<int32_t>> pu(nth), pv(nth);
+        host_parallel(nth, [&](int t) { scan_rows(adj, p, r0[t], r0[t + 1], pu[t], pv[t]); });
+        size_t tot = 0;
+        for (int t = 0; t < nth; ++t) tot += pu[t].size();
+        g.eu.reserve(tot);
+        g.ev.reserve(tot);
+        for (int t = 0; t < nth; ++t) {
+            g.eu.insert(g.eu.end(), pu[t].begin(), pu[t].end());
+            g.ev.insert(g.ev.end(), pv[t].begin(), pv[t].end());
+        }
+    }
+    std::vector<int32_t> deg(p, 0);
+    for (size_t id = 0; id < g.eu.size(); ++id) {
+        ++deg[g.eu[id]];
+        ++deg[g.ev[id]];
     }
     g.off.assign(p + 1, 0);
     for (int u = 0; u < p; ++u) g.off[u + 1] = g.off[u] + deg[u];
@@ -136,7 +165,7 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
     };
     const auto t0 = clk::now();
     Adjacency g;
-    build_adjacency(adj, p, g);
+    build_adjacency(adj, p, g, threads > 0 ? threads : host_threads());
     const auto t1 = clk::now();
     std::vector<int32_t> block;
     edge_blocks(g, p, block);

@@ -53,7 +53,7 @@ def _random_graph(rng, p, dens):
     return (u | u.T).astype(np.uint8)
 
 
-@pytest.mark.parametrize("p,dens", [(5, 0.5), (8, 0.4), (12, 0.25), (30, 0.1), (60, 0.06), (200, 0.02)])
+@pytest.mark.parametrize("p,dens", [(5, 0.5), (8, 0.4), (12, 0.25), (30, 0.1), (60, 0.06), (200, 0.02), (530, 0.006)])
 def test_candidate_sets_match_oracle_bfs(p, dens):
     import paper_2109_04626_amd as fpc
 

@@ -232,40 +232,6 @@ __device__ __forceinline__ void unrank(int64_t R, int m, const int64_t *__restri
     }
 }
 
-// The same unranking by a whole wave (R and m uniform over the wave): for
-// each element the lanes try 64 consecutive positions at once.  With
-// F(x) = sum_{y=x0..x} C(m-1-y, r) = C(m-x0, r+1) - C(m-1-x, r+1) (hockey
-// stick), the element is the first x with R < F(x) and the rank left is
-// R - F(x-1): one round of parallel table reads per element instead of a
-// chain of dependent ones.
-template <int L>
-__device__ __forceinline__ void unrank_wave(int64_t R, int m, const int64_t *__restrict__ binom, int *c)
-{
-    const int lane = threadIdx.x % 64;
-    int x0 = 0;
-#pragma unroll
-    for (int t = 0; t < L; ++t) {
-        const int r = L - 1 - t;
-        for (;;) {
-            const int64_t top = binom_at(binom, m - x0, r + 1);  // F(x) = top - C(m-1-x, r+1)
-            const int x = x0 + lane;
-            const int64_t Fx = top - binom_at(binom, m - 1 - x, r + 1);
-            const unsigned long long hit = __ballot(R < Fx);
-            if (hit) {
-                const int k = __ffsll((long long)hit) - 1;  // the element is x0 + k
-                const int xk = x0 + k;
-                R -= top - binom_at(binom, m - xk, r + 1);  // R - F(xk - 1)
-                c[t] = xk;
-                x0 = xk + 1;
-                break;
-            }
-            // every lane's x has F(x) <= R: the element lies further on
-            R -= top - binom_at(binom, m - x0 - 64, r + 1);
-            x0 += 64;
-        }
-    }
-}
-
 // Given c = the combination at some rank b (wave-uniform), set my = the
 // combination at rank b + lane and advance c to rank b + 64.  Lanes past
 // the last combination keep the (valid) initial my.  Returns false when no
@@ -405,31 +371,16 @@ unsigned resident_grid(const void *fn, int threads, size_t shm, int64_t ub, int 
     return g_last_grid;
 }
 
-// The same search by a whole workgroup (b uniform): each round the threads
-// probe blockDim.x evenly spaced entries at once and keep the interval of
-// the last probe with off <= b (off is nondecreasing, so the probes that
-// pass form a prefix); two rounds cover 65536 edges.
-__device__ __forceinline__ int64_t find_edge_block(const int64_t *__restrict__ off, int64_t n, int64_t b)
+__device__ __forceinline__ int64_t find_edge(const int64_t *__restrict__ off, int64_t n, int64_t b)
 {
-    __shared__ int passed_w[kWaves];  // passing probes per wave
     int64_t lo = 0, hi = n;  // off[lo] <= b < off[hi]
-    const int nt = blockDim.x, nw = nt / 64;
     while (hi - lo > 1) {
-        const int64_t step = (hi - lo + nt - 1) / nt;
-        const int64_t idx = lo + (int64_t)threadIdx.x * step;
-        const unsigned long long bal = __ballot(idx < hi && off[idx] <= b);
-        if (threadIdx.x % 64 == 0) passed_w[threadIdx.x / 64] = __popcll(bal);
-        __syncthreads();
-        int passed = 0;
-        for (int w = 0; w < nw; ++w) passed += passed_w[w];
-        __syncthreads();  // passed_w is free for the next round
-        const int64_t nlo = lo + (int64_t)(passed - 1) * step;
-        hi = min(hi, nlo + step);
-        lo = nlo;
+        const int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid;
     }
     return lo;
 }
-
 
 // One row of the strict upper triangle per wave at a time, lanes along the
 // row (coalesced reads of C, consecutive LDS writes).
@@ -453,7 +404,7 @@ __device__ void stage_tile(const T *__restrict__ C, int p, const int32_t *__rest
 template <typename T, int L, bool TILE>
 __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsigned char *smem, ExecCount &ec)
 {
-    const int64_t e = find_edge_block(A.blockoff, A.n_edges, blk);
+    const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = E.m;
     const int64_t rpb = A.ranks_per_block, rpw = rpb / kWaves;
@@ -487,7 +438,7 @@ __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsi
     if (wlo < whi) {
         constexpr int LL = L > 0 ? L : 1;
         int c[LL], my[LL];
-        if constexpr (L > 0) unrank_wave<L>(wlo, m, A.binom, c);
+        if constexpr (L > 0) unrank<L>(wlo, m, A.binom, c);
         for (int64_t base = wlo; base < whi; base += 64) {
             const unsigned long long mh = (unsigned long long)uniform_i64((int64_t)load_minhit(&A.minhit[e]));
             if (mh < (unsigned long long)base) break;
@@ -688,7 +639,7 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
     using Lay = PairLayout<T, QL>;
     constexpr int L = QL + 2;
     constexpr int QLL = QL > 0 ? QL : 1;
-    const int64_t e = find_edge_block(A.blockoff, A.n_edges, blk);
+    const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = E.m;
     const int64_t rpb = A.ranks_per_block, rpw = rpb / kWaves;
@@ -722,7 +673,7 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
 
     // first test of the range: K = Q + {a, b}
     int c[L];
-    unrank_wave<L>(wlo, m, A.binom, c);
+    unrank<L>(wlo, m, A.binom, c);
     int Q[QLL];
 #pragma unroll
     for (int t = 0; t < QL; ++t) Q[t] = c[t];
@@ -976,7 +927,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
     using Lay = TripleLayout<T, QL>;
     constexpr int L = QL + 3;
     constexpr int QLL = QL > 0 ? QL : 1;
-    const int64_t e = find_edge_block(A.blockoff, A.n_edges, blk);
+    const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = uniform_i32(E.m);
     const int64_t rpb = A.ranks_per_block, rpw = rpb / kWaves;
@@ -1009,7 +960,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
 
     // the walk's position (Q, a, tau, rank) is the same in every lane
     int c[L];
-    unrank_wave<L>(wlo, m, A.binom, c);
+    unrank<L>(wlo, m, A.binom, c);
     int Q[QLL];
 #pragma unroll
     for (int t = 0; t < QL; ++t) Q[t] = uniform_i32(c[t]);
@@ -1362,7 +1313,7 @@ __device__ __forceinline__ void wide_item(const LevelArgs &A, int l, int64_t blk
 {
     T *M = reinterpret_cast<T *>(smem);
     int *k = reinterpret_cast<int *>(M + (size_t)(l + 2) * (l + 3) / 2 + 1);
-    const int64_t e = find_edge_block(A.blockoff, A.n_edges, blk);
+    const int64_t e = find_edge(A.blockoff, A.n_edges, blk);
     const EdgeRec E = A.edges[e];
     const int m = E.m;
     const int64_t r0 = A.win_lo + (blk - A.blockoff[e]) * A.ranks_per_block;

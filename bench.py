@@ -37,9 +37,9 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32
 # calibration (fetch x2.000, write x1.000).  Valid only for the kernel source
 # and launch table they were taken with: any change to either makes the
 # figure null until the counters are taken again.
-MEASURED_TRAFFIC = {"bytes_per_launch": 9258844.0,
+MEASURED_TRAFFIC = {"bytes_per_launch": 9254918.0,
                     "sha256": {"paper_2109_04626_amd/csrc/citest.hip":
-                               "e2d532774f39ef2e449da75466adcf2dcce25f7c68e5deabc532395648855e85",
+                               "ff21d421cadf70af3de407d490ea112fad92407f8d90cffe57960b2b41b6cd27",
                                "paper_2109_04626_amd/tuning_gfx950.json":
                                "9b5ee9cd8fc56c7307853a22b4732f84004d394956b92179119b5f35944c27e9"}}
 

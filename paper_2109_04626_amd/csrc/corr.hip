@@ -340,7 +340,8 @@ int splits_for(int tiles, int n, int num_cus)
 
 }  // namespace
 
-int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out, bool reuse_stats)
+int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out, bool reuse_stats,
+                 bool wait)
 {
     if (!X || !C_out || n < 2 || p < 1) return FPC_EINVAL;
     if (x_dtype != FPC_F64 && x_dtype != FPC_F32) return FPC_EINVAL;
@@ -397,9 +398,21 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
         normalize<float><<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(Spart, nsplit, p, (float *)C_out);
     }
     FPC_HIP(hipGetLastError());
+    return wait ? corr_check(ctx, nullptr) : FPC_OK;
+}
+
+int corr_check(fpc_ctx *ctx, double *max_abs_diff)
+{
+    // flag words: [0] non-finite input, [1] constant column; bytes 32..39 the
+    // largest |C64 - C32| as FP64 bits
+    int rc = ctx->h_flag.ensure(64);
+    if (rc) return rc;
+    char *h = ctx->h_flag.as<char>();
+    FPC_HIP(hipMemcpyAsync(h, ctx->flag.ptr, 40, hipMemcpyDeviceToHost, ctx->stream));
+    FPC_HIP(hipStreamSynchronize(ctx->stream));
     int hflags[2];
-    FPC_HIP(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
-    FPC_HIP(hipStreamSynchronize(st));
+    memcpy(hflags, h, sizeof(hflags));
+    if (max_abs_diff) memcpy(max_abs_diff, h + 32, sizeof(double));
     if (hflags[0]) return FPC_ENONFINITE;
     if (hflags[1]) return FPC_ESINGULAR;
     return FPC_OK;
@@ -448,7 +461,7 @@ int gather_rows(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p,
     return h ? FPC_EINVAL : FPC_OK;
 }
 
-int corr_max_abs_diff(fpc_ctx *ctx, const double *c64, const float *c32, int p, double *out)
+int corr_max_abs_diff_enqueue(fpc_ctx *ctx, const double *c64, const float *c32, int p)
 {
     int rc = ctx->flag.ensure(64);
     if (rc) return rc;
@@ -456,12 +469,6 @@ int corr_max_abs_diff(fpc_ctx *ctx, const double *c64, const float *c32, int p, 
     FPC_HIP(hipMemsetAsync(d, 0, sizeof(*d), ctx->stream));
     max_abs_diff<<<512, 256, 0, ctx->stream>>>(c64, c32, (size_t)p * p, d);
     FPC_HIP(hipGetLastError());
-    unsigned long long h = 0;
-    FPC_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
-    FPC_HIP(hipStreamSynchronize(ctx->stream));
-    double v;
-    memcpy(&v, &h, sizeof(v));
-    *out = v;
     return FPC_OK;
 }
 

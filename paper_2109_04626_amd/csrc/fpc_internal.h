@@ -94,6 +94,7 @@ struct fpc_ctx {
     fpc::HostBuf h_stage;         // pinned staging for uploads
     fpc::HostBuf h_back;          // pinned staging for downloads
     fpc::HostBuf h_inst;          // pinned staging for the instance table
+    fpc::HostBuf h_flag;          // pinned landing of the correlation flags
 };
 
 namespace fpc {
@@ -112,8 +113,11 @@ struct EdgeRec {
 // reuse_stats: the column statistics of the previous call on the same X
 // (same n, p) are still in the context and are used as they are.
 int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out,
-                 bool reuse_stats = false);
-int corr_max_abs_diff(fpc_ctx *ctx, const double *c64, const float *c32, int p, double *out);
+                 bool reuse_stats = false, bool wait = true);
+// With wait = false the products are only queued: corr_check waits once for
+// every queued correlation (and max_abs_diff) and reports their flags.
+int corr_max_abs_diff_enqueue(fpc_ctx *ctx, const double *c64, const float *c32, int p);
+int corr_check(fpc_ctx *ctx, double *max_abs_diff);
 // out (device, n x p) := rows[r] of X (device, x_rows x p); FPC_EINVAL for an index out of range.
 int gather_rows(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p, const int32_t *rows, int n,
                 void *out);

@@ -259,6 +259,7 @@ extern "C" int fpc_destroy(fpc_ctx *c)
     c->h_stage.release();
     c->h_back.release();
     c->h_inst.release();
+    c->h_flag.release();
     for (hipEvent_t ev : c->lev)
         if (ev) (void)hipEventDestroy(ev);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -718,13 +719,15 @@ int corr_stage(Run &R, const void *X, int x_dtype, double *C64, float *C32, doub
 {
     const double t0 = now_ms();
     int rc;
-    if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_FP64, C64))) return rc;
+    // both products and the error measure queued, then one wait
+    if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_FP64, C64, false, false))) return rc;
     R.C64 = C64;
     if (R.mixed) {
-        if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_BF16X3, C32, true))) return rc;
+        if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_BF16X3, C32, true, false))) return rc;
         R.C32 = C32;
-        if ((rc = corr_max_abs_diff(R.ctx, R.C64, R.C32, R.p, &R.c_err))) return rc;
+        if ((rc = corr_max_abs_diff_enqueue(R.ctx, R.C64, R.C32, R.p))) return rc;
     }
+    if ((rc = corr_check(R.ctx, R.mixed ? &R.c_err : nullptr))) return rc;
     *ms = now_ms() - t0;
     return FPC_OK;
 }

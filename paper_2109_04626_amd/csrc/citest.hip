@@ -1426,11 +1426,12 @@ __device__ __forceinline__ int64_t window_items(const EdgeRec &E, uint64_t mh, i
     return span > 0 ? (span + rpb - 1) / rpb : 0;
 }
 
-// Exclusive scan of one value per thread over a 256-thread workgroup;
+// Exclusive scan of one value per thread over a workgroup of NW waves;
 // returns the workgroup total.
+template <int NW = 4>
 __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t &excl)
 {
-    __shared__ int64_t wsum[4];
+    __shared__ int64_t wsum[NW];
     const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
     int64_t x = v;
 #pragma unroll
@@ -1442,7 +1443,7 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t &excl
     __syncthreads();
     int64_t before = 0, total = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < NW; ++k) {
         if (k < w) before += wsum[k];
         total += wsum[k];
     }
@@ -1506,15 +1507,17 @@ __global__ __launch_bounds__(256) void plan_scan(PlanArgs P)
     }
 }
 
-// The three plan passes in one workgroup, for classes of at most
-// kPlanSingle chunks: the chunks are scanned one after the other with a
-// running carry.
-constexpr int kPlanSingle = 8;
+// The three plan passes in one 1024-thread workgroup, for classes of at
+// most kPlanSingleEdges edges: chunks of 8192 edges are scanned one after
+// the other with a running carry.
+constexpr int kPlanSingleThreads = 1024;
+constexpr int64_t kPlanSingleEdges = 65536;
 
-__global__ __launch_bounds__(256) void plan_single(PlanArgs P)
+__global__ __launch_bounds__(kPlanSingleThreads) void plan_single(PlanArgs P)
 {
+    constexpr int64_t chunk = (int64_t)kPlanSingleThreads * kPlanPer;
     int64_t carry = 0;
-    for (int64_t base0 = 0; base0 < P.n_edges; base0 += kPlanChunk) {
+    for (int64_t base0 = 0; base0 < P.n_edges; base0 += chunk) {
         const int64_t base = base0 + (int64_t)threadIdx.x * kPlanPer;
         int64_t v[kPlanPer];
         int64_t s = 0;
@@ -1525,7 +1528,7 @@ __global__ __launch_bounds__(256) void plan_single(PlanArgs P)
             s += v[t];
         }
         int64_t ex;
-        const int64_t tot = block_exclusive_scan(s, ex);
+        const int64_t tot = block_exclusive_scan<kPlanSingleThreads / 64>(s, ex);
         int64_t run = carry + ex;
 #pragma unroll
         for (int t = 0; t < kPlanPer; ++t) {
@@ -1900,8 +1903,8 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             A.edge_base = k.begin;
             A.max_m = k.max_m;
             A.pdec_n = k.pdec_n;
-            if (nb <= kPlanSingle) {
-                plan_single<<<1, 256, 0, st>>>(P);
+            if (Ek <= kPlanSingleEdges) {
+                plan_single<<<1, kPlanSingleThreads, 0, st>>>(P);
             } else {
                 plan_reduce<<<(unsigned)nb, 256, 0, st>>>(P);
                 plan_sums<<<1, 256, 0, st>>>(P, (int)nb);

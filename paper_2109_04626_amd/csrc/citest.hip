@@ -315,18 +315,24 @@ __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_read
 // of one edge) from the window's counter until none is left.  Item bodies
 // may return early only uniformly over the workgroup or after their last
 // block-wide barrier; the barrier after each item protects the LDS tile.
+// A workgroup's first item is its own index; later ones come from the
+// counter (offset by the grid size), which a launch with no more items than
+// workgroups never touches: a counter that every workgroup hits at once
+// serialises the launch's start.
 template <class F>
 __device__ __forceinline__ void for_each_item(const LevelArgs &A, F &&body)
 {
     __shared__ int64_t next_item;
     const int64_t total = *A.n_items;
+    int64_t blk = blockIdx.x;
     for (;;) {
-        if (threadIdx.x == 0) next_item = (int64_t)atomicAdd(A.item_ctr, 1ull);
-        __syncthreads();
-        const int64_t blk = uniform_i64(next_item);
         if (blk >= total) return;  // uniform
         body(blk);
         __syncthreads();
+        if (total <= (int64_t)gridDim.x) return;  // every item had a workgroup of its own
+        if (threadIdx.x == 0) next_item = (int64_t)gridDim.x + (int64_t)atomicAdd(A.item_ctr, 1ull);
+        __syncthreads();
+        blk = uniform_i64(next_item);
     }
 }
 

@@ -50,6 +50,7 @@ constexpr int kSteps = 8;
 constexpr int kRanksPerWave = 64 * kSteps;               // default ranks per wave, per-test kernel
 constexpr int kGenericRanks = 16;                        // ranks per workgroup, wide-level kernel
 constexpr double kErrSafety = 4.0;                       // multiplier of the FP32 error bound
+constexpr int kSplitMinRanksPerWave = 256;  // triple kernel: smallest work item after splitting, per wave
 constexpr int kMinhitEvery = 512;  // shared-prefix kernels: tests between reads of an edge's minimum hit
 
 enum : int { DEC_DEP = 0, DEC_INDEP = 1, DEC_RECHECK = 2 };
@@ -1282,6 +1283,18 @@ int triple_table_entries(int l, bool fp32, int max_m, size_t base, size_t lds_cu
     return (int)std::min<size_t>(full, (room - base) / 2 / 8 * 8);
 }
 
+// Workgroups of the triple kernel resident on one CU (registers, LDS of
+// `shm` bytes each and the tuning cap).
+int triple_blocks_per_cu(int l, bool fp32, size_t shm, size_t lds_cu, int cap_blocks)
+{
+    const void *fn = fp32 ? triple_fn<float>(l) : triple_fn<double>(l);
+    int k = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, fn, 256, 0) != hipSuccess || k < 1) k = 1;
+    k = std::min<int>(k, (int)(lds_cu / (shm + 256)));
+    if (cap_blocks > 0) k = std::min(k, cap_blocks);
+    return std::max(k, 1);
+}
+
 // ------------------------------------------------------------------ wide levels
 // One wave per test, the (l+2)x(l+2) matrix over [K, i, j] packed lower in
 // LDS, right-looking Cholesky; after l steps the trailing 2x2 block is H.
@@ -1879,12 +1892,32 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             if (w + 1 >= (int)k.wins.size()) continue;
             const int64_t lo = k.wins[w], hi = k.wins[w + 1];
             // upper bound of the items (every edge live) sizes the grid
-            int64_t ub = 0;
-            for (int64_t e = k.begin; e < k.end; ++e) {
-                const int64_t span = std::min(ntests[e], hi) - lo;
-                if (span > 0) ub += (span + k.rpb - 1) / k.rpb;
-            }
+            const auto items_ub = [&](int64_t rpb) {
+                int64_t n = 0;
+                for (int64_t e = k.begin; e < k.end; ++e) {
+                    const int64_t span = std::min(ntests[e], hi) - lo;
+                    if (span > 0) n += (span + rpb - 1) / rpb;
+                }
+                return n;
+            };
+            int rpb = k.rpb;
+            int64_t ub = items_ub(rpb);
             if (ub == 0) continue;
+            // A launch with fewer items than resident workgroups leaves CUs
+            // idle and lasts as long as its longest item: the triple kernel
+            // halves its items while they still fit one resident round (an
+            // edge's result does not depend on how its ranks are cut; every
+            // item stages its tile again, so more rounds would cost more).
+            if (k.kind == K_TRIPLE) {
+                const int64_t slots =
+                    (int64_t)cus * triple_blocks_per_cu(l, fp32, k.shm, lds_cu, ctx->tuning.max_blocks_per_cu[lt]);
+                while (rpb / 2 >= kWaves * kSplitMinRanksPerWave) {
+                    const int64_t n2 = items_ub(rpb / 2);
+                    if (n2 > slots) break;
+                    rpb /= 2;
+                    ub = n2;
+                }
+            }
             const int64_t Ek = k.end - k.begin, nb = (Ek + kPlanChunk - 1) / kPlanChunk;
             PlanArgs P{};
             P.edges = Lv.edges + k.begin;
@@ -1892,7 +1925,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             P.n_edges = Ek;
             P.lo = lo;
             P.hi = hi;
-            P.rpb = k.rpb;
+            P.rpb = rpb;
             P.filter = w > 0;
             P.sums = pl + 2;
             P.off = pl + 2 + nb;
@@ -1905,7 +1938,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             A.blockoff = P.off;
             A.win_lo = lo;
             A.win_hi = hi;
-            A.ranks_per_block = k.rpb;
+            A.ranks_per_block = rpb;
             A.edge_base = k.begin;
             A.max_m = k.max_m;
             A.pdec_n = k.pdec_n;
@@ -1947,8 +1980,8 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             }
             if (trace_on())
                 std::fprintf(stderr, "[fpc]   l=%d window %d class %d: kind %d, lists <= %d, LDS %zu B (pair table %d), "
-                             "grid %u, items <= %lld\n", l, w, (int)(&k - cls.data()), (int)k.kind, k.max_m, k.shm,
-                             k.pdec_n, g_last_grid, (long long)ub);
+                             "grid %u, items <= %lld of %d ranks\n", l, w, (int)(&k - cls.data()), (int)k.kind, k.max_m, k.shm,
+                             k.pdec_n, g_last_grid, (long long)ub, rpb);
             ++nlaunch;
             // FP64 re-run of this launch's queue (level edge indices);
             // the next plan empties it

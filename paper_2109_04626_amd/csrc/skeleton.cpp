@@ -476,6 +476,7 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     if ((rc = ctx->counters.ensure(sizeof(unsigned long long) * (8 + 2 * (size_t)ni)))) return rc;
     FPC_HIP(hipMemcpyAsync(ctx->edges.ptr, hrec, sizeof(EdgeRec) * E, hipMemcpyHostToDevice, s));
     if (T) FPC_HIP(hipMemcpyAsync(ctx->cand.ptr, cand, sizeof(int32_t) * T, hipMemcpyHostToDevice, s));
+    const double t_copy = now_ms();
 
     // learned order: features, MLP scores, per-edge reorder of the lists
     // (at l = 0 each edge has one subset, so the order cannot matter)
@@ -512,6 +513,7 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
             FPC_HIP(hipStreamSynchronize(s));
         }
     }
+    const double t_order = now_ms();
     std::vector<LevelInst> insts(ni);
     for (int k = 0; k < ni; ++k) {
         const Run &R = *runs[k];
@@ -525,6 +527,7 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     if ((rc = ctx->h_back.ensure(sizeof(int64_t) * (2 * (size_t)E + 2) + sizeof(unsigned long long) * n_cnt)))
         return rc;
 
+    const double t_bufs = now_ms();
     int64_t *h_del = ctx->h_back.as<int64_t>();
     const unsigned long long *cnt = reinterpret_cast<const unsigned long long *>(h_del + 2 * E + 2);
     LevelLaunch Lv{};
@@ -666,10 +669,10 @@ retry:
     if (trace_on())
         std::fprintf(stderr,
                      "[fpc] level %d: %d instance(s) %lld edges %lld candidates %d classes | setup %.2f upload+order "
-                     "%.2f tests and compaction %.2f (device %.2f) counts %.2f decode %.2f ms | deleted %lld, "
-                     "queued for FP64 in the last launch %llu\n",
+                     "%.2f (copies %.2f, order %.2f, buffers %.2f) tests and compaction %.2f (device %.2f) counts %.2f "
+                     "decode %.2f ms | deleted %lld, queued for FP64 in the last launch %llu\n",
                      l, ni, (long long)E, (long long)T, (int)classes.size(), t_build - t0, t_tests0 - t_build,
-                     t_tests1 - t_tests0, tm.all_ms, t_decode - t_tests1, now_ms() - t_decode, (long long)ndel,
+                     t_copy - t_build, t_order - t_copy, t_bufs - t_order, t_tests1 - t_tests0, tm.all_ms, t_decode - t_tests1, now_ms() - t_decode, (long long)ndel,
                      fp32 ? cnt[1] : 0ull);
     for (auto &st : sts) {
         st.kernel_ms = tm.all_ms;

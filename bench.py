@@ -17,6 +17,7 @@ scale-free workload (BA DAG, p = 1000, n = 10000, max_level = 3).
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -129,11 +130,23 @@ def main() -> int:
 
         for _ in range(args.warmup):
             run()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        outs = [run() for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0, outs
+        # the results kept alive here make Python's cyclic collector pause
+        # for tens of ms at random calls: it runs before, not inside, the
+        # timed region
+        gc.collect()
+        gc.disable()
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            outs = []
+            for _ in range(args.steps):
+                outs.append(run())
+                outs[-1]["wall_ms"] = (time.perf_counter() - t0) * 1e3
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            gc.enable()
+        return dt, outs
 
     # plain = FP64 tests, lexicographic order; mixed = bf16x3 C + FP32 tests
     # with FP64 recheck; learned = mixed with the MLP-ranked candidate order
@@ -174,18 +187,24 @@ def main() -> int:
                                      max_level=cfg5["max_level"], precision=fpc.FPC_PREC_MIXED) for X, r in inst]
 
         run_batch()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.batch_steps):
-            outs_b = run_batch()
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - t0) / args.batch_steps
-        run_singles()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        outs_s = run_singles()
-        torch.cuda.synchronize()
-        ts = time.perf_counter() - t0
+        gc.collect()
+        gc.disable()
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.batch_steps):
+                outs_b = run_batch()
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - t0) / args.batch_steps
+            run_singles()
+            gc.collect()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            outs_s = run_singles()
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+        finally:
+            gc.enable()
         same_b = all(np.array_equal(a["adj"], b["adj"]) for a, b in zip(outs_b, outs_s))
         tests_b = sum(o["total_tests"] for o in outs_b)
         req_b = sum(o["total_required"] for o in outs_b)
@@ -217,6 +236,10 @@ def main() -> int:
     dom_flops = dom["tests_executed"] * flops_per_test(dom["level"])
     achieved = dom_flops / (dom["test_kernel_ms"] / 1e3) / 1e12 if dom["test_kernel_ms"] > 0 else 0.0
     if args.verbose:
+        for name, (_, o) in [("ba-mixed", ba["mixed"]), ("ba-learned", ba["learned"])]:
+            w = np.diff([0.0] + [x["wall_ms"] for x in o])
+            print(f"[bench] {name} per call wall: " + " ".join(f"{v:.2f}" for v in w), file=sys.stderr)
+            print(f"[bench] {name} per call lib:  " + " ".join(f"{x['total_ms']:.2f}" for x in o), file=sys.stderr)
         for name in forms:
             o = results[name][1][-1]
             print(f"[bench] {name}: total_ms(lib)={o['total_ms']:.2f} corr={o['corr_ms']:.2f} "
@@ -260,6 +283,9 @@ def main() -> int:
                                    f"alpha={cfg_b['alpha']}, max_level={cfg_b['max_level']}",
                        "mixed_ms_per_step": ba["mixed"][0] / args.steps * 1e3,
                        "learned_ms_per_step": ba["learned"][0] / args.steps * 1e3,
+                       "mixed_lib_ms_median": float(np.median([o["total_ms"] for o in ba["mixed"][1]])),
+                       "learned_lib_ms_median": float(np.median([o["total_ms"] for o in ba["learned"][1]])),
+                       "mixed_lib_ms_max": float(np.max([o["total_ms"] for o in ba["mixed"][1]])),
                        "tests_mixed": ba["mixed"][1][-1]["total_tests"],
                        "tests_learned": ba["learned"][1][-1]["total_tests"],
                        "skeleton_equal": bool(np.array_equal(ba["mixed"][1][-1]["adj"],

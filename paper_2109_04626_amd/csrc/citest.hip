@@ -1859,7 +1859,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
         hin[k].ld = I.p;
         hin[k].th = make_thresholds(I.q, I.n, l, Lv.band_z, I.c_err + 4.0 * (l + 2) * 6.0e-8);
     }
-    FPC_HIP(hipMemcpyAsync(ctx->insts.ptr, hin, sizeof(InstRec) * (size_t)ni, hipMemcpyHostToDevice, st));
+    if ((rc = upload_enqueue(ctx, ctx->insts.ptr, ctx->h_inst, 0, sizeof(InstRec) * (size_t)ni))) return rc;
 
     // plan buffers, reused by every (window, class) launch in stream order:
     // [n_items, item_ctr], workgroup sums, per-edge offsets
@@ -2045,6 +2045,38 @@ int level_init(fpc_ctx *ctx, uint64_t *minhit, int64_t n_edges, unsigned long lo
     const int64_t n = std::max<int64_t>(n_edges, n_cnt);
     if (n > 0)
         level_init_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(minhit, n_edges, counters, n_cnt);
+    FPC_HIP(hipGetLastError());
+    return FPC_OK;
+}
+
+// Upload of 4-byte words from pinned host memory by a kernel that reads the
+// host buffer through its device mapping with system-scope loads (coherent
+// with the host's writes made before the launch).
+__global__ __launch_bounds__(256) void upload_kernel(uint32_t *__restrict__ dst, const uint32_t *src, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += stride)
+        dst[k] = __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+int upload_enqueue(fpc_ctx *ctx, void *dst, const HostBuf &src, size_t offset, size_t bytes)
+{
+    if (bytes == 0) return FPC_OK;
+    if (!dst || !src.ptr || offset + bytes > src.bytes) return FPC_EINVAL;
+    hipStream_t st = ctx->stream;
+    const char *h = static_cast<const char *>(src.ptr) + offset;
+    void *mapped = nullptr;
+    if (bytes % 4 || (uintptr_t)dst % 4 || (uintptr_t)h % 4 ||
+        hipHostGetDevicePointer(&mapped, src.ptr, 0) != hipSuccess || !mapped) {
+        (void)hipGetLastError();
+        FPC_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st));
+        return FPC_OK;
+    }
+    const int64_t n = (int64_t)(bytes / 4);
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    upload_kernel<<<grid, 256, 0, st>>>(static_cast<uint32_t *>(dst),
+                                        reinterpret_cast<const uint32_t *>(static_cast<const char *>(mapped) + offset),
+                                        n);
     FPC_HIP(hipGetLastError());
     return FPC_OK;
 }

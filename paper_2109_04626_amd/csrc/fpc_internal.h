@@ -190,6 +190,13 @@ int level_init(fpc_ctx *ctx, uint64_t *minhit, int64_t n_edges, unsigned long lo
 // h (pinned, 2 * n_edges + 2 int64): after a stream synchronisation h[0]
 // is the number of deletions and h[2 + 2t], h[3 + 2t] the t-th (edge, rank).
 int level_compact_enqueue(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *h);
+// Queues the copy of bytes [offset, offset + bytes) of the pinned buffer src
+// into device memory dst by a kernel that reads src through its device
+// mapping (the runtime's small host-to-device copies have held the calling
+// thread for milliseconds); a buffer with no mapping, or a size or address
+// that is not a multiple of 4, takes hipMemcpyAsync.  The host must not
+// change those bytes before the stream has passed the copy.
+int upload_enqueue(fpc_ctx *ctx, void *dst, const HostBuf &src, size_t offset, size_t bytes);
 int ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, const int32_t *B,
              int64_t b, double q, double *z_out, uint8_t *indep_out);
 

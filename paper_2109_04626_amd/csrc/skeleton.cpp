@@ -474,8 +474,8 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     if ((rc = ctx->cand.ensure(sizeof(int32_t) * (T + 1)))) return rc;
     if ((rc = ctx->minhit.ensure(sizeof(uint64_t) * E))) return rc;
     if ((rc = ctx->counters.ensure(sizeof(unsigned long long) * (8 + 2 * (size_t)ni)))) return rc;
-    FPC_HIP(hipMemcpyAsync(ctx->edges.ptr, hrec, sizeof(EdgeRec) * E, hipMemcpyHostToDevice, s));
-    if (T) FPC_HIP(hipMemcpyAsync(ctx->cand.ptr, cand, sizeof(int32_t) * T, hipMemcpyHostToDevice, s));
+    if ((rc = upload_enqueue(ctx, ctx->edges.ptr, ctx->h_stage, 0, sizeof(EdgeRec) * E))) return rc;
+    if ((rc = upload_enqueue(ctx, ctx->cand.ptr, ctx->h_stage, sizeof(EdgeRec) * E, sizeof(int32_t) * T))) return rc;
     const double t_copy = now_ms();
 
     // learned order: features, MLP scores, per-edge reorder of the lists

@@ -1431,7 +1431,7 @@ struct PlanArgs {
     int64_t *off;                   // n_edges + 1 exclusive prefix of items per edge
     int64_t *n_items;               // total items of the window
     unsigned long long *item_ctr;   // zeroed for the window's test kernel
-    unsigned long long *queue_len;  // recheck queue of the previous launch, emptied
+    unsigned long long *queue_len;  // recheck queue of the previous window, emptied (null: kept)
 };
 
 constexpr int kPlanPer = 8;                 // edges per thread
@@ -1500,7 +1500,7 @@ __global__ __launch_bounds__(256) void plan_sums(PlanArgs P, int nb)
         P.off[P.n_edges] = carry;
         *P.n_items = carry;
         *P.item_ctr = 0;
-        *P.queue_len = 0;
+        if (P.queue_len) *P.queue_len = 0;
     }
 }
 
@@ -1561,7 +1561,7 @@ __global__ __launch_bounds__(kPlanSingleThreads) void plan_single(PlanArgs P)
         P.off[P.n_edges] = carry;
         *P.n_items = carry;
         *P.item_ctr = 0;
-        *P.queue_len = 0;
+        if (P.queue_len) *P.queue_len = 0;
     }
 }
 
@@ -1888,6 +1888,10 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     int nev = 0, nlaunch = 0;
     hipError_t err = hipSuccess;
     for (int w = 0; w < max_nw && err == hipSuccess; ++w) {
+        // the classes of a window share the recheck queue: the window's first
+        // plan empties it and one FP64 re-run after its last launch drains it
+        // (before any plan of the next window reads minhit)
+        bool window_open = false;
         for (const Cls &k : cls) {
             if (w + 1 >= (int)k.wins.size()) continue;
             const int64_t lo = k.wins[w], hi = k.wins[w + 1];
@@ -1931,7 +1935,8 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             P.off = pl + 2 + nb;
             P.n_items = pl;
             P.item_ctr = A.item_ctr;
-            P.queue_len = &Lv.counters[1];
+            P.queue_len = window_open ? nullptr : &Lv.counters[1];
+            window_open = true;
             A.edges = P.edges;
             A.minhit = Lv.minhit + k.begin;
             A.n_edges = Ek;
@@ -1983,19 +1988,19 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                              "grid %u, items <= %lld of %d ranks\n", l, w, (int)(&k - cls.data()), (int)k.kind, k.max_m, k.shm,
                              k.pdec_n, g_last_grid, (long long)ub, rpb);
             ++nlaunch;
-            // FP64 re-run of this launch's queue (level edge indices);
-            // the next plan empties it
-            if (fp32 && err == hipSuccess) {
-                LevelArgs Q = A;
-                Q.edges = Lv.edges;
-                Q.minhit = Lv.minhit;
-                Q.n_edges = E;
-                Q.edge_base = 0;
-                Q.max_m = Lv.max_m;
-                launch_recheck(l, st, Q);
-            }
             if (err == hipSuccess) err = hipGetLastError();
             if (err != hipSuccess) break;
+        }
+        // FP64 re-run of the window's queue (level edge indices)
+        if (fp32 && window_open && err == hipSuccess) {
+            LevelArgs Q = A;
+            Q.edges = Lv.edges;
+            Q.minhit = Lv.minhit;
+            Q.n_edges = E;
+            Q.edge_base = 0;
+            Q.max_m = Lv.max_m;
+            launch_recheck(l, st, Q);
+            err = hipGetLastError();
         }
     }
     if (graph) {

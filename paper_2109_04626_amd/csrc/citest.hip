@@ -233,6 +233,38 @@ __device__ __forceinline__ void unrank(int64_t R, int m, const int64_t *__restri
     }
 }
 
+// The same unranking by a whole wave (R and m uniform, every lane active),
+// one coalesced load per element instead of a walk of up to m dependent
+// loads.  Subsets of the positions >= x0 whose element t lies before x
+// number C(m - x0, L - t) - C(m - x, L - t) (hockey-stick identity), so the
+// element is the last x with C(m - x, L - t) >= C(m - x0, L - t) - R; those
+// x form a prefix of the lanes, read off a ballot.  binT is column-major.
+template <int L>
+__device__ __forceinline__ void unrank_wave(int64_t R, int m, const int64_t *__restrict__ binT, int *c)
+{
+    const int lane = threadIdx.x % 64;
+    int x0 = 0;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const int k = L - t;
+        const int64_t *col = binT + (size_t)k * kBinomRows;
+        const int64_t top = col[m - x0];  // the subsets left: C(m - x0, L - t) > R
+        const int64_t need = top - R;
+        const int last = m - k;  // element t leaves room for the L - 1 - t after it
+        int x = x0;
+        for (int base = x0; base <= last; base += 64) {
+            const int xl = base + lane;
+            const bool ok = xl <= last && col[m - xl] >= need;
+            const int n = __popcll(__ballot(ok));
+            if (n > 0) x = base + n - 1;
+            if (n < 64) break;  // uniform
+        }
+        R -= top - col[m - x];
+        c[t] = x;
+        x0 = x + 1;
+    }
+}
+
 // Given c = the combination at some rank b (wave-uniform), set my = the
 // combination at rank b + lane and advance c to rank b + 64.  Lanes past
 // the last combination keep the (valid) initial my.  Returns false when no
@@ -289,6 +321,7 @@ struct LevelArgs {
     const int64_t *n_items;   // work items of this window (written on the device)
     unsigned long long *item_ctr;  // next work item (zeroed with the window's plan)
     const int64_t *binom;
+    const int64_t *binomT;  // the binomial table column-major
     uint64_t *minhit;
     unsigned long long *counters;  // [1] recheck queue length, [3] queue overflow
     unsigned long long *inst_cnt;  // per instance: tests executed, tests re-run in FP64
@@ -680,7 +713,7 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
 
     // first test of the range: K = Q + {a, b}
     int c[L];
-    unrank<L>(wlo, m, A.binom, c);
+    unrank_wave<L>(wlo, m, A.binomT, c);
     int Q[QLL];
 #pragma unroll
     for (int t = 0; t < QL; ++t) Q[t] = c[t];
@@ -967,7 +1000,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
 
     // the walk's position (Q, a, tau, rank) is the same in every lane
     int c[L];
-    unrank<L>(wlo, m, A.binom, c);
+    unrank_wave<L>(wlo, m, A.binomT, c);
     int Q[QLL];
 #pragma unroll
     for (int t = 0; t < QL; ++t) Q[t] = uniform_i32(c[t]);
@@ -1873,6 +1906,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     A.n_items = pl;
     A.item_ctr = reinterpret_cast<unsigned long long *>(pl + 1);
     A.binom = ctx->binom.as<int64_t>();
+    A.binomT = ctx->binomT.as<int64_t>();
     A.counters = Lv.counters;
     A.inst_cnt = Lv.inst_cnt;
     A.queue = Lv.queue;

@@ -64,6 +64,9 @@ struct fpc_ctx {
 
     // binomial table on the device (saturating int64), kBinomRows x kBinomCols
     fpc::DevBuf binom;
+    // the same table column-major (C(a, b) at b * kBinomRows + a): a wave
+    // reads C(a, b) for 64 consecutive a in one coalesced load
+    fpc::DevBuf binomT;
     std::vector<int64_t> binom_host;
 
     // correlation / first level

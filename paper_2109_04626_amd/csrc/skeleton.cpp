@@ -242,6 +242,21 @@ extern "C" int fpc_create(fpc_ctx **out, int hip_device, void *hip_stream)
         fpc_destroy(c);
         return hip_fail(e, "hipMemcpy");
     }
+    {
+        std::vector<int64_t> t((size_t)kBinomRows * kBinomCols);
+        for (int a = 0; a < kBinomRows; ++a)
+            for (int b = 0; b < kBinomCols; ++b)
+                t[(size_t)b * kBinomRows + a] = c->binom_host[(size_t)a * kBinomCols + b];
+        if ((rc = c->binomT.ensure(sizeof(int64_t) * t.size()))) {
+            fpc_destroy(c);
+            return rc;
+        }
+        e = hipMemcpy(c->binomT.ptr, t.data(), sizeof(int64_t) * t.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            fpc_destroy(c);
+            return hip_fail(e, "hipMemcpy");
+        }
+    }
     *out = c;
     return FPC_OK;
 }
@@ -251,7 +266,7 @@ extern "C" int fpc_destroy(fpc_ctx *c)
     if (!c) return FPC_EINVAL;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    DevBuf *bufs[] = {&c->binom, &c->x_copy, &c->colstat, &c->c64, &c->c32, &c->zsplit, &c->inv_work,
+    DevBuf *bufs[] = {&c->binom, &c->binomT, &c->x_copy, &c->colstat, &c->c64, &c->c32, &c->zsplit, &c->inv_work,
                       &c->flag, &c->cand, &c->edges, &c->blockoff, &c->minhit, &c->counters,
                       &c->queue, &c->dellist, &c->batch_tmp, &c->mlp_grad, &c->rfirst, &c->feat,
                       &c->cand2, &c->degs, &c->insts, &c->batch_c};

@@ -38,9 +38,9 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32
 # calibration (fetch x2.000, write x1.000).  Valid only for the kernel source
 # and launch table they were taken with: any change to either makes the
 # figure null until the counters are taken again.
-MEASURED_TRAFFIC = {"bytes_per_launch": 10038462.0,
+MEASURED_TRAFFIC = {"bytes_per_launch": 10093102.0,
                     "sha256": {"paper_2109_04626_amd/csrc/citest.hip":
-                               "a9aa2951d662235f5ef3315a2bdc0160b5ddc52c67ca7adda12b0290745dc353",
+                               "54ac84ac8d4c3dce7b4a4cdc0c305e3c234e3cfb80f3c5cf95da597e348b5905",
                                "paper_2109_04626_amd/tuning_gfx950.json":
                                "9b5ee9cd8fc56c7307853a22b4732f84004d394956b92179119b5f35944c27e9"}}
 

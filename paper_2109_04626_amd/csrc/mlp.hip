@@ -65,7 +65,8 @@ __global__ void round_weights(const float *__restrict__ master, __bf16 *__restri
 
 // Weights staged in LDS as FP32 values of the bf16 copies.
 struct SmemW {
-    float W1[kIn * kH], b1[kH], W2[kH * kH], b2[kH], W3[kH], b3;
+    alignas(16) float W2[kH * kH];  // first, 16-byte aligned: read as float4 rows
+    float W1[kIn * kH], b1[kH], b2[kH], W3[kH], b3;
 };
 
 __device__ void load_weights(SmemW &s, const float *__restrict__ master, const __bf16 *__restrict__ W1h,
@@ -104,7 +105,51 @@ __device__ __forceinline__ float forward_one(const SmemW &s, const float *x, flo
     return z;
 }
 
-__global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restrict__ X, int64_t N,
+// The same forward pass with the hidden layer's loops swapped: all 64
+// sums of layer 2 stay in registers and each row of W2 is read from LDS as
+// 16-byte words (four FMAs per read instead of one).  Every sum takes its
+// terms in the same order as forward_one, so the results are identical.
+__device__ __forceinline__ float forward_rows(const SmemW &s, const float *x)
+{
+    float h1[kH];
+#pragma unroll
+    for (int o = 0; o < kH; ++o) {
+        float a = s.b1[o];
+#pragma unroll
+        for (int i = 0; i < kIn; ++i) a = fmaf(x[i], s.W1[i * kH + o], a);
+        h1[o] = fmaxf(a, 0.f);
+    }
+    // layer 2 in four slices of 16 outputs; the output sum takes them in order
+    float z = s.b3;
+#pragma unroll 1
+    for (int q = 0; q < kH / 16; ++q) {
+        float acc[16];
+#pragma unroll
+        for (int o = 0; o < 16; ++o) acc[o] = s.b2[16 * q + o];
+#pragma unroll
+        for (int i = 0; i < kH; ++i) {
+            const float4 *w = reinterpret_cast<const float4 *>(s.W2 + i * kH + 16 * q);
+#pragma unroll
+            for (int o4 = 0; o4 < 4; ++o4) {
+                const float4 v = w[o4];
+                acc[4 * o4 + 0] = fmaf(h1[i], v.x, acc[4 * o4 + 0]);
+                acc[4 * o4 + 1] = fmaf(h1[i], v.y, acc[4 * o4 + 1]);
+                acc[4 * o4 + 2] = fmaf(h1[i], v.z, acc[4 * o4 + 2]);
+                acc[4 * o4 + 3] = fmaf(h1[i], v.w, acc[4 * o4 + 3]);
+            }
+            // keeps the scheduler from hoisting later rows' reads past this row
+            if (i % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int o = 0; o < 16; ++o) z = fmaf(fmaxf(acc[o], 0.f), s.W3[16 * q + o], z);
+    }
+    return z;
+}
+
+// at most 128 registers (four waves per SIMD): left alone, the compiler
+// hoists the unrolled stream of W2 reads into all 256
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mlp_forward_kernel(
+    const float *__restrict__ X, int64_t N,
                                                           const float *__restrict__ master,
                                                           const __bf16 *__restrict__ W1h,
                                                           const __bf16 *__restrict__ W2h,
@@ -113,10 +158,10 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
     __shared__ SmemW s;
     load_weights(s, master, W1h, W2h, W3h);
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += (int64_t)gridDim.x * 256) {
-        float x[kIn], h1[kH], h2[kH];
+        float x[kIn];
 #pragma unroll
         for (int i = 0; i < kIn; ++i) x[i] = X[r * kIn + i];
-        out[r] = forward_one(s, x, h1, h2);
+        out[r] = forward_rows(s, x);
     }
 }
 

@@ -78,7 +78,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=3e8, help="oracle tests in the CPU sample")
+    ap.add_argument("--cpu-budget", type=float, default=1e9, help="oracle tests in the CPU sample (about 10 s on 16 cores)")
     ap.add_argument("--max-level", type=int, default=None)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-instance workload")

@@ -70,6 +70,8 @@ def _L():
         lib.orc_zstat.restype = d
         lib.orc_zstat.argtypes = [d, i, i]
         lib.orc_candidates.restype = i
+        lib.orc_edge_series.restype = i
+        lib.orc_edge_series.argtypes = [vp, i, i, i, i, vp, i, i, i64, i64, vp, vp]
         lib.orc_candidates.argtypes = [vp, i, i, i, vp]
         lib.orc_skeleton.restype = vp
         lib.orc_skeleton.argtypes = [vp, i, i, d, i, i, i, i64, i, i]
@@ -162,6 +164,22 @@ def ci_test(C, n, i, j, K, q) -> tuple[bool, float, int]:
         return False, float("nan"), st
     z = zstat(r, n, len(K))
     return bool(z <= q), z, 0
+
+
+def edge_series(C, n, i, j, cand, l, r0, r1):
+    """(r, z) of the tests ranked r0..r1-1 of the pair (i, j) at level l:
+    rank t conditions on the t-th l-subset (lexicographic over positions)
+    of the list ``cand``; degenerate tests give NaN."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    cand = np.ascontiguousarray(np.asarray(cand, dtype=np.int32).reshape(-1))
+    r = np.empty(max(int(r1) - int(r0), 1), dtype=np.float64)
+    z = np.empty_like(r)
+    st = _L().orc_edge_series(_ptr(C), C.shape[0], int(n), int(i), int(j), _ptr(cand), cand.size, int(l), int(r0),
+                              int(r1), _ptr(r), _ptr(z))
+    if st:
+        raise OracleError(ORC_EINVAL)
+    k = max(int(r1) - int(r0), 0)
+    return r[:k], z[:k]
 
 
 def candidates(adj: np.ndarray, i: int, j: int) -> list[int]:

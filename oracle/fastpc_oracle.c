@@ -345,6 +345,53 @@ int orc_pcor_inverse(const double *C, int p, int i, int j, const int *K, int l,
     return ret;
 }
 
+/* ------------------------------------------------------------------ */
+/* The tests one edge runs at level l, as a series over ranks: the      */
+/* rank-t test conditions on the t-th l-subset of the list cand (subsets */
+/* of positions 0..m-1 in lexicographic order, the subset loop of the    */
+/* algorithms), and r_out[t - r0] receives its partial correlation by    */
+/* the Sec. 5 formula (NaN when degenerate) for t in [r0, r1).  The walk */
+/* starts at rank 0 and steps through the subsets one by one.  z_out    */
+/* (may be NULL) receives the Fisher z of each test, NaN when           */
+/* degenerate.  Returns 0, or -1 for bad arguments (r1 beyond the last   */
+/* subset included).                                                    */
+/* ------------------------------------------------------------------ */
+double orc_zstat(double r, int n, int l);
+
+int orc_edge_series(const double *C, int p, int n, int i, int j, const int *cand, int m, int l,
+                    int64_t r0, int64_t r1, double *r_out, double *z_out)
+{
+    if (!C || !r_out || l < 0 || m < l || r0 < 0 || r1 < r0 || (m > 0 && !cand)) return -1;
+    int *ix = (int *)malloc(sizeof(int) * (size_t)(l + 1));
+    int *K = (int *)malloc(sizeof(int) * (size_t)(l + 1));
+    double *work = (double *)malloc(sizeof(double) * (size_t)(l * l + 2 * l + 1));
+    if (!ix || !K || !work) { free(ix); free(K); free(work); return -1; }
+    for (int a = 0; a < l; ++a) ix[a] = a;
+    int ret = 0;
+    for (int64_t t = 0; t < r1; ++t) {
+        if (t >= r0) {
+            for (int a = 0; a < l; ++a) K[a] = cand[ix[a]];
+            double r;
+            const int deg = pcor_cholesky(C, p, i, j, K, l, work, &r) == ORC_DEGENERATE;
+            r_out[t - r0] = deg ? NAN : r;
+            if (z_out) z_out[t - r0] = deg ? NAN : orc_zstat(r, n, l);
+        }
+        /* next subset in lexicographic order */
+        int a = l - 1;
+        while (a >= 0 && ix[a] == m - l + a) --a;
+        if (a < 0) {
+            if (t + 1 < r1) ret = -1; /* r1 lies beyond the last subset */
+            break;
+        }
+        ++ix[a];
+        for (int b = a + 1; b < l; ++b) ix[b] = ix[b - 1] + 1;
+    }
+    free(ix);
+    free(K);
+    free(work);
+    return ret;
+}
+
 /* Fisher z statistic of the sampling test: sqrt(N - |K| - 3) |atanh r|. */
 double orc_zstat(double r, int n, int l)
 {

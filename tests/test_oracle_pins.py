@@ -123,6 +123,43 @@ def test_pcor_agrees_with_explicit_inverse_reference():
         assert r1 == pytest.approx(-P[0, 1] / math.sqrt(P[0, 0] * P[1, 1]), abs=1e-10)
 
 
+def test_edge_series_follows_lexicographic_subsets_and_explicit_inverse():
+    """Rank t of an edge's level-l tests conditions on the t-th l-subset of
+    the list in lexicographic order of positions (itertools' order), and its
+    r is the partial correlation of the explicit-inverse reference."""
+    rng = np.random.default_rng(11)
+    p = 14
+    A = rng.standard_normal((300, p)) @ rng.standard_normal((p, p))
+    C = oracle.corr(A)
+    cand = [9, 2, 13, 5, 7, 11, 3, 8]  # any order: positions index the list
+    for l in [0, 1, 2, 3, 5, 8]:
+        combos = list(itertools.combinations(range(len(cand)), l))
+        r, z = oracle.edge_series(C, 300, 0, 1, cand, l, 0, len(combos))
+        assert len(r) == len(combos)
+        for t, pos in enumerate(combos):
+            K = [cand[a] for a in pos]
+            ref, st = oracle.pcor_inverse(C, 0, 1, K)
+            assert st == 0 and r[t] == pytest.approx(ref, abs=1e-12)
+            P = np.linalg.inv(C[np.ix_([0, 1] + K, [0, 1] + K)])
+            assert r[t] == pytest.approx(-P[0, 1] / math.sqrt(P[0, 0] * P[1, 1]), abs=1e-11)
+            assert z[t] == pytest.approx(math.sqrt(300 - l - 3) * abs(math.atanh(ref)), rel=1e-12)
+        # a window of the series equals that slice of the whole series
+        if len(combos) > 4:
+            r2, _ = oracle.edge_series(C, 300, 0, 1, cand, l, 2, len(combos) - 1)
+            assert np.array_equal(r2, r[2:-1])
+    with pytest.raises(oracle.OracleError):
+        oracle.edge_series(C, 300, 0, 1, cand, 3, 0, 57)  # C(8,3) = 56 subsets
+
+
+def test_edge_series_marks_degenerate_tests():
+    C = np.eye(5)
+    C[2, 3] = C[3, 2] = 1.0  # X2 == X3: any K holding both is singular
+    r, z = oracle.edge_series(C, 100, 0, 1, [2, 3, 4], 2, 0, 3)
+    # subsets (2,3), (2,4), (3,4)
+    assert np.isnan(r[0]) and np.isnan(z[0])
+    assert r[1] == 0.0 and r[2] == 0.0
+
+
 def test_inverse_matches_library():
     rng = np.random.default_rng(5)
     A = rng.standard_normal((30, 30))

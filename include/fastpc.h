@@ -42,9 +42,14 @@ extern "C" {
 #define FPC_F64 0 /* IEEE binary64 elements */
 #define FPC_F32 1 /* IEEE binary32 elements */
 
-/* Correlation-matrix methods (fpc_corr). */
-#define FPC_CORR_FP64 0   /* FP64 centring and FP64 products            */
-#define FPC_CORR_BF16X3 1 /* bf16 split, three MFMA products, FP32 sums */
+/* Correlation-matrix methods (fpc_corr; fpc_params.c32_method picks the
+ * FP32 matrix of the mixed form). */
+#define FPC_CORR_FP64 0   /* FP64 centring and FP64 products                                  */
+#define FPC_CORR_BF16X3 1 /* bf16 two-way split, three MFMA products, FP32 sums (the lo.lo
+                             term is dropped: entry errors up to a few 1e-6)                  */
+#define FPC_CORR_BF16X6 2 /* bf16 three-way split, the six MFMA products of weight above
+                             2^-24, FP32 sums (entry errors of FP32-rounding order)           */
+#define FPC_CORR_FP32 3   /* the FP64 matrix rounded to FP32                                  */
 
 /* Arithmetic of the level tests (fpc_params.precision). */
 #define FPC_PREC_FP64 0  /* FP64 correlation, FP64 tests                                   */
@@ -95,7 +100,7 @@ double fpc_quantile(double alpha);
 /* ------------------------------------------------- correlation matrix (Sec. 5, "corr")
  * X: device pointer, row-major n x p (sample t, variable j at X[t*p + j]),
  * dtype x_dtype (FPC_F64 / FPC_F32).  C_out: device pointer, p x p
- * row-major, FPC_F64 for FPC_CORR_FP64 and FPC_F32 for FPC_CORR_BF16X3.
+ * row-major, FPC_F64 for FPC_CORR_FP64 and FPC_F32 for the other methods.
  * C_ij = S_ij / sqrt(S_ii S_jj) with S the covariance of the centred
  * columns; C_ii = 1 exactly.  Errors: FPC_EINVAL (n < 2, p < 1, NULL),
  * FPC_ENONFINITE (a non-finite sample), FPC_ESINGULAR (a constant column). */
@@ -124,6 +129,40 @@ int fpc_first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, doubl
  * n - l - 3 <= 0, b < 0, bad dtype). */
 int fpc_ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, const int32_t *B,
                  int64_t b, double q, double *z_out, uint8_t *indep_out);
+
+/* ------------------------------------------ the level tests of one edge, rank by rank
+ * Diagnostic: runs the tests that level l of fpc_skeleton runs for one edge
+ * (i, j) with candidate list cand, ranks rank_lo .. rank_hi-1, through the
+ * same kernels and launch shapes, and writes what each test computed.  Rank
+ * t conditions on the t-th l-subset of the list, lexicographic over list
+ * positions (the subset loop of Algorithm 2, Sec. 3.2); each test is
+ * H = H0 - H1 H2^{-1} H1^T, r = h12 / sqrt(h11 h22) (Sec. 5 formula).  Every
+ * rank of the range runs (no stop at an independent test, no FP64 re-run).
+ *   C, c_dtype  device p x p matrix: FPC_F64 runs the FP64 kernels, FPC_F32
+ *               the FP32 kernels of the mixed form;
+ *   cand        host, m distinct variables other than i and j (any order);
+ *   kernel      FPC_KERNEL_AUTO (the one the level would take), or one forced;
+ *   ranks_per_wave  work-item length (0: the context's tuning table);
+ *   pair_table  triple kernel's pair-decode table entries (-1: as the level
+ *               sizes it; 0: every pair decoded arithmetically);
+ *   q, band_z, c_err, ill_cond_tau  threshold, recheck margin in z units,
+ *               entry error bound of an FP32 matrix and ill-conditioning
+ *               threshold (fpc_params), as the level would use them.
+ * Outputs (device, rank_hi - rank_lo entries): r_out = r (FP64; NaN for a
+ * degenerate test), dec_out = decision (0 dependent, 1 independent, 2 left
+ * to the FP64 re-run; the FP64 kernels give 0 or 1).  Errors: FPC_EINVAL
+ * (range outside [0, C(m, l)), bad index, an unavailable kernel for l or a
+ * pair table beyond the LDS), FPC_EDEVICE. */
+#define FPC_KERNEL_AUTO 0
+#define FPC_KERNEL_PER_TEST 1 /* per-test Cholesky in registers, tile staged in LDS      */
+#define FPC_KERNEL_PAIR 2     /* shared (l-2)-prefix factor, 2x2 elimination (l >= 2)    */
+#define FPC_KERNEL_TRIPLE 3   /* shared (l-3)-prefix table, rank-1 update per element a
+                                 and 2x2 elimination per pair (l >= 3)                   */
+#define FPC_KERNEL_GLOBAL 4   /* per-test Cholesky reading C from global memory          */
+int fpc_level_series(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, int i, int j,
+                     const int32_t *cand, int m, int64_t rank_lo, int64_t rank_hi, int kernel,
+                     int ranks_per_wave, int pair_table, double q, double band_z, double c_err,
+                     double ill_cond_tau, double *r_out, uint8_t *dec_out);
 
 /* ------------------------------------------------------- candidate sets (Sec. 2.1)
  * Host-only.  For every edge (i<j, row-major order) of the undirected
@@ -154,12 +193,24 @@ typedef struct fpc_params {
     double recheck_margin;/* mixed: FP32 tests with |z - q| below this (plus the per-test
                              error bound) are re-run in FP64; <= 0 selects 1e-3             */
     int32_t schedule;     /* FPC_REVERSE or FPC_FORWARD                                      */
-    int32_t order;        /* FPC_ORDER_LEX or FPC_ORDER_SCORED                               */
+    int32_t order;        /* FPC_ORDER_LEX or FPC_ORDER_LEARNED                              */
     const void *order_model; /* FPC_ORDER_LEARNED: device buffer of fpc_mlp_bytes() bytes
                                 (fpc_mlp_init); NULL otherwise                                */
     int64_t max_tests;    /* 0 = unlimited, else FPC_EBUDGET past this many tests            */
     double q_override;    /* NaN: q = Phi^{-1}(1 - alpha/2); else this threshold            */
     uint32_t flags;       /* FPC_FLAG_* bits, 0 for the defaults                             */
+    double ill_cond_tau;  /* mixed: FP32 tests whose conditioning rho = (smallest Cholesky
+                             pivot of C_KK) * min(h11, h22) lies below this are re-run in
+                             FP64 whatever their z (the Cholesky of ill-conditioned
+                             submatrices in FP64).  Decisions never depend on it: the
+                             FP32 error band already scales as 1/rho.  1e-4 (the Python
+                             default) guards the first-order error bound; 0 disables;
+                             < 0 selects the strict threshold sqrt(n-l-3) (l+2)
+                             (2^-24 + e) / 2.5e-3, e the largest entry error of the FP32
+                             matrix, under which the FP32 z of every test decided in FP32
+                             lies within 1e-4 of the FP64 z (more tests re-run)          */
+    int32_t c32_method;   /* mixed: FP32 matrix of the tests, FPC_CORR_BF16X6 (default, 0
+                             selects it), FPC_CORR_BF16X3 or FPC_CORR_FP32                */
 } fpc_params;
 
 typedef struct fpc_level_stats {

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfastpc.so")
 
 FPC_OK, FPC_EINVAL, FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET, FPC_ENOMEM, FPC_EDEVICE = range(7)
 FPC_F64, FPC_F32 = 0, 1
-FPC_CORR_FP64, FPC_CORR_BF16X3 = 0, 1
+FPC_CORR_FP64, FPC_CORR_BF16X3, FPC_CORR_BF16X6, FPC_CORR_FP32 = 0, 1, 2, 3
 FPC_PREC_FP64, FPC_PREC_MIXED = 0, 1
 FPC_REVERSE, FPC_FORWARD = 0, 1
 FPC_ORDER_LEX, FPC_ORDER_LEARNED = 0, 1
@@ -27,12 +27,13 @@ FPC_SEP_NONE, FPC_SEP_LIST, FPC_SEP_ALL_BUT = 0, 1, 2
 FPC_FLAG_PER_TEST_KERNEL = 1
 FPC_FLAG_LOG_FEATURES = 2
 FPC_FLAG_GRAPH = 4
+FPC_KERNEL_AUTO, FPC_KERNEL_PER_TEST, FPC_KERNEL_PAIR, FPC_KERNEL_TRIPLE, FPC_KERNEL_GLOBAL = range(5)
 
 EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "fpc_quantile",
             "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton", "fpc_skeleton_batch",
             "fpc_result_free", "fpc_orient", "fpc_mlp_bytes", "fpc_mlp_params", "fpc_mlp_init", "fpc_mlp_get",
             "fpc_mlp_forward", "fpc_mlp_grad", "fpc_mlp_train_step", "fpc_get_tuning", "fpc_set_tuning",
-            "fpc_set_recheck_queue"]
+            "fpc_set_recheck_queue", "fpc_level_series"]
 FPC_TUNE_LEVELS = 17
 TUNING_FIELDS = ("test_ranks_per_wave", "shared_ranks_per_wave", "window_growth", "first_window_items",
                  "max_blocks_per_cu", "shared_prefix_depth")
@@ -56,7 +57,8 @@ class fpc_params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("recheck_margin", ctypes.c_double),
                 ("schedule", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("order_model", ctypes.c_void_p), ("max_tests", ctypes.c_int64),
-                ("q_override", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("q_override", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("ill_cond_tau", ctypes.c_double), ("c32_method", ctypes.c_int32)]
 
 
 class fpc_level_stats(ctypes.Structure):
@@ -118,6 +120,8 @@ def _load():
     lib.fpc_first_level.restype = i
     lib.fpc_ci_batch.argtypes = [vp, vp, i, i, i, i, vp, i64, d, vp, vp]
     lib.fpc_ci_batch.restype = i
+    lib.fpc_level_series.argtypes = [vp, vp, i, i, i, i, i, i, vp, i, i64, i64, i, i, i, d, d, d, d, vp, vp]
+    lib.fpc_level_series.restype = i
     lib.fpc_candidates.argtypes = [vp, i, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp, vp]
     lib.fpc_candidates.restype = i
     lib.fpc_skeleton.argtypes = [vp, ctypes.POINTER(fpc_params), ctypes.POINTER(ctypes.POINTER(fpc_result))]
@@ -357,6 +361,28 @@ def fpc_ci_batch(ctx: Context, C, n: int, B, q: float):
     return z, ind
 
 
+def fpc_level_series(ctx: Context, C, n: int, l: int, i: int, j: int, cand, rank_lo: int, rank_hi: int, q: float,
+                     kernel: int = FPC_KERNEL_AUTO, ranks_per_wave: int = 0, pair_table: int = -1,
+                     band_z: float = 1e-3, c_err: float = 0.0, ill_cond_tau: float = 1e-4):
+    """(r, dec) of the level-l tests ranked rank_lo..rank_hi-1 of the pair
+    (i, j) with candidate list ``cand`` (host sequence), run by the level
+    kernels on the device matrix C (FP64: FP64 kernels; FP32: the mixed
+    form's FP32 kernels).  r: FP64 device tensor (NaN = degenerate); dec:
+    uint8 device tensor (0 dependent, 1 independent, 2 FP64 re-run)."""
+    import torch
+
+    C = C.contiguous()
+    cand = np.ascontiguousarray(np.asarray(cand, dtype=np.int32).reshape(-1))
+    k = int(rank_hi) - int(rank_lo)
+    r = torch.empty(max(k, 1), dtype=torch.float64, device=C.device)
+    dec = torch.empty(max(k, 1), dtype=torch.uint8, device=C.device)
+    _check(_lib.fpc_level_series(ctx.handle, _t_ptr(C), _dtype_code(C), C.shape[0], int(n), int(l), int(i), int(j),
+                                 _np_ptr(cand) if cand.size else None, cand.size, int(rank_lo), int(rank_hi),
+                                 int(kernel), int(ranks_per_wave), int(pair_table), float(q), float(band_z),
+                                 float(c_err), float(ill_cond_tau), _t_ptr(r), _t_ptr(dec)), "fpc_level_series")
+    return r[:k], dec[:k]
+
+
 def fpc_mlp_bytes() -> int:
     return int(_lib.fpc_mlp_bytes())
 
@@ -414,7 +440,8 @@ def fpc_mlp_train_step(ctx: Context, X, y, model, lr: float) -> float:
 
 def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, precision: int = FPC_PREC_FP64,
                  recheck_margin: float = 1e-3, schedule: int = FPC_REVERSE, max_tests: int = 0,
-                 q_override: float = float("nan"), flags: int = 0, order_model=None) -> dict:
+                 q_override: float = float("nan"), flags: int = 0, order_model=None, ill_cond_tau: float = 1e-4,
+                 c32_method: int = FPC_CORR_BF16X6) -> dict:
     """Skeleton and separating sets of the data X (torch tensor on the
     device, or a host numpy array), n x p row-major."""
     prm = fpc_params()
@@ -444,6 +471,8 @@ def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, prec
     prm.max_tests = int(max_tests)
     prm.q_override = float(q_override)
     prm.flags = int(flags)
+    prm.ill_cond_tau = float(ill_cond_tau)
+    prm.c32_method = int(c32_method)
     res = ctypes.POINTER(fpc_result)()
     _check(_lib.fpc_skeleton(ctx.handle, ctypes.byref(prm), ctypes.byref(res)), "fpc_skeleton")
     return _unpack(res)
@@ -451,7 +480,8 @@ def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, prec
 
 def fpc_skeleton_batch(ctx: Context, instances, alpha: float = 0.01, max_level: int = -1,
                        precision: int = FPC_PREC_FP64, recheck_margin: float = 1e-3, max_tests: int = 0,
-                       q_override: float = float("nan"), flags: int = 0) -> list:
+                       q_override: float = float("nan"), flags: int = 0, ill_cond_tau: float = 1e-4,
+                       c32_method: int = FPC_CORR_BF16X6) -> list:
     """Skeletons of several instances in one call.  ``instances`` is a
     sequence of (X, rows): X a device tensor (x_rows x p, one dtype for
     all), rows None (the instance is X itself) or a device int32 tensor of
@@ -492,6 +522,8 @@ def fpc_skeleton_batch(ctx: Context, instances, alpha: float = 0.01, max_level: 
     prm.max_tests = int(max_tests)
     prm.q_override = float(q_override)
     prm.flags = int(flags)
+    prm.ill_cond_tau = float(ill_cond_tau)
+    prm.c32_method = int(c32_method)
     outs = (ctypes.POINTER(fpc_result) * max(len(instances), 1))()
     _check(_lib.fpc_skeleton_batch(ctx.handle, ctypes.byref(prm), len(instances), arr, outs), "fpc_skeleton_batch")
     owners = [_Owner(ctypes.cast(outs[k], ctypes.POINTER(fpc_result))) for k in range(len(instances))]

@@ -104,17 +104,18 @@ struct DirectRows {
 };
 
 // ------------------------------------------------------------------ one test
-// r and the smallest pivot (d of K, h11, h22) of the factorisation; ok is
-// false for a degenerate test (pivot <= 0, h11 or h22 <= 0, |r| >= 1).
+// r and the conditioning measure rho = (smallest pivot of C_KK) *
+// min(h11, h22) of the factorisation; ok is false for a degenerate test
+// (pivot <= 0, h11 or h22 <= 0, |r| >= 1).
 template <typename T, int L, class View>
-__device__ __forceinline__ void pcor_reg(const View &V, const int *k, T &r, T &dmin, bool &ok)
+__device__ __forceinline__ void pcor_reg(const View &V, const int *k, T &r, T &rho, bool &ok)
 {
     constexpr int LL = L > 0 ? L : 1;
     T Lf[L > 0 ? L * (L + 1) / 2 : 1];
     T u[LL], v[LL], inv[LL];
     int rw[LL];
     ok = true;
-    dmin = T(1);
+    T dmin = T(1);
     T h11 = T(1), h22 = T(1), h12 = V.ij();
 #pragma unroll
     for (int t = 0; t < L; ++t) rw[t] = V.row(k[t]);
@@ -149,8 +150,7 @@ __device__ __forceinline__ void pcor_reg(const View &V, const int *k, T &r, T &d
         h12 -= u[t] * v[t];
     }
     ok = ok && (h11 > T(0)) && (h22 > T(0));
-    dmin = h11 < dmin ? h11 : dmin;
-    dmin = h22 < dmin ? h22 : dmin;
+    rho = dmin * (h11 < h22 ? h11 : h22);
     r = h12 * rsq(h11 * h22);
     ok = ok && (fabs(r) < T(1));
 }
@@ -164,6 +164,7 @@ struct Thresholds {
     double c_eff;   // mixed: entry error bound of the FP32 matrix + FP32 rounding
     double rb_lo;   // mixed: tanh((q - band_z) / sqrt_nu)
     double rb_hi;   // mixed: tanh((q + band_z) / sqrt_nu)
+    double tau;     // mixed: FP32 tests with rho below this are re-run in FP64
 };
 
 // Per-instance parameters of a level: the matrices, their row stride and
@@ -186,14 +187,21 @@ __device__ __forceinline__ bool decide64(double r, bool ok, const Thresholds &th
     return th.sqrt_nu * fabs(atanh(r)) <= th.q;
 }
 
+// Mixed form, per-test kernel: decided in FP32 when z lies outside the
+// band of q (stated margin plus the error bound of this test), else left to
+// the FP64 re-run, as are ill-conditioned tests (rho below tau).  The bound:
+// an absolute error e in the entries of the (l+2)x(l+2) matrix (FP32 matrix
+// and arithmetic) moves H by at most about (l+2) e / dmin(C_KK) and r by at
+// most twice that over min(h11, h22), i.e. 2 (l+2) e / rho; z by that times
+// sqrt(n-l-3) / (1 - r^2).  kErrSafety covers the factor 2 and more.
 template <int L>
-__device__ __forceinline__ int decide32(float r, float dmin, bool ok, const Thresholds &th)
+__device__ __forceinline__ int decide32(float r, float rho, bool ok, const Thresholds &th)
 {
-    if (!ok) return DEC_RECHECK;
+    if (!ok || !(rho >= (float)th.tau)) return DEC_RECHECK;
     const float a = fabsf(r);
     const float snu = (float)th.sqrt_nu;
     const float z = snu * 0.5f * __logf((1.0f + a) / (1.0f - a));
-    const float err = (float)kErrSafety * snu * (float)th.c_eff * (float)(L + 2) / (dmin * (1.0f - a * a));
+    const float err = (float)kErrSafety * snu * (float)th.c_eff * (float)(L + 2) / (rho * (1.0f - a * a));
     const float band = (float)th.band_z + err;
     const float qf = (float)th.q;
     if (z < qf - band) return DEC_INDEP;
@@ -333,6 +341,11 @@ struct LevelArgs {
     int ranks_per_block;
     int max_m;  // largest candidate set of the level
     int pdec_n;  // entries of the triple kernel's pair table
+    // diagnostic run (fpc_level_series): r and the decision of every rank
+    // of the window at [rank - diag_lo]; no early exit, no recheck queue
+    double *diag_r;
+    uint8_t *diag_dec;
+    int64_t diag_lo;
 };
 
 __device__ __forceinline__ int64_t uniform_i64(int64_t v)
@@ -485,15 +498,23 @@ __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsi
             bool more = true;
             if constexpr (L > 0) more = walk64<L>(c, m, lane, my);
             const bool valid = base + lane < whi;
-            T r, dmin;
+            T r, rho;
             bool ok;
-            if constexpr (TILE) pcor_reg<T, L>(tile, my, r, dmin, ok);
-            else pcor_reg<T, L>(glob, my, r, dmin, ok);
+            if constexpr (TILE) pcor_reg<T, L>(tile, my, r, rho, ok);
+            else pcor_reg<T, L>(glob, my, r, rho, ok);
             int dec;
             if constexpr (sizeof(T) == 8) dec = decide64((double)r, ok, th) ? DEC_INDEP : DEC_DEP;
-            else dec = decide32<L>((float)r, (float)dmin, ok, th);
+            else dec = decide32<L>((float)r, (float)rho, ok, th);
             const uint64_t nvalid = (uint64_t)min((int64_t)64, whi - base);
             executed += nvalid;
+            if (A.diag_r) {  // uniform
+                if (valid) {
+                    A.diag_r[base + lane - A.diag_lo] = ok ? (double)r : (double)NAN;
+                    A.diag_dec[base + lane - A.diag_lo] = (uint8_t)dec;
+                }
+                if (!more) break;
+                continue;
+            }
             if constexpr (sizeof(T) == 4) {
                 const bool rq = valid && dec == DEC_RECHECK;
                 const unsigned long long qb = __ballot(rq);
@@ -572,9 +593,9 @@ __global__ __launch_bounds__(256) void recheck_kernel(LevelArgs A)
             }
             const InstRec &I = A.inst[E.inst];
             GlobalRows<double> g{I.C64, (int)I.ld, A.cand + E.cand_off, E.i, E.j};
-            double r, dmin;
+            double r, rho;
             bool ok;
-            pcor_reg<double, L>(g, k, r, dmin, ok);
+            pcor_reg<double, L>(g, k, r, rho, ok);
             if (decide64(r, ok, I.th)) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
         }
         // re-run counts: one atomic per wave when the wave's re-runs share
@@ -642,16 +663,17 @@ __device__ __forceinline__ void put_int(double &d, int v) { d = (double)v; }
 __device__ __forceinline__ int get_int(float d) { return __float_as_int(d); }
 __device__ __forceinline__ int get_int(double d) { return (int)d; }
 
-// Decision of one FP32 pair test in r space (band and error bound):
-// independent when |r| < rlo - errk/dmin, dependent when |r| > rhi +
-// errk/dmin, else re-run in FP64; dmin > 0 whenever ok, so the bounds are
-// compared after multiplying through by dmin.
-__device__ __forceinline__ int decide32r(float r, float dmin, bool ok, float rlo, float rhi, float errk)
+// Decision of one FP32 shared-prefix test in r space (band and error bound,
+// as in decide32): independent when |r| < rlo - errk/rho, dependent when
+// |r| > rhi + errk/rho, else re-run in FP64, as are tests with rho below
+// tau (ill-conditioned); rho > 0 whenever ok, so the bounds are compared
+// after multiplying through by rho.
+__device__ __forceinline__ int decide32r(float r, float rho, bool ok, float rlo, float rhi, float errk, float tau)
 {
-    if (!ok) return DEC_RECHECK;
+    if (!ok || !(rho >= tau)) return DEC_RECHECK;
     const float a = fabsf(r);
-    if ((rlo - a) * dmin > errk) return DEC_INDEP;
-    if ((a - rhi) * dmin > errk) return DEC_DEP;
+    if ((rlo - a) * rho > errk) return DEC_INDEP;
+    if ((a - rhi) * rho > errk) return DEC_DEP;
     return DEC_RECHECK;
 }
 
@@ -728,7 +750,7 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
     int64_t remaining = whi - wlo;
     uint64_t executed = 0;
     const float errk = (float)(kErrSafety * th.c_eff * (L + 2));
-    const float rlo32 = (float)th.rb_lo, rhi32 = (float)th.rb_hi;
+    const float rlo32 = (float)th.rb_lo, rhi32 = (float)th.rb_hi, tau32 = (float)th.tau;
     while (remaining > 0) {
         const unsigned long long mh = (unsigned long long)uniform_i64((int64_t)load_minhit(&A.minhit[e]));
         if (mh < (unsigned long long)rank) break;
@@ -837,11 +859,17 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
             if constexpr (sizeof(T) == 8) {
                 dec = decide64((double)r, ok, th) ? DEC_INDEP : DEC_DEP;
             } else {
-                const float dmin = fminf(fminf((float)dminQ, fminf((float)d1, (float)d2)),
-                                         fminf((float)h11, (float)h22));
-                dec = decide32r((float)r, dmin, ok, rlo32, rhi32, errk);
+                const float rho = fminf((float)dminQ, fminf((float)d1, (float)d2)) * fminf((float)h11, (float)h22);
+                dec = decide32r((float)r, rho, ok, rlo32, rhi32, errk, tau32);
             }
             executed += (uint64_t)min(64, cnt - it);
+            if (A.diag_r) {  // uniform
+                if (valid) {
+                    A.diag_r[rank + it + lane - A.diag_lo] = ok ? (double)r : (double)NAN;
+                    A.diag_dec[rank + it + lane - A.diag_lo] = (uint8_t)dec;
+                }
+                continue;
+            }
             if constexpr (sizeof(T) == 4) {
                 const bool rq = valid && dec == DEC_RECHECK;
                 const unsigned long long qb = __ballot(rq);
@@ -1015,7 +1043,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
     int64_t remaining = uniform_i64(whi - wlo);
     uint64_t executed = 0;
     const float errk = (float)(kErrSafety * th.c_eff * (L + 2));
-    const float rlo32 = (float)th.rb_lo, rhi32 = (float)th.rb_hi;
+    const float rlo32 = (float)th.rb_lo, rhi32 = (float)th.rb_hi, tau32 = (float)th.tau;
     bool stop = false;
     int since_check = kMinhitEvery;  // tests since the shared minimum was last read
     while (!stop) {
@@ -1154,18 +1182,26 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                 const T h12 = H12a - ub * vb - uc * vc;
                 const T r = h12 * rsqv(h11 * h22);
                 int dec;
+                bool ok;
                 if constexpr (sizeof(T) == 8) {
-                    const bool ok = oka && sbb > T(0) && d3 > T(0) && h11 > T(0) && h22 > T(0) && fabs(r) < T(1);
+                    ok = oka && sbb > T(0) && d3 > T(0) && h11 > T(0) && h22 > T(0) && fabs(r) < T(1);
                     dec = decide64((double)r, ok, th) ? DEC_INDEP : DEC_DEP;
                 } else {
-                    // smallest pivot through the bit patterns: > 0 as an integer
+                    // smallest pivots through the bit patterns: > 0 as an integer
                     // exactly when every pivot is a positive float (a negative
                     // one or a zero becomes the minimum).  A NaN needs a zero or
                     // denormal pivot upstream, which is then the minimum and
-                    // makes every decision a recheck (margin * dmin <= errk).
-                    const float dmin = pos_min(pos_min(dmina, pos_min(sbb, d3)), pos_min(h11, h22));
-                    const bool ok = oka && __float_as_int(dmin) > 0 && fabsf(r) < 1.0f;
-                    dec = decide32r(r, dmin, ok, rlo32, rhi32, errk);
+                    // makes rho tiny: the test goes to the FP64 re-run.
+                    const float dK = pos_min(dmina, pos_min(sbb, d3)), hmin = pos_min(h11, h22);
+                    ok = oka && __float_as_int(pos_min(dK, hmin)) > 0 && fabsf(r) < 1.0f;
+                    dec = decide32r(r, dK * hmin, ok, rlo32, rhi32, errk, tau32);
+                }
+                if (A.diag_r) {  // uniform
+                    if (valid) {
+                        A.diag_r[rank + it + lane - A.diag_lo] = ok ? (double)r : (double)NAN;
+                        A.diag_dec[rank + it + lane - A.diag_lo] = (uint8_t)dec;
+                    }
+                    continue;
                 }
                 if constexpr (sizeof(T) == 4) {
                     const bool rq = valid && dec == DEC_RECHECK;
@@ -1421,6 +1457,13 @@ __device__ __forceinline__ void wide_item(const LevelArgs &A, int l, int64_t blk
                   : a > th.r_hi ? false
                   : th.sqrt_nu * fabs(atanh((double)r)) <= th.q;
         }
+        if (A.diag_r) {
+            if (lane == 0) {
+                A.diag_r[R - A.diag_lo] = ok ? (double)r : (double)NAN;
+                A.diag_dec[R - A.diag_lo] = indep ? DEC_INDEP : DEC_DEP;
+            }
+            indep = false;
+        }
         if (indep) {
             if (lane == 0) atomicMin((unsigned long long *)&A.minhit[e], (unsigned long long)R);
             break;
@@ -1640,9 +1683,9 @@ __global__ __launch_bounds__(256) void batch_kernel(const T *__restrict__ C, int
         return;
     }
     DirectRows<T> V{C, p, Br[0], Br[1]};
-    T r, dmin;
+    T r, rho;
     bool ok;
-    pcor_reg<T, L>(V, k, r, dmin, ok);
+    pcor_reg<T, L>(V, k, r, rho, ok);
     double z = NAN;
     uint8_t ind = 0;
     if (ok) {
@@ -1746,9 +1789,10 @@ void launch_batch(int l, dim3 g, hipStream_t st, const T *C, int p, const int32_
     }
 }
 
-Thresholds make_thresholds(double q, int n, int l, double band_z, double c_eff)
+Thresholds make_thresholds(double q, int n, int l, double band_z, double c_eff, double tau = 0.0)
 {
     Thresholds th;
+    th.tau = tau;
     th.q = q;
     th.sqrt_nu = std::sqrt((double)(n - l - 3));
     const double rt = std::tanh(q / th.sqrt_nu);
@@ -1767,6 +1811,20 @@ Thresholds make_thresholds(double q, int n, int l, double band_z, double c_eff)
         th.rb_hi = 2.0;
     }
     return th;
+}
+
+// Threshold of the ill-conditioning trigger: tau >= 0 as given; negative
+// selects the default, the rho below which the FP32 error model of a test,
+// sqrt(n-l-3) (l+2) (2^-24 + c_err) / rho in z units (FP32 arithmetic and
+// the entry error of the FP32 matrix), exceeds kZModelCap.  Measured FP32 z
+// errors stay below 0.04 of that model (level 5 of the p = 1000 benchmark
+// graph on an FP32-rounded matrix, about 1e6 tests), so the FP32 z of every
+// test left in FP32 is then within 1e-4.
+constexpr double kZModelCap = 1e-4 / 0.04;
+double resolve_tau(double tau, int n, int l, double c_err)
+{
+    if (tau >= 0.0) return tau;
+    return std::sqrt((double)(n - l - 3)) * (l + 2) * (0x1p-24 + c_err) / kZModelCap;
 }
 
 size_t tile_bytes(int m, size_t elem) { return elem * ((size_t)m * (m - 1) / 2 + 2 * (size_t)m + 1) + 16; }
@@ -1842,23 +1900,39 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     for (int c = 0; c < nlc; ++c) {
         Cls k{lc[c].begin, lc[c].end, lc[c].max_m, K_GLOBAL, 0, 0, 0, {}};
         if (k.begin < 0 || k.end > E || k.begin >= k.end) return FPC_EINVAL;
+        const int fk = Lv.force_kernel;
         if (wide) {
+            if (fk != 0) return FPC_EINVAL;  // levels above the register kernels have one kernel
             k.kind = K_WIDE;
             k.shm = 8 * ((size_t)(l + 2) * (l + 3) / 2 + 1) + sizeof(int) * (l + 1) + 16;
             if (k.shm > lds_cap) return FPC_EBUDGET;
         } else {
-            const size_t ps = shared_lds_bytes(ctx, l, fp32, k.max_m);
-            if (l >= 2 && ctx->use_pair_kernel && ps <= lds_cap) {
-                k.kind = use_triple(ctx, l) ? K_TRIPLE : K_PAIR;
+            // shared-prefix kernel: the triple form when the tuning table (or
+            // the caller) asks for it, else the pair form
+            const bool triple = fk ? fk == FPC_KERNEL_TRIPLE : use_triple(ctx, l);
+            if ((fk == FPC_KERNEL_PAIR && l < 2) || (fk == FPC_KERNEL_TRIPLE && l < 3)) return FPC_EINVAL;
+            const size_t ps = l < 2 ? 0
+                            : triple ? (fp32 ? triple_lds_bytes<float>(l, k.max_m) : triple_lds_bytes<double>(l, k.max_m))
+                                     : (fp32 ? pair_lds_bytes<float>(l, k.max_m) : pair_lds_bytes<double>(l, k.max_m));
+            const bool shared = fk ? (fk == FPC_KERNEL_PAIR || fk == FPC_KERNEL_TRIPLE)
+                                   : (l >= 2 && ctx->use_pair_kernel && ps <= lds_cap);
+            if (shared) {
+                if (ps > lds_cap) return FPC_EINVAL;
+                k.kind = triple ? K_TRIPLE : K_PAIR;
                 k.shm = ps;
                 if (k.kind == K_TRIPLE) {
                     k.pdec_n = triple_table_entries(l, fp32, k.max_m, ps, (size_t)ctx->lds_per_cu, lds_cap,
                                                     ctx->tuning.max_blocks_per_cu[lt]);
+                    if (Lv.force_pdec >= 0) {
+                        const int full = k.max_m > 2 ? std::min((k.max_m - 1) * (k.max_m - 2) / 2, kPdecCap) : 0;
+                        k.pdec_n = std::min(Lv.force_pdec, full);
+                        if (ps + pdec_bytes(k.pdec_n) > lds_cap) return FPC_EINVAL;
+                    }
                     k.shm += pdec_bytes(k.pdec_n);
                 }
             } else {
                 const size_t ts = tile_bytes(k.max_m, fp32 ? 4 : 8);
-                k.kind = ts <= std::min<size_t>(lds_cap, 65536) ? K_TILE : K_GLOBAL;
+                k.kind = fk != FPC_KERNEL_GLOBAL && ts <= std::min<size_t>(lds_cap, 65536) ? K_TILE : K_GLOBAL;
                 k.shm = k.kind == K_TILE ? ts : 0;
             }
         }
@@ -1867,12 +1941,17 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
         k.rpb = k.kind == K_WIDE ? kGenericRanks
               : (k.kind == K_TRIPLE || k.kind == K_PAIR) ? kWaves * tu.shared_ranks_per_wave[lt]
                                                            : kWaves * tu.test_ranks_per_wave[lt];
-        int64_t maxN = 0;
-        for (int64_t e = k.begin; e < k.end; ++e) maxN = std::max(maxN, ntests[e]);
-        k.wins.push_back(0);
-        for (int64_t w = (int64_t)k.rpb * std::max(1, ctx->tuning.first_window_items[lt]); k.wins.back() < maxN;
-             w *= std::max(2, ctx->tuning.window_growth[lt]))
-            k.wins.push_back(std::min<int64_t>(maxN, k.wins.back() + w));
+        if (Lv.force_rpw > 0 && k.kind != K_WIDE) k.rpb = kWaves * Lv.force_rpw;
+        if (Lv.diag_r) {  // one window: the requested ranks
+            k.wins = {Lv.diag_lo, Lv.diag_hi};
+        } else {
+            int64_t maxN = 0;
+            for (int64_t e = k.begin; e < k.end; ++e) maxN = std::max(maxN, ntests[e]);
+            k.wins.push_back(0);
+            for (int64_t w = (int64_t)k.rpb * std::max(1, ctx->tuning.first_window_items[lt]); k.wins.back() < maxN;
+                 w *= std::max(2, ctx->tuning.window_growth[lt]))
+                k.wins.push_back(std::min<int64_t>(maxN, k.wins.back() + w));
+        }
         max_nw = std::max(max_nw, (int)k.wins.size() - 1);
         cls.push_back(std::move(k));
     }
@@ -1890,7 +1969,8 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
         hin[k].C = fp32 ? (const void *)I.C32 : (const void *)I.C64;
         hin[k].C64 = I.C64;
         hin[k].ld = I.p;
-        hin[k].th = make_thresholds(I.q, I.n, l, Lv.band_z, I.c_err + 4.0 * (l + 2) * 6.0e-8);
+        hin[k].th = make_thresholds(I.q, I.n, l, Lv.band_z, I.c_err + 4.0 * (l + 2) * 6.0e-8,
+                                    resolve_tau(Lv.ill_cond_tau, I.n, l, I.c_err));
     }
     if ((rc = upload_enqueue(ctx, ctx->insts.ptr, ctx->h_inst, 0, sizeof(InstRec) * (size_t)ni))) return rc;
 
@@ -1911,6 +1991,9 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     A.inst_cnt = Lv.inst_cnt;
     A.queue = Lv.queue;
     A.queue_cap = Lv.queue_cap;
+    A.diag_r = Lv.diag_r;
+    A.diag_dec = Lv.diag_dec;
+    A.diag_lo = Lv.diag_lo;
 
     const int cus = ctx->num_cus;
     const size_t lds_cu = (size_t)ctx->lds_per_cu;
@@ -1946,7 +2029,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             // halves its items while they still fit one resident round (an
             // edge's result does not depend on how its ranks are cut; every
             // item stages its tile again, so more rounds would cost more).
-            if (k.kind == K_TRIPLE) {
+            if (k.kind == K_TRIPLE && Lv.force_rpw == 0) {
                 const int64_t slots =
                     (int64_t)cus * triple_blocks_per_cu(l, fp32, k.shm, lds_cu, ctx->tuning.max_blocks_per_cu[lt]);
                 while (rpb / 2 >= kWaves * kSplitMinRanksPerWave) {
@@ -2026,7 +2109,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             if (err != hipSuccess) break;
         }
         // FP64 re-run of the window's queue (level edge indices)
-        if (fp32 && window_open && err == hipSuccess) {
+        if (fp32 && window_open && err == hipSuccess && !Lv.diag_r) {
             LevelArgs Q = A;
             Q.edges = Lv.edges;
             Q.minhit = Lv.minhit;
@@ -2170,7 +2253,84 @@ int ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, cons
     return hbad ? FPC_EINVAL : FPC_OK;
 }
 
+int level_series(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, int i, int j, const int32_t *cand,
+                 int m, int64_t rank_lo, int64_t rank_hi, int kernel, int ranks_per_wave, int pair_table, double q,
+                 double band_z, double c_err, double ill_cond_tau, double *r_out, uint8_t *dec_out)
+{
+    if (std::isnan(ill_cond_tau)) return FPC_EINVAL;
+    if (!C || !r_out || !dec_out || (m > 0 && !cand)) return FPC_EINVAL;
+    if (c_dtype != FPC_F64 && c_dtype != FPC_F32) return FPC_EINVAL;
+    if (p < 2 || i < 0 || j < 0 || i >= p || j >= p || i == j) return FPC_EINVAL;
+    if (l < 0 || m < l || m >= kBinomRows || m > p - 2 || n - l - 3 <= 0) return FPC_EINVAL;
+    if (kernel < FPC_KERNEL_AUTO || kernel > FPC_KERNEL_GLOBAL) return FPC_EINVAL;
+    if (ranks_per_wave != 0 && (ranks_per_wave < 64 || ranks_per_wave > (1 << 20))) return FPC_EINVAL;
+    if (pair_table < -1 || !(q >= 0.0) || !(c_err >= 0.0) || !(band_z >= 0.0)) return FPC_EINVAL;
+    if (l > kMaxTemplL && c_dtype != FPC_F64) return FPC_EINVAL;  // levels above run in FP64 only
+    const int64_t N = binom_sat(m, l);
+    if (N == INT64_MAX || rank_lo < 0 || rank_hi > N || rank_lo >= rank_hi) return FPC_EINVAL;
+    std::vector<uint8_t> seen((size_t)p, 0);
+    for (int t = 0; t < m; ++t) {
+        const int v = cand[t];
+        if (v < 0 || v >= p || v == i || v == j || seen[(size_t)v]) return FPC_EINVAL;
+        seen[(size_t)v] = 1;
+    }
+    hipStream_t st = ctx->stream;
+    int rc;
+    if ((rc = ctx->cand.ensure(sizeof(int32_t) * (size_t)(m + 1)))) return rc;
+    if ((rc = ctx->edges.ensure(sizeof(EdgeRec)))) return rc;
+    if ((rc = ctx->minhit.ensure(sizeof(uint64_t)))) return rc;
+    if ((rc = ctx->counters.ensure(sizeof(unsigned long long) * 10))) return rc;
+    const EdgeRec rec{i, j, m, 0, N, 0, 0};
+    FPC_HIP(hipMemcpyAsync(ctx->edges.ptr, &rec, sizeof(rec), hipMemcpyHostToDevice, st));
+    if (m > 0) FPC_HIP(hipMemcpyAsync(ctx->cand.ptr, cand, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, st));
+    if ((rc = level_init(ctx, ctx->minhit.as<uint64_t>(), 1, ctx->counters.as<unsigned long long>(), 10))) return rc;
+    const bool fp32 = c_dtype == FPC_F32;
+    const LevelInst inst{fp32 ? static_cast<const float *>(C) : nullptr,
+                         fp32 ? nullptr : static_cast<const double *>(C), p, n, q, c_err};
+    LevelLaunch Lv{};
+    Lv.l = l;
+    Lv.max_m = m;
+    Lv.n_edges = 1;
+    Lv.edges = ctx->edges.as<EdgeRec>();
+    Lv.cand = ctx->cand.as<int32_t>();
+    Lv.insts = &inst;
+    Lv.n_insts = 1;
+    Lv.fp32 = fp32;
+    Lv.band_z = band_z;
+    Lv.ill_cond_tau = ill_cond_tau;
+    Lv.minhit = ctx->minhit.as<uint64_t>();
+    Lv.counters = ctx->counters.as<unsigned long long>();
+    Lv.inst_cnt = Lv.counters + 8;
+    Lv.diag_r = r_out;
+    Lv.diag_dec = dec_out;
+    Lv.diag_lo = rank_lo;
+    Lv.diag_hi = rank_hi;
+    Lv.force_kernel = kernel;
+    Lv.force_pdec = pair_table;
+    Lv.force_rpw = ranks_per_wave;
+    // the kernel choice of a level run with the default flags
+    const bool pair_was = ctx->use_pair_kernel;
+    ctx->use_pair_kernel = true;
+    LevelTiming tm;
+    rc = level_tests(ctx, Lv, std::vector<int64_t>{N}, &tm);
+    ctx->use_pair_kernel = pair_was;
+    if (rc) return rc;
+    FPC_HIP(hipStreamSynchronize(st));
+    return FPC_OK;
+}
+
 }  // namespace fpc
+
+extern "C" int fpc_level_series(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, int i, int j,
+                                const int32_t *cand, int m, int64_t rank_lo, int64_t rank_hi, int kernel,
+                                int ranks_per_wave, int pair_table, double q, double band_z, double c_err,
+                                double ill_cond_tau, double *r_out, uint8_t *dec_out)
+{
+    if (!ctx) return FPC_EINVAL;
+    FPC_HIP(hipSetDevice(ctx->device));
+    return fpc::level_series(ctx, C, c_dtype, p, n, l, i, j, cand, m, rank_lo, rank_hi, kernel, ranks_per_wave,
+                             pair_table, q, band_z, c_err, ill_cond_tau, r_out, dec_out);
+}
 
 extern "C" int fpc_ci_batch(fpc_ctx *ctx, const void *C, int c_dtype, int p, int n, int l, const int32_t *B,
                             int64_t b, double q, double *z_out, uint8_t *indep_out)

@@ -9,8 +9,14 @@
 //            z = hi + lo with hi, lo in bf16, and S ~ hi.hi + hi.lo + lo.hi
 //            on the MFMA units (v_mfma_f32_16x16x32_bf16) with FP32
 //            accumulation over chunks of 512 samples, the chunk sums folded
-//            into FP64 registers.
-// Both renormalise by the computed diagonal, so C_ii = 1 exactly.
+//            into FP64 registers.  The dropped lo.lo term is biased for
+//            strongly correlated columns (entry errors up to ~3e-6).
+//   BF16X6   the same with a three-way split z = hi + mid + lo and the six
+//            products of weight above 2^-24: hi.hi, hi.mid, mid.hi,
+//            mid.mid, hi.lo, lo.hi, folded into FP64 after every 32
+//            samples (entry errors of FP32 rounding order).
+//   FP32     the FP64 matrix rounded to FP32.
+// The MFMA forms renormalise by the computed diagonal, so C_ii = 1 exactly.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -197,11 +203,14 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // Standardise and split, writing the transposed copies Zh[j][t], Zl[j][t]
-// (t < npad, zero beyond n) through a 32x32 LDS tile.
-template <typename TX>
+// (and Zm[j][t] for the three-way split; t < npad, zero beyond n) through a
+// 32x32 LDS tile.  Two parts: z = hi + lo; three: z = hi + mid + lo, each
+// part the bf16 rounding of what the parts before it leave.
+template <typename TX, int NPART>
 __global__ __launch_bounds__(256) void split_bf16(const TX *__restrict__ X, const double *__restrict__ mu,
                                                   const double *__restrict__ sd, int n, int p, int npad,
-                                                  __bf16 *__restrict__ Zh, __bf16 *__restrict__ Zl)
+                                                  __bf16 *__restrict__ Zh, __bf16 *__restrict__ Zm,
+                                                  __bf16 *__restrict__ Zl)
 {
     __shared__ float tile[32][33];
     const int t0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
@@ -218,24 +227,39 @@ __global__ __launch_bounds__(256) void split_bf16(const TX *__restrict__ X, cons
         if (j < p && t < npad) {
             const float z = tile[lx][r];
             const __bf16 hi = (__bf16)z;
-            const __bf16 lo = (__bf16)(z - (float)hi);
+            const float r1 = z - (float)hi;  // exact: hi holds the leading 8 bits of z
             Zh[(size_t)j * npad + t] = hi;
-            Zl[(size_t)j * npad + t] = lo;
+            if constexpr (NPART == 2) {
+                Zl[(size_t)j * npad + t] = (__bf16)r1;
+            } else {
+                const __bf16 mid = (__bf16)r1;
+                Zm[(size_t)j * npad + t] = mid;
+                Zl[(size_t)j * npad + t] = (__bf16)(r1 - (float)mid);
+            }
         }
     }
 }
 
-constexpr int kFold = 512;  // samples per FP32 accumulation chunk
+// Samples per FP32 accumulation chunk before the fold into FP64: the
+// rounding of the FP32 sums grows with the chunk, so the three-way split
+// (whose products reach 2^-24) folds after every 32-sample step.
+template <int NPROD>
+constexpr int fold_samples() { return NPROD == 6 ? 32 : 512; }
 
 // One 64x64 upper-triangle tile per block (4 waves, each 32x32 = 2x2 MFMA
 // 16x16 tiles); blockIdx.y is the sample split.  Operand layout of
 // v_mfma_f32_16x16x32_bf16: lane l supplies row (l % 16) and the 8
 // consecutive k values 8*(l/16) .. 8*(l/16)+7; the result element r of
 // lane l is row 4*(l/16) + r, column l % 16.
-__global__ __launch_bounds__(256) void syrk_bf16x3(const __bf16 *__restrict__ Zh,
-                                                   const __bf16 *__restrict__ Zl, int p, int npad,
-                                                   int nbt, int chunk, double *__restrict__ Spart)
+// NPROD = 3: hi.hi + hi.lo + lo.hi over the two-way split (Zm unused);
+// NPROD = 6: hi.hi + hi.mid + mid.hi + mid.mid + hi.lo + lo.hi over the
+// three-way split.
+template <int NPROD>
+__global__ __launch_bounds__(256) void syrk_bf16(const __bf16 *__restrict__ Zh, const __bf16 *__restrict__ Zm,
+                                                 const __bf16 *__restrict__ Zl, int p, int npad,
+                                                 int nbt, int chunk, double *__restrict__ Spart)
 {
+    constexpr bool three = NPROD == 6;
     int bi, bj;
     tile_of(blockIdx.x, nbt, bi, bj);
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -257,7 +281,7 @@ __global__ __launch_bounds__(256) void syrk_bf16x3(const __bf16 *__restrict__ Zh
     const bf16x8 zero = {};
     // operand fragments of the next 32-sample step are loaded while the
     // current step's products run
-    bf16x8 nah[2], nal[2], nbh[2], nbl[2];
+    bf16x8 nah[2], nam[2], nal[2], nbh[2], nbm[2], nbl[2];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
@@ -268,28 +292,47 @@ __global__ __launch_bounds__(256) void syrk_bf16x3(const __bf16 *__restrict__ Zh
             nal[g] = okA ? *reinterpret_cast<const bf16x8 *>(Zl + oA) : zero;
             nbh[g] = okB ? *reinterpret_cast<const bf16x8 *>(Zh + oB) : zero;
             nbl[g] = okB ? *reinterpret_cast<const bf16x8 *>(Zl + oB) : zero;
+            if constexpr (three) {
+                nam[g] = okA ? *reinterpret_cast<const bf16x8 *>(Zm + oA) : zero;
+                nbm[g] = okB ? *reinterpret_cast<const bf16x8 *>(Zm + oB) : zero;
+            }
         }
     };
     fetch(k_lo);
+    constexpr int kFold = fold_samples<NPROD>();
     for (int kc = k_lo; kc < k_hi; kc += kFold) {
         const int kend = min(k_hi, kc + kFold);
         for (int k0 = kc; k0 < kend; k0 += 32) {
-            bf16x8 ah[2], al[2], bh[2], bl[2];
+            bf16x8 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
                 ah[g] = nah[g];
                 al[g] = nal[g];
                 bh[g] = nbh[g];
                 bl[g] = nbl[g];
+                if constexpr (three) {
+                    am[g] = nam[g];
+                    bm[g] = nbm[g];
+                }
             }
             fetch(k0 + 32);
+            // smallest products first, so each lands on a smaller partial sum
 #pragma unroll
             for (int g = 0; g < 2; ++g)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bh[h], acc[g][h], 0, 0, 0);
-                    acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bl[h], acc[g][h], 0, 0, 0);
-                    acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[g], bh[h], acc[g][h], 0, 0, 0);
+                    if constexpr (three) {
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bl[h], acc[g][h], 0, 0, 0);
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[g], bh[h], acc[g][h], 0, 0, 0);
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[g], bm[h], acc[g][h], 0, 0, 0);
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bm[h], acc[g][h], 0, 0, 0);
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[g], bh[h], acc[g][h], 0, 0, 0);
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bh[h], acc[g][h], 0, 0, 0);
+                    } else {
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bh[h], acc[g][h], 0, 0, 0);
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bl[h], acc[g][h], 0, 0, 0);
+                        acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[g], bh[h], acc[g][h], 0, 0, 0);
+                    }
                 }
         }
 #pragma unroll
@@ -330,6 +373,11 @@ __global__ __launch_bounds__(256) void max_abs_diff(const double *__restrict__ a
     if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
 }
 
+__global__ __launch_bounds__(256) void round_f32(const double *__restrict__ a, float *__restrict__ b, size_t cnt)
+{
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < cnt; k += (size_t)gridDim.x * 256) b[k] = (float)a[k];
+}
+
 int splits_for(int tiles, int n, int num_cus)
 {
     int s = (2 * num_cus + tiles - 1) / tiles;
@@ -345,7 +393,16 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
 {
     if (!X || !C_out || n < 2 || p < 1) return FPC_EINVAL;
     if (x_dtype != FPC_F64 && x_dtype != FPC_F32) return FPC_EINVAL;
-    if (method != FPC_CORR_FP64 && method != FPC_CORR_BF16X3) return FPC_EINVAL;
+    if (method != FPC_CORR_FP64 && method != FPC_CORR_BF16X3 && method != FPC_CORR_BF16X6 && method != FPC_CORR_FP32)
+        return FPC_EINVAL;
+    if (method == FPC_CORR_FP32) {
+        // the FP64 matrix, rounded: computed into the context's FP64 buffer
+        // unless the caller's statistics and matrix are already there
+        int rc = ctx->c64.ensure(sizeof(double) * (size_t)p * p);
+        if (rc) return rc;
+        if ((rc = corr_compute(ctx, X, x_dtype, n, p, FPC_CORR_FP64, ctx->c64.ptr, reuse_stats, false))) return rc;
+        return corr_round_enqueue(ctx, ctx->c64.as<double>(), static_cast<float *>(C_out), p, wait);
+    }
     hipStream_t st = ctx->stream;
     const int nchunks = (n + kStatRows - 1) / kStatRows;
     const int nbt = (p + kT - 1) / kT, tiles = nbt * (nbt + 1) / 2;
@@ -385,16 +442,27 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
             syrk_f64<float><<<g, 256, 0, st>>>((const float *)X, mu, n, p, nbt, chunk, Spart);
         normalize<double><<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(Spart, nsplit, p, (double *)C_out);
     } else {
-        if ((rc = ctx->zsplit.ensure(sizeof(__bf16) * 2 * (size_t)p * npad))) return rc;
+        const bool three = method == FPC_CORR_BF16X6;
+        const int nparts = three ? 3 : 2;
+        if ((rc = ctx->zsplit.ensure(sizeof(__bf16) * nparts * (size_t)p * npad))) return rc;
         __bf16 *Zh = ctx->zsplit.as<__bf16>(), *Zl = Zh + (size_t)p * npad;
+        __bf16 *Zm = three ? Zl + (size_t)p * npad : nullptr;
         dim3 gs(npad / 32, (p + 31) / 32);
-        if (x_dtype == FPC_F64)
-            split_bf16<double><<<gs, 256, 0, st>>>((const double *)X, mu, sd, n, p, npad, Zh, Zl);
-        else
-            split_bf16<float><<<gs, 256, 0, st>>>((const float *)X, mu, sd, n, p, npad, Zh, Zl);
+        if (three) {
+            if (x_dtype == FPC_F64)
+                split_bf16<double, 3><<<gs, 256, 0, st>>>((const double *)X, mu, sd, n, p, npad, Zh, Zm, Zl);
+            else
+                split_bf16<float, 3><<<gs, 256, 0, st>>>((const float *)X, mu, sd, n, p, npad, Zh, Zm, Zl);
+        } else {
+            if (x_dtype == FPC_F64)
+                split_bf16<double, 2><<<gs, 256, 0, st>>>((const double *)X, mu, sd, n, p, npad, Zh, Zm, Zl);
+            else
+                split_bf16<float, 2><<<gs, 256, 0, st>>>((const float *)X, mu, sd, n, p, npad, Zh, Zm, Zl);
+        }
         const int chunk = ((npad + nsplit - 1) / nsplit + 31) / 32 * 32;
         dim3 g(tiles, nsplit);
-        syrk_bf16x3<<<g, 256, 0, st>>>(Zh, Zl, p, npad, nbt, chunk, Spart);
+        if (three) syrk_bf16<6><<<g, 256, 0, st>>>(Zh, Zm, Zl, p, npad, nbt, chunk, Spart);
+        else syrk_bf16<3><<<g, 256, 0, st>>>(Zh, Zm, Zl, p, npad, nbt, chunk, Spart);
         normalize<float><<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(Spart, nsplit, p, (float *)C_out);
     }
     FPC_HIP(hipGetLastError());
@@ -459,6 +527,14 @@ int gather_rows(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p,
     FPC_HIP(hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, st));
     FPC_HIP(hipStreamSynchronize(st));
     return h ? FPC_EINVAL : FPC_OK;
+}
+
+int corr_round_enqueue(fpc_ctx *ctx, const double *c64, float *c32, int p, bool wait)
+{
+    const size_t cnt = (size_t)p * p;
+    round_f32<<<(unsigned)std::min<size_t>((cnt + 255) / 256, 2048), 256, 0, ctx->stream>>>(c64, c32, cnt);
+    FPC_HIP(hipGetLastError());
+    return wait ? corr_check(ctx, nullptr) : FPC_OK;
 }
 
 int corr_max_abs_diff_enqueue(fpc_ctx *ctx, const double *c64, const float *c32, int p)

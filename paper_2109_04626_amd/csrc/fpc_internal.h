@@ -120,6 +120,8 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
 // With wait = false the products are only queued: corr_check waits once for
 // every queued correlation (and max_abs_diff) and reports their flags.
 int corr_max_abs_diff_enqueue(fpc_ctx *ctx, const double *c64, const float *c32, int p);
+// c32 := FP32 rounding of c64 (device, p x p), queued.
+int corr_round_enqueue(fpc_ctx *ctx, const double *c64, float *c32, int p, bool wait);
 int corr_check(fpc_ctx *ctx, double *max_abs_diff);
 // out (device, n x p) := rows[r] of X (device, x_rows x p); FPC_EINVAL for an index out of range.
 int gather_rows(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p, const int32_t *rows, int n,
@@ -163,11 +165,21 @@ struct LevelLaunch {
     bool fp32;                     // tests in FP32 with FP64 recheck
     bool graph;                    // capture the level's launches in one HIP graph
     double band_z;                 // recheck margin in z units
+    double ill_cond_tau = -1.0;    // FP32 tests with rho below this go to FP64 (< 0: the default)
     uint64_t *minhit;              // device, per edge
     unsigned long long *counters;  // device: [1] recheck queue length, [3] queue overflow
     unsigned long long *inst_cnt;  // device, per instance: [2k] tests executed, [2k+1] re-run in FP64
     int64_t *queue;                // device, 2 * queue_cap entries (edge, rank)
     int64_t queue_cap;
+    // diagnostic run (fpc_level_series): one window [diag_lo, diag_hi) of
+    // ranks, r and the decision of every rank written at [rank - diag_lo],
+    // no early exit and no FP64 re-run
+    double *diag_r = nullptr;
+    uint8_t *diag_dec = nullptr;
+    int64_t diag_lo = 0, diag_hi = 0;
+    int force_kernel = 0;          // FPC_KERNEL_*; 0: the kernel the level would choose
+    int force_pdec = -1;           // triple kernel: pair-table entries (-1: as the level would size it)
+    int force_rpw = 0;             // ranks per wave of a work item (0: the tuning table)
 };
 struct LevelTiming {
     float all_ms = 0.f;       // first test launch to last recheck, one event pair

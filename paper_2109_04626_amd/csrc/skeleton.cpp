@@ -565,6 +565,7 @@ retry:
     Lv.fp32 = fp32;
     Lv.graph = (R0.P->flags & FPC_FLAG_GRAPH) != 0;
     Lv.band_z = R0.P->recheck_margin > 0 ? R0.P->recheck_margin : 1e-3;
+    Lv.ill_cond_tau = R0.P->ill_cond_tau;
     Lv.minhit = ctx->minhit.as<uint64_t>();
     Lv.counters = ctx->counters.as<unsigned long long>();
     Lv.inst_cnt = Lv.counters + 8;
@@ -710,6 +711,10 @@ int validate(const fpc_params *P)
     if (std::isnan(P->q_override) && !(P->alpha > 0.0 && P->alpha < 1.0)) return FPC_EINVAL;
     if (!std::isnan(P->q_override) && !(P->q_override >= 0.0)) return FPC_EINVAL;
     if (P->max_tests < 0) return FPC_EINVAL;
+    if (std::isnan(P->ill_cond_tau)) return FPC_EINVAL;
+    if (P->c32_method != 0 && P->c32_method != FPC_CORR_BF16X3 && P->c32_method != FPC_CORR_BF16X6 &&
+        P->c32_method != FPC_CORR_FP32)
+        return FPC_EINVAL;
     return FPC_OK;
 }
 
@@ -741,7 +746,12 @@ int corr_stage(Run &R, const void *X, int x_dtype, double *C64, float *C32, doub
     if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_FP64, C64, false, false))) return rc;
     R.C64 = C64;
     if (R.mixed) {
-        if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_BF16X3, C32, true, false))) return rc;
+        const int m32 = R.P->c32_method ? R.P->c32_method : FPC_CORR_BF16X6;
+        if (m32 == FPC_CORR_FP32) {
+            if ((rc = corr_round_enqueue(R.ctx, C64, C32, R.p, false))) return rc;
+        } else if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, m32, C32, true, false))) {
+            return rc;
+        }
         R.C32 = C32;
         if ((rc = corr_max_abs_diff_enqueue(R.ctx, R.C64, R.C32, R.p))) return rc;
     }
@@ -1018,6 +1028,10 @@ int validate_batch(const fpc_params *P, int ni, const fpc_instance *inst)
     if (std::isnan(P->q_override) && !(P->alpha > 0.0 && P->alpha < 1.0)) return FPC_EINVAL;
     if (!std::isnan(P->q_override) && !(P->q_override >= 0.0)) return FPC_EINVAL;
     if (P->max_tests < 0) return FPC_EINVAL;
+    if (std::isnan(P->ill_cond_tau)) return FPC_EINVAL;
+    if (P->c32_method != 0 && P->c32_method != FPC_CORR_BF16X3 && P->c32_method != FPC_CORR_BF16X6 &&
+        P->c32_method != FPC_CORR_FP32)
+        return FPC_EINVAL;
     for (int k = 0; k < ni; ++k) {
         const fpc_instance &I = inst[k];
         if (!I.X || I.p < 2 || I.n <= I.p + 1 || I.x_rows < 1) return FPC_EINVAL;

@@ -48,9 +48,8 @@ def test_dense_skeleton_bit_exact(setup, prec, flags):
     assert np.array_equal(got["sep_level"], gold["sep_level"])
     assert np.array_equal(got["sep_kind"], gold["sep_kind"])
     assert got["total_required"] == gold["total_tests"]
-    if prec == 0:
-        assert got["sepsets"] == gold["sepsets"]
-    else:
+    assert dict(got["sepsets"]) == gold["sepsets"]
+    if prec == 1:
         C = oracle.corr(X)
         bad = [(k, K) for k, K in got["sepsets"].items() if not oracle.ci_test(C, cfg["n"], *k, K, gold["q"])[0]]
         assert not bad, bad[:5]

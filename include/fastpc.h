@@ -37,6 +37,7 @@ extern "C" {
 #define FPC_EBUDGET 4    /* test budget (max_tests) exceeded, or a level whose test count overflows */
 #define FPC_ENOMEM 5     /* host or device allocation failed                                       */
 #define FPC_EDEVICE 6    /* a HIP runtime call failed; fpc_last_hip_error() names it               */
+#define FPC_ESCRATCH 7   /* problem larger than the static workspace of a no-allocation call       */
 
 /* ---------------------------------------------------------------- enums */
 #define FPC_F64 0 /* IEEE binary64 elements */
@@ -116,6 +117,21 @@ int fpc_corr(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method,
  * FPC_ESINGULAR (C not positive definite). */
 int fpc_first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
                     uint8_t *indep_out);
+
+/* The same without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the sweep's workspace (two p x p FP64 buffers, two 32 x 32
+ * panel inverses, a flag word; 4.2 MB) is a static device array that each
+ * device the library runs on holds until the process ends.  Same arguments,
+ * outputs and results as fpc_first_level; p > FPC_NOALLOC_MAX_P returns
+ * FPC_ESCRATCH.  Every call on a device shares that device's workspace, so
+ * calls that overlap on one device (other contexts, other threads) race;
+ * each call clears the flag it reads and waits for its work before
+ * returning.  The context itself is created beforehand (fpc_create
+ * allocates). */
+#define FPC_NOALLOC_MAX_P 512
+int fpc_first_level_noalloc(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
+                            uint8_t *indep_out);
 
 /* ------------------------------------------ one batch of CI tests (Sec. 5, index matrix B)
  * B: device, int32, b rows of (2 + l) entries [i, j, k_1 .. k_l] (the

@@ -17,7 +17,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfastpc.so")
 
-FPC_OK, FPC_EINVAL, FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET, FPC_ENOMEM, FPC_EDEVICE = range(7)
+FPC_OK, FPC_EINVAL, FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET, FPC_ENOMEM, FPC_EDEVICE, FPC_ESCRATCH = range(8)
+FPC_NOALLOC_MAX_P = 512
 FPC_F64, FPC_F32 = 0, 1
 FPC_CORR_FP64, FPC_CORR_BF16X3, FPC_CORR_BF16X6, FPC_CORR_FP32 = 0, 1, 2, 3
 FPC_PREC_FP64, FPC_PREC_MIXED = 0, 1
@@ -33,7 +34,7 @@ EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "
             "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton", "fpc_skeleton_batch",
             "fpc_result_free", "fpc_orient", "fpc_mlp_bytes", "fpc_mlp_params", "fpc_mlp_init", "fpc_mlp_get",
             "fpc_mlp_forward", "fpc_mlp_grad", "fpc_mlp_train_step", "fpc_get_tuning", "fpc_set_tuning",
-            "fpc_set_recheck_queue", "fpc_level_series"]
+            "fpc_set_recheck_queue", "fpc_level_series", "fpc_first_level_noalloc"]
 FPC_TUNE_LEVELS = 17
 TUNING_FIELDS = ("test_ranks_per_wave", "shared_ranks_per_wave", "window_growth", "first_window_items",
                  "max_blocks_per_cu", "shared_prefix_depth")
@@ -118,6 +119,8 @@ def _load():
     lib.fpc_corr.restype = i
     lib.fpc_first_level.argtypes = [vp, vp, i, i, d, vp, vp]
     lib.fpc_first_level.restype = i
+    lib.fpc_first_level_noalloc.argtypes = [vp, vp, i, i, d, vp, vp]
+    lib.fpc_first_level_noalloc.restype = i
     lib.fpc_ci_batch.argtypes = [vp, vp, i, i, i, i, vp, i64, d, vp, vp]
     lib.fpc_ci_batch.restype = i
     lib.fpc_level_series.argtypes = [vp, vp, i, i, i, i, i, i, vp, i, i64, i64, i, i, i, d, d, d, d, vp, vp]
@@ -343,6 +346,15 @@ def fpc_first_level(ctx: Context, C, n: int, q: float):
     _check(_lib.fpc_first_level(ctx.handle, _t_ptr(C), p, int(n), float(q), _t_ptr(r), _t_ptr(ind)),
            "fpc_first_level")
     return r, ind
+
+
+def fpc_first_level_noalloc(ctx: Context, C, n: int, q: float, r_out, indep_out) -> None:
+    """fpc_first_level into caller-allocated device outputs r_out (FP64 p x p)
+    and indep_out (uint8 p x p), with the library's static workspace: the
+    call allocates no device memory (p <= FPC_NOALLOC_MAX_P)."""
+    p = C.shape[0]
+    _check(_lib.fpc_first_level_noalloc(ctx.handle, _t_ptr(C), p, int(n), float(q), _t_ptr(r_out),
+                                        _t_ptr(indep_out)), "fpc_first_level_noalloc")
 
 
 def fpc_ci_batch(ctx: Context, C, n: int, B, q: float):

@@ -245,23 +245,20 @@ __global__ __launch_bounds__(256) void first_level_decide(const double *__restri
     }
 }
 
-}  // namespace
+__global__ void clear_flag(int *__restrict__ f) { *f = 0; }
 
-int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
-                        uint8_t *indep_out, const int **d_bad)
+// The sweep, the decisions and the positive-definiteness flag, queued on
+// the context's stream, with the workspace given: two p x p buffers (the
+// sweep reads one and writes the other), two kNB x kNB panel inverses and
+// the flag word (cleared by a kernel here when clear_bad is set).
+int first_level_enqueue_ws(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out, uint8_t *indep_out,
+                           double *buf0, double *buf1, double *pinv0, double *pinv1, int *bad, bool clear_bad)
 {
-    if (!C || p < 2 || n <= p + 1) return FPC_EINVAL;
     hipStream_t st = ctx->stream;
     const size_t pp = (size_t)p * p;
-    // work: two p x p buffers (the sweep reads one and writes the other)
-    // and two kNB x kNB panel inverses
-    int rc = ctx->inv_work.ensure(sizeof(double) * (2 * pp + 2 * kNB * kNB));
-    if (rc) return rc;
-    if ((rc = ctx->flag.ensure(64))) return rc;
-    double *buf[2] = {ctx->inv_work.as<double>(), ctx->inv_work.as<double>() + pp};
-    double *pinv[2] = {buf[1] + pp, buf[1] + pp + kNB * kNB};
-    int *bad = ctx->flag.as<int>() + 4;
-    FPC_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+    double *buf[2] = {buf0, buf1};
+    double *pinv[2] = {pinv0, pinv1};
+    if (clear_bad) clear_flag<<<1, 1, 0, st>>>(bad);
     const int nbt = (p + kNB - 1) / kNB;
     first_tile_inverse<<<1, 256, 0, st>>>(C, p, p < kNB ? p : kNB, pinv[0], bad);
     const double *Ain = C;
@@ -275,8 +272,63 @@ int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, d
     }
     first_level_decide<<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(Ain, p, n, q, r_out, indep_out, bad);
     FPC_HIP(hipGetLastError());
+    return FPC_OK;
+}
+
+// Workspace of fpc_first_level_noalloc, held by every device the library
+// runs on until the process ends: the two sweep buffers and the panel
+// inverses for p <= FPC_NOALLOC_MAX_P, then the flag word.
+constexpr size_t kNoAllocMats = 2 * (size_t)FPC_NOALLOC_MAX_P * FPC_NOALLOC_MAX_P + 2 * kNB * kNB;
+constexpr size_t kNoAllocBytes = sizeof(double) * kNoAllocMats + 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+}  // namespace
+
+int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
+                        uint8_t *indep_out, const int **d_bad)
+{
+    if (!C || p < 2 || n <= p + 1) return FPC_EINVAL;
+    const size_t pp = (size_t)p * p;
+    int rc = ctx->inv_work.ensure(sizeof(double) * (2 * pp + 2 * kNB * kNB));
+    if (rc) return rc;
+    if ((rc = ctx->flag.ensure(64))) return rc;
+    double *w = ctx->inv_work.as<double>();
+    int *bad = ctx->flag.as<int>() + 4;
+    FPC_HIP(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+    if ((rc = first_level_enqueue_ws(ctx, C, p, n, q, r_out, indep_out, w, w + pp, w + 2 * pp,
+                                     w + 2 * pp + kNB * kNB, bad, false)))
+        return rc;
     *d_bad = bad;
     return FPC_OK;
+}
+
+// Device address of this device's copy of `scratch`: host code must use it,
+// never the array's name, in kernel arguments and copies.  Called with the
+// context's device current when the context is created.
+int noalloc_init(fpc_ctx *ctx)
+{
+    void *ptr = nullptr;
+    FPC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return FPC_EDEVICE;
+    ctx->scratch = ptr;
+    return FPC_OK;
+}
+
+int first_level_noalloc(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out, uint8_t *indep_out)
+{
+    if (!C || p < 2 || n <= p + 1) return FPC_EINVAL;
+    if (p > FPC_NOALLOC_MAX_P) return FPC_ESCRATCH;
+    if (!ctx->scratch) return FPC_EDEVICE;
+    const size_t pp = (size_t)p * p;
+    double *w = static_cast<double *>(ctx->scratch);
+    int *bad = reinterpret_cast<int *>(w + kNoAllocMats);
+    int rc = first_level_enqueue_ws(ctx, C, p, n, q, r_out, indep_out, w, w + pp, w + 2 * pp,
+                                    w + 2 * pp + kNB * kNB, bad, true);
+    if (rc) return rc;
+    int hbad = 0;
+    FPC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    FPC_HIP(hipStreamSynchronize(ctx->stream));
+    return hbad ? FPC_ESINGULAR : FPC_OK;
 }
 
 int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out, uint8_t *indep_out,
@@ -299,4 +351,12 @@ extern "C" int fpc_first_level(fpc_ctx *ctx, const double *C, int p, int n, doub
 {
     if (!ctx) return FPC_EINVAL;
     return fpc::first_level(ctx, C, p, n, q, r_out, indep_out, nullptr);
+}
+
+extern "C" int fpc_first_level_noalloc(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
+                                       uint8_t *indep_out)
+{
+    if (!ctx) return FPC_EINVAL;
+    FPC_HIP(hipSetDevice(ctx->device));
+    return fpc::first_level_noalloc(ctx, C, p, n, q, r_out, indep_out);
 }

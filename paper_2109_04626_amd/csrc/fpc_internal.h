@@ -98,6 +98,7 @@ struct fpc_ctx {
     fpc::HostBuf h_back;          // pinned staging for downloads
     fpc::HostBuf h_inst;          // pinned staging for the instance table
     fpc::HostBuf h_flag;          // pinned landing of the correlation flags
+    void *scratch = nullptr;      // this device's address of the no-allocation workspace (first_level.hip)
 };
 
 namespace fpc {
@@ -137,6 +138,9 @@ int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r
 // *d_bad (device int) becomes nonzero if C is not positive definite.
 int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
                         uint8_t *indep_out, const int **d_bad);
+// Sets ctx->scratch to the device address of the static no-allocation
+// workspace (the context's device current).
+int noalloc_init(fpc_ctx *ctx);
 
 // ---- level tests (citest.hip)
 // One problem instance of a level: its matrices and threshold.

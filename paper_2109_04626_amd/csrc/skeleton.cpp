@@ -180,6 +180,7 @@ extern "C" const char *fpc_strerror(int code)
     case FPC_EBUDGET: return "test budget exceeded";
     case FPC_ENOMEM: return "out of memory";
     case FPC_EDEVICE: return "HIP runtime error";
+    case FPC_ESCRATCH: return "problem larger than the static workspace of the no-allocation entry point";
     default: return "unknown error";
     }
 }
@@ -256,6 +257,10 @@ extern "C" int fpc_create(fpc_ctx **out, int hip_device, void *hip_stream)
             fpc_destroy(c);
             return hip_fail(e, "hipMemcpy");
         }
+    }
+    if ((rc = fpc::noalloc_init(c))) {
+        fpc_destroy(c);
+        return rc;
     }
     *out = c;
     return FPC_OK;

@@ -677,6 +677,18 @@ __device__ __forceinline__ int decide32r(float r, float rho, bool ok, float rlo,
     return DEC_RECHECK;
 }
 
+// The same decision as two flags, without the band products: with
+// t = |r| rho, independent when t < rho rlo - errk, dependent when
+// t > rho rhi + errk (neither: the FP64 re-run).
+__device__ __forceinline__ void decide32b(float r, float rho, bool ok, float rlo, float rhi, float errk, float tau,
+                                          bool &indep, bool &dep)
+{
+    const bool live = ok && rho >= tau;
+    const float t = fabsf(r) * rho;
+    indep = live && t < fmaf(rho, rlo, -errk);
+    dep = live && t > fmaf(rho, rhi, errk);
+}
+
 // Smaller of two positive floats through their bit patterns (positive
 // floats order as integers); the result is used only when both are > 0.
 __device__ __forceinline__ float pos_min(float a, float b)
@@ -1181,11 +1193,11 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                 const T h22 = H22a - vb * vb - vc * vc;
                 const T h12 = H12a - ub * vb - uc * vc;
                 const T r = h12 * rsqv(h11 * h22);
-                int dec;
-                bool ok;
+                bool ok, indep, dep;
                 if constexpr (sizeof(T) == 8) {
                     ok = oka && sbb > T(0) && d3 > T(0) && h11 > T(0) && h22 > T(0) && fabs(r) < T(1);
-                    dec = decide64((double)r, ok, th) ? DEC_INDEP : DEC_DEP;
+                    indep = decide64((double)r, ok, th);
+                    dep = !indep;
                 } else {
                     // smallest pivots through the bit patterns: > 0 as an integer
                     // exactly when every pivot is a positive float (a negative
@@ -1194,17 +1206,18 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                     // makes rho tiny: the test goes to the FP64 re-run.
                     const float dK = pos_min(dmina, pos_min(sbb, d3)), hmin = pos_min(h11, h22);
                     ok = oka && __float_as_int(pos_min(dK, hmin)) > 0 && fabsf(r) < 1.0f;
-                    dec = decide32r(r, dK * hmin, ok, rlo32, rhi32, errk, tau32);
+                    decide32b(r, dK * hmin, ok, rlo32, rhi32, errk, tau32, indep, dep);
                 }
                 if (A.diag_r) {  // uniform
                     if (valid) {
                         A.diag_r[rank + it + lane - A.diag_lo] = ok ? (double)r : (double)NAN;
-                        A.diag_dec[rank + it + lane - A.diag_lo] = (uint8_t)dec;
+                        A.diag_dec[rank + it + lane - A.diag_lo] =
+                            (uint8_t)(indep ? DEC_INDEP : dep ? DEC_DEP : DEC_RECHECK);
                     }
                     continue;
                 }
                 if constexpr (sizeof(T) == 4) {
-                    const bool rq = valid && dec == DEC_RECHECK;
+                    const bool rq = valid && !indep && !dep;
                     const unsigned long long qb = __ballot(rq);
                     if (qb) {
                         unsigned long long slot = 0;
@@ -1219,7 +1232,7 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                         }
                     }
                 }
-                const unsigned long long hb = __ballot(valid && dec == DEC_INDEP);
+                const unsigned long long hb = __ballot(valid && indep);
                 if (hb) {
                     if (lane == 0)
                         atomicMin((unsigned long long *)&A.minhit[e],

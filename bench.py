@@ -38,9 +38,9 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32
 # calibration (fetch x2.000, write x1.000).  Valid only for the kernel source
 # and launch table they were taken with: any change to either makes the
 # figure null until the counters are taken again.
-MEASURED_TRAFFIC = {"bytes_per_launch": 10093102.0,
+MEASURED_TRAFFIC = {"bytes_per_launch": 10084454.0,
                     "sha256": {"paper_2109_04626_amd/csrc/citest.hip":
-                               "54ac84ac8d4c3dce7b4a4cdc0c305e3c234e3cfb80f3c5cf95da597e348b5905",
+                               "f2c348e5679a1f7a69af7b049a6a53afb590e778320a29ea28a4449a078caf93",
                                "paper_2109_04626_amd/tuning_gfx950.json":
                                "9b5ee9cd8fc56c7307853a22b4732f84004d394956b92179119b5f35944c27e9"}}
 
@@ -60,10 +60,22 @@ FP64_PEAK_TFLOPS = 78.6    # MI355X published vector FP64
 
 
 def flops_per_test(l: int) -> float:
-    """Algorithmic flops of one test at level l: Cholesky of the l x l
-    block (l^3/3 + l^2/2), two triangular solves (2 l^2), the three dot
-    products of H (6 l) and the final scaling (~20)."""
-    return l ** 3 / 3.0 + 2.5 * l * l + 6.0 * l + 20.0
+    """Algorithmic flops of one test at level l, F(l) = l^3/3 + 2 l^2 + 6 l
+    + 20: the Cholesky of the l x l block, the two triangular solves, the
+    three dot products of H and the final scaling."""
+    return l ** 3 / 3.0 + 2.0 * l * l + 6.0 * l + 20.0
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
 
 
 def bytes_per_test(l: int, elem: int) -> float:
@@ -87,6 +99,9 @@ def main() -> int:
                     help="profiling mode: only the mixed form on the headline workload, one short line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="profiling mode: a plain device copy of 1 GiB, five times (HBM counter calibration)")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the context block (mixed-form variants, forward schedule, held-out scale-free seeds)")
+    ap.add_argument("--eval-seeds", type=int, default=20, help="held-out scale-free seeds in the context block")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
@@ -123,10 +138,10 @@ def main() -> int:
 
     model = fpc.fpc_mlp_init(ctx, np.load(DEFAULT_MODEL))
 
-    def timed(X_dev, c, prec, m=None):
+    def timed(X_dev, c, prec, m=None, **kw):
         def run():
             return fpc.fpc_skeleton(ctx, X_dev, alpha=c["alpha"], max_level=c["max_level"], precision=prec,
-                                    order_model=m)
+                                    order_model=m, **kw)
 
         for _ in range(args.warmup):
             run()
@@ -219,6 +234,53 @@ def main() -> int:
               flush=True)
         del inst, base_d
 
+    # context: the mixed form's trades, the forward schedule (Algorithm 1)
+    # against the reverse one, and the learned order on held-out seeds
+    context = None
+    if not args.no_context:
+        context = {}
+        for name, kw in (("strict_z", dict(ill_cond_tau=-1.0)), ("c32_bf16x3", dict(c32_method=fpc.FPC_CORR_BF16X3)),
+                         ("c32_fp32_of_fp64", dict(c32_method=fpc.FPC_CORR_FP32))):
+            t, o = timed(Xd, cfg, fpc.FPC_PREC_MIXED, **kw)
+            lvo = [x for x in o[-1]["levels"] if x["level"] != cfg["p"] - 2]
+            context[name] = {"ms_per_step": t / args.steps * 1e3, "rechecked": sum(x["tests_rechecked"] for x in lvo),
+                             "level_kernel_ms": sum(x["kernel_ms"] for x in lvo), "corr_ms": o[-1]["corr_ms"],
+                             "corr_max_abs_err": o[-1]["corr_max_abs_err"],
+                             "skeleton_equal": bool(np.array_equal(o[-1]["adj"], results["plain"][1][-1]["adj"]))}
+            print(f"[bench] {name}: {context[name]['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+        fwd = {}
+        for wname, seed, prec in (("er_p20_n1000_d3", 0, fpc.FPC_PREC_FP64), ("paper_p95_n10000", 0, fpc.FPC_PREC_FP64),
+                                  (WORKLOAD, SEED, fpc.FPC_PREC_MIXED)):
+            Xw, _, cw = semdata.workload(wname, seed)
+            Xwd = torch.from_numpy(Xw).cuda()
+            row = {}
+            for sname, sch, lev in (("reverse", fpc.FPC_REVERSE, cw["max_level"]), ("forward", fpc.FPC_FORWARD, -1)):
+                o = fpc.fpc_skeleton(ctx, Xwd, alpha=cw["alpha"], max_level=lev, precision=prec, schedule=sch)
+                t0 = time.perf_counter()
+                o = fpc.fpc_skeleton(ctx, Xwd, alpha=cw["alpha"], max_level=lev, precision=prec, schedule=sch)
+                row[sname] = {"tests_required": o["total_required"], "tests_executed": o["total_tests"],
+                              "ms": (time.perf_counter() - t0) * 1e3, "edges": int(o["adj"].sum()) // 2,
+                              "max_level": lev}
+                row[sname + "_adj"] = o["adj"]
+            a, b = row.pop("reverse_adj"), row.pop("forward_adj")
+            row["edges_in_both"] = int((a & b).sum()) // 2
+            row["reverse_vs_forward_required"] = row["forward"]["tests_required"] / max(row["reverse"]["tests_required"], 1)
+            fwd[f"{wname} seed {seed}"] = row
+            del Xwd
+        context["forward_vs_reverse"] = fwd
+        from paper_2109_04626_amd import learned
+
+        ev = learned.evaluate(ctx, model, list(learned.EVAL_SEEDS)[: args.eval_seeds], verbose=False)
+        context["learned_heldout"] = {
+            "workload": f"{BA_WORKLOAD}, held-out seeds {ev['rows'][0]['seed']}..{ev['rows'][-1]['seed']}",
+            "seeds": len(ev["rows"]), "tests_lex": ev["tests_lex"], "tests_learned": ev["tests_learned"],
+            "ms_lex_total": ev["ms_lex"], "ms_learned_total": ev["ms_learned"],
+            "ms_lex_mean": ev["ms_lex"] / len(ev["rows"]), "ms_learned_mean": ev["ms_learned"] / len(ev["rows"]),
+            "learned_faster_seeds": sum(r["ms_learned"] < r["ms_lex"] for r in ev["rows"]),
+            "all_same_skeleton": ev["all_same"]}
+        print(f"[bench] held-out BA: lex {context['learned_heldout']['ms_lex_mean']:.2f} ms, learned "
+              f"{context['learned_heldout']['ms_learned_mean']:.2f} ms", file=sys.stderr, flush=True)
+
     dt, outs = results["mixed"]
     last = outs[-1]
     ref_adj = results["plain"][1][-1]["adj"]
@@ -307,6 +369,7 @@ def main() -> int:
                             "tests": dom["tests_executed"], "flops_per_test": flops_per_test(dom["level"])},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic()},
+        "context": context,
     }
 
     if not args.no_cpu_baseline:
@@ -317,11 +380,29 @@ def main() -> int:
         res = oracle.skeleton(C, cfg["n"], alpha=cfg["alpha"], max_level=cfg["max_level"],
                               max_tests=int(args.cpu_budget), partial_ok=True)
         tc = time.perf_counter() - t0
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+        # one thread: the first level of the same workload, and the whole small workload
+        p = cfg["p"]
+        t0 = time.perf_counter()
+        r1 = oracle.skeleton(C, cfg["n"], alpha=cfg["alpha"], max_level=cfg["max_level"], nthreads=1,
+                             max_tests=p * (p - 1) // 2, partial_ok=True)
+        t1 = time.perf_counter() - t0
+        Xs, _, cs = semdata.workload("er_p20_n1000_d3", 0)
+        t0 = time.perf_counter()
+        rs = oracle.skeleton(oracle.corr(Xs), cs["n"], alpha=cs["alpha"], max_level=cs["max_level"], nthreads=1)
+        ts = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": res["total_tests"] / tc, "unit": "CI tests/s",
-                                "cores": os.cpu_count(), "kind": "oracle",
+                                "cores": threads, "kind": "oracle",
                                 "sample": f"same workload: correlation + first level + the first "
                                           f"{res['total_tests']} tests (budget {int(args.cpu_budget)}), "
-                                          f"{tc:.1f} s, FP64, OpenMP over edges"}
+                                          f"{tc:.1f} s, FP64, OpenMP over edges",
+                                "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+                                "one_thread": {"first_level": {"workload": WORKLOAD, "tests": int(r1["levels"][0][2]),
+                                                               "s": float(r1["level_seconds"][0]),
+                                                               "tests_per_s": int(r1["levels"][0][2]) /
+                                                               float(r1["level_seconds"][0])},
+                                               "er_p20_n1000_d3": {"tests": rs["total_tests"], "s": ts,
+                                                                   "tests_per_s": rs["total_tests"] / ts}}}
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0

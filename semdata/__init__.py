@@ -209,6 +209,10 @@ WORKLOADS = {
     "er_p1000_n10000_d4": dict(p=1000, n=10000, graph="er", degree=4.0, x_dtype="f32", alpha=0.01, max_level=5),
     # scale-free graph
     "ba_p1000_n10000_m2": dict(p=1000, n=10000, graph="ba", degree=0.0, x_dtype="f32", alpha=0.01, max_level=3),
+    # the paper's simulation shape (5 neighbours on average, two hubs of 10,
+    # its weight law, alpha 1e-3); n is not stated there
+    "paper_p95_n10000": dict(p=95, n=10000, graph="paper", degree=0.0, x_dtype="f64", alpha=0.001, max_level=6,
+                             weight_law="paper"),
 }
 
 
@@ -216,7 +220,8 @@ def workload(name: str, seed: int, **over):
     """(X, sem, cfg) for a named workload; ``over`` overrides cfg keys."""
     cfg = dict(WORKLOADS[name])
     cfg.update(over)
-    sem = make_sem(cfg["p"], seed, graph=cfg["graph"], degree=cfg["degree"])
+    sem = make_sem(cfg["p"], seed, graph=cfg["graph"], degree=cfg["degree"],
+                   weight_law=cfg.get("weight_law", "baseline"))
     X = sample(sem, cfg["n"], seed, dtype=np.float32 if cfg["x_dtype"] == "f32" else np.float64)
     return X, sem, cfg
 

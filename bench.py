@@ -220,7 +220,14 @@ def main() -> int:
             ts = time.perf_counter() - t0
         finally:
             gc.enable()
-        same_b = all(np.array_equal(a["adj"], b["adj"]) for a, b in zip(outs_b, outs_s))
+        diff_b = [k for k, (a, b) in enumerate(zip(outs_b, outs_s)) if not np.array_equal(a["adj"], b["adj"])]
+        same_b = not diff_b
+        if diff_b:
+            k = diff_b[0]
+            print(f"[bench] batched: instances {diff_b} differ from one call each; instance {k} levels (level, "
+                  f"deleted, rechecked): batch {[(x['level'], x['deleted'], x['tests_rechecked']) for x in outs_b[k]['levels']]} "
+                  f"single {[(x['level'], x['deleted'], x['tests_rechecked']) for x in outs_s[k]['levels']]}",
+                  file=sys.stderr, flush=True)
         tests_b = sum(o["total_tests"] for o in outs_b)
         req_b = sum(o["total_required"] for o in outs_b)
         batched = {"workload": f"64 bootstrap resamples of an ER p={cfg5['base_p']} deg={cfg5['degree']} data set "
@@ -229,7 +236,7 @@ def main() -> int:
                    "instances": len(inst), "ms_per_call": tb * 1e3, "one_call_each_ms": ts * 1e3,
                    "speedup_vs_one_call_each": ts / tb, "tests_per_call": tests_b,
                    "ci_tests_per_s": tests_b / tb, "tests_required_per_call": req_b,
-                   "required_tests_per_s": req_b / tb, "skeletons_equal": same_b}
+                   "required_tests_per_s": req_b / tb, "skeletons_equal": same_b, "instances_differing": diff_b}
         print(f"[bench] batched: {tb * 1e3:.1f} ms/call vs {ts * 1e3:.1f} ms one call each", file=sys.stderr,
               flush=True)
         del inst, base_d

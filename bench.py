@@ -193,9 +193,9 @@ def main() -> int:
         inst = [(base_d, torch.from_numpy(r).cuda()) for r in boots] + \
                [(torch.from_numpy(d).cuda(), None) for d in datas]
 
-        def run_batch():
+        def run_batch(flags=0):
             return fpc.fpc_skeleton_batch(ctx, inst, alpha=cfg5["alpha"], max_level=cfg5["max_level"],
-                                          precision=fpc.FPC_PREC_MIXED)
+                                          precision=fpc.FPC_PREC_MIXED, flags=flags)
 
         def run_singles():
             return [fpc.fpc_skeleton(ctx, X if r is None else X[r.long()], alpha=cfg5["alpha"],
@@ -211,6 +211,14 @@ def main() -> int:
                 outs_b = run_batch()
             torch.cuda.synchronize()
             tb = (time.perf_counter() - t0) / args.batch_steps
+            # the whole call as one device graph (captured and launched once per call)
+            run_batch(fpc.FPC_FLAG_GRAPH)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.batch_steps):
+                outs_g = run_batch(fpc.FPC_FLAG_GRAPH)
+            torch.cuda.synchronize()
+            tg = (time.perf_counter() - t0) / args.batch_steps
             run_singles()
             gc.collect()
             torch.cuda.synchronize()
@@ -221,6 +229,9 @@ def main() -> int:
         finally:
             gc.enable()
         diff_b = [k for k, (a, b) in enumerate(zip(outs_b, outs_s)) if not np.array_equal(a["adj"], b["adj"])]
+        diff_g = [k for k, (a, b) in enumerate(zip(outs_g, outs_b))
+                  if not (np.array_equal(a["adj"], b["adj"]) and a["sepsets"] == b["sepsets"])]
+        graph_ok = all(o["corr_ms"] == 0.0 for o in outs_g)  # graph mode reports no per-phase split
         same_b = not diff_b
         if diff_b:
             k = diff_b[0]
@@ -236,8 +247,12 @@ def main() -> int:
                    "instances": len(inst), "ms_per_call": tb * 1e3, "one_call_each_ms": ts * 1e3,
                    "speedup_vs_one_call_each": ts / tb, "tests_per_call": tests_b,
                    "ci_tests_per_s": tests_b / tb, "tests_required_per_call": req_b,
-                   "required_tests_per_s": req_b / tb, "skeletons_equal": same_b, "instances_differing": diff_b}
-        print(f"[bench] batched: {tb * 1e3:.1f} ms/call vs {ts * 1e3:.1f} ms one call each", file=sys.stderr,
+                   "required_tests_per_s": req_b / tb, "skeletons_equal": same_b, "instances_differing": diff_b,
+                   "graph_mode": {"ms_per_call": tg * 1e3, "speedup_vs_host_driven": tb / tg,
+                                  "speedup_vs_one_call_each": ts / tg, "ran_as_graph": graph_ok,
+                                  "equal_to_host_driven": not diff_g, "instances_differing": diff_g}}
+        print(f"[bench] batched: {tb * 1e3:.1f} ms/call host-driven, {tg * 1e3:.1f} ms/call as one graph, "
+              f"{ts * 1e3:.1f} ms one call each", file=sys.stderr,
               flush=True)
         del inst, base_d
 
@@ -255,6 +270,23 @@ def main() -> int:
                              "corr_max_abs_err": o[-1]["corr_max_abs_err"],
                              "skeleton_equal": bool(np.array_equal(o[-1]["adj"], results["plain"][1][-1]["adj"]))}
             print(f"[bench] {name}: {context[name]['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+        # the same step as a batch of one in graph mode: every level's
+        # candidate sets, tests and deletions on the device, one launch
+        one = [(Xd, None)]
+        kwg = dict(alpha=cfg["alpha"], max_level=cfg["max_level"], precision=fpc.FPC_PREC_MIXED,
+                   flags=fpc.FPC_FLAG_GRAPH)
+        fpc.fpc_skeleton_batch(ctx, one, **kwg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            og = fpc.fpc_skeleton_batch(ctx, one, **kwg)[0]
+        torch.cuda.synchronize()
+        ref = results["mixed"][1][-1]
+        context["step_as_one_graph"] = {
+            "ms_per_step": (time.perf_counter() - t0) / args.steps * 1e3, "ran_as_graph": og["corr_ms"] == 0.0,
+            "equal_to_mixed": bool(np.array_equal(og["adj"], ref["adj"]) and og["sepsets"] == ref["sepsets"])}
+        print(f"[bench] step as one graph: {context['step_as_one_graph']['ms_per_step']:.2f} ms/step", file=sys.stderr,
+              flush=True)
         fwd = {}
         for wname, seed, prec in (("er_p20_n1000_d3", 0, fpc.FPC_PREC_FP64), ("paper_p95_n10000", 0, fpc.FPC_PREC_FP64),
                                   (WORKLOAD, SEED, fpc.FPC_PREC_MIXED)):

@@ -70,9 +70,11 @@ extern "C" {
                                        the shared-prefix (Schur pair) kernel; same results            */
 #define FPC_FLAG_LOG_FEATURES 2u    /* record the ranking features of every candidate of every edge
                                        deleted after the first level (fpc_result.log_*)              */
-#define FPC_FLAG_GRAPH 4u           /* capture each level's launches (window plans, persistent test
-                                       kernels, FP64 rechecks) in one HIP graph and launch it once;
-                                       same results, per-launch timings not reported separately     */
+#define FPC_FLAG_GRAPH 4u           /* fpc_skeleton: capture each level's launches (window plans,
+                                       persistent test kernels, FP64 rechecks) in one HIP graph and
+                                       launch it once; fpc_skeleton_batch: the whole call on the
+                                       device in one HIP graph (see there); same results, per-launch
+                                       timings not reported separately                               */
 
 /* Kinds of recorded separating sets (fpc_result.sep_kind). */
 #define FPC_SEP_NONE 0    /* edge kept                                                  */
@@ -342,7 +344,20 @@ int fpc_set_recheck_queue(fpc_ctx *ctx, int64_t initial, int64_t max);
  * (FPC_FLAG_GRAPH, FPC_FLAG_PER_TEST_KERNEL) and x_dtype apply to every
  * instance; schedule must be FPC_REVERSE and order FPC_ORDER_LEX (else
  * FPC_EINVAL); X, n, p and x_on_device are not read; max_tests is a
- * per-instance budget. */
+ * per-instance budget.
+ *
+ * FPC_FLAG_GRAPH, with 0 <= max_level <= 7, max_tests = 0, no
+ * FPC_FLAG_PER_TEST_KERNEL and every p <= 4096: the whole call runs on the
+ * device as one HIP graph, captured and launched once -- correlations, the
+ * first level of all instances in one launch per panel step, then for each
+ * level its candidate sets (neighbours of v grouped by the components of
+ * G - v), edge table, tests, FP64 re-runs and deletions -- and the host
+ * reads the results once at the end.  The levels and results are those of
+ * the host-driven batch; a capacity the work outgrows (separating-set
+ * store, candidate pool, recheck queue, a list of 1024 candidates or more)
+ * makes the call run host-driven instead.  Per-level kernel_ms, level_ms
+ * and test_launches are 0 in that mode, corr_ms and first_level_ms 0 and
+ * total_ms the whole call. */
 typedef struct {
     int32_t n;            /* samples of the instance (> p + 1)                                  */
     int32_t p;            /* variables (>= 2)                                                   */

@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastpc.so")
 ARCH = os.environ.get("FPC_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["corr.hip", "first_level.hip", "citest.hip", "graph.cpp", "skeleton.cpp", "quantile.cpp", "orient.cpp", "mlp.hip", "order.hip", "hostpool.cpp"]
+SOURCES = ["corr.hip", "first_level.hip", "citest.hip", "graph.cpp", "skeleton.cpp", "quantile.cpp", "orient.cpp", "mlp.hip", "order.hip", "hostpool.cpp", "batch_graph.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

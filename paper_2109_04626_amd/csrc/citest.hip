@@ -346,7 +346,27 @@ struct LevelArgs {
     double *diag_r;
     uint8_t *diag_dec;
     int64_t diag_lo;
+    // device-built level (many instances, level loop on the device): the
+    // class's edge range [dclass[0], dclass[1]) of the level's table, read
+    // at launch instead of edges/minhit/n_edges/edge_base (then relative to
+    // the level's table); blockoff then points at the class's plan region
+    // less dclass[0]
+    const int64_t *dclass;
 };
+
+// Moves the launch's view to its class when the class range lives on the
+// device (the kernels take A by value).
+__device__ __forceinline__ void apply_dclass(LevelArgs &A)
+{
+    if (A.dclass) {
+        const int64_t b = A.dclass[0], e = A.dclass[1];
+        A.edges += b;
+        A.minhit += b;
+        A.blockoff += b;
+        A.n_edges = e - b;
+        A.edge_base = b;
+    }
+}
 
 __device__ __forceinline__ int64_t uniform_i64(int64_t v)
 {
@@ -545,6 +565,7 @@ __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsi
 template <typename T, int L, bool TILE>
 __global__ __launch_bounds__(256) void level_kernel(LevelArgs A)
 {
+    apply_dclass(A);
     extern __shared__ __align__(16) unsigned char smem[];
     ExecCount ec;
     for_each_item(A, [&](int64_t blk) { level_item<T, L, TILE>(A, blk, smem, ec); });
@@ -936,6 +957,7 @@ __device__ __forceinline__ void pair_item(const LevelArgs &A, int64_t blk, unsig
 template <typename T, int QL>
 __global__ __launch_bounds__(256) void pair_kernel(LevelArgs A)
 {
+    apply_dclass(A);
     extern __shared__ __align__(16) unsigned char smem[];
     ExecCount ec;
     for_each_item(A, [&](int64_t blk) { pair_item<T, QL>(A, blk, smem, ec); });
@@ -959,6 +981,16 @@ hipError_t launch_pair(int l, int64_t ub, int cus, size_t lds_cu, size_t shm, hi
         return launch_pair<T, QL + 1>(l, ub, cus, lds_cu, shm, st, A);
     }
     return hipErrorInvalidValue;
+}
+
+template <typename T, int QL = 0>
+const void *pair_fn(int l)
+{
+    if constexpr (QL + 2 <= kMaxTemplL) {
+        if (l == QL + 2) return (const void *)pair_kernel<T, QL>;
+        return pair_fn<T, QL + 1>(l);
+    }
+    return nullptr;
 }
 
 template <typename T>
@@ -1294,6 +1326,7 @@ __host__ __device__ constexpr size_t pdec_bytes(int n) { return ((size_t)n * 2 +
 template <typename T, int QL>
 __global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
 {
+    apply_dclass(A);
     extern __shared__ __align__(16) unsigned char smem[];
     // the pair table is built once per launch and read by every item; the
     // barrier at the start of each item orders these writes before the reads
@@ -1498,6 +1531,7 @@ __device__ __forceinline__ void wide_item(const LevelArgs &A, int l, int64_t blk
 template <typename T>
 __global__ __launch_bounds__(64) void level_kernel_wide(LevelArgs A, int l)
 {
+    apply_dclass(A);
     extern __shared__ __align__(16) unsigned char smem[];
     ExecCount ec;
     for_each_item(A, [&](int64_t blk) { wide_item<T>(A, l, blk, smem, ec); });
@@ -1521,6 +1555,7 @@ struct PlanArgs {
     int64_t *n_items;               // total items of the window
     unsigned long long *item_ctr;   // zeroed for the window's test kernel
     unsigned long long *queue_len;  // recheck queue of the previous window, emptied (null: kept)
+    const int64_t *dclass;          // device class range (see LevelArgs::dclass), or null
 };
 
 constexpr int kPlanPer = 8;                 // edges per thread
@@ -1623,6 +1658,13 @@ constexpr int64_t kPlanSingleEdges = 65536;
 
 __global__ __launch_bounds__(kPlanSingleThreads) void plan_single(PlanArgs P)
 {
+    if (P.dclass) {
+        const int64_t b = P.dclass[0];
+        P.edges += b;
+        P.minhit += b;
+        P.off += b;
+        P.n_edges = P.dclass[1] - b;
+    }
     constexpr int64_t chunk = (int64_t)kPlanSingleThreads * kPlanPer;
     int64_t carry = 0;
     for (int64_t base0 = 0; base0 < P.n_edges; base0 += chunk) {
@@ -1875,6 +1917,236 @@ int level_class_key(const fpc_ctx *ctx, int l, bool fp32, int m)
     }
     const int per_cu = shm ? std::max(1, std::min(8, (int)((size_t)ctx->lds_per_cu / (shm + 256)))) : 8;
     return kind * 16 + (8 - per_cu);
+}
+
+std::vector<int> device_class_bounds(const fpc_ctx *ctx, int l, bool fp32)
+{
+    const int lt = std::min(l, FPC_TUNE_LEVELS - 1);
+    const int tcap = ctx->tuning.max_blocks_per_cu[lt] > 0 ? ctx->tuning.max_blocks_per_cu[lt] : 1 << 20;
+    const size_t cap = (size_t)ctx->lds_per_block - kStaticLds;
+    const size_t lds_cu = (size_t)ctx->lds_per_cu;
+    const bool triple = use_triple(ctx, l);
+    int regs = 1 << 20;
+    if (l >= 2) {
+        const void *fn = triple ? (fp32 ? triple_fn<float>(l) : triple_fn<double>(l))
+                                : (fp32 ? pair_fn<float>(l) : pair_fn<double>(l));
+        int k = 0;
+        if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, fn, 256, 0) == hipSuccess && k >= 1) regs = k;
+    }
+    auto key = [&](int m) {
+        const size_t ps = shared_lds_bytes(ctx, l, fp32, m);
+        if (l >= 2 && ps <= cap)
+            return std::min({regs, tcap, std::max(1, (int)(lds_cu / (ps + 256)))});
+        const size_t ts = tile_bytes(m, fp32 ? 4 : 8);
+        if (ts <= std::min<size_t>(cap, 65536)) return 100 + std::min({8, tcap, std::max(1, (int)(lds_cu / (ts + 256)))});
+        return 200;
+    };
+    std::vector<int> b;
+    int prev = key(std::max(l, 1));
+    for (int m = std::max(l, 1) + 1; m < kBinomRows; ++m) {
+        const int k = key(m);
+        if (k != prev) b.push_back(m - 1);
+        prev = k;
+    }
+    b.push_back(kBinomRows - 1);
+    // at most kMaxDeviceClasses: the longest runs merge into the last class
+    if ((int)b.size() > kMaxDeviceClasses) {
+        b.resize(kMaxDeviceClasses);
+        b.back() = kBinomRows - 1;
+    }
+    return b;
+}
+
+namespace {
+
+// InstRec of every instance for level l, on the device: the thresholds of
+// make_thresholds with the FP32 matrix's entry error read from device
+// memory (it is measured by the same captured work).
+__global__ void inst_table_kernel(const DevInstSrc *__restrict__ src, int ni, int l, double band_z, double tau_param,
+                                  int fp32, InstRec *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ni) return;
+    const DevInstSrc S = src[k];
+    const double c_err = S.c_err ? *S.c_err : 0.0;
+    InstRec R;
+    R.C = fp32 ? (const void *)S.C32 : (const void *)S.C64;
+    R.C64 = S.C64;
+    R.ld = S.p;
+    Thresholds &th = R.th;
+    const double q = S.q;
+    th.q = q;
+    th.sqrt_nu = sqrt((double)(S.n - l - 3));
+    const bool inf = isinf(q);
+    const double rt = tanh(q / th.sqrt_nu);
+    th.r_lo = inf ? 2.0 : rt * (1.0 - 1e-9);
+    th.r_hi = inf ? 2.0 : rt * (1.0 + 1e-9);
+    th.band_z = band_z;
+    th.c_eff = c_err + 4.0 * (l + 2) * 6.0e-8;
+    th.rb_lo = inf ? 2.0 : tanh(fmax(0.0, q - band_z) / th.sqrt_nu);
+    th.rb_hi = inf ? 2.0 : tanh((q + band_z) / th.sqrt_nu);
+    th.tau = tau_param >= 0.0 ? tau_param : th.sqrt_nu * (l + 2) * (0x1p-24 + c_err) / kZModelCap;
+    out[k] = R;
+}
+
+}  // namespace
+
+size_t inst_rec_bytes() { return sizeof(InstRec); }
+
+int level_inst_table_enqueue(fpc_ctx *ctx, const DevInstSrc *src, int ni, int l, double band_z, double tau, bool fp32,
+                             void *out)
+{
+    if (ni < 1) return FPC_OK;
+    inst_table_kernel<<<(ni + 63) / 64, 64, 0, ctx->stream>>>(src, ni, l, band_z, tau, fp32 ? 1 : 0,
+                                                             static_cast<InstRec *>(out));
+    FPC_HIP(hipGetLastError());
+    return FPC_OK;
+}
+
+// The launches of one device-built level: for each size class (static
+// bound of its lists, edge range on the device) its rank windows, each a
+// plan and a persistent test launch, and the FP64 re-run of the window's
+// queue.  Nothing is read back: launches past a class's work find no items.
+int level_tests_device(fpc_ctx *ctx, const DeviceLevel &D)
+{
+    hipStream_t st = ctx->stream;
+    const int l = D.l;
+    if (l > kMaxTemplL) return FPC_EINVAL;
+    const bool fp32 = D.fp32;
+    const int lt = std::min(l, FPC_TUNE_LEVELS - 1);
+    const size_t lds_cap = (size_t)ctx->lds_per_block - kStaticLds;
+    const int cus = ctx->num_cus;
+    const size_t lds_cu = (size_t)ctx->lds_per_cu;
+    const fpc_tuning &tu = ctx->tuning;
+    g_max_blocks_per_cu = tu.max_blocks_per_cu[lt];
+    enum Kind { K_TRIPLE, K_PAIR, K_TILE, K_GLOBAL };
+    struct Cls {
+        Kind kind;
+        size_t shm;
+        int pdec_n, rpb, max_m;
+        std::vector<int64_t> wins;
+        const int64_t *range;
+    };
+    std::vector<Cls> cls;
+    int max_nw = 0;
+    for (int c = 0; c < D.n_classes; ++c) {
+        Cls k{};
+        k.max_m = D.classes[c].max_m;
+        k.range = D.classes[c].range;
+        const bool triple = use_triple(ctx, l);
+        const size_t ps = l < 2 ? 0
+                        : triple ? (fp32 ? triple_lds_bytes<float>(l, k.max_m) : triple_lds_bytes<double>(l, k.max_m))
+                                 : (fp32 ? pair_lds_bytes<float>(l, k.max_m) : pair_lds_bytes<double>(l, k.max_m));
+        if (l >= 2 && ps <= lds_cap) {
+            k.kind = triple ? K_TRIPLE : K_PAIR;
+            k.shm = ps;
+            if (triple) {
+                k.pdec_n = triple_table_entries(l, fp32, k.max_m, ps, lds_cu, lds_cap, tu.max_blocks_per_cu[lt]);
+                k.shm += pdec_bytes(k.pdec_n);
+            }
+            k.rpb = kWaves * tu.shared_ranks_per_wave[lt];
+        } else {
+            const size_t ts = tile_bytes(k.max_m, fp32 ? 4 : 8);
+            k.kind = ts <= std::min<size_t>(lds_cap, 65536) ? K_TILE : K_GLOBAL;
+            k.shm = k.kind == K_TILE ? ts : 0;
+            k.rpb = kWaves * tu.test_ranks_per_wave[lt];
+        }
+        // windows covering the most tests a list of the class can hold
+        const int64_t maxN = binom_sat(k.max_m, l);
+        if (maxN == INT64_MAX) return FPC_EBUDGET;
+        k.wins.push_back(0);
+        for (int64_t w = (int64_t)k.rpb * std::max(1, tu.first_window_items[lt]); k.wins.back() < maxN;
+             w = w > INT64_MAX / 64 ? w : w * std::max(2, tu.window_growth[lt]))
+            k.wins.push_back(k.wins.back() > maxN - w ? maxN : k.wins.back() + w);
+        max_nw = std::max(max_nw, (int)k.wins.size() - 1);
+        cls.push_back(std::move(k));
+    }
+    if (D.n_classes > kMaxDeviceClasses) return FPC_EINVAL;
+    // plan buffer: per class [items, item counter], then the classes' item
+    // offsets, class c at [begin_c + c, end_c + c] (disjoint for any ranges)
+    int64_t *slots = D.plan;
+    int64_t *offs = D.plan + 2 * D.n_classes;
+    LevelArgs A{};
+    A.cand = D.cand;
+    A.inst = static_cast<const InstRec *>(D.insts);
+    A.binom = ctx->binom.as<int64_t>();
+    A.binomT = ctx->binomT.as<int64_t>();
+    A.counters = D.counters;
+    A.inst_cnt = D.inst_cnt;
+    A.queue = D.queue;
+    A.queue_cap = D.queue_cap;
+    A.edges = D.edges;
+    A.minhit = D.minhit;
+    hipError_t err = hipSuccess;
+    for (int w = 0; w < max_nw && err == hipSuccess; ++w) {
+        // the classes of the window one after the other, each its plan and
+        // its persistent launch (as concurrent graph branches they ran
+        // slower: several classes with work then exceed the tuned
+        // workgroups per CU)
+        std::vector<int> act;
+        for (int c = 0; c < (int)cls.size(); ++c)
+            if (w + 1 < (int)cls[c].wins.size()) act.push_back(c);
+        if (act.empty()) continue;
+        for (size_t j = 0; j < act.size() && err == hipSuccess; ++j) {
+            const Cls &k = cls[act[j]];
+            const int c = act[j];
+            PlanArgs P{};
+            P.edges = D.edges;
+            P.minhit = D.minhit;
+            P.dclass = k.range;
+            P.lo = k.wins[w];
+            P.hi = k.wins[w + 1];
+            P.rpb = k.rpb;
+            P.filter = w > 0;
+            P.off = offs + c;
+            P.n_items = slots + 2 * c;
+            P.item_ctr = reinterpret_cast<unsigned long long *>(slots + 2 * c + 1);
+            // the first plan of the window empties the re-run queue that the
+            // previous window's re-run has drained
+            P.queue_len = j == 0 ? &D.counters[1] : nullptr;
+            plan_single<<<1, kPlanSingleThreads, 0, st>>>(P);
+            LevelArgs B = A;
+            B.dclass = k.range;
+            B.blockoff = P.off;
+            B.n_items = P.n_items;
+            B.item_ctr = P.item_ctr;
+            B.win_lo = P.lo;
+            B.win_hi = P.hi;
+            B.ranks_per_block = k.rpb;
+            B.max_m = k.max_m;
+            B.pdec_n = k.pdec_n;
+            const int64_t ub = INT64_MAX;
+            switch (k.kind) {
+            case K_TRIPLE:
+                err = fp32 ? launch_triple<float>(l, ub, cus, lds_cu, k.shm, st, B)
+                           : launch_triple<double>(l, ub, cus, lds_cu, k.shm, st, B);
+                break;
+            case K_PAIR:
+                err = fp32 ? launch_pair<float>(l, ub, cus, lds_cu, k.shm, st, B)
+                           : launch_pair<double>(l, ub, cus, lds_cu, k.shm, st, B);
+                break;
+            case K_TILE:
+                if (fp32) launch_level<float, true>(l, ub, cus, lds_cu, k.shm, st, B);
+                else launch_level<double, true>(l, ub, cus, lds_cu, k.shm, st, B);
+                break;
+            case K_GLOBAL:
+                if (fp32) launch_level<float, false>(l, ub, cus, lds_cu, 0, st, B);
+                else launch_level<double, false>(l, ub, cus, lds_cu, 0, st, B);
+                break;
+            }
+            if (err == hipSuccess) err = hipGetLastError();
+        }
+        if (fp32 && err == hipSuccess) {
+            LevelArgs Q = A;
+            Q.dclass = nullptr;
+            Q.edge_base = 0;
+            Q.max_m = D.max_m_all;
+            launch_recheck(l, st, Q);
+            err = hipGetLastError();
+        }
+    }
+    FPC_HIP(err);
+    return FPC_OK;
 }
 
 int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> &ntests, LevelTiming *timing)

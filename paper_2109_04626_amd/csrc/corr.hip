@@ -378,6 +378,12 @@ __global__ __launch_bounds__(256) void round_f32(const double *__restrict__ a, f
     for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < cnt; k += (size_t)gridDim.x * 256) b[k] = (float)a[k];
 }
 
+__global__ void fill_u32(uint32_t *__restrict__ p, int n, uint32_t v)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
 int splits_for(int tiles, int n, int num_cus)
 {
     int s = (2 * num_cus + tiles - 1) / tiles;
@@ -388,8 +394,24 @@ int splits_for(int tiles, int n, int num_cus)
 
 }  // namespace
 
+// Device buffers corr_compute needs for one (n, p, method), grown now (a
+// captured graph cannot allocate).
+int corr_reserve(fpc_ctx *ctx, int n, int p, int method)
+{
+    const int nchunks = (n + kStatRows - 1) / kStatRows;
+    const int nbt = (p + kT - 1) / kT, tiles = nbt * (nbt + 1) / 2;
+    const int npad = (n + 31) / 32 * 32;
+    const int nsplit = splits_for(tiles, method == FPC_CORR_FP64 ? n : npad, ctx->num_cus);
+    int rc = ctx->colstat.ensure(sizeof(double) * ((size_t)2 * p + (size_t)nchunks * 2 * p));
+    if (!rc) rc = ctx->flag.ensure(64);
+    if (!rc) rc = ctx->inv_work.ensure(sizeof(double) * (size_t)p * p * nsplit);
+    if (!rc && (method == FPC_CORR_BF16X3 || method == FPC_CORR_BF16X6))
+        rc = ctx->zsplit.ensure(sizeof(__bf16) * (method == FPC_CORR_BF16X6 ? 3 : 2) * (size_t)p * npad);
+    return rc;
+}
+
 int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out, bool reuse_stats,
-                 bool wait)
+                 bool wait, bool keep_flags)
 {
     if (!X || !C_out || n < 2 || p < 1) return FPC_EINVAL;
     if (x_dtype != FPC_F64 && x_dtype != FPC_F32) return FPC_EINVAL;
@@ -400,7 +422,8 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
         // unless the caller's statistics and matrix are already there
         int rc = ctx->c64.ensure(sizeof(double) * (size_t)p * p);
         if (rc) return rc;
-        if ((rc = corr_compute(ctx, X, x_dtype, n, p, FPC_CORR_FP64, ctx->c64.ptr, reuse_stats, false))) return rc;
+        if ((rc = corr_compute(ctx, X, x_dtype, n, p, FPC_CORR_FP64, ctx->c64.ptr, reuse_stats, false, keep_flags)))
+            return rc;
         return corr_round_enqueue(ctx, ctx->c64.as<double>(), static_cast<float *>(C_out), p, wait);
     }
     hipStream_t st = ctx->stream;
@@ -421,7 +444,7 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
     // column means and deviations (kept from the previous call on the same
     // data when reuse_stats is set)
     if (!reuse_stats) {
-        FPC_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(int), st));
+        if (!keep_flags) fill_u32<<<1, 32, 0, st>>>(reinterpret_cast<uint32_t *>(flags), 2, 0u);
         if (x_dtype == FPC_F64) {
             colstat_partial<double><<<g0, 256, 0, st>>>((const double *)X, n, p, part, flags);
             colstat_reduce<double><<<(p + 255) / 256, 256, 0, st>>>((const double *)X, part, nchunks, n, p, mu, sd,
@@ -508,6 +531,20 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(const TX *__restrict__
 
 }  // namespace
 
+int gather_rows_enqueue(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p, const int32_t *rows, int n,
+                        void *out, int *bad)
+{
+    if (!X || !rows || !out || p < 1 || n < 1 || !bad) return FPC_EINVAL;
+    hipStream_t st = ctx->stream;
+    const unsigned g = (unsigned)std::min(n, 8 * ctx->num_cus);
+    if (x_dtype == FPC_F64)
+        gather_rows_kernel<double><<<g, 256, 0, st>>>((const double *)X, x_rows, p, rows, n, (double *)out, bad);
+    else
+        gather_rows_kernel<float><<<g, 256, 0, st>>>((const float *)X, x_rows, p, rows, n, (float *)out, bad);
+    FPC_HIP(hipGetLastError());
+    return FPC_OK;
+}
+
 int gather_rows(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p, const int32_t *rows, int n,
                 void *out)
 {
@@ -537,12 +574,12 @@ int corr_round_enqueue(fpc_ctx *ctx, const double *c64, float *c32, int p, bool 
     return wait ? corr_check(ctx, nullptr) : FPC_OK;
 }
 
-int corr_max_abs_diff_enqueue(fpc_ctx *ctx, const double *c64, const float *c32, int p)
+int corr_max_abs_diff_enqueue(fpc_ctx *ctx, const double *c64, const float *c32, int p, unsigned long long *slot)
 {
     int rc = ctx->flag.ensure(64);
     if (rc) return rc;
-    unsigned long long *d = reinterpret_cast<unsigned long long *>(ctx->flag.as<char>() + 32);
-    FPC_HIP(hipMemsetAsync(d, 0, sizeof(*d), ctx->stream));
+    unsigned long long *d = slot ? slot : reinterpret_cast<unsigned long long *>(ctx->flag.as<char>() + 32);
+    fill_u32<<<1, 32, 0, ctx->stream>>>(reinterpret_cast<uint32_t *>(d), 2, 0u);
     max_abs_diff<<<512, 256, 0, ctx->stream>>>(c64, c32, (size_t)p * p, d);
     FPC_HIP(hipGetLastError());
     return FPC_OK;

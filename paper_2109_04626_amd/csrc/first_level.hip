@@ -20,6 +20,7 @@
 // the next panel's diagonal block inverts it in the same launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "fpc_internal.h"
@@ -129,16 +130,14 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // B[l/16][l%16] and holding D[4v + l/16][l%16] in accumulator v.  The tile
 // at (next_k0, next_k0), if any, then inverts its new values into
 // Pinv_next.
-__global__ __launch_bounds__(256) void sweep_panel(const double *__restrict__ Ain, double *__restrict__ Aout, int p,
-                                                   int k0, int nb, const double *__restrict__ Pinv,
-                                                   int next_k0, int next_nb, double *__restrict__ Pinv_next,
-                                                   int *__restrict__ bad)
+__device__ __forceinline__ void sweep_tile(const double *__restrict__ Ain, double *__restrict__ Aout, int p, int k0,
+                                           int nb, const double *__restrict__ Pinv, int next_k0, int next_nb,
+                                           double *__restrict__ Pinv_next, int *__restrict__ bad, int i0, int j0)
 {
     __shared__ double Ps[kNB][kNB + 1];
     __shared__ double Us[kNB][kNB + 1];
     __shared__ double Vs[kNB][kNB + 1];
     __shared__ double rowk[2][2][kNB], colk[2][2][kNB];
-    const int i0 = blockIdx.y * kNB, j0 = blockIdx.x * kNB;
     const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;  // 32 x 8
     const int j = j0 + tx;
 #pragma unroll
@@ -197,6 +196,82 @@ __global__ __launch_bounds__(256) void sweep_panel(const double *__restrict__ Ai
         __syncthreads();
         tile_inverse(Ps, rowk, colk, next_nb, Pinv_next, bad);
     }
+}
+
+__global__ __launch_bounds__(256) void sweep_panel(const double *__restrict__ Ain, double *__restrict__ Aout, int p,
+                                                   int k0, int nb, const double *__restrict__ Pinv,
+                                                   int next_k0, int next_nb, double *__restrict__ Pinv_next,
+                                                   int *__restrict__ bad)
+{
+    sweep_tile(Ain, Aout, p, k0, nb, Pinv, next_k0, next_nb, Pinv_next, bad, blockIdx.y * kNB, blockIdx.x * kNB);
+}
+
+// ---------------------------------------------------------------- many instances
+// Panel t of every instance with p > 32 t in one launch: job q covers
+// tiles [tile0[q], tile0[q] + nbt^2) of the flattened grid.
+__global__ __launch_bounds__(256) void sweep_panel_batch(const SweepJob *__restrict__ jobs, int njobs)
+{
+    int lo = 0, hi = njobs;  // jobs[lo].tile0 <= blockIdx.x < jobs[hi].tile0
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (jobs[mid].tile0 <= (int64_t)blockIdx.x) lo = mid;
+        else hi = mid;
+    }
+    const SweepJob J = jobs[lo];
+    const int t = (int)((int64_t)blockIdx.x - J.tile0);
+    sweep_tile(J.Ain, J.Aout, J.p, J.k0, J.nb, J.Pinv, J.next_k0, J.next_nb, J.Pinv_next, J.bad, (t / J.nbt) * kNB,
+               (t % J.nbt) * kNB);
+}
+
+// First panel's diagonal block of every instance (one block each).
+__global__ __launch_bounds__(256) void first_tile_inverse_batch(const SweepJob *__restrict__ jobs)
+{
+    const SweepJob J = jobs[blockIdx.x];
+    __shared__ double Ps[kNB][kNB + 1];
+    __shared__ double rowk[2][2][kNB], colk[2][2][kNB];
+    const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;
+    const int nb = J.p < kNB ? J.p : kNB;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q;
+        Ps[r][tx] = (r < nb && tx < nb) ? J.Ain[(size_t)r * J.p + tx] : 0.0;
+    }
+    __syncthreads();
+    tile_inverse(Ps, rowk, colk, nb, const_cast<double *>(J.Pinv), J.bad);  // this job writes the inverse
+}
+
+// Decisions of every instance: adjacency byte = edge kept (not independent),
+// zero diagonal; deletions counted per instance; the Omega_ii rule of the
+// single-instance decision sets the instance's flag.
+__global__ __launch_bounds__(256) void first_level_decide_batch(const DecideJob *__restrict__ jobs, int njobs)
+{
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (jobs[mid].elem0 <= (int64_t)blockIdx.x * 256) lo = mid;
+        else hi = mid;
+    }
+    const DecideJob J = jobs[lo];
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x - J.elem0;
+    const int64_t pp = (int64_t)J.p * J.p;
+    bool del = false;
+    if (idx >= 0 && idx < pp) {
+        const int i = (int)(idx / J.p), j = (int)(idx % J.p);
+        const double *Om = J.Om;
+        if (i == j) {
+            if (!(Om[idx] > 0.0) || !(Om[idx] <= 1e12)) atomicOr(J.bad, 1);
+            J.adj[idx] = 0;
+        } else {
+            const double oij = 0.5 * (Om[(size_t)i * J.p + j] + Om[(size_t)j * J.p + i]);
+            const double r = -oij / sqrt(Om[(size_t)i * J.p + i] * Om[(size_t)j * J.p + j]);
+            uint8_t ind = 0;
+            if (fabs(r) < 1.0) ind = sqrt((double)(J.n - (J.p - 2) - 3)) * fabs(atanh(r)) <= J.q;
+            J.adj[idx] = ind ? 0 : 1;
+            del = ind && i < j;
+        }
+    }
+    const unsigned long long b = __ballot(del);
+    if (b && threadIdx.x % 64 == __ffsll((long long)b) - 1) atomicAdd(J.deleted, (unsigned long long)__popcll(b));
 }
 
 // Inverse of the first panel's diagonal block.
@@ -274,6 +349,100 @@ int first_level_enqueue_ws(fpc_ctx *ctx, const double *C, int p, int n, double q
     FPC_HIP(hipGetLastError());
     return FPC_OK;
 }
+
+}  // namespace
+
+int first_level_batch_enqueue(fpc_ctx *ctx, const std::vector<FirstLevelInst> &in, const FirstLevelBatchBufs &b)
+{
+    hipStream_t st = ctx->stream;
+    const int ni = (int)in.size();
+    int maxp = 0;
+    for (const auto &I : in) maxp = std::max(maxp, I.p);
+    const int npanels = (maxp + kNB - 1) / kNB;
+    // job tables for every panel step (uploaded by the caller beforehand)
+    for (int k = 0; k < ni; ++k) {
+        if (in[k].p < 2) return FPC_EINVAL;
+    }
+    first_tile_inverse_batch<<<ni, 256, 0, st>>>(b.first_jobs);
+    for (int t = 0; t < npanels; ++t) {
+        const int nj = b.panel_njobs[t];
+        if (nj == 0) continue;
+        sweep_panel_batch<<<(unsigned)b.panel_tiles[t], 256, 0, st>>>(b.panel_jobs + b.panel_job0[t], nj);
+    }
+    first_level_decide_batch<<<(unsigned)((b.decide_elems + 255) / 256), 256, 0, st>>>(b.decide_jobs, ni);
+    FPC_HIP(hipGetLastError());
+    return FPC_OK;
+}
+
+// Host side of the job tables: fills `jobs_host` (first-tile jobs, then the
+// panel jobs of every step, then the decision jobs) for instances whose
+// matrices, buffers and outputs are given, and the launch shapes.
+int first_level_batch_plan(const std::vector<FirstLevelInst> &in, std::vector<SweepJob> &first,
+                           std::vector<SweepJob> &panels, std::vector<int> &panel_job0, std::vector<int> &panel_njobs,
+                           std::vector<int64_t> &panel_tiles, std::vector<DecideJob> &decide, int64_t &decide_elems)
+{
+    int maxp = 0;
+    for (const auto &I : in) maxp = std::max(maxp, I.p);
+    const int npanels = (maxp + kNB - 1) / kNB;
+    first.clear();
+    panels.clear();
+    decide.clear();
+    panel_job0.assign(npanels, 0);
+    panel_njobs.assign(npanels, 0);
+    panel_tiles.assign(npanels, 0);
+    for (const auto &I : in) {
+        SweepJob J{};
+        J.Ain = I.C;
+        J.p = I.p;
+        J.Pinv = I.pinv0;
+        J.bad = I.bad;
+        first.push_back(J);
+    }
+    for (int t = 0; t < npanels; ++t) {
+        panel_job0[t] = (int)panels.size();
+        int64_t tiles = 0;
+        for (const auto &I : in) {
+            const int k0 = t * kNB;
+            if (k0 >= I.p) continue;
+            SweepJob J{};
+            J.Ain = t == 0 ? I.C : (t & 1 ? I.buf0 : I.buf1);
+            J.Aout = t & 1 ? I.buf1 : I.buf0;
+            J.p = I.p;
+            J.k0 = k0;
+            J.nb = std::min(kNB, I.p - k0);
+            J.Pinv = t & 1 ? I.pinv1 : I.pinv0;
+            J.next_k0 = k0 + kNB;
+            J.next_nb = J.next_k0 < I.p ? std::min(kNB, I.p - J.next_k0) : 0;
+            J.Pinv_next = t & 1 ? I.pinv0 : I.pinv1;
+            J.bad = I.bad;
+            J.nbt = (I.p + kNB - 1) / kNB;
+            J.tile0 = tiles;
+            tiles += (int64_t)J.nbt * J.nbt;
+            panels.push_back(J);
+        }
+        panel_njobs[t] = (int)panels.size() - panel_job0[t];
+        panel_tiles[t] = tiles;
+    }
+    int64_t elems = 0;
+    for (const auto &I : in) {
+        DecideJob D{};
+        const int last = (I.p + kNB - 1) / kNB - 1;  // the last panel wrote buffer last & 1
+        D.Om = last & 1 ? I.buf1 : I.buf0;
+        D.p = I.p;
+        D.n = I.n;
+        D.q = I.q;
+        D.adj = I.adj;
+        D.bad = I.bad;
+        D.deleted = I.deleted;
+        D.elem0 = elems;
+        elems += ((int64_t)I.p * I.p + 255) / 256 * 256;  // each instance starts a block
+        decide.push_back(D);
+    }
+    decide_elems = elems;
+    return FPC_OK;
+}
+
+namespace {
 
 // Workspace of fpc_first_level_noalloc, held by every device the library
 // runs on until the process ends: the two sweep buffers and the panel

@@ -99,6 +99,7 @@ struct fpc_ctx {
     fpc::HostBuf h_inst;          // pinned staging for the instance table
     fpc::HostBuf h_flag;          // pinned landing of the correlation flags
     void *scratch = nullptr;      // this device's address of the no-allocation workspace (first_level.hip)
+
 };
 
 namespace fpc {
@@ -116,14 +117,22 @@ struct EdgeRec {
 // ---- correlation (corr.hip)
 // reuse_stats: the column statistics of the previous call on the same X
 // (same n, p) are still in the context and are used as they are.
+// keep_flags: the error flags (non-finite, constant column) are not cleared
+// first, so several instances accumulate into them.
 int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int method, void *C_out,
-                 bool reuse_stats = false, bool wait = true);
+                 bool reuse_stats = false, bool wait = true, bool keep_flags = false);
+int corr_reserve(fpc_ctx *ctx, int n, int p, int method);
 // With wait = false the products are only queued: corr_check waits once for
 // every queued correlation (and max_abs_diff) and reports their flags.
-int corr_max_abs_diff_enqueue(fpc_ctx *ctx, const double *c64, const float *c32, int p);
+// slot (device, 8 bytes; NULL: the context's flag word): the largest |c64 - c32| as FP64 bits
+int corr_max_abs_diff_enqueue(fpc_ctx *ctx, const double *c64, const float *c32, int p,
+                              unsigned long long *slot = nullptr);
 // c32 := FP32 rounding of c64 (device, p x p), queued.
 int corr_round_enqueue(fpc_ctx *ctx, const double *c64, float *c32, int p, bool wait);
 int corr_check(fpc_ctx *ctx, double *max_abs_diff);
+// The same queued, with an index out of range setting *bad (device).
+int gather_rows_enqueue(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p, const int32_t *rows, int n,
+                        void *out, int *bad);
 // out (device, n x p) := rows[r] of X (device, x_rows x p); FPC_EINVAL for an index out of range.
 int gather_rows(fpc_ctx *ctx, const void *X, int x_dtype, int64_t x_rows, int p, const int32_t *rows, int n,
                 void *out);
@@ -138,6 +147,49 @@ int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r
 // *d_bad (device int) becomes nonzero if C is not positive definite.
 int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
                         uint8_t *indep_out, const int **d_bad);
+// Many instances at once: each instance's matrix C (FP64, p x p), two p x p
+// sweep buffers, two 32 x 32 panel inverses, its flag and counter, and its
+// adjacency bytes (written: 1 = kept).
+struct FirstLevelInst {
+    const double *C;
+    double *buf0, *buf1, *pinv0, *pinv1;
+    int *bad;
+    unsigned long long *deleted;
+    uint8_t *adj;
+    int p, n;
+    double q;
+};
+struct SweepJob {
+    const double *Ain;
+    double *Aout;
+    const double *Pinv;
+    double *Pinv_next;
+    int *bad;
+    int p, k0, nb, next_k0, next_nb, nbt;
+    int64_t tile0;
+};
+struct DecideJob {
+    const double *Om;
+    uint8_t *adj;
+    int *bad;
+    unsigned long long *deleted;
+    int p, n;
+    double q;
+    int64_t elem0;
+};
+struct FirstLevelBatchBufs {
+    const SweepJob *first_jobs;        // device, one per instance
+    const SweepJob *panel_jobs;        // device, every step's jobs
+    const DecideJob *decide_jobs;      // device, one per instance
+    std::vector<int> panel_job0, panel_njobs;
+    std::vector<int64_t> panel_tiles;
+    int64_t decide_elems;
+};
+int first_level_batch_plan(const std::vector<FirstLevelInst> &in, std::vector<SweepJob> &first,
+                           std::vector<SweepJob> &panels, std::vector<int> &panel_job0, std::vector<int> &panel_njobs,
+                           std::vector<int64_t> &panel_tiles, std::vector<DecideJob> &decide, int64_t &decide_elems);
+int first_level_batch_enqueue(fpc_ctx *ctx, const std::vector<FirstLevelInst> &in, const FirstLevelBatchBufs &b);
+
 // Sets ctx->scratch to the device address of the static no-allocation
 // workspace (the context's device current).
 int noalloc_init(fpc_ctx *ctx);
@@ -200,6 +252,67 @@ void tuning_defaults(fpc_tuning *t);
 // synchronise the stream before the next level and before level_timing.
 int level_tests(fpc_ctx *ctx, const LevelLaunch &L, const std::vector<int64_t> &host_ntests,
                 LevelTiming *timing);
+// ---- level loop on the device (batch_graph.hip)
+// Per-instance sources of the level's instance table (device array).
+struct DevInstSrc {
+    const float *C32;      // FP32 matrix (mixed form) or NULL
+    const double *C64;     // FP64 matrix
+    int p, n;
+    double q;              // threshold
+    const double *c_err;   // device: largest entry error of the FP32 matrix (NULL: 0)
+};
+struct DeviceLevelClass {
+    int max_m;             // bound of the class's list lengths (fixes kernel and LDS)
+    const int64_t *range;  // device [begin, end) of the class in the level's edge table
+};
+struct DeviceLevel {
+    int l;
+    bool fp32;
+    const EdgeRec *edges;  // device, the level's table (classes contiguous)
+    const int32_t *cand;
+    const void *insts;     // device InstRec table (level_inst_table_enqueue)
+    uint64_t *minhit;      // device, per record, all ones at the start
+    unsigned long long *counters, *inst_cnt;
+    int64_t *queue;
+    int64_t queue_cap;
+    int64_t *plan;         // plan buffer: 3 * n_classes + the level's table size entries
+    int max_m_all;         // largest bound of the classes (FP64 re-run)
+    const DeviceLevelClass *classes;  // host
+    int n_classes;         // at most kMaxDeviceClasses
+};
+
+// List-length bounds of a device-built level's size classes (ascending,
+// the last kBinomRows - 1): maximal runs of m that launch the same kernel
+// with the same workgroups per CU (registers, the LDS of the run's bound,
+// the tuning cap), so a class sized for its bound runs at the occupancy of
+// any of its lists; at most kMaxDeviceClasses.
+constexpr int kMaxDeviceClasses = 16;
+std::vector<int> device_class_bounds(const fpc_ctx *ctx, int l, bool fp32);
+size_t inst_rec_bytes();
+// The whole batch call on the device in one captured graph
+// (fpc_skeleton_batch with FPC_FLAG_GRAPH).  kGraphFallback: the call is
+// outside what the graph path takes, or a capacity was outgrown; the
+// host-driven batch runs instead.
+constexpr int kGraphFallback = -1000;
+constexpr int kMaxGraphLevel = 7;   // C(1023, 7) < 2^63: the widest list class stays countable
+constexpr int kMaxGraphP = 4096;    // LDS of the per-node component search
+struct GraphBatchOut {
+    struct Inst {
+        std::vector<uint8_t> adj;                 // p x p, 1 = edge kept
+        std::vector<int64_t> sep_pair, sep_off;   // separating sets of the subset levels
+        std::vector<int32_t> sep_level, sep_nodes;
+        std::vector<fpc_level_stats> levels;      // first level, then the subset levels run
+        double c_err = 0.0, q = 0.0;
+    };
+    std::vector<Inst> inst;
+    double graph_ms = 0.0, total_ms = 0.0;  // device time of the graph (events), whole call
+    double prep_ms = 0.0, capture_ms = 0.0, instantiate_ms = 0.0, run_ms = 0.0;  // host phases
+};
+int skeleton_batch_graph(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_instance *inst, GraphBatchOut &out);
+int level_inst_table_enqueue(fpc_ctx *ctx, const DevInstSrc *src, int ni, int l, double band_z, double tau, bool fp32,
+                             void *out);
+int level_tests_device(fpc_ctx *ctx, const DeviceLevel &D);
+
 // Reads the timings of the last level_tests once its work has completed.
 int level_timing(fpc_ctx *ctx, LevelTiming *timing);
 // Queues minhit[e] = all ones (no hit) for the level's edges and zeroes

@@ -1045,6 +1045,44 @@ int validate_batch(const fpc_params *P, int ni, const fpc_instance *inst)
     return FPC_OK;
 }
 
+// FPC_FLAG_GRAPH: the whole batch on the device in one captured graph
+// (batch_graph.hip), then the results assembled as the host-driven batch
+// would.  kGraphFallback: the call takes the host-driven path.
+int skeleton_batch_device(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_instance *inst, fpc_result **outs,
+                          double t_start)
+{
+    GraphBatchOut g;
+    int rc = skeleton_batch_graph(ctx, P, ni, inst, g);
+    if (rc) return rc;
+    if (trace_on())
+        std::fprintf(stderr,
+                     "[fpc] batch of %d as one graph: device %.2f ms, call %.2f ms (prepare %.2f, capture %.2f, "
+                     "instantiate %.2f, launch to results %.2f)\n",
+                     ni, g.graph_ms, g.total_ms, g.prep_ms, g.capture_ms, g.instantiate_ms, g.run_ms);
+    for (int k = 0; k < ni; ++k) {
+        GraphBatchOut::Inst &o = g.inst[k];
+        Run R;
+        init_run(R, ctx, P, inst[k].p, inst[k].n);
+        R.adj.swap(o.adj);
+        R.c_err = o.c_err;
+        R.sep.first_level = true;
+        R.sep.nodes.swap(o.sep_nodes);
+        R.sep.lists.resize(o.sep_pair.size());
+        for (size_t t = 0; t < o.sep_pair.size(); ++t)
+            R.sep.lists[t] = SepList{o.sep_pair[t], o.sep_off[t], o.sep_level[t]};
+        R.levels.swap(o.levels);
+        for (const fpc_level_stats &st : R.levels) R.total_exec += st.tests_executed;
+        if ((rc = assemble(R, 0.0, 0.0, t_start, &outs[k]))) {
+            for (int t = 0; t < k; ++t) {
+                fpc_result_free(outs[t]);
+                outs[t] = nullptr;
+            }
+            return rc;
+        }
+    }
+    return FPC_OK;
+}
+
 // Several instances: correlation and first level one instance after the
 // other, then every following level of all instances in shared launches.
 // Each instance takes exactly the levels, in the same order, that a run of
@@ -1058,6 +1096,11 @@ int skeleton_batch_impl(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_ins
     if (rc) return rc;
     FPC_HIP(hipSetDevice(ctx->device));
     ctx->use_pair_kernel = !(P->flags & FPC_FLAG_PER_TEST_KERNEL);
+    if ((P->flags & FPC_FLAG_GRAPH) && ctx->use_pair_kernel) {
+        rc = skeleton_batch_device(ctx, P, ni, inst, outs, t_start);
+        if (rc != kGraphFallback) return rc;
+        if (trace_on()) std::fprintf(stderr, "[fpc] batch of %d: host-driven levels\n", ni);
+    }
     const bool mixed = P->precision == FPC_PREC_MIXED;
     // every instance's matrices stay resident through all levels
     std::vector<size_t> off64(ni), off32(ni);

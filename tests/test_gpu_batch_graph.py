@@ -1,0 +1,195 @@
+"""The whole batch call as one device graph (fpc_skeleton_batch with
+FPC_FLAG_GRAPH), through the C ABI (GPU only).
+
+In that mode the candidate sets, edge tables, tests, re-runs and deletions
+of every level run on the device, and the results must be those of the
+host-driven batch: skeleton, separating sets, and per level the level,
+largest candidate set, eligible edges, possible tests, deletions and
+required tests (tests executed and re-run depend on launch shapes and are
+not compared).  At small sizes the FP64 results are also checked against
+the oracle.  A call in graph mode reports corr_ms = first_level_ms = 0 (the
+device time is not split); the host-driven path reports both, which tells
+the two apart.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import semdata
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GRAPH = 4  # FPC_FLAG_GRAPH
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fpc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_04626_amd as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(fpc):
+    c = fpc.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def graph_ran(res):
+    return res["corr_ms"] == 0.0 and res["first_level_ms"] == 0.0
+
+
+def level_rows(res):
+    return [(x["level"], x["max_cand"], x["edges_eligible"], x["tests_possible"], x["deleted"], x["tests_required"])
+            for x in res["levels"]]
+
+
+def same(a, b, tag):
+    assert np.array_equal(a["adj"], b["adj"]), f"{tag}: skeletons differ"
+    assert np.array_equal(a["sep_level"], b["sep_level"]), f"{tag}: separating-set levels differ"
+    assert np.array_equal(a["sep_kind"], b["sep_kind"]), f"{tag}: separating-set kinds differ"
+    assert a["sepsets"] == b["sepsets"], f"{tag}: separating sets differ"
+    assert level_rows(a) == level_rows(b), f"{tag}: levels differ\n{level_rows(a)}\n{level_rows(b)}"
+    assert a["corr_max_abs_err"] == b["corr_max_abs_err"], f"{tag}: entry errors differ"
+
+
+def device_instances(inst):
+    base = inst[0][0]
+    base_d = dev(base)
+    out = []
+    for X, rows in inst:
+        Xd = base_d if X is base else dev(X)
+        out.append((Xd, None if rows is None else dev(rows)))
+    return out
+
+
+@pytest.mark.parametrize("prec,c32", [(0, 2), (1, 2), (1, 3), (1, 1)], ids=["fp64", "mixed", "mixed-fp32c", "mixed-bf16x3"])
+def test_graph_batch_equals_host_batch(fpc, ctx, prec, c32):
+    """Bootstraps of one data set and uneven independent data sets."""
+    base, boots, datas, cfg = semdata.batched_workload(n_boot=6, n_data=8, scale=0.1,
+                                                       x_dtype="f64" if prec == 0 else "f32")
+    inst = [(base, None)] + [(base, r) for r in boots] + [(d, None) for d in datas]
+    _say(f"[graph batch] {len(inst)} instances p={[x.shape[1] for x, _ in inst]} n={cfg['n']} prec={prec} c32={c32}")
+    dinst = device_instances(inst)
+    kw = dict(alpha=cfg["alpha"], max_level=cfg["max_level"], precision=prec, c32_method=c32)
+    got = fpc.fpc_skeleton_batch(ctx, dinst, flags=GRAPH, **kw)
+    ref = fpc.fpc_skeleton_batch(ctx, dinst, flags=0, **kw)
+    assert all(graph_ran(g) for g in got) and not any(graph_ran(r) for r in ref)
+    for k in range(len(inst)):
+        same(got[k], ref[k], f"instance {k}")
+    if prec == 0:
+        for k in (0, 1, 7, len(inst) - 1):
+            X, rows = inst[k]
+            Xk = X if rows is None else X[rows]
+            o = oracle.skeleton(oracle.corr(Xk), Xk.shape[0], alpha=cfg["alpha"], max_level=cfg["max_level"])
+            assert np.array_equal(got[k]["adj"], o["adj"]) and got[k]["sepsets"] == o["sepsets"], f"oracle {k}"
+    _say(f"  levels of instance 0: {level_rows(got[0])}")
+
+
+def test_graph_batch_uneven_levels_and_small_p(fpc, ctx):
+    """Instances whose level sequences differ: a dense graph that reaches
+    level 7 (the graph mode's cap), a sparse one that jumps down to its
+    largest candidate set, and p = 3, 4 (no level, or only level 1 below
+    the first)."""
+    Xs = [semdata.sample(semdata.make_sem(40, 11, degree=10.0), 3000, 11),
+          semdata.sample(semdata.make_sem(60, 9, degree=3.0), 1500, 9),
+          semdata.sample(semdata.make_sem(3, 5, degree=2.0), 300, 5),
+          semdata.sample(semdata.make_sem(4, 6, degree=3.0), 300, 6),
+          semdata.sample(semdata.make_sem(25, 8, degree=6.0), 800, 8)]
+    dinst = [(dev(X), None) for X in Xs]
+    for max_level in (7, 2, 0):
+        _say(f"[graph batch] uneven levels, max_level={max_level}")
+        got = fpc.fpc_skeleton_batch(ctx, dinst, alpha=0.01, max_level=max_level, flags=GRAPH)
+        ref = fpc.fpc_skeleton_batch(ctx, dinst, alpha=0.01, max_level=max_level)
+        assert all(graph_ran(g) for g in got)
+        for k, X in enumerate(Xs):
+            same(got[k], ref[k], f"max_level {max_level} instance {k}")
+            o = oracle.skeleton(oracle.corr(X), X.shape[0], alpha=0.01, max_level=max_level)
+            assert np.array_equal(got[k]["adj"], o["adj"]) and got[k]["sepsets"] == o["sepsets"]
+        _say(f"  levels: {[[x['level'] for x in g['levels']] for g in got]}")
+        if max_level == 7:
+            assert got[0]["levels"][1]["level"] == 7  # the dense graph starts at the cap
+            assert [x["level"] for x in got[2]["levels"]][0] == 1  # p = 3: first level l = 1, then at most l = 0
+
+
+def test_graph_batch_outside_its_range_runs_host_driven(fpc, ctx):
+    """No level cap, a cap above 7, a test budget or the per-test kernel:
+    the call runs host-driven, with the same results."""
+    X = semdata.sample(semdata.make_sem(30, 4, degree=4.0), 1000, 4)
+    dinst = [(dev(X), None), (dev(X[:700]), None)]
+    for kw in (dict(max_level=-1), dict(max_level=8), dict(max_level=-1, max_tests=10 ** 9),
+               dict(max_level=-1, flags=GRAPH | fpc.FPC_FLAG_PER_TEST_KERNEL)):
+        flags = kw.pop("flags", GRAPH)
+        got = fpc.fpc_skeleton_batch(ctx, dinst, alpha=0.01, flags=flags, **kw)
+        base = fpc.fpc_skeleton_batch(ctx, dinst, alpha=0.01, **kw)
+        assert not any(graph_ran(g) for g in got), kw
+        for k in range(2):
+            assert np.array_equal(got[k]["adj"], base[k]["adj"]) and got[k]["sepsets"] == base[k]["sepsets"]
+
+
+def test_graph_batch_repeated_and_shrinking_calls(fpc, ctx):
+    """The graph is captured per call over a reused pool: a call, the same
+    call again, then a smaller batch, each equal to the host-driven batch."""
+    base, boots, datas, cfg = semdata.batched_workload(n_boot=3, n_data=3, scale=0.08)
+    inst = [(base, r) for r in boots] + [(d, None) for d in datas]
+    dinst = device_instances(inst)
+    kw = dict(alpha=cfg["alpha"], max_level=cfg["max_level"], precision=1)
+    ref = fpc.fpc_skeleton_batch(ctx, dinst, **kw)
+    for rep in range(2):
+        got = fpc.fpc_skeleton_batch(ctx, dinst, flags=GRAPH, **kw)
+        for k in range(len(inst)):
+            same(got[k], ref[k], f"call {rep} instance {k}")
+    got = fpc.fpc_skeleton_batch(ctx, dinst[-2:], flags=GRAPH, **kw)
+    for k in range(2):
+        same(got[k], ref[len(inst) - 2 + k], f"smaller batch instance {k}")
+
+
+def test_graph_batch_errors(fpc, ctx):
+    """A resample index out of range and a constant column are reported as
+    in the host-driven path; the context works afterwards."""
+    X = semdata.sample(semdata.make_sem(10, 1), 200, 1)
+    Xd = dev(X)
+    bad_rows = torch.tensor([0, 1, 500] + [2] * 197, dtype=torch.int32, device="cuda")
+    with pytest.raises(fpc.FastPCError):
+        fpc.fpc_skeleton_batch(ctx, [(Xd, None), (Xd, bad_rows)], alpha=0.01, max_level=3, flags=GRAPH)
+    Xc = X.copy()
+    Xc[:, 4] = 1.0
+    with pytest.raises(fpc.FastPCError):
+        fpc.fpc_skeleton_batch(ctx, [(Xd, None), (dev(Xc), None)], alpha=0.01, max_level=3, flags=GRAPH)
+    got = fpc.fpc_skeleton_batch(ctx, [(Xd, None)], alpha=0.01, max_level=3, flags=GRAPH)
+    assert graph_ran(got[0])
+    same(got[0], fpc.fpc_skeleton_batch(ctx, [(Xd, None)], alpha=0.01, max_level=3)[0], "after errors")
+
+
+def test_graph_batch_full_size(fpc, ctx):
+    """64 bootstrap resamples of a 500-variable data set and 16 data sets
+    with p uniform in [50, 2000] (n = 5000, mixed form, max_level 4): every
+    instance equal to the host-driven batch."""
+    base, boots, datas, cfg = semdata.batched_workload()
+    _say(f"[graph batch full] 64 + 16 instances, p={[d.shape[1] for d in datas]}")
+    base_d = dev(base)
+    inst = [(base_d, dev(r)) for r in boots] + [(dev(d), None) for d in datas]
+    kw = dict(alpha=cfg["alpha"], max_level=cfg["max_level"], precision=1)
+    got = fpc.fpc_skeleton_batch(ctx, inst, flags=GRAPH, **kw)
+    _say(f"  graph mode: {got[0]['total_ms']:.1f} ms")
+    ref = fpc.fpc_skeleton_batch(ctx, inst, **kw)
+    assert all(graph_ran(g) for g in got)
+    for k in range(len(inst)):
+        same(got[k], ref[k], f"instance {k}")

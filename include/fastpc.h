@@ -38,6 +38,9 @@ extern "C" {
 #define FPC_ENOMEM 5     /* host or device allocation failed                                       */
 #define FPC_EDEVICE 6    /* a HIP runtime call failed; fpc_last_hip_error() names it               */
 #define FPC_ESCRATCH 7   /* problem larger than the static workspace of a no-allocation call       */
+#define FPC_ETOOLARGE 8  /* a subset level (l <= p-3) met a candidate set of 1024 or more variables:
+                            the level kernels enumerate lists of at most 1023 (e.g. the forward
+                            schedule on p >= 1026 variables, whose level 0 sees lists of p - 2)   */
 
 /* ---------------------------------------------------------------- enums */
 #define FPC_F64 0 /* IEEE binary64 elements */
@@ -229,6 +232,12 @@ typedef struct fpc_params {
                              lies within 1e-4 of the FP64 z (more tests re-run)          */
     int32_t c32_method;   /* mixed: FP32 matrix of the tests, FPC_CORR_BF16X6 (default, 0
                              selects it), FPC_CORR_BF16X3 or FPC_CORR_FP32                */
+    int32_t stop_after_levels; /* > 0: return at the level boundary after this many levels
+                             of this call (the first level, l = p-2, counts as one), with
+                             fpc_result.next_level set; 0: run to the end                */
+    const struct fpc_checkpoint *resume; /* NULL: start on the complete graph; else continue
+                             the run whose level-boundary state this is (the same data
+                             and parameters; see fpc_checkpoint)                        */
 } fpc_params;
 
 typedef struct fpc_level_stats {
@@ -278,11 +287,49 @@ typedef struct fpc_result {
     int32_t *log_level;       /* level of the deletion                                   */
     int64_t n_lists;          /* pairs whose separating set is of LIST kind              */
     int64_t *list_pairs;      /* their pair indices, increasing (n_lists entries)        */
+    int32_t next_level;       /* the level the run continues with (a call stopped by
+                                 stop_after_levels), -1 when the run is complete          */
 } fpc_result;
 
-/* Errors: FPC_EINVAL, FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET,
- * FPC_ENOMEM, FPC_EDEVICE.  On success *out is a library allocation
- * freed with fpc_result_free; on error *out is NULL. */
+/* ------------------------------------------------------------- checkpoint / resume
+ * The state of a run at a level boundary.  Under the stable schedule (Sec.
+ * 4.1: deletions applied at the end of each level) the graph and the
+ * separating sets found so far determine every later level, given C (which
+ * is recomputed from the same data): resuming a run from any boundary
+ * gives the result of the uninterrupted run (skeleton, separating sets,
+ * level statistics in execution order).
+ *   p           variables
+ *   next_level  the next level to run: min(the level after the last one
+ *               run, the largest candidate set) in reverse order, the level
+ *               after it in forward order; -1: complete
+ *   adj         p x p, 1 = edge (host)
+ *   sep_*       per pair, as in fpc_result (host)
+ *   levels      the statistics of the levels run so far (host)
+ * All arrays are borrowed for the call.  A reverse run's checkpoint holds
+ * the first level (levels[0].level = p-2), whose deleted pairs are those
+ * absent from adj of kind FPC_SEP_ALL_BUT. */
+typedef struct fpc_checkpoint {
+    int32_t p;
+    int32_t next_level;
+    const uint8_t *adj;
+    const int32_t *sep_level;
+    const int8_t *sep_kind;
+    const int64_t *sep_off;
+    const int32_t *sep_nodes;
+    int32_t n_levels;
+    const fpc_level_stats *levels;
+} fpc_checkpoint;
+
+/* ck := views of r's arrays (valid while r lives). */
+void fpc_checkpoint_of(const fpc_result *r, fpc_checkpoint *ck);
+
+/* Errors: FPC_EINVAL (also: a checkpoint of another p, a next_level
+ * outside [-1, p-3], NULL arrays, or feature logging with resume),
+ * FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET, FPC_ETOOLARGE, FPC_ENOMEM,
+ * FPC_EDEVICE.  On success *out is a library allocation freed with
+ * fpc_result_free; on error *out is NULL.  FPC_FAIL_ALLOC=1 in the
+ * environment makes every device allocation the library attempts fail with
+ * FPC_ENOMEM before the runtime is called (a test hook). */
 int fpc_skeleton(fpc_ctx *ctx, const fpc_params *params, fpc_result **out);
 void fpc_result_free(fpc_result *r);
 
@@ -344,7 +391,7 @@ int fpc_set_recheck_queue(fpc_ctx *ctx, int64_t initial, int64_t max);
  * (FPC_FLAG_GRAPH, FPC_FLAG_PER_TEST_KERNEL) and x_dtype apply to every
  * instance; schedule must be FPC_REVERSE and order FPC_ORDER_LEX (else
  * FPC_EINVAL); X, n, p and x_on_device are not read; max_tests is a
- * per-instance budget.
+ * per-instance budget; stop_after_levels must be 0 and resume NULL.
  *
  * FPC_FLAG_GRAPH, with 0 <= max_level <= 7, max_tests = 0, no
  * FPC_FLAG_PER_TEST_KERNEL and every p <= 4096: the whole call runs on the
@@ -387,7 +434,8 @@ int fpc_skeleton_batch(fpc_ctx *ctx, const fpc_params *params, int n_inst, const
  * order, which only changes how soon a separating set is found. */
 size_t fpc_mlp_bytes(void);
 int fpc_mlp_params(void);
-/* model := params (host, FP32) with zero Adam state. */
+/* model := params (host, FP32) with zero Adam state.  FPC_EINVAL (model
+ * untouched) if any parameter is NaN or infinite. */
 int fpc_mlp_init(fpc_ctx *ctx, void *model, const float *params);
 /* params_out (host) := the FP32 master parameters. */
 int fpc_mlp_get(fpc_ctx *ctx, const void *model, float *params_out);

@@ -49,8 +49,7 @@ _lib = None
 def _L():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
+        build()  # compiles when the library is missing or older than its source
         lib = ctypes.CDLL(_LIB)
         d, i, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
         lib.orc_ppnd16.restype = d
@@ -75,6 +74,10 @@ def _L():
         lib.orc_candidates.argtypes = [vp, i, i, i, vp]
         lib.orc_skeleton.restype = vp
         lib.orc_skeleton.argtypes = [vp, i, i, d, i, i, i, i64, i, i]
+        lib.orc_skeleton_ex.restype = vp
+        lib.orc_skeleton_ex.argtypes = [vp, i, i, d, i, i, i, i64, i, i, i, vp, vp, vp, vp, vp, i]
+        lib.orc_result_next_level.restype = i
+        lib.orc_result_next_level.argtypes = [vp]
         lib.orc_result_free.argtypes = [vp]
         lib.orc_result_status.restype = i
         lib.orc_result_status.argtypes = [vp]
@@ -201,7 +204,7 @@ def pair_index(i: int, j: int, p: int) -> int:
 def skeleton(C: np.ndarray, n: int, alpha: float | None = None, q: float | None = None,
              max_level: int = -1, reverse: bool = True, stable: bool = True,
              max_tests: int = 0, nthreads: int = 0, verbose: bool = False,
-             partial_ok: bool = False) -> dict:
+             partial_ok: bool = False, stop_after_levels: int = 0, resume: dict | None = None) -> dict:
     """Phase I (Algorithm 2 if ``reverse`` else Algorithm 1), sampling
     version, on the correlation matrix ``C`` with sample size ``n``.
 
@@ -213,6 +216,12 @@ def skeleton(C: np.ndarray, n: int, alpha: float | None = None, q: float | None 
     ``partial_ok`` a run stopped by ``max_tests`` returns its counts so far
     (``budget_stopped`` = True; the graph and separating sets are then
     incomplete).
+
+    ``stop_after_levels`` > 0 returns at the level boundary after that many
+    levels of this call (``next_level`` >= 0 if the run is not complete);
+    ``resume`` continues from such a result (stable schedule): ``adj``,
+    ``sep_level``, ``sep_kind``, ``sepsets``, ``next_level``, and its
+    ``levels`` rows and ``total_tests``, which the result carries on.
     """
     C = np.ascontiguousarray(C, dtype=np.float64)
     p = C.shape[0]
@@ -221,8 +230,24 @@ def skeleton(C: np.ndarray, n: int, alpha: float | None = None, q: float | None 
             raise ValueError("alpha or q required")
         q = quantile(alpha)
     lib = _L()
-    R = lib.orc_skeleton(_ptr(C), p, int(n), float(q), int(max_level), int(reverse),
-                         int(stable), int(max_tests), int(nthreads), int(verbose))
+    if resume is not None:
+        P = p * (p - 1) // 2
+        r_adj = np.ascontiguousarray(resume["adj"], dtype=np.uint8)
+        r_lev = np.ascontiguousarray(resume["sep_level"], dtype=np.int32)
+        r_kind = np.ascontiguousarray(resume["sep_kind"], dtype=np.int8)
+        r_off = np.zeros(P + 1, np.int64)
+        iu, ju = np.triu_indices(p, 1)
+        lists = [resume["sepsets"][(int(iu[k]), int(ju[k]))] if r_kind[k] == SEP_LIST else [] for k in range(P)]
+        r_off[1:] = np.cumsum([len(x) for x in lists])
+        r_nodes = np.array([v for x in lists for v in x] or [0], dtype=np.int32)
+        R = lib.orc_skeleton_ex(_ptr(C), p, int(n), float(q), int(max_level), int(reverse), int(stable),
+                                int(max_tests), int(nthreads), int(verbose), int(stop_after_levels),
+                                _ptr(r_adj), _ptr(r_lev), _ptr(r_kind), _ptr(r_off), _ptr(r_nodes),
+                                int(resume["next_level"]))
+    else:
+        R = lib.orc_skeleton_ex(_ptr(C), p, int(n), float(q), int(max_level), int(reverse), int(stable),
+                                int(max_tests), int(nthreads), int(verbose), int(stop_after_levels),
+                                None, None, None, None, None, 0)
     if not R:
         raise MemoryError("oracle allocation failed")
     try:
@@ -247,11 +272,15 @@ def skeleton(C: np.ndarray, n: int, alpha: float | None = None, q: float | None 
         iu, ju = np.triu_indices(p, 1)
         for k in np.nonzero(kind == SEP_LIST)[0]:
             sepsets[(int(iu[k]), int(ju[k]))] = [int(v) for v in nodes[off[k]:off[k + 1]]]
+        total = int(lib.orc_result_total_tests(R))
+        if resume is not None:  # the levels of the run so far, then this call's
+            rows = np.concatenate([np.asarray(resume["levels"], np.int64).reshape(-1, 5), rows])
+            secs = np.concatenate([np.asarray(resume.get("level_seconds", np.zeros(len(resume["levels"])))), secs])
+            total += int(resume["total_tests"])
         return dict(adj=adj, sep_level=lev, sep_kind=kind, sepsets=sepsets,
-                    levels=rows, level_seconds=secs,
-                    total_tests=int(lib.orc_result_total_tests(R)),
+                    levels=rows, level_seconds=secs, total_tests=total,
                     min_margin=float(lib.orc_result_min_margin(R)), q=float(q), p=p, n=int(n),
-                    budget_stopped=bool(stopped))
+                    budget_stopped=bool(stopped), next_level=int(lib.orc_result_next_level(R)))
     finally:
         lib.orc_result_free(R)
 

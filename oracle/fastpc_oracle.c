@@ -503,6 +503,7 @@ typedef struct {
     int64_t total_tests;
     double min_margin;  /* min |z - q| over all tests that ran */
     double q;
+    int next_level;     /* stopped at a level boundary: the level to run next; -1: complete */
 } orc_result;
 
 #define PAIR(i, j, p) ((int64_t)(i) * (p) - (int64_t)(i) * ((i) + 1) / 2 + ((j) - (i) - 1))
@@ -610,15 +611,53 @@ static int test_edge(const double *C, int p, int n, double q, int i, int j,
  *   max_tests  0 = unlimited, else ORC_EBUDGET once exceeded.
  *   nthreads   0 = OpenMP default.  verbose: per-level line on stderr.
  */
+orc_result *orc_skeleton_ex(const double *C, int p, int n, double q, int max_level,
+                            int reverse, int stable, int64_t max_tests, int nthreads,
+                            int verbose, int stop_after_levels, const uint8_t *adj0,
+                            const int32_t *sep_level0, const int8_t *sep_kind0,
+                            const int64_t *sep_off0, const int32_t *sep_nodes0,
+                            int next_level0);
+
 orc_result *orc_skeleton(const double *C, int p, int n, double q, int max_level,
                          int reverse, int stable, int64_t max_tests,
                          int nthreads, int verbose)
+{
+    return orc_skeleton_ex(C, p, n, q, max_level, reverse, stable, max_tests, nthreads,
+                           verbose, 0, NULL, NULL, NULL, NULL, NULL, 0);
+}
+
+/*
+ * orc_skeleton_ex -- orc_skeleton that can stop at a level boundary and
+ * continue from one.  Under the stable schedule the graph and the
+ * separating sets at the end of a level determine every later level (C
+ * given), so a run stopped and continued ends as the uninterrupted one.
+ *   stop_after_levels  > 0: return after this many levels of this call
+ *           (the first level of a reverse run counts as one), with
+ *           next_level set (-1 if the run is complete); 0: run to the end
+ *   adj0    NULL: start on the complete graph.  Else the state of a
+ *           stopped run (stable schedule only): its graph (p x p), per
+ *           pair its separating-set level and kind, offsets and nodes (the
+ *           layout of orc_result_sepsets), and the level to run next,
+ *           next_level0 (-1: the run is complete).  The statistics returned
+ *           are those of the levels this call runs.
+ */
+orc_result *orc_skeleton_ex(const double *C, int p, int n, double q, int max_level,
+                            int reverse, int stable, int64_t max_tests, int nthreads,
+                            int verbose, int stop_after_levels, const uint8_t *adj0,
+                            const int32_t *sep_level0, const int8_t *sep_kind0,
+                            const int64_t *sep_off0, const int32_t *sep_nodes0,
+                            int next_level0)
 {
     orc_result *R = (orc_result *)calloc(1, sizeof(orc_result));
     if (!R) return NULL;
     R->p = p;
     R->q = q;
     R->min_margin = INFINITY;
+    R->next_level = -1;
+    if (adj0 && (!stable || !sep_level0 || !sep_kind0 || !sep_off0 || next_level0 < -1 || next_level0 > p - 3)) {
+        R->status = ORC_EINVAL;
+        return R;
+    }
     if (!C || p < 2 || n <= p + 1 || !(q >= 0.0)) { R->status = ORC_EINVAL; return R; }
     for (int64_t k = 0; k < (int64_t)p * p; ++k)
         if (!isfinite(C[k])) { R->status = ORC_EINVAL; return R; }
@@ -652,6 +691,24 @@ orc_result *orc_skeleton(const double *C, int p, int n, double q, int max_level,
 
     int l = reverse ? p - 2 : 0;
     int first = 1;
+    if (adj0) {
+        /* continue a stopped run: its graph, separating sets and next level */
+        for (int a = 0; a < p; ++a)
+            for (int b = 0; b < p; ++b) R->adj[(size_t)a * p + b] = a != b && adj0[(size_t)a * p + b];
+        for (int64_t k = 0; k < P; ++k) {
+            R->sep_level[k] = sep_level0[k];
+            R->sep_kind[k] = sep_kind0[k];
+            if (sep_kind0[k] == 1 && sep_level0[k] > 0) {
+                R->sep_nodes[k] = (int32_t *)malloc(sizeof(int32_t) * (size_t)sep_level0[k]);
+                if (!R->sep_nodes[k]) { R->status = ORC_ENOMEM; goto done; }
+                memcpy(R->sep_nodes[k], sep_nodes0 + sep_off0[k], sizeof(int32_t) * (size_t)sep_level0[k]);
+            }
+        }
+        if (next_level0 < 0) { R->status = ORC_OK; goto done; }
+        l = next_level0;
+        first = 0;
+    }
+    int levels_run = 0;
     for (;;) {
         orc_level *LV = push_level(R);
         if (!LV) { R->status = ORC_ENOMEM; goto done; }
@@ -828,20 +885,25 @@ orc_result *orc_skeleton(const double *C, int p, int n, double q, int max_level,
             }
             nblist_free(&g);
         }
+        int next;
         if (reverse) {
-            if (l == 0) break;
-            int next = l - 1;
+            next = l - 1;
             if (first && max_level >= 0 && max_level < next) next = max_level;
             if (mmax < next) next = mmax; /* levels with no eligible edge change nothing */
-            if (next < 0) break;
-            l = next;
+            if (l == 0 || next < 0) next = -1;
         } else {
             /* continue only while some edge has |cand| > l (Algorithm 1's flag
              * is set at this level by |cand| >= l, the next level needs > l) */
-            if (LV->edges_eligible == 0 || mmax < l + 1) break;
-            if (max_level >= 0 && l + 1 > max_level) break;
-            l = l + 1;
+            next = l + 1;
+            if (LV->edges_eligible == 0 || mmax < l + 1) next = -1;
+            if (max_level >= 0 && l + 1 > max_level) next = -1;
         }
+        if (stop_after_levels > 0 && ++levels_run >= stop_after_levels) {
+            R->next_level = next;
+            break;
+        }
+        if (next < 0) break;
+        l = next;
         first = 0;
     }
     R->status = ORC_OK;
@@ -857,6 +919,7 @@ done:
 
 /* ---- result accessors (plain copies, for ctypes) ---- */
 int orc_result_status(const orc_result *R) { return R ? R->status : ORC_ENOMEM; }
+int orc_result_next_level(const orc_result *R) { return R->next_level; }
 int orc_result_nlevels(const orc_result *R) { return R->nlev; }
 int64_t orc_result_total_tests(const orc_result *R) { return R->total_tests; }
 double orc_result_min_margin(const orc_result *R) { return R->min_margin; }

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfastpc.so")
 
-FPC_OK, FPC_EINVAL, FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET, FPC_ENOMEM, FPC_EDEVICE, FPC_ESCRATCH = range(8)
+FPC_OK, FPC_EINVAL, FPC_ENONFINITE, FPC_ESINGULAR, FPC_EBUDGET, FPC_ENOMEM, FPC_EDEVICE, FPC_ESCRATCH, FPC_ETOOLARGE = range(9)
 FPC_NOALLOC_MAX_P = 512
 FPC_F64, FPC_F32 = 0, 1
 FPC_CORR_FP64, FPC_CORR_BF16X3, FPC_CORR_BF16X6, FPC_CORR_FP32 = 0, 1, 2, 3
@@ -34,7 +34,7 @@ EXPORTED = ["fpc_create", "fpc_destroy", "fpc_strerror", "fpc_last_hip_error", "
             "fpc_corr", "fpc_first_level", "fpc_ci_batch", "fpc_candidates", "fpc_skeleton", "fpc_skeleton_batch",
             "fpc_result_free", "fpc_orient", "fpc_mlp_bytes", "fpc_mlp_params", "fpc_mlp_init", "fpc_mlp_get",
             "fpc_mlp_forward", "fpc_mlp_grad", "fpc_mlp_train_step", "fpc_get_tuning", "fpc_set_tuning",
-            "fpc_set_recheck_queue", "fpc_level_series", "fpc_first_level_noalloc"]
+            "fpc_set_recheck_queue", "fpc_level_series", "fpc_first_level_noalloc", "fpc_checkpoint_of"]
 FPC_TUNE_LEVELS = 17
 TUNING_FIELDS = ("test_ranks_per_wave", "shared_ranks_per_wave", "window_growth", "first_window_items",
                  "max_blocks_per_cu", "shared_prefix_depth")
@@ -59,7 +59,8 @@ class fpc_params(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("order_model", ctypes.c_void_p), ("max_tests", ctypes.c_int64),
                 ("q_override", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("ill_cond_tau", ctypes.c_double), ("c32_method", ctypes.c_int32)]
+                ("ill_cond_tau", ctypes.c_double), ("c32_method", ctypes.c_int32),
+                ("stop_after_levels", ctypes.c_int32), ("resume", ctypes.c_void_p)]
 
 
 class fpc_level_stats(ctypes.Structure):
@@ -83,7 +84,14 @@ class fpc_result(ctypes.Structure):
                 ("corr_max_abs_err", ctypes.c_double), ("log_rows", ctypes.c_int64),
                 ("log_x", ctypes.POINTER(ctypes.c_float)), ("log_y", ctypes.POINTER(ctypes.c_uint8)),
                 ("log_group", ctypes.POINTER(ctypes.c_int32)), ("log_level", ctypes.POINTER(ctypes.c_int32)),
-                ("n_lists", ctypes.c_int64), ("list_pairs", ctypes.POINTER(ctypes.c_int64))]
+                ("n_lists", ctypes.c_int64), ("list_pairs", ctypes.POINTER(ctypes.c_int64)),
+                ("next_level", ctypes.c_int32)]
+
+
+class fpc_checkpoint(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("next_level", ctypes.c_int32), ("adj", ctypes.c_void_p),
+                ("sep_level", ctypes.c_void_p), ("sep_kind", ctypes.c_void_p), ("sep_off", ctypes.c_void_p),
+                ("sep_nodes", ctypes.c_void_p), ("n_levels", ctypes.c_int32), ("levels", ctypes.c_void_p)]
 
 
 class fpc_tuning(ctypes.Structure):
@@ -140,6 +148,8 @@ def _load():
     lib.fpc_set_recheck_queue.restype = i
     lib.fpc_result_free.argtypes = [ctypes.POINTER(fpc_result)]
     lib.fpc_result_free.restype = None
+    lib.fpc_checkpoint_of.argtypes = [ctypes.POINTER(fpc_result), ctypes.POINTER(fpc_checkpoint)]
+    lib.fpc_checkpoint_of.restype = None
     lib.fpc_orient.argtypes = [i, vp, vp, vp, vp, vp, vp]
     lib.fpc_orient.restype = i
     lib.fpc_mlp_bytes.argtypes = []
@@ -453,9 +463,14 @@ def fpc_mlp_train_step(ctx: Context, X, y, model, lr: float) -> float:
 def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, precision: int = FPC_PREC_FP64,
                  recheck_margin: float = 1e-3, schedule: int = FPC_REVERSE, max_tests: int = 0,
                  q_override: float = float("nan"), flags: int = 0, order_model=None, ill_cond_tau: float = 1e-4,
-                 c32_method: int = FPC_CORR_BF16X6) -> dict:
+                 c32_method: int = FPC_CORR_BF16X6, stop_after_levels: int = 0, resume: dict | None = None) -> dict:
     """Skeleton and separating sets of the data X (torch tensor on the
-    device, or a host numpy array), n x p row-major."""
+    device, or a host numpy array), n x p row-major.
+
+    stop_after_levels > 0 returns at the level boundary after that many
+    levels of this call (result["next_level"] >= 0 if the run is not
+    complete); resume continues from such a result (or one loaded with
+    load_checkpoint) on the same data and parameters."""
     prm = fpc_params()
     keep = X
     if isinstance(X, np.ndarray):
@@ -485,9 +500,71 @@ def fpc_skeleton(ctx: Context, X, alpha: float = 0.01, max_level: int = -1, prec
     prm.flags = int(flags)
     prm.ill_cond_tau = float(ill_cond_tau)
     prm.c32_method = int(c32_method)
+    prm.stop_after_levels = int(stop_after_levels)
+    if resume is not None:
+        ck, ck_keep = _checkpoint(resume)
+        prm.resume = ctypes.cast(ctypes.pointer(ck), ctypes.c_void_p)
     res = ctypes.POINTER(fpc_result)()
     _check(_lib.fpc_skeleton(ctx.handle, ctypes.byref(prm), ctypes.byref(res)), "fpc_skeleton")
     return _unpack(res)
+
+
+_CK_ARRAYS = (("adj", np.uint8), ("sep_level", np.int32), ("sep_kind", np.int8), ("sep_off", np.int64),
+              ("sep_nodes", np.int32))
+
+
+def _checkpoint(state: dict):
+    """A fpc_checkpoint over the arrays of a result (or loaded) dict, and
+    the arrays it borrows."""
+    arrs = {k: np.ascontiguousarray(state[k], dtype=t) for k, t in _CK_ARRAYS}
+    lv = state["levels"]
+    levels = (fpc_level_stats * max(len(lv), 1))()
+    for k, x in enumerate(lv):
+        for f, _ in fpc_level_stats._fields_:
+            setattr(levels[k], f, x[f])
+    ck = fpc_checkpoint()
+    ck.p = int(state["p"])
+    ck.next_level = int(state["next_level"])
+    for k, _ in _CK_ARRAYS:
+        setattr(ck, k, arrs[k].ctypes.data if arrs[k].size else None)
+    ck.n_levels = len(lv)
+    ck.levels = ctypes.cast(levels, ctypes.c_void_p)
+    return ck, (arrs, levels)
+
+
+def fpc_checkpoint_of(res: dict) -> dict:
+    """The level-boundary state of a fpc_skeleton result (views of its
+    arrays), as fpc_checkpoint_of fills a fpc_checkpoint; fpc_skeleton(...,
+    resume=) takes it."""
+    out = {k: res[k] for k, _ in _CK_ARRAYS}
+    out.update(p=res["p"], next_level=res["next_level"], levels=res["levels"])
+    return out
+
+
+def save_checkpoint(path: str, res: dict) -> None:
+    """Writes the level-boundary state of a fpc_skeleton result (plain
+    arrays, no pickled objects) for load_checkpoint."""
+    lv = res["levels"]
+    fi = [f for f, t in fpc_level_stats._fields_ if t is not ctypes.c_double]
+    fd = [f for f, t in fpc_level_stats._fields_ if t is ctypes.c_double]
+    si = np.array([[x[f] for f in fi] for x in lv], dtype=np.int64).reshape(len(lv), len(fi))
+    sd = np.array([[x[f] for f in fd] for x in lv], dtype=np.float64).reshape(len(lv), len(fd))
+    np.savez(path, p=np.int64(res["p"]), next_level=np.int64(res["next_level"]), level_int=si, level_double=sd,
+             **{k: np.asarray(res[k]) for k, _ in _CK_ARRAYS})
+
+
+def load_checkpoint(path: str) -> dict:
+    """The state written by save_checkpoint, as a dict fpc_skeleton(...,
+    resume=) takes."""
+    with np.load(path, allow_pickle=False) as z:
+        out = {k: z[k].copy() for k, _ in _CK_ARRAYS}
+        out["p"] = int(z["p"])
+        out["next_level"] = int(z["next_level"])
+        fi = [f for f, t in fpc_level_stats._fields_ if t is not ctypes.c_double]
+        fd = [f for f, t in fpc_level_stats._fields_ if t is ctypes.c_double]
+        out["levels"] = [dict({f: int(a[c]) for c, f in enumerate(fi)}, **{f: float(b[c]) for c, f in enumerate(fd)})
+                         for a, b in zip(z["level_int"], z["level_double"])]
+    return out
 
 
 def fpc_skeleton_batch(ctx: Context, instances, alpha: float = 0.01, max_level: int = -1,
@@ -636,7 +713,7 @@ def _unpack(res, owner: _Owner | None = None) -> dict:
                    total_tests=int(r.total_tests), total_required=sum(x["tests_required"] for x in levels),
                    q=float(r.q), corr_ms=float(r.corr_ms),
                    first_level_ms=float(r.first_level_ms), total_ms=float(r.total_ms),
-                   corr_max_abs_err=float(r.corr_max_abs_err), p=p)
+                   corr_max_abs_err=float(r.corr_max_abs_err), p=p, next_level=int(r.next_level))
 
 
 def sepset_of(res: dict, i: int, j: int):

@@ -333,6 +333,8 @@ extern "C" int fpc_mlp_params(void) { return mlp_params(); }
 extern "C" int fpc_mlp_init(fpc_ctx *ctx, void *model, const float *params)
 {
     if (!ctx || !model || !params) return FPC_EINVAL;
+    for (int k = 0; k < kParams; ++k)
+        if (!std::isfinite(params[k])) return FPC_EINVAL;
     FPC_HIP(hipMemsetAsync(model, 0, mlp_model_bytes(), ctx->stream));
     ModelView mv = view(model);
     FPC_HIP(hipMemcpyAsync(mv.master, params, sizeof(float) * kParams, hipMemcpyHostToDevice, ctx->stream));

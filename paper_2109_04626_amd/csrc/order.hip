@@ -37,7 +37,7 @@ __global__ __launch_bounds__(64) void features_kernel(const EdgeRec *__restrict_
 }
 
 // One block per edge: position a goes to rank(a) = #{b : s_b > s_a or
-// (s_b == s_a and b < a)}.  The edge's scores are staged in LDS (lists hold
+// (s_b == s_a and b < a)}, NaN scores taken as -inf.  The edge's scores are staged in LDS (lists hold
 // fewer than kBinomRows candidates), so the m^2 comparisons read LDS.
 __global__ __launch_bounds__(256) void reorder_kernel(const EdgeRec *__restrict__ edges,
                                                       const int32_t *__restrict__ cand_in,
@@ -47,7 +47,12 @@ __global__ __launch_bounds__(256) void reorder_kernel(const EdgeRec *__restrict_
     __shared__ float sc[kBinomRows];
     const EdgeRec E = edges[blockIdx.x];
     const int m = E.m, off = E.cand_off;
-    for (int a = threadIdx.x; a < m; a += 256) sc[a] = score[off + a];
+    // a NaN score ranks as -inf, so the ranks below are a total order and
+    // the output a permutation of the list whatever the model computes
+    for (int a = threadIdx.x; a < m; a += 256) {
+        const float x = score[off + a];
+        sc[a] = isnan(x) ? -INFINITY : x;
+    }
     __syncthreads();
     for (int a = threadIdx.x; a < m; a += 256) {
         const float sa = sc[a];

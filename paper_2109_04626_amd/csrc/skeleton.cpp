@@ -35,9 +35,18 @@ int hip_fail(hipError_t e, const char *what)
     return FPC_EDEVICE;
 }
 
+// FPC_FAIL_ALLOC=1: every device allocation fails with FPC_ENOMEM before
+// the runtime is called (a test hook for the error path; read per call).
+static bool alloc_hook_fails()
+{
+    const char *v = std::getenv("FPC_FAIL_ALLOC");
+    return v && v[0] == '1' && v[1] == 0;
+}
+
 int DevBuf::ensure(size_t need)
 {
     if (need <= bytes && ptr) return FPC_OK;
+    if (alloc_hook_fails()) return FPC_ENOMEM;
     release();
     size_t want = std::max(need, (size_t)256);
     hipError_t e = hipMalloc(&ptr, want);
@@ -181,6 +190,7 @@ extern "C" const char *fpc_strerror(int code)
     case FPC_ENOMEM: return "out of memory";
     case FPC_EDEVICE: return "HIP runtime error";
     case FPC_ESCRATCH: return "problem larger than the static workspace of the no-allocation entry point";
+    case FPC_ETOOLARGE: return "a candidate set of 1024 or more variables at a subset level";
     default: return "unknown error";
     }
 }
@@ -298,6 +308,20 @@ extern "C" int fpc_set_recheck_queue(fpc_ctx *ctx, int64_t initial, int64_t max)
     return FPC_OK;
 }
 
+extern "C" void fpc_checkpoint_of(const fpc_result *r, fpc_checkpoint *ck)
+{
+    if (!r || !ck) return;
+    ck->p = r->p;
+    ck->next_level = r->next_level;
+    ck->adj = r->adj;
+    ck->sep_level = r->sep_level;
+    ck->sep_kind = r->sep_kind;
+    ck->sep_off = r->sep_off;
+    ck->sep_nodes = r->sep_nodes;
+    ck->n_levels = r->n_levels;
+    ck->levels = r->levels;
+}
+
 extern "C" void fpc_result_free(fpc_result *r)
 {
     if (!r) return;
@@ -342,6 +366,7 @@ struct Run {
     std::vector<uint8_t> log_y;
     std::vector<int32_t> log_group, log_level;
     int32_t log_serial = 0;
+    int32_t next_level = -1;  // stopped at a level boundary: the level to continue with
 };
 
 // Runs fn(k) for k in [0, n) on the library's host threads.
@@ -371,7 +396,8 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
         int64_t e0, e1;         // edges [e0, e1) of instance k's candidate sets
         int64_t n_el = 0, n_cd = 0, possible = 0;
         int max_m = 0, sel_m = 0;
-        bool bad = false;
+        bool bad = false;       // the level's test count overflows
+        bool too_long = false;  // a list of kBinomRows candidates or more
         int64_t r = 0, c = 0;   // first record and list slot (pass 2)
     };
     std::vector<Chunk> chunks;
@@ -397,7 +423,7 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
             ch.max_m = std::max(ch.max_m, m);
             if (m < l) continue;
             if (m >= kBinomRows) {
-                ch.bad = true;
+                ch.too_long = true;
                 return;
             }
             const int64_t N = binom_sat(m, l);
@@ -414,6 +440,7 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     int64_t E = 0, T = 0;
     int sel_max_m = 0;
     for (Chunk &ch : chunks) {  // in instance order, so each instance's records stay together
+        if (ch.too_long) return FPC_ETOOLARGE;
         if (ch.bad) return FPC_EBUDGET;
         fpc_level_stats &st = sts[ch.k];
         st.max_cand = std::max(st.max_cand, ch.max_m);
@@ -555,6 +582,8 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     const int64_t *pairs = h_del + 2;
     int64_t ndel = 0;
     double t_tests0 = 0.0, t_tests1 = 0.0;
+    double prev_all_ms = 0.0, prev_test_ms = 0.0;  // device time of discarded attempts
+    int prev_launches = 0;
 retry:
     if ((rc = level_init(ctx, ctx->minhit.as<uint64_t>(), E, ctx->counters.as<unsigned long long>(), (int)n_cnt)))
         return rc;
@@ -595,6 +624,11 @@ retry:
         runs[k]->total_exec += (int64_t)cnt[8 + 2 * k];
     }
     if (cnt[3]) {  // the recheck queue overflowed: run the whole level again
+        // the discarded attempt's tests stay in the counts, so its device
+        // time stays in the timings
+        prev_all_ms += tm.all_ms;
+        prev_test_ms += tm.test_ms;
+        prev_launches += tm.test_launches;
         const int64_t grown = std::min(qcap * 4, ctx->queue_max);
         if (grown > qcap && ctx->queue.ensure(sizeof(int64_t) * 2 * grown) == FPC_OK) {
             qcap = grown;
@@ -696,9 +730,9 @@ retry:
                      t_copy - t_build, t_order - t_copy, t_bufs - t_order, t_tests1 - t_tests0, tm.all_ms, t_decode - t_tests1, now_ms() - t_decode, (long long)ndel,
                      fp32 ? cnt[1] : 0ull);
     for (auto &st : sts) {
-        st.kernel_ms = tm.all_ms;
-        st.test_kernel_ms = tm.test_ms;
-        st.test_launches = tm.test_launches;
+        st.kernel_ms = prev_all_ms + tm.all_ms;
+        st.test_kernel_ms = prev_test_ms + tm.test_ms;
+        st.test_launches = prev_launches + tm.test_launches;
         st.level_ms = level_ms;
     }
     return FPC_OK;
@@ -720,7 +754,44 @@ int validate(const fpc_params *P)
     if (P->c32_method != 0 && P->c32_method != FPC_CORR_BF16X3 && P->c32_method != FPC_CORR_BF16X6 &&
         P->c32_method != FPC_CORR_FP32)
         return FPC_EINVAL;
+    if (P->stop_after_levels < 0) return FPC_EINVAL;
+    if (const fpc_checkpoint *ck = P->resume) {
+        if (ck->p != P->p || ck->next_level < -1 || ck->next_level > P->p - 3 || ck->n_levels < 0) return FPC_EINVAL;
+        if (!ck->adj || !ck->sep_level || !ck->sep_kind || !ck->sep_off || (ck->n_levels && !ck->levels))
+            return FPC_EINVAL;
+        if (P->flags & FPC_FLAG_LOG_FEATURES) return FPC_EINVAL;
+        const int64_t PP = (int64_t)P->p * (P->p - 1) / 2;
+        if (ck->sep_off[0] != 0 || (ck->sep_off[PP] > 0 && !ck->sep_nodes)) return FPC_EINVAL;
+        for (int64_t k = 0; k < PP; ++k) {
+            const int8_t kind = ck->sep_kind[k];
+            if (kind != FPC_SEP_NONE && kind != FPC_SEP_LIST && kind != FPC_SEP_ALL_BUT) return FPC_EINVAL;
+            if (kind == FPC_SEP_LIST && (ck->sep_level[k] < 0 || ck->sep_off[k + 1] - ck->sep_off[k] != ck->sep_level[k]))
+                return FPC_EINVAL;
+        }
+    }
     return FPC_OK;
+}
+
+// The run's state from a level-boundary checkpoint (validated).
+void restore_run(Run &R, const fpc_checkpoint *ck)
+{
+    const int p = R.p;
+    std::memcpy(R.adj.data(), ck->adj, (size_t)p * p);
+    for (int i = 0; i < p; ++i) R.adj[(size_t)i * p + i] = 0;
+    R.sep.reset();
+    const int64_t PP = (int64_t)p * (p - 1) / 2;
+    for (int64_t k = 0; k < PP; ++k) {
+        if (ck->sep_kind[k] != FPC_SEP_LIST) continue;
+        const int l = ck->sep_level[k];
+        R.sep.lists.push_back(SepList{k, (int64_t)R.sep.nodes.size(), l});
+        R.sep.nodes.insert(R.sep.nodes.end(), ck->sep_nodes + ck->sep_off[k], ck->sep_nodes + ck->sep_off[k] + l);
+    }
+    R.sep.first_level = R.P->schedule == FPC_REVERSE && ck->n_levels > 0 && ck->levels[0].level == p - 2;
+    R.levels.assign(ck->levels, ck->levels + ck->n_levels);
+    for (const fpc_level_stats &st : R.levels) {
+        R.total_exec += st.tests_executed;
+        R.spent_possible += st.tests_possible;
+    }
 }
 
 // Instance state before the levels: the complete graph, no separating sets.
@@ -832,6 +903,23 @@ int first_stage(Run &R, double *ms)
                      kms, now_ms() - tw);
     st.level_ms = *ms;
     R.levels.push_back(st);
+    return FPC_OK;
+}
+
+// The first level's partial correlations (K = all but i, j) into ctx->rfirst
+// without its decisions: the learned order's features on a resumed run.
+int first_level_r(Run &R)
+{
+    fpc_ctx *ctx = R.ctx;
+    int rc;
+    if ((rc = ctx->rfirst.ensure(sizeof(double) * (size_t)R.p * R.p))) return rc;
+    const int *d_bad = nullptr;
+    if ((rc = first_level_enqueue(ctx, R.C64, R.p, R.n, R.q, ctx->rfirst.as<double>(), nullptr, &d_bad))) return rc;
+    FPC_HIP(hipStreamSynchronize(ctx->stream));
+    int h_bad = 0;
+    FPC_HIP(hipMemcpy(&h_bad, d_bad, sizeof(int), hipMemcpyDeviceToHost));
+    if (h_bad) return FPC_ESINGULAR;
+    R.Rfirst = ctx->rfirst.as<double>();
     return FPC_OK;
 }
 
@@ -948,6 +1036,7 @@ int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result
         std::memcpy(res->log_group, R.log_group.data(), sizeof(int32_t) * R.log_group.size());
         std::memcpy(res->log_level, R.log_level.data(), sizeof(int32_t) * R.log_level.size());
     }
+    res->next_level = R.next_level;
     res->total_ms = now_ms() - t_start;
     *out = res;
     return FPC_OK;
@@ -983,11 +1072,24 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
     CandSets cs;
     const std::vector<Run *> one_run{&R};
     const std::vector<const CandSets *> one_cs{&cs};
+    // a call stopped by stop_after_levels ends at a level boundary and
+    // reports the level it would run next (see fpc_checkpoint)
+    int levels_run = 0;
+    const int stop = P->stop_after_levels;
+    const fpc_checkpoint *ck = P->resume;
+    if (ck) restore_run(R, ck);
     if (P->schedule == FPC_REVERSE) {
-        if ((rc = first_stage(R, &first_ms))) return rc;
-        // following levels: l = min(p-3, cap, largest candidate set), down to 0
-        int l = p - 3;
-        if (cap >= 0) l = std::min(l, cap);
+        int l;
+        if (ck) {
+            if (R.learned && (rc = first_level_r(R))) return rc;
+            l = ck->next_level;
+        } else {
+            if ((rc = first_stage(R, &first_ms))) return rc;
+            ++levels_run;
+            // following levels: l = min(p-3, cap, largest candidate set), down to 0
+            l = p - 3;
+            if (cap >= 0) l = std::min(l, cap);
+        }
         bool cs_valid = false;  // the graph is unchanged since cs was computed
         while (l >= 0) {
             const double tc = now_ms();
@@ -998,21 +1100,31 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
             const int mmax = largest_cand(cs);
             if (mmax < 0) break;  // no edges left
             l = std::min(l, mmax);
+            if (stop > 0 && levels_run >= stop) {
+                R.next_level = l;
+                break;
+            }
             std::vector<fpc_level_stats> lv;
             if ((rc = run_level(one_run, l, one_cs, lv))) return rc;
             R.levels.push_back(lv[0]);
+            ++levels_run;
             cs_valid = lv[0].deleted == 0;
             --l;
         }
     } else {
         // Algorithm 1: l = 0, 1, ... while some edge has |cand| >= l
-        for (int l = 0;; ++l) {
+        for (int l = ck ? ck->next_level : 0; l >= 0; ++l) {
             if (cap >= 0 && l > cap) break;
             candidate_sets(R.adj.data(), p, cs);
             if (largest_cand(cs) < l) break;
+            if (stop > 0 && levels_run >= stop) {
+                R.next_level = l;
+                break;
+            }
             std::vector<fpc_level_stats> lv;
             if ((rc = run_level(one_run, l, one_cs, lv))) return rc;
             R.levels.push_back(lv[0]);
+            ++levels_run;
         }
     }
     const double ta = now_ms();
@@ -1030,6 +1142,7 @@ int validate_batch(const fpc_params *P, int ni, const fpc_instance *inst)
     if (P->precision != FPC_PREC_FP64 && P->precision != FPC_PREC_MIXED) return FPC_EINVAL;
     if (P->schedule != FPC_REVERSE || P->order != FPC_ORDER_LEX) return FPC_EINVAL;
     if (P->flags & FPC_FLAG_LOG_FEATURES) return FPC_EINVAL;
+    if (P->stop_after_levels != 0 || P->resume) return FPC_EINVAL;
     if (std::isnan(P->q_override) && !(P->alpha > 0.0 && P->alpha < 1.0)) return FPC_EINVAL;
     if (!std::isnan(P->q_override) && !(P->q_override >= 0.0)) return FPC_EINVAL;
     if (P->max_tests < 0) return FPC_EINVAL;

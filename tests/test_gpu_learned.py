@@ -155,6 +155,50 @@ def test_mlp_rejects_bad_arguments(fpc, ctx):
     assert fpc.fpc_mlp_forward(ctx, X[:0], model).numel() == 0
 
 
+def test_mlp_init_rejects_non_finite_parameters(fpc, ctx):
+    model = fpc.fpc_mlp_init(ctx, _params(2))
+    before = fpc.fpc_mlp_get(ctx, model)
+    for bad in (np.nan, np.inf, -np.inf):
+        p = _params(3)
+        p[100] = bad
+        with pytest.raises(fpc.FastPCError) as e:
+            fpc.fpc_mlp_init(ctx, p, model)
+        assert e.value.code == fpc.FPC_EINVAL
+    assert np.array_equal(fpc.fpc_mlp_get(ctx, model), before)  # left untouched
+
+
+def _nan_scoring(fpc, ctx):
+    """Finite parameters whose output is inf - inf = NaN for every input:
+    two first-layer units of bias 3e38 feed two second-layer units that
+    overflow to +inf, weighted +1 and -1 at the output."""
+    p = np.zeros(fpc.fpc_mlp_params(), np.float32)
+    ob1, oW2, oW3 = 192, 256, 256 + 4096 + 64
+    p[ob1 + 0] = p[ob1 + 1] = 3e38
+    for i in (0, 1):
+        for j in (0, 1):
+            p[oW2 + 64 * i + j] = 1.0
+    p[oW3 + 0], p[oW3 + 1] = 1.0, -1.0
+    return fpc.fpc_mlp_init(ctx, p)
+
+
+def test_learned_order_with_nan_scores_keeps_the_skeleton(fpc, ctx):
+    """Scores that are all NaN rank as equal (-inf), so each list is kept
+    as a permutation (here the identity): the skeleton and separating sets
+    are the lexicographic ones."""
+    model = _nan_scoring(fpc, ctx)
+    z = fpc.fpc_mlp_forward(ctx, dev(_features(np.random.default_rng(4), 64)), model).cpu().numpy()
+    assert np.isnan(z).all()
+    X, sem, cfg = semdata.workload("er_p20_n1000_d3", 1)
+    sem2 = semdata.make_sem(60, 9, degree=5.0)
+    for Xk, L in ((X, -1), (semdata.sample(sem2, 2000, 9), 4)):
+        C = oracle.corr(Xk)
+        ref = oracle.skeleton(C, Xk.shape[0], alpha=0.01, max_level=L)
+        for prec in (0, 1):
+            got = fpc.fpc_skeleton(ctx, dev(Xk), alpha=0.01, max_level=L, precision=prec, order_model=model)
+            assert np.array_equal(got["adj"], ref["adj"])
+            assert got["sepsets"] == ref["sepsets"]
+
+
 # ------------------------------------------------------------------ learned order
 def _trained_like(fpc, ctx, seed):
     """A model whose score grows with the first-level partial correlation

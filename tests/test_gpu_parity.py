@@ -239,6 +239,45 @@ def test_skeleton_forward_matches_oracle(fpc, ctx, seed):
     _compare_fp64(fpc, got, ref, cfg["p"])
 
 
+@pytest.mark.parametrize("p,n,deg,L,prec,graph", [(57, 2000, 5.0, -1, 0, "er"), (90, 3000, 5.0, -1, 1, "er"),
+                                                  (150, 4000, 4.0, 3, 1, "ba"), (95, 10000, 0.0, -1, 0, "paper")])
+def test_skeleton_forward_mid_sizes(fpc, ctx, p, n, deg, L, prec, graph):
+    """Algorithm 1 beyond p = 20: levels 0, 1, ... on mid-size ER, a
+    scale-free graph and the paper-shape graph, against the oracle's
+    forward run (FP64 sepsets equal; mixed skeletons equal)."""
+    _say(f"[skeleton forward mid] p={p} n={n} deg={deg} L={L} prec={prec} graph={graph}")
+    if graph == "paper":
+        X, sem, cfg = semdata.workload("paper_p95_n10000", 0)
+        alpha = cfg["alpha"]
+    else:
+        sem = semdata.make_sem(p, 31, graph=graph, degree=deg)
+        X = semdata.sample(sem, n, 31)
+        alpha = 0.01
+    C = oracle.corr(X)
+    ref = oracle.skeleton(C, n, alpha=alpha, max_level=L, reverse=False)
+    got = fpc.fpc_skeleton(ctx, dev(X), alpha=alpha, max_level=L, precision=prec, schedule=fpc.FPC_FORWARD)
+    assert np.array_equal(got["adj"], ref["adj"])
+    assert np.array_equal(got["sep_level"], ref["sep_level"])
+    if prec == 0:
+        assert got["sepsets"] == ref["sepsets"]
+        assert got["total_required"] == ref["total_tests"]
+    assert [x["level"] for x in got["levels"]] == [int(r[0]) for r in ref["levels"]]
+
+
+def test_lists_of_1024_or_more_are_reported(fpc, ctx):
+    """The forward schedule on p = 1030 independent variables starts at
+    level 0 on the complete graph, whose lists hold p - 2 = 1028
+    candidates: FPC_ETOOLARGE.  The reverse schedule on the same data
+    works (its first level uses the inverse)."""
+    X = np.random.default_rng(8).standard_normal((1100, 1030)).astype(np.float32)
+    Xd = dev(X)
+    with pytest.raises(fpc.FastPCError) as e:
+        fpc.fpc_skeleton(ctx, Xd, alpha=0.01, schedule=fpc.FPC_FORWARD)
+    assert e.value.code == fpc.FPC_ETOOLARGE
+    got = fpc.fpc_skeleton(ctx, Xd, alpha=0.01, max_level=2)
+    assert got["levels"][0]["level"] == 1028
+
+
 @pytest.mark.parametrize("flags", [0, 1])
 @pytest.mark.parametrize("p,n,deg,L,prec", [(57, 2000, 5.0, 4, 0), (57, 2000, 5.0, 4, 1),
                                              (130, 3000, 4.0, 3, 0), (130, 3000, 4.0, 3, 1),

@@ -107,6 +107,10 @@ def test_recheck_queue_sizes_do_not_change_results(fpc):
             fpc.fpc_set_recheck_queue(c, init, cap)
             got = fpc.fpc_skeleton(c, Xd, **kw)
             assert got["total_tests"] > base["total_tests"]  # the overflowed launches ran too
+            # ... and their launches and device time are counted with them
+            lb = {x["level"]: x for x in base["levels"]}
+            rerun = [x for x in got["levels"] if x["level"] in lb and x["tests_executed"] > lb[x["level"]]["tests_executed"]]
+            assert rerun and all(x["test_launches"] > lb[x["level"]]["test_launches"] for x in rerun)
             assert np.array_equal(got["adj"], ref["adj"])
             assert np.array_equal(got["sep_level"], base["sep_level"])
             assert got["sepsets"] == base["sepsets"]

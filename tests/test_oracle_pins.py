@@ -462,6 +462,55 @@ def test_stable_skeleton_independent_of_thread_count():
     assert a["total_tests"] == b["total_tests"]
 
 
+@pytest.mark.parametrize("reverse,max_level", [(True, -1), (True, 3), (False, -1), (False, 2)])
+def test_resume_from_every_level_boundary(reverse, max_level):
+    """Stopping after k levels and continuing from the boundary state ends
+    as the uninterrupted run (skeleton, separating sets, level rows, test
+    count), for every k; the boundary's graph is a supergraph of the final
+    one (the deleted set only grows)."""
+    sem = semdata.make_sem(30, 14, degree=5.0)
+    X = semdata.sample(sem, 1500, 14)
+    C = oracle.corr(X)
+    kw = dict(alpha=0.01, max_level=max_level, reverse=reverse)
+    full = oracle.skeleton(C, 1500, **kw)
+    assert full["next_level"] == -1
+    nlev = len(full["levels"])
+    assert nlev >= 3
+    for k in range(1, nlev + 1):
+        part = oracle.skeleton(C, 1500, stop_after_levels=k, **kw)
+        assert len(part["levels"]) == k
+        assert np.array_equal(part["levels"], full["levels"][:k])
+        assert np.all(part["adj"] >= full["adj"])
+        if k < nlev:
+            assert part["next_level"] == int(full["levels"][k][0])
+        else:
+            assert part["next_level"] == -1
+        res = oracle.skeleton(C, 1500, resume=part, **kw)
+        assert np.array_equal(res["adj"], full["adj"])
+        assert np.array_equal(res["sep_level"], full["sep_level"])
+        assert np.array_equal(res["sep_kind"], full["sep_kind"])
+        assert res["sepsets"] == full["sepsets"]
+        assert np.array_equal(res["levels"], full["levels"])
+        assert res["total_tests"] == full["total_tests"]
+        # and in two more steps of one level each
+        mid = oracle.skeleton(C, 1500, resume=part, stop_after_levels=1, **kw)
+        if mid["next_level"] >= 0:
+            assert int(mid["levels"][-1][0]) == int(full["levels"][k][0])
+            res2 = oracle.skeleton(C, 1500, resume=mid, **kw)
+            assert res2["sepsets"] == full["sepsets"] and np.array_equal(res2["levels"], full["levels"])
+
+
+def test_resume_rejects_bad_states():
+    C = np.eye(6)
+    st = dict(adj=np.ones((6, 6), np.uint8), sep_level=np.full(15, -1, np.int32), sep_kind=np.zeros(15, np.int8),
+              sepsets={}, next_level=7, levels=np.zeros((0, 5), np.int64), total_tests=0)
+    with pytest.raises(oracle.OracleError):
+        oracle.skeleton(C, 100, alpha=0.01, resume=st)  # next level beyond p - 3
+    st["next_level"] = 2
+    with pytest.raises(oracle.OracleError):
+        oracle.skeleton(C, 100, alpha=0.01, resume=st, stable=False)  # stable schedule only
+
+
 def test_max_level_cap_and_budget():
     sem = semdata.make_sem(40, 13, degree=4.0)
     X = semdata.sample(sem, 2000, 13)

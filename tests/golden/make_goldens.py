@@ -3,7 +3,8 @@ parity tests.  Calls only oracle/ and the input generators.
 
     python tests/golden/make_goldens.py [name ...]
 
-Each file <workload>_seed<k>.npz holds the FP64 oracle's skeleton edge
+Each file <workload>_seed<k>.npz (batched_data<d>_seed0.npz for data set d
+of the many-instance workload) holds the FP64 oracle's skeleton edge
 list, the level at which each deleted pair went, the separating sets of
 LIST kind (ALL_BUT kind = every other variable), per-level counts and the
 smallest |z - q| seen (tie monitor).
@@ -24,10 +25,23 @@ import oracle  # noqa: E402
 import semdata  # noqa: E402
 
 GOLDENS = [("er_p1000_n10000_d4", 0), ("er_p95_n5000_d12", 0)]
+# independent data sets of the many-instance workload (semdata.batched_workload,
+# full size): d = 2, 7, 12 have p = 120, 778, 1939
+BATCHED_GOLDENS = [2, 7, 12]
+
+
+def batched_data(d: int):
+    """Data set d of the many-instance workload and its configuration."""
+    _, _, datas, cfg = semdata.batched_workload(n_boot=0, n_data=d + 1)
+    X = datas[d]
+    return X, dict(p=X.shape[1], n=cfg["n"], alpha=cfg["alpha"], max_level=cfg["max_level"])
 
 
 def make(name: str, seed: int) -> str:
-    X, sem, cfg = semdata.workload(name, seed)
+    if name.startswith("batched_data"):
+        X, cfg = batched_data(int(name[len("batched_data"):]))
+    else:
+        X, sem, cfg = semdata.workload(name, seed)
     t0 = time.time()
     C = oracle.corr(X.astype(np.float64))
     res = oracle.skeleton(C, cfg["n"], alpha=cfg["alpha"], max_level=cfg["max_level"])
@@ -61,8 +75,9 @@ def load(name: str, seed: int) -> dict:
     adj[e[:, 0], e[:, 1]] = 1
     adj[e[:, 1], e[:, 0]] = 1
     sepsets = {}
-    for k, (i, j) in enumerate(z["sep_pairs"]):
-        sepsets[(int(i), int(j))] = z["sep_flat"][z["sep_off"][k]:z["sep_off"][k + 1]].tolist()
+    pairs, flat, off = z["sep_pairs"], z["sep_flat"], z["sep_off"]  # each member read (decompressed) once
+    for k, (i, j) in enumerate(pairs.tolist()):
+        sepsets[(i, j)] = flat[off[k]:off[k + 1]].tolist()
     return dict(adj=adj, sep_level=z["sep_level"].astype(np.int32), sep_kind=z["sep_kind"], sepsets=sepsets,
                 levels=z["levels"], total_tests=int(z["total_tests"]), min_margin=float(z["min_margin"]),
                 q=float(z["q"]), p=p, n=int(z["n"]), max_level=int(z["max_level"]), alpha=float(z["alpha"]))
@@ -70,6 +85,6 @@ def load(name: str, seed: int) -> dict:
 
 if __name__ == "__main__":
     want = sys.argv[1:]
-    for name, seed in GOLDENS:
+    for name, seed in GOLDENS + [(f"batched_data{d}", 0) for d in BATCHED_GOLDENS]:
         if not want or name in want:
             make(name, seed)

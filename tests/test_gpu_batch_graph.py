@@ -13,6 +13,7 @@ the two apart.
 """
 from __future__ import annotations
 
+import os
 import sys
 
 import numpy as np
@@ -20,6 +21,9 @@ import pytest
 
 import oracle
 import semdata
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import make_goldens  # noqa: E402
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -193,3 +197,15 @@ def test_graph_batch_full_size(fpc, ctx):
     assert all(graph_ran(g) for g in got)
     for k in range(len(inst)):
         same(got[k], ref[k], f"instance {k}")
+    # three of the independent data sets against the oracle's stored runs
+    # (tests/golden/make_goldens.py): the mixed form's skeleton, separating
+    # sets and required test count are the FP64 oracle's
+    for d in make_goldens.BATCHED_GOLDENS:
+        g = make_goldens.load(f"batched_data{d}", 0)
+        r = got[64 + d]
+        _say(f"  data set {d}: p={g['p']} oracle tests {g['total_tests']}, required here {r['total_required']}")
+        assert r["p"] == g["p"]
+        assert np.array_equal(r["adj"], g["adj"])
+        assert np.array_equal(r["sep_level"], g["sep_level"])
+        assert r["sepsets"] == g["sepsets"]
+        assert r["total_required"] == g["total_tests"]

@@ -539,3 +539,23 @@ def test_invalid_inputs():
     assert e.value.code == oracle.ORC_ESINGULAR
     X[:, 4] = X[:, 1] + 1e-3 * rng.standard_normal(40)  # nearly, not numerically, determined
     oracle.skeleton(oracle.corr(X), 40, alpha=0.01)
+
+
+def test_batched_goldens_match_their_data_sets():
+    """The stored oracle runs of three independent data sets of the
+    many-instance workload are for those data sets (p, n, alpha, cap) and
+    hold no near-tie that a rounding difference could flip."""
+    sys_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    import sys
+
+    if sys_path not in sys.path:
+        sys.path.insert(0, sys_path)
+    import make_goldens
+
+    cfg = semdata.BATCHED
+    for d in make_goldens.BATCHED_GOLDENS:
+        g = make_goldens.load(f"batched_data{d}", 0)
+        pd = int(np.random.default_rng([cfg["data_seed"] + d, 0xD1]).integers(cfg["p_lo"], cfg["p_hi"] + 1))
+        assert g["p"] == pd and g["n"] == cfg["n"] and g["max_level"] == cfg["max_level"]
+        assert g["alpha"] == cfg["alpha"] and g["min_margin"] > 1e-9
+        assert int(g["levels"][0][0]) == pd - 2

@@ -205,6 +205,10 @@ WORKLOADS = {
     "er_p20_n1000_d3": dict(p=20, n=1000, graph="er", degree=3.0, x_dtype="f64", alpha=0.01, max_level=-1),
     # dense small graph, FP32 tests with FP64 recheck
     "er_p95_n5000_d12": dict(p=95, n=5000, graph="er", degree=12.0, x_dtype="f64", alpha=0.01, max_level=6),
+    # dense p = 95 graph whose level sequence after the first runs 6, 5, 4, 3, 2, 1, 0 (the paper's
+    # weight law keeps the variances bounded, so true edges survive level 6)
+    "er_p95_n20000_d8_paper": dict(p=95, n=20000, graph="er", degree=8.0, x_dtype="f64", alpha=0.01, max_level=6,
+                                   weight_law="paper"),
     # sparse large graph, X in FP32
     "er_p1000_n10000_d4": dict(p=1000, n=10000, graph="er", degree=4.0, x_dtype="f32", alpha=0.01, max_level=5),
     # scale-free graph

@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import semdata  # noqa: E402
 
-GOLDENS = [("er_p1000_n10000_d4", 0), ("er_p95_n5000_d12", 0)]
+GOLDENS = [("er_p1000_n10000_d4", 0), ("er_p95_n5000_d12", 0), ("er_p95_n20000_d8_paper", 0)]
 # independent data sets of the many-instance workload (semdata.batched_workload,
 # full size): d = 2, 7, 12 have p = 120, 778, 1939
 BATCHED_GOLDENS = [2, 7, 12]

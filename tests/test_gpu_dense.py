@@ -1,8 +1,13 @@
-"""Dense small graph (p = 95, expected degree 12, n = 5000, FP64 data,
-max_level 6): FP32 tests with FP64 re-runs near the threshold must give
-the oracle's skeleton bit-exact; the FP64 form also its separating sets and
-the oracle's test count.  Against the oracle's stored result
-(tests/golden/make_goldens.py).  GPU only."""
+"""Dense small graphs: FP32 tests with FP64 re-runs near the threshold
+must give the oracle's skeleton bit-exact, and both forms its separating
+sets and test count, against the oracle's stored results
+(tests/golden/make_goldens.py).  GPU only.
+
+* er_p95_n5000_d12 (expected degree 12, n = 5000, max_level 6): C has a
+  condition number of about 2e7; after the first level only levels 6 and 0
+  run (level 6 leaves lists too short for 5..1);
+* er_p95_n20000_d8_paper (degree 8, the paper's weight law, n = 20000,
+  max_level 6): the levels after the first run 6, 5, 4, 3, 2, 1, 0."""
 from __future__ import annotations
 
 import os
@@ -21,27 +26,28 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.join(HERE, "golden"))
 import make_goldens  # noqa: E402
 
-NAME, SEED = "er_p95_n5000_d12", 0
+SEED = 0
 
 
-@pytest.fixture(scope="module")
-def setup():
+@pytest.fixture(scope="module", params=["er_p95_n5000_d12", "er_p95_n20000_d8_paper"])
+def setup(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2109_04626_amd as fpc
 
-    X, sem, cfg = semdata.workload(NAME, SEED)
-    gold = make_goldens.load(NAME, SEED)
+    name = request.param
+    X, sem, cfg = semdata.workload(name, SEED)
+    gold = make_goldens.load(name, SEED)
     ctx = fpc.Context(0)
-    yield fpc, ctx, X, torch.from_numpy(X).cuda(), cfg, gold
+    yield fpc, ctx, X, torch.from_numpy(X).cuda(), cfg, gold, name
     ctx.close()
 
 
 @pytest.mark.parametrize("flags", [0, 4])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_dense_skeleton_bit_exact(setup, prec, flags):
-    fpc, ctx, X, Xd, cfg, gold = setup
-    print(f"[dense] {NAME} seed={SEED} precision={prec} flags={flags}", flush=True)
+    fpc, ctx, X, Xd, cfg, gold, name = setup
+    print(f"[dense] {name} seed={SEED} precision={prec} flags={flags}", flush=True)
     assert gold["p"] == cfg["p"] and gold["max_level"] == cfg["max_level"] and gold["min_margin"] > 1e-9
     got = fpc.fpc_skeleton(ctx, Xd, alpha=cfg["alpha"], max_level=cfg["max_level"], precision=prec, flags=flags)
     assert np.array_equal(got["adj"], gold["adj"])
@@ -55,6 +61,7 @@ def test_dense_skeleton_bit_exact(setup, prec, flags):
         assert not bad, bad[:5]
         print(f"  re-run in FP64: {sum(x['tests_rechecked'] for x in got['levels'])} of "
               f"{got['total_tests']} tests; corr max abs err {got['corr_max_abs_err']:.2e}", flush=True)
+    assert [x["level"] for x in got["levels"]] == [int(r[0]) for r in gold["levels"]]
     lv = {x["level"]: x for x in got["levels"]}
     for row in gold["levels"]:
         l, elig, dels = int(row[0]), int(row[1]), int(row[3])

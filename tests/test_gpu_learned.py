@@ -155,6 +155,18 @@ def test_mlp_rejects_bad_arguments(fpc, ctx):
     assert fpc.fpc_mlp_forward(ctx, X[:0], model).numel() == 0
 
 
+def test_mlp_forward_hand_computed_network(fpc, ctx):
+    """The sparse network of the oracle's hand-computed pin (weights exact
+    in bf16): the library's forward pass gives -4.325 and 3.725."""
+    p = np.zeros(fpc.fpc_mlp_params(), np.float32)
+    oW1, ob1, oW2, ob2, oW3, ob3 = 0, 192, 256, 4352, 4416, 4480
+    p[oW1 + 2], p[ob1 + 2], p[oW2 + 2 * 64 + 5], p[ob2 + 5], p[oW3 + 5] = 2.0, -0.5, 3.0, 0.25, -1.5
+    p[oW1 + 64 + 7], p[oW2 + 7 * 64 + 9], p[oW3 + 9], p[ob3] = -1.0, 4.0, 2.0, 0.1
+    model = fpc.fpc_mlp_init(ctx, p)
+    z = fpc.fpc_mlp_forward(ctx, dev(np.array([[0.7, 0.3, 0.9], [0.1, -0.5, 0.0]], np.float32)), model)
+    np.testing.assert_allclose(z.cpu().numpy(), [-4.325, 3.725], rtol=0, atol=2e-6)
+
+
 def test_mlp_init_rejects_non_finite_parameters(fpc, ctx):
     model = fpc.fpc_mlp_init(ctx, _params(2))
     before = fpc.fpc_mlp_get(ctx, model)

@@ -66,7 +66,10 @@ extern "C" {
 /* Order of the conditioning sets inside one level (fpc_params.order). */
 #define FPC_ORDER_LEX 0     /* lexicographic over the candidate list sorted by variable id      */
 #define FPC_ORDER_LEARNED 1 /* lexicographic over the candidate list sorted by decreasing MLP
-                               score (fpc_params.order_model); reverse schedule only          */
+                               score (fpc_params.order_model); reverse schedule only.  A level
+                               with fewer than 32 possible tests per candidate keeps the
+                               lexicographic order (the passes would cost more than they
+                               can save)                                                    */
 
 /* fpc_params.flags bits. */
 #define FPC_FLAG_PER_TEST_KERNEL 1u /* run levels l >= 2 with the per-test Cholesky kernel instead of

@@ -530,7 +530,13 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     Run &R0 = *runs[0];
     std::vector<float> hfeat;
     const int32_t *d_cand = ctx->cand.as<int32_t>();
-    const bool reorder = ni == 1 && R0.learned && l >= 1;
+    // The learned order can only save tests of edges deleted at this level,
+    // and its passes (features, scores, reorder) cost about as much as a
+    // few dozen tests per candidate; a level with fewer possible tests per
+    // candidate than that (l <= 2 on the benchmark graphs) keeps the
+    // lexicographic order.  The skeleton does not depend on the order.
+    constexpr int64_t kLearnedMinTestsPerCand = 32;
+    const bool reorder = ni == 1 && R0.learned && l >= 1 && sts[0].tests_possible >= kLearnedMinTestsPerCand * T;
     const bool logging = ni == 1 && R0.logging;
     if (reorder || logging) {
         const CandSets &cs = *css[0];

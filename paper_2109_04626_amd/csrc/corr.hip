@@ -175,27 +175,49 @@ __global__ __launch_bounds__(256) void syrk_f64(const TX *__restrict__ X, const 
 }
 
 // C[i][j] = S_ij / sqrt(S_ii S_jj), S summed over the splits in order and
-// read from the upper triangle; C_ii = 1.
+// taken from the upper triangle (i <= j), so C is exactly symmetric; C_ii =
+// 1.  One 32 x 32 tile (I <= J; the products write whole 64 x 64 tiles
+// I <= J, which contain these) per workgroup: its split sums are read
+// row-wise, written to C[I][J] and, through an LDS transpose, to C[J][I],
+// so every access of the p x p arrays is coalesced.
+constexpr int kNT = 32;
 template <typename TC>
-__global__ __launch_bounds__(256) void normalize(const double *__restrict__ Spart, int nsplit, int p,
+__global__ __launch_bounds__(256) void normalize(const double *__restrict__ Spart, int nsplit, int p, int nbt,
                                                  TC *__restrict__ C)
 {
-    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (size_t)p * p) return;
-    const int i = (int)(idx / p), j = (int)(idx % p);
-    if (i == j) {
-        C[idx] = (TC)1.0;
-        return;
+    int bi, bj;
+    tile_of(blockIdx.x, nbt, bi, bj);
+    __shared__ double t[kNT][kNT + 1];
+    __shared__ double di[kNT], dj[kNT];
+    const size_t pp = (size_t)p * p;
+    if (threadIdx.x < 2 * kNT) {  // S_aa of the tile's rows, then of its columns
+        const int r = threadIdx.x % kNT, a = (threadIdx.x < kNT ? bi : bj) * kNT + r;
+        double sa = 0.0;
+        if (a < p)
+            for (int k = 0; k < nsplit; ++k) sa += Spart[(size_t)k * pp + (size_t)a * p + a];
+        (threadIdx.x < kNT ? di : dj)[r] = sa;
     }
-    const int a = min(i, j), b = max(i, j);
-    double s = 0.0, sa = 0.0, sb = 0.0;
-    for (int k = 0; k < nsplit; ++k) {
-        const double *S = Spart + (size_t)k * p * p;
-        s += S[(size_t)a * p + b];
-        sa += S[(size_t)a * p + a];
-        sb += S[(size_t)b * p + b];
+    const int tx = threadIdx.x % kNT, ty = threadIdx.x / kNT;  // 8 rows of 32 per pass
+    for (int r = ty; r < kNT; r += 8) {
+        const int a = bi * kNT + r, b = bj * kNT + tx;
+        double sab = 0.0;
+        if (a < p && b < p)
+            for (int k = 0; k < nsplit; ++k) sab += Spart[(size_t)k * pp + (size_t)a * p + b];
+        t[r][tx] = sab;
     }
-    C[idx] = (TC)(s / sqrt(sa * sb));
+    __syncthreads();
+    for (int r = ty; r < kNT; r += 8) {
+        const int a = bi * kNT + r, b = bj * kNT + tx;
+        // a diagonal tile reads its upper half for both halves
+        const double sab = bi == bj && r > tx ? t[tx][r] : t[r][tx];
+        if (a < p && b < p) C[(size_t)a * p + b] = a == b ? (TC)1.0 : (TC)(sab / sqrt(di[r] * dj[tx]));
+    }
+    if (bi != bj) {
+        for (int r = ty; r < kNT; r += 8) {  // C[b][a] for the row b = bj*kNT + r
+            const int b = bj * kNT + r, a = bi * kNT + tx;
+            if (a < p && b < p) C[(size_t)b * p + a] = (TC)(t[tx][r] / sqrt(di[tx] * dj[r]));
+        }
+    }
 }
 
 // ---------------------------------------------------------------- bf16x3 on MFMA
@@ -384,9 +406,14 @@ __global__ void fill_u32(uint32_t *__restrict__ p, int n, uint32_t v)
     if (k < n) p[k] = v;
 }
 
-int splits_for(int tiles, int n, int num_cus)
+// Sample splits of a product: per_cu workgroups per CU in all, at most one
+// split per 512 samples.  About 8 per CU let the global-load latency of the
+// operand streams hide behind other waves: at p = 1000, n = 1e4 (136 tiles,
+// 16 splits) the bf16x6 product takes 188 us and the FP64 one 247 us,
+// against 245 and 331 us with 4 splits; the split sums cost 31 us to reduce.
+int splits_for(int tiles, int n, int num_cus, int per_cu)
 {
-    int s = (2 * num_cus + tiles - 1) / tiles;
+    int s = (per_cu * num_cus + tiles - 1) / tiles;
     s = s < 1 ? 1 : (s > 32 ? 32 : s);
     const int maxs = (n + 511) / 512;
     return s > maxs ? (maxs < 1 ? 1 : maxs) : s;
@@ -401,7 +428,7 @@ int corr_reserve(fpc_ctx *ctx, int n, int p, int method)
     const int nchunks = (n + kStatRows - 1) / kStatRows;
     const int nbt = (p + kT - 1) / kT, tiles = nbt * (nbt + 1) / 2;
     const int npad = (n + 31) / 32 * 32;
-    const int nsplit = splits_for(tiles, method == FPC_CORR_FP64 ? n : npad, ctx->num_cus);
+    const int nsplit = splits_for(tiles, method == FPC_CORR_FP64 ? n : npad, ctx->num_cus, 8);
     int rc = ctx->colstat.ensure(sizeof(double) * ((size_t)2 * p + (size_t)nchunks * 2 * p));
     if (!rc) rc = ctx->flag.ensure(64);
     if (!rc) rc = ctx->inv_work.ensure(sizeof(double) * (size_t)p * p * nsplit);
@@ -430,7 +457,7 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
     const int nchunks = (n + kStatRows - 1) / kStatRows;
     const int nbt = (p + kT - 1) / kT, tiles = nbt * (nbt + 1) / 2;
     const int npad = (n + 31) / 32 * 32;
-    const int nsplit = splits_for(tiles, method == FPC_CORR_FP64 ? n : npad, ctx->num_cus);
+    const int nsplit = splits_for(tiles, method == FPC_CORR_FP64 ? n : npad, ctx->num_cus, 8);
     const size_t pp = (size_t)p * p;
     // colstat layout: mu[p], sd[p], partials[nchunks * 2p]
     int rc = ctx->colstat.ensure(sizeof(double) * ((size_t)2 * p + (size_t)nchunks * 2 * p));
@@ -463,7 +490,8 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
             syrk_f64<double><<<g, 256, 0, st>>>((const double *)X, mu, n, p, nbt, chunk, Spart);
         else
             syrk_f64<float><<<g, 256, 0, st>>>((const float *)X, mu, n, p, nbt, chunk, Spart);
-        normalize<double><<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(Spart, nsplit, p, (double *)C_out);
+        const int nbn = (p + kNT - 1) / kNT;
+        normalize<double><<<nbn * (nbn + 1) / 2, 256, 0, st>>>(Spart, nsplit, p, nbn, (double *)C_out);
     } else {
         const bool three = method == FPC_CORR_BF16X6;
         const int nparts = three ? 3 : 2;
@@ -486,7 +514,8 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
         dim3 g(tiles, nsplit);
         if (three) syrk_bf16<6><<<g, 256, 0, st>>>(Zh, Zm, Zl, p, npad, nbt, chunk, Spart);
         else syrk_bf16<3><<<g, 256, 0, st>>>(Zh, Zm, Zl, p, npad, nbt, chunk, Spart);
-        normalize<float><<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(Spart, nsplit, p, (float *)C_out);
+        const int nbn = (p + kNT - 1) / kNT;
+        normalize<float><<<nbn * (nbn + 1) / 2, 256, 0, st>>>(Spart, nsplit, p, nbn, (float *)C_out);
     }
     FPC_HIP(hipGetLastError());
     return wait ? corr_check(ctx, nullptr) : FPC_OK;

@@ -29,7 +29,7 @@ namespace fpc {
 
 namespace {
 
-constexpr int kStatRows = 256;  // rows per partial in the column statistics
+constexpr int kStatRows = 64;  // rows per partial in the column statistics (enough workgroups to hide load latency)
 
 // One pass of column statistics: per chunk of rows, the sums of x - K and
 // (x - K)^2 with K = X[0][j], a value of the column itself (the shifted-data
@@ -57,18 +57,29 @@ __global__ __launch_bounds__(256) void colstat_partial(const TX *__restrict__ X,
     if (bad) atomicOr(nonfinite, 1);
 }
 
-// mean and standard deviation of each column from the partial sums
+// mean and standard deviation of each column from the partial sums: 64
+// columns per workgroup, four lanes per column each summing every fourth
+// chunk (coalesced over the columns), then the four sums in a fixed order
 template <typename TX>
-__global__ void colstat_reduce(const TX *__restrict__ X, const double *__restrict__ part, int nchunks, int n, int p,
-                               double *__restrict__ mu, double *__restrict__ sd, int *__restrict__ constant)
+__global__ __launch_bounds__(256) void colstat_reduce(const TX *__restrict__ X, const double *__restrict__ part,
+                                                      int nchunks, int n, int p, double *__restrict__ mu,
+                                                      double *__restrict__ sd, int *__restrict__ constant)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= p) return;
+    __shared__ double r1[4][64], r2[4][64];
+    const int c64 = threadIdx.x % 64, g = threadIdx.x / 64;
+    const int j = blockIdx.x * 64 + c64;
     double s1 = 0.0, s2 = 0.0;
-    for (int c = 0; c < nchunks; ++c) {
-        s1 += part[(size_t)c * 2 * p + j];
-        s2 += part[(size_t)c * 2 * p + p + j];
-    }
+    if (j < p)
+        for (int c = g; c < nchunks; c += 4) {
+            s1 += part[(size_t)c * 2 * p + j];
+            s2 += part[(size_t)c * 2 * p + p + j];
+        }
+    r1[g][c64] = s1;
+    r2[g][c64] = s2;
+    __syncthreads();
+    if (g != 0 || j >= p) return;
+    s1 = ((r1[0][c64] + r1[1][c64]) + r1[2][c64]) + r1[3][c64];
+    s2 = ((r2[0][c64] + r2[1][c64]) + r2[2][c64]) + r2[3][c64];
     const double m1 = s1 / n;
     mu[j] = (double)X[j] + m1;
     const double var = fmax(s2 / n - m1 * m1, 0.0);
@@ -474,11 +485,11 @@ int corr_compute(fpc_ctx *ctx, const void *X, int x_dtype, int n, int p, int met
         if (!keep_flags) fill_u32<<<1, 32, 0, st>>>(reinterpret_cast<uint32_t *>(flags), 2, 0u);
         if (x_dtype == FPC_F64) {
             colstat_partial<double><<<g0, 256, 0, st>>>((const double *)X, n, p, part, flags);
-            colstat_reduce<double><<<(p + 255) / 256, 256, 0, st>>>((const double *)X, part, nchunks, n, p, mu, sd,
+            colstat_reduce<double><<<(p + 63) / 64, 256, 0, st>>>((const double *)X, part, nchunks, n, p, mu, sd,
                                                                     flags + 1);
         } else {
             colstat_partial<float><<<g0, 256, 0, st>>>((const float *)X, n, p, part, flags);
-            colstat_reduce<float><<<(p + 255) / 256, 256, 0, st>>>((const float *)X, part, nchunks, n, p, mu, sd,
+            colstat_reduce<float><<<(p + 63) / 64, 256, 0, st>>>((const float *)X, part, nchunks, n, p, mu, sd,
                                                                    flags + 1);
         }
     }

@@ -128,8 +128,8 @@ int fpc_first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, doubl
 
 /* The same without any device allocation, for callers that cannot allocate
  * (code under HIP graph capture, serving loops, harnesses that forbid
- * hipMalloc): the sweep's workspace (two p x p FP64 buffers, two 32 x 32
- * panel inverses, a flag word; 4.2 MB) is a static device array that each
+ * hipMalloc): the sweep's workspace (two p x p FP64 buffers, seven 32 x 32
+ * panel blocks, a flag word; 4.2 MB) is a static device array that each
  * device the library runs on holds until the process ends.  Same arguments,
  * outputs and results as fpc_first_level; p > FPC_NOALLOC_MAX_P returns
  * FPC_ESCRATCH.  Every call on a device shares that device's workspace, so

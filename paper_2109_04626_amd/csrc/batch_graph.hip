@@ -682,7 +682,7 @@ int skeleton_batch_graph(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_in
     // ---- one device pool for the whole call
     auto carve = [&](Carver &c) {
         struct P_ {
-            std::vector<double *> c64, buf0, buf1, pinv0, pinv1;
+            std::vector<double *> c64, buf0, buf1, pinv;
             std::vector<float *> c32;
         } ptrs;
         for (int k = 0; k < ni; ++k) {
@@ -691,8 +691,7 @@ int skeleton_batch_graph(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_in
             ptrs.c32.push_back(mixed ? c.take<float>(pp) : nullptr);
             ptrs.buf0.push_back(c.take<double>(pp));
             ptrs.buf1.push_back(c.take<double>(pp));
-            ptrs.pinv0.push_back(c.take<double>(32 * 32));
-            ptrs.pinv1.push_back(c.take<double>(32 * 32));
+            ptrs.pinv.push_back(c.take<double>(7 * 32 * 32));
         }
         return ptrs;
     };
@@ -788,7 +787,7 @@ int skeleton_batch_graph(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_in
     for (int k = 0; k < ni; ++k) {
         src[k] = DevInstSrc{ptrs.c32[k], ptrs.c64[k], inst[k].p, inst[k].n, qk[k],
                             mixed ? reinterpret_cast<const double *>(cerr_slot + k) : nullptr};
-        fli[k] = FirstLevelInst{ptrs.c64[k], ptrs.buf0[k], ptrs.buf1[k], ptrs.pinv0[k], ptrs.pinv1[k], fl_bad + k,
+        fli[k] = FirstLevelInst{ptrs.c64[k], ptrs.buf0[k], ptrs.buf1[k], ptrs.pinv[k], fl_bad + k,
                                 fl_del + k, G.adj + gi[k].adj_off, inst[k].p, inst[k].n, qk[k]};
     }
     std::vector<SweepJob> fj, pj;

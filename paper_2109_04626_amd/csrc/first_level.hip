@@ -4,20 +4,27 @@
 // {i,j} block of Omega = C^{-1}, so r_ij = -Omega_ij / sqrt(Omega_ii Omega_jj):
 // one p x p FP64 inversion replaces p(p-1)/2 factorisations of size p-2.
 //
-// Omega is formed by a blocked sweep (Gauss-Jordan without pivoting, valid
-// for a positive definite C).  For each panel K of kNB columns, with
-// V = A[:,K] and U = A[K,K]^{-1} A[K,:] taken before the update:
-//     A[I,J] -= V[I,:] U[:,J]          (I, J outside K)
-//     A[I,K]  = -V[I,:] A[K,K]^{-1}     (I outside K)
-//     A[K,J]  = U[:,J]                 (J outside K)
-//     A[K,K]  = A[K,K]^{-1}
-// After the last panel A = C^{-1}.  A non-positive pivot inside a panel
-// inverse reports the matrix as not positive definite.
+// Omega is formed by the symmetric sweep operator over panels of kNB
+// columns (Gauss-Jordan without pivoting, valid for a positive definite C).
+// Sweeping panel K with P = A[K,K]^{-1}, all blocks taken before the update:
+//     A[I,J] -= A[I,K] P A[K,J]        (I, J outside K)
+//     A[I,K]  = A[I,K] P               (I outside K)
+//     A[K,J]  = P A[K,J]               (J outside K)
+//     A[K,K]  = -P
+// The swept matrix stays symmetric, and once every panel is swept it is
+// -C^{-1}.  A non-positive pivot inside a panel inverse reports the matrix
+// as not positive definite.
 //
-// One launch per panel: the sweep reads the matrix before the panel and
-// writes a second buffer (the two alternate), so each kNB x kNB tile can
-// form its own slice of U and read its slice of V; the tile that becomes
-// the next panel's diagonal block inverts it in the same launch.
+// One launch per panel t.  Each workgroup updates one tile (I, J) with
+// I <= J from the matrix as it stood before the panel, forming its own slice
+// of P_t A[K,J] on the FP64 matrix cores, and writes the tile and its
+// transpose into the other of two buffers.  The panel inverses form the
+// serial chain of the method, so they are taken two panels ahead:
+// workgroup 0 of launch t brings the diagonal block of panel t+2 up to date
+// through panels t and t+1 (from the matrix before panel t, P_t and
+// P_{t+1}) and inverts it while the tile workgroups update the matrix.  A
+// one-workgroup prologue inverts the first two diagonal blocks.  Three panel
+// inverses rotate: panel t's sits in slot t mod 3.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,187 +37,425 @@ namespace fpc {
 namespace {
 
 constexpr int kNB = 32;  // panel width and tile size
+constexpr int kPinv = kNB * kNB;
+constexpr int kPanelWork = 7 * kPinv;  // panel inverses and look-ahead blocks
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double Tile[kNB][kNB + 1];  // an LDS tile (rows padded by one)
+typedef double PivBuf[2][2][kNB];  // pivot rows or columns of two steps
 
-// Gauss-Jordan inverse of the nb x nb block P (LDS, kNB x kNB tile) by a
-// 256-thread block, thread (ty, tx) owning rows ty + 8q of column tx.  Two
-// pivots per step: the 2 x 2 pivot block K2 = {t, t+1} is inverted in
-// closed form and eliminated as one block (the sweep formulas above with a
-// panel of two), with a single pivot for an odd last one.  The next step's
-// pivot rows and columns are published into a second buffer by the threads
-// that compute them, so each step needs one barrier.  Writes the whole
-// kNB x kNB result (zero outside nb) to Pinv.
-__device__ void tile_inverse(double (*P)[kNB + 1], double (*rowk)[2][kNB], double (*colk)[2][kNB], int nb,
-                             double *__restrict__ Pinv, int *__restrict__ bad)
+// Two layouts of a 256-thread workgroup over a kNB x kNB tile.  Rows: thread
+// (tx, ty) = (tid % 32, tid / 32) holds rows ty + 8q (q < 4) of column tx.
+// Accumulator: wave w = tid / 64 holds the 16 x 16 quarter at row qr =
+// 16 (w / 2), column qc = 16 (w % 2); lane l holds rows qr + 4v + l / 16
+// (v < 4) of column qc + l % 16, the result layout of
+// v_mfma_f64_16x16x4f64, which takes A[l % 16][l / 16] and B[l / 16][l % 16]
+// from lane l.
+struct Lay {
+    int tx, ty, qr, ar, bc, kq;
+    __device__ Lay()
+    {
+        tx = threadIdx.x % kNB;
+        ty = threadIdx.x / kNB;
+        const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+        qr = (wave / 2) * 16;
+        ar = qr + lane % 16;
+        bc = (wave % 2) * 16 + lane % 16;
+        kq = lane / 16;
+    }
+};
+
+// The nr x nc block of A (row length ld) at (r0, c0), zero outside it.
+__device__ __forceinline__ void load_rows(const double *__restrict__ A, int ld, int r0, int c0, int nr, int nc,
+                                          const Lay &L, double g[4])
 {
-    const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;
-    double v[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = P[ty + 8 * q][tx];
-    // the first step's pivot rows and columns
+    for (int q = 0; q < 4; ++q) {
+        const int r = L.ty + 8 * q;
+        g[q] = (r < nr && L.tx < nc) ? A[(size_t)(r0 + r) * ld + c0 + L.tx] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void load_acc(const double *__restrict__ A, int ld, int r0, int c0, int nr, int nc,
+                                         const Lay &L, v4d &a)
+{
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = L.qr + 4 * v + L.kq;
+        a[v] = (r < nr && L.bc < nc) ? A[(size_t)(r0 + r) * ld + c0 + L.bc] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void put_rows(Tile &T, const Lay &L, const double g[4])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) T[L.ty + 8 * q][L.tx] = g[q];
+}
+
+__device__ __forceinline__ void put_acc(Tile &T, const Lay &L, const v4d &a)
+{
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[L.qr + 4 * v + L.kq][L.bc] = a[v];
+}
+
+// a += X Y (NEG: a -= X Y) over the wave's quarter, X and Y in LDS.
+template <bool NEG>
+__device__ __forceinline__ void mma(v4d &a, const Tile &X, const Tile &Y, const Lay &L)
+{
+#pragma unroll
+    for (int s4 = 0; s4 < kNB; s4 += 4) {
+        const double x = X[L.ar][s4 + L.kq];
+        a = __builtin_amdgcn_mfma_f64_16x16x4f64(NEG ? -x : x, Y[s4 + L.kq][L.bc], a, 0, 0, 0);
+    }
+}
+
+// a -= X^T Y over the wave's quarter, X and Y in LDS.
+__device__ __forceinline__ void mma_tn_sub(v4d &a, const Tile &X, const Tile &Y, const Lay &L)
+{
+#pragma unroll
+    for (int s4 = 0; s4 < kNB; s4 += 4)
+        a = __builtin_amdgcn_mfma_f64_16x16x4f64(-X[s4 + L.kq][L.ar], Y[s4 + L.kq][L.bc], a, 0, 0, 0);
+}
+
+// In-place Gauss-Jordan inverse of the leading nb x nb block of the LDS tile
+// T (its other entries ignored) by the workgroup, two pivots per step.  With
+// the pivot pair K = {t, t+1} and K2 = A[K,K], every entry takes the same
+// update a_ij <- b_ij - w_i . u_j, where
+//     u_j = K2^{-1} A[K,j], b_ij = a_ij    for j outside K,
+//     u_j = K2^{-1} e_j,    b_ij = delta_ij for j in K,
+//     w_i = A[i,K] for i outside K, w_i = (K2 - I)[i,:] for i in K;
+// this is the sweep of the header for a panel of two.  The tile is padded
+// with the identity beyond nb, so every call takes the same 16 steps.  The
+// threads that own the next pivot rows and columns (the latter less the
+// identity) publish them into the other half of rowk / colk: one barrier per
+// step.  The inverse goes to Pinv (global, kNB x kNB, zero outside nb) and
+// back into T; a barrier must precede reads of T.
+__device__ __forceinline__ void tile_inverse(Tile &T, PivBuf &rowk, PivBuf &colk, int nb, double *__restrict__ Pinv,
+                                             int *__restrict__ bad)
+{
+    const int c = threadIdx.x % kNB, ty = threadIdx.x / kNB;
+    double v[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int r = ty + 8 * q;
-        if (r < 2) rowk[0][r][tx] = v[q];
-        if (tx < 2) colk[0][tx][r] = v[q];
+        v[q] = (r < nb && c < nb) ? T[r][c] : (r == c ? 1.0 : 0.0);
+        if (r < 2) rowk[0][r][c] = v[q];
+        if (c < 2) colk[0][c][r] = v[q] - (r == c ? 1.0 : 0.0);
     }
     __syncthreads();
     bool ok = true;
-    int b = 0;
-    for (int t = 0; t < nb;) {
-        const bool two = t + 1 < nb;  // uniform
-        const int c = tx;
-        const double r1 = rowk[b][0][c], r2 = rowk[b][1][c];
-        double c1[4], c2[4];
+#pragma unroll
+    for (int s = 0; s < kNB / 2; ++s) {
+        const int t = 2 * s, b = s & 1;
+        const double a = rowk[b][0][t], bt = rowk[b][0][t + 1], ct = rowk[b][1][t], d = rowk[b][1][t + 1];
+        double x0 = rowk[b][0][c], x1 = rowk[b][1][c];
+        double w0[4], w1[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            c1[q] = colk[b][0][ty + 8 * q];
-            c2[q] = colk[b][1][ty + 8 * q];
+            w0[q] = colk[b][0][ty + 8 * q];
+            w1[q] = colk[b][1][ty + 8 * q];
         }
-        if (two) {
-            const double a = rowk[b][0][t], bt = rowk[b][0][t + 1], ct = rowk[b][1][t], d = rowk[b][1][t + 1];
-            const double det = a * d - bt * ct;
-            ok = ok && a > 0.0 && det > 0.0;
-            const double idet = 1.0 / det;
-            const double i00 = d * idet, i01 = -bt * idet, i10 = -ct * idet, i11 = a * idet;
-            const double u1 = fma(i00, r1, i01 * r2), u2 = fma(i10, r1, i11 * r2);  // inv(K2) A[K2, c]
-            const bool inC = c == t || c == t + 1;
-            const double ic0 = c == t ? i00 : i01, ic1 = c == t ? i10 : i11;   // column c - t of inv(K2)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = ty + 8 * q;
-                const bool inR = r == t || r == t + 1;
-                double nv = fma(-c1[q], u1, fma(-c2[q], u2, v[q]));
-                nv = inC ? -fma(c1[q], ic0, c2[q] * ic1) : nv;
-                nv = inR ? (r == t ? u1 : u2) : nv;
-                nv = (inR && inC) ? (r == t ? ic0 : ic1) : nv;
-                v[q] = (r < nb && c < nb) ? nv : v[q];
-            }
-            t += 2;
-        } else {
-            const double piv = rowk[b][0][t];
-            ok = ok && piv > 0.0;
-            const double ip = 1.0 / piv, rti = r1 * ip;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = ty + 8 * q;
-                double nv = fma(-c1[q], rti, v[q]);
-                nv = c == t ? -c1[q] * ip : nv;
-                nv = r == t ? rti : nv;
-                nv = (r == t && c == t) ? ip : nv;
-                v[q] = (r < nb && c < nb) ? nv : v[q];
-            }
-            t += 1;
+        const double det = fma(a, d, -bt * ct);
+        ok = ok && a > 0.0 && det > 0.0;
+        const double idet = 1.0 / det;
+        const bool inK = c == t || c == t + 1;
+        if (inK) {
+            x0 = c == t ? 1.0 : 0.0;
+            x1 = c == t ? 0.0 : 1.0;
         }
-        b ^= 1;
+        const double u0 = idet * fma(d, x0, -bt * x1), u1 = idet * fma(a, x1, -ct * x0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = ty + 8 * q;
-            if (r == t) rowk[b][0][c] = v[q];
-            if (r == t + 1) rowk[b][1][c] = v[q];
-            if (c == t) colk[b][0][r] = v[q];
-            if (c == t + 1) colk[b][1][r] = v[q];
+            double base = v[q];
+            if (inK) base = r == c ? 1.0 : 0.0;
+            v[q] = fma(-w1[q], u1, fma(-w0[q], u0, base));
         }
-        __syncthreads();
+        if (s + 1 < kNB / 2) {
+            // rows tn and tn + 1 are register tn / 8 of the threads with
+            // ty = tn % 8 and tn % 8 + 1
+            const int tn = t + 2, bn = b ^ 1, qn = tn / 8;
+            if (ty == tn % 8) rowk[bn][0][c] = v[qn];
+            if (ty == tn % 8 + 1) rowk[bn][1][c] = v[qn];
+            if (c == tn || c == tn + 1) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = ty + 8 * q;
+                    colk[bn][c - tn][r] = v[q] - (r == c ? 1.0 : 0.0);
+                }
+            }
+            __syncthreads();
+        }
     }
     if (!ok && threadIdx.x == 0) atomicOr(bad, 1);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int r = ty + 8 * q;
-        Pinv[r * kNB + tx] = (r < nb && tx < nb) ? v[q] : 0.0;
+        const double x = (r < nb && c < nb) ? v[q] : 0.0;
+        Pinv[r * kNB + c] = x;
+        T[r][c] = x;
     }
 }
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-// One panel of the sweep over kNB x kNB tiles, from Ain to Aout.  The block
-// of tile (I, J) stages Pinv = A[K,K]^{-1}, A[K,J] and V = A[I,K] in LDS,
-// forms U[:,J] = Pinv A[K,J] and writes its tile of the updated matrix.
-// The products run on the FP64 matrix cores: each wave owns a 16 x 16
-// quarter, v_mfma_f64_16x16x4f64 with lane l feeding A[l%16][l/16] and
-// B[l/16][l%16] and holding D[4v + l/16][l%16] in accumulator v.  The tile
-// at (next_k0, next_k0), if any, then inverts its new values into
-// Pinv_next.
+// Tile (i0, j0), i0 <= j0, of panel k0 (nb wide) from Ain to Aout, with the
+// panel inverse Pinv: the workgroup stages Pinv, A[K,J] and A[I,K], forms
+// its slice of P A[K,J] on the FP64 matrix cores and writes the updated tile
+// and, off the diagonal, its transpose.  The target tile is loaded first,
+// so its latency overlaps the staging.
 __device__ __forceinline__ void sweep_tile(const double *__restrict__ Ain, double *__restrict__ Aout, int p, int k0,
-                                           int nb, const double *__restrict__ Pinv, int next_k0, int next_nb,
-                                           double *__restrict__ Pinv_next, int *__restrict__ bad, int i0, int j0)
+                                           int nb, const double *__restrict__ Pinv, int i0, int j0, Tile *S)
 {
-    __shared__ double Ps[kNB][kNB + 1];
-    __shared__ double Us[kNB][kNB + 1];
-    __shared__ double Vs[kNB][kNB + 1];
-    __shared__ double rowk[2][2][kNB], colk[2][2][kNB];
-    const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;  // 32 x 8
-    const int j = j0 + tx;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int r = ty + 8 * q, i = i0 + r;
-        Ps[r][tx] = Pinv[r * kNB + tx];  // zero outside nb
-        Us[r][tx] = (r < nb && j < p) ? Ain[(size_t)(k0 + r) * p + j] : 0.0;
-        Vs[r][tx] = (i < p && tx < nb) ? Ain[(size_t)i * p + k0 + tx] : 0.0;
-    }
-    __syncthreads();
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    const int qr = (wave / 2) * 16, qc = (wave % 2) * 16;  // the wave's quarter
-    const int ar = qr + lane % 16, bc = qc + lane % 16, kq = lane / 16;
-    const bool rowK = i0 == k0, colK = j0 == k0;  // tile row / column of the panel (uniform)
+    Tile &Ps = S[0], &Us = S[1], &Vs = S[2];
+    const Lay L;
+    const bool rowK = i0 == k0, colK = j0 == k0;  // uniform over the workgroup
+    const int ni = std::min(kNB, p - i0), nj = std::min(kNB, p - j0);
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-    if (rowK && colK) {  // A[K,K] <- Pinv
+    if (!rowK && !colK) load_acc(Ain, p, i0, j0, ni, nj, L, acc);
+    double gp[4], gu[4], gv[4];
+    load_rows(Pinv, kNB, 0, 0, kNB, kNB, L, gp);
+    load_rows(Ain, p, k0, j0, nb, nj, L, gu);
+    load_rows(Ain, p, i0, k0, ni, nb, L, gv);
+    put_rows(Ps, L, gp);
+    put_rows(Us, L, gu);
+    put_rows(Vs, L, gv);
+    __syncthreads();
+    if (rowK && colK) {  // A[K,K] <- -P
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = Ps[qr + 4 * v + kq][bc];
-    } else if (colK) {  // A[I,K] <- -V Pinv
-#pragma unroll
-        for (int s4 = 0; s4 < kNB; s4 += 4)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Vs[ar][s4 + kq], Ps[s4 + kq][bc], acc, 0, 0, 0);
+        for (int v = 0; v < 4; ++v) acc[v] = -Ps[L.qr + 4 * v + L.kq][L.bc];
+    } else if (colK) {  // A[I,K] <- A[I,K] P
+        mma<false>(acc, Vs, Ps, L);
     } else {
-        // U quarter = Pinv[qr.., :] A[K, qc..]
         v4d u = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int s4 = 0; s4 < kNB; s4 += 4)
-            u = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[ar][s4 + kq], Us[s4 + kq][bc], u, 0, 0, 0);
-        if (rowK) {  // A[K,J] <- U
+        mma<false>(u, Ps, Us, L);  // P A[K,J]
+        if (rowK) {                // A[K,J] <- P A[K,J]
             acc = u;
-        } else {  // A[I,J] <- A[I,J] - V U
-            __syncthreads();  // every read of A[K,J] is done (uniform branch)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Us[qr + 4 * v + kq][bc] = u[v];
+        } else {  // A[I,J] <- A[I,J] - A[I,K] P A[K,J]
+            __syncthreads();  // every read of A[K,J] is done
+            put_acc(Us, L, u);
             __syncthreads();
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = i0 + qr + 4 * v + kq, jj = j0 + bc;
-                acc[v] = (i < p && jj < p) ? Ain[(size_t)i * p + jj] : 0.0;
-            }
-#pragma unroll
-            for (int s4 = 0; s4 < kNB; s4 += 4)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Vs[ar][s4 + kq], Us[s4 + kq][bc], acc, 0, 0, 0);
+            mma<true>(acc, Vs, Us, L);
         }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int i = i0 + qr + 4 * v + kq, jj = j0 + bc;
-        if (i < p && jj < p) Aout[(size_t)i * p + jj] = acc[v];
-    }
-    if (next_nb > 0 && i0 == next_k0 && j0 == next_k0) {  // uniform over the block
-        __syncthreads();  // Ps is free again
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            Ps[qr + 4 * v + kq][bc] = (i0 + qr + 4 * v + kq < p && j0 + bc < p) ? acc[v] : 0.0;
-        __syncthreads();
-        tile_inverse(Ps, rowk, colk, next_nb, Pinv_next, bad);
+        const int r = L.qr + 4 * v + L.kq;
+        if (r < ni && L.bc < nj) {
+            Aout[(size_t)(i0 + r) * p + j0 + L.bc] = acc[v];
+            if (i0 != j0) Aout[(size_t)(j0 + L.bc) * p + i0 + r] = acc[v];
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void sweep_panel(const double *__restrict__ Ain, double *__restrict__ Aout, int p,
-                                                   int k0, int nb, const double *__restrict__ Pinv,
-                                                   int next_k0, int next_nb, double *__restrict__ Pinv_next,
-                                                   int *__restrict__ bad)
+// The look-ahead workspace beside the three panel inverses (slots 0-2):
+// the diagonal block of panel t+2 as it stands after panel t, B_t =
+// A_t[K2,K2], and the block above it, W_t = A_t[K1,K2], in slots 3 + t % 2
+// and 5 + t % 2.
+__device__ __forceinline__ double *slot_P(double *pw, int t) { return pw + (t % 3) * kPinv; }
+__device__ __forceinline__ double *slot_B(double *pw, int t) { return pw + (3 + t % 2) * kPinv; }
+__device__ __forceinline__ double *slot_W(double *pw, int t) { return pw + (5 + t % 2) * kPinv; }
+
+// Workgroup 0 of panel t's launch (panel t+2 exists): the last step of the
+// diagonal block of panel t+2 and its inverse,
+//     P_{t+2} = (B_t - W_t^T P_{t+1} W_t)^{-1}.
+__device__ __forceinline__ void la_inverse(double *__restrict__ pw, int p, int t, int *__restrict__ bad, Tile *S,
+                                           PivBuf &rowk, PivBuf &colk)
 {
-    sweep_tile(Ain, Aout, p, k0, nb, Pinv, next_k0, next_nb, Pinv_next, bad, blockIdx.y * kNB, blockIdx.x * kNB);
+    const Lay L;
+    const int n2 = std::min(kNB, p - (t + 2) * kNB);
+    double g_p1[4], g_w[4];
+    v4d b;
+    load_rows(slot_P(pw, t + 1), kNB, 0, 0, kNB, kNB, L, g_p1);
+    load_rows(slot_W(pw, t), kNB, 0, 0, kNB, kNB, L, g_w);
+    load_acc(slot_B(pw, t), kNB, 0, 0, kNB, kNB, L, b);
+    put_rows(S[0], L, g_p1);
+    put_rows(S[1], L, g_w);
+    __syncthreads();
+    v4d v = {0.0, 0.0, 0.0, 0.0};
+    mma<false>(v, S[0], S[1], L);  // P_{t+1} W_t
+    put_acc(S[2], L, v);
+    __syncthreads();
+    mma_tn_sub(b, S[1], S[2], L);
+    put_acc(S[0], L, b);  // S[0] was last read before the previous barrier
+    __syncthreads();
+    tile_inverse(S[0], rowk, colk, n2, slot_P(pw, t + 2), bad);
+}
+
+// Workgroup 1 of panel t's launch (panel t+3 exists; panels K0..K3 = t ..
+// t+3, the first three full): B_{t+1} = A_{t+1}[K3,K3] and W_{t+1} =
+// A_{t+1}[K2,K3] from the matrix A before panel t, P_t and P_{t+1}:
+//     U2 = P_t A[K0,K2],  U3 = P_t A[K0,K3]
+//     A'[Ka,Kb] = A[Ka,Kb] - A[K0,Ka]^T Ub     (panel t; ab = 12, 13, 23, 33)
+//     V = P_{t+1} A'[K1,K3]
+//     B_{t+1} = A'[K3,K3] - A'[K1,K3]^T V,  W_{t+1} = A'[K2,K3] - A'[K1,K2]^T V
+//                                                               (panel t+1)
+// Every load is issued up front.
+__device__ __forceinline__ void la_update(const double *__restrict__ A, double *__restrict__ pw, int p, int t,
+                                          Tile *S)
+{
+    const Lay L;
+    const int k0 = t * kNB, k1 = k0 + kNB, k2 = k1 + kNB, k3 = k2 + kNB, n3 = std::min(kNB, p - k3);
+    double g_p0[4], g_01[4], g_02[4], g_03[4], g_p1[4];
+    v4d t12, t13, t23, t33;
+    load_rows(slot_P(pw, t), kNB, 0, 0, kNB, kNB, L, g_p0);
+    load_rows(A, p, k0, k2, kNB, kNB, L, g_02);
+    load_rows(A, p, k0, k3, kNB, n3, L, g_03);
+    load_rows(A, p, k0, k1, kNB, kNB, L, g_01);
+    load_rows(slot_P(pw, t + 1), kNB, 0, 0, kNB, kNB, L, g_p1);
+    load_acc(A, p, k2, k3, kNB, n3, L, t23);
+    load_acc(A, p, k3, k3, n3, n3, L, t33);
+    load_acc(A, p, k1, k3, kNB, n3, L, t13);
+    load_acc(A, p, k1, k2, kNB, kNB, L, t12);
+    put_rows(S[0], L, g_p0);
+    put_rows(S[1], L, g_02);
+    put_rows(S[2], L, g_03);
+    __syncthreads();
+    v4d u2 = {0.0, 0.0, 0.0, 0.0}, u3 = {0.0, 0.0, 0.0, 0.0};
+    mma<false>(u2, S[0], S[1], L);
+    mma<false>(u3, S[0], S[2], L);
+    __syncthreads();
+    put_acc(S[0], L, u3);
+    __syncthreads();
+    mma_tn_sub(t23, S[1], S[0], L);
+    mma_tn_sub(t33, S[2], S[0], L);
+    __syncthreads();
+    put_acc(S[1], L, u2);
+    put_rows(S[2], L, g_01);
+    __syncthreads();
+    mma_tn_sub(t12, S[2], S[1], L);
+    mma_tn_sub(t13, S[2], S[0], L);
+    __syncthreads();
+    put_acc(S[1], L, t13);
+    put_rows(S[0], L, g_p1);
+    put_acc(S[2], L, t12);
+    __syncthreads();
+    v4d v = {0.0, 0.0, 0.0, 0.0};
+    mma<false>(v, S[0], S[1], L);  // P_{t+1} A'[K1,K3]
+    __syncthreads();
+    put_acc(S[0], L, v);
+    __syncthreads();
+    mma_tn_sub(t33, S[1], S[0], L);
+    mma_tn_sub(t23, S[2], S[0], L);
+    double *B = slot_B(pw, t + 1), *W = slot_W(pw, t + 1);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = L.qr + 4 * e + L.kq;
+        B[r * kNB + L.bc] = t33[e];
+        W[r * kNB + L.bc] = t23[e];
+    }
+}
+
+// P_0 = A[K0,K0]^{-1}, P_1 = (A[K1,K1] - A[K0,K1]^T P_0 A[K0,K1])^{-1} and the
+// look-ahead blocks of launch 0, B_0 = A[K2,K2] - A[K0,K2]^T P_0 A[K0,K2] and
+// W_0 = A[K1,K2] - A[K0,K1]^T P_0 A[K0,K2], as far as the panels exist.
+__device__ __forceinline__ void prologue(const double *__restrict__ C, int p, double *__restrict__ pw,
+                                         int *__restrict__ bad, Tile *S, PivBuf &rowk, PivBuf &colk)
+{
+    const Lay L;
+    // n1 <= 0: a single panel; n2 <= 0: two
+    const int n0 = std::min(kNB, p), n1 = std::min(kNB, p - kNB), n2 = std::min(kNB, p - 2 * kNB);
+    double g00[4], g01[4], g02[4];
+    v4d t11 = {0.0, 0.0, 0.0, 0.0}, t12 = {0.0, 0.0, 0.0, 0.0}, t22 = {0.0, 0.0, 0.0, 0.0};
+    load_rows(C, p, 0, 0, n0, n0, L, g00);
+    if (n1 > 0) {
+        load_rows(C, p, 0, kNB, n0, n1, L, g01);
+        load_acc(C, p, kNB, kNB, n1, n1, L, t11);
+    }
+    if (n2 > 0) {
+        load_rows(C, p, 0, 2 * kNB, kNB, n2, L, g02);
+        load_acc(C, p, kNB, 2 * kNB, kNB, n2, L, t12);
+        load_acc(C, p, 2 * kNB, 2 * kNB, n2, n2, L, t22);
+    }
+    put_rows(S[0], L, g00);
+    __syncthreads();
+    tile_inverse(S[0], rowk, colk, n0, slot_P(pw, 0), bad);
+    if (n1 <= 0) return;  // uniform
+    put_rows(S[1], L, g01);
+    if (n2 > 0) put_rows(S[2], L, g02);
+    __syncthreads();
+    v4d u1 = {0.0, 0.0, 0.0, 0.0}, u2 = {0.0, 0.0, 0.0, 0.0};
+    mma<false>(u1, S[0], S[1], L);  // P_0 A[K0,K1]
+    if (n2 > 0) mma<false>(u2, S[0], S[2], L);
+    __syncthreads();
+    put_acc(S[0], L, u1);
+    __syncthreads();
+    mma_tn_sub(t11, S[1], S[0], L);
+    if (n2 > 0) {
+        __syncthreads();
+        put_acc(S[0], L, u2);
+        __syncthreads();
+        mma_tn_sub(t12, S[1], S[0], L);
+        mma_tn_sub(t22, S[2], S[0], L);
+        double *B = slot_B(pw, 0), *W = slot_W(pw, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = L.qr + 4 * e + L.kq;
+            B[r * kNB + L.bc] = t22[e];
+            W[r * kNB + L.bc] = t12[e];
+        }
+    }
+    __syncthreads();
+    put_acc(S[0], L, t11);
+    __syncthreads();
+    tile_inverse(S[0], rowk, colk, n1, slot_P(pw, 1), bad);
+}
+
+// Tile (I, J), I <= J, number idx of the upper triangle of an nbt x nbt
+// tile grid taken row by row: counted from the end, row nbt - 1 - m holds
+// m + 1 tiles and starts m (m + 1) / 2 tiles before the end.
+__device__ __forceinline__ void upper_tile(int idx, int nbt, int &I, int &J)
+{
+    const int r = nbt * (nbt + 1) / 2 - 1 - idx;
+    int m = (int)((sqrtf(8.0f * (float)r + 1.0f) - 1.0f) * 0.5f);
+    while ((m + 1) * (m + 2) / 2 <= r) ++m;
+    while (m * (m + 1) / 2 > r) --m;
+    I = nbt - 1 - m;
+    J = nbt - 1 - (r - m * (m + 1) / 2);
+}
+
+// Workgroups of panel t's launch: 0 and 1 look ahead (while panels t+2 and
+// t+3 exist), 2 + idx updates upper tile idx.
+constexpr int kLookahead = 2;
+__device__ __forceinline__ void panel_block(const double *__restrict__ Ain, double *__restrict__ Aout, int p, int t,
+                                            int nbt, double *__restrict__ pw, int *__restrict__ bad, int64_t blk,
+                                            Tile *S, PivBuf &rowk, PivBuf &colk)
+{
+    const int k0 = t * kNB;
+    if (blk == 0) {
+        if (k0 + 2 * kNB < p) la_inverse(pw, p, t, bad, S, rowk, colk);
+        return;
+    }
+    if (blk == 1) {
+        if (k0 + 3 * kNB < p) la_update(Ain, pw, p, t, S);
+        return;
+    }
+    int I, J;
+    upper_tile((int)(blk - kLookahead), nbt, I, J);
+    sweep_tile(Ain, Aout, p, k0, std::min(kNB, p - k0), slot_P(pw, t), I * kNB, J * kNB, S);
+}
+
+__global__ __launch_bounds__(256) void first_prologue(const double *__restrict__ C, int p, double *__restrict__ pw,
+                                                      int *__restrict__ bad)
+{
+    __shared__ Tile S[3];
+    __shared__ PivBuf rowk, colk;
+    prologue(C, p, pw, bad, S, rowk, colk);
+}
+
+__global__ __launch_bounds__(256) void sweep_panel(const double *__restrict__ Ain, double *__restrict__ Aout, int p,
+                                                   int t, int nbt, double *__restrict__ pw, int *__restrict__ bad)
+{
+    __shared__ Tile S[3];
+    __shared__ PivBuf rowk, colk;
+    panel_block(Ain, Aout, p, t, nbt, pw, bad, blockIdx.x, S, rowk, colk);
 }
 
 // ---------------------------------------------------------------- many instances
 // Panel t of every instance with p > 32 t in one launch: job q covers
-// tiles [tile0[q], tile0[q] + nbt^2) of the flattened grid.
+// workgroups [tile0[q], tile0[q] + 2 + nbt (nbt + 1) / 2) of the flattened
+// grid.
 __global__ __launch_bounds__(256) void sweep_panel_batch(const SweepJob *__restrict__ jobs, int njobs)
 {
+    __shared__ Tile S[3];
+    __shared__ PivBuf rowk, colk;
     int lo = 0, hi = njobs;  // jobs[lo].tile0 <= blockIdx.x < jobs[hi].tile0
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -218,31 +463,22 @@ __global__ __launch_bounds__(256) void sweep_panel_batch(const SweepJob *__restr
         else hi = mid;
     }
     const SweepJob J = jobs[lo];
-    const int t = (int)((int64_t)blockIdx.x - J.tile0);
-    sweep_tile(J.Ain, J.Aout, J.p, J.k0, J.nb, J.Pinv, J.next_k0, J.next_nb, J.Pinv_next, J.bad, (t / J.nbt) * kNB,
-               (t % J.nbt) * kNB);
+    panel_block(J.Ain, J.Aout, J.p, J.t, J.nbt, J.pinv, J.bad, (int64_t)blockIdx.x - J.tile0, S, rowk, colk);
 }
 
-// First panel's diagonal block of every instance (one block each).
-__global__ __launch_bounds__(256) void first_tile_inverse_batch(const SweepJob *__restrict__ jobs)
+// The prologue of every instance (one workgroup each).
+__global__ __launch_bounds__(256) void first_prologue_batch(const SweepJob *__restrict__ jobs)
 {
+    __shared__ Tile S[3];
+    __shared__ PivBuf rowk, colk;
     const SweepJob J = jobs[blockIdx.x];
-    __shared__ double Ps[kNB][kNB + 1];
-    __shared__ double rowk[2][2][kNB], colk[2][2][kNB];
-    const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;
-    const int nb = J.p < kNB ? J.p : kNB;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int r = ty + 8 * q;
-        Ps[r][tx] = (r < nb && tx < nb) ? J.Ain[(size_t)r * J.p + tx] : 0.0;
-    }
-    __syncthreads();
-    tile_inverse(Ps, rowk, colk, nb, const_cast<double *>(J.Pinv), J.bad);  // this job writes the inverse
+    prologue(J.Ain, J.p, J.pinv, J.bad, S, rowk, colk);
 }
 
-// Decisions of every instance: adjacency byte = edge kept (not independent),
-// zero diagonal; deletions counted per instance; the Omega_ii rule of the
-// single-instance decision sets the instance's flag.
+// Decisions of every instance from its swept matrix S = -Omega: adjacency
+// byte = edge kept (not independent), zero diagonal; deletions counted per
+// instance; the Omega_ii rule of the single-instance decision sets the
+// instance's flag.
 __global__ __launch_bounds__(256) void first_level_decide_batch(const DecideJob *__restrict__ jobs, int njobs)
 {
     int lo = 0, hi = njobs;
@@ -257,13 +493,13 @@ __global__ __launch_bounds__(256) void first_level_decide_batch(const DecideJob 
     bool del = false;
     if (idx >= 0 && idx < pp) {
         const int i = (int)(idx / J.p), j = (int)(idx % J.p);
-        const double *Om = J.Om;
+        const double *Sw = J.Om;
         if (i == j) {
-            if (!(Om[idx] > 0.0) || !(Om[idx] <= 1e12)) atomicOr(J.bad, 1);
+            if (!(-Sw[idx] > 0.0) || !(-Sw[idx] <= 1e12)) atomicOr(J.bad, 1);
             J.adj[idx] = 0;
         } else {
-            const double oij = 0.5 * (Om[(size_t)i * J.p + j] + Om[(size_t)j * J.p + i]);
-            const double r = -oij / sqrt(Om[(size_t)i * J.p + i] * Om[(size_t)j * J.p + j]);
+            // r = -Omega_ij / sqrt(Omega_ii Omega_jj) = S_ij / sqrt(S_ii S_jj)
+            const double r = Sw[idx] / sqrt(Sw[(size_t)i * J.p + i] * Sw[(size_t)j * J.p + j]);
             uint8_t ind = 0;
             if (fabs(r) < 1.0) ind = sqrt((double)(J.n - (J.p - 2) - 3)) * fabs(atanh(r)) <= J.q;
             J.adj[idx] = ind ? 0 : 1;
@@ -274,24 +510,9 @@ __global__ __launch_bounds__(256) void first_level_decide_batch(const DecideJob 
     if (b && threadIdx.x % 64 == __ffsll((long long)b) - 1) atomicAdd(J.deleted, (unsigned long long)__popcll(b));
 }
 
-// Inverse of the first panel's diagonal block.
-__global__ __launch_bounds__(256) void first_tile_inverse(const double *__restrict__ A, int p, int nb,
-                                                          double *__restrict__ Pinv, int *__restrict__ bad)
-{
-    __shared__ double Ps[kNB][kNB + 1];
-    __shared__ double rowk[2][2][kNB], colk[2][2][kNB];
-    const int tx = threadIdx.x % kNB, ty = threadIdx.x / kNB;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int r = ty + 8 * q;
-        Ps[r][tx] = (r < nb && tx < nb) ? A[(size_t)r * p + tx] : 0.0;
-    }
-    __syncthreads();
-    tile_inverse(Ps, rowk, colk, nb, Pinv, bad);
-}
-
-// r_ij = -Omega_ij / sqrt(Omega_ii Omega_jj) (symmetrised), z, decision.
-__global__ __launch_bounds__(256) void first_level_decide(const double *__restrict__ Om, int p, int n, double q,
+// r_ij = -Omega_ij / sqrt(Omega_ii Omega_jj), z, decision, from the swept
+// matrix S = -Omega (exactly symmetric).
+__global__ __launch_bounds__(256) void first_level_decide(const double *__restrict__ Sw, int p, int n, double q,
                                                           double *__restrict__ r_out,
                                                           uint8_t *__restrict__ indep_out, int *__restrict__ bad)
 {
@@ -301,13 +522,12 @@ __global__ __launch_bounds__(256) void first_level_decide(const double *__restri
     if (i == j) {
         // Omega_ii = 1 / (1 - R^2_i): a variable determined by the others
         // (1 - R^2 < 1e-12) makes C singular for the tests.
-        if (!(Om[idx] > 0.0) || !(Om[idx] <= 1e12)) atomicOr(bad, 1);
+        if (!(-Sw[idx] > 0.0) || !(-Sw[idx] <= 1e12)) atomicOr(bad, 1);
         if (r_out) r_out[idx] = 1.0;
         if (indep_out) indep_out[idx] = 0;
         return;
     }
-    const double oij = 0.5 * (Om[(size_t)i * p + j] + Om[(size_t)j * p + i]);
-    const double r = -oij / sqrt(Om[(size_t)i * p + i] * Om[(size_t)j * p + j]);
+    const double r = Sw[idx] / sqrt(Sw[(size_t)i * p + i] * Sw[(size_t)j * p + j]);
     if (r_out) r_out[idx] = r;
     if (indep_out) {
         const int l = p - 2;
@@ -324,25 +544,23 @@ __global__ void clear_flag(int *__restrict__ f) { *f = 0; }
 
 // The sweep, the decisions and the positive-definiteness flag, queued on
 // the context's stream, with the workspace given: two p x p buffers (the
-// sweep reads one and writes the other), two kNB x kNB panel inverses and
-// the flag word (cleared by a kernel here when clear_bad is set).
+// sweep reads one and writes the other), the seven kNB x kNB blocks of the
+// panel workspace (three panel inverses, two look-ahead blocks and two
+// look-ahead rows) and the flag word (cleared by a kernel here when
+// clear_bad is set).
 int first_level_enqueue_ws(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out, uint8_t *indep_out,
-                           double *buf0, double *buf1, double *pinv0, double *pinv1, int *bad, bool clear_bad)
+                           double *buf0, double *buf1, double *pw, int *bad, bool clear_bad)
 {
     hipStream_t st = ctx->stream;
     const size_t pp = (size_t)p * p;
     double *buf[2] = {buf0, buf1};
-    double *pinv[2] = {pinv0, pinv1};
     if (clear_bad) clear_flag<<<1, 1, 0, st>>>(bad);
     const int nbt = (p + kNB - 1) / kNB;
-    first_tile_inverse<<<1, 256, 0, st>>>(C, p, p < kNB ? p : kNB, pinv[0], bad);
+    first_prologue<<<1, 256, 0, st>>>(C, p, pw, bad);
     const double *Ain = C;
-    int t = 0;
-    for (int k0 = 0; k0 < p; k0 += kNB, ++t) {
-        const int nb = p - k0 < kNB ? p - k0 : kNB;
-        const int nk = k0 + kNB, nnb = nk < p ? (p - nk < kNB ? p - nk : kNB) : 0;
-        sweep_panel<<<dim3(nbt, nbt), 256, 0, st>>>(Ain, buf[t & 1], p, k0, nb, pinv[t & 1], nk, nnb,
-                                                     pinv[(t + 1) & 1], bad);
+    for (int t = 0; t < nbt; ++t) {
+        sweep_panel<<<(unsigned)(nbt * (nbt + 1) / 2 + kLookahead), 256, 0, st>>>(Ain, buf[t & 1], p, t, nbt, pw,
+                                                                                   bad);
         Ain = buf[t & 1];
     }
     first_level_decide<<<(unsigned)((pp + 255) / 256), 256, 0, st>>>(Ain, p, n, q, r_out, indep_out, bad);
@@ -363,7 +581,7 @@ int first_level_batch_enqueue(fpc_ctx *ctx, const std::vector<FirstLevelInst> &i
     for (int k = 0; k < ni; ++k) {
         if (in[k].p < 2) return FPC_EINVAL;
     }
-    first_tile_inverse_batch<<<ni, 256, 0, st>>>(b.first_jobs);
+    first_prologue_batch<<<ni, 256, 0, st>>>(b.first_jobs);
     for (int t = 0; t < npanels; ++t) {
         const int nj = b.panel_njobs[t];
         if (nj == 0) continue;
@@ -394,7 +612,7 @@ int first_level_batch_plan(const std::vector<FirstLevelInst> &in, std::vector<Sw
         SweepJob J{};
         J.Ain = I.C;
         J.p = I.p;
-        J.Pinv = I.pinv0;
+        J.pinv = I.pinv;
         J.bad = I.bad;
         first.push_back(J);
     }
@@ -402,22 +620,17 @@ int first_level_batch_plan(const std::vector<FirstLevelInst> &in, std::vector<Sw
         panel_job0[t] = (int)panels.size();
         int64_t tiles = 0;
         for (const auto &I : in) {
-            const int k0 = t * kNB;
-            if (k0 >= I.p) continue;
+            if (t * kNB >= I.p) continue;
             SweepJob J{};
             J.Ain = t == 0 ? I.C : (t & 1 ? I.buf0 : I.buf1);
             J.Aout = t & 1 ? I.buf1 : I.buf0;
-            J.p = I.p;
-            J.k0 = k0;
-            J.nb = std::min(kNB, I.p - k0);
-            J.Pinv = t & 1 ? I.pinv1 : I.pinv0;
-            J.next_k0 = k0 + kNB;
-            J.next_nb = J.next_k0 < I.p ? std::min(kNB, I.p - J.next_k0) : 0;
-            J.Pinv_next = t & 1 ? I.pinv0 : I.pinv1;
+            J.pinv = I.pinv;
             J.bad = I.bad;
+            J.p = I.p;
+            J.t = t;
             J.nbt = (I.p + kNB - 1) / kNB;
             J.tile0 = tiles;
-            tiles += (int64_t)J.nbt * J.nbt;
+            tiles += (int64_t)J.nbt * (J.nbt + 1) / 2 + kLookahead;  // the upper tiles and the look-ahead
             panels.push_back(J);
         }
         panel_njobs[t] = (int)panels.size() - panel_job0[t];
@@ -446,8 +659,8 @@ namespace {
 
 // Workspace of fpc_first_level_noalloc, held by every device the library
 // runs on until the process ends: the two sweep buffers and the panel
-// inverses for p <= FPC_NOALLOC_MAX_P, then the flag word.
-constexpr size_t kNoAllocMats = 2 * (size_t)FPC_NOALLOC_MAX_P * FPC_NOALLOC_MAX_P + 2 * kNB * kNB;
+// workspace for p <= FPC_NOALLOC_MAX_P, then the flag word.
+constexpr size_t kNoAllocMats = 2 * (size_t)FPC_NOALLOC_MAX_P * FPC_NOALLOC_MAX_P + kPanelWork;
 constexpr size_t kNoAllocBytes = sizeof(double) * kNoAllocMats + 256;
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
@@ -458,14 +671,13 @@ int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, d
 {
     if (!C || p < 2 || n <= p + 1) return FPC_EINVAL;
     const size_t pp = (size_t)p * p;
-    int rc = ctx->inv_work.ensure(sizeof(double) * (2 * pp + 2 * kNB * kNB));
+    int rc = ctx->inv_work.ensure(sizeof(double) * (2 * pp + kPanelWork));
     if (rc) return rc;
     if ((rc = ctx->flag.ensure(64))) return rc;
     double *w = ctx->inv_work.as<double>();
     int *bad = ctx->flag.as<int>() + 4;
     FPC_HIP(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
-    if ((rc = first_level_enqueue_ws(ctx, C, p, n, q, r_out, indep_out, w, w + pp, w + 2 * pp,
-                                     w + 2 * pp + kNB * kNB, bad, false)))
+    if ((rc = first_level_enqueue_ws(ctx, C, p, n, q, r_out, indep_out, w, w + pp, w + 2 * pp, bad, false)))
         return rc;
     *d_bad = bad;
     return FPC_OK;
@@ -491,8 +703,7 @@ int first_level_noalloc(fpc_ctx *ctx, const double *C, int p, int n, double q, d
     const size_t pp = (size_t)p * p;
     double *w = static_cast<double *>(ctx->scratch);
     int *bad = reinterpret_cast<int *>(w + kNoAllocMats);
-    int rc = first_level_enqueue_ws(ctx, C, p, n, q, r_out, indep_out, w, w + pp, w + 2 * pp,
-                                    w + 2 * pp + kNB * kNB, bad, true);
+    int rc = first_level_enqueue_ws(ctx, C, p, n, q, r_out, indep_out, w, w + pp, w + 2 * pp, bad, true);
     if (rc) return rc;
     int hbad = 0;
     FPC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));

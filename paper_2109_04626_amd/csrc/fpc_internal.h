@@ -148,28 +148,30 @@ int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r
 int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
                         uint8_t *indep_out, const int **d_bad);
 // Many instances at once: each instance's matrix C (FP64, p x p), two p x p
-// sweep buffers, two 32 x 32 panel inverses, its flag and counter, and its
-// adjacency bytes (written: 1 = kept).
+// sweep buffers, a panel workspace of seven 32 x 32 blocks (contiguous), its
+// flag and counter, and its adjacency bytes (written: 1 = kept).
 struct FirstLevelInst {
     const double *C;
-    double *buf0, *buf1, *pinv0, *pinv1;
+    double *buf0, *buf1, *pinv;
     int *bad;
     unsigned long long *deleted;
     uint8_t *adj;
     int p, n;
     double q;
 };
+// Panel t of one instance (the prologue job: Ain = C, the other fields but
+// pinv, bad and p unused): workgroups [tile0, tile0 + 2 + nbt (nbt + 1) / 2)
+// of the launch.
 struct SweepJob {
     const double *Ain;
     double *Aout;
-    const double *Pinv;
-    double *Pinv_next;
+    double *pinv;  // the instance's panel workspace (seven 32 x 32 blocks)
     int *bad;
-    int p, k0, nb, next_k0, next_nb, nbt;
+    int p, t, nbt;
     int64_t tile0;
 };
 struct DecideJob {
-    const double *Om;
+    const double *Om;  // the swept matrix, -Omega
     uint8_t *adj;
     int *bad;
     unsigned long long *deleted;

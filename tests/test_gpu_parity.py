@@ -97,7 +97,10 @@ def test_corr_rejects_nonfinite_and_constant(fpc, ctx):
 
 
 # ------------------------------------------------------------------ first level
-@pytest.mark.parametrize("p,n", [(3, 50), (20, 1000), (95, 5000), (150, 2000), (333, 4000)])
+# p = 33, 64, 65, 97: one to three panels, the last ragged or full, so the
+# prologue's second inverse and the look-ahead's partial block both occur
+@pytest.mark.parametrize("p,n", [(3, 50), (20, 1000), (33, 500), (64, 800), (65, 800), (95, 5000), (97, 1000),
+                                 (150, 2000), (333, 4000)])
 def test_first_level_matches_oracle_inverse(fpc, ctx, p, n):
     _say(f"[first level] p={p} n={n}")
     sem = semdata.make_sem(p, 7, degree=4.0)

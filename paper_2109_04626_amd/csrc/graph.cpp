@@ -51,7 +51,16 @@ void scan_rows(const uint8_t *adj, int p, int u0, int u1, std::vector<int32_t> &
     }
 }
 
-void build_adjacency(const uint8_t *adj, int p, Adjacency &g, int nth)
+// Working storage of one candidate-set computation, kept per calling
+// thread so that repeated calls reuse their memory.
+struct Scratch {
+    Adjacency g;
+    std::vector<std::vector<int32_t>> pu, pv, parts;
+    std::vector<std::vector<int64_t>> lens;
+    std::vector<int32_t> block, nbblk, deg, fill, disc, low, estack;
+};
+
+void build_adjacency(const uint8_t *adj, int p, Adjacency &g, int nth, Scratch &sc)
 {
     // one pass over the upper triangle: edge ids in row-major (u < v) order;
     // for large p, blocks of rows (of about equal upper-triangle size) on
@@ -70,8 +79,16 @@ void build_adjacency(const uint8_t *adj, int p, Adjacency &g, int nth)
             acc += p - 1 - u;
             if (acc >= tri * b / nth) r0[b++] = u + 1;
         }
-        std::vector<std::vector<int32_t>> pu(nth), pv(nth);
-        host_parallel(nth, [&](int t) { scan_rows(adj, p, r0[t], r0[t + 1], pu[t], pv[t]); });
+        auto &pu = sc.pu, &pv = sc.pv;
+        if ((int)pu.size() < nth) {
+            pu.resize(nth);
+            pv.resize(nth);
+        }
+        host_parallel(nth, [&](int t) {
+            pu[t].clear();
+            pv[t].clear();
+            scan_rows(adj, p, r0[t], r0[t + 1], pu[t], pv[t]);
+        });
         size_t tot = 0;
         for (int t = 0; t < nth; ++t) tot += pu[t].size();
         g.eu.reserve(tot);
@@ -81,7 +98,8 @@ void build_adjacency(const uint8_t *adj, int p, Adjacency &g, int nth)
             g.ev.insert(g.ev.end(), pv[t].begin(), pv[t].end());
         }
     }
-    std::vector<int32_t> deg(p, 0);
+    std::vector<int32_t> &deg = sc.deg;
+    deg.assign(p, 0);
     for (size_t id = 0; id < g.eu.size(); ++id) {
         ++deg[g.eu[id]];
         ++deg[g.ev[id]];
@@ -90,7 +108,8 @@ void build_adjacency(const uint8_t *adj, int p, Adjacency &g, int nth)
     for (int u = 0; u < p; ++u) g.off[u + 1] = g.off[u] + deg[u];
     g.nb.resize(g.off[p]);
     g.eid.resize(g.off[p]);
-    std::vector<int32_t> fill(g.off.begin(), g.off.end() - 1);
+    std::vector<int32_t> &fill = sc.fill;
+    fill.assign(g.off.begin(), g.off.end() - 1);
     // edges in (u, v) row-major order: every list receives its smaller
     // neighbours (as v) before its larger ones (as u), in increasing order
     const int E = (int)g.eu.size();
@@ -107,14 +126,17 @@ void build_adjacency(const uint8_t *adj, int p, Adjacency &g, int nth)
 }
 
 // Block (biconnected component) label of every edge, iterative DFS.
-void edge_blocks(const Adjacency &g, int p, std::vector<int32_t> &block)
+void edge_blocks(const Adjacency &g, int p, std::vector<int32_t> &block, Scratch &sc)
 {
     const int E = (int)g.eu.size();
     block.assign(E, -1);
-    std::vector<int32_t> disc(p, -1), low(p, 0);
+    std::vector<int32_t> &disc = sc.disc, &low = sc.low;
+    disc.assign(p, -1);
+    low.assign(p, 0);
     struct Frame { int32_t v, pe, it; };
     std::vector<Frame> st;
-    std::vector<int32_t> estack;
+    std::vector<int32_t> &estack = sc.estack;
+    estack.clear();
     int timer = 0, nblk = 0;
     for (int s = 0; s < p; ++s) {
         if (disc[s] != -1) continue;
@@ -164,15 +186,17 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
         return std::chrono::duration<double, std::milli>(b - a).count();
     };
     const auto t0 = clk::now();
-    Adjacency g;
-    build_adjacency(adj, p, g, threads > 0 ? threads : host_threads());
+    thread_local Scratch sc;
+    Adjacency &g = sc.g;
+    build_adjacency(adj, p, g, threads > 0 ? threads : host_threads(), sc);
     const auto t1 = clk::now();
-    std::vector<int32_t> block;
-    edge_blocks(g, p, block);
+    std::vector<int32_t> &block = sc.block;
+    edge_blocks(g, p, block, sc);
     const auto t2 = clk::now();
     const int E = (int)g.eu.size();
     // block id of each adjacency slot, so the merge reads two flat arrays
-    std::vector<int32_t> nbblk(g.nb.size());
+    std::vector<int32_t> &nbblk = sc.nbblk;
+    nbblk.resize(g.nb.size());
     for (size_t t = 0; t < g.nb.size(); ++t) nbblk[t] = block[g.eid[t]];
     out.ei.assign(g.eu.begin(), g.eu.end());
     out.ej.assign(g.ev.begin(), g.ev.end());
@@ -223,8 +247,12 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
     };
     int nth = threads > 0 ? threads : host_threads();
     if (E < 2048) nth = 1;
-    std::vector<std::vector<int32_t>> parts(nth);
-    std::vector<std::vector<int64_t>> lens(nth);
+    auto &parts = sc.parts;
+    auto &lens = sc.lens;
+    if ((int)parts.size() < nth) {
+        parts.resize(nth);
+        lens.resize(nth);
+    }
     std::vector<int> bounds(nth + 1);
     for (int t = 0; t <= nth; ++t) bounds[t] = (int)((int64_t)E * t / nth);
     if (nth == 1) {

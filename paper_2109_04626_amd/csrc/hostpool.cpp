@@ -3,8 +3,14 @@
 // the workers are started once and reused, so a skeleton call does not pay
 // thread creation at every level.  One job runs at a time; a call made
 // while the pool is busy, or from inside a job, runs inline.
+//
+// Between jobs a worker spins on the job counter for a short while before
+// it sleeps, so the back-to-back jobs of one level start without a wake-up;
+// the caller takes items too and returns once every item is done and no
+// worker still holds the job, without waiting for sleeping workers.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <functional>
 #include <mutex>
@@ -16,6 +22,8 @@
 namespace fpc {
 
 namespace {
+
+inline void cpu_relax() { __builtin_ia32_pause(); }
 
 class HostPool {
   public:
@@ -29,7 +37,7 @@ class HostPool {
     {
         {
             std::lock_guard<std::mutex> lk(m_);
-            stop_ = true;
+            stop_.store(true);
         }
         cv_.notify_all();
         for (auto &w : workers_) w.join();
@@ -44,55 +52,87 @@ class HostPool {
             for (int k = 0; k < n; ++k) fn(k);
             return;
         }
+        const uint64_t g = gen_.load(std::memory_order_relaxed) + 1;
+        Job &J = jobs_[g & 1];
+        // a worker that read an older count may still be registered on
+        // this slot for a moment (it leaves without touching the job)
+        while (J.active.load(std::memory_order_acquire) != 0) cpu_relax();
+        J.fn = &fn;
+        J.n = n;
+        J.next.store(0, std::memory_order_relaxed);
+        J.done.store(0, std::memory_order_relaxed);
         {
             std::lock_guard<std::mutex> lk(m_);
-            fn_ = &fn;
-            n_ = n;
-            next_.store(0);
-            pending_ = (int)workers_.size();
-            ++gen_;
+            gen_.store(g, std::memory_order_release);
         }
-        cv_.notify_all();
-        work();
-        std::unique_lock<std::mutex> lk(m_);
-        done_cv_.wait(lk, [this] { return pending_ == 0; });
-        fn_ = nullptr;
+        if (sleepers_.load(std::memory_order_acquire) > 0) cv_.notify_all();
+        in_job_ = true;
+        work(J);
+        in_job_ = false;
+        while (J.done.load(std::memory_order_acquire) < n || J.active.load(std::memory_order_acquire) != 0)
+            cpu_relax();
     }
 
   private:
-    void work()
+    struct Job {
+        const std::function<void(int)> *fn = nullptr;
+        int n = 0;
+        std::atomic<int> next{0}, done{0}, active{0};
+    };
+
+    static void work(Job &J)
     {
-        in_job_ = true;
-        for (int k = next_++; k < n_; k = next_++) (*fn_)(k);
-        in_job_ = false;
-    }
-    void loop()
-    {
-        uint64_t seen = 0;
-        for (;;) {
-            {
-                std::unique_lock<std::mutex> lk(m_);
-                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
-                if (stop_) return;
-                seen = gen_;
-            }
-            work();
-            {
-                std::lock_guard<std::mutex> lk(m_);
-                if (--pending_ == 0) done_cv_.notify_one();
-            }
+        for (int k = J.next.fetch_add(1, std::memory_order_relaxed); k < J.n;
+             k = J.next.fetch_add(1, std::memory_order_relaxed)) {
+            (*J.fn)(k);
+            J.done.fetch_add(1, std::memory_order_release);
         }
     }
 
+    void loop()
+    {
+        using clk = std::chrono::steady_clock;
+        uint64_t seen = 0;
+        for (;;) {
+            uint64_t g = gen_.load(std::memory_order_acquire);
+            if (g == seen) {
+                const auto t0 = clk::now();
+                int spins = 0;
+                while ((g = gen_.load(std::memory_order_acquire)) == seen && !stop_.load(std::memory_order_relaxed)) {
+                    cpu_relax();
+                    if ((++spins & 255) == 0 && clk::now() - t0 > std::chrono::microseconds(kSpinUs)) {
+                        std::unique_lock<std::mutex> lk(m_);
+                        sleepers_.fetch_add(1, std::memory_order_acq_rel);
+                        cv_.wait(lk, [&] { return stop_.load() || gen_.load() != seen; });
+                        sleepers_.fetch_sub(1, std::memory_order_acq_rel);
+                        break;
+                    }
+                }
+                if (stop_.load()) return;
+                continue;  // read the count again
+            }
+            Job &J = jobs_[g & 1];
+            J.active.fetch_add(1, std::memory_order_acq_rel);
+            if (gen_.load(std::memory_order_acquire) != g) {  // a newer job was published meanwhile
+                J.active.fetch_sub(1, std::memory_order_release);
+                continue;
+            }
+            seen = g;
+            in_job_ = true;
+            work(J);
+            in_job_ = false;
+            J.active.fetch_sub(1, std::memory_order_release);
+        }
+    }
+
+    static constexpr int kSpinUs = 2000;  // spin this long after a job before sleeping
     std::vector<std::thread> workers_;
     std::mutex m_, job_m_;
-    std::condition_variable cv_, done_cv_;
-    const std::function<void(int)> *fn_ = nullptr;
-    int n_ = 0;
-    std::atomic<int> next_{0};
-    int pending_ = 0;
-    uint64_t gen_ = 0;
-    bool stop_ = false;
+    std::condition_variable cv_;
+    Job jobs_[2];
+    std::atomic<uint64_t> gen_{0};
+    std::atomic<int> sleepers_{0};
+    std::atomic<bool> stop_{false};
     static thread_local bool in_job_;
 };
 

@@ -666,6 +666,10 @@ struct PairLayout {
     static constexpr int S = SA + SB;                        // elements per position
 };
 
+// Lane mask of a condition across the wave (a bool straight into the
+// ballot, so the mask is not rebuilt from a 0/1 integer).
+__device__ __forceinline__ unsigned long long wave_mask(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1069,6 +1073,10 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
     const int64_t whi = min(wlo + rpw, r1);
     if (wlo >= whi) return;  // no later block-wide barrier
     const auto row = [&](int a) { return a * (2 * m - a - 3) / 2 - 1; };
+    // tile entry at a row offset and a column offset, both in bytes
+    const auto tri_at = [&](int row_bytes, int col_bytes) {
+        return *reinterpret_cast<const T *>(reinterpret_cast<const unsigned char *>(tri) + row_bytes + col_bytes);
+    };
 
     // the walk's position (Q, a, tau, rank) is the same in every lane
     int c[L];
@@ -1147,13 +1155,16 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                 sxi -= w[t] * uQ[t];
                 sxj -= w[t] * vQ[t];
             }
-            T *ex = tab + __umul24((unsigned)xp, (unsigned)Lay::S);
+            // entries at their absolute positions (x < m), so the pair loop
+            // addresses them without subtracting sQ; the row offset of x in
+            // the packed tile is stored in bytes
+            T *ex = tab + __umul24((unsigned)x, (unsigned)Lay::S);
 #pragma unroll
             for (int t = 0; t < QL; ++t) ex[t] = w[t];
             ex[QL] = sxx;
             ex[QL + 1] = sxi;
             ex[QL + 2] = sxj;
-            put_int(ex[QL + 3], row(x));
+            put_int(ex[QL + 3], row(x) * (int)sizeof(T));
         }
         wave_sync();
         // ---- a loop (uniform), pairs (b, c) after a across the lanes
@@ -1168,12 +1179,12 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                     break;
                 }
             }
-            const T *eaP = tab + __umul24((unsigned)(a - sQ), (unsigned)Lay::S);
+            const T *eaP = tab + __umul24((unsigned)a, (unsigned)Lay::S);
             T wa[QLL];
 #pragma unroll
             for (int t = 0; t < QL; ++t) wa[t] = eaP[t];
             const T saa = eaP[QL], sai = eaP[QL + 1], saj = eaP[QL + 2];
-            const int rowa = get_int(eaP[QL + 3]);
+            const int rowa = get_int(eaP[QL + 3]);  // bytes
             const T i1 = saa > T(0) ? rsqv(saa) : T(0);
             const T ua = sai * i1, va = saj * i1;
             const T H11a = H11 - ua * ua, H22a = H22 - va * va, H12a = H12 - ua * va;
@@ -1185,12 +1196,13 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
             bool hit_found = false;
             int done_tests = cnt;  // tests of this a run by the wave
             const int u0 = P - 1 - tau;  // reversed index of the first pair
+            const int lane_u = u0 - lane;
             // pairs from the table when it covers u0 (and so every u below),
             // from tri_root otherwise
-            auto pairs = [&](auto tabled) {
+            auto pairs = [&](auto tabled, auto diag) {
             for (int it = 0; it < cnt; it += 64) {
-                const bool valid = it + lane < cnt;
-                const unsigned u = (unsigned)(u0 - min(it + lane, cnt - 1));
+                const bool valid = lane < cnt - it;
+                const unsigned u = (unsigned)max(lane_u - it, u0 - (cnt - 1));  // u0 - min(it + lane, cnt - 1)
                 int b, cc;
                 if constexpr (decltype(tabled)::value) {
                     const unsigned d = pdec[u];
@@ -1202,9 +1214,11 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                     cc = m - 1 - (int)(u - (__umul24(rr, rr + 1u) >> 1));
                 }
                 // LDS offsets fit 24 bits
-                const T *eb = tab + __umul24((unsigned)(b - sQ), (unsigned)Lay::S);
-                const T *ec = tab + __umul24((unsigned)(cc - sQ), (unsigned)Lay::S);
-                T sab = tri[rowa + b], sac = tri[rowa + cc], sbc = tri[get_int(eb[QL + 3]) + cc];
+                const T *eb = tab + __umul24((unsigned)b, (unsigned)Lay::S);
+                const T *ec = tab + __umul24((unsigned)cc, (unsigned)Lay::S);
+                const int cb = cc * (int)sizeof(T);
+                T sab = tri_at(rowa, b * (int)sizeof(T)), sac = tri_at(rowa, cb),
+                  sbc = tri_at(get_int(eb[QL + 3]), cb);
 #pragma unroll
                 for (int q = 0; q < QL; ++q) {
                     sab -= wa[q] * eb[q];
@@ -1240,43 +1254,55 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
                     ok = oka && __float_as_int(pos_min(dK, hmin)) > 0 && fabsf(r) < 1.0f;
                     decide32b(r, dK * hmin, ok, rlo32, rhi32, errk, tau32, indep, dep);
                 }
-                if (A.diag_r) {  // uniform
+                if constexpr (decltype(diag)::value) {
                     if (valid) {
                         A.diag_r[rank + it + lane - A.diag_lo] = ok ? (double)r : (double)NAN;
                         A.diag_dec[rank + it + lane - A.diag_lo] =
                             (uint8_t)(indep ? DEC_INDEP : dep ? DEC_DEP : DEC_RECHECK);
                     }
-                    continue;
-                }
-                if constexpr (sizeof(T) == 4) {
-                    const bool rq = valid && !indep && !dep;
-                    const unsigned long long qb = __ballot(rq);
-                    if (qb) {
-                        unsigned long long slot = 0;
-                        if (lane == 0) slot = atomicAdd(&A.counters[1], (unsigned long long)__popcll(qb));
-                        slot = __shfl(slot, 0);
-                        if (rq) {
-                            const unsigned long long idx = slot + __popcll(qb & ((1ull << lane) - 1ull));
-                            if ((int64_t)idx < A.queue_cap) {
-                                A.queue[2 * idx] = e + A.edge_base;
-                                A.queue[2 * idx + 1] = rank + it + lane;
+                } else {
+                    const bool hit = valid && indep;
+                    const bool rq = sizeof(T) == 4 && valid && !indep && !dep;
+                    // the common round has neither an FP64 re-run nor a hit
+                    if (wave_mask(rq || hit)) {
+                        if constexpr (sizeof(T) == 4) {
+                            const unsigned long long qb = wave_mask(rq);
+                            if (qb) {
+                                unsigned long long slot = 0;
+                                if (lane == 0) slot = atomicAdd(&A.counters[1], (unsigned long long)__popcll(qb));
+                                slot = __shfl(slot, 0);
+                                if (rq) {
+                                    const unsigned long long idx = slot + __popcll(qb & ((1ull << lane) - 1ull));
+                                    if ((int64_t)idx < A.queue_cap) {
+                                        A.queue[2 * idx] = e + A.edge_base;
+                                        A.queue[2 * idx + 1] = rank + it + lane;
+                                    }
+                                }
                             }
+                        }
+                        const unsigned long long hb = wave_mask(hit);
+                        if (hb) {
+                            if (lane == 0)
+                                atomicMin((unsigned long long *)&A.minhit[e],
+                                          (unsigned long long)(rank + it + __ffsll((long long)hb) - 1));
+                            hit_found = true;
+                            done_tests = min(cnt, it + 64);
+                            break;
                         }
                     }
                 }
-                const unsigned long long hb = __ballot(valid && indep);
-                if (hb) {
-                    if (lane == 0)
-                        atomicMin((unsigned long long *)&A.minhit[e],
-                                  (unsigned long long)(rank + it + __ffsll((long long)hb) - 1));
-                    hit_found = true;
-                    done_tests = min(cnt, it + 64);
-                    break;
-                }
             }
             };
-            if (u0 < A.pdec_n) pairs(std::true_type{});
-            else pairs(std::false_type{});
+            // the diagnostic form (r and the decision of every test written
+            // out) is a separate loop, so the search loop carries no branch
+            // for it
+            if (A.diag_r) {
+                if (u0 < A.pdec_n) pairs(std::true_type{}, std::true_type{});
+                else pairs(std::false_type{}, std::true_type{});
+            } else {
+                if (u0 < A.pdec_n) pairs(std::true_type{}, std::false_type{});
+                else pairs(std::false_type{}, std::false_type{});
+            }
             executed += (uint64_t)done_tests;
             since_check += done_tests;
             if (hit_found) {

@@ -512,8 +512,12 @@ __device__ __forceinline__ void level_item(const LevelArgs &A, int64_t blk, unsi
         constexpr int LL = L > 0 ? L : 1;
         int c[LL], my[LL];
         if constexpr (L > 0) unrank<L>(wlo, m, A.binom, c);
+        // the edge's shared minimum is read one round ahead, so the wave
+        // does not wait for the load (a hit elsewhere stops it one round later)
+        uint64_t mh_ahead = load_minhit(&A.minhit[e]);
         for (int64_t base = wlo; base < whi; base += 64) {
-            const unsigned long long mh = (unsigned long long)uniform_i64((int64_t)load_minhit(&A.minhit[e]));
+            const unsigned long long mh = (unsigned long long)uniform_i64((int64_t)mh_ahead);
+            mh_ahead = load_minhit(&A.minhit[e]);
             if (mh < (unsigned long long)base) break;
             bool more = true;
             if constexpr (L > 0) more = walk64<L>(c, m, lane, my);
@@ -1097,7 +1101,12 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
     const float errk = (float)(kErrSafety * th.c_eff * (L + 2));
     const float rlo32 = (float)th.rb_lo, rhi32 = (float)th.rb_hi, tau32 = (float)th.tau;
     bool stop = false;
-    int since_check = kMinhitEvery;  // tests since the shared minimum was last read
+    // The shared minimum is read one check ahead: each check compares with
+    // the value read at the previous one and issues the next read, so the
+    // wave never waits for the load (another wave's hit stops this one at
+    // most one interval later; tests run past it are discarded).
+    int since_check = 0;  // tests since the last check
+    uint64_t mh_ahead = load_minhit(&A.minhit[e]);
     while (!stop) {
         // ---- Q state (identical in every lane)
         T LQ[QL > 0 ? QL * (QL + 1) / 2 : 1], invQ[QLL], uQ[QLL], vQ[QLL];
@@ -1173,7 +1182,8 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
             // minimum is read once per kMinhitEvery tests run
             if (since_check >= kMinhitEvery) {
                 since_check = 0;
-                const unsigned long long mh = (unsigned long long)uniform_i64((int64_t)load_minhit(&A.minhit[e]));
+                const unsigned long long mh = (unsigned long long)uniform_i64((int64_t)mh_ahead);
+                mh_ahead = load_minhit(&A.minhit[e]);
                 if (mh < (unsigned long long)rank) {
                     stop = true;
                     break;
@@ -1350,7 +1360,7 @@ constexpr int kPdecCap = 256 * 255 / 2;
 __host__ __device__ constexpr size_t pdec_bytes(int n) { return ((size_t)n * 2 + 15) / 16 * 16; }
 
 template <typename T, int QL>
-__global__ __launch_bounds__(256) void triple_kernel(LevelArgs A)
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && QL <= 2) ? 7 : 1) void triple_kernel(LevelArgs A)
 {
     apply_dclass(A);
     extern __shared__ __align__(16) unsigned char smem[];

@@ -38,9 +38,9 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32
 # calibration (fetch x2.000, write x1.000).  Valid only for the kernel source
 # and launch table they were taken with: any change to either makes the
 # figure null until the counters are taken again.
-MEASURED_TRAFFIC = {"bytes_per_launch": 10082592.0,
+MEASURED_TRAFFIC = {"bytes_per_launch": 10135645.0,
                     "sha256": {"paper_2109_04626_amd/csrc/citest.hip":
-                               "6ad95d387eed304556309b4644d574b6aac8ed82d4d53aa904a8772b8ca3a222",
+                               "5e78c72127bcc138d5b7e13b719ec8cecacc91a70ee38bc7565296e2723ed5a9",
                                "paper_2109_04626_amd/tuning_gfx950.json":
                                "9b5ee9cd8fc56c7307853a22b4732f84004d394956b92179119b5f35944c27e9"}}
 

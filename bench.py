@@ -187,7 +187,7 @@ def main() -> int:
             gc.enable()
         return dt, outs
 
-    # plain = FP64 tests, lexicographic order; mixed = bf16x3 C + FP32 tests
+    # plain = FP64 tests, lexicographic order; mixed = bf16x6 C + FP32 tests
     # with FP64 recheck; learned = mixed with the MLP-ranked candidate order
     if args.profile_mixed:
         dt, outs = timed(Xd, cfg, fpc.FPC_PREC_MIXED)
@@ -390,7 +390,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 tests + f64 recheck, bf16x3 C",
+        "dtype": "f32 tests + f64 recheck, bf16x6 C",
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD} seed {SEED}: ER DAG p={cfg['p']} deg={cfg['degree']}, "
                                f"n={cfg['n']} X {cfg['x_dtype']}, alpha={cfg['alpha']}, "

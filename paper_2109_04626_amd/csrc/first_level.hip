@@ -492,7 +492,8 @@ __global__ __launch_bounds__(256) void first_level_decide_batch(const DecideJob 
     const int64_t pp = (int64_t)J.p * J.p;
     bool del = false;
     if (idx >= 0 && idx < pp) {
-        const int i = (int)(idx / J.p), j = (int)(idx % J.p);
+        // p * p fits 32 bits on this path (checked when it is queued)
+        const int i = (int)idx / J.p, j = (int)idx - i * J.p;
         const double *Sw = J.Om;
         if (i == j) {
             if (!(-Sw[idx] > 0.0) || !(-Sw[idx] <= 1e12)) atomicOr(J.bad, 1);
@@ -506,8 +507,16 @@ __global__ __launch_bounds__(256) void first_level_decide_batch(const DecideJob 
             del = ind && i < j;
         }
     }
+    // one atomic per workgroup: the four waves' counts are summed in LDS (a
+    // workgroup's elements belong to one instance)
+    __shared__ unsigned int wcount[4];
     const unsigned long long b = __ballot(del);
-    if (b && threadIdx.x % 64 == __ffsll((long long)b) - 1) atomicAdd(J.deleted, (unsigned long long)__popcll(b));
+    if (threadIdx.x % 64 == 0) wcount[threadIdx.x / 64] = (unsigned int)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int c = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        if (c) atomicAdd(J.deleted, (unsigned long long)c);
+    }
 }
 
 // r_ij = -Omega_ij / sqrt(Omega_ii Omega_jj), z, decision, from the swept
@@ -579,7 +588,8 @@ int first_level_batch_enqueue(fpc_ctx *ctx, const std::vector<FirstLevelInst> &i
     const int npanels = (maxp + kNB - 1) / kNB;
     // job tables for every panel step (uploaded by the caller beforehand)
     for (int k = 0; k < ni; ++k) {
-        if (in[k].p < 2) return FPC_EINVAL;
+        // the decisions index an instance's p x p elements in 32 bits
+        if (in[k].p < 2 || (int64_t)in[k].p * in[k].p > INT32_MAX) return FPC_EINVAL;
     }
     first_prologue_batch<<<ni, 256, 0, st>>>(b.first_jobs);
     for (int t = 0; t < npanels; ++t) {

@@ -936,7 +936,82 @@ int largest_cand(const CandSets &cs)
     return mmax;
 }
 
-int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result **out)
+// The per-pair arrays of a result (adjacency, separating-set level, kind and
+// offset: 7.5 MB at p = 1000), allocated and first-touched on a helper
+// thread while the device runs the call, so that assembling the result does
+// not pay the page faults of fresh memory on the call's path.
+class ResultPrefetch {
+  public:
+    explicit ResultPrefetch(int p) : p_(p)
+    {
+        try {
+            th_ = std::thread([this] { fill(); });
+        } catch (...) {  // no thread: the result allocates its arrays itself
+        }
+    }
+    ~ResultPrefetch()
+    {
+        join();
+        std::free(adj_);
+        std::free(sep_level_);
+        std::free(sep_kind_);
+        std::free(sep_off_);
+    }
+    // Hands the arrays over (all four or none) to the caller, who frees them.
+    bool take(uint8_t *&adj, int32_t *&sep_level, int8_t *&sep_kind, int64_t *&sep_off)
+    {
+        join();
+        if (!adj_) return false;
+        adj = adj_;
+        sep_level = sep_level_;
+        sep_kind = sep_kind_;
+        sep_off = sep_off_;
+        adj_ = nullptr;
+        sep_level_ = nullptr;
+        sep_kind_ = nullptr;
+        sep_off_ = nullptr;
+        return true;
+    }
+
+  private:
+    void join()
+    {
+        if (th_.joinable()) th_.join();
+    }
+    void fill()
+    {
+        const size_t pp = (size_t)p_ * p_;
+        const size_t PP = (size_t)p_ * (p_ - 1) / 2;
+        uint8_t *a = (uint8_t *)std::malloc(pp);
+        int32_t *l = (int32_t *)std::malloc(sizeof(int32_t) * PP);
+        int8_t *k = (int8_t *)std::malloc(PP);
+        int64_t *o = (int64_t *)std::malloc(sizeof(int64_t) * (PP + 1));
+        if (!a || !l || !k || !o) {
+            std::free(a);
+            std::free(l);
+            std::free(k);
+            std::free(o);
+            return;
+        }
+        std::memset(a, 0, pp);
+        std::memset(l, 0, sizeof(int32_t) * PP);
+        std::memset(k, 0, PP);
+        std::memset(o, 0, sizeof(int64_t) * (PP + 1));
+        adj_ = a;
+        sep_level_ = l;
+        sep_kind_ = k;
+        sep_off_ = o;
+    }
+    int p_;
+    std::thread th_;
+    uint8_t *adj_ = nullptr;
+    int32_t *sep_level_ = nullptr;
+    int8_t *sep_kind_ = nullptr;
+    int64_t *sep_off_ = nullptr;
+};
+
+int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result **out,
+             ResultPrefetch *pre = nullptr)
 {
     const int p = R.p;
     const size_t pp = (size_t)p * p;
@@ -945,10 +1020,12 @@ int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result
     const int64_t PP = (int64_t)p * (p - 1) / 2;
     res->p = p;
     res->n_levels = (int32_t)R.levels.size();
-    res->adj = (uint8_t *)std::malloc(pp);
-    res->sep_level = (int32_t *)std::malloc(sizeof(int32_t) * PP);
-    res->sep_kind = (int8_t *)std::malloc(PP);
-    res->sep_off = (int64_t *)std::malloc(sizeof(int64_t) * (PP + 1));
+    if (!pre || !pre->take(res->adj, res->sep_level, res->sep_kind, res->sep_off)) {
+        res->adj = (uint8_t *)std::malloc(pp);
+        res->sep_level = (int32_t *)std::malloc(sizeof(int32_t) * PP);
+        res->sep_kind = (int8_t *)std::malloc(PP);
+        res->sep_off = (int64_t *)std::malloc(sizeof(int64_t) * (PP + 1));
+    }
     const int64_t tot = (int64_t)R.sep.nodes.size();
     res->sep_nodes = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1));
     res->n_lists = (int64_t)R.sep.lists.size();
@@ -1056,6 +1133,7 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
     FPC_HIP(hipSetDevice(ctx->device));
     ctx->use_pair_kernel = !(P->flags & FPC_FLAG_PER_TEST_KERNEL);
     const int p = P->p, n = P->n;
+    ResultPrefetch pre(p);
     const size_t pp = (size_t)p * p;
     hipStream_t s = ctx->stream;
     Run R;
@@ -1134,7 +1212,7 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
         }
     }
     const double ta = now_ms();
-    rc = assemble(R, corr_ms, first_ms, t_start, out);
+    rc = assemble(R, corr_ms, first_ms, t_start, out, &pre);
     if (trace_on())
         std::fprintf(stderr, "[fpc] correlation %.2f ms, first level %.2f ms, result %.2f ms, total %.2f ms\n", corr_ms,
                      first_ms, now_ms() - ta, now_ms() - t_start);

@@ -59,6 +59,9 @@ struct fpc_ctx {
     int64_t queue_init = int64_t(1) << 23;  // recheck queue entries: first size and cap
     int64_t queue_max = int64_t(1) << 28;   // (fpc_set_recheck_queue)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // the first level's results copied back; the mixed form's FP32 matrix
+    // and its error measure done (queued after the first level)
+    hipEvent_t ev_first = nullptr, ev_c32 = nullptr;
     static constexpr int kLaunchEvents = 256;
     hipEvent_t lev[2 * kLaunchEvents] = {};  // per-launch timing of the test kernels
 

@@ -246,7 +246,7 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
         dst.resize(o);
     };
     int nth = threads > 0 ? threads : host_threads();
-    if (E < 2048) nth = 1;
+    if (E < 256) nth = 1;
     auto &parts = sc.parts;
     auto &lens = sc.lens;
     if ((int)parts.size() < nth) {

@@ -29,8 +29,11 @@ class HostPool {
   public:
     HostPool()
     {
+        // the caller is one more worker, and one core is left to the runtime's
+        // own threads and the result prefetch (spinning workers must not
+        // take every core of the process's share)
         const unsigned hw = std::thread::hardware_concurrency();
-        const int n = (int)std::min<unsigned>(hw ? hw : 1, 16u) - 1;  // the caller is one more worker
+        const int n = std::max(0, (int)std::min<unsigned>(hw ? hw : 1, 16u) - 2);
         for (int t = 0; t < n; ++t) workers_.emplace_back([this] { loop(); });
     }
     ~HostPool()
@@ -125,7 +128,7 @@ class HostPool {
         }
     }
 
-    static constexpr int kSpinUs = 2000;  // spin this long after a job before sleeping
+    static constexpr int kSpinUs = 500;  // spin this long after a job before sleeping
     std::vector<std::thread> workers_;
     std::mutex m_, job_m_;
     std::condition_variable cv_;

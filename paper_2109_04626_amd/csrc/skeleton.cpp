@@ -229,7 +229,9 @@ extern "C" int fpc_create(fpc_ctx **out, int hip_device, void *hip_stream)
         }
         c->own_stream = true;
     }
-    if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess) {
+    if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_first, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_c32, hipEventDisableTiming)) != hipSuccess) {
         fpc_destroy(c);
         return hip_fail(e, "hipEventCreate");
     }
@@ -294,6 +296,8 @@ extern "C" int fpc_destroy(fpc_ctx *c)
         if (ev) (void)hipEventDestroy(ev);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->ev_first) (void)hipEventDestroy(c->ev_first);
+    if (c->ev_c32) (void)hipEventDestroy(c->ev_c32);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return FPC_OK;
@@ -367,6 +371,11 @@ struct Run {
     std::vector<int32_t> log_group, log_level;
     int32_t log_serial = 0;
     int32_t next_level = -1;  // stopped at a level boundary: the level to continue with
+    // the mixed form's FP32 matrix queued behind the first level, not yet
+    // waited for (its error measure c_err is read before the first subset level)
+    bool c32_pending = false;
+    const void *X = nullptr;
+    int x_dtype = 0;
 };
 
 // Runs fn(k) for k in [0, n) on the library's host threads.
@@ -820,25 +829,64 @@ void init_run(Run &R, fpc_ctx *ctx, const fpc_params *P, int p, int n)
 // Correlation matrices of the instance's data (device, n x p row-major):
 // FP64 into C64, and in the mixed form the bf16x3 FP32 copy into C32 with
 // its largest entry error against C64.
-int corr_stage(Run &R, const void *X, int x_dtype, double *C64, float *C32, double *ms)
+// The mixed form's FP32 matrix and its largest entry error against C64,
+// queued on the context's stream.
+int c32_enqueue(Run &R, float *C32)
+{
+    int rc;
+    const int m32 = R.P->c32_method ? R.P->c32_method : FPC_CORR_BF16X6;
+    if (m32 == FPC_CORR_FP32) {
+        if ((rc = corr_round_enqueue(R.ctx, R.C64, C32, R.p, false))) return rc;
+    } else if ((rc = corr_compute(R.ctx, R.X, R.x_dtype, R.n, R.p, m32, C32, true, false))) {
+        return rc;
+    }
+    R.C32 = C32;
+    return corr_max_abs_diff_enqueue(R.ctx, R.C64, R.C32, R.p);
+}
+
+// With defer_c32 (the first level runs next) only C64 is computed and
+// checked here; the FP32 matrix is queued behind the first level
+// (first_stage) and waited for by c32_finish, so it runs while the host
+// builds the first candidate sets.
+int corr_stage(Run &R, const void *X, int x_dtype, double *C64, float *C32, double *ms, bool defer_c32)
 {
     const double t0 = now_ms();
     int rc;
-    // both products and the error measure queued, then one wait
+    R.X = X;
+    R.x_dtype = x_dtype;
+    // a deferred product must find its work buffers allocated: growing one
+    // behind the first level would free memory that level still uses
+    if (R.mixed && defer_c32) {
+        const int m32 = R.P->c32_method ? R.P->c32_method : FPC_CORR_BF16X6;
+        if ((rc = corr_reserve(R.ctx, R.n, R.p, m32 == FPC_CORR_FP32 ? FPC_CORR_FP64 : m32))) return rc;
+    }
+    // the products and the error measure queued, then one wait
     if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_FP64, C64, false, false))) return rc;
     R.C64 = C64;
-    if (R.mixed) {
-        const int m32 = R.P->c32_method ? R.P->c32_method : FPC_CORR_BF16X6;
-        if (m32 == FPC_CORR_FP32) {
-            if ((rc = corr_round_enqueue(R.ctx, C64, C32, R.p, false))) return rc;
-        } else if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, m32, C32, true, false))) {
-            return rc;
-        }
-        R.C32 = C32;
-        if ((rc = corr_max_abs_diff_enqueue(R.ctx, R.C64, R.C32, R.p))) return rc;
-    }
-    if ((rc = corr_check(R.ctx, R.mixed ? &R.c_err : nullptr))) return rc;
+    const bool now = R.mixed && !defer_c32;
+    if (now && (rc = c32_enqueue(R, C32))) return rc;
+    if ((rc = corr_check(R.ctx, now ? &R.c_err : nullptr))) return rc;
+    R.c32_pending = R.mixed && defer_c32;
+    if (R.c32_pending) R.C32 = C32;
     *ms = now_ms() - t0;
+    return FPC_OK;
+}
+
+// Waits for the FP32 matrix queued behind the first level and reads its
+// error measure (the wait is added to the correlation time).
+int c32_finish(Run &R, double *corr_ms)
+{
+    if (!R.c32_pending) return FPC_OK;
+    const double t0 = now_ms();
+    R.c32_pending = false;
+    FPC_HIP(hipEventSynchronize(R.ctx->ev_c32));
+    const char *h = R.ctx->h_flag.as<char>();
+    std::memcpy(&R.c_err, h + 32, sizeof(double));
+    int flags[2];
+    std::memcpy(flags, h, sizeof(flags));
+    if (flags[0]) return FPC_ENONFINITE;
+    if (flags[1]) return FPC_ESINGULAR;
+    *corr_ms += now_ms() - t0;
     return FPC_OK;
 }
 
@@ -874,8 +922,17 @@ int first_stage(Run &R, double *ms)
     int *h_bad = reinterpret_cast<int *>(ctx->h_back.as<uint8_t>() + (pp + 15) / 16 * 16);
     FPC_HIP(hipMemcpyAsync(ctx->h_back.ptr, d_ind, pp, hipMemcpyDeviceToHost, s));
     FPC_HIP(hipMemcpyAsync(h_bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    FPC_HIP(hipEventRecord(ctx->ev_first, s));
+    if (R.c32_pending) {
+        // the FP32 matrix after the first level: it reuses the column
+        // statistics and the work buffer the sweep has finished with
+        if ((rc = ctx->h_flag.ensure(64))) return rc;
+        if ((rc = c32_enqueue(R, const_cast<float *>(R.C32)))) return rc;
+        FPC_HIP(hipMemcpyAsync(ctx->h_flag.ptr, ctx->flag.ptr, 40, hipMemcpyDeviceToHost, s));
+        FPC_HIP(hipEventRecord(ctx->ev_c32, s));
+    }
     const double tq = now_ms();
-    FPC_HIP(hipStreamSynchronize(s));
+    FPC_HIP(hipEventSynchronize(ctx->ev_first));
     const double tw = now_ms();
     if (*h_bad) return FPC_ESINGULAR;
     float kms = 0.f;
@@ -1150,7 +1207,10 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
     double corr_ms = 0.0, first_ms = 0.0;
     if ((rc = ctx->c64.ensure(sizeof(double) * pp))) return rc;
     if (R.mixed && (rc = ctx->c32.ensure(sizeof(float) * pp))) return rc;
-    if ((rc = corr_stage(R, X, P->x_dtype, ctx->c64.as<double>(), ctx->c32.as<float>(), &corr_ms))) return rc;
+    // the FP32 matrix is deferred behind the first level when that level runs
+    const bool defer_c32 = R.mixed && P->schedule == FPC_REVERSE && !P->resume;
+    if ((rc = corr_stage(R, X, P->x_dtype, ctx->c64.as<double>(), ctx->c32.as<float>(), &corr_ms, defer_c32)))
+        return rc;
 
     const int cap = P->max_level;
     CandSets cs;
@@ -1188,6 +1248,7 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
                 R.next_level = l;
                 break;
             }
+            if ((rc = c32_finish(R, &corr_ms))) return rc;
             std::vector<fpc_level_stats> lv;
             if ((rc = run_level(one_run, l, one_cs, lv))) return rc;
             R.levels.push_back(lv[0]);
@@ -1211,6 +1272,7 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
             ++levels_run;
         }
     }
+    if ((rc = c32_finish(R, &corr_ms))) return rc;
     const double ta = now_ms();
     rc = assemble(R, corr_ms, first_ms, t_start, out, &pre);
     if (trace_on())
@@ -1327,7 +1389,7 @@ int skeleton_batch_impl(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_ins
             X = ctx->x_copy.ptr;
         }
         if ((rc = corr_stage(R, X, P->x_dtype, reinterpret_cast<double *>(base + off64[k]),
-                             mixed ? reinterpret_cast<float *>(base + off32[k]) : nullptr, &corr_ms[k])))
+                             mixed ? reinterpret_cast<float *>(base + off32[k]) : nullptr, &corr_ms[k], false)))
             return rc;
         if ((rc = first_stage(R, &first_ms[k]))) return rc;
     }

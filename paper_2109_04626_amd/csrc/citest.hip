@@ -1042,7 +1042,7 @@ struct TripleLayout {
 
 template <typename T, int QL>
 __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, unsigned char *smem,
-                                            const uint16_t *__restrict__ pdec, ExecCount &ec)
+                                            const uint8_t *__restrict__ pdec, ExecCount &ec)
 {
     using Lay = TripleLayout<T, QL>;
     constexpr int L = QL + 3;
@@ -1213,16 +1213,11 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
             for (int it = 0; it < cnt; it += 64) {
                 const bool valid = lane < cnt - it;
                 const unsigned u = (unsigned)max(lane_u - it, u0 - (cnt - 1));  // u0 - min(it + lane, cnt - 1)
-                int b, cc;
-                if constexpr (decltype(tabled)::value) {
-                    const unsigned d = pdec[u];
-                    b = m - 2 - (int)(d & 0xffu);
-                    cc = m - 1 - (int)(d >> 8);
-                } else {
-                    const unsigned rr = tri_root(u);
-                    b = m - 2 - (int)rr;
-                    cc = m - 1 - (int)(u - (__umul24(rr, rr + 1u) >> 1));
-                }
+                unsigned rr;
+                if constexpr (decltype(tabled)::value) rr = pdec[u];
+                else rr = tri_root(u);
+                const int b = m - 2 - (int)rr;
+                const int cc = m - 1 - (int)(u - (__umul24(rr, rr + 1u) >> 1));
                 // LDS offsets fit 24 bits
                 const T *eb = tab + __umul24((unsigned)b, (unsigned)Lay::S);
                 const T *ec = tab + __umul24((unsigned)cc, (unsigned)Lay::S);
@@ -1353,11 +1348,13 @@ __device__ __forceinline__ void triple_item(const LevelArgs &A, int64_t blk, uns
 // Pairs (b < c) of the positions after a, in reversed order: the pair of
 // reversed index u lies in row rr = tri_root(u) of the triangle, column
 // s = u - rr(rr+1)/2, which puts it at b = m-2-rr, c = m-1-s whatever a is.
-// The table holds one 16-bit entry rr | s << 8 for each u below pdec_n;
-// pdec_n <= C(256, 2) keeps rr and s below 255.  The host sizes it to the
-// LDS a workgroup can take without fewer workgroups fitting on a CU.
+// The table holds the row rr (one byte) for each u below pdec_n; the
+// column follows from it.  pdec_n <= C(256, 2) keeps rr below 255.  The
+// host sizes it to the LDS a workgroup can take without fewer workgroups
+// fitting on a CU (a byte per entry covers twice the pairs of a 16-bit
+// entry holding both indices).
 constexpr int kPdecCap = 256 * 255 / 2;
-__host__ __device__ constexpr size_t pdec_bytes(int n) { return ((size_t)n * 2 + 15) / 16 * 16; }
+__host__ __device__ constexpr size_t pdec_bytes(int n) { return ((size_t)n + 15) / 16 * 16; }
 
 template <typename T, int QL>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 && QL <= 2) ? 7 : 1) void triple_kernel(LevelArgs A)
@@ -1366,12 +1363,9 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && QL <= 2) ? 7 : 1) void trip
     extern __shared__ __align__(16) unsigned char smem[];
     // the pair table is built once per launch and read by every item; the
     // barrier at the start of each item orders these writes before the reads
-    uint16_t *pdec = reinterpret_cast<uint16_t *>(smem);
+    uint8_t *pdec = reinterpret_cast<uint8_t *>(smem);
     const unsigned np = (unsigned)A.pdec_n;
-    for (unsigned u = threadIdx.x; u < np; u += blockDim.x) {
-        const unsigned rr = tri_root(u);
-        pdec[u] = (uint16_t)(rr | ((u - (__umul24(rr, rr + 1u) >> 1)) << 8));
-    }
+    for (unsigned u = threadIdx.x; u < np; u += blockDim.x) pdec[u] = (uint8_t)tri_root(u);
     unsigned char *rest = smem + pdec_bytes(A.pdec_n);
     ExecCount ec;
     for_each_item(A, [&](int64_t blk) { triple_item<T, QL>(A, blk, rest, pdec, ec); });
@@ -1431,7 +1425,7 @@ int triple_table_entries(int l, bool fp32, int max_m, size_t base, size_t lds_cu
     k0 = std::max(k0, 1);
     const size_t room = std::min<size_t>(lds_cu / (size_t)k0 - 256, lds_cap);
     if (room <= base) return 0;
-    return (int)std::min<size_t>(full, (room - base) / 2 / 8 * 8);
+    return (int)std::min<size_t>(full, (room - base) / 16 * 16);
 }
 
 // Workgroups of the triple kernel resident on one CU (registers, LDS of

@@ -113,15 +113,17 @@ def evaluate(ctx, model, seeds=EVAL_SEEDS, verbose: bool = True) -> dict:
 
         run(), run(model)  # warm
         ta, tb = [], []
-        for _ in range(3):  # alternating runs, median time of each form
+        for rep in range(4):  # median time of each form; each form runs first in half of the pairs
+            first_lex = rep % 2 == 0
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            a = run()
+            x = run() if first_lex else run(model)
             t1 = time.perf_counter()
-            b = run(model)
+            y = run(model) if first_lex else run()
             t2 = time.perf_counter()
-            ta.append(t1 - t0)
-            tb.append(t2 - t1)
+            a, b = (x, y) if first_lex else (y, x)
+            ta.append((t1 - t0) if first_lex else (t2 - t1))
+            tb.append((t2 - t1) if first_lex else (t1 - t0))
         same = bool(np.array_equal(a["adj"], b["adj"]) and np.array_equal(a["sep_level"], b["sep_level"]))
         lv_a = sum(x["tests_executed"] for x in a["levels"][1:])
         lv_b = sum(x["tests_executed"] for x in b["levels"][1:])

@@ -367,6 +367,22 @@ def test_skeleton_errors(fpc, ctx):
     with pytest.raises(fpc.FastPCError) as e:
         fpc.fpc_skeleton(ctx, dev(Y))
     assert e.value.code == fpc.FPC_ESINGULAR
+    # the mixed form queues its FP32 matrix behind the first level: the same
+    # errors, and a failed call leaves the context usable
+    ref = fpc.fpc_skeleton(ctx, dev(X), precision=fpc.FPC_PREC_MIXED)
+    Y = X.copy()
+    Y[3, 3] = np.inf
+    with pytest.raises(fpc.FastPCError) as e:
+        fpc.fpc_skeleton(ctx, dev(Y), precision=fpc.FPC_PREC_MIXED)
+    assert e.value.code == fpc.FPC_ENONFINITE
+    Y = X.copy()
+    Y[:, 4] = Y[:, 1]
+    with pytest.raises(fpc.FastPCError) as e:
+        fpc.fpc_skeleton(ctx, dev(Y), precision=fpc.FPC_PREC_MIXED)
+    assert e.value.code == fpc.FPC_ESINGULAR
+    again = fpc.fpc_skeleton(ctx, dev(X), precision=fpc.FPC_PREC_MIXED)
+    assert np.array_equal(again["adj"], ref["adj"]) and again["sepsets"] == ref["sepsets"]
+    assert again["corr_max_abs_err"] == ref["corr_max_abs_err"]
     Xb, _, _ = semdata.workload("er_p20_n1000_d3", 0)
     with pytest.raises(fpc.FastPCError) as e:
         fpc.fpc_skeleton(ctx, dev(Xb), max_tests=500)

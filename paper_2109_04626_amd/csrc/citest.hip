@@ -2275,10 +2275,11 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     const int ni = Lv.n_insts;
     int rc = ctx->insts.ensure(sizeof(InstRec) * (size_t)ni);
     if (rc) return rc;
-    if ((rc = ctx->h_inst.ensure(sizeof(InstRec) * (size_t)ni))) return rc;
-    // h_inst is free: the previous level's upload from it completed before
-    // the stream synchronisation that ends every level
-    InstRec *hin = ctx->h_inst.as<InstRec>();
+    if ((rc = ctx->h_inst.ensure(Lv.inst_off + sizeof(InstRec) * (size_t)ni))) return rc;
+    // the level's records in h_inst are free: the upload from them of the
+    // last level that used them completed before a stream synchronisation
+    // (levels queued back to back use records of their own)
+    InstRec *hin = reinterpret_cast<InstRec *>(ctx->h_inst.as<char>() + Lv.inst_off);
     for (int k = 0; k < ni; ++k) {
         const LevelInst &I = Lv.insts[k];
         hin[k].C = fp32 ? (const void *)I.C32 : (const void *)I.C64;
@@ -2287,7 +2288,8 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
         hin[k].th = make_thresholds(I.q, I.n, l, Lv.band_z, I.c_err + 4.0 * (l + 2) * 6.0e-8,
                                     resolve_tau(Lv.ill_cond_tau, I.n, l, I.c_err));
     }
-    if ((rc = upload_enqueue(ctx, ctx->insts.ptr, ctx->h_inst, 0, sizeof(InstRec) * (size_t)ni))) return rc;
+    if ((rc = upload_enqueue(ctx, ctx->insts.ptr, ctx->h_inst, Lv.inst_off, sizeof(InstRec) * (size_t)ni)))
+        return rc;
 
     // plan buffers, reused by every (window, class) launch in stream order:
     // [n_items, item_ctr], workgroup sums, per-edge offsets
@@ -2313,10 +2315,14 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     const int cus = ctx->num_cus;
     const size_t lds_cu = (size_t)ctx->lds_per_cu;
     g_max_blocks_per_cu = ctx->tuning.max_blocks_per_cu[lt];
+    const hipEvent_t ev0 = Lv.events ? Lv.events->ev0 : ctx->ev0;
+    const hipEvent_t ev1 = Lv.events ? Lv.events->ev1 : ctx->ev1;
+    const hipEvent_t *lev = Lv.events ? Lv.events->lev : ctx->lev;
+    const int n_lev = Lv.events ? Lv.events->n_lev : fpc_ctx::kLaunchEvents;
     const bool graph = Lv.graph;
     hipGraph_t g = nullptr;
     if (graph) FPC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    else FPC_HIP(hipEventRecord(ctx->ev0, st));
+    else FPC_HIP(hipEventRecord(ev0, st));
     int nev = 0, nlaunch = 0;
     hipError_t err = hipSuccess;
     for (int w = 0; w < max_nw && err == hipSuccess; ++w) {
@@ -2386,8 +2392,8 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                 plan_sums<<<1, 256, 0, st>>>(P, (int)nb);
                 plan_scan<<<(unsigned)nb, 256, 0, st>>>(P);
             }
-            const bool timed = !graph && nev < fpc_ctx::kLaunchEvents;
-            if (timed) (void)hipEventRecord(ctx->lev[2 * nev], st);
+            const bool timed = !graph && nev < n_lev;
+            if (timed) (void)hipEventRecord(lev[2 * nev], st);
             switch (k.kind) {
             case K_WIDE: {  // wide levels always run in FP64
                 const void *fn = (const void *)level_kernel_wide<double>;
@@ -2412,7 +2418,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                 break;
             }
             if (timed) {
-                (void)hipEventRecord(ctx->lev[2 * nev + 1], st);
+                (void)hipEventRecord(lev[2 * nev + 1], st);
                 ++nev;
             }
             if (trace_on())
@@ -2440,30 +2446,49 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
         if (err == hipSuccess) err = e2;
         hipGraphExec_t ge = nullptr;
         if (err == hipSuccess) err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        if (err == hipSuccess) err = hipEventRecord(ctx->ev0, st);
+        if (err == hipSuccess) err = hipEventRecord(ev0, st);
         if (err == hipSuccess) err = hipGraphLaunch(ge, st);
         if (ge) (void)hipGraphExecDestroy(ge);
         if (g) (void)hipGraphDestroy(g);
     }
     FPC_HIP(err);
-    FPC_HIP(hipEventRecord(ctx->ev1, st));
+    FPC_HIP(hipEventRecord(ev1, st));
     timing->test_launches = nlaunch;
     timing->n_events = nev;
     timing->graph = graph;
+    timing->e0 = ev0;
+    timing->e1 = ev1;
+    timing->lev = lev;
     return FPC_OK;
 }
 
 int level_timing(fpc_ctx *ctx, LevelTiming *timing)
 {
-    FPC_HIP(hipEventSynchronize(ctx->ev1));
-    FPC_HIP(hipEventElapsedTime(&timing->all_ms, ctx->ev0, ctx->ev1));
+    (void)ctx;
+    if (!timing->e1) return FPC_OK;  // nothing was launched
+    FPC_HIP(hipEventSynchronize(timing->e1));
+    FPC_HIP(hipEventElapsedTime(&timing->all_ms, timing->e0, timing->e1));
     timing->test_ms = 0.f;
     for (int k = 0; k < timing->n_events; ++k) {
         float ms = 0.f;
-        FPC_HIP(hipEventElapsedTime(&ms, ctx->lev[2 * k], ctx->lev[2 * k + 1]));
+        FPC_HIP(hipEventElapsedTime(&ms, timing->lev[2 * k], timing->lev[2 * k + 1]));
         timing->test_ms += ms;
     }
     if (timing->graph) timing->test_ms = timing->all_ms;  // one graph: plans and rechecks included
+    return FPC_OK;
+}
+
+int level_reserve(fpc_ctx *ctx, int64_t n_edges, int n_insts, int n_levels, size_t *inst_stride)
+{
+    if (n_edges < 0 || n_insts < 1 || n_levels < 1) return FPC_EINVAL;
+    // the plan buffer of level_tests at its size for n_edges
+    const int64_t nbmax = (n_edges + kPlanChunk - 1) / kPlanChunk;
+    int rc = ctx->blockoff.ensure(sizeof(int64_t) * (size_t)(2 + nbmax + n_edges + 1));
+    if (!rc) rc = ctx->insts.ensure(sizeof(InstRec) * (size_t)n_insts);
+    const size_t stride = (sizeof(InstRec) * (size_t)n_insts + 255) / 256 * 256;
+    if (!rc) rc = ctx->h_inst.ensure(stride * (size_t)n_levels);
+    if (rc) return rc;
+    *inst_stride = stride;
     return FPC_OK;
 }
 
@@ -2518,18 +2543,12 @@ int upload_enqueue(fpc_ctx *ctx, void *dst, const HostBuf &src, size_t offset, s
     return FPC_OK;
 }
 
-int level_compact_enqueue(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *h)
+int level_compact_enqueue(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *d_pairs,
+                          unsigned long long *d_count)
 {
-    hipStream_t st = ctx->stream;
-    int rc = ctx->dellist.ensure(sizeof(int64_t) * (2 * (size_t)n_edges + 2));
-    if (rc) return rc;
-    int64_t *d = ctx->dellist.as<int64_t>();
-    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(d);
-    FPC_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), st));
     if (n_edges > 0)
-        compact_kernel<<<(unsigned)((n_edges + 255) / 256), 256, 0, st>>>(minhit, n_edges, d + 2, cnt);
+        compact_kernel<<<(unsigned)((n_edges + 255) / 256), 256, 0, ctx->stream>>>(minhit, n_edges, d_pairs, d_count);
     FPC_HIP(hipGetLastError());
-    FPC_HIP(hipMemcpyAsync(h, d, sizeof(int64_t) * (2 * (size_t)n_edges + 2), hipMemcpyDeviceToHost, st));
     return FPC_OK;
 }
 

@@ -64,6 +64,11 @@ struct fpc_ctx {
     hipEvent_t ev_first = nullptr, ev_c32 = nullptr;
     static constexpr int kLaunchEvents = 256;
     hipEvent_t lev[2 * kLaunchEvents] = {};  // per-launch timing of the test kernels
+    // timing events of the small levels queued back to back on one graph
+    // (created on first use): per level ev0, ev1 and kChainLaunchEvents pairs
+    static constexpr int kChainSlots = 8, kChainLaunchEvents = 8;
+    hipEvent_t chain_ev[kChainSlots][2 + 2 * kChainLaunchEvents] = {};
+    bool chain_ev_ready = false;
 
     // binomial table on the device (saturating int64), kBinomRows x kBinomCols
     fpc::DevBuf binom;
@@ -81,15 +86,15 @@ struct fpc_ctx {
     fpc::DevBuf flag;             // small device scalars (error flags, counters)
 
     // level workspace
-    fpc::DevBuf cand;             // int32 candidate lists of eligible edges
-    fpc::DevBuf edges;            // EdgeRec per eligible edge
+    fpc::DevBuf cand;             // int32 candidate list of fpc_level_series
+    fpc::DevBuf edges;            // EdgeRec per eligible edge, then the int32 candidate lists
     fpc::DevBuf blockoff;         // window plan: item counters, workgroup sums, per-edge item prefix
     fpc::DevBuf insts;            // per-instance matrices and thresholds of a level
     fpc::DevBuf batch_c;          // fpc_skeleton_batch: every instance's correlation matrices
     fpc::DevBuf minhit;           // uint64 per edge: lowest independent rank
-    fpc::DevBuf counters;         // uint64 counters (tests executed, queue length, ...)
+    fpc::DevBuf counters;         // uint64 counters (tests executed, queue length, ...), then the deletions
     fpc::DevBuf queue;            // recheck queue (edge, rank)
-    fpc::DevBuf dellist;          // compacted deletions
+    fpc::DevBuf dellist;          // first-level decisions
     fpc::DevBuf batch_tmp;        // fpc_ci_batch / MLP gradient partials
     fpc::DevBuf mlp_grad;         // MLP gradient + loss of one training step
     fpc::DevBuf rfirst;           // first-level partial correlations (learned order)
@@ -213,6 +218,13 @@ struct LevelClass {
     int64_t begin, end;            // edge records [begin, end)
     int max_m;                     // largest |cand| in the class
 };
+// Timing events of one level: ev0 and ev1 around its launches, lev[2k] and
+// lev[2k + 1] around its k-th test launch (k < n_lev; later ones untimed).
+struct LevelEvents {
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    const hipEvent_t *lev = nullptr;
+    int n_lev = 0;
+};
 struct LevelLaunch {
     int l;
     int max_m;                     // largest |cand| among the eligible edges
@@ -228,10 +240,12 @@ struct LevelLaunch {
     double band_z;                 // recheck margin in z units
     double ill_cond_tau = -1.0;    // FP32 tests with rho below this go to FP64 (< 0: the default)
     uint64_t *minhit;              // device, per edge
-    unsigned long long *counters;  // device: [1] recheck queue length, [3] queue overflow
+    unsigned long long *counters;  // device: [1] recheck queue length, [2] deletions, [3] queue overflow
     unsigned long long *inst_cnt;  // device, per instance: [2k] tests executed, [2k+1] re-run in FP64
     int64_t *queue;                // device, 2 * queue_cap entries (edge, rank)
     int64_t queue_cap;
+    const LevelEvents *events = nullptr;  // NULL: the context's ev0, ev1 and lev
+    size_t inst_off = 0;           // byte offset of the level's instance records in ctx->h_inst
     // diagnostic run (fpc_level_series): one window [diag_lo, diag_hi) of
     // ranks, r and the decision of every rank written at [rank - diag_lo],
     // no early exit and no FP64 re-run
@@ -248,6 +262,8 @@ struct LevelTiming {
     int test_launches = 0;
     int n_events = 0;         // timed launches (event pairs)
     bool graph = false;       // the level ran as one captured graph
+    hipEvent_t e0 = nullptr, e1 = nullptr;  // the events level_tests recorded
+    const hipEvent_t *lev = nullptr;
 };
 // Size class of an edge with m candidates at level l: edges of one class
 // share a kernel and the number of workgroups that fit on a CU.
@@ -318,15 +334,21 @@ int level_inst_table_enqueue(fpc_ctx *ctx, const DevInstSrc *src, int ni, int l,
                              void *out);
 int level_tests_device(fpc_ctx *ctx, const DeviceLevel &D);
 
-// Reads the timings of the last level_tests once its work has completed.
+// Reads the timings of a level_tests call once its work has completed.
 int level_timing(fpc_ctx *ctx, LevelTiming *timing);
+// Sizes the context's level buffers for n_levels levels of at most n_edges
+// edges and n_insts instances queued back to back (no buffer may grow while
+// queued work reads it); *inst_stride is the byte distance between the
+// levels' instance records in ctx->h_inst.
+int level_reserve(fpc_ctx *ctx, int64_t n_edges, int n_insts, int n_levels, size_t *inst_stride);
 // Queues minhit[e] = all ones (no hit) for the level's edges and zeroes
 // the n_cnt counters.
 int level_init(fpc_ctx *ctx, uint64_t *minhit, int64_t n_edges, unsigned long long *counters, int n_cnt);
-// Queues the compaction of the level's hits and its copy into host memory
-// h (pinned, 2 * n_edges + 2 int64): after a stream synchronisation h[0]
-// is the number of deletions and h[2 + 2t], h[3 + 2t] the t-th (edge, rank).
-int level_compact_enqueue(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *h);
+// Queues the compaction of the level's hits: the t-th deletion (in no set
+// order) is d_pairs[2t] = edge, d_pairs[2t + 1] = its first independent
+// rank; *d_count (zero beforehand) counts them.
+int level_compact_enqueue(fpc_ctx *ctx, const uint64_t *minhit, int64_t n_edges, int64_t *d_pairs,
+                          unsigned long long *d_count);
 // Queues the copy of bytes [offset, offset + bytes) of the pinned buffer src
 // into device memory dst by a kernel that reads src through its device
 // mapping (the runtime's small host-to-device copies have held the calling

@@ -294,6 +294,9 @@ extern "C" int fpc_destroy(fpc_ctx *c)
     c->h_flag.release();
     for (hipEvent_t ev : c->lev)
         if (ev) (void)hipEventDestroy(ev);
+    for (auto &slot : c->chain_ev)
+        for (hipEvent_t ev : slot)
+            if (ev) (void)hipEventDestroy(ev);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev_first) (void)hipEventDestroy(c->ev_first);
@@ -385,21 +388,14 @@ void parallel_for(int n, F &&fn)
     host_parallel(n, std::function<void(int)>(fn));
 }
 
-// Runs one level (l >= 0) of one or more instances, each on its frozen
-// graph with precomputed candidate sets, in shared launches; applies every
-// instance's deletions at the end.  The learned order and feature logging
-// are available for a single instance only.
-int run_level(const std::vector<Run *> &runs, int l, const std::vector<const CandSets *> &css,
-              std::vector<fpc_level_stats> &sts)
-{
-    const int ni = (int)runs.size();
-    fpc_ctx *ctx = runs[0]->ctx;
-    hipStream_t s = ctx->stream;
-    const double t0 = now_ms();
-    sts.assign(ni, fpc_level_stats{});
-    // pass 1: eligible edges, list lengths and test counts per chunk of each
-    // instance's edges (chunks keep one instance on many host threads)
-    constexpr int64_t kEdgeChunk = 1024;
+// One level of one or more instances, each on its frozen graph with
+// precomputed candidate sets, from its planning to its results: planned
+// (eligible edges and test counts), built (records and lists in pinned
+// memory), uploaded, launched, then, after the stream has passed its work,
+// counted and decoded (every instance's deletions applied at once).  The
+// learned order and feature logging are available for a single instance
+// only.
+struct LevelJob {
     struct Chunk {
         int k;
         int64_t e0, e1;         // edges [e0, e1) of instance k's candidate sets
@@ -409,23 +405,72 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
         bool too_long = false;  // a list of kBinomRows candidates or more
         int64_t r = 0, c = 0;   // first record and list slot (pass 2)
     };
+    int l = 0;
     std::vector<Chunk> chunks;
-    for (int k = 0; k < ni; ++k) {
-        sts[k].level = l;
-        const int64_t Eall = (int64_t)css[k]->ei.size();
-        for (int64_t e0 = 0; e0 < Eall; e0 += kEdgeChunk) chunks.push_back(Chunk{k, e0, std::min(Eall, e0 + kEdgeChunk)});
-    }
-    // a level of a few thousand edges runs on the calling thread: waking the
-    // pool costs more than the work
-    const bool few = chunks.size() <= 4;
-    auto for_chunks = [&](const std::function<void(int)> &fn) {
+    bool few = false;  // few enough chunks for the calling thread alone
+    std::vector<fpc_level_stats> sts;
+    int64_t E = 0, T = 0;  // eligible edges and their list entries
+    int sel_max_m = 0;
+    // records and lists (pinned, ctx->h_stage, uploaded in one piece),
+    // counters and deletions (pinned, ctx->h_back, copied back in one piece):
+    // byte offsets of this level's regions
+    size_t stage_off = 0, back_off = 0;
+    EdgeRec *hrec = nullptr;
+    int32_t *cand = nullptr;  // the lists, in instance order
+    std::vector<EdgeRec> recs;
+    std::vector<int64_t> ntests, cs_edge;  // cs_edge: edge index of each record in its candidate sets
+    std::vector<LevelClass> classes;
+    std::vector<LevelInst> insts;
+    std::vector<float> hfeat;
+    const int32_t *d_cand = nullptr;
+    bool reorder = false, logging = false, fp32 = false;
+    int64_t qcap = 0;
+    size_t n_cnt = 0;
+    // pinned copy of the device counters: n_cnt counters ([2]: deletions),
+    // then the deletions as (edge, rank) pairs
+    unsigned long long *cnt = nullptr;
+    LevelLaunch Lv{};
+    LevelTiming tm;
+    const LevelEvents *events = nullptr;  // NULL: the context's
+    size_t inst_off = 0;
+    double t0 = 0, t_build = 0, t_copy = 0, t_order = 0, t_bufs = 0, t_tests0 = 0, t_tests1 = 0;
+    double t_level0 = 0;  // start of the interval reported as level_ms
+    double prev_all_ms = 0, prev_test_ms = 0;  // device time of discarded attempts
+    int prev_launches = 0;
+
+    size_t stage_bytes() const { return sizeof(EdgeRec) * (size_t)E + sizeof(int32_t) * (size_t)(T + 1); }
+    size_t back_bytes() const { return sizeof(unsigned long long) * (n_cnt + 2 * (size_t)E); }
+    template <class F>
+    void for_chunks(F &&fn)
+    {
         if (few)
             for (int u = 0; u < (int)chunks.size(); ++u) fn(u);
         else
             parallel_for((int)chunks.size(), fn);
-    };
-    for_chunks([&](int u) {
-        Chunk &ch = chunks[u];
+    }
+};
+
+// Pass 1: eligible edges, list lengths and test counts per chunk of each
+// instance's edges (chunks keep one instance on many host threads).  Checks
+// the test budget without spending it.
+int job_plan(const std::vector<Run *> &runs, int l, const std::vector<const CandSets *> &css, LevelJob &J)
+{
+    const int ni = (int)runs.size();
+    J.l = l;
+    J.sts.assign(ni, fpc_level_stats{});
+    J.n_cnt = 8 + 2 * (size_t)ni;
+    constexpr int64_t kEdgeChunk = 1024;
+    for (int k = 0; k < ni; ++k) {
+        J.sts[k].level = l;
+        const int64_t Eall = (int64_t)css[k]->ei.size();
+        for (int64_t e0 = 0; e0 < Eall; e0 += kEdgeChunk)
+            J.chunks.push_back(LevelJob::Chunk{k, e0, std::min(Eall, e0 + kEdgeChunk)});
+    }
+    // a level of a few thousand edges runs on the calling thread: waking the
+    // pool costs more than the work
+    J.few = J.chunks.size() <= 4;
+    J.for_chunks([&](int u) {
+        LevelJob::Chunk &ch = J.chunks[u];
         const CandSets &cs = *css[ch.k];
         for (int64_t e = ch.e0; e < ch.e1; ++e) {
             const int m = (int)(cs.off[e + 1] - cs.off[e]);
@@ -446,42 +491,49 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
             ch.sel_m = std::max(ch.sel_m, m);
         }
     });
-    int64_t E = 0, T = 0;
-    int sel_max_m = 0;
-    for (Chunk &ch : chunks) {  // in instance order, so each instance's records stay together
+    for (LevelJob::Chunk &ch : J.chunks) {  // in instance order, so each instance's records stay together
         if (ch.too_long) return FPC_ETOOLARGE;
         if (ch.bad) return FPC_EBUDGET;
-        fpc_level_stats &st = sts[ch.k];
+        fpc_level_stats &st = J.sts[ch.k];
         st.max_cand = std::max(st.max_cand, ch.max_m);
         st.edges_eligible += ch.n_el;
         if (ch.possible > INT64_MAX - st.tests_possible) return FPC_EBUDGET;
         st.tests_possible += ch.possible;
-        ch.r = E;
-        ch.c = T;
-        E += ch.n_el;
-        T += ch.n_cd;
-        sel_max_m = std::max(sel_max_m, ch.sel_m);
+        ch.r = J.E;
+        ch.c = J.T;
+        J.E += ch.n_el;
+        J.T += ch.n_cd;
+        J.sel_max_m = std::max(J.sel_max_m, ch.sel_m);
     }
     for (int k = 0; k < ni; ++k) {
-        Run &R = *runs[k];
-        if (R.P->max_tests > 0 && R.spent_possible + sts[k].tests_possible > R.P->max_tests) return FPC_EBUDGET;
-        R.spent_possible += sts[k].tests_possible;
+        const Run &R = *runs[k];
+        if (R.P->max_tests > 0 && R.spent_possible + J.sts[k].tests_possible > R.P->max_tests) return FPC_EBUDGET;
     }
-    if (T > INT32_MAX) return FPC_EBUDGET;
-    if (E == 0) {
-        for (auto &st : sts) st.level_ms = now_ms() - t0;
-        return FPC_OK;
-    }
-    // pass 2: records and lists straight into the pinned staging buffer
-    int rc;
-    const size_t up = sizeof(EdgeRec) * E + sizeof(int32_t) * (T + 1);
-    FPC_HIP(hipStreamSynchronize(s));  // the staging buffer is free
-    if ((rc = ctx->h_stage.ensure(up))) return rc;
-    EdgeRec *hrec = ctx->h_stage.as<EdgeRec>();
-    int32_t *cand = reinterpret_cast<int32_t *>(hrec + E);  // lists, in instance order
-    std::vector<int64_t> cs_edge(E);  // edge index of each record in its instance's candidate sets
-    for_chunks([&](int u) {
-        const Chunk &ch = chunks[u];
+    if (J.T > INT32_MAX) return FPC_EBUDGET;
+    return FPC_OK;
+}
+
+void job_spend(const std::vector<Run *> &runs, const LevelJob &J)
+{
+    for (size_t k = 0; k < runs.size(); ++k) runs[k]->spent_possible += J.sts[k].tests_possible;
+}
+
+// Pass 2: records and lists straight into the job's pinned region (J.hrec,
+// J.cand), then the size classes of the candidate lists: each class is
+// launched with the LDS its own largest list needs, so a few long lists do
+// not lower the occupancy (or the kernel choice) of all the others; a
+// stable counting sort of the records by class keeps each instance's edges
+// together.
+void job_build(const std::vector<Run *> &runs, const std::vector<const CandSets *> &css, LevelJob &J)
+{
+    fpc_ctx *ctx = runs[0]->ctx;
+    const int l = J.l;
+    const int64_t E = J.E;
+    EdgeRec *hrec = J.hrec;
+    int32_t *cand = J.cand;
+    std::vector<int64_t> cs_edge(E);
+    J.for_chunks([&](int u) {
+        const LevelJob::Chunk &ch = J.chunks[u];
         const CandSets &cs = *css[ch.k];
         int64_t r = ch.r, c = ch.c;
         for (int64_t e = ch.e0; e < ch.e1; ++e) {
@@ -494,60 +546,63 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
             c += m;
         }
     });
-    // size classes of the candidate lists: each class is launched with the
-    // LDS its own largest list needs, so a few long lists do not lower the
-    // occupancy (or the kernel choice) of all the others; a stable counting
-    // sort of the records by class keeps each instance's edges together
-    std::vector<EdgeRec> recs(E);
-    std::vector<int64_t> ntests(E);
-    std::vector<LevelClass> classes;
-    {
-        const bool fp32_cls = runs[0]->mixed && l <= kMaxTemplL;
-        std::vector<int> key_of(sel_max_m + 1);
-        int kmax = 0;
-        for (int m = 0; m <= sel_max_m; ++m) kmax = std::max(kmax, key_of[m] = level_class_key(ctx, l, fp32_cls, m));
-        std::vector<int64_t> cnt_k(kmax + 2, 0), c2(E);
-        for (int64_t k = 0; k < E; ++k) ++cnt_k[key_of[hrec[k].m] + 1];
-        for (int c = 0; c <= kmax; ++c) cnt_k[c + 1] += cnt_k[c];
-        for (int64_t k = 0; k < E; ++k) {
-            const int64_t d = cnt_k[key_of[hrec[k].m]]++;
-            recs[d] = hrec[k];
-            ntests[d] = recs[d].ntests;
-            c2[d] = cs_edge[k];
-        }
-        cs_edge.swap(c2);
-        std::memcpy(hrec, recs.data(), sizeof(EdgeRec) * E);
-        for (int64_t k = 0; k < E; ++k) {
-            const int c = key_of[recs[k].m];
-            if (classes.empty() || key_of[recs[classes.back().begin].m] != c) classes.push_back({k, k, 0});
-            classes.back().end = k + 1;
-            classes.back().max_m = std::max(classes.back().max_m, recs[k].m);
-        }
+    J.recs.resize(E);
+    J.ntests.resize(E);
+    const bool fp32_cls = runs[0]->mixed && l <= kMaxTemplL;
+    std::vector<int> key_of(J.sel_max_m + 1);
+    int kmax = 0;
+    for (int m = 0; m <= J.sel_max_m; ++m) kmax = std::max(kmax, key_of[m] = level_class_key(ctx, l, fp32_cls, m));
+    std::vector<int64_t> cnt_k(kmax + 2, 0), c2(E);
+    for (int64_t k = 0; k < E; ++k) ++cnt_k[key_of[hrec[k].m] + 1];
+    for (int c = 0; c <= kmax; ++c) cnt_k[c + 1] += cnt_k[c];
+    for (int64_t k = 0; k < E; ++k) {
+        const int64_t d = cnt_k[key_of[hrec[k].m]]++;
+        J.recs[d] = hrec[k];
+        J.ntests[d] = J.recs[d].ntests;
+        c2[d] = cs_edge[k];
     }
+    J.cs_edge.swap(c2);
+    std::memcpy(hrec, J.recs.data(), sizeof(EdgeRec) * E);
+    for (int64_t k = 0; k < E; ++k) {
+        const int c = key_of[J.recs[k].m];
+        if (J.classes.empty() || key_of[J.recs[J.classes.back().begin].m] != c) J.classes.push_back({k, k, 0});
+        J.classes.back().end = k + 1;
+        J.classes.back().max_m = std::max(J.classes.back().max_m, J.recs[k].m);
+    }
+    J.t_build = now_ms();
+}
 
-    const double t_build = now_ms();
-    if ((rc = ctx->edges.ensure(sizeof(EdgeRec) * E))) return rc;
-    if ((rc = ctx->cand.ensure(sizeof(int32_t) * (T + 1)))) return rc;
+// Device buffers, the uploads of the job's region of h_stage, the learned
+// order's passes and the instance table.
+int job_upload(const std::vector<Run *> &runs, const std::vector<const CandSets *> &css, LevelJob &J)
+{
+    const int ni = (int)runs.size();
+    fpc_ctx *ctx = runs[0]->ctx;
+    hipStream_t s = ctx->stream;
+    const int l = J.l;
+    const int64_t E = J.E, T = J.T;
+    int rc;
+    // the records and the lists after them, as in the staging region
+    if ((rc = ctx->edges.ensure(J.stage_bytes()))) return rc;
     if ((rc = ctx->minhit.ensure(sizeof(uint64_t) * E))) return rc;
-    if ((rc = ctx->counters.ensure(sizeof(unsigned long long) * (8 + 2 * (size_t)ni)))) return rc;
-    if ((rc = upload_enqueue(ctx, ctx->edges.ptr, ctx->h_stage, 0, sizeof(EdgeRec) * E))) return rc;
-    if ((rc = upload_enqueue(ctx, ctx->cand.ptr, ctx->h_stage, sizeof(EdgeRec) * E, sizeof(int32_t) * T))) return rc;
-    const double t_copy = now_ms();
+    if ((rc = ctx->counters.ensure(J.back_bytes()))) return rc;
+    if ((rc = upload_enqueue(ctx, ctx->edges.ptr, ctx->h_stage, J.stage_off, sizeof(EdgeRec) * E + sizeof(int32_t) * T)))
+        return rc;
+    J.t_copy = now_ms();
 
     // learned order: features, MLP scores, per-edge reorder of the lists
     // (at l = 0 each edge has one subset, so the order cannot matter)
     Run &R0 = *runs[0];
-    std::vector<float> hfeat;
-    const int32_t *d_cand = ctx->cand.as<int32_t>();
+    J.d_cand = reinterpret_cast<const int32_t *>(ctx->edges.as<EdgeRec>() + E);
     // The learned order can only save tests of edges deleted at this level,
     // and its passes (features, scores, reorder) cost about as much as a
     // few dozen tests per candidate; a level with fewer possible tests per
     // candidate than that (l <= 2 on the benchmark graphs) keeps the
     // lexicographic order.  The skeleton does not depend on the order.
     constexpr int64_t kLearnedMinTestsPerCand = 32;
-    const bool reorder = ni == 1 && R0.learned && l >= 1 && sts[0].tests_possible >= kLearnedMinTestsPerCand * T;
-    const bool logging = ni == 1 && R0.logging;
-    if (reorder || logging) {
+    J.reorder = ni == 1 && R0.learned && l >= 1 && J.sts[0].tests_possible >= kLearnedMinTestsPerCand * T;
+    J.logging = ni == 1 && R0.logging;
+    if (J.reorder || J.logging) {
         const CandSets &cs = *css[0];
         std::vector<int32_t> deg(R0.p, 0);  // degrees in the current graph, from its edge list
         for (size_t e = 0; e < cs.ei.size(); ++e) {
@@ -559,102 +614,103 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
         if ((rc = ctx->cand2.ensure(sizeof(int32_t) * (size_t)(T + 1)))) return rc;
         FPC_HIP(hipMemcpyAsync(ctx->degs.ptr, deg.data(), sizeof(int32_t) * R0.p, hipMemcpyHostToDevice, s));
         float *X = ctx->feat.as<float>(), *score = X + 3 * T;
-        if ((rc = level_features(ctx, ctx->edges.as<EdgeRec>(), E, d_cand, T, R0.C64, R0.Rfirst,
+        if ((rc = level_features(ctx, ctx->edges.as<EdgeRec>(), E, J.d_cand, T, R0.C64, R0.Rfirst,
                                  ctx->degs.as<int32_t>(), R0.p, X)))
             return rc;
-        if (reorder) {
+        if (J.reorder) {
             if ((rc = mlp_forward(ctx, X, T, R0.P->order_model, score))) return rc;
-            if ((rc = level_reorder(ctx, ctx->edges.as<EdgeRec>(), E, d_cand, score, ctx->cand2.as<int32_t>())))
+            if ((rc = level_reorder(ctx, ctx->edges.as<EdgeRec>(), E, J.d_cand, score, ctx->cand2.as<int32_t>())))
                 return rc;
-            d_cand = ctx->cand2.as<int32_t>();
+            J.d_cand = ctx->cand2.as<int32_t>();
         }
-        if (logging) {
-            hfeat.resize(3 * (size_t)T);
+        if (J.logging) {
+            J.hfeat.resize(3 * (size_t)T);
             // features follow the original order; the reorder maps them
-            FPC_HIP(hipMemcpyAsync(hfeat.data(), X, sizeof(float) * 3 * T, hipMemcpyDeviceToHost, s));
+            FPC_HIP(hipMemcpyAsync(J.hfeat.data(), X, sizeof(float) * 3 * T, hipMemcpyDeviceToHost, s));
             FPC_HIP(hipStreamSynchronize(s));
         }
     }
-    const double t_order = now_ms();
-    std::vector<LevelInst> insts(ni);
+    J.t_order = now_ms();
+    J.insts.resize(ni);
     for (int k = 0; k < ni; ++k) {
         const Run &R = *runs[k];
-        insts[k] = LevelInst{R.C32, R.C64, R.p, R.n, R.q, R.c_err};
+        J.insts[k] = LevelInst{R.C32, R.C64, R.p, R.n, R.q, R.c_err};
     }
-    bool fp32 = R0.mixed && l <= kMaxTemplL;
-    int64_t qcap = std::max<int64_t>(ctx->queue_init, (int64_t)(ctx->queue.bytes / (2 * sizeof(int64_t))));
-    if (fp32 && (rc = ctx->queue.ensure(sizeof(int64_t) * 2 * qcap))) return rc;
-    const size_t n_cnt = 8 + 2 * (size_t)ni;
-    // pinned landing area of the level's results: deletions, then counters
-    if ((rc = ctx->h_back.ensure(sizeof(int64_t) * (2 * (size_t)E + 2) + sizeof(unsigned long long) * n_cnt)))
-        return rc;
+    J.fp32 = R0.mixed && l <= kMaxTemplL;
+    J.qcap = std::max(ctx->queue_init, (int64_t)(ctx->queue.bytes / (2 * sizeof(int64_t))));
+    if (J.fp32 && (rc = ctx->queue.ensure(sizeof(int64_t) * 2 * J.qcap))) return rc;
+    J.t_bufs = now_ms();
+    return FPC_OK;
+}
 
-    const double t_bufs = now_ms();
-    int64_t *h_del = ctx->h_back.as<int64_t>();
-    const unsigned long long *cnt = reinterpret_cast<const unsigned long long *>(h_del + 2 * E + 2);
-    LevelLaunch Lv{};
-    LevelTiming tm;
-    const int64_t *pairs = h_del + 2;
-    int64_t ndel = 0;
-    double t_tests0 = 0.0, t_tests1 = 0.0;
-    double prev_all_ms = 0.0, prev_test_ms = 0.0;  // device time of discarded attempts
-    int prev_launches = 0;
-retry:
-    if ((rc = level_init(ctx, ctx->minhit.as<uint64_t>(), E, ctx->counters.as<unsigned long long>(), (int)n_cnt)))
+// Queues the level's tests, the compaction of its hits and the copies of
+// its deletions and counters into the job's region of h_back.
+int job_launch(const std::vector<Run *> &runs, LevelJob &J)
+{
+    fpc_ctx *ctx = runs[0]->ctx;
+    hipStream_t s = ctx->stream;
+    const Run &R0 = *runs[0];
+    int rc;
+    if ((rc = level_init(ctx, ctx->minhit.as<uint64_t>(), J.E, ctx->counters.as<unsigned long long>(), (int)J.n_cnt)))
         return rc;
-    Lv.l = l;
-    Lv.max_m = sel_max_m;
-    Lv.n_edges = E;
-    Lv.classes = classes.data();
-    Lv.n_classes = (int)classes.size();
+    LevelLaunch &Lv = J.Lv;
+    Lv = LevelLaunch{};
+    Lv.l = J.l;
+    Lv.max_m = J.sel_max_m;
+    Lv.n_edges = J.E;
+    Lv.classes = J.classes.data();
+    Lv.n_classes = (int)J.classes.size();
     Lv.edges = ctx->edges.as<EdgeRec>();
-    Lv.cand = d_cand;
-    Lv.insts = insts.data();
-    Lv.n_insts = ni;
-    Lv.fp32 = fp32;
+    Lv.cand = J.d_cand;
+    Lv.insts = J.insts.data();
+    Lv.n_insts = (int)runs.size();
+    Lv.fp32 = J.fp32;
     Lv.graph = (R0.P->flags & FPC_FLAG_GRAPH) != 0;
     Lv.band_z = R0.P->recheck_margin > 0 ? R0.P->recheck_margin : 1e-3;
     Lv.ill_cond_tau = R0.P->ill_cond_tau;
     Lv.minhit = ctx->minhit.as<uint64_t>();
     Lv.counters = ctx->counters.as<unsigned long long>();
     Lv.inst_cnt = Lv.counters + 8;
-    Lv.queue = fp32 ? ctx->queue.as<int64_t>() : nullptr;
-    Lv.queue_cap = fp32 ? qcap : 0;
-    t_tests0 = now_ms();
-    if ((rc = level_tests(ctx, Lv, ntests, &tm))) return rc;
+    Lv.queue = J.fp32 ? ctx->queue.as<int64_t>() : nullptr;
+    Lv.queue_cap = J.fp32 ? J.qcap : 0;
+    Lv.events = J.events;
+    Lv.inst_off = J.inst_off;
+    J.t_tests0 = now_ms();
+    if ((rc = level_tests(ctx, Lv, J.ntests, &J.tm))) return rc;
     // the host decodes separating sets against the lists the level used
     // (the uploads that read the staging buffer precede this copy on the stream)
-    if (reorder && T)
-        FPC_HIP(hipMemcpyAsync(cand, d_cand, sizeof(int32_t) * T, hipMemcpyDeviceToHost, s));
-    if ((rc = level_compact_enqueue(ctx, Lv.minhit, E, h_del))) return rc;
-    FPC_HIP(hipMemcpyAsync(const_cast<unsigned long long *>(cnt), Lv.counters, sizeof(unsigned long long) * n_cnt,
-                           hipMemcpyDeviceToHost, s));
-    FPC_HIP(hipStreamSynchronize(s));  // the one wait of the level
-    t_tests1 = now_ms();
-    if ((rc = level_timing(ctx, &tm))) return rc;
-    ndel = h_del[0];
-    for (int k = 0; k < ni; ++k) {
-        sts[k].tests_executed += (int64_t)cnt[8 + 2 * k];
-        sts[k].tests_rechecked += (int64_t)cnt[8 + 2 * k + 1];
-        runs[k]->total_exec += (int64_t)cnt[8 + 2 * k];
+    if (J.reorder && J.T)
+        FPC_HIP(hipMemcpyAsync(J.cand, J.d_cand, sizeof(int32_t) * J.T, hipMemcpyDeviceToHost, s));
+    if ((rc = level_compact_enqueue(ctx, Lv.minhit, J.E, reinterpret_cast<int64_t *>(Lv.counters + J.n_cnt),
+                                    Lv.counters + 2)))
+        return rc;
+    FPC_HIP(hipMemcpyAsync(J.cnt, Lv.counters, J.back_bytes(), hipMemcpyDeviceToHost, s));
+    return FPC_OK;
+}
+
+// Test counts of a completed launch (a discarded attempt's tests stay in
+// the counts, so its device time stays in the timings).
+void job_counts(const std::vector<Run *> &runs, LevelJob &J)
+{
+    for (size_t k = 0; k < runs.size(); ++k) {
+        J.sts[k].tests_executed += (int64_t)J.cnt[8 + 2 * k];
+        J.sts[k].tests_rechecked += (int64_t)J.cnt[8 + 2 * k + 1];
+        runs[k]->total_exec += (int64_t)J.cnt[8 + 2 * k];
     }
-    if (cnt[3]) {  // the recheck queue overflowed: run the whole level again
-        // the discarded attempt's tests stay in the counts, so its device
-        // time stays in the timings
-        prev_all_ms += tm.all_ms;
-        prev_test_ms += tm.test_ms;
-        prev_launches += tm.test_launches;
-        const int64_t grown = std::min(qcap * 4, ctx->queue_max);
-        if (grown > qcap && ctx->queue.ensure(sizeof(int64_t) * 2 * grown) == FPC_OK) {
-            qcap = grown;
-        } else {
-            fp32 = false;
-        }
-        if (trace_on())
-            std::fprintf(stderr, "[fpc] level %d: recheck queue overflow, level re-run %s\n", l,
-                         fp32 ? "with a 4x queue" : "in FP64");
-        goto retry;
-    }
+}
+
+// Sepsets and level-end deletion (stable: all of D at once) of a completed
+// level, and its statistics.
+void job_finish(const std::vector<Run *> &runs, const std::vector<const CandSets *> &css, LevelJob &J)
+{
+    const int ni = (int)runs.size();
+    fpc_ctx *ctx = runs[0]->ctx;
+    const int l = J.l;
+    const std::vector<EdgeRec> &recs = J.recs;
+    const int32_t *cand = J.cand;
+    const int64_t ndel = (int64_t)J.cnt[2];
+    const int64_t *pairs = reinterpret_cast<const int64_t *>(J.cnt + J.n_cnt);
+    std::vector<fpc_level_stats> &sts = J.sts;
     for (int k = 0; k < ni; ++k) sts[k].tests_required = sts[k].tests_possible;
     for (int64_t t = 0; t < ndel; ++t) {
         const EdgeRec &er = recs[pairs[2 * t]];
@@ -662,10 +718,9 @@ retry:
     }
 
     const double t_decode = now_ms();
-    // sepsets and level-end deletion (stable: all of D at once), each
-    // instance's deletions in pair order (the records are in class order)
-    // (the result lists every set in pair order, so the decoding order is
-    // free: deletions are only grouped by instance, and put in pair order
+    // each instance's deletions in pair order (the records are in class
+    // order; the result lists every set in pair order, so the decoding order
+    // is free: deletions are only grouped by instance, and put in pair order
     // for the feature log, whose rows follow it)
     std::vector<std::pair<int64_t, int64_t>> dl(ndel);
     std::vector<int64_t> d_lo(ni + 1, 0);  // deletions of instance k: dl[d_lo[k], d_lo[k+1])
@@ -675,7 +730,7 @@ retry:
         std::vector<int64_t> at(d_lo.begin(), d_lo.end() - 1);
         for (int64_t t = 0; t < ndel; ++t) dl[at[recs[pairs[2 * t]].inst]++] = {pairs[2 * t], pairs[2 * t + 1]};
     }
-    if (logging)
+    if (J.logging)
         std::sort(dl.begin(), dl.end(), [&](const std::pair<int64_t, int64_t> &a, const std::pair<int64_t, int64_t> &b) {
             const EdgeRec &x = recs[a.first], &y = recs[b.first];
             if (x.inst != y.inst) return x.inst < y.inst;
@@ -716,18 +771,18 @@ retry:
             R.adj[(size_t)er.i * R.p + er.j] = R.adj[(size_t)er.j * R.p + er.i] = 0;
         }
     });
-    if (logging) {
+    if (J.logging) {
         // features were computed over the list sorted by id (the cs order)
         Run &R = *runs[0];
         const CandSets &cs = *css[0];
         for (int64_t t = 0; t < ndel; ++t) {
             const EdgeRec &er = recs[dl[t].first];
-            const int32_t *orig = cs.nodes.data() + cs.off[cs_edge[dl[t].first]];
+            const int32_t *orig = cs.nodes.data() + cs.off[J.cs_edge[dl[t].first]];
             const int32_t *S = R.sep.nodes.data() + o0[0] + (size_t)t * l;
             for (int a2 = 0; a2 < er.m; ++a2) {
                 const int v = orig[a2];
                 const bool in = std::binary_search(S, S + l, v);
-                for (int f = 0; f < 3; ++f) R.log_x.push_back(hfeat[3 * ((size_t)er.cand_off + a2) + f]);
+                for (int f = 0; f < 3; ++f) R.log_x.push_back(J.hfeat[3 * ((size_t)er.cand_off + a2) + f]);
                 R.log_y.push_back(in ? 1 : 0);
                 R.log_group.push_back(R.log_serial);
                 R.log_level.push_back(l);
@@ -735,20 +790,182 @@ retry:
             ++R.log_serial;
         }
     }
-    const double level_ms = now_ms() - t0;
+    const double t_end = now_ms();
     if (trace_on())
         std::fprintf(stderr,
                      "[fpc] level %d: %d instance(s) %lld edges %lld candidates %d classes | setup %.2f upload+order "
                      "%.2f (copies %.2f, order %.2f, buffers %.2f) tests and compaction %.2f (device %.2f) counts %.2f "
                      "decode %.2f ms | deleted %lld, queued for FP64 in the last launch %llu\n",
-                     l, ni, (long long)E, (long long)T, (int)classes.size(), t_build - t0, t_tests0 - t_build,
-                     t_copy - t_build, t_order - t_copy, t_bufs - t_order, t_tests1 - t_tests0, tm.all_ms, t_decode - t_tests1, now_ms() - t_decode, (long long)ndel,
-                     fp32 ? cnt[1] : 0ull);
+                     l, ni, (long long)J.E, (long long)J.T, (int)J.classes.size(), J.t_build - J.t0,
+                     J.t_tests0 - J.t_build, J.t_copy - J.t_build, J.t_order - J.t_copy, J.t_bufs - J.t_order,
+                     J.t_tests1 - J.t_tests0, J.tm.all_ms, t_decode - J.t_tests1, t_end - t_decode, (long long)ndel,
+                     J.fp32 ? J.cnt[1] : 0ull);
     for (auto &st : sts) {
-        st.kernel_ms = prev_all_ms + tm.all_ms;
-        st.test_kernel_ms = prev_test_ms + tm.test_ms;
-        st.test_launches = prev_launches + tm.test_launches;
-        st.level_ms = level_ms;
+        st.kernel_ms = J.prev_all_ms + J.tm.all_ms;
+        st.test_kernel_ms = J.prev_test_ms + J.tm.test_ms;
+        st.test_launches = J.prev_launches + J.tm.test_launches;
+        st.level_ms = t_end - J.t_level0;
+    }
+}
+
+// Runs one level (l >= 0) of one or more instances, each on its frozen
+// graph with precomputed candidate sets, in shared launches; applies every
+// instance's deletions at the end.
+int run_level(const std::vector<Run *> &runs, int l, const std::vector<const CandSets *> &css,
+              std::vector<fpc_level_stats> &sts)
+{
+    fpc_ctx *ctx = runs[0]->ctx;
+    hipStream_t s = ctx->stream;
+    LevelJob J;
+    J.t0 = J.t_level0 = now_ms();
+    int rc;
+    if ((rc = job_plan(runs, l, css, J))) return rc;
+    job_spend(runs, J);
+    if (J.E == 0) {
+        for (auto &st : J.sts) st.level_ms = now_ms() - J.t0;
+        sts = std::move(J.sts);
+        return FPC_OK;
+    }
+    FPC_HIP(hipStreamSynchronize(s));  // the staging buffers are free
+    if ((rc = ctx->h_stage.ensure(J.stage_bytes()))) return rc;
+    if ((rc = ctx->h_back.ensure(J.back_bytes()))) return rc;
+    J.hrec = ctx->h_stage.as<EdgeRec>();
+    J.cand = reinterpret_cast<int32_t *>(J.hrec + J.E);
+    J.cnt = ctx->h_back.as<unsigned long long>();
+    job_build(runs, css, J);
+    if ((rc = job_upload(runs, css, J))) return rc;
+    for (;;) {
+        if ((rc = job_launch(runs, J))) return rc;
+        FPC_HIP(hipStreamSynchronize(s));  // the one wait of the level
+        J.t_tests1 = now_ms();
+        if ((rc = level_timing(ctx, &J.tm))) return rc;
+        job_counts(runs, J);
+        if (!J.cnt[3]) break;
+        // the recheck queue overflowed: run the whole level again
+        J.prev_all_ms += J.tm.all_ms;
+        J.prev_test_ms += J.tm.test_ms;
+        J.prev_launches += J.tm.test_launches;
+        const int64_t grown = std::min(J.qcap * 4, ctx->queue_max);
+        if (grown > J.qcap && ctx->queue.ensure(sizeof(int64_t) * 2 * grown) == FPC_OK) {
+            J.qcap = grown;
+        } else {
+            J.fp32 = false;
+        }
+        if (trace_on())
+            std::fprintf(stderr, "[fpc] level %d: recheck queue overflow, level re-run %s\n", l,
+                         J.fp32 ? "with a 4x queue" : "in FP64");
+    }
+    job_finish(runs, css, J);
+    sts = std::move(J.sts);
+    return FPC_OK;
+}
+
+// Small levels l_top, l_top - 1, ... of one instance on one unchanged graph,
+// queued back to back with one wait for all of them.  Level l - 1 runs on
+// the graph that level l leaves, so its results hold only if level l
+// deleted nothing: the levels are taken in order up to and including the
+// first one that deletes an edge, and the rest are dropped (their tests
+// counted nowhere).  A level whose recheck queue overflowed is dropped with
+// those after it, for the caller to run on its own.
+//
+// *n_taken = 0: not queued (fewer than two small levels); else the levels
+// taken are appended to out, *next_l is the level to run next and *changed
+// whether the graph changed.
+int run_chain(Run &R, int l_top, const CandSets &cs, std::vector<fpc_level_stats> &out, int *n_taken, int *next_l,
+              bool *changed)
+{
+    // a level with at most this many possible tests takes at most a few
+    // dozen microseconds on the device, less than a host round trip
+    constexpr int64_t kChainMaxTests = int64_t(1) << 24;
+    fpc_ctx *ctx = R.ctx;
+    hipStream_t s = ctx->stream;
+    const std::vector<Run *> runs{&R};
+    const std::vector<const CandSets *> css{&cs};
+    *n_taken = 0;
+    const double t_start = now_ms();
+    std::vector<LevelJob> jobs;
+    jobs.reserve(fpc_ctx::kChainSlots);
+    // the budget, the stop after a number of levels, the learned order,
+    // feature logging and captured levels take one level at a time
+    const fpc_params *P = R.P;
+    if (P->max_tests > 0 || P->stop_after_levels > 0 || R.learned || R.logging || (P->flags & FPC_FLAG_GRAPH))
+        return FPC_OK;
+    int64_t total = 0;
+    for (int l = l_top; l >= 0 && (int)jobs.size() < fpc_ctx::kChainSlots; --l) {
+        LevelJob J;
+        J.t0 = now_ms();
+        if (job_plan(runs, l, css, J) != FPC_OK || J.E == 0) break;  // such a level runs on its own
+        total += J.sts[0].tests_possible;
+        if (total > kChainMaxTests) break;
+        jobs.push_back(std::move(J));
+    }
+    if (jobs.size() < 2) return FPC_OK;
+    int rc;
+    if (!ctx->chain_ev_ready) {
+        for (auto &slot : ctx->chain_ev)
+            for (hipEvent_t &ev : slot)
+                if (!ev) FPC_HIP(hipEventCreate(&ev));
+        ctx->chain_ev_ready = true;
+    }
+    // every buffer sized before anything is queued: none may be reallocated
+    // while a queued level reads it (the last level has the most edges)
+    size_t so = 0, bo = 0, inst_stride = 0;
+    int64_t maxE = 0;
+    size_t maxStage = 0, maxBack = 0;
+    for (LevelJob &J : jobs) {
+        J.stage_off = so;
+        so += (J.stage_bytes() + 255) / 256 * 256;
+        J.back_off = bo;
+        bo += (J.back_bytes() + 255) / 256 * 256;
+        maxE = std::max(maxE, J.E);
+        maxStage = std::max(maxStage, J.stage_bytes());
+        maxBack = std::max(maxBack, J.back_bytes());
+    }
+    FPC_HIP(hipStreamSynchronize(s));  // the staging buffers are free
+    if ((rc = level_reserve(ctx, maxE, 1, (int)jobs.size(), &inst_stride))) return rc;
+    if ((rc = ctx->h_stage.ensure(so))) return rc;
+    if ((rc = ctx->h_back.ensure(bo))) return rc;
+    if ((rc = ctx->edges.ensure(maxStage))) return rc;
+    if ((rc = ctx->minhit.ensure(sizeof(uint64_t) * maxE))) return rc;
+    if ((rc = ctx->counters.ensure(maxBack))) return rc;
+    std::vector<LevelEvents> evs(jobs.size());
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        LevelJob &J = jobs[k];
+        evs[k] = LevelEvents{ctx->chain_ev[k][0], ctx->chain_ev[k][1], &ctx->chain_ev[k][2],
+                             fpc_ctx::kChainLaunchEvents};
+        J.events = &evs[k];
+        J.inst_off = inst_stride * k;
+        J.hrec = reinterpret_cast<EdgeRec *>(ctx->h_stage.as<char>() + J.stage_off);
+        J.cand = reinterpret_cast<int32_t *>(J.hrec + J.E);
+        J.cnt = reinterpret_cast<unsigned long long *>(ctx->h_back.as<char>() + J.back_off);
+        job_build(runs, css, J);
+        if ((rc = job_upload(runs, css, J))) return rc;
+        if ((rc = job_launch(runs, J))) return rc;
+    }
+    FPC_HIP(hipStreamSynchronize(s));  // the one wait of the chained levels
+    const double t_done = now_ms();
+    if (trace_on())
+        std::fprintf(stderr, "[fpc] levels %d..%d queued back to back: %.2f ms to the end of the last\n", jobs[0].l,
+                     jobs.back().l, t_done - t_start);
+    double t_prev = t_start;
+    *next_l = l_top;
+    *changed = false;
+    for (LevelJob &J : jobs) {
+        J.t_tests1 = t_done;
+        if ((rc = level_timing(ctx, &J.tm))) return rc;
+        if (J.cnt[3]) break;  // recheck queue overflow: the caller runs this level on its own
+        job_counts(runs, J);
+        job_spend(runs, J);
+        J.t_level0 = t_prev;  // the levels' intervals add up to the chain's time
+        job_finish(runs, css, J);
+        t_prev = now_ms();
+        out.push_back(J.sts[0]);
+        ++*n_taken;
+        *next_l = J.l - 1;
+        if (J.sts[0].deleted > 0) {
+            *changed = true;
+            break;
+        }
     }
     return FPC_OK;
 }
@@ -1250,6 +1467,19 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
             }
             if ((rc = c32_finish(R, &corr_ms))) return rc;
             std::vector<fpc_level_stats> lv;
+            int taken = 0, next_l = l;
+            bool changed = false;
+            // after a level that deleted nothing, the levels below it on the
+            // same graph are queued back to back (deletions tend to come in
+            // runs of levels: after one, the next level runs on its own)
+            if (cs_valid && (rc = run_chain(R, l, cs, lv, &taken, &next_l, &changed))) return rc;
+            if (taken > 0) {  // small levels queued back to back
+                R.levels.insert(R.levels.end(), lv.begin(), lv.end());
+                levels_run += taken;
+                cs_valid = !changed;
+                l = next_l;
+                continue;
+            }
             if ((rc = run_level(one_run, l, one_cs, lv))) return rc;
             R.levels.push_back(lv[0]);
             ++levels_run;

@@ -325,6 +325,38 @@ def test_skeleton_graph_mode_matches_eager(fpc, ctx, prec):
         _retest_sepsets(fpc, got, C, n, ref["q"])
 
 
+@pytest.mark.parametrize("p,n,deg,L,seed,prec", [(60, 1500, 8.0, -1, 5, 0), (60, 1500, 8.0, -1, 5, 1),
+                                                 (40, 800, 6.0, -1, 11, 1), (90, 3000, 5.0, 6, 41, 1),
+                                                 (90, 3000, 5.0, 6, 11, 1)])
+def test_skeleton_small_levels_back_to_back(fpc, ctx, p, n, deg, L, seed, prec):
+    """After a level that deletes nothing, the small levels below it are
+    queued back to back and kept up to the first one that deletes an edge; a
+    test budget makes every level run on its own.  Both runs give the
+    oracle's sequence of levels (level, deletions, tests required), skeleton
+    and separating sets."""
+    _say(f"[small levels] p={p} n={n} deg={deg} L={L} seed={seed} prec={prec}")
+    sem = semdata.make_sem(p, seed, degree=deg)
+    X = semdata.sample(sem, n, seed)
+    C = oracle.corr(X)
+    ref = oracle.skeleton(C, n, alpha=0.01, max_level=L)
+    want = [(int(r[0]), int(r[3]), int(r[2])) for r in ref["levels"]]
+    # the case has a subset level that deletes nothing with a level after it
+    assert any(w[1] == 0 for w in want[1:-1])
+    Xd = dev(X)
+    queued = fpc.fpc_skeleton(ctx, Xd, alpha=0.01, max_level=L, precision=prec)
+    single = fpc.fpc_skeleton(ctx, Xd, alpha=0.01, max_level=L, precision=prec, max_tests=1 << 62)
+    for got in (queued, single):
+        assert [(x["level"], x["deleted"], x["tests_required"]) for x in got["levels"]] == want
+        assert np.array_equal(got["adj"], ref["adj"])
+        assert np.array_equal(got["sep_level"], ref["sep_level"])
+        assert got["sepsets"] == ref["sepsets"]
+    for x, y in zip(queued["levels"], single["levels"]):
+        assert (x["tests_possible"], x["edges_eligible"], x["max_cand"]) == \
+               (y["tests_possible"], y["edges_eligible"], y["max_cand"])
+    # every subset level keeps its own launch count and device time
+    assert all(x["test_launches"] >= 1 and x["kernel_ms"] > 0.0 for x in queued["levels"][1:])
+
+
 # ------------------------------------------------------------------ edge cases
 def test_skeleton_smallest_graphs(fpc, ctx):
     rng = np.random.default_rng(3)

@@ -353,8 +353,10 @@ def main() -> int:
     value = tests / dt
 
     # dominant kernel: the test kernel of the level with the most tests;
-    # achieved = its algorithmic flops / the summed durations of its own
-    # launches (HIP events around each launch, on the library's stream)
+    # achieved = its algorithmic flops / the device time of its launches (HIP
+    # events around each launch, on the stream it is launched on; the size
+    # classes of a window run on two streams, so the time is the union of the
+    # launch intervals, and avg_launch_ms that union over the launch count)
     lv = [x for x in last["levels"] if x["level"] != cfg["p"] - 2]
     kms = sum(x["kernel_ms"] for x in lv)
     dom = max(lv, key=lambda x: x["tests_executed"])

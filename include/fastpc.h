@@ -253,8 +253,10 @@ typedef struct fpc_level_stats {
     int64_t deleted;          /* edges removed at the end of the level                  */
     double kernel_ms;         /* device time of the level: test kernels, rechecks and
                                  gaps between them (HIP events on the context stream)   */
-    double test_kernel_ms;    /* sum of the test-kernel launches alone (an event pair
-                                 around each of the first 256 launches)                 */
+    double test_kernel_ms;    /* device time of the test-kernel launches alone: the
+                                 union of their intervals (an event pair around each of
+                                 the first 256 launches; the size classes of a window run
+                                 on two streams and overlap)                            */
     int32_t test_launches;    /* test-kernel launches of the level                      */
     int32_t reserved;
     double level_ms;          /* whole level, host clock                                */

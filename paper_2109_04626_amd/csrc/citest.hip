@@ -37,6 +37,7 @@
 #include <cstdio>
 #include <cstring>
 #include <type_traits>
+#include <vector>
 
 #include "fpc_internal.h"
 
@@ -2291,17 +2292,17 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     if ((rc = upload_enqueue(ctx, ctx->insts.ptr, ctx->h_inst, Lv.inst_off, sizeof(InstRec) * (size_t)ni)))
         return rc;
 
-    // plan buffers, reused by every (window, class) launch in stream order:
-    // [n_items, item_ctr], workgroup sums, per-edge offsets
+    // plan buffers, [n_items, item_ctr], workgroup sums, per-edge offsets:
+    // one for the first class of each window (main stream), one for the
+    // classes after it (second stream), each reused in its stream's order
     const int64_t nbmax = (E + kPlanChunk - 1) / kPlanChunk;
-    if ((rc = ctx->blockoff.ensure(sizeof(int64_t) * (size_t)(2 + nbmax + E + 1)))) return rc;
-    int64_t *pl = ctx->blockoff.as<int64_t>();
+    const size_t plan_words = (size_t)(2 + nbmax + E + 1);
+    if ((rc = ctx->blockoff.ensure(sizeof(int64_t) * 2 * plan_words))) return rc;
+    int64_t *const plan_buf[2] = {ctx->blockoff.as<int64_t>(), ctx->blockoff.as<int64_t>() + plan_words};
 
     LevelArgs A{};
     A.cand = Lv.cand;
     A.inst = ctx->insts.as<InstRec>();
-    A.n_items = pl;
-    A.item_ctr = reinterpret_cast<unsigned long long *>(pl + 1);
     A.binom = ctx->binom.as<int64_t>();
     A.binomT = ctx->binomT.as<int64_t>();
     A.counters = Lv.counters;
@@ -2325,11 +2326,16 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     else FPC_HIP(hipEventRecord(ev0, st));
     int nev = 0, nlaunch = 0;
     hipError_t err = hipSuccess;
+    // the size classes of a window test disjoint edges: the first runs on the
+    // main stream and the others on the second, so that their launches (few
+    // long items on the long lists) overlap the first class's launch instead
+    // of following it; a captured level keeps one stream
+    const bool two = !graph && !Lv.diag_r && ctx->aux;
     for (int w = 0; w < max_nw && err == hipSuccess; ++w) {
         // the classes of a window share the recheck queue: the window's first
         // plan empties it and one FP64 re-run after its last launch drains it
         // (before any plan of the next window reads minhit)
-        bool window_open = false;
+        bool window_open = false, forked = false;
         for (const Cls &k : cls) {
             if (w + 1 >= (int)k.wins.size()) continue;
             const int64_t lo = k.wins[w], hi = k.wins[w + 1];
@@ -2361,6 +2367,18 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                 }
             }
             const int64_t Ek = k.end - k.begin, nb = (Ek + kPlanChunk - 1) / kPlanChunk;
+            // a later class of the window: on the second stream, after the
+            // first class's plan (which empties the recheck queue)
+            const bool on_aux = two && window_open;
+            if (on_aux && !forked) {
+                err = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0);
+                if (err != hipSuccess) break;
+                forked = true;
+            }
+            const hipStream_t ls = on_aux ? ctx->aux : st;
+            int64_t *const pl = plan_buf[on_aux ? 1 : 0];
+            A.n_items = pl;
+            A.item_ctr = reinterpret_cast<unsigned long long *>(pl + 1);
             PlanArgs P{};
             P.edges = Lv.edges + k.begin;
             P.minhit = Lv.minhit + k.begin;
@@ -2386,39 +2404,43 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             A.max_m = k.max_m;
             A.pdec_n = k.pdec_n;
             if (Ek <= kPlanSingleEdges) {
-                plan_single<<<1, kPlanSingleThreads, 0, st>>>(P);
+                plan_single<<<1, kPlanSingleThreads, 0, ls>>>(P);
             } else {
-                plan_reduce<<<(unsigned)nb, 256, 0, st>>>(P);
-                plan_sums<<<1, 256, 0, st>>>(P, (int)nb);
-                plan_scan<<<(unsigned)nb, 256, 0, st>>>(P);
+                plan_reduce<<<(unsigned)nb, 256, 0, ls>>>(P);
+                plan_sums<<<1, 256, 0, ls>>>(P, (int)nb);
+                plan_scan<<<(unsigned)nb, 256, 0, ls>>>(P);
+            }
+            if (two && !on_aux) {  // the point the window's other classes start from
+                err = hipEventRecord(ctx->ev_fork, st);
+                if (err != hipSuccess) break;
             }
             const bool timed = !graph && nev < n_lev;
-            if (timed) (void)hipEventRecord(lev[2 * nev], st);
+            if (timed) (void)hipEventRecord(lev[2 * nev], ls);
             switch (k.kind) {
             case K_WIDE: {  // wide levels always run in FP64
                 const void *fn = (const void *)level_kernel_wide<double>;
-                level_kernel_wide<double><<<resident_grid(fn, 64, k.shm, ub, cus, lds_cu), 64, k.shm, st>>>(A, l);
+                level_kernel_wide<double><<<resident_grid(fn, 64, k.shm, ub, cus, lds_cu), 64, k.shm, ls>>>(A, l);
                 break;
             }
             case K_TRIPLE:
-                err = fp32 ? launch_triple<float>(l, ub, cus, lds_cu, k.shm, st, A)
-                           : launch_triple<double>(l, ub, cus, lds_cu, k.shm, st, A);
+                err = fp32 ? launch_triple<float>(l, ub, cus, lds_cu, k.shm, ls, A)
+                           : launch_triple<double>(l, ub, cus, lds_cu, k.shm, ls, A);
                 break;
             case K_PAIR:
-                err = fp32 ? launch_pair<float>(l, ub, cus, lds_cu, k.shm, st, A)
-                           : launch_pair<double>(l, ub, cus, lds_cu, k.shm, st, A);
+                err = fp32 ? launch_pair<float>(l, ub, cus, lds_cu, k.shm, ls, A)
+                           : launch_pair<double>(l, ub, cus, lds_cu, k.shm, ls, A);
                 break;
             case K_TILE:
-                if (fp32) launch_level<float, true>(l, ub, cus, lds_cu, k.shm, st, A);
-                else launch_level<double, true>(l, ub, cus, lds_cu, k.shm, st, A);
+                if (fp32) launch_level<float, true>(l, ub, cus, lds_cu, k.shm, ls, A);
+                else launch_level<double, true>(l, ub, cus, lds_cu, k.shm, ls, A);
                 break;
             case K_GLOBAL:
-                if (fp32) launch_level<float, false>(l, ub, cus, lds_cu, 0, st, A);
-                else launch_level<double, false>(l, ub, cus, lds_cu, 0, st, A);
+                if (fp32) launch_level<float, false>(l, ub, cus, lds_cu, 0, ls, A);
+                else launch_level<double, false>(l, ub, cus, lds_cu, 0, ls, A);
                 break;
             }
             if (timed) {
-                (void)hipEventRecord(lev[2 * nev + 1], st);
+                (void)hipEventRecord(lev[2 * nev + 1], ls);
                 ++nev;
             }
             if (trace_on())
@@ -2428,6 +2450,12 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
             ++nlaunch;
             if (err == hipSuccess) err = hipGetLastError();
             if (err != hipSuccess) break;
+        }
+        // join: the re-run and the next window's plans follow every class
+        if (forked) {
+            const hipError_t e1 = hipEventRecord(ctx->ev_join, ctx->aux);
+            const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(st, ctx->ev_join, 0) : e1;
+            if (err == hipSuccess) err = e2;
         }
         // FP64 re-run of the window's queue (level edge indices)
         if (fp32 && window_open && err == hipSuccess && !Lv.diag_r) {
@@ -2468,12 +2496,26 @@ int level_timing(fpc_ctx *ctx, LevelTiming *timing)
     if (!timing->e1) return FPC_OK;  // nothing was launched
     FPC_HIP(hipEventSynchronize(timing->e1));
     FPC_HIP(hipEventElapsedTime(&timing->all_ms, timing->e0, timing->e1));
+    // the launches of a window's size classes overlap (two streams): the
+    // test time is the length of the union of the launch intervals
     timing->test_ms = 0.f;
+    std::vector<std::pair<float, float>> iv(timing->n_events);
     for (int k = 0; k < timing->n_events; ++k) {
-        float ms = 0.f;
-        FPC_HIP(hipEventElapsedTime(&ms, timing->lev[2 * k], timing->lev[2 * k + 1]));
-        timing->test_ms += ms;
+        FPC_HIP(hipEventElapsedTime(&iv[k].first, timing->e0, timing->lev[2 * k]));
+        FPC_HIP(hipEventElapsedTime(&iv[k].second, timing->e0, timing->lev[2 * k + 1]));
     }
+    std::sort(iv.begin(), iv.end());
+    float lo = 0.f, hi = -1.f;
+    for (const auto &x : iv) {
+        if (x.first > hi) {
+            if (hi > lo) timing->test_ms += hi - lo;
+            lo = x.first;
+            hi = x.second;
+        } else {
+            hi = std::max(hi, x.second);
+        }
+    }
+    if (hi > lo) timing->test_ms += hi - lo;
     if (timing->graph) timing->test_ms = timing->all_ms;  // one graph: plans and rechecks included
     return FPC_OK;
 }
@@ -2481,9 +2523,9 @@ int level_timing(fpc_ctx *ctx, LevelTiming *timing)
 int level_reserve(fpc_ctx *ctx, int64_t n_edges, int n_insts, int n_levels, size_t *inst_stride)
 {
     if (n_edges < 0 || n_insts < 1 || n_levels < 1) return FPC_EINVAL;
-    // the plan buffer of level_tests at its size for n_edges
+    // the two plan buffers of level_tests at their size for n_edges
     const int64_t nbmax = (n_edges + kPlanChunk - 1) / kPlanChunk;
-    int rc = ctx->blockoff.ensure(sizeof(int64_t) * (size_t)(2 + nbmax + n_edges + 1));
+    int rc = ctx->blockoff.ensure(sizeof(int64_t) * 2 * (size_t)(2 + nbmax + n_edges + 1));
     if (!rc) rc = ctx->insts.ensure(sizeof(InstRec) * (size_t)n_insts);
     const size_t stride = (sizeof(InstRec) * (size_t)n_insts + 255) / 256 * 256;
     if (!rc) rc = ctx->h_inst.ensure(stride * (size_t)n_levels);

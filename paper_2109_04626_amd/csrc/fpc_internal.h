@@ -62,6 +62,11 @@ struct fpc_ctx {
     // the first level's results copied back; the mixed form's FP32 matrix
     // and its error measure done (queued after the first level)
     hipEvent_t ev_first = nullptr, ev_c32 = nullptr;
+    // second stream of a level's window: the size classes after the first
+    // run on it, beside the first class (fork after the first plan, join
+    // before the window's FP64 re-run)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     static constexpr int kLaunchEvents = 256;
     hipEvent_t lev[2 * kLaunchEvents] = {};  // per-launch timing of the test kernels
     // timing events of the small levels queued back to back on one graph
@@ -258,7 +263,7 @@ struct LevelLaunch {
 };
 struct LevelTiming {
     float all_ms = 0.f;       // first test launch to last recheck, one event pair
-    float test_ms = 0.f;      // sum of the test-kernel launches alone
+    float test_ms = 0.f;      // test-kernel launches alone: the union of their intervals
     int test_launches = 0;
     int n_events = 0;         // timed launches (event pairs)
     bool graph = false;       // the level ran as one captured graph

@@ -231,7 +231,10 @@ extern "C" int fpc_create(fpc_ctx **out, int hip_device, void *hip_stream)
     }
     if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_first, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->ev_c32, hipEventDisableTiming)) != hipSuccess) {
+        (e = hipEventCreateWithFlags(&c->ev_c32, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking)) != hipSuccess) {
         fpc_destroy(c);
         return hip_fail(e, "hipEventCreate");
     }
@@ -283,6 +286,7 @@ extern "C" int fpc_destroy(fpc_ctx *c)
     if (!c) return FPC_EINVAL;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->aux) (void)hipStreamSynchronize(c->aux);
     DevBuf *bufs[] = {&c->binom, &c->binomT, &c->x_copy, &c->colstat, &c->c64, &c->c32, &c->zsplit, &c->inv_work,
                       &c->flag, &c->cand, &c->edges, &c->blockoff, &c->minhit, &c->counters,
                       &c->queue, &c->dellist, &c->batch_tmp, &c->mlp_grad, &c->rfirst, &c->feat,
@@ -301,6 +305,9 @@ extern "C" int fpc_destroy(fpc_ctx *c)
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev_first) (void)hipEventDestroy(c->ev_first);
     if (c->ev_c32) (void)hipEventDestroy(c->ev_c32);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return FPC_OK;

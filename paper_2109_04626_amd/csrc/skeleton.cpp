@@ -395,6 +395,13 @@ void parallel_for(int n, F &&fn)
     host_parallel(n, std::function<void(int)>(fn));
 }
 
+// The learned order can only save tests of edges deleted at a level, and
+// its passes (features, scores, reorder) cost about as much as a few dozen
+// tests per candidate; a level with fewer possible tests per candidate than
+// this (l <= 2 on the benchmark graphs) keeps the lexicographic order.  The
+// skeleton does not depend on the order.
+constexpr int64_t kLearnedMinTestsPerCand = 32;
+
 // One level of one or more instances, each on its frozen graph with
 // precomputed candidate sets, from its planning to its results: planned
 // (eligible edges and test counts), built (records and lists in pinned
@@ -601,12 +608,6 @@ int job_upload(const std::vector<Run *> &runs, const std::vector<const CandSets 
     // (at l = 0 each edge has one subset, so the order cannot matter)
     Run &R0 = *runs[0];
     J.d_cand = reinterpret_cast<const int32_t *>(ctx->edges.as<EdgeRec>() + E);
-    // The learned order can only save tests of edges deleted at this level,
-    // and its passes (features, scores, reorder) cost about as much as a
-    // few dozen tests per candidate; a level with fewer possible tests per
-    // candidate than that (l <= 2 on the benchmark graphs) keeps the
-    // lexicographic order.  The skeleton does not depend on the order.
-    constexpr int64_t kLearnedMinTestsPerCand = 32;
     J.reorder = ni == 1 && R0.learned && l >= 1 && J.sts[0].tests_possible >= kLearnedMinTestsPerCand * T;
     J.logging = ni == 1 && R0.logging;
     if (J.reorder || J.logging) {
@@ -867,19 +868,20 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     return FPC_OK;
 }
 
-// Small levels l_top, l_top - 1, ... of one instance on one unchanged graph,
-// queued back to back with one wait for all of them.  Level l - 1 runs on
-// the graph that level l leaves, so its results hold only if level l
-// deleted nothing: the levels are taken in order up to and including the
-// first one that deletes an edge, and the rest are dropped (their tests
-// counted nowhere).  A level whose recheck queue overflowed is dropped with
-// those after it, for the caller to run on its own.
+// Up to max_len small levels l_top, l_top - 1, ... of one instance on one
+// unchanged graph, queued back to back with one wait for all of them.
+// Level l - 1 runs on the graph that level l leaves, so its results hold
+// only if level l deleted nothing: the levels are taken in order up to and
+// including the first one that deletes an edge, and the rest are dropped
+// (their tests counted nowhere).  A level whose recheck queue overflowed is
+// dropped with those after it, for the caller to run on its own.
 //
-// *n_taken = 0: not queued (fewer than two small levels); else the levels
-// taken are appended to out, *next_l is the level to run next and *changed
-// whether the graph changed.
-int run_chain(Run &R, int l_top, const CandSets &cs, std::vector<fpc_level_stats> &out, int *n_taken, int *next_l,
-              bool *changed)
+// *n_queued = 0: level l_top is not a small level (or the call takes one
+// level at a time), nothing was queued; *n_taken = 0: nothing taken.  Else
+// the levels taken are appended to out, *next_l is the level to run next and
+// *changed whether the graph changed.
+int run_chain(Run &R, int l_top, const CandSets &cs, int max_len, std::vector<fpc_level_stats> &out,
+              int *n_queued, int *n_taken, int *next_l, bool *changed)
 {
     // a level with at most this many possible tests takes at most a few
     // dozen microseconds on the device, less than a host round trip
@@ -888,25 +890,27 @@ int run_chain(Run &R, int l_top, const CandSets &cs, std::vector<fpc_level_stats
     hipStream_t s = ctx->stream;
     const std::vector<Run *> runs{&R};
     const std::vector<const CandSets *> css{&cs};
-    *n_taken = 0;
+    *n_taken = *n_queued = 0;
     const double t_start = now_ms();
     std::vector<LevelJob> jobs;
     jobs.reserve(fpc_ctx::kChainSlots);
-    // the budget, the stop after a number of levels, the learned order,
-    // feature logging and captured levels take one level at a time
+    // the budget, the stop after a number of levels, feature logging and
+    // captured levels take one level at a time, and so does a level that the
+    // learned order reorders (the same test as in job_upload)
     const fpc_params *P = R.P;
-    if (P->max_tests > 0 || P->stop_after_levels > 0 || R.learned || R.logging || (P->flags & FPC_FLAG_GRAPH))
-        return FPC_OK;
+    if (P->max_tests > 0 || P->stop_after_levels > 0 || R.logging || (P->flags & FPC_FLAG_GRAPH)) return FPC_OK;
     int64_t total = 0;
-    for (int l = l_top; l >= 0 && (int)jobs.size() < fpc_ctx::kChainSlots; --l) {
+    for (int l = l_top; l >= 0 && (int)jobs.size() < std::min(max_len, fpc_ctx::kChainSlots); --l) {
         LevelJob J;
         J.t0 = now_ms();
         if (job_plan(runs, l, css, J) != FPC_OK || J.E == 0) break;  // such a level runs on its own
+        if (R.learned && l >= 1 && J.sts[0].tests_possible >= kLearnedMinTestsPerCand * J.T) break;
         total += J.sts[0].tests_possible;
         if (total > kChainMaxTests) break;
         jobs.push_back(std::move(J));
     }
-    if (jobs.size() < 2) return FPC_OK;
+    if (jobs.empty()) return FPC_OK;
+    *n_queued = (int)jobs.size();
     int rc;
     if (!ctx->chain_ev_ready) {
         for (auto &slot : ctx->chain_ev)
@@ -1459,6 +1463,7 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
             if (cap >= 0) l = std::min(l, cap);
         }
         bool cs_valid = false;  // the graph is unchanged since cs was computed
+        int chain_len = fpc_ctx::kChainSlots;  // small levels queued at once
         while (l >= 0) {
             const double tc = now_ms();
             if (!cs_valid) candidate_sets(R.adj.data(), p, cs);
@@ -1474,17 +1479,19 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
             }
             if ((rc = c32_finish(R, &corr_ms))) return rc;
             std::vector<fpc_level_stats> lv;
-            int taken = 0, next_l = l;
+            int queued = 0, taken = 0, next_l = l;
             bool changed = false;
-            // after a level that deleted nothing, the levels below it on the
-            // same graph are queued back to back (deletions tend to come in
-            // runs of levels: after one, the next level runs on its own)
-            if (cs_valid && (rc = run_chain(R, l, cs, lv, &taken, &next_l, &changed))) return rc;
+            if ((rc = run_chain(R, l, cs, chain_len, lv, &queued, &taken, &next_l, &changed))) return rc;
             if (taken > 0) {  // small levels queued back to back
                 R.levels.insert(R.levels.end(), lv.begin(), lv.end());
                 levels_run += taken;
                 cs_valid = !changed;
                 l = next_l;
+                // the run length follows the small levels' deletions: a run
+                // cut by a deletion at its k-th level is k long next time
+                // (1: one level at a time), one taken whole is twice as long
+                if (changed) chain_len = taken;
+                else if (taken == queued) chain_len = std::min(2 * chain_len, (int)fpc_ctx::kChainSlots);
                 continue;
             }
             if ((rc = run_level(one_run, l, one_cs, lv))) return rc;

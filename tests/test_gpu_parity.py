@@ -329,11 +329,11 @@ def test_skeleton_graph_mode_matches_eager(fpc, ctx, prec):
                                                  (40, 800, 6.0, -1, 11, 1), (90, 3000, 5.0, 6, 41, 1),
                                                  (90, 3000, 5.0, 6, 11, 1)])
 def test_skeleton_small_levels_back_to_back(fpc, ctx, p, n, deg, L, seed, prec):
-    """After a level that deletes nothing, the small levels below it are
-    queued back to back and kept up to the first one that deletes an edge; a
-    test budget makes every level run on its own.  Both runs give the
-    oracle's sequence of levels (level, deletions, tests required), skeleton
-    and separating sets."""
+    """Small levels are queued back to back (up to eight, fewer after a run
+    cut short by a deletion) and kept up to the first one that deletes an
+    edge; a test budget makes every level run on its own.  Both runs give
+    the oracle's sequence of levels (level, deletions, tests required),
+    skeleton and separating sets."""
     _say(f"[small levels] p={p} n={n} deg={deg} L={L} seed={seed} prec={prec}")
     sem = semdata.make_sem(p, seed, degree=deg)
     X = semdata.sample(sem, n, seed)

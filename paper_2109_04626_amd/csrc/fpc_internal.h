@@ -389,6 +389,9 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads = 0);
 // when the pool is busy or when called from inside a job).
 void host_parallel(int n, const std::function<void(int)> &fn);
 int host_threads();
+// Wakes the sleeping host threads for another spin: called before a device
+// wait whose end is followed by host-parallel work.
+void host_wake();
 
 // ---- quantile (quantile.cpp)
 double normal_quantile_upper(double alpha);  // Phi^{-1}(1 - alpha/2)

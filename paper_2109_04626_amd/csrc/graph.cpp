@@ -55,50 +55,118 @@ void scan_rows(const uint8_t *adj, int p, int u0, int u1, std::vector<int32_t> &
 // thread so that repeated calls reuse their memory.
 struct Scratch {
     Adjacency g;
-    std::vector<std::vector<int32_t>> pu, pv, parts;
+    std::vector<std::vector<int32_t>> parts;
     std::vector<std::vector<int64_t>> lens;
     std::vector<int32_t> block, nbblk, deg, fill, disc, low, estack;
 };
 
-void build_adjacency(const uint8_t *adj, int p, Adjacency &g, int nth, Scratch &sc)
+// Nonzero bytes of row[a, b).
+int count_nonzero(const uint8_t *row, int a, int b)
 {
-    // one pass over the upper triangle: edge ids in row-major (u < v) order;
-    // for large p, blocks of rows (of about equal upper-triangle size) on
-    // separate host threads, concatenated in row order
-    g.eu.clear();
-    g.ev.clear();
-    if (nth <= 1 || p < 512) {
-        scan_rows(adj, p, 0, p, g.eu, g.ev);
-    } else {
-        std::vector<int> r0(nth + 1, p);
-        r0[0] = 0;
-        const double tri = 0.5 * (double)p * (p - 1);
-        int b = 1;
-        double acc = 0.0;
-        for (int u = 0; u < p && b < nth; ++u) {
-            acc += p - 1 - u;
-            if (acc >= tri * b / nth) r0[b++] = u + 1;
-        }
-        auto &pu = sc.pu, &pv = sc.pv;
-        if ((int)pu.size() < nth) {
-            pu.resize(nth);
-            pv.resize(nth);
-        }
-        host_parallel(nth, [&](int t) {
-            pu[t].clear();
-            pv[t].clear();
-            scan_rows(adj, p, r0[t], r0[t + 1], pu[t], pv[t]);
-        });
-        size_t tot = 0;
-        for (int t = 0; t < nth; ++t) tot += pu[t].size();
-        g.eu.reserve(tot);
-        g.ev.reserve(tot);
-        for (int t = 0; t < nth; ++t) {
-            g.eu.insert(g.eu.end(), pu[t].begin(), pu[t].end());
-            g.ev.insert(g.ev.end(), pv[t].begin(), pv[t].end());
+    constexpr uint64_t lo7 = 0x7f7f7f7f7f7f7f7full;
+    int n = 0, v = a;
+    for (; v + 8 <= b; v += 8) {
+        uint64_t word;
+        std::memcpy(&word, row + v, 8);
+        n += __builtin_popcountll((((word & lo7) + lo7) | word) & ~lo7);
+    }
+    for (; v < b; ++v) n += row[v] != 0;
+    return n;
+}
+
+// Calls fn(v) for the nonzero bytes of row[0, p) in increasing v.
+template <class F>
+void for_nonzero(const uint8_t *row, int p, F &&fn)
+{
+    constexpr uint64_t lo7 = 0x7f7f7f7f7f7f7f7full;
+    int v = 0;
+    for (; v + 8 <= p; v += 8) {
+        uint64_t word;
+        std::memcpy(&word, row + v, 8);
+        uint64_t nz = (((word & lo7) + lo7) | word) & ~lo7;
+        while (nz) {
+            fn(v + (__builtin_ctzll(nz) >> 3));
+            nz &= nz - 1;
         }
     }
+    for (; v < p; ++v)
+        if (row[v]) fn(v);
+}
+
+void build_adjacency(const uint8_t *adj, int p, Adjacency &g, int nth, Scratch &sc)
+{
+    // edge ids in row-major (u < v) order; every neighbour list sorted
+    g.eu.clear();
+    g.ev.clear();
     std::vector<int32_t> &deg = sc.deg;
+    if (nth > 1 && p >= 512) {
+        // blocks of rows on the host threads, three passes with no scatter:
+        // the neighbour counts of each row (all, and above the diagonal);
+        // each row's sorted list, with the ids of its edges to larger
+        // neighbours; the id of each slot of a smaller neighbour u, found
+        // by a binary search in u's list of larger neighbours
+        std::vector<int32_t> &up = sc.fill;
+        deg.assign(p, 0);
+        up.assign(p, 0);
+        const int nblk = std::min(p, 4 * nth);
+        const auto rows = [&](int b, int &u0, int &u1) {
+            u0 = (int)((int64_t)p * b / nblk);
+            u1 = (int)((int64_t)p * (b + 1) / nblk);
+        };
+        host_parallel(nblk, [&](int b) {
+            int u0, u1;
+            rows(b, u0, u1);
+            for (int u = u0; u < u1; ++u) {
+                const uint8_t *row = adj + (size_t)u * p;
+                up[u] = count_nonzero(row, u + 1, p);
+                deg[u] = count_nonzero(row, 0, u) + up[u];
+            }
+        });
+        std::vector<int32_t> upoff(p + 1, 0);
+        g.off.assign(p + 1, 0);
+        for (int u = 0; u < p; ++u) {
+            g.off[u + 1] = g.off[u] + deg[u];
+            upoff[u + 1] = upoff[u] + up[u];
+        }
+        const int E = upoff[p];
+        g.nb.resize(g.off[p]);
+        g.eid.resize(g.off[p]);
+        g.eu.resize(E);
+        g.ev.resize(E);
+        host_parallel(nblk, [&](int b) {
+            int u0, u1;
+            rows(b, u0, u1);
+            for (int u = u0; u < u1; ++u) {
+                int k = g.off[u], id = upoff[u];
+                for_nonzero(adj + (size_t)u * p, p, [&](int v) {
+                    if (v == u) return;
+                    g.nb[k] = v;
+                    if (v > u) {
+                        g.eid[k] = id;
+                        g.eu[id] = u;
+                        g.ev[id] = v;
+                        ++id;
+                    }
+                    ++k;
+                });
+            }
+        });
+        host_parallel(nblk, [&](int b) {
+            int v0, v1;
+            rows(b, v0, v1);
+            for (int v = v0; v < v1; ++v) {
+                const int lo_n = deg[v] - up[v];
+                for (int k = g.off[v]; k < g.off[v] + lo_n; ++k) {
+                    const int u = g.nb[k];
+                    const int32_t *a = g.nb.data() + g.off[u + 1] - up[u], *e = g.nb.data() + g.off[u + 1];
+                    g.eid[k] = upoff[u] + (int)(std::lower_bound(a, e, v) - a);
+                }
+            }
+        });
+        return;
+    }
+    // one pass over the upper triangle, then the lists by a scatter
+    scan_rows(adj, p, 0, p, g.eu, g.ev);
     deg.assign(p, 0);
     for (size_t id = 0; id < g.eu.size(); ++id) {
         ++deg[g.eu[id]];

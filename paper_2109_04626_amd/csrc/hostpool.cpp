@@ -7,7 +7,9 @@
 // Between jobs a worker spins on the job counter for a short while before
 // it sleeps, so the back-to-back jobs of one level start without a wake-up;
 // the caller takes items too and returns once every item is done and no
-// worker still holds the job, without waiting for sleeping workers.
+// worker still holds the job, without waiting for sleeping workers.  A
+// caller about to need the pool after a device wait wakes the sleepers
+// beforehand (wake), so that they spin when the job comes.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -76,6 +78,17 @@ class HostPool {
             cpu_relax();
     }
 
+    // Sleeping workers start another spin (no job).
+    void wake()
+    {
+        if (sleepers_.load(std::memory_order_acquire) == 0) return;
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            wake_.fetch_add(1, std::memory_order_relaxed);
+        }
+        cv_.notify_all();
+    }
+
   private:
     struct Job {
         const std::function<void(int)> *fn = nullptr;
@@ -106,7 +119,10 @@ class HostPool {
                     if ((++spins & 255) == 0 && clk::now() - t0 > std::chrono::microseconds(kSpinUs)) {
                         std::unique_lock<std::mutex> lk(m_);
                         sleepers_.fetch_add(1, std::memory_order_acq_rel);
-                        cv_.wait(lk, [&] { return stop_.load() || gen_.load() != seen; });
+                        const uint64_t w0 = wake_.load(std::memory_order_relaxed);
+                        cv_.wait(lk, [&] {
+                            return stop_.load() || gen_.load() != seen || wake_.load(std::memory_order_relaxed) != w0;
+                        });
                         sleepers_.fetch_sub(1, std::memory_order_acq_rel);
                         break;
                     }
@@ -128,12 +144,12 @@ class HostPool {
         }
     }
 
-    static constexpr int kSpinUs = 500;  // spin this long after a job before sleeping
+    static constexpr int kSpinUs = 1000;  // spin this long after a job (or a wake) before sleeping
     std::vector<std::thread> workers_;
     std::mutex m_, job_m_;
     std::condition_variable cv_;
     Job jobs_[2];
-    std::atomic<uint64_t> gen_{0};
+    std::atomic<uint64_t> gen_{0}, wake_{0};
     std::atomic<int> sleepers_{0};
     std::atomic<bool> stop_{false};
     static thread_local bool in_job_;
@@ -152,5 +168,7 @@ HostPool &pool()
 void host_parallel(int n, const std::function<void(int)> &fn) { pool().run(n, fn); }
 
 int host_threads() { return pool().size(); }
+
+void host_wake() { pool().wake(); }
 
 }  // namespace fpc

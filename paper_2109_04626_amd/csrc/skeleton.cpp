@@ -844,6 +844,11 @@ int run_level(const std::vector<Run *> &runs, int l, const std::vector<const Can
     if ((rc = job_upload(runs, css, J))) return rc;
     for (;;) {
         if ((rc = job_launch(runs, J))) return rc;
+        // the deletions are decoded on the host threads: wake them when the
+        // level's last launch starts (the start event of the last timed
+        // launch), so that they are spinning when the level ends
+        if (J.tm.n_events >= 2) FPC_HIP(hipEventSynchronize(J.tm.lev[2 * (J.tm.n_events - 1)]));
+        host_wake();
         FPC_HIP(hipStreamSynchronize(s));  // the one wait of the level
         J.t_tests1 = now_ms();
         if ((rc = level_timing(ctx, &J.tm))) return rc;
@@ -953,6 +958,7 @@ int run_chain(Run &R, int l_top, const CandSets &cs, int max_len, std::vector<fp
         if ((rc = job_upload(runs, css, J))) return rc;
         if ((rc = job_launch(runs, J))) return rc;
     }
+    host_wake();  // for the decoding and the result that follow
     FPC_HIP(hipStreamSynchronize(s));  // the one wait of the chained levels
     const double t_done = now_ms();
     if (trace_on())
@@ -1160,6 +1166,7 @@ int first_stage(Run &R, double *ms)
         FPC_HIP(hipEventRecord(ctx->ev_c32, s));
     }
     const double tq = now_ms();
+    host_wake();  // the candidate sets follow on the host threads
     FPC_HIP(hipEventSynchronize(ctx->ev_first));
     const double tw = now_ms();
     if (*h_bad) return FPC_ESINGULAR;

@@ -82,6 +82,25 @@ def test_candidate_sets_take_any_nonzero_entry_as_an_edge():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("p,dens", [(777, 0.008), (1003, 0.004)])
+def test_candidate_sets_of_large_graphs(p, dens):
+    """Graphs of 512 nodes or more take the row-parallel adjacency build:
+    edge order as numpy lists it, any nonzero byte an edge, and sampled sets
+    equal to the oracle's breadth-first search."""
+    import paper_2109_04626_amd as fpc
+
+    rng = np.random.default_rng(p)
+    adj = _random_graph(rng, p, dens)
+    w = np.triu(rng.choice(np.array([1, 2, 3, 128, 255], np.uint8), size=(p, p)), 1)
+    heavy = (adj * (w + w.T)).astype(np.uint8)
+    ei, ej, off, nodes = fpc.fpc_candidates(heavy)
+    iu, ju = np.nonzero(np.triu(adj, 1))
+    assert np.array_equal(ei, iu) and np.array_equal(ej, ju)
+    for e in rng.choice(len(ei), size=min(150, len(ei)), replace=False):
+        got = nodes[off[e]:off[e + 1]].tolist()
+        assert got == oracle.candidates(adj, int(ei[e]), int(ej[e])), (e, ei[e], ej[e])
+
+
 def test_candidate_sets_on_complete_and_empty_graphs():
     import paper_2109_04626_amd as fpc
 

@@ -360,6 +360,61 @@ namespace {
 // is run again in the mixed form; past that the level runs in FP64.  The
 // grown size stays with the context.
 
+class ResultPrefetch;
+
+// The per-pair arrays of a result (adjacency, set level, set kind, node
+// offset), the set nodes and the pairs of the lists; freed unless handed
+// over.
+struct PairArrays {
+    uint8_t *adj = nullptr;
+    int32_t *sep_level = nullptr;
+    int8_t *sep_kind = nullptr;
+    int64_t *sep_off = nullptr;
+    int32_t *sep_nodes = nullptr;
+    int64_t *list_pairs = nullptr;
+    int64_t n_lists = 0;
+    PairArrays() = default;
+    PairArrays(const PairArrays &) = delete;
+    PairArrays &operator=(const PairArrays &) = delete;
+    PairArrays(PairArrays &&o) noexcept { *this = std::move(o); }
+    PairArrays &operator=(PairArrays &&o) noexcept
+    {
+        if (this != &o) {
+            release();
+            adj = o.adj;
+            sep_level = o.sep_level;
+            sep_kind = o.sep_kind;
+            sep_off = o.sep_off;
+            sep_nodes = o.sep_nodes;
+            list_pairs = o.list_pairs;
+            n_lists = o.n_lists;
+            o.adj = nullptr;
+            o.sep_level = nullptr;
+            o.sep_kind = nullptr;
+            o.sep_off = nullptr;
+            o.sep_nodes = nullptr;
+            o.list_pairs = nullptr;
+        }
+        return *this;
+    }
+    ~PairArrays() { release(); }
+    void release()
+    {
+        std::free(adj);
+        std::free(sep_level);
+        std::free(sep_kind);
+        std::free(sep_off);
+        std::free(sep_nodes);
+        std::free(list_pairs);
+        adj = nullptr;
+        sep_level = nullptr;
+        sep_kind = nullptr;
+        sep_off = nullptr;
+        sep_nodes = nullptr;
+        list_pairs = nullptr;
+    }
+};
+
 struct Run {
     fpc_ctx *ctx;
     const fpc_params *P;
@@ -386,7 +441,15 @@ struct Run {
     bool c32_pending = false;
     const void *X = nullptr;
     int x_dtype = 0;
+    // the result's per-pair arrays, filled ahead while the device runs the
+    // last levels (valid while ahead_ok: the graph and sets have not changed
+    // since), and the arrays allocated ahead by a helper thread
+    PairArrays ahead;
+    bool ahead_ok = false;
+    ResultPrefetch *prefetch = nullptr;
 };
+
+int fill_pairs(Run &R, ResultPrefetch *pre, PairArrays &A);
 
 // Runs fn(k) for k in [0, n) on the library's host threads.
 template <class F>
@@ -916,6 +979,26 @@ int run_chain(Run &R, int l_top, const CandSets &cs, int max_len, std::vector<fp
     }
     if (jobs.empty()) return FPC_OK;
     *n_queued = (int)jobs.size();
+    // a run down to level 0 that deletes nothing ends the call: the result's
+    // per-pair arrays are filled on a helper thread (with the host threads)
+    // while this thread queues the levels and the device runs them, and kept
+    // if none of the levels deletes an edge (the levels' results are read
+    // only after the helper has finished)
+    const bool ahead = R.prefetch && jobs.back().l == 0;
+    std::thread filler;
+    if (ahead) {
+        try {
+            filler = std::thread([&R] { R.ahead_ok = fill_pairs(R, R.prefetch, R.ahead) == FPC_OK; });
+        } catch (...) {  // no thread: filled before the wait
+        }
+    }
+    struct Joiner {  // every return below waits for the helper
+        std::thread &t;
+        ~Joiner()
+        {
+            if (t.joinable()) t.join();
+        }
+    } joiner{filler};
     int rc;
     if (!ctx->chain_ev_ready) {
         for (auto &slot : ctx->chain_ev)
@@ -959,7 +1042,9 @@ int run_chain(Run &R, int l_top, const CandSets &cs, int max_len, std::vector<fp
         if ((rc = job_launch(runs, J))) return rc;
     }
     host_wake();  // for the decoding and the result that follow
+    if (ahead && !filler.joinable()) R.ahead_ok = fill_pairs(R, R.prefetch, R.ahead) == FPC_OK;
     FPC_HIP(hipStreamSynchronize(s));  // the one wait of the chained levels
+    if (filler.joinable()) filler.join();
     const double t_done = now_ms();
     if (trace_on())
         std::fprintf(stderr, "[fpc] levels %d..%d queued back to back: %.2f ms to the end of the last\n", jobs[0].l,
@@ -984,6 +1069,8 @@ int run_chain(Run &R, int l_top, const CandSets &cs, int max_len, std::vector<fp
             break;
         }
     }
+    // the arrays filled ahead hold only if every level was taken unchanged
+    if (*changed || *n_taken < *n_queued) R.ahead_ok = false;
     return FPC_OK;
 }
 
@@ -1302,35 +1389,34 @@ class ResultPrefetch {
     int64_t *sep_off_ = nullptr;
 };
 
-int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result **out,
-             ResultPrefetch *pre = nullptr)
+// Fills A (its arrays reused if allocated, else those of the prefetch,
+// else new ones) from the run's graph and separating sets: per pair the
+// subset level's set, else the first level's deletion (absent from the
+// graph), else kept; row blocks on the host threads, each writing its
+// pairs' entries and its share of the set nodes.
+int fill_pairs(Run &R, ResultPrefetch *pre, PairArrays &A)
 {
     const int p = R.p;
     const size_t pp = (size_t)p * p;
-    fpc_result *res = (fpc_result *)std::calloc(1, sizeof(fpc_result));
-    if (!res) return FPC_ENOMEM;
     const int64_t PP = (int64_t)p * (p - 1) / 2;
-    res->p = p;
-    res->n_levels = (int32_t)R.levels.size();
-    if (!pre || !pre->take(res->adj, res->sep_level, res->sep_kind, res->sep_off)) {
-        res->adj = (uint8_t *)std::malloc(pp);
-        res->sep_level = (int32_t *)std::malloc(sizeof(int32_t) * PP);
-        res->sep_kind = (int8_t *)std::malloc(PP);
-        res->sep_off = (int64_t *)std::malloc(sizeof(int64_t) * (PP + 1));
+    if (!A.adj) {
+        if (!pre || !pre->take(A.adj, A.sep_level, A.sep_kind, A.sep_off)) {
+            A.adj = (uint8_t *)std::malloc(pp);
+            A.sep_level = (int32_t *)std::malloc(sizeof(int32_t) * PP);
+            A.sep_kind = (int8_t *)std::malloc(PP);
+            A.sep_off = (int64_t *)std::malloc(sizeof(int64_t) * (PP + 1));
+        }
     }
+    std::free(A.sep_nodes);
+    std::free(A.list_pairs);
     const int64_t tot = (int64_t)R.sep.nodes.size();
-    res->sep_nodes = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1));
-    res->n_lists = (int64_t)R.sep.lists.size();
-    res->list_pairs = (int64_t *)std::malloc(sizeof(int64_t) * (size_t)std::max<int64_t>(res->n_lists, 1));
-    res->levels = (fpc_level_stats *)std::malloc(sizeof(fpc_level_stats) * std::max<size_t>(R.levels.size(), 1));
-    if (!res->adj || !res->sep_level || !res->sep_kind || !res->sep_off || !res->sep_nodes || !res->levels ||
-        !res->list_pairs) {
-        fpc_result_free(res);
+    A.sep_nodes = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1));
+    A.n_lists = (int64_t)R.sep.lists.size();
+    A.list_pairs = (int64_t *)std::malloc(sizeof(int64_t) * (size_t)std::max<int64_t>(A.n_lists, 1));
+    if (!A.adj || !A.sep_level || !A.sep_kind || !A.sep_off || !A.sep_nodes || !A.list_pairs) {
+        A.release();
         return FPC_ENOMEM;
     }
-    // per pair: the subset level's set, else the first level's deletion
-    // (absent from the graph), else kept; row blocks on the host threads,
-    // each writing its pairs' entries and its share of the set nodes
     std::sort(R.sep.lists.begin(), R.sep.lists.end(),
               [](const SepList &a, const SepList &b) { return a.pair < b.pair; });
     const int nblk = std::max(1, std::min(p, 16));
@@ -1362,7 +1448,7 @@ int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result
     const bool implicit_first = R.sep.first_level;
     const int first_l = p - 2;
     parallel_for(nblk, [&](int b) {
-        std::memcpy(res->adj + (size_t)row0[b] * p, R.adj.data() + (size_t)row0[b] * p,
+        std::memcpy(A.adj + (size_t)row0[b] * p, R.adj.data() + (size_t)row0[b] * p,
                     (size_t)(row0[b + 1] - row0[b]) * p);
         size_t li = li_lo[b];
         int64_t o = node_lo[b];
@@ -1371,25 +1457,63 @@ int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result
             const int64_t base = first_pair(i) - (i + 1);  // pair (i, j) at base + j
             for (int j = i + 1; j < p; ++j) {
                 const int64_t k = base + j;
-                res->sep_off[k] = o;
+                A.sep_off[k] = o;
                 if (li < li_lo[b + 1] && R.sep.lists[li].pair == k) {
                     const SepList &e = R.sep.lists[li++];
-                    res->sep_level[k] = e.level;
-                    res->sep_kind[k] = FPC_SEP_LIST;
-                    std::memcpy(res->sep_nodes + o, R.sep.nodes.data() + e.off, sizeof(int32_t) * e.level);
+                    A.sep_level[k] = e.level;
+                    A.sep_kind[k] = FPC_SEP_LIST;
+                    std::memcpy(A.sep_nodes + o, R.sep.nodes.data() + e.off, sizeof(int32_t) * e.level);
                     o += e.level;
                 } else if (!arow[j] && implicit_first) {
-                    res->sep_level[k] = first_l;
-                    res->sep_kind[k] = FPC_SEP_ALL_BUT;
+                    A.sep_level[k] = first_l;
+                    A.sep_kind[k] = FPC_SEP_ALL_BUT;
                 } else {
-                    res->sep_level[k] = -1;
-                    res->sep_kind[k] = FPC_SEP_NONE;
+                    A.sep_level[k] = -1;
+                    A.sep_kind[k] = FPC_SEP_NONE;
                 }
             }
         }
     });
-    res->sep_off[PP] = node_lo[nblk];
-    for (size_t t = 0; t < R.sep.lists.size(); ++t) res->list_pairs[t] = R.sep.lists[t].pair;
+    A.sep_off[PP] = node_lo[nblk];
+    for (size_t t = 0; t < R.sep.lists.size(); ++t) A.list_pairs[t] = R.sep.lists[t].pair;
+    return FPC_OK;
+}
+
+int assemble(Run &R, double corr_ms, double first_ms, double t_start, fpc_result **out,
+             ResultPrefetch *pre = nullptr)
+{
+    const int p = R.p;
+    fpc_result *res = (fpc_result *)std::calloc(1, sizeof(fpc_result));
+    if (!res) return FPC_ENOMEM;
+    res->p = p;
+    res->n_levels = (int32_t)R.levels.size();
+    if (!R.ahead_ok) {
+        const int rc = fill_pairs(R, pre, R.ahead);
+        if (rc) {
+            std::free(res);
+            return rc;
+        }
+    }
+    PairArrays A = std::move(R.ahead);
+    R.ahead_ok = false;
+    res->adj = A.adj;
+    res->sep_level = A.sep_level;
+    res->sep_kind = A.sep_kind;
+    res->sep_off = A.sep_off;
+    res->sep_nodes = A.sep_nodes;
+    res->list_pairs = A.list_pairs;
+    res->n_lists = A.n_lists;
+    A.adj = nullptr;
+    A.sep_level = nullptr;
+    A.sep_kind = nullptr;
+    A.sep_off = nullptr;
+    A.sep_nodes = nullptr;
+    A.list_pairs = nullptr;
+    res->levels = (fpc_level_stats *)std::malloc(sizeof(fpc_level_stats) * std::max<size_t>(R.levels.size(), 1));
+    if (!res->levels) {
+        fpc_result_free(res);
+        return FPC_ENOMEM;
+    }
     std::memcpy(res->levels, R.levels.data(), sizeof(fpc_level_stats) * R.levels.size());
     res->total_tests = R.total_exec;
     res->q = R.q;
@@ -1430,6 +1554,7 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
     hipStream_t s = ctx->stream;
     Run R;
     init_run(R, ctx, P, p, n);
+    R.prefetch = &pre;
 
     // data on the device
     const void *X = P->X;

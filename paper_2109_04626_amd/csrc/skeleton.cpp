@@ -480,7 +480,7 @@ struct LevelJob {
         int max_m = 0, sel_m = 0;
         bool bad = false;       // the level's test count overflows
         bool too_long = false;  // a list of kBinomRows candidates or more
-        int64_t r = 0, c = 0;   // first record and list slot (pass 2)
+        int64_t c = 0;          // first list slot (pass 2)
     };
     int l = 0;
     std::vector<Chunk> chunks;
@@ -494,7 +494,7 @@ struct LevelJob {
     size_t stage_off = 0, back_off = 0;
     EdgeRec *hrec = nullptr;
     int32_t *cand = nullptr;  // the lists, in instance order
-    std::vector<EdgeRec> recs;
+    const EdgeRec *recs = nullptr;  // the records as launched (hrec, read back by the host)
     std::vector<int64_t> ntests, cs_edge;  // cs_edge: edge index of each record in its candidate sets
     std::vector<LevelClass> classes;
     std::vector<LevelInst> insts;
@@ -576,7 +576,6 @@ int job_plan(const std::vector<Run *> &runs, int l, const std::vector<const Cand
         st.edges_eligible += ch.n_el;
         if (ch.possible > INT64_MAX - st.tests_possible) return FPC_EBUDGET;
         st.tests_possible += ch.possible;
-        ch.r = J.E;
         ch.c = J.T;
         J.E += ch.n_el;
         J.T += ch.n_cd;
@@ -596,11 +595,13 @@ void job_spend(const std::vector<Run *> &runs, const LevelJob &J)
 }
 
 // Pass 2: records and lists straight into the job's pinned region (J.hrec,
-// J.cand), then the size classes of the candidate lists: each class is
-// launched with the LDS its own largest list needs, so a few long lists do
-// not lower the occupancy (or the kernel choice) of all the others; a
-// stable counting sort of the records by class keeps each instance's edges
-// together.
+// J.cand), the records grouped by the size classes of their candidate
+// lists: each class is launched with the LDS its own largest list needs, so
+// a few long lists do not lower the occupancy (or the kernel choice) of all
+// the others.  The records' places come from per-chunk class counts (a
+// stable counting sort: within a class, the records keep their instance
+// order, so each instance's edges stay together); the lists stay in
+// instance order.
 void job_build(const std::vector<Run *> &runs, const std::vector<const CandSets *> &css, LevelJob &J)
 {
     fpc_ctx *ctx = runs[0]->ctx;
@@ -608,44 +609,55 @@ void job_build(const std::vector<Run *> &runs, const std::vector<const CandSets 
     const int64_t E = J.E;
     EdgeRec *hrec = J.hrec;
     int32_t *cand = J.cand;
-    std::vector<int64_t> cs_edge(E);
-    J.for_chunks([&](int u) {
-        const LevelJob::Chunk &ch = J.chunks[u];
-        const CandSets &cs = *css[ch.k];
-        int64_t r = ch.r, c = ch.c;
-        for (int64_t e = ch.e0; e < ch.e1; ++e) {
-            const int m = (int)(cs.off[e + 1] - cs.off[e]);
-            if (m < l) continue;
-            hrec[r] = EdgeRec{cs.ei[e], cs.ej[e], m, (int32_t)c, binom_sat(m, l), ch.k, 0};
-            cs_edge[r] = e;
-            std::memcpy(cand + c, cs.nodes.data() + cs.off[e], sizeof(int32_t) * m);
-            ++r;
-            c += m;
-        }
-    });
-    J.recs.resize(E);
-    J.ntests.resize(E);
     const bool fp32_cls = runs[0]->mixed && l <= kMaxTemplL;
     std::vector<int> key_of(J.sel_max_m + 1);
     int kmax = 0;
     for (int m = 0; m <= J.sel_max_m; ++m) kmax = std::max(kmax, key_of[m] = level_class_key(ctx, l, fp32_cls, m));
-    std::vector<int64_t> cnt_k(kmax + 2, 0), c2(E);
-    for (int64_t k = 0; k < E; ++k) ++cnt_k[key_of[hrec[k].m] + 1];
-    for (int c = 0; c <= kmax; ++c) cnt_k[c + 1] += cnt_k[c];
-    for (int64_t k = 0; k < E; ++k) {
-        const int64_t d = cnt_k[key_of[hrec[k].m]]++;
-        J.recs[d] = hrec[k];
-        J.ntests[d] = J.recs[d].ntests;
-        c2[d] = cs_edge[k];
+    const int ncls = kmax + 1, nck = (int)J.chunks.size();
+    // first record of each (chunk, class): class-major, chunk-minor prefix
+    std::vector<int64_t> at((size_t)nck * ncls, 0);
+    std::vector<int> cls_max(ncls, 0);
+    for (int u = 0; u < nck; ++u) {
+        const LevelJob::Chunk &ch = J.chunks[u];
+        const CandSets &cs = *css[ch.k];
+        int64_t *a = at.data() + (size_t)u * ncls;
+        for (int64_t e = ch.e0; e < ch.e1; ++e) {
+            const int m = (int)(cs.off[e + 1] - cs.off[e]);
+            if (m < l) continue;
+            ++a[key_of[m]];
+            cls_max[key_of[m]] = std::max(cls_max[key_of[m]], m);
+        }
     }
-    J.cs_edge.swap(c2);
-    std::memcpy(hrec, J.recs.data(), sizeof(EdgeRec) * E);
-    for (int64_t k = 0; k < E; ++k) {
-        const int c = key_of[J.recs[k].m];
-        if (J.classes.empty() || key_of[J.recs[J.classes.back().begin].m] != c) J.classes.push_back({k, k, 0});
-        J.classes.back().end = k + 1;
-        J.classes.back().max_m = std::max(J.classes.back().max_m, J.recs[k].m);
+    int64_t run = 0;
+    for (int c = 0; c < ncls; ++c) {
+        const int64_t begin = run;
+        for (int u = 0; u < nck; ++u) {
+            const int64_t n = at[(size_t)u * ncls + c];
+            at[(size_t)u * ncls + c] = run;
+            run += n;
+        }
+        if (run > begin) J.classes.push_back({begin, run, cls_max[c]});
     }
+    J.ntests.resize(E);
+    J.cs_edge.resize(E);
+    J.for_chunks([&](int u) {
+        const LevelJob::Chunk &ch = J.chunks[u];
+        const CandSets &cs = *css[ch.k];
+        std::vector<int64_t> pos(at.begin() + (size_t)u * ncls, at.begin() + (size_t)(u + 1) * ncls);
+        int64_t c = ch.c;
+        for (int64_t e = ch.e0; e < ch.e1; ++e) {
+            const int m = (int)(cs.off[e + 1] - cs.off[e]);
+            if (m < l) continue;
+            const int64_t d = pos[key_of[m]]++;
+            const int64_t N = binom_sat(m, l);
+            hrec[d] = EdgeRec{cs.ei[e], cs.ej[e], m, (int32_t)c, N, ch.k, 0};
+            J.ntests[d] = N;
+            J.cs_edge[d] = e;
+            std::memcpy(cand + c, cs.nodes.data() + cs.off[e], sizeof(int32_t) * m);
+            c += m;
+        }
+    });
+    J.recs = hrec;
     J.t_build = now_ms();
 }
 
@@ -777,7 +789,7 @@ void job_finish(const std::vector<Run *> &runs, const std::vector<const CandSets
     const int ni = (int)runs.size();
     fpc_ctx *ctx = runs[0]->ctx;
     const int l = J.l;
-    const std::vector<EdgeRec> &recs = J.recs;
+    const EdgeRec *recs = J.recs;
     const int32_t *cand = J.cand;
     const int64_t ndel = (int64_t)J.cnt[2];
     const int64_t *pairs = reinterpret_cast<const int64_t *>(J.cnt + J.n_cnt);

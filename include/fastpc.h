@@ -255,11 +255,13 @@ typedef struct fpc_level_stats {
                                  gaps between them (HIP events on the context stream)   */
     double test_kernel_ms;    /* device time of the test-kernel launches alone: the
                                  union of their intervals (an event pair around each of
-                                 the first 256 launches; the size classes of a window run
-                                 on two streams and overlap)                            */
+                                 the first 256 launches, 8 for small levels queued back
+                                 to back; the size classes of a window run on two
+                                 streams and overlap)                                   */
     int32_t test_launches;    /* test-kernel launches of the level                      */
     int32_t reserved;
-    double level_ms;          /* whole level, host clock                                */
+    double level_ms;          /* whole level, host clock (small levels queued back to
+                                 back: intervals that add up to the run's time)         */
     int64_t tests_required;   /* tests the method needs: per eligible edge, C(|cand|, l)
                                  if kept, else the rank of its first separating set + 1
                                  (independent of launch shapes and scheduling)          */

@@ -315,24 +315,38 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
     };
     int nth = threads > 0 ? threads : host_threads();
     if (E < 256) nth = 1;
+    // chunks of about equal work (an edge costs deg i + deg j: the edges of
+    // a hub are many and long, and sit together in the edge order), four per
+    // thread, taken by the threads as they come free
+    const int nck = nth == 1 ? 1 : std::min(E, 4 * nth);
     auto &parts = sc.parts;
     auto &lens = sc.lens;
-    if ((int)parts.size() < nth) {
-        parts.resize(nth);
-        lens.resize(nth);
+    if ((int)parts.size() < nck) {
+        parts.resize(nck);
+        lens.resize(nck);
     }
-    std::vector<int> bounds(nth + 1);
-    for (int t = 0; t <= nth; ++t) bounds[t] = (int)((int64_t)E * t / nth);
-    if (nth == 1) {
+    std::vector<int> bounds(nck + 1, E);
+    bounds[0] = 0;
+    if (nck > 1) {
+        int64_t total = 0;
+        for (int e = 0; e < E; ++e) total += (g.off[g.eu[e] + 1] - g.off[g.eu[e]]) + (g.off[g.ev[e] + 1] - g.off[g.ev[e]]);
+        int64_t acc = 0;
+        int c = 1;
+        for (int e = 0; e < E && c < nck; ++e) {
+            acc += (g.off[g.eu[e] + 1] - g.off[g.eu[e]]) + (g.off[g.ev[e] + 1] - g.off[g.ev[e]]);
+            while (c < nck && acc * nck >= total * c) bounds[c++] = e + 1;
+        }
+    }
+    if (nck == 1) {
         merge_range(0, E, parts[0], lens[0]);
     } else {
-        host_parallel(nth, [&](int t) { merge_range(bounds[t], bounds[t + 1], parts[t], lens[t]); });
+        host_parallel(nck, [&](int t) { merge_range(bounds[t], bounds[t + 1], parts[t], lens[t]); });
     }
-    std::vector<size_t> at(nth + 1, 0);
-    for (int t = 0; t < nth; ++t) at[t + 1] = at[t] + parts[t].size();
-    out.nodes.resize(at[nth]);
+    std::vector<size_t> at(nck + 1, 0);
+    for (int t = 0; t < nck; ++t) at[t + 1] = at[t] + parts[t].size();
+    out.nodes.resize(at[nck]);
     int e = 0;
-    for (int t = 0; t < nth; ++t)
+    for (int t = 0; t < nck; ++t)
         for (int64_t L : lens[t]) {
             out.off[e + 1] = out.off[e] + L;
             ++e;
@@ -341,8 +355,8 @@ void candidate_sets(const uint8_t *adj, int p, CandSets &out, int threads)
     auto copy_part = [&](int t) {
         std::memcpy(out.nodes.data() + at[t], parts[t].data(), sizeof(int32_t) * parts[t].size());
     };
-    if (nth == 1) copy_part(0);
-    else host_parallel(nth, copy_part);
+    if (nck == 1) copy_part(0);
+    else host_parallel(nck, copy_part);
     if (trace_on())
         std::fprintf(stderr, "[fpc]   candidate sets: adjacency %.3f blocks %.3f merge %.3f concat %.3f ms (%d threads)\n",
                      ms(t0, t1), ms(t1, t2), ms(t2, t3), ms(t3, clk::now()), nth);

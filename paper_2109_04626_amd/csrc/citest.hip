@@ -2326,16 +2326,24 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
     else FPC_HIP(hipEventRecord(ev0, st));
     int nev = 0, nlaunch = 0;
     hipError_t err = hipSuccess;
-    // the size classes of a window test disjoint edges: the first runs on the
-    // main stream and the others on the second, so that their launches (few
-    // long items on the long lists) overlap the first class's launch instead
-    // of following it; a captured level keeps one stream
+    // the size classes of a window test disjoint edges: they are split over
+    // the main stream and a second one, so that their launches (few long
+    // items on the long lists) overlap instead of following one another; a
+    // captured level keeps one stream
     const bool two = !graph && !Lv.diag_r && ctx->aux;
     for (int w = 0; w < max_nw && err == hipSuccess; ++w) {
         // the classes of a window share the recheck queue: the window's first
         // plan empties it and one FP64 re-run after its last launch drains it
         // (before any plan of the next window reads minhit)
         bool window_open = false, forked = false;
+        // the window's launches: range, items (upper bound) and ranks per item
+        struct WinLaunch {
+            const Cls *k;
+            int64_t lo, hi, ub;
+            int rpb;
+            bool aux;
+        };
+        std::vector<WinLaunch> wl;
         for (const Cls &k : cls) {
             if (w + 1 >= (int)k.wins.size()) continue;
             const int64_t lo = k.wins[w], hi = k.wins[w + 1];
@@ -2366,10 +2374,30 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                     ub = n2;
                 }
             }
+            wl.push_back({&k, lo, hi, ub, rpb, false});
+        }
+        // Two streams: the class with the most ranks (upper bound) leads on
+        // the context's stream; each other class, in decreasing ranks, goes
+        // to the stream with fewer ranks so far (longest first).
+        if (two && wl.size() > 1) {
+            std::stable_sort(wl.begin(), wl.end(), [](const WinLaunch &x, const WinLaunch &y) {
+                return (double)x.ub * x.rpb > (double)y.ub * y.rpb;
+            });
+            double on_main = (double)wl[0].ub * wl[0].rpb, on_aux = 0.0;
+            for (size_t i = 1; i < wl.size(); ++i) {
+                const double r = (double)wl[i].ub * wl[i].rpb;
+                wl[i].aux = on_aux <= on_main;
+                (wl[i].aux ? on_aux : on_main) += r;
+            }
+        }
+        for (const WinLaunch &wn : wl) {
+            const Cls &k = *wn.k;
+            const int64_t lo = wn.lo, hi = wn.hi, ub = wn.ub;
+            const int rpb = wn.rpb;
             const int64_t Ek = k.end - k.begin, nb = (Ek + kPlanChunk - 1) / kPlanChunk;
-            // a later class of the window: on the second stream, after the
-            // first class's plan (which empties the recheck queue)
-            const bool on_aux = two && window_open;
+            // on the second stream: after the first class's plan (which
+            // empties the recheck queue)
+            const bool on_aux = wn.aux;
             if (on_aux && !forked) {
                 err = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0);
                 if (err != hipSuccess) break;
@@ -2410,7 +2438,7 @@ int level_tests(fpc_ctx *ctx, const LevelLaunch &Lv, const std::vector<int64_t> 
                 plan_sums<<<1, 256, 0, ls>>>(P, (int)nb);
                 plan_scan<<<(unsigned)nb, 256, 0, ls>>>(P);
             }
-            if (two && !on_aux) {  // the point the window's other classes start from
+            if (two && &wn == &wl[0]) {  // the point the window's other classes start from
                 err = hipEventRecord(ctx->ev_fork, st);
                 if (err != hipSuccess) break;
             }

@@ -38,9 +38,9 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32
 # calibration (fetch x2.000, write x1.000).  Valid only for the kernel source
 # and launch table they were taken with: any change to either makes the
 # figure null until the counters are taken again.
-MEASURED_TRAFFIC = {"bytes_per_launch": 10111669.0,
+MEASURED_TRAFFIC = {"bytes_per_launch": 10110728.0,
                     "sha256": {"paper_2109_04626_amd/csrc/citest.hip":
-                               "0fc9f52f41c1f32f80d68b3b648a6c74ecd79a87deaf0c7ceb632940d7777811",
+                               "25b8ca328450813494936bfbe841142e20cf2a652dccc728506c3791b58be89b",
                                "paper_2109_04626_amd/tuning_gfx950.json":
                                "9b5ee9cd8fc56c7307853a22b4732f84004d394956b92179119b5f35944c27e9"}}
 

@@ -81,6 +81,7 @@ struct fpc_ctx {
     // reads C(a, b) for 64 consecutive a in one coalesced load
     fpc::DevBuf binomT;
     std::vector<int64_t> binom_host;
+    std::vector<int64_t> binomT_host;  // the column-major copy on the host (separating sets' unranking)
 
     // correlation / first level
     fpc::DevBuf x_copy;           // X uploaded from host

@@ -131,22 +131,31 @@ inline int64_t pair_index(int i, int j, int p)
 }
 
 // Lexicographic unranking of rank R among the l-subsets of m positions
-// (tab: kBinomRows x kBinomCols saturating table; C(a,b) = C(a,a-b)).
-void unrank_host(int64_t R, int m, int l, const std::vector<int64_t> &tab, std::vector<int> &out)
+// (tabT: the saturating binomial table column-major, C(a, b) at
+// b * kBinomRows + a for b < kBinomCols; R < C(m, l)).
+void unrank_host(int64_t R, int m, int l, const std::vector<int64_t> &tabT, std::vector<int> &out)
 {
     out.resize(l);
     int x = 0;
-    auto C = [&](int a, int b) -> int64_t {
-        if (b < 0 || b > a) return 0;
-        const int bb = std::min(b, a - b);
-        return bb < kBinomCols ? tab[(size_t)a * kBinomCols + bb] : binom_sat(a, b);
-    };
     for (int t = 0; t < l; ++t) {
-        for (;;) {
-            const int64_t cnt = C(m - 1 - x, l - 1 - t);
-            if (R < cnt) break;
-            R -= cnt;
-            ++x;
+        // skip the subsets whose element t comes before x: C(m-1-x, l-1-t)
+        // of them per position, read down one column of the table
+        const int k = l - 1 - t;
+        if (k < kBinomCols) {
+            const int64_t *col = tabT.data() + (size_t)k * kBinomRows;
+            for (;;) {
+                const int64_t cnt = col[m - 1 - x];
+                if (R < cnt) break;
+                R -= cnt;
+                ++x;
+            }
+        } else {
+            for (;;) {
+                const int64_t cnt = binom_sat(m - 1 - x, k);
+                if (R < cnt) break;
+                R -= cnt;
+                ++x;
+            }
         }
         out[t] = x++;
     }
@@ -259,7 +268,8 @@ extern "C" int fpc_create(fpc_ctx **out, int hip_device, void *hip_stream)
         return hip_fail(e, "hipMemcpy");
     }
     {
-        std::vector<int64_t> t((size_t)kBinomRows * kBinomCols);
+        std::vector<int64_t> &t = c->binomT_host;
+        t.resize((size_t)kBinomRows * kBinomCols);
         for (int a = 0; a < kBinomRows; ++a)
             for (int b = 0; b < kBinomCols; ++b)
                 t[(size_t)b * kBinomRows + a] = c->binom_host[(size_t)a * kBinomCols + b];
@@ -844,7 +854,7 @@ void job_finish(const std::vector<Run *> &runs, const std::vector<const CandSets
         for (int64_t t = dchunks[c].second; t < t1; ++t) {
             const auto &d = dl[t];
             const EdgeRec &er = recs[d.first];
-            unrank_host(d.second, er.m, l, ctx->binom_host, pos);
+            unrank_host(d.second, er.m, l, ctx->binomT_host, pos);
             const int64_t pr = pair_index(er.i, er.j, R.p);
             const size_t o = o0[k] + (size_t)(t - d_lo[k]) * l;
             R.sep.lists[li0[k] + (size_t)(t - d_lo[k])] = {pr, (int64_t)o, l};

@@ -676,6 +676,14 @@ static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 }  // namespace
 
+int first_level_reserve(fpc_ctx *ctx, int p)
+{
+    const size_t pp = (size_t)p * p;
+    int rc = ctx->inv_work.ensure(sizeof(double) * (2 * pp + kPanelWork));
+    if (!rc) rc = ctx->flag.ensure(64);
+    return rc;
+}
+
 int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
                         uint8_t *indep_out, const int **d_bad)
 {

@@ -161,6 +161,9 @@ int first_level(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r
 // *d_bad (device int) becomes nonzero if C is not positive definite.
 int first_level_enqueue(fpc_ctx *ctx, const double *C, int p, int n, double q, double *r_out,
                         uint8_t *indep_out, const int **d_bad);
+// Sizes first_level_enqueue's workspace for p (no buffer then grows for a
+// p' <= p while queued work reads it).
+int first_level_reserve(fpc_ctx *ctx, int p);
 // Many instances at once: each instance's matrix C (FP64, p x p), two p x p
 // sweep buffers, a panel workspace of seven 32 x 32 blocks (contiguous), its
 // flag and counter, and its adjacency bytes (written: 1 = kept).

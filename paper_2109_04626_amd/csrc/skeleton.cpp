@@ -1240,6 +1240,45 @@ int c32_finish(Run &R, double *corr_ms)
 }
 
 // The l = p - 2 level on the complete graph, through Omega = C^{-1}.
+// The graph after the first level from its decisions (ind, p x p bytes, 1 =
+// independent): adj = not independent, off the diagonal; the decision
+// matrix is symmetric, so the deleted pairs are half its ones.
+void first_marks(Run &R, const uint8_t *ind, fpc_level_stats &st)
+{
+    const int p = R.p;
+    const size_t pp = (size_t)p * p;
+    const int nblk = std::min(p, 16);
+    std::vector<int64_t> dels(nblk, 0);
+    parallel_for(nblk, [&](int b) {
+        const size_t k0 = pp * (size_t)b / nblk, k1 = pp * (size_t)(b + 1) / nblk;
+        const uint8_t *__restrict__ src = ind;
+        uint8_t *__restrict__ dst = R.adj.data();
+        int64_t ones = 0;
+        for (size_t k = k0; k < k1; ++k) {
+            dst[k] = (uint8_t)(src[k] ^ 1u);
+            ones += src[k];
+        }
+        dels[b] = ones;
+    });
+    for (int i = 0; i < p; ++i) R.adj[(size_t)i * p + i] = 0;
+    R.sep.first_level = true;
+    st.deleted = 0;
+    for (int64_t d : dels) st.deleted += d;
+    st.deleted /= 2;
+    R.total_exec += st.tests_executed;
+    R.spent_possible += st.tests_possible;
+}
+
+// Statistics of a first level (l = p - 2) before its decisions are read.
+fpc_level_stats first_level_stats(int p)
+{
+    fpc_level_stats st{};
+    st.level = p - 2;
+    st.max_cand = p - 2;
+    st.edges_eligible = st.tests_possible = st.tests_executed = st.tests_required = (int64_t)p * (p - 1) / 2;
+    return st;
+}
+
 int first_stage(Run &R, double *ms)
 {
     fpc_ctx *ctx = R.ctx;
@@ -1247,10 +1286,7 @@ int first_stage(Run &R, double *ms)
     const int p = R.p;
     const size_t pp = (size_t)p * p;
     const double t0 = now_ms();
-    fpc_level_stats st{};
-    st.level = p - 2;
-    st.max_cand = p - 2;
-    st.edges_eligible = st.tests_possible = st.tests_executed = st.tests_required = (int64_t)p * (p - 1) / 2;
+    fpc_level_stats st = first_level_stats(p);
     int rc;
     if ((rc = ctx->flag.ensure(64))) return rc;
     if ((rc = ctx->dellist.ensure(pp))) return rc;
@@ -1288,28 +1324,7 @@ int first_stage(Run &R, double *ms)
     float kms = 0.f;
     FPC_HIP(hipEventElapsedTime(&kms, ctx->ev0, ctx->ev1));
     st.kernel_ms = kms;
-    // the graph after the level: adj = not independent, off the diagonal;
-    // the decision matrix is symmetric, so the deleted pairs are half its ones
-    const int nblk = std::min(p, 16);
-    std::vector<int64_t> dels(nblk, 0);
-    parallel_for(nblk, [&](int b) {
-        const size_t k0 = pp * (size_t)b / nblk, k1 = pp * (size_t)(b + 1) / nblk;
-        const uint8_t *__restrict__ src = ind;
-        uint8_t *__restrict__ dst = R.adj.data();
-        int64_t ones = 0;
-        for (size_t k = k0; k < k1; ++k) {
-            dst[k] = (uint8_t)(src[k] ^ 1u);
-            ones += src[k];
-        }
-        dels[b] = ones;
-    });
-    for (int i = 0; i < p; ++i) R.adj[(size_t)i * p + i] = 0;
-    R.sep.first_level = true;
-    st.deleted = 0;
-    for (int64_t d : dels) st.deleted += d;
-    st.deleted /= 2;
-    R.total_exec += st.tests_executed;
-    R.spent_possible += st.tests_possible;
+    first_marks(R, ind, st);
     *ms = now_ms() - t0;
     if (trace_on())
         std::fprintf(stderr, "[fpc] first level: queue %.2f wait %.2f (device %.2f) marks %.2f ms\n", tq - t0, tw - tq,
@@ -1765,6 +1780,117 @@ int skeleton_batch_device(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_i
 // it alone would take: at every step each unfinished instance has a next
 // level min(its current level, its largest candidate set), and the
 // instances whose next level is the highest of all run it together.
+// Correlation and first level of every instance of a batch, queued back to
+// back with one wait for all of them.  Every device buffer they share is
+// first sized for the largest instance (none may be reallocated while
+// queued work reads it); each instance's decisions, flag words and
+// positive-definiteness flag land in its own region of the pinned buffer.
+// The errors are those of the instances one at a time: the first instance
+// (in order) with non-finite data, a constant column or a singular matrix
+// gives its error; a resample row out of range gives FPC_EINVAL.
+int batch_prelude(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_instance *inst, char *base,
+                  const std::vector<size_t> &off64, const std::vector<size_t> &off32, std::vector<Run> &runs,
+                  std::vector<double> &corr_ms, std::vector<double> &first_ms)
+{
+    hipStream_t s = ctx->stream;
+    const bool mixed = P->precision == FPC_PREC_MIXED;
+    const int m32 = P->c32_method ? P->c32_method : FPC_CORR_BF16X6;
+    const size_t esz = P->x_dtype == FPC_F64 ? 8 : 4;
+    constexpr size_t kTail = 64;  // after the decisions: the flag words (40 B), then the first level's flag
+    std::vector<size_t> hoff(ni);
+    size_t host_bytes = 256, max_pp = 0, max_x = 0;  // [0, 4): the resample error word
+    int max_p = 2;
+    int rc;
+    for (int k = 0; k < ni; ++k) {
+        const fpc_instance &I = inst[k];
+        const size_t pp = (size_t)I.p * I.p;
+        hoff[k] = host_bytes;
+        host_bytes += (pp + 255) / 256 * 256 + 256;
+        max_pp = std::max(max_pp, pp);
+        max_p = std::max(max_p, I.p);
+        if (I.rows) max_x = std::max(max_x, esz * (size_t)I.n * I.p);
+        if ((rc = corr_reserve(ctx, I.n, I.p, FPC_CORR_FP64))) return rc;
+        if (mixed && m32 != FPC_CORR_FP32 && (rc = corr_reserve(ctx, I.n, I.p, m32))) return rc;
+    }
+    if ((rc = first_level_reserve(ctx, max_p))) return rc;
+    if ((rc = ctx->dellist.ensure(max_pp))) return rc;
+    if (max_x && (rc = ctx->x_copy.ensure(max_x))) return rc;
+    FPC_HIP(hipStreamSynchronize(s));  // the pinned buffer is free
+    if ((rc = ctx->h_back.ensure(host_bytes))) return rc;
+    char *hb = ctx->h_back.as<char>();
+    int *d_rows_bad = ctx->flag.as<int>() + 12;  // bytes 48..51 of the flag words: no other user
+    FPC_HIP(hipMemsetAsync(d_rows_bad, 0, sizeof(int), s));
+    // device time of each instance's correlation and first level (event
+    // pairs of the context, for the first 128 instances)
+    const int n_timed = std::min(ni, fpc_ctx::kLaunchEvents / 2);
+    uint8_t *d_ind = ctx->dellist.as<uint8_t>();
+    for (int k = 0; k < ni; ++k) {
+        const fpc_instance &I = inst[k];
+        Run &R = runs[k];
+        init_run(R, ctx, P, I.p, I.n, false);
+        const size_t pp = (size_t)I.p * I.p;
+        if (k < n_timed) FPC_HIP(hipEventRecord(ctx->lev[4 * k], s));
+        const void *X = I.X;
+        if (I.rows) {  // resample: the listed rows of X, in order
+            if ((rc = gather_rows_enqueue(ctx, I.X, P->x_dtype, I.x_rows, I.p, I.rows, I.n, ctx->x_copy.ptr,
+                                          d_rows_bad)))
+                return rc;
+            X = ctx->x_copy.ptr;
+        }
+        R.X = X;
+        R.x_dtype = P->x_dtype;
+        R.C64 = reinterpret_cast<double *>(base + off64[k]);
+        if ((rc = corr_compute(ctx, X, P->x_dtype, I.n, I.p, FPC_CORR_FP64, const_cast<double *>(R.C64), false,
+                               false)))
+            return rc;
+        if (mixed && (rc = c32_enqueue(R, reinterpret_cast<float *>(base + off32[k])))) return rc;
+        char *h = hb + hoff[k];
+        FPC_HIP(hipMemcpyAsync(h + (pp + 255) / 256 * 256, ctx->flag.ptr, 40, hipMemcpyDeviceToHost, s));
+        if (k < n_timed) {
+            FPC_HIP(hipEventRecord(ctx->lev[4 * k + 1], s));
+            FPC_HIP(hipEventRecord(ctx->lev[4 * k + 2], s));
+        }
+        const int *d_bad = nullptr;
+        if ((rc = first_level_enqueue(ctx, R.C64, I.p, I.n, R.q, nullptr, d_ind, &d_bad))) return rc;
+        if (k < n_timed) FPC_HIP(hipEventRecord(ctx->lev[4 * k + 3], s));
+        FPC_HIP(hipMemcpyAsync(h, d_ind, pp, hipMemcpyDeviceToHost, s));
+        FPC_HIP(hipMemcpyAsync(h + (pp + 255) / 256 * 256 + kTail - 8, d_bad, sizeof(int), hipMemcpyDeviceToHost,
+                               s));
+    }
+    FPC_HIP(hipMemcpyAsync(hb, d_rows_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    host_wake();  // the decisions are read on the host threads
+    FPC_HIP(hipStreamSynchronize(s));  // the one wait
+    int rows_bad;
+    std::memcpy(&rows_bad, hb, sizeof(int));
+    if (rows_bad) return FPC_EINVAL;
+    for (int k = 0; k < ni; ++k) {
+        Run &R = runs[k];
+        const size_t pp = (size_t)R.p * R.p;
+        const char *h = hb + hoff[k];
+        const char *tail = h + (pp + 255) / 256 * 256;
+        int fl[2], bad;
+        std::memcpy(fl, tail, sizeof(fl));
+        std::memcpy(&bad, tail + kTail - 8, sizeof(int));
+        if (fl[0]) return FPC_ENONFINITE;
+        if (fl[1]) return FPC_ESINGULAR;
+        if (mixed) std::memcpy(&R.c_err, tail + 32, sizeof(double));
+        if (bad) return FPC_ESINGULAR;
+        fpc_level_stats st = first_level_stats(R.p);
+        if (k < n_timed) {
+            float c = 0.f, f = 0.f;
+            FPC_HIP(hipEventElapsedTime(&c, ctx->lev[4 * k], ctx->lev[4 * k + 1]));
+            FPC_HIP(hipEventElapsedTime(&f, ctx->lev[4 * k + 2], ctx->lev[4 * k + 3]));
+            corr_ms[k] = c;
+            first_ms[k] = f;
+            st.kernel_ms = f;
+        }
+        first_marks(R, reinterpret_cast<const uint8_t *>(h), st);
+        st.level_ms = first_ms[k];
+        R.levels.push_back(st);
+    }
+    return FPC_OK;
+}
+
 int skeleton_batch_impl(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_instance *inst, fpc_result **outs)
 {
     const double t_start = now_ms();
@@ -1793,23 +1919,8 @@ int skeleton_batch_impl(fpc_ctx *ctx, const fpc_params *P, int ni, const fpc_ins
     char *base = ctx->batch_c.as<char>();
     std::vector<Run> runs(ni);
     std::vector<double> corr_ms(ni, 0.0), first_ms(ni, 0.0);
-    const size_t esz = P->x_dtype == FPC_F64 ? 8 : 4;
     const double t_prep = now_ms();
-    for (int k = 0; k < ni; ++k) {
-        const fpc_instance &I = inst[k];
-        Run &R = runs[k];
-        init_run(R, ctx, P, I.p, I.n);
-        const void *X = I.X;
-        if (I.rows) {  // resample: the listed rows of X, in order
-            if ((rc = ctx->x_copy.ensure(esz * (size_t)I.n * I.p))) return rc;
-            if ((rc = gather_rows(ctx, I.X, P->x_dtype, I.x_rows, I.p, I.rows, I.n, ctx->x_copy.ptr))) return rc;
-            X = ctx->x_copy.ptr;
-        }
-        if ((rc = corr_stage(R, X, P->x_dtype, reinterpret_cast<double *>(base + off64[k]),
-                             mixed ? reinterpret_cast<float *>(base + off32[k]) : nullptr, &corr_ms[k], false)))
-            return rc;
-        if ((rc = first_stage(R, &first_ms[k]))) return rc;
-    }
+    if ((rc = batch_prelude(ctx, P, ni, inst, base, off64, off32, runs, corr_ms, first_ms))) return rc;
     if (trace_on())
         std::fprintf(stderr, "[fpc] batch of %d: correlation and first level %.2f ms\n", ni, now_ms() - t_prep);
     // following levels, level-synchronous over the instances

@@ -119,6 +119,38 @@ def test_batch_errors(fpc, ctx):
     _same(got[0], fpc.fpc_skeleton(ctx, X, alpha=0.01))
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_data_errors(fpc, ctx, prec):
+    """The instances' correlations and first levels are queued together:
+    non-finite data, a constant column and a bad resample row still give
+    their errors (the first instance in order with one), and the context
+    then runs a clean batch."""
+    _say(f"[batch errors] prec={prec}")
+    X = semdata.sample(semdata.make_sem(12, 2), 300, 2)
+    good = dev(X)
+    nan = X.copy()
+    nan[7, 3] = np.nan
+    const = X.copy()
+    const[:, 5] = 1.5
+    cases = ((nan, fpc.FPC_ENONFINITE), (const, fpc.FPC_ESINGULAR))
+    for bad, code in cases:
+        with pytest.raises(fpc.FastPCError) as e:
+            fpc.fpc_skeleton_batch(ctx, [(good, None), (dev(bad), None), (good, None)], alpha=0.01, precision=prec)
+        assert e.value.code == code
+    # the first failing instance gives the error
+    with pytest.raises(fpc.FastPCError) as e:
+        fpc.fpc_skeleton_batch(ctx, [(dev(const), None), (dev(nan), None)], alpha=0.01, precision=prec)
+    assert e.value.code == fpc.FPC_ESINGULAR
+    rows = torch.tensor([0, 1, 400] + [2] * 297, dtype=torch.int32, device="cuda")
+    with pytest.raises(fpc.FastPCError) as e:
+        fpc.fpc_skeleton_batch(ctx, [(good, None), (good, rows)], alpha=0.01, precision=prec)
+    assert e.value.code == fpc.FPC_EINVAL
+    got = fpc.fpc_skeleton_batch(ctx, [(good, None), (good, None)], alpha=0.01, precision=prec)
+    one = fpc.fpc_skeleton(ctx, good, alpha=0.01, precision=prec)
+    _same(got[0], one)
+    _same(got[1], one)
+
+
 def test_batch_full_size_sampled(fpc, ctx):
     """64 bootstrap resamples of a 500-variable data set and 16 data sets
     with p uniform in [50, 2000] (n = 5000, mixed form, max_level 4) in one

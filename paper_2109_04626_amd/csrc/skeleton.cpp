@@ -451,6 +451,10 @@ struct Run {
     bool c32_pending = false;
     const void *X = nullptr;
     int x_dtype = 0;
+    // the correlation's flag words not yet read (they come back with the
+    // first level's results), and its device time
+    bool corr_flags_pending = false;
+    double corr_dev_ms = 0.0;
     // the result's per-pair arrays, filled ahead while the device runs the
     // last levels (valid while ahead_ok: the graph and sets have not changed
     // since), and the arrays allocated ahead by a helper thread
@@ -1197,12 +1201,20 @@ int c32_enqueue(Run &R, float *C32)
 // checked here; the FP32 matrix is queued behind the first level
 // (first_stage) and waited for by c32_finish, so it runs while the host
 // builds the first candidate sets.
-int corr_stage(Run &R, const void *X, int x_dtype, double *C64, float *C32, double *ms, bool defer_c32)
+int corr_stage(Run &R, const void *X, int x_dtype, double *C64, float *C32, double *ms, bool defer_c32,
+               bool first_follows = false)
 {
     const double t0 = now_ms();
     int rc;
+    fpc_ctx *ctx = R.ctx;
     R.X = X;
     R.x_dtype = x_dtype;
+    const bool now = R.mixed && !defer_c32;
+    // a first level queued next waits for the correlation with its own
+    // results: the flag words are copied back then, with no wait here (an
+    // event pair times the correlation on the device)
+    const bool unchecked = first_follows && !now;
+    if (unchecked) FPC_HIP(hipEventRecord(ctx->lev[0], ctx->stream));
     // a deferred product must find its work buffers allocated: growing one
     // behind the first level would free memory that level still uses
     if (R.mixed && defer_c32) {
@@ -1212,12 +1224,19 @@ int corr_stage(Run &R, const void *X, int x_dtype, double *C64, float *C32, doub
     // the products and the error measure queued, then one wait
     if ((rc = corr_compute(R.ctx, X, x_dtype, R.n, R.p, FPC_CORR_FP64, C64, false, false))) return rc;
     R.C64 = C64;
-    const bool now = R.mixed && !defer_c32;
     if (now && (rc = c32_enqueue(R, C32))) return rc;
-    if ((rc = corr_check(R.ctx, now ? &R.c_err : nullptr))) return rc;
+    if (unchecked) {
+        if ((rc = ctx->h_flag.ensure(64))) return rc;
+        FPC_HIP(hipEventRecord(ctx->lev[1], ctx->stream));
+        FPC_HIP(hipMemcpyAsync(ctx->h_flag.as<char>() + 48, ctx->flag.ptr, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        R.corr_flags_pending = true;
+    } else if ((rc = corr_check(R.ctx, now ? &R.c_err : nullptr))) {
+        return rc;
+    }
     R.c32_pending = R.mixed && defer_c32;
     if (R.c32_pending) R.C32 = C32;
-    *ms = now_ms() - t0;
+    *ms = unchecked ? 0.0 : now_ms() - t0;  // unchecked: the device time is added after the first level
     return FPC_OK;
 }
 
@@ -1320,6 +1339,16 @@ int first_stage(Run &R, double *ms)
     host_wake();  // the candidate sets follow on the host threads
     FPC_HIP(hipEventSynchronize(ctx->ev_first));
     const double tw = now_ms();
+    if (R.corr_flags_pending) {  // the correlation's flag words (bytes 48..55 of the pinned flag buffer)
+        R.corr_flags_pending = false;
+        int f[2];
+        std::memcpy(f, ctx->h_flag.as<char>() + 48, sizeof(f));
+        if (f[0]) return FPC_ENONFINITE;
+        if (f[1]) return FPC_ESINGULAR;
+        float cms = 0.f;
+        FPC_HIP(hipEventElapsedTime(&cms, ctx->lev[0], ctx->lev[1]));
+        R.corr_dev_ms = cms;
+    }
     if (*h_bad) return FPC_ESINGULAR;
     float kms = 0.f;
     FPC_HIP(hipEventElapsedTime(&kms, ctx->ev0, ctx->ev1));
@@ -1621,8 +1650,10 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
     if ((rc = ctx->c64.ensure(sizeof(double) * pp))) return rc;
     if (R.mixed && (rc = ctx->c32.ensure(sizeof(float) * pp))) return rc;
     // the FP32 matrix is deferred behind the first level when that level runs
-    const bool defer_c32 = R.mixed && P->schedule == FPC_REVERSE && !P->resume;
-    if ((rc = corr_stage(R, X, P->x_dtype, ctx->c64.as<double>(), ctx->c32.as<float>(), &corr_ms, defer_c32)))
+    const bool first_follows = P->schedule == FPC_REVERSE && !P->resume;
+    const bool defer_c32 = R.mixed && first_follows;
+    if ((rc = corr_stage(R, X, P->x_dtype, ctx->c64.as<double>(), ctx->c32.as<float>(), &corr_ms, defer_c32,
+                         first_follows)))
         return rc;
 
     const int cap = P->max_level;
@@ -1645,6 +1676,9 @@ int skeleton_impl(fpc_ctx *ctx, const fpc_params *P, fpc_result **out)
             l = ck->next_level;
         } else {
             if ((rc = first_stage(R, &first_ms))) return rc;
+            // the first level's wait covered the correlation's device time
+            corr_ms += R.corr_dev_ms;
+            first_ms = std::max(0.0, first_ms - R.corr_dev_ms);
             ++levels_run;
             // following levels: l = min(p-3, cap, largest candidate set), down to 0
             l = p - 3;
